@@ -1,0 +1,674 @@
+/*
+ * qed_oracle.c -- plain FP64 CPU oracle of the per-particle strong-field QED step of
+ * Gonoskov et al., arXiv:1412.6426.  TEST INFRASTRUCTURE ONLY (see qed_oracle.h).
+ *
+ * Everything here is scalar double precision with libm, built with -ffp-contract=off,
+ * and follows the paper's equations in the paper's notation; no blocking, fusion or
+ * reordering beyond what the equations state.  Equation numbers refer to the paper's
+ * sequential numbering (Eq. (3) H_eff, (4) chi, (6) chi = gamma H_eff/E_S, (21) quantum
+ * spectrum, (24) P(delta), (25) P_m, (29) dt requirement, (30) P_p, (31)-(32) chi_gamma,
+ * (33) photon dt requirement).
+ *
+ * Readings of points where the paper is silent or ambiguous (each also listed in the
+ * design notes of the repository):
+ *  - modified generator photon energy is delta = f_m(r1) = r1^3 (Sec. IV.G);
+ *  - the "<<" in Eqs. (29), (33) becomes dt_q = kappa * (bound), with n_sub = ceil(dt/dt_q);
+ *  - n_sub and the fields are fixed once per step from the step-start state (Sec. IV.H);
+ *  - inside a sub-step: Boris push, position update, chi, then the event decision;
+ *  - children are stored at once but processed from the next step on;
+ *  - emission recoil conserves momentum: k = delta*gamma*p/|p|, p <- p - k (Sec. IV.F);
+ *  - pair split: electron r1*k, positron (1-r1)*k (Sec. V.A);
+ *  - the rates are tabulated as in Sec. IV.F ("tabulate ... and use interpolation"):
+ *    three 1-D tables in z = 2^u of e^z*F(z) for F = int K_{5/3}, K_{2/3}, int K_{1/3},
+ *    4096 nodes uniform in u on [-20, 7], linear interpolation in u, a small-z series
+ *    below z = 2^-20 and zero above z = 2^7.
+ */
+#include "qed_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* fine-structure constant, CODATA 2018 */
+static const double OR_ALPHA = 7.2973525693e-3;
+static const double OR_PI = 3.14159265358979323846;
+
+/* ------------------------------------------------------------------------------------
+ * Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as
+ * 1, 2, 3", SC'11): ten rounds of two 32x32->64 multiplications with a Weyl key schedule.
+ * Pinned by the published known-answer vectors of the generator.
+ * ------------------------------------------------------------------------------------ */
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    uint64_t prod0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    uint64_t prod1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    uint32_t hi0 = (uint32_t)(prod0 >> 32), lo0 = (uint32_t)prod0;
+    uint32_t hi1 = (uint32_t)(prod1 >> 32), lo1 = (uint32_t)prod1;
+    uint32_t n0 = hi1 ^ c1 ^ k0;
+    uint32_t n1 = lo1;
+    uint32_t n2 = hi0 ^ c3 ^ k1;
+    uint32_t n3 = lo0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Uniform number strictly inside (0,1) from two 32-bit words: the top 52 bits of the
+ * 64-bit word hi:lo, plus one half, times 2^-52.  (The paper draws r in [0,1]; the open
+ * interval keeps delta = r1^3 away from 0 and 1.) */
+double or_uniform(uint32_t lo, uint32_t hi) {
+  uint64_t x = ((uint64_t)hi << 32) | (uint64_t)lo;
+  return ((double)(x >> 12) + 0.5) * 0x1p-52;
+}
+
+/* ------------------------------------------------------------------------------------
+ * Bessel-function integrals.  DLMF 10.32.9: K_nu(z) = int_0^inf exp(-z cosh t) cosh(nu t) dt.
+ * Integrating over z from z to infinity gives int_z^inf K_nu = int_0^inf exp(-z cosh t)
+ * cosh(nu t)/cosh t dt.  Both are computed scaled by e^z, by the trapezoid rule in t,
+ * which converges geometrically for these analytic, double-exponentially decaying
+ * integrands.  cosh t - 1 is formed as 2 sinh^2(t/2) to keep relative accuracy near t=0.
+ * Pinned against scipy.special.kv and against quadrature of kv (tests).
+ * ------------------------------------------------------------------------------------ */
+double or_kint_scaled(double nu, int over_cosh, double z) {
+  double h = 1.0 / 32.0;
+  if (z > 256.0) h = 0.5 / sqrt(z);
+  double sum = 0.5; /* t = 0 term: exp(0) cosh(0) / cosh(0) = 1, half weight */
+  double prev = 1.0;
+  for (long k = 1; k < 2000000; ++k) {
+    double t = (double)k * h;
+    double sh = sinh(0.5 * t);
+    double f = exp(-z * 2.0 * sh * sh) * cosh(nu * t);
+    if (over_cosh) f /= cosh(t);
+    sum += f;
+    if (f <= prev && f < 1e-18 * sum) break;
+    prev = f;
+  }
+  return sum * h;
+}
+
+double or_A(double z) { return or_kint_scaled(5.0 / 3.0, 1, z) * exp(-z); }
+double or_B(double z) { return or_kint_scaled(2.0 / 3.0, 0, z) * exp(-z); }
+double or_C(double z) { return or_kint_scaled(1.0 / 3.0, 1, z) * exp(-z); }
+/* synchrotron functions of Sec. IV.E: F1(x) = x int_x^inf K_{5/3}, F2(x) = x K_{2/3}(x) */
+double or_F1(double x) { return x * or_A(x); }
+double or_F2(double x) { return x * or_B(x); }
+
+/* ------------------------------------------------------------------------------------
+ * Tables (the paper's "tabulate in advance and interpolate", Sec. IV.F).
+ * Small-z series (below z = 2^-20), from K_nu = (1/2)Gamma(nu)(z/2)^-nu (1 + (z/2)^2/(1-nu)
+ * + ...) + (1/2)Gamma(-nu)(z/2)^nu (1 + ...) (DLMF 10.27.4 with 10.25.2) and
+ * int_0^inf K_{1/3} = pi/sqrt(3) (DLMF 10.43.19):
+ *   K_{2/3}(z)        = b0 z^-2/3 + b1 z^2/3 + (3/4) b0 z^4/3 + O(z^8/3)
+ *   int_z^inf K_{1/3} = c0 - c1 z^2/3 - c2 z^4/3 + O(z^8/3)
+ *   int_z^inf K_{5/3} = 2 K_{2/3} - int_z^inf K_{1/3}   (from K_{nu-1}+K_{nu+1} = -2K'_nu)
+ * Pinned against the quadrature at small z (tests).
+ * ------------------------------------------------------------------------------------ */
+int or_tables_build(or_tables *t) {
+  t->n = OR_TABLE_N;
+  t->u_lo = OR_U_LO;
+  t->u_hi = OR_U_HI;
+  t->du = (OR_U_HI - OR_U_LO) / (double)(OR_TABLE_N - 1);
+  t->gA = (double *)malloc(sizeof(double) * OR_TABLE_N);
+  t->gB = (double *)malloc(sizeof(double) * OR_TABLE_N);
+  t->gC = (double *)malloc(sizeof(double) * OR_TABLE_N);
+  if (!t->gA || !t->gB || !t->gC) return -1;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int i = 0; i < OR_TABLE_N; ++i) {
+    double z = exp2(OR_U_LO + (double)i * t->du);
+    t->gA[i] = or_kint_scaled(5.0 / 3.0, 1, z);
+    t->gB[i] = or_kint_scaled(2.0 / 3.0, 0, z);
+    t->gC[i] = or_kint_scaled(1.0 / 3.0, 1, z);
+  }
+  t->s_b0 = 0.5 * tgamma(2.0 / 3.0) * pow(2.0, 2.0 / 3.0);
+  t->s_b1 = 0.5 * tgamma(-2.0 / 3.0) * pow(2.0, -2.0 / 3.0);
+  t->s_c0 = OR_PI / sqrt(3.0);
+  t->s_c1 = 0.5 * tgamma(1.0 / 3.0) * pow(2.0, 1.0 / 3.0) * 1.5;
+  t->s_c2 = 0.5 * tgamma(-1.0 / 3.0) * pow(2.0, -1.0 / 3.0) * 0.75;
+  return 0;
+}
+
+void or_tables_free(or_tables *t) {
+  free(t->gA);
+  free(t->gB);
+  free(t->gC);
+  t->gA = t->gB = t->gC = 0;
+}
+
+void or_eval_abc(const or_tables *t, int backend, double z, double *A, double *B, double *C) {
+  if (!(z > 0.0)) { /* z <= 0 or NaN: no defined rate */
+    *A = *B = *C = NAN;
+    return;
+  }
+  if (backend == OR_EXACT) {
+    *A = or_A(z);
+    *B = or_B(z);
+    *C = or_C(z);
+    return;
+  }
+  if (z >= exp2(t->u_hi)) {
+    *A = *B = *C = 0.0;
+    return;
+  }
+  if (z < exp2(t->u_lo)) {
+    double z23 = cbrt(z * z);
+    double zm23 = 1.0 / z23;
+    double z43 = z23 * z23;
+    double b = t->s_b0 * zm23 + t->s_b1 * z23 + 0.75 * t->s_b0 * z43;
+    double c = t->s_c0 - t->s_c1 * z23 - t->s_c2 * z43;
+    *B = b;
+    *C = c;
+    *A = 2.0 * b - c;
+    return;
+  }
+  double s = (log2(z) - t->u_lo) / t->du;
+  int i = (int)floor(s);
+  if (i < 0) i = 0;
+  if (i > t->n - 2) i = t->n - 2;
+  double f = s - (double)i;
+  double e = exp(-z);
+  *A = (t->gA[i] + f * (t->gA[i + 1] - t->gA[i])) * e;
+  *B = (t->gB[i] + f * (t->gB[i + 1] - t->gB[i])) * e;
+  *C = (t->gC[i] + f * (t->gC[i + 1] - t->gC[i])) * e;
+}
+
+/* ------------------------------------------------------------------------------------
+ * Rates.  dtfac = Delta t * e^2 m c / hbar^2 = (sub-step duration) * alpha / eps_r.
+ * ------------------------------------------------------------------------------------ */
+
+/* Eq. (24): probability of emitting a photon with energy delta*m c^2*gamma during the
+ * interval, with z_q of Eq. (21). */
+double or_rate_emission(const or_tables *t, int backend, double delta, double chi, double gamma,
+                        double dtfac) {
+  if (!(chi > 0.0) || !(delta > 0.0) || !(delta < 1.0)) return 0.0;
+  double zq = (2.0 / 3.0) * (1.0 / chi) * delta / (1.0 - delta);
+  double A, B, C;
+  or_eval_abc(t, backend, zq, &A, &B, &C);
+  double F1 = zq * A;
+  double F2 = zq * B;
+  return dtfac * (sqrt(3.0) / (2.0 * OR_PI)) * (chi / gamma) * ((1.0 - delta) / delta) *
+         (F1 + 1.5 * delta * chi * zq * F2);
+}
+
+/* Eq. (25) with f_m(x) = x^3 (Sec. IV.G): P_m(r1) = f_m'(r1) P(f_m(r1)). */
+double or_rate_modified(const or_tables *t, int backend, double r1, double chi, double gamma,
+                        double dtfac) {
+  double delta = r1 * r1 * r1;
+  return 3.0 * r1 * r1 * or_rate_emission(t, backend, delta, chi, gamma, dtfac);
+}
+
+/* Eq. (30): probability that a photon of energy kabs (units m c^2) creates a pair with
+ * the electron taking the fraction delta_e.  Both (delta_e - 1) delta_e and the brace are
+ * negative, so the product is positive; it is evaluated as printed. */
+double or_rate_pair(const or_tables *t, int backend, double delta_e, double chi_g, double kabs,
+                    double dtfac) {
+  if (!(chi_g > 0.0) || !(delta_e > 0.0) || !(delta_e < 1.0)) return 0.0;
+  double zp = (2.0 / 3.0) / (chi_g * (1.0 - delta_e) * delta_e);
+  double A, B, C;
+  or_eval_abc(t, backend, zp, &A, &B, &C);
+  double F1 = zp * A;
+  double F2 = zp * B;
+  return dtfac * (sqrt(3.0) / (2.0 * OR_PI)) * (chi_g / kabs) * (delta_e - 1.0) * delta_e *
+         (F1 - 1.5 * chi_g * zp * F2);
+}
+
+/* ------------------------------------------------------------------------------------
+ * Kinematics.
+ * ------------------------------------------------------------------------------------ */
+
+/* Eq. (4) in normalised units: chi = eps_r sqrt((gamma E + p x B)^2 - (p.E)^2). */
+double or_chi_lepton(const double p[3], const double E[3], const double B[3], double eps_r) {
+  double gamma = sqrt(1.0 + p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+  double v0 = gamma * E[0] + (p[1] * B[2] - p[2] * B[1]);
+  double v1 = gamma * E[1] + (p[2] * B[0] - p[0] * B[2]);
+  double v2 = gamma * E[2] + (p[0] * B[1] - p[1] * B[0]);
+  double pe = p[0] * E[0] + p[1] * E[1] + p[2] * E[2];
+  double r = v0 * v0 + v1 * v1 + v2 * v2 - pe * pe;
+  if (r < 0.0) r = 0.0;
+  return eps_r * sqrt(r);
+}
+
+/* Eqs. (31)-(32): chi_gamma = (hbar omega / m c^2) H_eff^gamma / E_S with
+ * H_eff^gamma = sqrt((E + khat x B)^2 - (khat.E)^2). */
+double or_chi_photon(const double k[3], const double E[3], const double B[3], double eps_r) {
+  double kabs = sqrt(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
+  if (!(kabs > 0.0)) return 0.0;
+  double n0 = k[0] / kabs, n1 = k[1] / kabs, n2 = k[2] / kabs;
+  double v0 = E[0] + (n1 * B[2] - n2 * B[1]);
+  double v1 = E[1] + (n2 * B[0] - n0 * B[2]);
+  double v2 = E[2] + (n0 * B[1] - n1 * B[0]);
+  double ne = n0 * E[0] + n1 * E[1] + n2 * E[2];
+  double r = v0 * v0 + v1 * v1 + v2 * v2 - ne * ne;
+  if (r < 0.0) r = 0.0;
+  double H = sqrt(r);
+  return kabs * H * eps_r; /* H / E_S = H * eps_r */
+}
+
+/* Boris push (Appendix A): half step in E, rotation in B, half step in E; charge q. */
+void or_boris(double p[3], double q, double h, const double E[3], const double B[3]) {
+  double pm[3], t[3], pp[3], s[3];
+  for (int i = 0; i < 3; ++i) pm[i] = p[i] + q * 0.5 * h * E[i];
+  double g = sqrt(1.0 + pm[0] * pm[0] + pm[1] * pm[1] + pm[2] * pm[2]);
+  for (int i = 0; i < 3; ++i) t[i] = q * 0.5 * h * B[i] / g;
+  double t2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+  pp[0] = pm[0] + (pm[1] * t[2] - pm[2] * t[1]);
+  pp[1] = pm[1] + (pm[2] * t[0] - pm[0] * t[2]);
+  pp[2] = pm[2] + (pm[0] * t[1] - pm[1] * t[0]);
+  for (int i = 0; i < 3; ++i) s[i] = 2.0 * t[i] / (1.0 + t2);
+  double pl[3];
+  pl[0] = pm[0] + (pp[1] * s[2] - pp[2] * s[1]);
+  pl[1] = pm[1] + (pp[2] * s[0] - pp[0] * s[2]);
+  pl[2] = pm[2] + (pp[0] * s[1] - pp[1] * s[0]);
+  for (int i = 0; i < 3; ++i) p[i] = pl[i] + q * 0.5 * h * E[i];
+}
+
+/* CIC (trilinear) interpolation of one Yee component whose nodes sit at
+ * origin + (index + off) * dx, periodic in every direction. */
+static double or_cic(const float *g, const int n[3], const double dx[3], const double org[3],
+                     const double off[3], const double x[3]) {
+  int i0[3];
+  double fr[3];
+  for (int d = 0; d < 3; ++d) {
+    double s = (x[d] - org[d]) / dx[d] - off[d];
+    double fl = floor(s);
+    fr[d] = s - fl;
+    long ii = (long)fl % n[d];
+    if (ii < 0) ii += n[d];
+    i0[d] = (int)ii;
+  }
+  double acc = 0.0;
+  for (int c = 0; c < 2; ++c)
+    for (int b = 0; b < 2; ++b)
+      for (int a = 0; a < 2; ++a) {
+        int ii = (i0[0] + a) % n[0];
+        int jj = (i0[1] + b) % n[1];
+        int kk = (i0[2] + c) % n[2];
+        double wgt = (a ? fr[0] : 1.0 - fr[0]) * (b ? fr[1] : 1.0 - fr[1]) *
+                     (c ? fr[2] : 1.0 - fr[2]);
+        acc += wgt * (double)g[((long)kk * n[1] + jj) * n[0] + ii];
+      }
+  return acc;
+}
+
+void or_field_at(const or_field *f, const double x[3], double t, double E[3], double B[3]) {
+  switch (f->kind) {
+    case OR_FIELD_UNIFORM:
+      for (int i = 0; i < 3; ++i) {
+        E[i] = f->e0[i];
+        B[i] = f->b0[i];
+      }
+      break;
+    case OR_FIELD_ROTATING_E: {
+      double ph = f->omega * t + f->phase;
+      E[0] = f->amp * cos(ph);
+      E[1] = f->amp * sin(ph);
+      E[2] = 0.0;
+      B[0] = B[1] = B[2] = 0.0;
+      break;
+    }
+    case OR_FIELD_CP_STANDING: {
+      /* two counter-propagating circularly polarised waves of amplitude amp, k = omega */
+      double ph = f->omega * t + f->phase;
+      double ce = 2.0 * f->amp * cos(f->omega * x[0]);
+      double cb = 2.0 * f->amp * sin(f->omega * x[0]);
+      E[0] = 0.0;
+      E[1] = ce * cos(ph);
+      E[2] = ce * sin(ph);
+      B[0] = 0.0;
+      B[1] = cb * cos(ph);
+      B[2] = cb * sin(ph);
+      break;
+    }
+    case OR_FIELD_YEE: {
+      static const double off[6][3] = {{0.5, 0, 0},   {0, 0.5, 0},   {0, 0, 0.5},
+                                       {0, 0.5, 0.5}, {0.5, 0, 0.5}, {0.5, 0.5, 0}};
+      for (int c = 0; c < 3; ++c) E[c] = or_cic(f->grid[c], f->n, f->dx, f->origin, off[c], x);
+      for (int c = 0; c < 3; ++c)
+        B[c] = or_cic(f->grid[3 + c], f->n, f->dx, f->origin, off[3 + c], x);
+      break;
+    }
+    default:
+      E[0] = E[1] = E[2] = B[0] = B[1] = B[2] = NAN;
+  }
+}
+
+/* Eq. (29) with the "<<" read as dt_q = kappa * 14 (lambda_C/c) (E_S/H_eff)^(2/3), and
+ * H_eff/E_S = chi/gamma from Eq. (6); lambda_C/c = 2 pi eps_r in units of 1/w_r. */
+double or_dtq_lepton(double chi, double gamma, double eps_r, double kappa) {
+  double h_over_es = chi / gamma;
+  return kappa * 14.0 * (2.0 * OR_PI * eps_r) * pow(1.0 / h_over_es, 2.0 / 3.0);
+}
+
+/* Eq. (33): dt_q = kappa * 130 (lambda_C/c) (E_S/H_eff^gamma), H^gamma/E_S = chi_g/kabs. */
+double or_dtq_photon(double chi_g, double kabs, double eps_r, double kappa) {
+  double h_over_es = chi_g / kabs;
+  return kappa * 130.0 * (2.0 * OR_PI * eps_r) * (1.0 / h_over_es);
+}
+
+/* Sec. IV.H: divide dt into subintervals not greater than dt_q. */
+int or_substeps(double dt, double dtq, int *near_int, int *clamped) {
+  double r = dt / dtq;
+  *near_int = 0;
+  *clamped = 0;
+  double nr = nearbyint(r);
+  if (nr >= 1.0 && fabs(r - nr) <= 1e-12 * nr) *near_int = 1;
+  if (!(r > 1.0)) return 1;
+  double c = ceil(r);
+  if (c > (double)OR_NSUB_MAX) {
+    *clamped = 1;
+    return OR_NSUB_MAX;
+  }
+  return (int)c;
+}
+
+uint64_t or_child_id(uint64_t parent, uint64_t seed, int64_t step, int substep, int purpose) {
+  uint32_t ctr[4] = {(uint32_t)step, ((uint32_t)substep & 0xFFFFu) | ((uint32_t)purpose << 16),
+                     (uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t key[2] = {(uint32_t)parent, (uint32_t)(parent >> 32)};
+  uint32_t o[4];
+  or_philox4x32_10(ctr, key, o);
+  uint64_t id = (((uint64_t)o[1] << 32) | (uint64_t)o[0]) | (1ull << 63);
+  if (id == OR_ID_DEAD) id = OR_ID_DEAD - 1;
+  return id;
+}
+
+static void or_draw(uint64_t id, uint64_t seed, int64_t step, int substep, double *r1,
+                    double *r2) {
+  uint32_t ctr[4] = {(uint32_t)step, (uint32_t)substep & 0xFFFFu, (uint32_t)seed,
+                     (uint32_t)(seed >> 32)};
+  uint32_t key[2] = {(uint32_t)id, (uint32_t)(id >> 32)};
+  uint32_t o[4];
+  or_philox4x32_10(ctr, key, o);
+  *r1 = or_uniform(o[0], o[1]);
+  *r2 = or_uniform(o[2], o[3]);
+}
+
+/* ------------------------------------------------------------------------------------
+ * The step.
+ * ------------------------------------------------------------------------------------ */
+typedef struct {
+  double x[3], p[3], w;
+  uint64_t id, parent;
+  uint32_t birth;
+  int species;
+} or_child;
+
+typedef struct {
+  or_child *v;
+  int64_t n, cap;
+} or_childbuf;
+
+static void or_push_child(or_childbuf *b, const or_child *c) {
+  if (b->n == b->cap) {
+    int64_t nc = b->cap ? 2 * b->cap : 1024;
+    or_child *nv = (or_child *)realloc(b->v, sizeof(or_child) * (size_t)nc);
+    if (!nv) abort();
+    b->v = nv;
+    b->cap = nc;
+  }
+  b->v[b->n++] = *c;
+}
+
+static void or_note_decision(or_stats *s, double P, double r2, int is_pair) {
+  if (!isfinite(P)) {
+    s->nonfinite++;
+    return;
+  }
+  if (is_pair) {
+    if (P > s->max_p_pair) s->max_p_pair = P;
+  } else {
+    if (P > s->max_p_emit) s->max_p_emit = P;
+  }
+  if (P >= 1.0) s->saturated++;
+  if (fabs(r2 - P) < 1e-12) s->near_threshold++;
+}
+
+static void or_stats_merge(or_stats *a, const or_stats *b) {
+  a->emitted += b->emitted;
+  a->pairs += b->pairs;
+  a->dropped += b->dropped;
+  a->saturated += b->saturated;
+  a->near_threshold += b->near_threshold;
+  a->nsub_near_int += b->nsub_near_int;
+  a->nsub_clamped += b->nsub_clamped;
+  a->nonfinite += b->nonfinite;
+  a->substeps += b->substeps;
+  a->photon_energy += b->photon_energy;
+  if (b->max_p_emit > a->max_p_emit) a->max_p_emit = b->max_p_emit;
+  if (b->max_p_pair > a->max_p_pair) a->max_p_pair = b->max_p_pair;
+  for (int i = 0; i < OR_NSUB_HIST; ++i) a->nsub_hist[i] += b->nsub_hist[i];
+}
+
+static void or_lepton_advance(const or_tables *t, or_store *st, int species, int64_t j,
+                              const or_field *f, const or_params *p, double tn, or_childbuf *cb,
+                              or_stats *s) {
+  double q = (species == 0) ? -1.0 : 1.0;
+  double x[3] = {st->x[j], st->y[j], st->z[j]};
+  double mom[3] = {st->px[j], st->py[j], st->pz[j]};
+  uint64_t id = st->id[j];
+  double E[3], B[3];
+  or_field_at(f, x, tn, E, B); /* once per step (Sec. IV.H) */
+  double gamma = sqrt(1.0 + mom[0] * mom[0] + mom[1] * mom[1] + mom[2] * mom[2]);
+  double chi = or_chi_lepton(mom, E, B, p->eps_r);
+  int nsub = 1, near_int = 0, clamped = 0;
+  if (p->forced_substeps > 0) {
+    nsub = p->forced_substeps;
+  } else if (p->adaptive && chi > 0.0) {
+    nsub = or_substeps(p->dt, or_dtq_lepton(chi, gamma, p->eps_r, p->kappa), &near_int,
+                       &clamped);
+  }
+  if (!isfinite(chi)) s->nonfinite++;
+  s->nsub_near_int += near_int;
+  s->nsub_clamped += clamped;
+  s->nsub_hist[nsub < OR_NSUB_HIST ? nsub : OR_NSUB_HIST - 1]++;
+  double h = p->dt / (double)nsub;
+  double dtfac = h * OR_ALPHA / p->eps_r;
+  uint32_t nev = st->n_events ? st->n_events[j] : 0;
+  for (int k = 0; k < nsub; ++k) {
+    or_boris(mom, q, h, E, B);
+    gamma = sqrt(1.0 + mom[0] * mom[0] + mom[1] * mom[1] + mom[2] * mom[2]);
+    for (int d = 0; d < 3; ++d) x[d] += h * mom[d] / gamma;
+    chi = or_chi_lepton(mom, E, B, p->eps_r);
+    s->substeps++;
+    if (!p->emission) continue;
+    double r1, r2;
+    or_draw(id, p->seed, p->step, k, &r1, &r2);
+    double Pm = or_rate_modified(t, p->backend, r1, chi, gamma, dtfac);
+    or_note_decision(s, Pm, r2, 0);
+    if (r2 < Pm) {
+      double delta = r1 * r1 * r1;
+      double eps = delta * gamma; /* photon energy, units m c^2 */
+      double pabs = sqrt(mom[0] * mom[0] + mom[1] * mom[1] + mom[2] * mom[2]);
+      if (!(pabs > 0.0)) {
+        s->nonfinite++;
+        continue;
+      }
+      or_child c;
+      for (int d = 0; d < 3; ++d) {
+        c.p[d] = (eps / pabs) * mom[d];
+        c.x[d] = x[d];
+      }
+      for (int d = 0; d < 3; ++d) mom[d] = mom[d] - c.p[d];
+      c.w = st->w[j];
+      c.id = or_child_id(id, p->seed, p->step, k, 1);
+      c.parent = id;
+      c.birth = (uint32_t)(((uint64_t)(p->step + 1) << 14) | (uint32_t)k);
+      c.species = 2;
+      or_push_child(cb, &c);
+      nev++;
+      s->emitted++;
+      s->photon_energy += st->w[j] * eps;
+    }
+  }
+  st->x[j] = x[0];
+  st->y[j] = x[1];
+  st->z[j] = x[2];
+  st->px[j] = mom[0];
+  st->py[j] = mom[1];
+  st->pz[j] = mom[2];
+  if (st->n_events) st->n_events[j] = nev;
+}
+
+static void or_photon_advance(const or_tables *t, or_store *st, int64_t j, const or_field *f,
+                              const or_params *p, double tn, or_childbuf *cb, or_stats *s) {
+  uint64_t id = st->id[j];
+  if (id == OR_ID_DEAD) return;
+  double x[3] = {st->x[j], st->y[j], st->z[j]};
+  double k[3] = {st->px[j], st->py[j], st->pz[j]};
+  double kabs = sqrt(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
+  if (!(kabs > 0.0) || !isfinite(kabs)) {
+    s->nonfinite++;
+    return;
+  }
+  double E[3], B[3];
+  or_field_at(f, x, tn, E, B);
+  double chi_g = or_chi_photon(k, E, B, p->eps_r);
+  int nsub = 1, near_int = 0, clamped = 0;
+  if (p->forced_substeps > 0) {
+    nsub = p->forced_substeps;
+  } else if (p->adaptive && chi_g > 0.0) {
+    nsub = or_substeps(p->dt, or_dtq_photon(chi_g, kabs, p->eps_r, p->kappa), &near_int,
+                       &clamped);
+  }
+  if (!isfinite(chi_g)) s->nonfinite++;
+  s->nsub_near_int += near_int;
+  s->nsub_clamped += clamped;
+  double h = p->dt / (double)nsub;
+  double dtfac = h * OR_ALPHA / p->eps_r;
+  int dead = 0;
+  for (int kk = 0; kk < nsub; ++kk) {
+    if (p->push_photons)
+      for (int d = 0; d < 3; ++d) x[d] += h * (k[d] / kabs); /* photons move at c along k */
+    chi_g = or_chi_photon(k, E, B, p->eps_r);
+    s->substeps++;
+    if (!p->pairs) continue;
+    double r1, r2;
+    or_draw(id, p->seed, p->step, kk, &r1, &r2);
+    double Pp = or_rate_pair(t, p->backend, r1, chi_g, kabs, dtfac);
+    or_note_decision(s, Pp, r2, 1);
+    if (r2 < Pp) {
+      or_child e, pos;
+      for (int d = 0; d < 3; ++d) {
+        e.x[d] = x[d];
+        pos.x[d] = x[d];
+        e.p[d] = r1 * k[d];
+        pos.p[d] = (1.0 - r1) * k[d];
+      }
+      e.w = pos.w = st->w[j];
+      e.parent = pos.parent = id;
+      e.birth = pos.birth = (uint32_t)(((uint64_t)(p->step + 1) << 14) | (uint32_t)kk);
+      e.id = or_child_id(id, p->seed, p->step, kk, 2);
+      pos.id = or_child_id(id, p->seed, p->step, kk, 3);
+      e.species = 0;
+      pos.species = 1;
+      or_push_child(cb, &e);
+      or_push_child(cb, &pos);
+      s->pairs++;
+      dead = 1;
+      break;
+    }
+  }
+  st->x[j] = x[0];
+  st->y[j] = x[1];
+  st->z[j] = x[2];
+  if (dead) st->id[j] = OR_ID_DEAD;
+}
+
+static void or_append(or_store *st, const or_child *c, or_stats *s) {
+  or_store *d = &st[c->species];
+  if (d->count >= d->capacity) {
+    s->dropped++;
+    return;
+  }
+  int64_t i = d->count++;
+  d->x[i] = c->x[0];
+  d->y[i] = c->x[1];
+  d->z[i] = c->x[2];
+  d->px[i] = c->p[0];
+  d->py[i] = c->p[1];
+  d->pz[i] = c->p[2];
+  d->w[i] = c->w;
+  d->id[i] = c->id;
+  d->parent[i] = c->parent;
+  d->birth[i] = c->birth;
+  if (d->n_events) d->n_events[i] = 0;
+}
+
+int or_step(const or_tables *t, or_store *st, const or_field *f, const or_params *p,
+            or_stats *s) {
+  memset(s, 0, sizeof(*s));
+  const int64_t n0[3] = {st[0].count, st[1].count, st[2].count};
+  const double tn = p->t0 + (double)p->step * p->dt;
+  int nthreads = 1;
+#ifdef _OPENMP
+  nthreads = omp_get_max_threads();
+#endif
+  or_childbuf *bufs = (or_childbuf *)calloc((size_t)nthreads, sizeof(or_childbuf));
+  or_stats *ts = (or_stats *)calloc((size_t)nthreads, sizeof(or_stats));
+  if (!bufs || !ts) return -1;
+#pragma omp parallel num_threads(nthreads)
+  {
+    int tid = 0;
+#ifdef _OPENMP
+    tid = omp_get_thread_num();
+#endif
+    for (int sp = 0; sp < 2; ++sp) {
+#pragma omp for schedule(static)
+      for (int64_t j = 0; j < n0[sp]; ++j)
+        or_lepton_advance(t, &st[sp], sp, j, f, p, tn, &bufs[tid], &ts[tid]);
+    }
+    if (p->push_photons || p->pairs) {
+#pragma omp for schedule(static)
+      for (int64_t j = 0; j < n0[2]; ++j)
+        or_photon_advance(t, &st[2], j, f, p, tn, &bufs[tid], &ts[tid]);
+    }
+  }
+  for (int i = 0; i < nthreads; ++i) {
+    or_stats_merge(s, &ts[i]);
+    for (int64_t c = 0; c < bufs[i].n; ++c) or_append(st, &bufs[i].v[c], s);
+    free(bufs[i].v);
+  }
+  free(bufs);
+  free(ts);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------------------
+ * Generator trials for the statistical pins: trial i draws (r1, r2) from Philox with
+ * counter (i, i>>32, 0, 0) and the given key, then applies the generator decision.
+ * ------------------------------------------------------------------------------------ */
+int64_t or_emission_trials(const or_tables *t, int backend, double chi, double gamma, double dtfac,
+                           uint64_t key, int64_t n, double *delta_out) {
+  int64_t m = 0;
+  uint32_t kk[2] = {(uint32_t)key, (uint32_t)(key >> 32)};
+  for (int64_t i = 0; i < n; ++i) {
+    uint32_t ctr[4] = {(uint32_t)i, (uint32_t)((uint64_t)i >> 32), 0u, 0u}, o[4];
+    or_philox4x32_10(ctr, kk, o);
+    double r1 = or_uniform(o[0], o[1]);
+    double r2 = or_uniform(o[2], o[3]);
+    if (r2 < or_rate_modified(t, backend, r1, chi, gamma, dtfac)) delta_out[m++] = r1 * r1 * r1;
+  }
+  return m;
+}
+
+int64_t or_pair_trials(const or_tables *t, int backend, double chi_g, double kabs, double dtfac,
+                       uint64_t key, int64_t n, double *delta_out) {
+  int64_t m = 0;
+  uint32_t kk[2] = {(uint32_t)key, (uint32_t)(key >> 32)};
+  for (int64_t i = 0; i < n; ++i) {
+    uint32_t ctr[4] = {(uint32_t)i, (uint32_t)((uint64_t)i >> 32), 0u, 0u}, o[4];
+    or_philox4x32_10(ctr, kk, o);
+    double r1 = or_uniform(o[0], o[1]);
+    double r2 = or_uniform(o[2], o[3]);
+    if (r2 < or_rate_pair(t, backend, r1, chi_g, kabs, dtfac)) delta_out[m++] = r1;
+  }
+  return m;
+}

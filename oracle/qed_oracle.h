@@ -1,0 +1,121 @@
+/*
+ * qed_oracle.h -- plain, slow, FP64 CPU oracle of the strong-field QED step of
+ * Gonoskov et al., "Extended PIC schemes for physics in ultra-strong laser fields:
+ * review and developments" (arXiv:1412.6426).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only tests, the smoke check and the benchmark's CPU
+ * baseline may load this library.  It shares no code, header, table or constant
+ * with the HIP library under paper_1412_6426_amd/; the two are written
+ * independently from the paper and compared output by output.
+ *
+ * Units (normalised with a reference angular frequency w_r):
+ *   time 1/w_r, length c/w_r, momentum m c, energy m c^2, fields m c w_r / e.
+ *   eps_r = hbar w_r / (m c^2); the Sauter-Schwinger field is E_S = 1/eps_r and the
+ *   Compton time lambda_C / c = 2 pi eps_r in these units.
+ * Species: 0 electron (charge -1), 1 positron (+1), 2 photon (p holds hbar k / (m c)).
+ *
+ * Parity status of every function is stated in qed_oracle.c next to it.
+ */
+#ifndef QED_ORACLE_H
+#define QED_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OR_TABLE_N 4096
+#define OR_U_LO (-20.0) /* log2 of the smallest tabulated z */
+#define OR_U_HI (7.0)   /* log2 of the largest tabulated z; F = 0 beyond */
+#define OR_ID_DEAD 0xFFFFFFFFFFFFFFFFull
+#define OR_NO_PARENT 0xFFFFFFFFFFFFFFFFull
+#define OR_NSUB_MAX 16383
+#define OR_NSUB_HIST 32
+
+enum { OR_EXACT = 0, OR_TABLE = 1 };
+enum { OR_FIELD_UNIFORM = 0, OR_FIELD_ROTATING_E = 1, OR_FIELD_CP_STANDING = 2, OR_FIELD_YEE = 3 };
+
+typedef struct {
+  int n;
+  double u_lo, u_hi, du;
+  double *gA, *gB, *gC; /* e^z * F(z) at z = 2^(u_lo + i du) */
+  double s_b0, s_b1, s_c0, s_c1, s_c2; /* small-z series constants */
+} or_tables;
+
+typedef struct {
+  double *x, *y, *z, *px, *py, *pz, *w;
+  uint64_t *id, *parent;
+  uint32_t *birth, *n_events; /* n_events may be NULL for photons */
+  int64_t count, capacity;
+} or_store;
+
+typedef struct {
+  int kind;
+  double e0[3], b0[3];       /* uniform field */
+  double amp, omega, phase;  /* rotating E / CP standing wave amplitude, frequency, phase */
+  const float *grid[6];      /* Yee: Ex, Ey, Ez, Bx, By, Bz, each n[2]*n[1]*n[0], x fastest */
+  int n[3];
+  double dx[3], origin[3];
+} or_field;
+
+typedef struct {
+  double dt, eps_r, kappa, t0;
+  int adaptive, forced_substeps;
+  int emission, pairs, push_photons;
+  int backend;
+  uint64_t seed;
+  int64_t step;
+} or_params;
+
+typedef struct {
+  int64_t emitted, pairs, dropped, saturated, near_threshold, nsub_near_int, nsub_clamped,
+      nonfinite, substeps;
+  double photon_energy, max_p_emit, max_p_pair;
+  int64_t nsub_hist[OR_NSUB_HIST];
+} or_stats;
+
+/* counter-based generator (Salmon et al., SC'11) */
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+double or_uniform(uint32_t lo, uint32_t hi);
+
+/* Bessel-function integrals (DLMF 10.32.9): scaled by e^z */
+double or_kint_scaled(double nu, int over_cosh, double z);
+double or_A(double z); /* int_z^inf K_{5/3} */
+double or_B(double z); /* K_{2/3}(z)        */
+double or_C(double z); /* int_z^inf K_{1/3} */
+double or_F1(double x);
+double or_F2(double x);
+
+int or_tables_build(or_tables *t);
+void or_tables_free(or_tables *t);
+void or_eval_abc(const or_tables *t, int backend, double z, double *A, double *B, double *C);
+
+double or_rate_emission(const or_tables *t, int backend, double delta, double chi, double gamma,
+                        double dtfac);
+double or_rate_modified(const or_tables *t, int backend, double r1, double chi, double gamma,
+                        double dtfac);
+double or_rate_pair(const or_tables *t, int backend, double delta_e, double chi_g, double kabs,
+                    double dtfac);
+
+double or_chi_lepton(const double p[3], const double E[3], const double B[3], double eps_r);
+double or_chi_photon(const double k[3], const double E[3], const double B[3], double eps_r);
+void or_boris(double p[3], double q, double h, const double E[3], const double B[3]);
+void or_field_at(const or_field *f, const double x[3], double t, double E[3], double B[3]);
+int or_substeps(double dt, double dtq, int *near_int, int *clamped);
+double or_dtq_lepton(double chi, double gamma, double eps_r, double kappa);
+double or_dtq_photon(double chi_g, double kabs, double eps_r, double kappa);
+uint64_t or_child_id(uint64_t parent, uint64_t seed, int64_t step, int substep, int purpose);
+
+int or_step(const or_tables *t, or_store *st /* [3] */, const or_field *f, const or_params *p,
+            or_stats *s);
+
+/* Batch helpers for statistical pins: run the generators on Philox draws keyed by `key`. */
+int64_t or_emission_trials(const or_tables *t, int backend, double chi, double gamma, double dtfac,
+                           uint64_t key, int64_t n, double *delta_out);
+int64_t or_pair_trials(const or_tables *t, int backend, double chi_g, double kabs, double dtfac,
+                       uint64_t key, int64_t n, double *delta_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

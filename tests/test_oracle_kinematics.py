@@ -1,0 +1,232 @@
+"""Pins of the oracle's chi, Boris push, field providers, CIC gather and sub-step rule."""
+import math
+
+import numpy as np
+import pytest
+
+from tests.test_oracle_bessel import printed
+
+
+def boost(E, B, p, beta_vec):
+    """Lorentz boost (units c = 1) of fields and a 4-momentum (gamma, p) by velocity beta_vec
+    (textbook transformation, e.g. Jackson eq. 11.149)."""
+    b = np.asarray(beta_vec, float)
+    bb = b @ b
+    g = 1.0 / math.sqrt(1.0 - bb)
+    E, B, p = map(np.asarray, (E, B, p))
+    Ep = g * (E + np.cross(b, B)) - g * g / (g + 1) * b * (b @ E)
+    Bp = g * (B - np.cross(b, E)) - g * g / (g + 1) * b * (b @ B)
+    e = math.sqrt(1 + p @ p)
+    pp = p + ((g - 1) * (p @ b) / bb - g * e) * b
+    return Ep, Bp, pp
+
+
+def test_chi_lorentz_invariant(orc):
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        E, B = rng.normal(size=3) * 10, rng.normal(size=3) * 10
+        p = rng.normal(size=3) * 30
+        beta = rng.normal(size=3)
+        beta *= rng.uniform(0.05, 0.9) / np.linalg.norm(beta)
+        c0 = orc.chi_lepton(p, E, B, 0.01)
+        Ep, Bp, pp = boost(E, B, p, beta)
+        assert orc.chi_lepton(pp, Ep, Bp, 0.01) == pytest.approx(c0, rel=1e-10)
+        # photon: chi_gamma is the same invariant with gamma -> |k|
+        k = p
+        cg = orc.chi_photon(k, E, B, 0.01)
+        kabs = np.linalg.norm(k)
+        g = 1.0 / math.sqrt(1 - beta @ beta)
+        kp = k + ((g - 1) * (k @ beta) / (beta @ beta) - g * kabs) * beta
+        assert orc.chi_photon(kp, Ep, Bp, 0.01) == pytest.approx(cg, rel=1e-9)
+
+
+def test_chi_special_cases(orc):
+    eps = 3e-6
+    # at rest in an electric field: chi = eps_r |E|  (H_eff = E, gamma = 1)
+    assert orc.chi_lepton([0, 0, 0], [300, 400, 0], [0, 0, 0], eps) == pytest.approx(eps * 500)
+    # p perpendicular to a pure B: chi = eps_r |p| |B|
+    assert orc.chi_lepton([0, 1e3, 0], [0, 0, 0], [0, 0, 2.0], eps) == pytest.approx(eps * 2e3)
+    # co-propagating with a plane wave E = E y, B = E z along +x: chi = eps_r E (gamma - p_x)
+    for px in (10.0, 1e3, 1e5):
+        g = math.sqrt(1 + px * px)
+        want = eps * 50.0 / (g + px)  # gamma - p = 1/(gamma + p), no cancellation
+        assert orc.chi_lepton([px, 0, 0], [0, 50.0, 0], [0, 0, 50.0], eps) == \
+            pytest.approx(want, rel=1e-9 * px)
+    # photon along the wave's direction of propagation: H_eff^gamma = 0
+    assert orc.chi_photon([1e3, 0, 0], [0, 50.0, 0], [0, 0, 50.0], eps) == 0.0
+    # photon against the wave: H_eff^gamma = 2E
+    assert orc.chi_photon([-1e3, 0, 0], [0, 50.0, 0], [0, 0, 50.0], eps) == \
+        pytest.approx(eps * 1e3 * 100.0)
+
+
+def test_boris_pure_b_rotation_angle(orc):
+    """Boris rotates p about B by exactly 2 atan(h|B|/(2 gamma)) and keeps |p|."""
+    p0 = np.array([300.0, 400.0, 7.0])
+    B = np.array([0.0, 0.0, 2.5])
+    g = math.sqrt(1 + p0 @ p0)
+    for h in (1e-3, 0.1, 10.0):
+        p1 = orc.boris(p0, -1.0, h, [0, 0, 0], B)
+        assert np.linalg.norm(p1) == pytest.approx(np.linalg.norm(p0), rel=1e-15)
+        ang = math.atan2(p0[0] * p1[1] - p0[1] * p1[0], p0[0] * p1[0] + p0[1] * p1[1])
+        # electron (q = -1) rotates counter-clockwise about +z
+        assert ang == pytest.approx(2 * math.atan(h * 2.5 / (2 * g)), rel=1e-12)
+        assert p1[2] == p0[2]
+
+
+def test_boris_pure_e_exact(orc):
+    """In a pure E field Boris reduces to p += q E h (exact)."""
+    p = np.array([1.0, -2.0, 3.0])
+    E = np.array([0.3, 0.0, -7.0])
+    for q in (-1.0, 1.0):
+        got = orc.boris(p, q, 0.25, E, [0, 0, 0])
+        assert np.allclose(got, p + q * E * 0.25, rtol=0, atol=1e-15)
+
+
+def test_push_converges_second_order_to_hyperbolic_motion(orc):
+    """x(t) for a charge starting at rest in uniform E along x: gamma(t) = sqrt(1+(Et)^2),
+    x(t) = (gamma(t) - 1)/E.  The leapfrog position error falls as h^2."""
+    E = 2.0
+    T = 3.0
+    errs = []
+    for n in (50, 100, 200):
+        h = T / n
+        x, p = 0.0, -0.5 * E * h * 0 + 0.0
+        p = np.array([0.0, 0.0, 0.0])
+        # half-step offset: p lives at half-integer times
+        p = orc.boris(p, 1.0, 0.5 * h, [E, 0, 0], [0, 0, 0])
+        for _ in range(n):
+            g = math.sqrt(1 + p @ p)
+            x += h * p[0] / g
+            p = orc.boris(p, 1.0, h, [E, 0, 0], [0, 0, 0])
+        errs.append(abs(x - (math.sqrt(1 + (E * T) ** 2) - 1) / E))
+    assert errs[0] / errs[1] == pytest.approx(4.0, rel=0.05)
+    assert errs[1] / errs[2] == pytest.approx(4.0, rel=0.05)
+
+
+def test_exb_drift(orc):
+    """|E| < |B|, E perpendicular to B: the time-averaged velocity is E x B / B^2."""
+    E = np.array([0.0, 0.3, 0.0])
+    B = np.array([0.0, 0.0, 1.0])
+    p = np.zeros(3)
+    h = 0.04
+    xs = np.zeros(3)
+    n = 50000
+    for _ in range(n):
+        p = orc.boris(p, -1.0, h, E, B)
+        xs += h * p / math.sqrt(1 + p @ p)
+    v = xs / (n * h)
+    assert v[0] == pytest.approx(0.3, rel=2e-3)
+
+
+def test_standing_wave_satisfies_maxwell(orc):
+    f = orc.Field(kind=orc.FIELD_CP_STANDING, amp=2.0, omega=1.0)
+    d = 1e-5
+    for x, t in ((0.3, 0.1), (1.7, 2.2), (-0.4, 5.0)):
+        E, B = orc.field_at(f, [x, 0, 0], t)
+        Exp, Bxp = orc.field_at(f, [x + d, 0, 0], t)
+        Exm, Bxm = orc.field_at(f, [x - d, 0, 0], t)
+        Etp, Btp = orc.field_at(f, [x, 0, 0], t + d)
+        Etm, Btm = orc.field_at(f, [x, 0, 0], t - d)
+        dEdx, dBdx = (Exp - Exm) / (2 * d), (Bxp - Bxm) / (2 * d)
+        dEdt, dBdt = (Etp - Etm) / (2 * d), (Btp - Btm) / (2 * d)
+        curlE = np.array([0.0, -dEdx[2], dEdx[1]])
+        curlB = np.array([0.0, -dBdx[2], dBdx[1]])
+        assert np.allclose(curlE, -dBdt, atol=1e-7)
+        assert np.allclose(curlB, dEdt, atol=1e-7)
+        assert np.linalg.norm(E) == pytest.approx(4.0 * abs(math.cos(x)), abs=1e-12)
+
+
+def test_rotating_field(orc):
+    f = orc.Field(kind=orc.FIELD_ROTATING_E, amp=1000.0, omega=1.0)
+    E, B = orc.field_at(f, [1, 2, 3], math.pi / 3)
+    assert np.allclose(E, [500.0, 1000 * math.sin(math.pi / 3), 0.0])
+    assert not B.any()
+
+
+def _linear_grid(n, dx, org, coef):
+    """Six Yee components sampled from linear functions a + b.x at their own nodes."""
+    from paper_1412_6426_amd.workloads import yee_offsets
+    grids = []
+    ii = np.arange(n)
+    for c, off in enumerate(yee_offsets()):
+        X = org[0] + (ii + off[0]) * dx
+        Y = org[1] + (ii + off[1]) * dx
+        Z = org[2] + (ii + off[2]) * dx
+        a, bx, by, bz = coef[c]
+        g = a + bx * X[None, None, :] + by * Y[None, :, None] + bz * Z[:, None, None]
+        grids.append(np.ascontiguousarray(g.astype(np.float32)))
+    return grids
+
+
+def test_cic_exact_for_linear_fields(orc):
+    n, dx, org = 12, 0.5, (-3.0, -3.0, -3.0)
+    rng = np.random.default_rng(2)
+    coef = [tuple(rng.integers(-4, 5, 4).astype(float) / 4) for _ in range(6)]
+    grids = _linear_grid(n, dx, org, coef)
+    f = orc.Field(kind=orc.FIELD_YEE, grid=grids, dx=(dx, dx, dx), origin=org)
+    for _ in range(50):
+        # stay away from the periodic seam, where linear data is not periodic
+        x = rng.uniform(-1.5, 1.5, 3)
+        E, B = orc.field_at(f, x, 0.0)
+        want = [a + bx * x[0] + by * x[1] + bz * x[2] for (a, bx, by, bz) in coef]
+        assert np.allclose(np.concatenate([E, B]), want, rtol=0, atol=1e-12)
+
+
+def test_cic_periodic_and_constant(orc):
+    n, dx = 8, 1.0
+    grids = [np.full((n, n, n), float(c + 1), dtype=np.float32) for c in range(6)]
+    f = orc.Field(kind=orc.FIELD_YEE, grid=grids, dx=(dx, dx, dx), origin=(0, 0, 0))
+    for x in ([0.0, 0.0, 0.0], [7.9, 7.99, -0.2], [123.4, -55.5, 8.0]):
+        E, B = orc.field_at(f, x, 0.0)
+        assert np.allclose(np.concatenate([E, B]), [1, 2, 3, 4, 5, 6], atol=1e-12)
+    # one hot node: weight falls off trilinearly, wraps around the box
+    g = np.zeros((n, n, n), dtype=np.float32)
+    g[0, 0, 0] = 1.0
+    f = orc.Field(kind=orc.FIELD_YEE, grid=[g] * 6, dx=(1, 1, 1), origin=(0, 0, 0))
+    E, B = orc.field_at(f, [-0.25, 0.0, 0.0], 0.0)  # Ey node (0,0.5,0): s_y = -0.5
+    assert E[1] == pytest.approx(0.75 * 0.5, abs=1e-12)
+
+
+def test_dt_requirements_printed(orc):
+    pv = printed()
+    eps = 0.37
+    lam_c = 2 * math.pi * eps  # lambda_C / c in units of 1/w_r
+    # Eq. (29) at E_S/H_eff = 1: 14 lambda_C/c;  Eq. (33): 130 lambda_C/c
+    assert orc.dtq_lepton(1.0, 1.0, eps) == pytest.approx(pv["dt_lepton_coeff"][0] * lam_c)
+    assert orc.dtq_photon(1.0, 1.0, eps) == pytest.approx(pv["dt_photon_coeff"][0] * lam_c)
+    # (E_S/H)^(2/3) scaling, H/E_S = chi/gamma (Eq. (6))
+    assert orc.dtq_lepton(0.5, 4.0, eps) == pytest.approx(14 * lam_c * 8.0 ** (2 / 3))
+    # Eq. (29) is the simplified form of Eq. (28): below it for gamma >= 1, E_S/H >= 1
+    pre = pv["dt_full_prefactor"][0]
+    assert pre == pytest.approx(137 / (2 * math.pi), rel=1e-3)
+    for g in (1.0, 10.0, 1e4):
+        for s in (1.0, 3.0, 1e3):
+            full = pre * lam_c * min(pv["dt_full_first"][0] * g ** (1 / 3) * s ** (2 / 3),
+                                     pv["dt_full_second"][0] * s)
+            assert orc.dtq_lepton(g / s, g, eps) <= full * 1.0001
+
+
+def test_substep_rule(orc):
+    assert orc.substeps(1.0, 2.0) == (1, 0, 0)
+    assert orc.substeps(7.14, 1.0)[0] == 8
+    assert orc.substeps(3.0, 1.0) == (3, 1, 0)  # exact integer ratio: flagged near-integer
+    assert orc.substeps(1e9 + 0.5, 1.0) == (16383, 0, 1)
+
+
+@pytest.mark.parametrize("chi_over_gamma", [1e-4, 1e-2, 0.3, 1.0])
+def test_kappa1_keeps_probabilities_below_one(orc, chi_over_gamma):
+    """With h = dt_q (kappa = 1, the largest sub-step) and H_eff <= E_S every acceptance
+    probability stays below one, so no decision saturates."""
+    eps = 1.0
+    rs = np.concatenate([np.logspace(-8, -0.0001, 300), 1 - np.logspace(-12, -1, 200)])
+    for gamma in (1.0, 10.0, 1e3, 1e5):
+        chi = chi_over_gamma * gamma
+        h = orc.dtq_lepton(chi, gamma, eps)
+        dtfac = h * 7.2973525693e-3 / eps
+        pm = max(orc.rate_modified(r, chi, gamma, dtfac, orc.EXACT) for r in rs)
+        assert pm < 1.0
+        kabs = gamma
+        hp = orc.dtq_photon(chi, kabs, eps)
+        dtp = hp * 7.2973525693e-3 / eps
+        pp = max(orc.rate_pair(d, chi, kabs, dtp, orc.EXACT) for d in np.linspace(0.01, 0.99, 99))
+        assert pp < 1.0

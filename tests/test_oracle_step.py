@@ -1,0 +1,214 @@
+"""Pins of the oracle's full step (Sec. IV.H adaptive event generator with Sec. V.A pairs):
+conservation laws, the sub-step rule on the uniform-field workload, convergence of the
+adaptive sub-division to brute force, the classical radiation-reaction limit, and the
+failure counters."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1412_6426_amd import workloads as W
+
+ALPHA = 7.2973525693e-3
+
+
+def make_stores(orc, init, caps):
+    st = [orc.Store(caps[0]), orc.Store(caps[1]), orc.Store(caps[2], with_events=False)]
+    for s, cols in zip(st, init):
+        s.load(cols)
+    return st
+
+
+def uniform_b_state(orc, gammas, pitches, reps, B=1e-3, first_id=0):
+    """Electrons of the given gammas/pitch angles (to B along z) repeated reps times."""
+    n = len(gammas) * reps
+    g = np.tile(np.asarray(gammas, float), reps)
+    th = np.tile(np.asarray(pitches, float), reps)
+    pab = np.sqrt(g * g - 1)
+    zero = np.zeros(n)
+    cols = W._seed_columns(zero, zero, zero, pab * np.sin(th), zero, pab * np.cos(th),
+                           first_id=first_id)
+    return [cols, W.empty_columns(), W.empty_columns()]
+
+
+def test_config1_substeps_are_eight(orc):
+    w = W.uniform_b(n=200, steps=3)
+    st = make_stores(orc, W.uniform_b_initial(w), w.capacity)
+    fld = orc.Field(kind=orc.FIELD_UNIFORM, b0=w.field.b0)
+    par = orc.Params(dt=w.dt, eps_r=w.eps_r, pairs=0, push_photons=0, seed=w.seed)
+    out = orc.run(st, fld, par, 3)
+    # dt = 0.01 T_gyro = 0.01 * 2 pi gamma^2 (gamma = 1000, chi = 1) vs
+    # dt_q = 14 * 2 pi * (gamma/chi)^(2/3): dt/dt_q = 7.14 -> 8 sub-steps (chi/gamma is fixed)
+    for s in out:
+        assert s["nsub_hist"][8] == 200
+        assert s["saturated"] == 0 and s["nonfinite"] == 0
+    assert out[0]["substeps"] == 1600
+
+
+def _abs_momentum_sum(stores):
+    tot = 0.0
+    for s in stores:
+        v = s.view()
+        alive = v["id"] != np.uint64(0xFFFFFFFFFFFFFFFF)
+        tot += np.sqrt(v["px"] ** 2 + v["py"] ** 2 + v["pz"] ** 2)[alive].sum()
+    return tot
+
+
+def test_conservation_in_pure_b_with_pairs(orc):
+    """In a pure magnetic field Boris keeps |p|; an emission splits |p| into |p-k| + |k|
+    (k along p) and a pair splits |k| into r1|k| + (1-r1)|k|.  So the sum of |p| over all
+    live particles is conserved, charge is conserved, and every child links to a parent."""
+    B = 0.05
+    init = uniform_b_state(orc, [1000.0] * 4, [math.pi / 2, 1.2, 0.8, 0.4], reps=100, B=B)
+    st = make_stores(orc, init, (200000, 200000, 2000000))
+    fld = orc.Field(kind=orc.FIELD_UNIFORM, b0=(0, 0, B))
+    par = orc.Params(dt=2000.0, eps_r=1.0, seed=3)
+    before = _abs_momentum_sum(st)
+    out = orc.run(st, fld, par, 15)
+    after = _abs_momentum_sum(st)
+    assert after == pytest.approx(before, rel=1e-12)
+    e, p, g = (s.view() for s in st)
+    npairs = sum(s["pairs"] for s in out)
+    nemit = sum(s["emitted"] for s in out)
+    assert npairs > 50 and nemit > 1000
+    assert len(e["id"]) - len(p["id"]) == 400  # charge conservation
+    assert len(p["id"]) == npairs
+    assert len(g["id"]) == nemit
+    assert int((g["id"] == np.uint64(0xFFFFFFFFFFFFFFFF)).sum()) == npairs
+    assert e["n_events"].sum() + p["n_events"].sum() == nemit
+    # ids unique among live particles; children carry the top bit; parents exist
+    live = np.concatenate([e["id"], p["id"], g["id"][g["id"] != np.uint64(2 ** 64 - 1)]])
+    assert len(np.unique(live)) == len(live)
+    all_ids = set(np.concatenate([e["id"], p["id"]]).tolist())
+    assert set(g["parent"].tolist()) <= all_ids
+    assert set(p["parent"].tolist()).isdisjoint(all_ids)  # positrons come from photons
+    assert all(out_s["saturated"] == 0 for out_s in out)
+    # children record their birth step and sub-step
+    assert (g["birth"] >> 14).min() >= 1 and (g["birth"] >> 14).max() <= 15
+
+
+def test_photons_move_at_c(orc):
+    init = [W.empty_columns(), W.empty_columns(),
+            W._seed_columns([0.0], [1.0], [2.0], [3.0], [0.0], [4.0])]
+    init[2]["n_events"] = np.zeros(1, np.uint32)
+    st = make_stores(orc, init, (10, 10, 10))
+    fld = orc.Field(kind=orc.FIELD_UNIFORM)
+    par = orc.Params(dt=0.5, eps_r=1e-6, seed=1)
+    orc.run(st, fld, par, 4)
+    v = st[2].view()
+    assert v["x"][0] == pytest.approx(0.6 * 2.0)
+    assert v["z"][0] == pytest.approx(2.0 + 0.8 * 2.0)
+
+
+def _ensemble(orc, kappa=1.0, forced=0, emission=1, reps=2000, dt_frac=0.03, seed=11):
+    gam = [200.0, 500.0, 1000.0, 2000.0] * 2
+    pit = [math.pi / 2] * 4 + [0.6] * 4
+    Bz = 1.0 / math.sqrt(1000.0 ** 2 - 1)  # chi = 1 for gamma = 1000 at 90 degrees
+    init = uniform_b_state(orc, gam, pit, reps, B=Bz)
+    n = len(gam) * reps
+    st = make_stores(orc, init, (n, 1, 8 * n))
+    fld = orc.Field(kind=orc.FIELD_UNIFORM, b0=(0, 0, Bz))
+    dt = dt_frac * 2 * math.pi * 1000.0 ** 2
+    par = orc.Params(dt=dt, eps_r=1.0, kappa=kappa, forced_substeps=forced, emission=emission,
+                     pairs=0, push_photons=0, seed=seed)
+    orc.run(st, fld, par, 1)
+    e = st[0].view()
+    gfin = np.sqrt(1 + e["px"] ** 2 + e["py"] ** 2 + e["pz"] ** 2).reshape(reps, 8)
+    nev = e["n_events"].astype(float).reshape(reps, 8)
+    pos = np.stack([e["x"], e["y"], e["z"]], 1).reshape(reps, 8, 3)
+    mom = np.stack([e["px"], e["py"], e["pz"]], 1).reshape(reps, 8, 3)
+    return gfin, nev, pos, mom
+
+
+@pytest.mark.slow
+def test_adaptive_converges_to_brute_force(orc):
+    """For 8 particles (4 gammas x 2 pitch angles, chi up to 2), ensemble means over 2000
+    repetitions of the final gamma and photon count from one adaptive step (22 sub-steps)
+    and from a quarter-size kappa agree, within statistical error, with brute force at
+    10^4 sub-steps.  With QED off the momenta converge at second order, positions at first."""
+    ga, na, _, _ = _ensemble(orc)
+    gq, nq, _, _ = _ensemble(orc, kappa=0.25, seed=12)
+    gb, nb, _, _ = _ensemble(orc, forced=10_000, seed=13)
+    for (xa, xb) in ((ga, gb), (na, nb), (gq, gb), (nq, nb)):
+        z = (xa.mean(0) - xb.mean(0)) / np.sqrt(xa.var(0) / len(xa) + xb.var(0) / len(xb))
+        assert np.abs(z).max() < 4.0
+    assert nb.mean() > 0.5  # the step does see emissions
+    # QED off: momenta converge at O(h^2) towards the 10^4-sub-step trajectory (the Boris
+    # rotation angle per sub-step is 2 atan(h B / 2 gamma)); positions at O(h), because the
+    # half-step lag of p behind x in the leapfrog is h/2 and changes with the sub-division
+    _, _, x_ref, p_ref = _ensemble(orc, forced=10_000, emission=0, reps=1)
+    perr, xerr = [], []
+    for f in (11, 22, 44):
+        _, _, x, p = _ensemble(orc, forced=f, emission=0, reps=1)
+        perr.append(np.abs(p - p_ref).max())
+        xerr.append(np.abs(x - x_ref).max())
+    assert perr[0] / perr[1] == pytest.approx(4.0, rel=0.1)
+    assert perr[1] / perr[2] == pytest.approx(4.0, rel=0.1)
+    assert xerr[0] / xerr[1] == pytest.approx(2.0, rel=0.1)
+    assert xerr[1] / xerr[2] == pytest.approx(2.0, rel=0.1)
+
+
+def test_classical_radiation_reaction(orc):
+    """At chi = 0.01 the mean energy radiated in dt matches the Larmor power of Eq. (7),
+    (2/3) chi^2 alpha m c^2/tau_C, with its first quantum correction (1 - 55 sqrt(3)/16 chi):
+    the modified generator reproduces classical radiation reaction (Sec. IV.G)."""
+    gamma, chi, n = 1000.0, 0.01, 100_000
+    Bz = chi / math.sqrt(gamma * gamma - 1)
+    init = uniform_b_state(orc, [gamma], [math.pi / 2], n, B=Bz)
+    st = make_stores(orc, init, (n, 1, 4 * n))
+    fld = orc.Field(kind=orc.FIELD_UNIFORM, b0=(0, 0, Bz))
+    dt = 5e6
+    par = orc.Params(dt=dt, eps_r=1.0, pairs=0, push_photons=0, seed=21)
+    out = orc.run(st, fld, par, 1)
+    e = st[0].view()
+    loss = math.sqrt(gamma * gamma - 1) - np.sqrt(e["px"] ** 2 + e["py"] ** 2 + e["pz"] ** 2)
+    want = (2 / 3) * chi ** 2 * ALPHA * dt * (1 - 55 * math.sqrt(3) / 16 * chi)
+    sig = loss.std() / math.sqrt(n)
+    assert abs(loss.mean() - want) < 3 * sig + 3e-3 * want
+    assert out[0]["photon_energy"] == pytest.approx(loss.sum(), rel=1e-9)
+
+
+def test_capacity_drops_are_counted(orc):
+    w = W.uniform_b(n=500, steps=2)
+    st = make_stores(orc, W.uniform_b_initial(w), (500, 1, 40))
+    fld = orc.Field(kind=orc.FIELD_UNIFORM, b0=w.field.b0)
+    par = orc.Params(dt=w.dt, eps_r=1.0, pairs=0, push_photons=0)
+    out = orc.run(st, fld, par, 2)
+    assert out[-1]["dropped"] > 0 and len(out) == 1  # the run stops at the first drop
+    assert st[2].count == 40
+
+
+def test_nonfinite_and_saturation_counters(orc):
+    w = W.uniform_b(n=20, steps=1)
+    init = W.uniform_b_initial(w)
+    init[0]["px"][3] = np.nan
+    st = make_stores(orc, init, (20, 1, 1000))
+    fld = orc.Field(kind=orc.FIELD_UNIFORM, b0=w.field.b0)
+    out = orc.run(st, fld, orc.Params(dt=w.dt, eps_r=1.0, pairs=0, push_photons=0), 1)
+    assert out[0]["nonfinite"] > 0
+    # adaptive sub-division off with a huge step: P_m >= 1 somewhere
+    st = make_stores(orc, W.uniform_b_initial(w), (20, 1, 1000))
+    out = orc.run(st, fld, orc.Params(dt=50 * w.dt, eps_r=1.0, adaptive=0, pairs=0,
+                                      push_photons=0), 1)
+    assert out[0]["saturated"] > 0
+
+
+def test_resume_is_bit_exact(orc):
+    w = W.rotating_e(n=300, a0=1000.0)
+    fld = orc.Field(kind=orc.FIELD_ROTATING_E, amp=1000.0)
+    caps = (100000, 100000, 1000000)
+
+    def params():
+        return orc.Params(dt=w.dt, eps_r=w.eps_r, seed=5)
+
+    a = make_stores(orc, W.rotating_e_initial(300, seed=1), caps)
+    orc.run(a, fld, params(), 60)
+    b = make_stores(orc, W.rotating_e_initial(300, seed=1), caps)
+    orc.run(b, fld, params(), 30)
+    b2 = make_stores(orc, [s.view() for s in b], caps)  # checkpoint -> restore
+    orc.run(b2, fld, params(), 30, first_step=30)
+    for s1, s2 in zip(a, b2):
+        v1, v2 = s1.view(), s2.view()
+        o1, o2 = np.argsort(v1["id"]), np.argsort(v2["id"])
+        for k in v1:
+            assert np.array_equal(v1[k][o1], v2[k][o2])
