@@ -1,0 +1,237 @@
+/*
+ * qed.h -- C ABI of the MI355X (gfx950) strong-field QED step library (libqed.so).
+ *
+ * The library implements, on the GPU, the per-particle QED step that the extended PIC
+ * scheme of Gonoskov et al., "Extended PIC schemes for physics in ultra-strong laser
+ * fields: review and developments" (arXiv:1412.6426) adds to every time step:
+ *   - field acquisition at the particle (analytic fields, or CIC from a Yee grid; Appendix A),
+ *   - the quantum parameter chi (Sec. IV.C, Eqs. (3), (4), (6); photons Eqs. (31), (32)),
+ *   - the adaptive sub-division of dt (Sec. IV.H, Eq. (29); photons Eq. (33)),
+ *   - the Boris push (Appendix A),
+ *   - the modified event generator for photon emission (Sec. IV.G, Eqs. (24), (25)),
+ *   - the Breit-Wheeler pair generator (Sec. V.A, Eq. (30)),
+ *   - the append of the new particles into structure-of-arrays stores.
+ *
+ * Conventions shared by every entry point
+ *   - Units: time 1/w_r, length c/w_r, momentum m c, energy m c^2, fields m c w_r / e, with
+ *     eps_r = hbar w_r / (m c^2).  The Sauter-Schwinger field is 1/eps_r.
+ *   - Species: 0 electron (charge -1), 1 positron (+1), 2 photon (p holds hbar k / (m c)).
+ *   - Every pointer named d_* or held in a qed_soa / qed_instance is DEVICE memory owned by
+ *     the caller; structs passed by pointer (qed_stores, qed_field, qed_params) are HOST
+ *     memory read during the call only.  The library never allocates device memory and
+ *     keeps no pointer after a call returns.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Every call only enqueues work on
+ *     it: no host synchronisation, no allocation, no memset node -- so a sequence of calls
+ *     can be captured into a hipGraph and replayed.  Kernel arguments are frozen at capture;
+ *     everything that changes from step to step (step index, counts) lives in device memory.
+ *   - Errors: the return value reports argument validation and launch failures only.  What
+ *     happens on the device (children dropped for lack of capacity, non-finite values,
+ *     probabilities >= 1) never aborts; it is counted in the qed_stats record and in the
+ *     instance descriptors, readable once the stream has synchronised.
+ *   - Calls are reentrant; concurrent calls must not share stores, stats or work buffers.
+ */
+#ifndef QED_H
+#define QED_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QED_OK = 0,
+  QED_ERR_ARG = 1,          /* invalid argument (null pointer, size, unknown enum value) */
+  QED_ERR_HIP = 2,          /* a HIP runtime call or kernel launch failed */
+  QED_ERR_UNSUPPORTED = 3   /* valid request this build does not implement */
+} qed_status;
+
+typedef enum { QED_FP64 = 0, QED_MIXED = 1 } qed_precision;
+
+enum { QED_ELECTRON = 0, QED_POSITRON = 1, QED_PHOTON = 2, QED_NSPECIES = 3 };
+
+typedef enum {
+  QED_FIELD_UNIFORM = 0,     /* E = e0*amp_i, B = b0*amp_i */
+  QED_FIELD_ROTATING_E = 1,  /* E = amp*amp_i (cos phi, sin phi, 0), B = 0, phi = omega t + phase */
+  QED_FIELD_CP_STANDING = 2, /* E = 2 a cos(omega x) (0, cos phi, sin phi),
+                                B = 2 a sin(omega x) (0, cos phi, sin phi), a = amp*amp_i */
+  QED_FIELD_YEE = 3          /* CIC (trilinear) gather from a periodic FP32 Yee grid */
+} qed_field_kind;
+
+#define QED_TABLE_N 4096
+#define QED_ID_DEAD 0xFFFFFFFFFFFFFFFFull   /* id of a photon removed by pair creation */
+#define QED_NO_PARENT 0xFFFFFFFFFFFFFFFFull /* parent id of a seed particle */
+#define QED_NSUB_MAX 16383
+#define QED_NSUB_HIST 32
+#define QED_SPECTRUM_BINS 130               /* 10 bins per decade of eps/mc^2 from 1e-8 */
+
+/* status bits of qed_stats.status */
+#define QED_STATUS_DROPPED 1u
+#define QED_STATUS_NONFINITE 2u
+#define QED_STATUS_SATURATED 4u
+#define QED_STATUS_NSUB_CLAMPED 8u
+#define QED_STATUS_NO_TABLES 16u  /* d_tables was not filled by qed_build_tables: nothing done */
+
+/* ---------------------------------------------------------------------------------------
+ * Rate tables (Sec. IV.F: "tabulate in advance and use interpolation").
+ *
+ * Three functions of z are tabulated, from which the emission rate of Eq. (24) and the
+ * pair rate of Eq. (30) follow once their explicit delta and chi factors are pulled out:
+ *   A(z) = int_z^inf K_{5/3},  B(z) = K_{2/3}(z),  C(z) = int_z^inf K_{1/3}.
+ * Nodes: z_i = 2^(-20 + 27 i / 4095), i = 0..4095; stored value e^z F(z), computed in FP64
+ * by trapezoid quadrature of DLMF 10.32.9; FP32 copies for QED_MIXED.  Below z = 2^-20 the
+ * small-z series is used, above z = 2^7 the functions are taken as zero.  Also holds a
+ * per-octave upper bound of the pair rate used to settle most photon decisions early.
+ * --------------------------------------------------------------------------------------- */
+
+/* Layout of the tables buffer (byte offsets):
+ *        0  double[4096][2]  (e^z A, e^z B) at node i
+ *    65536  double[4096][2]  (e^z B, e^z C)
+ *   131072  float[4096][2]   FP32 copy of the first block
+ *   163840  float[4096][2]   FP32 copy of the second block
+ *   196608  double[128]      pair bound: sup over delta_e of the bracket of Eq. (30) for
+ *                            chi_gamma < 2^(j-64), j = 0..127
+ *   197632  float[128]       FP32 copy
+ *   198144  double[8]        b0, b1, c0, c1, c2 (small-z series), 0, 0, 0
+ *   198208  uint32           0x51454454 once built
+ * Size in bytes of the device buffer qed_build_tables fills: */
+size_t qed_table_bytes(void);
+
+/* Fill d_tables (device, qed_table_bytes() bytes, 256-byte aligned) on `stream`.
+ * QED_ERR_ARG if d_tables is NULL, misaligned or bytes is too small. */
+qed_status qed_build_tables(void *d_tables, size_t bytes, void *stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Particle stores.  One structure-of-arrays per species; all columns have the same length
+ * (the store's total capacity) and are indexed by slot.  Instance i owns the slots
+ * [base[s], base[s] + capacity[s]) of species s; its live slots are the first count[s].
+ * --------------------------------------------------------------------------------------- */
+typedef struct {
+  double *x, *y, *z;      /* position */
+  double *px, *py, *pz;   /* momentum (photons: hbar k / m c) */
+  double *w;              /* statistical weight; children copy the parent's (Sec. V.A) */
+  uint64_t *id;           /* particle id; seeds 0..N-1, children a hash with the top bit set */
+  uint64_t *parent;       /* id of the parent, QED_NO_PARENT for seeds */
+  uint32_t *birth;        /* (step+1) << 14 | sub-step of creation; 0 for seeds */
+  uint32_t *n_events;     /* leptons: photons emitted so far; may be NULL for photons */
+} qed_soa;
+
+/* Per-instance descriptor (device array of n_instances, initialised by the caller).
+ * count[] and dropped are updated by the library; frozen is set by it when
+ * freeze_on_drop is on. */
+typedef struct {
+  int64_t base[3];      /* first slot of the instance's segment in each species store */
+  int64_t capacity[3];  /* slots in the segment */
+  int64_t count[3];     /* live slots (removed photons keep their slot, id = QED_ID_DEAD) */
+  int64_t dropped;      /* children not stored for lack of capacity, cumulative */
+  uint64_t seed;        /* random stream of the instance */
+  double amp;           /* field amplitude multiplier of the instance (analytic fields) */
+  int32_t frozen;       /* nonzero: the instance is skipped */
+  int32_t reserved;
+} qed_instance;
+
+typedef struct {
+  qed_soa species[3];
+  qed_instance *d_instances;
+  int n_instances;
+} qed_stores;
+
+typedef struct {
+  int kind;                 /* qed_field_kind */
+  double e0[3], b0[3];      /* QED_FIELD_UNIFORM */
+  double amp, omega, phase; /* QED_FIELD_ROTATING_E / QED_FIELD_CP_STANDING */
+  const float *grid[6];     /* QED_FIELD_YEE: device Ex, Ey, Ez, Bx, By, Bz, each n[2]*n[1]*n[0]
+                               floats, x fastest; component c sits at origin + (i + off_c) dx,
+                               off = (1/2,0,0) (0,1/2,0) (0,0,1/2) (0,1/2,1/2) (1/2,0,1/2) (1/2,1/2,0) */
+  int n[3];
+  double dx[3], origin[3];
+} qed_field;
+
+typedef struct {
+  double dt;            /* global time step */
+  double eps_r;         /* hbar w_r / m c^2 */
+  double kappa;         /* sub-step safety factor: dt_q = kappa * bound of Eq. (29) / (33) */
+  double t0;            /* time of step 0; step n evaluates fields at t0 + n dt */
+  int adaptive;         /* 1: sub-divide dt per particle (Sec. IV.H) */
+  int forced_substeps;  /* > 0: every particle uses exactly this many sub-steps */
+  int emission;         /* photon emission on/off */
+  int pairs;            /* pair creation on/off */
+  int push_photons;     /* photons advance at c along k */
+  int precision;        /* qed_precision */
+  int freeze_on_drop;   /* 1: an instance that dropped children is frozen from the next step */
+  int tile;             /* particles per work tile; 0 = library default */
+  int block;            /* threads per workgroup (64..1024, multiple of 64); 0 = default */
+  int grid_blocks;      /* persistent workgroups per kernel; 0 = from the device's CU count */
+  void *events[4];      /* optional hipEvent_t recorded on `stream` right before/after the
+                           lepton kernel ([0], [1]) and the photon kernel ([2], [3]); NULL
+                           entries are skipped.  Owned by the caller. */
+} qed_params;
+
+/* Per-step record written by qed_step (device memory). */
+typedef struct {
+  int64_t step;                 /* global step index n */
+  int64_t n_start[3];           /* live slots per species at the step start (all instances) */
+  int64_t advanced[3];          /* particles advanced this step (removed photons excluded) */
+  int64_t emitted;              /* photon emissions */
+  int64_t pairs;                /* pair creations */
+  int64_t dropped;              /* children not stored (capacity) */
+  int64_t saturated;            /* decisions with probability >= 1 */
+  int64_t near_threshold;       /* decisions with |r2 - P| < 1e-12 */
+  int64_t nsub_near_int;        /* dt/dt_q within 1e-12 (relative) of an integer */
+  int64_t nsub_clamped;         /* n_sub capped at QED_NSUB_MAX */
+  int64_t nonfinite;            /* NaN/Inf met in chi, rates or momenta */
+  int64_t substeps;             /* particle sub-steps executed */
+  int64_t wave_iters;           /* lepton-kernel wavefront iterations */
+  int64_t low_occupancy_iters;  /* of which fewer than half the lanes held a particle */
+  int64_t early_out;            /* photon decisions settled by the pair-rate bound */
+  double photon_energy;         /* sum of w * eps of the emitted photons */
+  double max_p_emit;            /* largest evaluated emission probability */
+  double max_p_pair;            /* largest evaluated pair probability */
+  int64_t nsub_hist[QED_NSUB_HIST];          /* leptons per n_sub (last bin: >= 31) */
+  int64_t photon_hist[QED_SPECTRUM_BINS];    /* emitted photons per log10(eps) bin */
+  uint32_t status;              /* QED_STATUS_* bits */
+  uint32_t reserved;
+} qed_stats;
+
+/* Size of the workspace qed_step needs for n_instances instances. */
+size_t qed_work_bytes(int n_instances);
+
+/* One global step n = *d_step of every non-frozen instance (Sec. IV.H):
+ *   for each lepton and photon alive at the step start: fields at the start position
+ *   (once per step), chi, n_sub, then n_sub times {push, chi, one event decision}; children
+ *   are appended at the end of their instance's segment and are processed from step n+1.
+ * Increments *d_step and overwrites *d_stats.  d_work: qed_work_bytes(n_instances) bytes.
+ * QED_ERR_ARG on null or inconsistent arguments.  If d_tables does not hold built tables
+ * the kernels do nothing and set QED_STATUS_NO_TABLES. */
+qed_status qed_step(const void *d_tables, const qed_stores *stores, const qed_field *field,
+                    const qed_params *params, int64_t *d_step, qed_stats *d_stats, void *d_work,
+                    size_t work_bytes, void *stream);
+
+/* Append the record *d_stats to d_log[*d_log_count] and increment *d_log_count, unless
+ * *d_log_count >= log_capacity (then the record is discarded and the count still grows,
+ * so the caller sees the overflow).  Graph-capturable. */
+qed_status qed_append_stats(const qed_stats *d_stats, qed_stats *d_log, int64_t log_capacity,
+                            int64_t *d_log_count, void *stream);
+
+/* Diagnostics and harness helpers (not part of the step). */
+
+/* Weighted histogram of eps = |k| (m c^2) of live photons of all instances into
+ * d_hist[bins] (log10-spaced over [lo, hi); under/overflow not counted).  Accumulates. */
+qed_status qed_photon_spectrum(const qed_stores *stores, double lo, double hi, int bins,
+                               double *d_hist, void *stream);
+
+/* Sample the QED_FIELD_CP_STANDING wave of amplitude amp (frequency omega, phase) at time t
+ * onto a periodic Yee grid: d_grid[6] device arrays laid out as in qed_field.  Stands in
+ * for a field solver in the standing-wave workload. */
+qed_status qed_fill_standing_wave(float *const d_grid[6], const int n[3], const double dx[3],
+                                  const double origin[3], double amp, double omega,
+                                  double phase, double t, void *stream);
+
+const char *qed_status_string(qed_status s);
+int qed_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QED_H */

@@ -1,0 +1,43 @@
+"""Build libqed.so for gfx950 in-tree (paper_1412_6426_amd/lib/libqed.so).
+
+``python -m paper_1412_6426_amd.build`` runs one hipcc command over the HIP sources in
+``csrc/``.  Packed-FP32 instructions are disabled for all device code.
+"""
+import glob
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+SRC_DIR = os.path.join(HERE, "csrc")
+LIB_DIR = os.path.join(HERE, "lib")
+LIB = os.path.join(LIB_DIR, "libqed.so")
+ARCH = os.environ.get("QED_OFFLOAD_ARCH", "gfx950")
+
+
+def sources():
+    return sorted(glob.glob(os.path.join(SRC_DIR, "*.hip")))
+
+
+def hipcc_command(out: str, extra=()):
+    return ["hipcc", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-Wall", "-Wno-unused-result",
+            "-I", os.path.join(ROOT, "include"), "-I", SRC_DIR,
+            *extra, "-o", out, *sources()]
+
+
+def build(verbose: bool = False, extra=()) -> str:
+    os.makedirs(LIB_DIR, exist_ok=True)
+    tmp = LIB + ".tmp"
+    cmd = hipcc_command(tmp, extra)
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True, extra=tuple(a for a in sys.argv[1:] if a != "-v"))

@@ -1,0 +1,219 @@
+// qed_api.hip -- extern "C" entry points of libqed: argument validation, launch geometry
+// and the host-side constants of the rate tables.  No entry point allocates device memory
+// or synchronises the host.
+#include <math.h>
+
+#include <mutex>
+
+#include "qed_internal.h"
+
+using namespace qedk;
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_mu;
+int g_cu_count[kMaxDevices];
+int g_occ[kMaxDevices][2][2];  // [precision][photon] resident 256-thread blocks per CU
+
+bool device_geometry(int* cus, int precision, bool photon, int block, int* per_cu) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return false;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (g_cu_count[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n <= 0)
+      return false;
+    g_cu_count[dev] = n;
+  }
+  *cus = g_cu_count[dev];
+  if (block == 256) {
+    int& o = g_occ[dev][precision][photon ? 1 : 0];
+    if (o == 0) o = step_blocks_per_cu(precision, photon, 256);
+    *per_cu = o;
+  } else {
+    *per_cu = step_blocks_per_cu(precision, photon, block);
+  }
+  return true;
+}
+
+bool soa_ok(const qed_soa& s, bool need_events) {
+  return s.x && s.y && s.z && s.px && s.py && s.pz && s.w && s.id && s.parent && s.birth &&
+         (!need_events || s.n_events);
+}
+
+bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
+
+}  // namespace
+
+extern "C" {
+
+size_t qed_table_bytes(void) { return sizeof(DevTables); }
+
+qed_status qed_build_tables(void* d_tables, size_t bytes, void* stream) {
+  if (!d_tables || bytes < sizeof(DevTables) || (reinterpret_cast<uintptr_t>(d_tables) & 255u))
+    return QED_ERR_ARG;
+  // Small-z series of K_{2/3} and int_z^inf K_{1/3} (from K_nu = (1/2)Gamma(nu)(z/2)^-nu(...)
+  // + (1/2)Gamma(-nu)(z/2)^nu(...), DLMF 10.27.4, and int_0^inf K_{1/3} = pi/sqrt 3):
+  //   K_{2/3} = b0 z^-2/3 + b1 z^2/3 + (3/4) b0 z^4/3,  int K_{1/3} = c0 - c1 z^2/3 - c2 z^4/3.
+  Series64 s;
+  s.b0 = 0.5 * tgamma(2.0 / 3.0) * exp2(2.0 / 3.0);
+  s.b1 = 0.5 * tgamma(-2.0 / 3.0) * exp2(-2.0 / 3.0);
+  s.c0 = kPi / sqrt(3.0);
+  s.c1 = 0.75 * tgamma(1.0 / 3.0) * exp2(1.0 / 3.0);
+  s.c2 = 0.375 * tgamma(-1.0 / 3.0) * exp2(-1.0 / 3.0);
+  const hipError_t e =
+      launch_build_tables(static_cast<DevTables*>(d_tables), s, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? QED_OK : QED_ERR_HIP;
+}
+
+size_t qed_work_bytes(int n_instances) {
+  if (n_instances < 1) return 0;
+  return WorkLayout::make(n_instances).total;
+}
+
+qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_field* field,
+                    const qed_params* params, int64_t* d_step, qed_stats* d_stats, void* d_work,
+                    size_t work_bytes, void* stream) {
+  if (!d_tables || !stores || !field || !params || !d_step || !d_stats || !d_work)
+    return QED_ERR_ARG;
+  const qed_params& P = *params;
+  const int ni = stores->n_instances;
+  if (ni < 1 || !stores->d_instances) return QED_ERR_ARG;
+  if (work_bytes < qed_work_bytes(ni) || (reinterpret_cast<uintptr_t>(d_work) & 63u))
+    return QED_ERR_ARG;
+  if (!soa_ok(stores->species[QED_ELECTRON], true) || !soa_ok(stores->species[QED_POSITRON], true))
+    return QED_ERR_ARG;
+  const bool run_photons = P.pairs || P.push_photons;
+  if ((P.emission || run_photons) && !soa_ok(stores->species[QED_PHOTON], false))
+    return QED_ERR_ARG;
+  if (!finite_pos(P.dt) || !finite_pos(P.eps_r) || !finite_pos(P.kappa) || !isfinite(P.t0))
+    return QED_ERR_ARG;
+  if (P.precision != QED_FP64 && P.precision != QED_MIXED) return QED_ERR_ARG;
+  if (P.forced_substeps < 0 || P.forced_substeps > QED_NSUB_MAX) return QED_ERR_ARG;
+  if (P.tile < 0 || P.grid_blocks < 0) return QED_ERR_ARG;
+  const int block = P.block == 0 ? 256 : P.block;
+  if (block < 64 || block > 256 || (block & 63)) return QED_ERR_ARG;
+
+  StepArgs a{};
+  for (int s = 0; s < 3; ++s) a.sp[s] = stores->species[s];
+  a.inst = stores->d_instances;
+  a.n_inst = ni;
+  a.tables = static_cast<const DevTables*>(d_tables);
+  a.field.kind = field->kind;
+  switch (field->kind) {
+    case QED_FIELD_UNIFORM:
+      for (int d = 0; d < 3; ++d) {
+        if (!isfinite(field->e0[d]) || !isfinite(field->b0[d])) return QED_ERR_ARG;
+        a.e0[d] = field->e0[d];
+        a.b0[d] = field->b0[d];
+      }
+      break;
+    case QED_FIELD_ROTATING_E:
+    case QED_FIELD_CP_STANDING:
+      if (!isfinite(field->amp) || !isfinite(field->omega) || !isfinite(field->phase))
+        return QED_ERR_ARG;
+      break;
+    case QED_FIELD_YEE:
+      for (int c = 0; c < 6; ++c)
+        if (!field->grid[c]) return QED_ERR_ARG;
+      for (int d = 0; d < 3; ++d) {
+        if (field->n[d] < 2 || !finite_pos(field->dx[d]) || !isfinite(field->origin[d]))
+          return QED_ERR_ARG;
+        a.field.n[d] = field->n[d];
+        a.field.inv_dx[d] = 1.0 / field->dx[d];
+        a.field.origin[d] = field->origin[d];
+      }
+      for (int c = 0; c < 6; ++c) a.field.grid[c] = field->grid[c];
+      break;
+    default:
+      return QED_ERR_ARG;
+  }
+  a.field.amp = field->amp;
+  a.field.omega = field->omega;
+  a.field.phase = field->phase;
+  a.field.tn = 0.0;  // filled per step on the device for the position-dependent kinds
+  a.dt = P.dt;
+  a.t0 = P.t0;
+  a.eps_r = P.eps_r;
+  a.inv_lep_scale = 1.0 / (P.kappa * 28.0 * kPi * P.eps_r);
+  a.inv_pho_scale = 1.0 / (P.kappa * 260.0 * kPi * P.eps_r);
+  a.dtfac_per_h = kAlpha / P.eps_r;
+  a.adaptive = P.adaptive;
+  a.forced = P.forced_substeps;
+  a.emission = P.emission;
+  a.pairs = P.pairs;
+  a.push_photons = P.push_photons;
+  a.freeze_on_drop = P.freeze_on_drop;
+  a.tile = P.tile > 0 ? P.tile : 1024;
+  const WorkLayout L = WorkLayout::make(ni);
+  uint8_t* w = static_cast<uint8_t*>(d_work);
+  a.hdr = reinterpret_cast<WorkHdr*>(w);
+  a.n0 = reinterpret_cast<long long*>(w + L.n0);
+  a.lep_pref = reinterpret_cast<long long*>(w + L.lep_pref);
+  a.pho_pref = reinterpret_cast<long long*>(w + L.pho_pref);
+  a.eb = reinterpret_cast<double*>(w + L.eb);
+  a.stats = d_stats;
+  a.d_step = reinterpret_cast<long long*>(d_step);
+  for (int i = 0; i < 4; ++i) a.events[i] = static_cast<hipEvent_t>(P.events[i]);
+
+  int cus = 0, lep_per_cu = 0, pho_per_cu = 0;
+  if (!device_geometry(&cus, P.precision, false, block, &lep_per_cu) ||
+      !device_geometry(&cus, P.precision, true, block, &pho_per_cu))
+    return QED_ERR_HIP;
+  LaunchShape lep{P.grid_blocks > 0 ? P.grid_blocks : cus * lep_per_cu, block};
+  LaunchShape pho{P.grid_blocks > 0 ? P.grid_blocks : cus * pho_per_cu, block};
+  const hipError_t e =
+      launch_step(a, P.precision, lep, pho, run_photons, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? QED_OK : QED_ERR_HIP;
+}
+
+qed_status qed_append_stats(const qed_stats* d_stats, qed_stats* d_log, int64_t log_capacity,
+                            int64_t* d_log_count, void* stream) {
+  if (!d_stats || !d_log || !d_log_count || log_capacity < 0) return QED_ERR_ARG;
+  const hipError_t e =
+      launch_append_stats(d_stats, d_log, (long long)log_capacity,
+                          reinterpret_cast<long long*>(d_log_count), static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? QED_OK : QED_ERR_HIP;
+}
+
+qed_status qed_photon_spectrum(const qed_stores* stores, double lo, double hi, int bins,
+                               double* d_hist, void* stream) {
+  if (!stores || !d_hist || !stores->d_instances || stores->n_instances < 1 ||
+      stores->n_instances > 65535 || bins < 1 || !finite_pos(lo) || !finite_pos(hi) || hi <= lo)
+    return QED_ERR_ARG;
+  if (!soa_ok(stores->species[QED_PHOTON], false)) return QED_ERR_ARG;
+  const hipError_t e = launch_spectrum(stores->species[QED_PHOTON], stores->d_instances,
+                                       stores->n_instances, lo, hi, bins, d_hist,
+                                       static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? QED_OK : QED_ERR_HIP;
+}
+
+qed_status qed_fill_standing_wave(float* const d_grid[6], const int n[3], const double dx[3],
+                                  const double origin[3], double amp, double omega,
+                                  double phase, double t, void* stream) {
+  if (!d_grid || !n || !dx || !origin) return QED_ERR_ARG;
+  for (int c = 0; c < 6; ++c)
+    if (!d_grid[c]) return QED_ERR_ARG;
+  for (int d = 0; d < 3; ++d)
+    if (n[d] < 1 || !finite_pos(dx[d]) || !isfinite(origin[d])) return QED_ERR_ARG;
+  if (!isfinite(amp) || !isfinite(omega) || !isfinite(phase) || !isfinite(t)) return QED_ERR_ARG;
+  const hipError_t e = launch_fill_standing(d_grid, n, dx, origin, amp, omega, phase, t,
+                                            static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? QED_OK : QED_ERR_HIP;
+}
+
+const char* qed_status_string(qed_status s) {
+  switch (s) {
+    case QED_OK: return "ok";
+    case QED_ERR_ARG: return "invalid argument";
+    case QED_ERR_HIP: return "HIP runtime or launch failure";
+    case QED_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+int qed_version(void) { return 100; }
+
+}  // extern "C"

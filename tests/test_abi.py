@@ -1,0 +1,91 @@
+"""The C-ABI library loads, exports every symbol include/qed.h declares, and validates its
+arguments on the host (no GPU needed: no compute call is made)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qed.h")
+
+
+@pytest.fixture(scope="module")
+def Q():
+    from paper_1412_6426_amd import build, qed
+    if not os.path.exists(qed.LIB_PATH):
+        build.build()
+    qed.lib()
+    return qed
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(qed_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_three_calls():
+    names = declared_functions()
+    for must in ("qed_build_tables", "qed_step", "qed_append_stats"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(Q):
+    lib = C.CDLL(Q.LIB_PATH)
+    names = declared_functions()
+    assert set(names) == set(Q.EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_ctypes_layout_matches_header(Q, tmp_path):
+    """Compile a probe against include/qed.h with gcc and compare every struct's size and
+    every field's offset with the ctypes mirror."""
+    structs = [Q.qed_soa, Q.qed_instance, Q.qed_stores, Q.qed_field, Q.qed_params, Q.qed_stats]
+    lines = ['#include "qed.h"', "#include <stdio.h>", "#include <stddef.h>", "int main(void){"]
+    expect = []
+    for S in structs:
+        lines.append(f'printf("%zu\\n", sizeof({S.__name__}));')
+        expect.append(C.sizeof(S))
+        for name, _ in S._fields_:
+            lines.append(f'printf("%zu\\n", offsetof({S.__name__}, {name}));')
+            expect.append(getattr(S, name).offset)
+    lines.append("return 0;}")
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    import subprocess
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    assert got == expect
+    assert Q.qed_table_bytes() == 198656
+
+
+def test_host_side_queries(Q):
+    assert Q.qed_version() >= 100
+    assert Q.qed_work_bytes(0) == 0
+    w1, w64 = Q.qed_work_bytes(1), Q.qed_work_bytes(64)
+    assert 64 <= w1 < w64
+    assert Q.lib().qed_status_string(1) == b"invalid argument"
+
+
+def test_argument_validation_without_device(Q):
+    L = Q.lib()
+    assert L.qed_build_tables(None, 0, None) == Q.QED_ERR_ARG
+    assert L.qed_build_tables(C.c_void_p(256), 16, None) == Q.QED_ERR_ARG  # too small
+    assert L.qed_build_tables(C.c_void_p(8), 1 << 20, None) == Q.QED_ERR_ARG  # misaligned
+    st = Q.qed_stores()
+    f = Q.qed_field()
+    p = Q.qed_params()
+    # null everything
+    assert L.qed_step(None, C.byref(st), C.byref(f), C.byref(p), None, None, None, 0,
+                      None) == Q.QED_ERR_ARG
+    # no instances
+    fake = C.c_void_p(4096)
+    assert L.qed_step(fake, C.byref(st), C.byref(f), C.byref(p), fake, fake, fake, 1 << 20,
+                      None) == Q.QED_ERR_ARG
+    assert L.qed_append_stats(None, None, 0, None, None) == Q.QED_ERR_ARG
+    assert L.qed_photon_spectrum(C.byref(st), 1.0, 0.5, 10, fake, None) == Q.QED_ERR_ARG

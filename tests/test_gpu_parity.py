@@ -1,0 +1,303 @@
+"""GPU (HIP, through the C ABI) vs the FP64 CPU oracle, element by element.
+
+Integers (ids, parent ids, birth codes, event counts, counts of removed photons) must be
+bit-exact; momenta and positions agree within 1e-12 of max(|v|, 1); weights exactly.
+The near-threshold counter reports decisions within 1e-12 of their acceptance
+probability, the only ones allowed to flip (none did in these cases)."""
+import math
+
+import numpy as np
+import pytest
+
+from tests.conftest import gpu_available
+from tests.parity_util import (compare_all, compare_species, oracle_field, oracle_params,
+                               oracle_stores)
+
+pytestmark = pytest.mark.gpu
+
+if not gpu_available():
+    pytest.skip("needs a HIP device", allow_module_level=True)
+
+import torch  # noqa: E402
+
+from paper_1412_6426_amd import qed as Q  # noqa: E402
+from paper_1412_6426_amd import runner as R  # noqa: E402
+from paper_1412_6426_amd import workloads as W  # noqa: E402
+from paper_1412_6426_amd.engine import Engine  # noqa: E402
+
+
+def _note(msg):
+    print(msg, flush=True)
+
+
+# ---------------------------------------------------------------------------------------
+def test_tables_match_oracle(orc):
+    _note("tables")
+    e = Engine([(1, 1, 1)], [0])
+    e.build_tables()
+    torch.cuda.synchronize()
+    raw = e.tables.cpu().numpy()
+    ab = raw[0:65536].view(np.float64).reshape(4096, 2)
+    bc = raw[65536:131072].view(np.float64).reshape(4096, 2)
+    ab32 = raw[131072:163840].view(np.float32).reshape(4096, 2)
+    bound = raw[196608:197632].view(np.float64)
+    series = raw[198144:198208].view(np.float64)
+    magic = raw[198208:198212].view(np.uint32)[0]
+    gA, gB, gC = orc.table_arrays()
+    np.testing.assert_allclose(ab[:, 0], gA, rtol=1e-13, atol=0)
+    np.testing.assert_allclose(ab[:, 1], gB, rtol=1e-13, atol=0)
+    np.testing.assert_allclose(bc[:, 0], gB, rtol=1e-13, atol=0)
+    np.testing.assert_allclose(bc[:, 1], gC, rtol=1e-13, atol=0)
+    assert np.array_equal(ab32, ab.astype(np.float32))
+    t = orc.tables()
+    np.testing.assert_allclose(series[:5], [t.s_b0, t.s_b1, t.s_c0, t.s_c1, t.s_c2], rtol=1e-14)
+    assert magic == 0x51454454
+    # the per-octave bound really bounds the pair bracket (oracle, exact rates)
+    for j in (40, 55, 62, 64, 66, 70, 80):
+        chi = 2.0 ** (j - 64)
+        d = np.linspace(1e-4, 0.5, 2000)
+        brk = [orc.rate_pair(x, chi, 1.0, 1.0, orc.EXACT) * math.sqrt(3) * math.pi for x in d]
+        assert max(brk) <= bound[j]
+
+
+def test_uniform_b_full_size_parity(orc):
+    """Uniform static B, 10^4 electrons at gamma = 1000 (chi = 1), dt = T_gyro/100,
+    100 steps, emission only, photons recorded: the whole run, both stores."""
+    w = W.uniform_b()
+    init = W.uniform_b_initial(w)
+    _note(f"uniform_b full: {w.description}")
+    e = R.engine_single(w, init)
+    stats = R.run(e, R.field_of(w), R.params_of(w), w.n_steps)
+    os_ = oracle_stores(orc, init, w.capacity)
+    ostats = orc.run(os_, oracle_field(orc, w), oracle_params(orc, w), w.n_steps)
+    assert sum(s["near_threshold"] for s in stats) == 0
+    assert [s["emitted"] for s in stats] == [s["emitted"] for s in ostats]
+    assert all(s["nsub_hist"][8] == 10_000 for s in stats)
+    compare_all(e, os_, label="uniform_b")
+    assert sum(s["saturated"] for s in stats) == 0 and stats[-1]["status"] == 0
+
+
+@pytest.mark.parametrize("precision_check", ["f64"])
+def test_rotating_cascade_parity(orc, precision_check):
+    """Rotating-E cascade (a0 = 1000, lambda = 0.8 um, dt = T/200) from 300 seeds through
+    300 steps: emission, pairs, photon push; every store compared."""
+    w = W.rotating_e(n=300, periods=1.5, capacity=400_000, lepton_capacity=40_000)
+    init = W.rotating_e_initial(300, seed=3)
+    _note(f"rotating cascade: {w.description}")
+    e = R.engine_single(w, init)
+    stats = R.run(e, R.field_of(w), R.params_of(w), w.n_steps)
+    os_ = oracle_stores(orc, init, w.capacity)
+    ostats = orc.run(os_, oracle_field(orc, w), oracle_params(orc, w), w.n_steps)
+    assert len(stats) == len(ostats) == w.n_steps
+    assert sum(s["pairs"] for s in stats) > 20
+    assert [s["pairs"] for s in stats] == [s["pairs"] for s in ostats]
+    assert [s["emitted"] for s in stats] == [s["emitted"] for s in ostats]
+    assert sum(s["near_threshold"] for s in stats) == 0
+    compare_all(e, os_, label="rotating")
+
+
+def test_forced_substeps_and_nonadaptive(orc):
+    w = W.rotating_e(n=97, periods=0.25, capacity=50_000, lepton_capacity=5000)
+    init = W.rotating_e_initial(97, seed=9)
+    for over in (dict(forced_substeps=5), dict(adaptive=0)):
+        _note(f"substep variant {over}")
+        e = R.engine_single(w, init)
+        R.run(e, R.field_of(w), R.params_of(w, **over), w.n_steps)
+        os_ = oracle_stores(orc, init, w.capacity)
+        orc.run(os_, oracle_field(orc, w), oracle_params(orc, w, **over), w.n_steps)
+        compare_all(e, os_, label=str(over))
+
+
+def test_empty_and_single_particle(orc):
+    w = W.rotating_e(n=1, periods=0.1, capacity=1000, lepton_capacity=100)
+    _note("empty store")
+    e = R.engine_single(w, [W.empty_columns()] * 3)
+    st = R.run(e, R.field_of(w), R.params_of(w), 3)
+    assert st[-1]["counts"] == [[0, 0, 0]] and st[-1]["substeps"] == 0
+    assert int(e.step_ctr.item()) == 3
+    _note("single particle")
+    init = W.rotating_e_initial(1, seed=1)
+    e = R.engine_single(w, init)
+    R.run(e, R.field_of(w), R.params_of(w), w.n_steps)
+    os_ = oracle_stores(orc, init, w.capacity)
+    orc.run(os_, oracle_field(orc, w), oracle_params(orc, w), w.n_steps)
+    compare_all(e, os_, label="single")
+
+
+def test_capacity_overflow_is_counted_and_contained(orc):
+    """Tiny photon capacity: drops counted, count clamped, nothing written past the
+    instance's segment (a guard instance after it keeps its contents)."""
+    w = W.uniform_b(n=500, steps=2)
+    init = W.uniform_b_initial(w)
+    _note("capacity overflow")
+    e = Engine([(500, 1, 40), (1, 1, 64)], [0, 1])
+    e.build_tables()
+    for s in range(3):
+        e.load(0, s, init[s])
+    guard = W._seed_columns(*[np.full(64, 7.0)] * 6)
+    guard["n_events"] = np.zeros(64, np.uint32)
+    e.load(1, 2, guard)
+    st = R.run(e, R.field_of(w), R.params_of(w), 1)
+    assert st[0]["dropped"] > 0 and st[0]["status"] & Q.QED_STATUS_DROPPED
+    inst = e.instances()
+    assert inst[0]["count"][2] == 40 and inst[0]["dropped"] == st[0]["dropped"]
+    g = e.read(1, 2)
+    assert np.all(g["x"] == 7.0) and np.all(g["pz"] == 7.0)
+    assert st[0]["emitted"] == 40 + st[0]["dropped"]
+
+
+def test_failure_counters(orc):
+    w = W.uniform_b(n=20, steps=1)
+    init = W.uniform_b_initial(w)
+    init[0]["px"] = init[0]["px"].copy()
+    init[0]["px"][3] = np.nan
+    _note("nonfinite")
+    e = R.engine_single(w, init)
+    st = R.run(e, R.field_of(w), R.params_of(w), 1)
+    assert st[0]["nonfinite"] > 0 and st[0]["status"] & Q.QED_STATUS_NONFINITE
+    _note("saturation")
+    e = R.engine_single(w, W.uniform_b_initial(w))
+    p = R.params_of(w, adaptive=0, dt=50 * w.dt)
+    st = R.run(e, R.field_of(w), p, 1)
+    assert st[0]["saturated"] > 0 and st[0]["status"] & Q.QED_STATUS_SATURATED
+    _note("tables not built")
+    e = R.engine_single(w, W.uniform_b_initial(w), build_tables=False)
+    st = R.run(e, R.field_of(w), R.params_of(w), 1)
+    assert st[0]["status"] & Q.QED_STATUS_NO_TABLES and st[0]["substeps"] == 0
+
+
+def _batched_oracle(orc, w, inits, i, periods):
+    wi = W.rotating_e(n=w.instance_n[i], a0=w.instance_amp[i], periods=periods, seed=i,
+                      capacity=w.instance_capacity[2], lepton_capacity=w.instance_capacity[1])
+    os_ = oracle_stores(orc, inits[i], w.instance_capacity)
+    ost = orc.run(os_, oracle_field(orc, wi), oracle_params(orc, wi), w.n_steps)
+    return os_, ost
+
+
+def test_batched_instances_match_single_runs(orc):
+    """Five instances of different size, amplitude and seed (one empty) in one launch:
+    each equals its own oracle run."""
+    w = W.batched_rotating(instances=5, a_lo=600.0, a_hi=2400.0, periods=0.75,
+                           n_override=[37, 0, 129, 64, 200], total_capacity=5 * 400_000,
+                           precision="f64")
+    inits = W.batched_initial(w)
+    _note(f"batched: {w.description}")
+    e = R.engine_batched(w, inits)
+    st = R.run(e, R.field_of(w), R.params_of(w), w.n_steps, stop_on_drop=False)
+    assert sum(s["dropped"] for s in st) == 0
+    for i in range(w.instances):
+        os_, _ = _batched_oracle(orc, w, inits, i, 0.75)
+        compare_all(e, os_, inst=i, label=f"instance {i}")
+
+
+def test_batched_freeze_on_drop(orc):
+    """An instance that runs out of photon slots freezes after that step; the others keep
+    going and still equal their oracle runs."""
+    w = W.batched_rotating(instances=3, a_lo=700.0, a_hi=2400.0, periods=0.75,
+                           n_override=[50, 40, 200], total_capacity=3 * 30_000,
+                           precision="f64")
+    inits = W.batched_initial(w)
+    _note("batched freeze")
+    e = R.engine_batched(w, inits)
+    st = R.run(e, R.field_of(w), R.params_of(w), w.n_steps, stop_on_drop=False)
+    inst = e.instances()
+    assert inst[2]["dropped"] > 0 and inst[2]["frozen"] == 1
+    assert inst[2]["count"][2] == w.instance_capacity[2]
+    first = next(k for k, s in enumerate(st) if s["dropped"] > 0)
+    assert first < w.n_steps - 1  # the freeze is exercised for at least one step
+    for i in (0, 1):
+        assert inst[i]["frozen"] == 0
+        os_, _ = _batched_oracle(orc, w, inits, i, 0.75)
+        compare_all(e, os_, inst=i, label=f"instance {i}")
+    # the frozen instance equals the oracle stopped at the same step, up to which
+    # children were dropped: compare its leptons (unaffected by photon drops)
+    os_, ost = _batched_oracle(orc, w, inits, 2, 0.75)
+    assert len(ost) == first + 1
+    compare_species(e.read(2, 0), os_[0].view(), 0, label="frozen e-")
+    compare_species(e.read(2, 1), os_[1].view(), 1, label="frozen e+")
+
+
+def test_runs_are_reproducible(orc):
+    w = W.rotating_e(n=500, periods=0.6, capacity=100_000, lepton_capacity=10_000)
+    init = W.rotating_e_initial(500, seed=4)
+    outs = []
+    for rep in range(2):
+        _note(f"determinism run {rep}")
+        e = R.engine_single(w, init)
+        R.run(e, R.field_of(w), R.params_of(w, tile=64 * (rep + 1)), w.n_steps)
+        outs.append([e.read(0, s) for s in range(3)])
+    for s in range(3):
+        compare_species(outs[0][s], outs[1][s], s, rtol=0.0, label="rerun")
+
+
+def test_stats_log_and_graph_replay(orc):
+    """Steps captured once in a hipGraph and replayed equal eager steps; qed_append_stats
+    appends one record per replay."""
+    w = W.rotating_e(n=400, periods=0.5, capacity=100_000, lepton_capacity=10_000)
+    init = W.rotating_e_initial(400, seed=5)
+    _note("eager reference")
+    ref = R.engine_single(w, init)
+    R.run(ref, R.field_of(w), R.params_of(w), w.n_steps)
+    _note("graph replay")
+    e = R.engine_single(w, init)
+    log = torch.zeros((w.n_steps + 5) * e.stats_buf.numel(), dtype=torch.uint8, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    f, p = R.field_of(w), R.params_of(w)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        e.step(f, p, stream=s.cuda_stream)  # warm-up outside the graph
+        Q.qed_append_stats(e.stats_buf.data_ptr(), log.data_ptr(), w.n_steps + 5,
+                           cnt.data_ptr(), s.cuda_stream)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=s):
+        e.step(f, p, stream=s.cuda_stream)
+        Q.qed_append_stats(e.stats_buf.data_ptr(), log.data_ptr(), w.n_steps + 5,
+                           cnt.data_ptr(), s.cuda_stream)
+    for _ in range(w.n_steps - 1):
+        g.replay()
+        torch.cuda.synchronize()
+    assert int(cnt.item()) == w.n_steps
+    assert int(e.step_ctr.item()) == w.n_steps
+    for sp in range(3):
+        compare_species(e.read(0, sp), ref.read(0, sp), sp, rtol=0.0, label="graph")
+    recs = log.cpu().numpy()[:w.n_steps * e.stats_buf.numel()].view(np.int64)
+    steps = recs.reshape(w.n_steps, -1)[:, 0]
+    assert list(steps) == list(range(w.n_steps))
+
+
+def test_yee_grid_parity(orc):
+    """Standing-wave cascade on a small periodic Yee grid (32^3, lambda/32 cells): the
+    same FP32 grid values (sampled at every t_n) feed both sides."""
+    w = W.standing_wave_grid(n=300, cells=32, capacity=200_000, lepton_capacity=20_000,
+                             steps=40, a0=2000.0)
+    init = W.standing_wave_initial(300, seed=2)
+    _note(f"yee grid: {w.description}")
+    e = R.engine_single(w, init)
+    grid = R.YeeGrid(w)
+    f = R.field_of(w, grid=grid.g)
+    p = R.params_of(w)
+    os_ = oracle_stores(orc, init, w.capacity)
+    op = oracle_params(orc, w)
+    e.set_step(0)
+    for n in range(w.n_steps):
+        vals = W.standing_wave_grid_values(w.field, w.t0 + n * w.dt)
+        grid.load_numpy(vals)
+        e.step(f, p)
+        torch.cuda.synchronize()
+        op.step = n
+        orc.step(os_, oracle_field(orc, w, grids=vals), op)
+    assert e.stats()["n_start"][2] > 100
+    compare_all(e, os_, label="yee")
+
+
+def test_fill_standing_wave_matches_numpy():
+    w = W.standing_wave_grid(n=1, cells=16)
+    grid = R.YeeGrid(w)
+    t = 0.37
+    grid.fill(t, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    want = W.standing_wave_grid_values(w.field, t)
+    for g, v in zip(grid.g, want):
+        np.testing.assert_allclose(g.cpu().numpy(), v, rtol=2e-7, atol=1e-3)
