@@ -160,9 +160,12 @@ typedef struct {
   int push_photons;     /* photons advance at c along k */
   int precision;        /* qed_precision */
   int freeze_on_drop;   /* 1: an instance that dropped children is frozen from the next step */
-  int tile;             /* particles per work tile; 0 = library default */
-  int block;            /* threads per workgroup (64..1024, multiple of 64); 0 = default */
-  int grid_blocks;      /* persistent workgroups per kernel; 0 = from the device's CU count */
+  int tile;             /* work split: each wavefront takes chunks of `tile` consecutive
+                           particles, dealt round-robin; 0 = one contiguous chunk per
+                           wavefront (N / wavefronts) */
+  int block;            /* threads per workgroup (64..256, multiple of 64); 0 = 256 */
+  int grid_blocks;      /* persistent workgroups per kernel (<= 4096); 0 = resident
+                           workgroups per CU times the CU count */
   void *events[4];      /* optional hipEvent_t recorded on `stream` right before/after the
                            lepton kernel ([0], [1]) and the photon kernel ([2], [3]); NULL
                            entries are skipped.  Owned by the caller. */

@@ -92,7 +92,7 @@ qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_fi
     return QED_ERR_ARG;
   if (P.precision != QED_FP64 && P.precision != QED_MIXED) return QED_ERR_ARG;
   if (P.forced_substeps < 0 || P.forced_substeps > QED_NSUB_MAX) return QED_ERR_ARG;
-  if (P.tile < 0 || P.grid_blocks < 0) return QED_ERR_ARG;
+  if (P.tile < 0 || P.grid_blocks < 0 || P.grid_blocks > kMaxGridBlocks) return QED_ERR_ARG;
   const int block = P.block == 0 ? 256 : P.block;
   if (block < 64 || block > 256 || (block & 63)) return QED_ERR_ARG;
 
@@ -146,7 +146,7 @@ qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_fi
   a.pairs = P.pairs;
   a.push_photons = P.push_photons;
   a.freeze_on_drop = P.freeze_on_drop;
-  a.tile = P.tile > 0 ? P.tile : 1024;
+  a.tile = P.tile;
   const WorkLayout L = WorkLayout::make(ni);
   uint8_t* w = static_cast<uint8_t*>(d_work);
   a.hdr = reinterpret_cast<WorkHdr*>(w);
@@ -154,6 +154,8 @@ qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_fi
   a.lep_pref = reinterpret_cast<long long*>(w + L.lep_pref);
   a.pho_pref = reinterpret_cast<long long*>(w + L.pho_pref);
   a.eb = reinterpret_cast<double*>(w + L.eb);
+  a.lep_part = reinterpret_cast<unsigned long long*>(w + L.lep_part);
+  a.pho_part = reinterpret_cast<unsigned long long*>(w + L.pho_part);
   a.stats = d_stats;
   a.d_step = reinterpret_cast<long long*>(d_step);
   for (int i = 0; i < 4; ++i) a.events[i] = static_cast<hipEvent_t>(P.events[i]);
@@ -164,6 +166,10 @@ qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_fi
     return QED_ERR_HIP;
   LaunchShape lep{P.grid_blocks > 0 ? P.grid_blocks : cus * lep_per_cu, block};
   LaunchShape pho{P.grid_blocks > 0 ? P.grid_blocks : cus * pho_per_cu, block};
+  if (lep.grid > kMaxGridBlocks) lep.grid = kMaxGridBlocks;
+  if (pho.grid > kMaxGridBlocks) pho.grid = kMaxGridBlocks;
+  a.lep_grid = lep.grid;
+  a.pho_grid = run_photons ? pho.grid : 0;
   const hipError_t e =
       launch_step(a, P.precision, lep, pho, run_photons, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? QED_OK : QED_ERR_HIP;

@@ -9,37 +9,54 @@
 
 namespace qedk {
 
-// Header of the qed_step workspace; followed by the per-instance arrays laid out by
-// WorkLayout.
+// Upper bound of workgroups per persistent kernel (the workspace holds one partial stats
+// record per workgroup).
+constexpr int kMaxGridBlocks = 4096;
+
+// Per-workgroup partial stats: 64-bit words, stored field-major ([field][block]) so that
+// the finalize kernel reduces each field with coalesced loads.
+enum PartialField : int {
+  kPfSubsteps = 0, kPfEvents, kPfSaturated, kPfNear, kPfNonfinite, kPfNearInt, kPfClamped,
+  kPfDropped, kPfEarly, kPfAdv0, kPfAdv1, kPfWaveIters, kPfLowOcc,
+  kPfEnergy,  // double bits
+  kPfMaxP,    // double bits
+  kPfNsub,    // QED_NSUB_HIST words
+  kPfHist = kPfNsub + QED_NSUB_HIST,  // QED_SPECTRUM_BINS words
+  kPfCount = kPfHist + QED_SPECTRUM_BINS
+};
+
+// Header of the qed_step workspace; followed by the arrays laid out by WorkLayout.
 struct alignas(64) WorkHdr {
-  unsigned long long lep_queue;  // next lepton tile to hand out
-  unsigned long long pho_queue;  // next photon tile
-  long long lep_tiles;           // lepton tiles this step
-  long long pho_tiles;           // photon tiles this step
-  long long step;                // global step index n
-  double tn;                     // field time t0 + n dt
+  long long lep_total;  // leptons (e- and e+, all instances) alive at the step start
+  long long pho_total;  // photon slots to visit (0 when the photon kernel does not run)
+  long long step;       // global step index n
+  double tn;            // field time t0 + n dt
   uint32_t tables_ok;
-  uint32_t reserved[3];
+  uint32_t reserved[7];
 };
 
 struct WorkLayout {
   size_t n0;        // long long [n_inst * 3]: live slots at step start (0 when frozen)
-  size_t lep_pref;  // long long [2 n_inst + 1]: tile prefix over (instance, e-/e+) segments
-  size_t pho_pref;  // long long [n_inst + 1]
+  size_t lep_pref;  // long long [2 n_inst + 1]: particle prefix over (instance, e-/e+)
+  size_t pho_pref;  // long long [n_inst + 1]: particle prefix over instances
   size_t eb;        // double [n_inst * 6]: E, B of space-independent fields at t_n
+  size_t lep_part;  // uint64 [kPfCount][kMaxGridBlocks]
+  size_t pho_part;  // uint64 [kPfCount][kMaxGridBlocks]
   size_t total;
   static WorkLayout make(int n_inst) {
     WorkLayout L;
     size_t off = sizeof(WorkHdr);
     auto take = [&off](size_t bytes) {
       size_t o = off;
-      off += (bytes + 63) & ~(size_t)63;
+      off += (bytes + 255) & ~(size_t)255;
       return o;
     };
     L.n0 = take(sizeof(long long) * 3 * (size_t)n_inst);
     L.lep_pref = take(sizeof(long long) * (2 * (size_t)n_inst + 1));
     L.pho_pref = take(sizeof(long long) * ((size_t)n_inst + 1));
     L.eb = take(sizeof(double) * 6 * (size_t)n_inst);
+    L.lep_part = take(sizeof(unsigned long long) * kPfCount * kMaxGridBlocks);
+    L.pho_part = take(sizeof(unsigned long long) * kPfCount * kMaxGridBlocks);
     L.total = off;
     return L;
   }
@@ -57,12 +74,15 @@ struct StepArgs {
   double inv_pho_scale;  // 1 / (kappa 260 pi eps_r)
   double dtfac_per_h;    // alpha / eps_r
   int adaptive, forced, emission, pairs, push_photons, freeze_on_drop;
-  long long tile;
+  long long tile;  // particles per work chunk (0: one chunk per wavefront)
   WorkHdr* hdr;
   long long* n0;
   long long* lep_pref;
   long long* pho_pref;
   double* eb;
+  unsigned long long* lep_part;
+  unsigned long long* pho_part;
+  int lep_grid, pho_grid;  // workgroups of the two persistent kernels
   qed_stats* stats;
   long long* d_step;
   hipEvent_t events[4];

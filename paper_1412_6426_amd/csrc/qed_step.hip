@@ -2,23 +2,31 @@
 // of Gonoskov et al., arXiv:1412.6426, with the Sec. V.A pair generator).
 //
 // One step is four launches on the caller's stream:
-//   prep     (1 workgroup)  snapshot live counts, tile prefix sums, space-independent
-//                           fields at t_n, zero the stats record;
+//   prep     (1 workgroup)  snapshot live counts, particle prefix sums over the
+//                           (instance, species) segments, space-independent fields at t_n,
+//                           zero the stats record;
 //   leptons  (persistent)   electrons and positrons: push, chi, emission, photon append;
 //   photons  (persistent)   photons: push, chi_gamma, pair creation, e-/e+ append;
-//   finalize (1 workgroup)  clamp counts, status bits, step index + 1.
+//   finalize (1 workgroup)  reduce per-workgroup partial stats, clamp counts, status bits,
+//                           step index + 1.
 // Children land after the step-start counts, so they are first processed at step n+1.
 //
-// Work distribution: each wavefront pulls tiles of `tile` consecutive slots from a global
-// queue and keeps its 64 lanes busy by refilling any lane whose particle has finished all
-// of its sub-steps from the current tile ("per-wavefront work queue"): a wavefront
-// iteration advances every active lane by exactly one sub-step, so lanes with n_sub = 1 and
-// n_sub = 20 share a wavefront without idling.  Rate tables are staged once per workgroup
-// into LDS.  New particles are appended with one wavefront ballot, a prefix popcount and a
-// single atomic reservation per (wavefront, instance).
+// Work distribution: the particles alive at the step start form one index space per kernel
+// (segments of all instances laid end to end).  Each wavefront owns fixed chunks of it --
+// no queue, no atomics -- and keeps its 64 lanes busy by refilling any lane whose particle
+// has finished all of its sub-steps from the next particles of its chunk ("per-wavefront
+// work queue"): one wavefront iteration advances every active lane by one sub-step, so
+// lanes with n_sub = 1 and n_sub = 20 share a wavefront without idling.
+//
+// Appends: emitted photons and created pairs are staged per wavefront in LDS and reserved
+// in batches of up to 32 with one atomic per (batch, instance, species).  Statistics are reduced per workgroup in LDS and written as
+// partials; the finalize kernel sums them, so no global atomic is issued per wavefront.
 #include "qed_internal.h"
 
 namespace qedk {
+
+constexpr int kWavesPerBlock = 4;  // launch bound 256 threads
+constexpr int kStageCap = 32;      // staged photon children per wavefront
 
 // ------------------------------------------------------------------------------------
 // prep / finalize
@@ -57,30 +65,27 @@ __global__ void __launch_bounds__(256) prep_kernel(StepArgs a, int run_photons) 
       eb[2] = eb[3] = eb[4] = eb[5] = 0.0;
     }
   }
-  // zero the stats record
   unsigned long long* sw = reinterpret_cast<unsigned long long*>(a.stats);
   for (int w = threadIdx.x; w < (int)(sizeof(qed_stats) / 8); w += blockDim.x) sw[w] = 0ull;
   __syncthreads();
   if (threadIdx.x == 0) {
-    long long lt = 0, pt = 0, ns[3] = {0, 0, 0};
+    long long lp = 0, pp = 0, ns[3] = {0, 0, 0};
     a.lep_pref[0] = 0;
     a.pho_pref[0] = 0;
     for (int i = 0; i < a.n_inst; ++i) {
       for (int s = 0; s < 2; ++s) {
         const long long c = a.n0[i * 3 + s];
-        lt += (c + a.tile - 1) / a.tile;
-        a.lep_pref[2 * i + s + 1] = lt;
+        lp += c;
+        a.lep_pref[2 * i + s + 1] = lp;
         ns[s] += c;
       }
       const long long c = a.n0[i * 3 + 2];
-      if (run_photons) pt += (c + a.tile - 1) / a.tile;
-      a.pho_pref[i + 1] = pt;
+      if (run_photons) pp += c;
+      a.pho_pref[i + 1] = pp;
       ns[2] += c;
     }
-    hdr->lep_queue = 0ull;
-    hdr->pho_queue = 0ull;
-    hdr->lep_tiles = lt;
-    hdr->pho_tiles = pt;
+    hdr->lep_total = lp;
+    hdr->pho_total = pp;
     hdr->step = n;
     hdr->tn = tn;
     hdr->tables_ok = (uint32_t)ok;
@@ -90,14 +95,75 @@ __global__ void __launch_bounds__(256) prep_kernel(StepArgs a, int run_photons) 
   }
 }
 
-__global__ void __launch_bounds__(256) finalize_kernel(StepArgs a) {
+__device__ __forceinline__ void stats_add(int64_t* p, unsigned long long v) {
+  if (v) atomicAdd(reinterpret_cast<unsigned long long*>(p), v);
+}
+
+__global__ void __launch_bounds__(1024) finalize_kernel(StepArgs a) {
   for (int i = threadIdx.x; i < a.n_inst; i += blockDim.x) {
     qed_instance& I = a.inst[i];
     for (int s = 0; s < 3; ++s)
       if (I.count[s] > I.capacity[s]) I.count[s] = I.capacity[s];
   }
+  qed_stats* st = a.stats;
+  const int lane = (int)(threadIdx.x & 63u);
+  const int wave = (int)(threadIdx.x >> 6);
+  const int nw = (int)(blockDim.x >> 6);
+  for (int job = wave; job < 2 * kPfCount; job += nw) {
+    const bool pho = job >= kPfCount;
+    const int f = pho ? job - kPfCount : job;
+    const int G = pho ? a.pho_grid : a.lep_grid;
+    const unsigned long long* col = (pho ? a.pho_part : a.lep_part) + (size_t)f * kMaxGridBlocks;
+    if (f == kPfEnergy || f == kPfMaxP) {
+      double v = 0.0;
+      for (int b = lane; b < G; b += 64) {
+        const double x = __longlong_as_double((long long)col[b]);
+        v = (f == kPfEnergy) ? v + x : fmax(v, x);
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const double y = __shfl_xor(v, o, 64);
+        v = (f == kPfEnergy) ? v + y : fmax(v, y);
+      }
+      if (lane == 0) {
+        if (f == kPfEnergy) {
+          if (!pho) st->photon_energy = v;
+        } else {
+          if (pho) st->max_p_pair = v;
+          else st->max_p_emit = v;
+        }
+      }
+      continue;
+    }
+    unsigned long long v = 0ull;
+    for (int b = lane; b < G; b += 64) v += col[b];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane != 0 || v == 0ull) continue;
+    switch (f) {
+      case kPfSubsteps: stats_add(&st->substeps, v); break;
+      case kPfEvents: stats_add(pho ? &st->pairs : &st->emitted, v); break;
+      case kPfSaturated: stats_add(&st->saturated, v); break;
+      case kPfNear: stats_add(&st->near_threshold, v); break;
+      case kPfNonfinite: stats_add(&st->nonfinite, v); break;
+      case kPfNearInt: stats_add(&st->nsub_near_int, v); break;
+      case kPfClamped: stats_add(&st->nsub_clamped, v); break;
+      case kPfDropped: stats_add(&st->dropped, v); break;
+      case kPfEarly: stats_add(&st->early_out, v); break;
+      case kPfAdv0: stats_add(&st->advanced[pho ? QED_PHOTON : QED_ELECTRON], v); break;
+      case kPfAdv1: stats_add(&st->advanced[QED_POSITRON], v); break;
+      case kPfWaveIters: stats_add(&st->wave_iters, v); break;
+      case kPfLowOcc: stats_add(&st->low_occupancy_iters, v); break;
+      default:
+        if (!pho && f >= kPfNsub && f < kPfNsub + QED_NSUB_HIST)
+          st->nsub_hist[f - kPfNsub] = (int64_t)v;
+        else if (!pho && f >= kPfHist)
+          st->photon_hist[f - kPfHist] = (int64_t)v;
+    }
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    qed_stats* st = a.stats;
+    __threadfence();
     uint32_t status = st->status;
     if (st->dropped > 0) status |= QED_STATUS_DROPPED;
     if (st->nonfinite > 0) status |= QED_STATUS_NONFINITE;
@@ -118,20 +184,32 @@ enum FieldMode : int {
   kFieldLocal = 2   // evaluated at each particle (CP standing wave, Yee-grid CIC)
 };
 
+// Per-lane accumulators (few, to keep registers for the hot path); wavefront-uniform
+// counts (sub-steps, events, particles advanced) are kept in scalar registers, and rare
+// events (saturation, non-finite values, near-threshold decisions, clamps, drops) go
+// straight into the workgroup's LDS record.
+struct BlockStats;
+__device__ __forceinline__ void block_count(BlockStats& bs, int field);
+
 struct LaneCounters {
-  int substeps = 0, events = 0, saturated = 0, near = 0, nonfinite = 0, near_int = 0,
-      clamped = 0, dropped = 0, early = 0, adv0 = 0, adv1 = 0;
+  BlockStats* bs = nullptr;
+  int early = 0, subs = 0;
   double energy = 0.0, maxp = 0.0;
 
   __device__ __forceinline__ void note(double P, double r2) {
     if (!isfinite(P)) {
-      ++nonfinite;
+      block_count(*bs, kPfNonfinite);
       return;
     }
     maxp = fmax(maxp, P);
-    saturated += (P >= 1.0);
-    near += (fabs(r2 - P) < kNearThreshold);
+    if (P >= 1.0) block_count(*bs, kPfSaturated);
+    if (fabs(r2 - P) < kNearThreshold) block_count(*bs, kPfNear);
   }
+};
+
+// Wavefront-uniform counts.
+struct WaveCounters {
+  long long substeps = 0, events = 0, adv0 = 0, adv1 = 0, wave_iters = 0, low_occ = 0;
 };
 
 template <typename T>
@@ -146,46 +224,56 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-__device__ void flush_counters(const StepArgs& a, const LaneCounters& c, bool photon_kernel,
-                               long long wave_iters, long long low_occ) {
-  const long long sub = wave_sum((long long)c.substeps), ev = wave_sum((long long)c.events);
-  const long long sat = wave_sum((long long)c.saturated), nr = wave_sum((long long)c.near);
-  const long long nf = wave_sum((long long)c.nonfinite), ni = wave_sum((long long)c.near_int);
-  const long long cl = wave_sum((long long)c.clamped), dr = wave_sum((long long)c.dropped);
-  const long long eo = wave_sum((long long)c.early);
-  const long long a0 = wave_sum((long long)c.adv0), a1 = wave_sum((long long)c.adv1);
-  const double en = wave_sum(c.energy), mp = wave_max(c.maxp);
-  if (lane_id() == 0) {
-    qed_stats* st = a.stats;
-    auto add = [](int64_t* p, long long v) {
-      if (v) atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);
-    };
-    add(&st->substeps, sub);
-    add(photon_kernel ? &st->pairs : &st->emitted, ev);
-    add(&st->saturated, sat);
-    add(&st->near_threshold, nr);
-    add(&st->nonfinite, nf);
-    add(&st->nsub_near_int, ni);
-    add(&st->nsub_clamped, cl);
-    add(&st->dropped, dr);
-    add(&st->early_out, eo);
-    if (photon_kernel) {
-      add(&st->advanced[QED_PHOTON], a0);
-    } else {
-      add(&st->advanced[QED_ELECTRON], a0);
-      add(&st->advanced[QED_POSITRON], a1);
-    }
-    if (!photon_kernel) {
-      add(&st->wave_iters, wave_iters);
-      add(&st->low_occupancy_iters, low_occ);
-      if (en != 0.0) atomicAdd(&st->photon_energy, en);
-    }
-    atomic_max_nonneg(photon_kernel ? &st->max_p_pair : &st->max_p_emit, mp);
+// Workgroup-level partial stats in LDS.
+struct BlockStats {
+  unsigned long long w[kPfCount];
+  double energy, maxp;
+};
+
+__device__ __forceinline__ void block_count(BlockStats& bs, int field) {
+  atomicAdd(&bs.w[field], 1ull);
+}
+
+__device__ __forceinline__ void block_stats_init(BlockStats& bs) {
+  for (int i = threadIdx.x; i < kPfCount; i += blockDim.x) bs.w[i] = 0ull;
+  if (threadIdx.x == 0) {
+    bs.energy = 0.0;
+    bs.maxp = 0.0;
   }
 }
 
-// Append one child per flagged lane to species SP of the lane's own instance: one ballot,
-// a prefix popcount and one atomic reservation per instance present in the wavefront.
+// Wave totals of the counters into the workgroup's LDS record.
+__device__ void wave_to_block(BlockStats& bs, const LaneCounters& c, const WaveCounters& wc) {
+  const long long early = wave_sum((long long)c.early);
+  const long long subs = wave_sum((long long)c.subs);
+  const double en = wave_sum(c.energy);
+  const double mp = wave_max(c.maxp);
+  if (lane_id() == 0) {
+    const long long vals[7] = {wc.substeps + subs, wc.events, wc.adv0, wc.adv1, wc.wave_iters,
+                               wc.low_occ, early};
+    const int fields[7] = {kPfSubsteps, kPfEvents, kPfAdv0, kPfAdv1, kPfWaveIters, kPfLowOcc,
+                           kPfEarly};
+    for (int i = 0; i < 7; ++i)
+      if (vals[i]) atomicAdd(&bs.w[fields[i]], (unsigned long long)vals[i]);
+    if (en != 0.0) atomicAdd(&bs.energy, en);
+    if (mp > 0.0)
+      atomicMax(reinterpret_cast<unsigned long long*>(&bs.maxp),
+                (unsigned long long)__double_as_longlong(mp));
+  }
+}
+
+// After a __syncthreads: store the workgroup's record as column blockIdx.x of `part`.
+__device__ __forceinline__ void block_stats_store(const BlockStats& bs, unsigned long long* part) {
+  for (int i = threadIdx.x; i < kPfCount; i += blockDim.x) {
+    unsigned long long v = bs.w[i];
+    if (i == kPfEnergy) v = (unsigned long long)__double_as_longlong(bs.energy);
+    if (i == kPfMaxP) v = (unsigned long long)__double_as_longlong(bs.maxp);
+    part[(size_t)i * kMaxGridBlocks + blockIdx.x] = v;
+  }
+}
+
+// Append one child per flagged lane to species SP of the lane's instance: one ballot, a
+// prefix popcount and one atomic reservation per instance present among the flagged lanes.
 // write(store, slot) fills the child's columns.  Must be called by all 64 lanes.
 template <int SP, class Writer>
 __device__ __forceinline__ void wave_append(const StepArgs& a, bool flag, int inst,
@@ -209,44 +297,70 @@ __device__ __forceinline__ void wave_append(const StepArgs& a, bool flag, int in
         write(a.sp[SP], I.base[SP] + pos);
       } else {
         atomicAdd(reinterpret_cast<unsigned long long*>(&a.inst[li].dropped), 1ull);
-        ++cnt.dropped;
+        block_count(*cnt.bs, kPfDropped);
       }
     }
     m &= ~same;
   }
 }
 
-// Hand out the next tile of a queue to the whole wavefront; returns false once drained.
-// pref holds nseg+1 tile prefix sums over segments: (instance, e-/e+) for leptons,
-// instances for photons.
+// Current piece of a wavefront's work: slots [cur, end) of one (instance, species) segment.
 struct TileCursor {
   long long cur = 0, end = 0;
   int inst = 0, species = 0;
 };
 
-__device__ __forceinline__ bool next_tile(const StepArgs& a, unsigned long long* queue,
-                                          long long ntiles, const long long* pref, int nseg,
-                                          bool lepton, TileCursor& tc) {
-  long long t = 0;
-  if (lane_id() == 0) t = (long long)atomicAdd(queue, 1ull);
-  t = wave_bcast(t, 0);
-  if (t >= ntiles) return false;
-  int lo = 0, hi = nseg;  // pref[lo] <= t < pref[hi]
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (pref[mid] <= t) lo = mid;
-    else hi = mid;
+// A wavefront's share of the index space [0, N): chunks chunk, chunk + W, ... of T particles.
+struct WaveRange {
+  long long g, gend, chunk, T, W, N;
+
+  __device__ __forceinline__ void init(long long n, long long tile) {
+    const long long wpb = blockDim.x >> 6;
+    W = (long long)gridDim.x * wpb;
+    const long long wv = (long long)blockIdx.x * wpb +
+                         __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    N = n;
+    T = tile > 0 ? tile : (n + W - 1) / W;
+    if (T < 1) T = 1;
+    chunk = wv - W;
+    g = gend = 0;
   }
-  const int inst = lepton ? (lo >> 1) : lo;
-  const int sp = lepton ? (lo & 1) : QED_PHOTON;
-  const long long lt = t - pref[lo];
-  const long long n0 = a.n0[inst * 3 + sp];
-  const long long base = a.inst[inst].base[sp];
-  tc.cur = base + lt * a.tile;
-  tc.end = base + min((lt + 1) * a.tile, n0);
-  tc.inst = inst;
-  tc.species = sp;
-  return true;
+  // Next piece within one segment; false once the wavefront's share is exhausted.
+  __device__ __forceinline__ bool next(const StepArgs& a, const long long* pref, int nseg,
+                                       bool lepton, TileCursor& tc) {
+    while (g >= gend) {
+      chunk += W;
+      const long long s = chunk * T;
+      if (s >= N) return false;
+      g = s;
+      gend = min(s + T, N);
+    }
+    int lo = 0, hi = nseg;  // pref[lo] <= g < pref[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (pref[mid] <= g) lo = mid;
+      else hi = mid;
+    }
+    const int inst = lepton ? (lo >> 1) : lo;
+    const int sp = lepton ? (lo & 1) : QED_PHOTON;
+    const long long piece_end = min(gend, pref[lo + 1]);
+    const long long base = a.inst[inst].base[sp];
+    tc.cur = base + (g - pref[lo]);
+    tc.end = tc.cur + (piece_end - g);
+    tc.inst = inst;
+    tc.species = sp;
+    g = piece_end;
+    return true;
+  }
+};
+
+// Does this workgroup own any work?  (its first wavefront's first chunk starts below N)
+__device__ __forceinline__ bool block_has_work(long long N, long long tile) {
+  const long long wpb = blockDim.x >> 6;
+  const long long W = (long long)gridDim.x * wpb;
+  long long T = tile > 0 ? tile : (N + W - 1) / W;
+  if (T < 1) T = 1;
+  return (long long)blockIdx.x * wpb * T < N;
 }
 
 template <bool MIXED>
@@ -261,6 +375,88 @@ struct TabType<true> {
 // Column pointer of electrons or positrons without indexing the kernel-argument array.
 #define LEPTON_COL(col, sp) ((sp) == QED_ELECTRON ? a.sp[QED_ELECTRON].col : a.sp[QED_POSITRON].col)
 
+// Per-wavefront LDS staging of emitted photons.
+struct PhotonStage {
+  double x[kStageCap], y[kStageCap], z[kStageCap];
+  double px[kStageCap], py[kStageCap], pz[kStageCap], w[kStageCap];
+  unsigned long long id[kStageCap], parent[kStageCap];
+  unsigned int birth[kStageCap];
+  int inst[kStageCap];
+};
+
+// Reserve slots for the `staged` records and copy them out (lane j takes record j).
+__device__ __forceinline__ void flush_stage(const StepArgs& a, PhotonStage& sg, int staged,
+                                            LaneCounters& cnt) {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  const int lane = lane_id();
+  const bool has = lane < staged;
+  const int j = has ? lane : 0;
+  const int rinst = has ? sg.inst[j] : -1;
+  wave_append<QED_PHOTON>(a, has, rinst, cnt, [&](const qed_soa& o, long long s) {
+    o.x[s] = sg.x[j];
+    o.y[s] = sg.y[j];
+    o.z[s] = sg.z[j];
+    o.px[s] = sg.px[j];
+    o.py[s] = sg.py[j];
+    o.pz[s] = sg.pz[j];
+    o.w[s] = sg.w[j];
+    o.id[s] = sg.id[j];
+    o.parent[s] = sg.parent[j];
+    o.birth[s] = sg.birth[j];
+    if (o.n_events) o.n_events[s] = 0u;
+  });
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+// Per-wavefront LDS staging of pair creations (one record -> an electron and a positron).
+struct PairStage {
+  double x[kStageCap], y[kStageCap], z[kStageCap];
+  double kx[kStageCap], ky[kStageCap], kz[kStageCap], r1[kStageCap], w[kStageCap];
+  unsigned long long parent[kStageCap];
+  unsigned int sub[kStageCap];
+  int inst[kStageCap];
+};
+
+__device__ __forceinline__ void flush_pairs(const StepArgs& a, PairStage& sg, int staged,
+                                            uint32_t step, LaneCounters& cnt) {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  const int lane = lane_id();
+  const bool has = lane < staged;
+  const int j = has ? lane : 0;
+  const int rinst = has ? sg.inst[j] : -1;
+  const uint64_t seed = has ? a.inst[rinst].seed : 0ull;
+  const double r1 = sg.r1[j];
+  // electron takes r1 of the photon momentum, positron the rest (Sec. V.A)
+  wave_append<QED_ELECTRON>(a, has, rinst, cnt, [&](const qed_soa& o, long long s) {
+    o.x[s] = sg.x[j];
+    o.y[s] = sg.y[j];
+    o.z[s] = sg.z[j];
+    o.px[s] = r1 * sg.kx[j];
+    o.py[s] = r1 * sg.ky[j];
+    o.pz[s] = r1 * sg.kz[j];
+    o.w[s] = sg.w[j];
+    o.id[s] = child_id(sg.parent[j], seed, step, sg.sub[j], kElectronChild);
+    o.parent[s] = sg.parent[j];
+    o.birth[s] = birth_code(step, sg.sub[j]);
+    if (o.n_events) o.n_events[s] = 0u;
+  });
+  wave_append<QED_POSITRON>(a, has, rinst, cnt, [&](const qed_soa& o, long long s) {
+    const double r1c = 1.0 - r1;
+    o.x[s] = sg.x[j];
+    o.y[s] = sg.y[j];
+    o.z[s] = sg.z[j];
+    o.px[s] = r1c * sg.kx[j];
+    o.py[s] = r1c * sg.ky[j];
+    o.pz[s] = r1c * sg.kz[j];
+    o.w[s] = sg.w[j];
+    o.id[s] = child_id(sg.parent[j], seed, step, sg.sub[j], kPositronChild);
+    o.parent[s] = sg.parent[j];
+    o.birth[s] = birth_code(step, sg.sub[j]);
+    if (o.n_events) o.n_events[s] = 0u;
+  });
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
 // ------------------------------------------------------------------------------------
 // leptons
 // ------------------------------------------------------------------------------------
@@ -268,21 +464,20 @@ template <bool MIXED, int FMODE>
 __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
   using Tab = typename TabType<MIXED>::T;
   __shared__ Tab tab[kTableN];
-  __shared__ unsigned int s_nsub[QED_NSUB_HIST];
-  __shared__ unsigned int s_hist[QED_SPECTRUM_BINS];
-  __shared__ int s_go;
+  __shared__ BlockStats bs;
+  __shared__ PhotonStage stage[kWavesPerBlock];
   WorkHdr* hdr = a.hdr;
-  if (threadIdx.x == 0)
-    s_go = (__hip_atomic_load(&hdr->lep_queue, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-            (unsigned long long)hdr->lep_tiles);
-  __syncthreads();
-  if (!s_go) return;
+  const long long N = hdr->lep_total;
+  block_stats_init(bs);
+  if (!block_has_work(N, a.tile)) {
+    __syncthreads();
+    block_stats_store(bs, a.lep_part);
+    return;
+  }
   {
     const Tab* src = MIXED ? reinterpret_cast<const Tab*>(a.tables->ab32)
                            : reinterpret_cast<const Tab*>(a.tables->ab64);
     for (int i = threadIdx.x; i < kTableN; i += blockDim.x) tab[i] = src[i];
-    for (int i = threadIdx.x; i < QED_NSUB_HIST; i += blockDim.x) s_nsub[i] = 0u;
-    for (int i = threadIdx.x; i < QED_SPECTRUM_BINS; i += blockDim.x) s_hist[i] = 0u;
   }
   __syncthreads();
 
@@ -291,16 +486,20 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
   const Series32 ser32 = {(float)ser64.b0, (float)ser64.b1, (float)ser64.c0, (float)ser64.c1,
                           (float)ser64.c2};
   const uint32_t step = (uint32_t)hdr->step;
-  const long long ntiles = hdr->lep_tiles;
   const int nseg = 2 * a.n_inst;
   FieldArgs fld = a.field;
   fld.tn = hdr->tn;
   const uint64_t below = lanes_below();
+  PhotonStage& sg = stage[threadIdx.x >> 6];
 
   LaneCounters cnt;
-  long long wave_iters = 0, low_occ = 0;
+  cnt.bs = &bs;
+  WaveCounters wc;
   TileCursor tc;
+  WaveRange wr;
+  wr.init(N, a.tile);
   bool open = true;
+  int staged = 0;
 
   // lane state
   long long slot = -1;
@@ -311,11 +510,11 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
   double qh2 = 0.0, h = 0.0, dtfac = 0.0;
 
   while (true) {
-    // ---- refill idle lanes from the wavefront's queue ----
+    // ---- refill idle lanes from the wavefront's share ----
     uint64_t freem = wave_ballot(slot < 0);
     while (freem != 0 && open) {
       if (tc.cur >= tc.end) {
-        open = next_tile(a, &hdr->lep_queue, ntiles, a.lep_pref, nseg, true, tc);
+        open = wr.next(a, a.lep_pref, nseg, true, tc);
         continue;
       }
       const int nfree = __popcll(freem);
@@ -355,25 +554,26 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
             ni = nsub_from_ratio(substep_ratio_lepton(a.dt, chi, g, a.inv_lep_scale));
           }
           nsub = ni.n;
-          cnt.near_int += ni.near_int;
-          cnt.clamped += ni.clamped;
+          if (ni.near_int) block_count(bs, kPfNearInt);
+          if (ni.clamped) block_count(bs, kPfClamped);
         }
-        if (!isfinite(chi)) ++cnt.nonfinite;
-        atomicAdd(&s_nsub[nsub < QED_NSUB_HIST ? nsub : QED_NSUB_HIST - 1], 1u);
-        cnt.adv0 += (sp == QED_ELECTRON);
-        cnt.adv1 += (sp != QED_ELECTRON);
+        if (!isfinite(chi)) block_count(bs, kPfNonfinite);
+        atomicAdd(&bs.w[kPfNsub + (nsub < QED_NSUB_HIST ? nsub : QED_NSUB_HIST - 1)], 1ull);
         h = a.dt / (double)nsub;
         dtfac = h * a.dtfac_per_h;
         qh2 = (sp == QED_ELECTRON ? -0.5 : 0.5) * h;
         k = 0;
       }
+      if (tc.species == QED_ELECTRON) wc.adv0 += take;
+      else wc.adv1 += take;
       tc.cur += take;
       freem = wave_ballot(slot < 0);
     }
     const uint64_t act = wave_ballot(slot >= 0);
     if (act == 0) break;
-    ++wave_iters;
-    low_occ += (__popcll(act) < 32);
+    ++wc.wave_iters;
+    wc.low_occ += (__popcll(act) < 32);
+    wc.substeps += __popcll(act);
 
     // ---- one sub-step: push, chi, emission decision (Sec. IV.G) ----
     bool emit = false;
@@ -389,7 +589,6 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
       const double hg = h / g;
       x = {x.x + hg * p.x, x.y + hg * p.y, x.z + hg * p.z};
       const double chi = chi_of(p, g, E, FMODE == kFieldE ? V3{0.0, 0.0, 0.0} : B, a.eps_r);
-      ++cnt.substeps;
       if (a.emission) {
         const uint4 o = draw_words(id, seed, step, (uint32_t)k, kDraw);
         double delta;
@@ -421,31 +620,60 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
             const double eps = delta * g;
             f = eps / pabs;
             ++nev;
-            ++cnt.events;
+            const float lb = (__log10f((float)eps) + 8.0f) * 10.0f;
+            if (lb >= 0.0f && lb < (float)QED_SPECTRUM_BINS)
+              atomicAdd(&bs.w[kPfHist + (int)lb], 1ull);
             const double w = LEPTON_COL(w, sp)[slot];
             cnt.energy += w * eps;
-            const float lb = (__log10f((float)eps) + 8.0f) * 10.0f;
-            if (lb >= 0.0f && lb < (float)QED_SPECTRUM_BINS) atomicAdd(&s_hist[(int)lb], 1u);
           } else {
             emit = false;
-            ++cnt.nonfinite;
+            block_count(bs, kPfNonfinite);
           }
         }
       }
     }
-    wave_append<QED_PHOTON>(a, emit, inst, cnt, [&](const qed_soa& o, long long s) {
-      o.x[s] = x.x;
-      o.y[s] = x.y;
-      o.z[s] = x.z;
-      o.px[s] = f * p.x;
-      o.py[s] = f * p.y;
-      o.pz[s] = f * p.z;
-      o.w[s] = LEPTON_COL(w, sp)[slot];
-      o.id[s] = child_id(id, seed, step, (uint32_t)k, kPhotonChild);
-      o.parent[s] = id;
-      o.birth[s] = birth_code(step, (uint32_t)k);
-      if (o.n_events) o.n_events[s] = 0u;
-    });
+
+    // ---- stage the emitted photons; reserve store slots once per batch ----
+    const uint64_t em = wave_ballot(emit);
+    if (em) {
+      const int n_new = __popcll(em);
+      wc.events += n_new;
+      if (staged + n_new > kStageCap) {
+        flush_stage(a, sg, staged, cnt);
+        staged = 0;
+      }
+      if (n_new > kStageCap) {
+        wave_append<QED_PHOTON>(a, emit, inst, cnt, [&](const qed_soa& o, long long s) {
+          o.x[s] = x.x;
+          o.y[s] = x.y;
+          o.z[s] = x.z;
+          o.px[s] = f * p.x;
+          o.py[s] = f * p.y;
+          o.pz[s] = f * p.z;
+          o.w[s] = LEPTON_COL(w, sp)[slot];
+          o.id[s] = child_id(id, seed, step, (uint32_t)k, kPhotonChild);
+          o.parent[s] = id;
+          o.birth[s] = birth_code(step, (uint32_t)k);
+          if (o.n_events) o.n_events[s] = 0u;
+        });
+      } else {
+        if (emit) {
+          const int r = staged + __popcll(em & below);
+          sg.x[r] = x.x;
+          sg.y[r] = x.y;
+          sg.z[r] = x.z;
+          sg.px[r] = f * p.x;
+          sg.py[r] = f * p.y;
+          sg.pz[r] = f * p.z;
+          sg.w[r] = LEPTON_COL(w, sp)[slot];
+          sg.id[r] = child_id(id, seed, step, (uint32_t)k, kPhotonChild);
+          sg.parent[r] = id;
+          sg.birth[r] = birth_code(step, (uint32_t)k);
+          sg.inst[r] = inst;
+        }
+        staged += n_new;
+      }
+    }
     if (emit) {
       // recoil: the lepton keeps p - k (momentum conservation, Sec. IV.F)
       const V3 kq = {f * p.x, f * p.y, f * p.z};
@@ -465,200 +693,319 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
       slot = -1;
     }
   }
+  if (staged > 0) flush_stage(a, sg, staged, cnt);
 
-  flush_counters(a, cnt, false, wave_iters, low_occ);
+  wave_to_block(bs, cnt, wc);
   __syncthreads();
-  for (int i = threadIdx.x; i < QED_NSUB_HIST; i += blockDim.x)
-    if (s_nsub[i]) atomicAdd(reinterpret_cast<unsigned long long*>(&a.stats->nsub_hist[i]),
-                             (unsigned long long)s_nsub[i]);
-  for (int i = threadIdx.x; i < QED_SPECTRUM_BINS; i += blockDim.x)
-    if (s_hist[i]) atomicAdd(reinterpret_cast<unsigned long long*>(&a.stats->photon_hist[i]),
-                             (unsigned long long)s_hist[i]);
+  block_stats_store(bs, a.lep_part);
 }
 
 // ------------------------------------------------------------------------------------
 // photons
 // ------------------------------------------------------------------------------------
-// Photons keep chi_gamma fixed over the step (fields frozen, k unchanged), and most of them
-// are far from pair threshold: a per-octave bound of the pair probability settles those
-// decisions from r2 alone, so the rate tables are read straight from the (L2-resident)
-// table buffer rather than staged in LDS, leaving LDS free for occupancy.
-template <bool MIXED, int FMODE>
-__global__ void __launch_bounds__(256) photon_kernel(StepArgs a) {
-  __shared__ int s_go;
-  WorkHdr* hdr = a.hdr;
-  if (threadIdx.x == 0)
-    s_go = (__hip_atomic_load(&hdr->pho_queue, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-            (unsigned long long)hdr->pho_tiles);
-  __syncthreads();
-  if (!s_go) return;
+// Photons keep chi_gamma fixed over the step (fields frozen, k unchanged), almost always
+// need a single sub-step, and are mostly far from pair threshold: a per-octave bound of
+// the pair probability settles those decisions from r2 alone.  The kernel therefore runs
+// two phases per wavefront:
+//   light  -- each lane takes the next photon of the wavefront's chunk: fields, chi_gamma,
+//             n_sub, then for each sub-step the push and the draw; a draw with r2 below
+//             the bound makes the photon a candidate (slot and sub-step recorded in LDS)
+//             and its processing stops there;
+//   exact  -- once enough candidates are recorded, each lane re-derives one candidate's
+//             state from the stores (same arithmetic, same draws), evaluates the pair
+//             probability of Eq. (30) at the recorded sub-step and finishes the photon.
+// Keeping the table lookups, logarithms and exponentials out of the light loop keeps its
+// register footprint, and thereby the number of resident wavefronts, high.
+constexpr int kCandCap = 96;  // recorded candidates per wavefront (flushed above 32)
 
+struct Candidates {
+  long long slot[kCandCap];
+  int sub[kCandCap];
+  int inst[kCandCap];
+};
+
+struct PhotonSetup {
+  double chi, hk, pref, pbound;
+  int nsub;
+};
+
+// Fields, chi_gamma, n_sub and the rate prefactors of one photon (identical in both phases).
+template <bool MIXED, int FMODE>
+__device__ __forceinline__ PhotonSetup photon_setup(const StepArgs& a, const FieldArgs& fld,
+                                                    int inst, const V3& x, const V3& kv,
+                                                    double kabs, BlockStats* bs) {
+  PhotonSetup ps;
+  const double inv_k = 1.0 / kabs;
+  V3 E, B{0.0, 0.0, 0.0};
+  if (FMODE == kFieldLocal) {
+    field_at_position(fld, a.inst[inst].amp, x, E, B);
+  } else {
+    const double* eb = a.eb + 6 * inst;
+    E = {eb[0], eb[1], eb[2]};
+    if (FMODE == kFieldEB) B = {eb[3], eb[4], eb[5]};
+  }
+  // chi_gamma (Eqs. (31), (32))
+  ps.chi = chi_of(kv, kabs, E, B, a.eps_r);
+  ps.nsub = 1;
+  if (a.forced > 0) {
+    ps.nsub = a.forced;
+  } else if (a.adaptive && ps.chi > 0.0) {
+    // dt / dt_q with dt_q = kappa 130 (2 pi eps_r) |k| / chi_gamma (Eq. (33))
+    const NsubInfo ni = nsub_from_ratio(a.dt * (ps.chi * inv_k) * a.inv_pho_scale);
+    ps.nsub = ni.n;
+    if (bs) {
+      if (ni.near_int) block_count(*bs, kPfNearInt);
+      if (ni.clamped) block_count(*bs, kPfClamped);
+    }
+  }
+  if (bs && !isfinite(ps.chi)) block_count(*bs, kPfNonfinite);
+  const double h = ps.nsub == 1 ? a.dt : a.dt / (double)ps.nsub;
+  ps.hk = h * inv_k;
+  ps.pref = h * (a.dtfac_per_h * kInvSqrt3Pi) * inv_k;
+  // upper bound of the pair probability over delta_e for this chi octave
+  ps.pbound = 0.0;
+  if (ps.chi > 0.0) {
+    int e2;
+    frexp(ps.chi, &e2);  // chi < 2^e2
+    const int oi = e2 + kBoundOffset;
+    if (oi >= kBoundOctaves) ps.pbound = __builtin_inf();
+    else if (oi >= 0)
+      ps.pbound = ps.pref * (MIXED ? (double)a.tables->pair_bound32[oi] : a.tables->pair_bound64[oi]);
+  }
+  return ps;
+}
+
+// Below the bound?  (the mixed path compares in FP32, as its exact evaluation does)
+template <bool MIXED>
+__device__ __forceinline__ bool below_bound(const uint4& o, double pbound) {
+  if (MIXED) return uniform32(o.w) < (float)pbound;
+  return uniform64(o.z, o.w) < pbound;
+}
+
+// Exact pair decision of Eq. (30) for draw o; returns r1 through *r1out.
+template <bool MIXED>
+__device__ __forceinline__ bool pair_decision(const StepArgs& a, const Series64& s64,
+                                              const Series32& s32, const uint4& o, double chi,
+                                              double pref, LaneCounters& cnt, double* r1out) {
+  if (MIXED) {
+    const float r1 = uniform32(o.y), r2 = uniform32(o.w);
+    const float omd = 1.0f - r1;
+    const float z = (2.0f / 3.0f) / ((float)chi * r1 * omd);
+    const float P = (float)pref * pair_bracket32(a.tables->bc32, s32, z, r1 / omd + omd / r1);
+    cnt.note((double)P, (double)r2);
+    *r1out = (double)r1;
+    return r2 < P;
+  }
+  const double r1 = uniform64(o.x, o.y), r2 = uniform64(o.z, o.w);
+  const double omd = 1.0 - r1;
+  const double z = (2.0 / 3.0) / (chi * r1 * omd);
+  const double P = pref * pair_bracket64(a.tables->bc64, s64, z, r1 / omd + omd / r1);
+  cnt.note(P, r2);
+  *r1out = r1;
+  return r2 < P;
+}
+
+template <bool MIXED, int FMODE>
+__device__ __forceinline__ void photon_exact_phase(const StepArgs& a, const FieldArgs& fld,
+                                                Candidates& cd, int ncand, PairStage& ps,
+                                                int& staged, uint32_t step, BlockStats& bs,
+                                                LaneCounters& cnt, WaveCounters& wc) {
   const Series64 ser64 = {a.tables->series[0], a.tables->series[1], a.tables->series[2],
                           a.tables->series[3], a.tables->series[4]};
   const Series32 ser32 = {(float)ser64.b0, (float)ser64.b1, (float)ser64.c0, (float)ser64.c1,
                           (float)ser64.c2};
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  const int lane = lane_id();
+  const uint64_t below = lanes_below();
+  const qed_soa& S = a.sp[QED_PHOTON];
+  const bool has = lane < ncand;
+  bool pair = false;
+  double r1 = 0.0;
+  int kpair = 0, inst = 0;
+  long long s = 0;
+  V3 x{}, kv{};
+  uint64_t id = 0;
+  if (has) {
+    s = cd.slot[lane];
+    const int kc = cd.sub[lane];
+    inst = cd.inst[lane];
+    id = S.id[s];
+    x = {S.x[s], S.y[s], S.z[s]};
+    kv = {S.px[s], S.py[s], S.pz[s]};
+    const double kabs = sqrt(dot(kv, kv));
+    const uint64_t seed = a.inst[inst].seed;
+    const PhotonSetup st = photon_setup<MIXED, FMODE>(a, fld, inst, x, kv, kabs, nullptr);
+    int done = st.nsub;
+    for (int k = 0; k < st.nsub; ++k) {
+      if (a.push_photons) x = {x.x + st.hk * kv.x, x.y + st.hk * kv.y, x.z + st.hk * kv.z};
+      if (k < kc) continue;  // settled by the bound in the light phase
+      const uint4 o = draw_words(id, seed, step, (uint32_t)k, kDraw);
+      if (k > kc && !below_bound<MIXED>(o, st.pbound)) {
+        ++cnt.early;
+        continue;
+      }
+      if (pair_decision<MIXED>(a, ser64, ser32, o, st.chi, st.pref, cnt, &r1)) {
+        pair = true;
+        kpair = k;
+        done = k + 1;
+        break;
+      }
+    }
+    cnt.subs += done - kc;  // sub-steps 0..kc-1 were counted in the light phase
+    if (a.push_photons) {
+      S.x[s] = x.x;
+      S.y[s] = x.y;
+      S.z[s] = x.z;
+    }
+    if (pair) S.id[s] = QED_ID_DEAD;
+  }
+  // ---- stage pair creations; reserve e-/e+ slots once per batch ----
+  const uint64_t pm = wave_ballot(pair);
+  if (pm) {
+    const int n_new = __popcll(pm);
+    wc.events += n_new;
+    if (staged + n_new > kStageCap) {
+      flush_pairs(a, ps, staged, step, cnt);
+      staged = 0;
+    }
+    if (pair) {
+      const int r = staged + __popcll(pm & below);
+      ps.x[r] = x.x;
+      ps.y[r] = x.y;
+      ps.z[r] = x.z;
+      ps.kx[r] = kv.x;
+      ps.ky[r] = kv.y;
+      ps.kz[r] = kv.z;
+      ps.r1[r] = r1;
+      ps.w[r] = S.w[s];
+      ps.parent[r] = id;
+      ps.sub[r] = (unsigned)kpair;
+      ps.inst[r] = inst;
+    }
+    staged += n_new;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+template <bool MIXED, int FMODE>
+__global__ void __launch_bounds__(256) photon_kernel(StepArgs a) {
+  __shared__ BlockStats bs;
+  __shared__ PairStage pstage[kWavesPerBlock];
+  __shared__ Candidates cands[kWavesPerBlock];
+  WorkHdr* hdr = a.hdr;
+  const long long N = hdr->pho_total;
+  block_stats_init(bs);
+  __syncthreads();
+  if (!block_has_work(N, a.tile)) {
+    block_stats_store(bs, a.pho_part);
+    return;
+  }
   const uint32_t step = (uint32_t)hdr->step;
-  const long long ntiles = hdr->pho_tiles;
   FieldArgs fld = a.field;
   fld.tn = hdr->tn;
   const uint64_t below = lanes_below();
+  const int lane = lane_id();
   const qed_soa& S = a.sp[QED_PHOTON];
+  PairStage& ps = pstage[threadIdx.x >> 6];
+  Candidates& cd = cands[threadIdx.x >> 6];
 
   LaneCounters cnt;
+  cnt.bs = &bs;
+  WaveCounters wc;
   TileCursor tc;
-  bool open = true;
+  WaveRange wr;
+  wr.init(N, a.tile);
+  int staged = 0, ncand = 0;
 
-  long long slot = -1;
-  int inst = 0, k = 0, nsub = 0;
-  V3 x{}, kv{};
-  uint64_t id = 0, seed = 0;
-  double hk = 0.0, chi = 0.0, pref = 0.0, pbound = 0.0;
-
-  while (true) {
-    uint64_t freem = wave_ballot(slot < 0);
-    while (freem != 0 && open) {
-      if (tc.cur >= tc.end) {
-        open = next_tile(a, &hdr->pho_queue, ntiles, a.pho_pref, a.n_inst, false, tc);
-        continue;
+  while (wr.next(a, a.pho_pref, a.n_inst, false, tc)) {
+    const int inst = tc.inst;
+    const uint64_t seed = a.inst[inst].seed;
+    for (long long base = tc.cur; base < tc.end; base += 64) {
+      const long long s = base + lane;
+      bool cand = false;
+      int kcand = 0;
+      V3 x{}, kv{};
+      uint64_t id = QED_ID_DEAD;
+      if (s < tc.end) {
+        // one round trip: id, position and momentum together
+        id = S.id[s];
+        x = {S.x[s], S.y[s], S.z[s]};
+        kv = {S.px[s], S.py[s], S.pz[s]};
       }
-      const int nfree = __popcll(freem);
-      const long long avail = tc.end - tc.cur;
-      const int take = (int)(avail < nfree ? avail : nfree);
-      const int rank = __popcll(freem & below);
-      if (slot < 0 && rank < take) {
-        const long long s = tc.cur + rank;
-        const uint64_t pid = S.id[s];
-        if (pid != QED_ID_DEAD) {
-          x = {S.x[s], S.y[s], S.z[s]};
-          kv = {S.px[s], S.py[s], S.pz[s]};
-          const double kabs = sqrt(dot(kv, kv));
-          if (!(kabs > 0.0) || !isfinite(kabs)) {
-            ++cnt.nonfinite;
-          } else {
-            slot = s;
-            inst = tc.inst;
-            id = pid;
-            ++cnt.adv0;
-            seed = a.inst[inst].seed;
-            V3 E, B{0.0, 0.0, 0.0};
-            if (FMODE == kFieldLocal) {
-              field_at_position(fld, a.inst[inst].amp, x, E, B);
-            } else {
-              const double* eb = a.eb + 6 * inst;
-              E = {eb[0], eb[1], eb[2]};
-              if (FMODE == kFieldEB) B = {eb[3], eb[4], eb[5]};
-            }
-            // chi_gamma (Eqs. (31), (32))
-            chi = chi_of(kv, kabs, E, B, a.eps_r);
-            nsub = 1;
-            if (a.forced > 0) {
-              nsub = a.forced;
-            } else if (a.adaptive && chi > 0.0) {
-              const NsubInfo ni =
-                  nsub_from_ratio(substep_ratio_photon(a.dt, chi, kabs, a.inv_pho_scale));
-              nsub = ni.n;
-              cnt.near_int += ni.near_int;
-              cnt.clamped += ni.clamped;
-            }
-            if (!isfinite(chi)) ++cnt.nonfinite;
-            const double h = a.dt / (double)nsub;
-            hk = h / kabs;
-            pref = h * a.dtfac_per_h * kInvSqrt3Pi / kabs;
-            pbound = 0.0;
-            if (chi > 0.0) {
-              int e2;
-              frexp(chi, &e2);  // chi < 2^e2
-              const int oi = e2 + kBoundOffset;
-              if (oi >= kBoundOctaves) pbound = __builtin_inf();
-              else if (oi >= 0)
-                pbound = pref * (MIXED ? (double)a.tables->pair_bound32[oi]
-                                       : a.tables->pair_bound64[oi]);
-            }
-            k = 0;
+      const double kabs = sqrt(dot(kv, kv));
+      const bool live = id != QED_ID_DEAD;
+      const bool ok = live && kabs > 0.0 && isfinite(kabs);
+      if (live && !ok) block_count(bs, kPfNonfinite);
+      wc.adv0 += __popcll(wave_ballot(ok));
+      if (ok) {
+        const PhotonSetup st = photon_setup<MIXED, FMODE>(a, fld, inst, x, kv, kabs, &bs);
+        int k = 0;
+        for (; k < st.nsub; ++k) {
+          if (a.push_photons) x = {x.x + st.hk * kv.x, x.y + st.hk * kv.y, x.z + st.hk * kv.z};
+          if (!a.pairs) continue;
+          const uint4 o = draw_words(id, seed, step, (uint32_t)k, kDraw);
+          if (below_bound<MIXED>(o, st.pbound)) {
+            cand = true;
+            kcand = k;
+            break;
           }
+          ++cnt.early;
         }
-      }
-      tc.cur += take;
-      freem = wave_ballot(slot < 0);
-    }
-    if (wave_ballot(slot >= 0) == 0) break;
-
-    bool pair = false;
-    double r1d = 0.0;
-    if (slot >= 0) {
-      if (a.push_photons) x = {x.x + hk * kv.x, x.y + hk * kv.y, x.z + hk * kv.z};
-      ++cnt.substeps;
-      if (a.pairs) {
-        const uint4 o = draw_words(id, seed, step, (uint32_t)k, kDraw);
-        if (MIXED) {
-          const float r1 = uniform32(o.y), r2 = uniform32(o.w);
-          r1d = (double)r1;
-          if (r2 >= (float)pbound) {
-            ++cnt.early;
-          } else {
-            const float omd = 1.0f - r1;
-            const float z = (2.0f / 3.0f) / ((float)chi * r1 * omd);
-            const float P = (float)pref * pair_bracket32(a.tables->bc32, ser32, z,
-                                                         r1 / omd + omd / r1);
-            cnt.note((double)P, (double)r2);
-            pair = r2 < P;
+        if (!cand) {
+          cnt.subs += st.nsub;
+          if (a.push_photons) {
+            S.x[s] = x.x;
+            S.y[s] = x.y;
+            S.z[s] = x.z;
           }
         } else {
-          const double r1 = uniform64(o.x, o.y), r2 = uniform64(o.z, o.w);
-          r1d = r1;
-          if (r2 >= pbound) {
-            ++cnt.early;
-          } else {
-            const double omd = 1.0 - r1;
-            const double z = (2.0 / 3.0) / (chi * r1 * omd);
-            const double P = pref * pair_bracket64(a.tables->bc64, ser64, z, r1 / omd + omd / r1);
-            cnt.note(P, r2);
-            pair = r2 < P;
-          }
+          cnt.subs += kcand;
         }
-        cnt.events += pair;
       }
-    }
-    // electron takes r1 of the photon momentum, positron the rest (Sec. V.A)
-    wave_append<QED_ELECTRON>(a, pair, inst, cnt, [&](const qed_soa& o, long long s) {
-      o.x[s] = x.x;
-      o.y[s] = x.y;
-      o.z[s] = x.z;
-      o.px[s] = r1d * kv.x;
-      o.py[s] = r1d * kv.y;
-      o.pz[s] = r1d * kv.z;
-      o.w[s] = S.w[slot];
-      o.id[s] = child_id(id, seed, step, (uint32_t)k, kElectronChild);
-      o.parent[s] = id;
-      o.birth[s] = birth_code(step, (uint32_t)k);
-      if (o.n_events) o.n_events[s] = 0u;
-    });
-    wave_append<QED_POSITRON>(a, pair, inst, cnt, [&](const qed_soa& o, long long s) {
-      const double r1c = 1.0 - r1d;
-      o.x[s] = x.x;
-      o.y[s] = x.y;
-      o.z[s] = x.z;
-      o.px[s] = r1c * kv.x;
-      o.py[s] = r1c * kv.y;
-      o.pz[s] = r1c * kv.z;
-      o.w[s] = S.w[slot];
-      o.id[s] = child_id(id, seed, step, (uint32_t)k, kPositronChild);
-      o.parent[s] = id;
-      o.birth[s] = birth_code(step, (uint32_t)k);
-      if (o.n_events) o.n_events[s] = 0u;
-    });
-
-    if (slot >= 0 && (pair || ++k == nsub)) {
-      if (a.push_photons) {
-        S.x[slot] = x.x;
-        S.y[slot] = x.y;
-        S.z[slot] = x.z;
+      // ---- record candidates; settle them exactly once enough have gathered ----
+      const uint64_t cm = wave_ballot(cand);
+      if (cm) {
+        if (cand) {
+          const int r = ncand + __popcll(cm & below);
+          cd.slot[r] = s;
+          cd.sub[r] = kcand;
+          cd.inst[r] = inst;
+        }
+        ncand += __popcll(cm);
+        if (ncand > 32) {
+          for (int c0 = 0; c0 < ncand; c0 += 64) {
+            // shift the next 64 records to the front for the exact phase
+            photon_exact_phase<MIXED, FMODE>(a, fld, cd, min(ncand - c0, 64), ps, staged, step,
+                                             bs, cnt, wc);
+            if (ncand - c0 > 64) {
+              __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+              const int j = c0 + 64 + lane;
+              long long sl = 0;
+              int su = 0, in = 0;
+              if (j < ncand) {
+                sl = cd.slot[j];
+                su = cd.sub[j];
+                in = cd.inst[j];
+              }
+              __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+              if (j < ncand) {
+                cd.slot[lane] = sl;
+                cd.sub[lane] = su;
+                cd.inst[lane] = in;
+              }
+            }
+          }
+          ncand = 0;
+        }
       }
-      if (pair) S.id[slot] = QED_ID_DEAD;
-      slot = -1;
     }
   }
-  flush_counters(a, cnt, true, 0, 0);
+  if (ncand > 0)
+    photon_exact_phase<MIXED, FMODE>(a, fld, cd, ncand, ps, staged, step, bs, cnt, wc);
+  if (staged > 0) flush_pairs(a, ps, staged, step, cnt);
+  wave_to_block(bs, cnt, wc);
+  __syncthreads();
+  block_stats_store(bs, a.pho_part);
 }
 
 #undef LEPTON_COL
@@ -696,7 +1043,7 @@ hipError_t launch_step(const StepArgs& a, int precision, LaunchShape lep, Launch
     else if (fm == kFieldE) launch_persistent<false, kFieldE>(a, lep, pho, run_photons, s);
     else launch_persistent<false, kFieldLocal>(a, lep, pho, run_photons, s);
   }
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(1024), 0, s, a);
   return hipGetLastError();
 }
 
