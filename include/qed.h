@@ -133,6 +133,7 @@ typedef struct {
 
 typedef struct {
   qed_soa species[3];
+  int64_t slots[3];           /* length of every column of each species store */
   qed_instance *d_instances;
   int n_instances;
 } qed_stores;
@@ -197,14 +198,17 @@ typedef struct {
   uint32_t reserved;
 } qed_stats;
 
-/* Size of the workspace qed_step needs for n_instances instances. */
-size_t qed_work_bytes(int n_instances);
+/* Size of the workspace qed_step needs for n_instances instances and a photon store of
+ * photon_slots slots (it holds the per-step list of photons whose pair decision needs the
+ * exact rate, at most one entry per photon). */
+size_t qed_work_bytes(int n_instances, int64_t photon_slots);
 
 /* One global step n = *d_step of every non-frozen instance (Sec. IV.H):
  *   for each lepton and photon alive at the step start: fields at the start position
  *   (once per step), chi, n_sub, then n_sub times {push, chi, one event decision}; children
  *   are appended at the end of their instance's segment and are processed from step n+1.
- * Increments *d_step and overwrites *d_stats.  d_work: qed_work_bytes(n_instances) bytes.
+ * Increments *d_step and overwrites *d_stats.  d_work: at least
+ * qed_work_bytes(n_instances, stores->slots[QED_PHOTON]) bytes, 256-byte aligned.
  * QED_ERR_ARG on null or inconsistent arguments.  If d_tables does not hold built tables
  * the kernels do nothing and set QED_STATUS_NO_TABLES. */
 qed_status qed_step(const void *d_tables, const qed_stores *stores, const qed_field *field,

@@ -68,9 +68,9 @@ qed_status qed_build_tables(void* d_tables, size_t bytes, void* stream) {
   return e == hipSuccess ? QED_OK : QED_ERR_HIP;
 }
 
-size_t qed_work_bytes(int n_instances) {
-  if (n_instances < 1) return 0;
-  return WorkLayout::make(n_instances).total;
+size_t qed_work_bytes(int n_instances, int64_t photon_slots) {
+  if (n_instances < 1 || photon_slots < 0) return 0;
+  return WorkLayout::make(n_instances, photon_slots).total;
 }
 
 qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_field* field,
@@ -81,7 +81,9 @@ qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_fi
   const qed_params& P = *params;
   const int ni = stores->n_instances;
   if (ni < 1 || !stores->d_instances) return QED_ERR_ARG;
-  if (work_bytes < qed_work_bytes(ni) || (reinterpret_cast<uintptr_t>(d_work) & 63u))
+  if (stores->slots[0] < 0 || stores->slots[1] < 0 || stores->slots[2] < 0) return QED_ERR_ARG;
+  if (work_bytes < qed_work_bytes(ni, stores->slots[QED_PHOTON]) ||
+      (reinterpret_cast<uintptr_t>(d_work) & 255u))
     return QED_ERR_ARG;
   if (!soa_ok(stores->species[QED_ELECTRON], true) || !soa_ok(stores->species[QED_POSITRON], true))
     return QED_ERR_ARG;
@@ -147,7 +149,7 @@ qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_fi
   a.push_photons = P.push_photons;
   a.freeze_on_drop = P.freeze_on_drop;
   a.tile = P.tile;
-  const WorkLayout L = WorkLayout::make(ni);
+  const WorkLayout L = WorkLayout::make(ni, stores->slots[QED_PHOTON]);
   uint8_t* w = static_cast<uint8_t*>(d_work);
   a.hdr = reinterpret_cast<WorkHdr*>(w);
   a.n0 = reinterpret_cast<long long*>(w + L.n0);
@@ -156,6 +158,9 @@ qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_fi
   a.eb = reinterpret_cast<double*>(w + L.eb);
   a.lep_part = reinterpret_cast<unsigned long long*>(w + L.lep_part);
   a.pho_part = reinterpret_cast<unsigned long long*>(w + L.pho_part);
+  a.ex_part = reinterpret_cast<unsigned long long*>(w + L.ex_part);
+  a.cand = reinterpret_cast<unsigned long long*>(w + L.cand);
+  a.cand_cap = (long long)((work_bytes - L.cand) / sizeof(unsigned long long));
   a.stats = d_stats;
   a.d_step = reinterpret_cast<long long*>(d_step);
   for (int i = 0; i < 4; ++i) a.events[i] = static_cast<hipEvent_t>(P.events[i]);
@@ -170,6 +175,7 @@ qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_fi
   if (pho.grid > kMaxGridBlocks) pho.grid = kMaxGridBlocks;
   a.lep_grid = lep.grid;
   a.pho_grid = run_photons ? pho.grid : 0;
+  a.ex_grid = (run_photons && P.pairs) ? kExactGridBlocks : 0;
   const hipError_t e =
       launch_step(a, P.precision, lep, pho, run_photons, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? QED_OK : QED_ERR_HIP;

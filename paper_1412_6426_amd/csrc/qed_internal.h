@@ -12,6 +12,8 @@ namespace qedk {
 // Upper bound of workgroups per persistent kernel (the workspace holds one partial stats
 // record per workgroup).
 constexpr int kMaxGridBlocks = 4096;
+// Workgroups of the exact pair-decision kernel (a grid-stride loop over the candidates).
+constexpr int kExactGridBlocks = 512;
 
 // Per-workgroup partial stats: 64-bit words, stored field-major ([field][block]) so that
 // the finalize kernel reduces each field with coalesced loads.
@@ -27,12 +29,13 @@ enum PartialField : int {
 
 // Header of the qed_step workspace; followed by the arrays laid out by WorkLayout.
 struct alignas(64) WorkHdr {
-  long long lep_total;  // leptons (e- and e+, all instances) alive at the step start
-  long long pho_total;  // photon slots to visit (0 when the photon kernel does not run)
-  long long step;       // global step index n
-  double tn;            // field time t0 + n dt
+  long long lep_total;         // leptons (e- and e+, all instances) alive at the step start
+  long long pho_total;         // photon slots to visit (0 when the photon kernel does not run)
+  long long step;              // global step index n
+  double tn;                   // field time t0 + n dt
+  unsigned long long n_cand;   // photons recorded for the exact pair decision this step
   uint32_t tables_ok;
-  uint32_t reserved[7];
+  uint32_t reserved[5];
 };
 
 struct WorkLayout {
@@ -42,8 +45,10 @@ struct WorkLayout {
   size_t eb;        // double [n_inst * 6]: E, B of space-independent fields at t_n
   size_t lep_part;  // uint64 [kPfCount][kMaxGridBlocks]
   size_t pho_part;  // uint64 [kPfCount][kMaxGridBlocks]
+  size_t ex_part;   // uint64 [kPfCount][kMaxGridBlocks]
+  size_t cand;      // uint64 [photon slots]: (photon index << 16) | sub-step
   size_t total;
-  static WorkLayout make(int n_inst) {
+  static WorkLayout make(int n_inst, long long photon_slots) {
     WorkLayout L;
     size_t off = sizeof(WorkHdr);
     auto take = [&off](size_t bytes) {
@@ -57,6 +62,8 @@ struct WorkLayout {
     L.eb = take(sizeof(double) * 6 * (size_t)n_inst);
     L.lep_part = take(sizeof(unsigned long long) * kPfCount * kMaxGridBlocks);
     L.pho_part = take(sizeof(unsigned long long) * kPfCount * kMaxGridBlocks);
+    L.ex_part = take(sizeof(unsigned long long) * kPfCount * kMaxGridBlocks);
+    L.cand = take(sizeof(unsigned long long) * (size_t)(photon_slots > 0 ? photon_slots : 1));
     L.total = off;
     return L;
   }
@@ -82,7 +89,10 @@ struct StepArgs {
   double* eb;
   unsigned long long* lep_part;
   unsigned long long* pho_part;
-  int lep_grid, pho_grid;  // workgroups of the two persistent kernels
+  unsigned long long* ex_part;
+  unsigned long long* cand;
+  long long cand_cap;
+  int lep_grid, pho_grid, ex_grid;  // workgroups of the lepton, photon and exact-pair kernels
   qed_stats* stats;
   long long* d_step;
   hipEvent_t events[4];

@@ -1,12 +1,14 @@
 // qed_step.hip -- the per-step kernels of the QED step (Sec. IV.H adaptive event generator
 // of Gonoskov et al., arXiv:1412.6426, with the Sec. V.A pair generator).
 //
-// One step is four launches on the caller's stream:
+// One step is five launches on the caller's stream:
 //   prep     (1 workgroup)  snapshot live counts, particle prefix sums over the
 //                           (instance, species) segments, space-independent fields at t_n,
 //                           zero the stats record;
 //   leptons  (persistent)   electrons and positrons: push, chi, emission, photon append;
-//   photons  (persistent)   photons: push, chi_gamma, pair creation, e-/e+ append;
+//   photons  (persistent)   photons: push, chi_gamma, pair-rate bound; draws below the
+//                           bound are listed for
+//   exact    (grid-stride)  the exact pair decision and the e-/e+ append;
 //   finalize (1 workgroup)  reduce per-workgroup partial stats, clamp counts, status bits,
 //                           step index + 1.
 // Children land after the step-start counts, so they are first processed at step n+1.
@@ -86,6 +88,7 @@ __global__ void __launch_bounds__(256) prep_kernel(StepArgs a, int run_photons) 
     }
     hdr->lep_total = lp;
     hdr->pho_total = pp;
+    hdr->n_cand = 0ull;
     hdr->step = n;
     hdr->tn = tn;
     hdr->tables_ok = (uint32_t)ok;
@@ -109,11 +112,15 @@ __global__ void __launch_bounds__(1024) finalize_kernel(StepArgs a) {
   const int lane = (int)(threadIdx.x & 63u);
   const int wave = (int)(threadIdx.x >> 6);
   const int nw = (int)(blockDim.x >> 6);
-  for (int job = wave; job < 2 * kPfCount; job += nw) {
-    const bool pho = job >= kPfCount;
-    const int f = pho ? job - kPfCount : job;
-    const int G = pho ? a.pho_grid : a.lep_grid;
-    const unsigned long long* col = (pho ? a.pho_part : a.lep_part) + (size_t)f * kMaxGridBlocks;
+  // partial sets: 0 lepton kernel, 1 photon kernel, 2 exact pair-decision kernel
+  for (int job = wave; job < 3 * kPfCount; job += nw) {
+    const int kind = job / kPfCount;
+    const int f = job - kind * kPfCount;
+    const bool pho = kind > 0;
+    const int G = kind == 0 ? a.lep_grid : (kind == 1 ? a.pho_grid : a.ex_grid);
+    const unsigned long long* base =
+        kind == 0 ? a.lep_part : (kind == 1 ? a.pho_part : a.ex_part);
+    const unsigned long long* col = base + (size_t)f * kMaxGridBlocks;
     if (f == kPfEnergy || f == kPfMaxP) {
       double v = 0.0;
       for (int b = lane; b < G; b += 64) {
@@ -125,12 +132,11 @@ __global__ void __launch_bounds__(1024) finalize_kernel(StepArgs a) {
         const double y = __shfl_xor(v, o, 64);
         v = (f == kPfEnergy) ? v + y : fmax(v, y);
       }
-      if (lane == 0) {
+      if (lane == 0 && v != 0.0) {
         if (f == kPfEnergy) {
-          if (!pho) st->photon_energy = v;
+          if (!pho) atomicAdd(&st->photon_energy, v);
         } else {
-          if (pho) st->max_p_pair = v;
-          else st->max_p_emit = v;
+          atomic_max_nonneg(pho ? &st->max_p_pair : &st->max_p_emit, v);
         }
       }
       continue;
@@ -306,7 +312,8 @@ __device__ __forceinline__ void wave_append(const StepArgs& a, bool flag, int in
 
 // Current piece of a wavefront's work: slots [cur, end) of one (instance, species) segment.
 struct TileCursor {
-  long long cur = 0, end = 0;
+  long long cur = 0, end = 0;  // slots
+  long long g = 0;             // index of slot `cur` in the kernel's particle index space
   int inst = 0, species = 0;
 };
 
@@ -347,6 +354,7 @@ struct WaveRange {
     const long long base = a.inst[inst].base[sp];
     tc.cur = base + (g - pref[lo]);
     tc.end = tc.cur + (piece_end - g);
+    tc.g = g;
     tc.inst = inst;
     tc.species = sp;
     g = piece_end;
@@ -705,31 +713,24 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
 // ------------------------------------------------------------------------------------
 // Photons keep chi_gamma fixed over the step (fields frozen, k unchanged), almost always
 // need a single sub-step, and are mostly far from pair threshold: a per-octave bound of
-// the pair probability settles those decisions from r2 alone.  The kernel therefore runs
-// two phases per wavefront:
-//   light  -- each lane takes the next photon of the wavefront's chunk: fields, chi_gamma,
-//             n_sub, then for each sub-step the push and the draw; a draw with r2 below
-//             the bound makes the photon a candidate (slot and sub-step recorded in LDS)
-//             and its processing stops there;
-//   exact  -- once enough candidates are recorded, each lane re-derives one candidate's
-//             state from the stores (same arithmetic, same draws), evaluates the pair
-//             probability of Eq. (30) at the recorded sub-step and finishes the photon.
-// Keeping the table lookups, logarithms and exponentials out of the light loop keeps its
-// register footprint, and thereby the number of resident wavefronts, high.
-constexpr int kCandCap = 96;  // recorded candidates per wavefront (flushed above 32)
-
-struct Candidates {
-  long long slot[kCandCap];
-  int sub[kCandCap];
-  int inst[kCandCap];
-};
+// the pair probability settles those decisions from r2 alone.  Two kernels:
+//   photon_kernel -- each lane takes the next photon of the wavefront's chunk: fields,
+//             chi_gamma, n_sub, then for each sub-step the push and the draw; a draw with
+//             r2 below the bound makes the photon a candidate -- its index and sub-step go
+//             to a list in the workspace -- and its processing stops there;
+//   photon_exact_kernel -- each lane re-derives one candidate's state from the stores (same
+//             arithmetic, same draws), evaluates the pair probability of Eq. (30) at the
+//             recorded sub-step, finishes the photon's sub-steps and stages the pairs.
+// The table lookups, logarithms and exponentials stay out of the bulk kernel, whose small
+// register footprint lets many wavefronts stay resident to hide HBM latency.
+constexpr int kCandCap = 96;  // candidates gathered per wavefront before a flush (> 32)
 
 struct PhotonSetup {
   double chi, hk, pref, pbound;
   int nsub;
 };
 
-// Fields, chi_gamma, n_sub and the rate prefactors of one photon (identical in both phases).
+// Fields, chi_gamma, n_sub and the rate prefactors of one photon (identical in both kernels).
 template <bool MIXED, int FMODE>
 __device__ __forceinline__ PhotonSetup photon_setup(const StepArgs& a, const FieldArgs& fld,
                                                     int inst, const V3& x, const V3& kv,
@@ -805,84 +806,17 @@ __device__ __forceinline__ bool pair_decision(const StepArgs& a, const Series64&
   return r2 < P;
 }
 
-template <bool MIXED, int FMODE>
-__device__ __forceinline__ void photon_exact_phase(const StepArgs& a, const FieldArgs& fld,
-                                                Candidates& cd, int ncand, PairStage& ps,
-                                                int& staged, uint32_t step, BlockStats& bs,
-                                                LaneCounters& cnt, WaveCounters& wc) {
-  const Series64 ser64 = {a.tables->series[0], a.tables->series[1], a.tables->series[2],
-                          a.tables->series[3], a.tables->series[4]};
-  const Series32 ser32 = {(float)ser64.b0, (float)ser64.b1, (float)ser64.c0, (float)ser64.c1,
-                          (float)ser64.c2};
+// Move the wavefront's gathered candidates to the workspace list (one reservation).
+__device__ __forceinline__ void flush_candidates(const StepArgs& a, unsigned long long* cl,
+                                                 int ncand, BlockStats& bs) {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  const int lane = lane_id();
-  const uint64_t below = lanes_below();
-  const qed_soa& S = a.sp[QED_PHOTON];
-  const bool has = lane < ncand;
-  bool pair = false;
-  double r1 = 0.0;
-  int kpair = 0, inst = 0;
-  long long s = 0;
-  V3 x{}, kv{};
-  uint64_t id = 0;
-  if (has) {
-    s = cd.slot[lane];
-    const int kc = cd.sub[lane];
-    inst = cd.inst[lane];
-    id = S.id[s];
-    x = {S.x[s], S.y[s], S.z[s]};
-    kv = {S.px[s], S.py[s], S.pz[s]};
-    const double kabs = sqrt(dot(kv, kv));
-    const uint64_t seed = a.inst[inst].seed;
-    const PhotonSetup st = photon_setup<MIXED, FMODE>(a, fld, inst, x, kv, kabs, nullptr);
-    int done = st.nsub;
-    for (int k = 0; k < st.nsub; ++k) {
-      if (a.push_photons) x = {x.x + st.hk * kv.x, x.y + st.hk * kv.y, x.z + st.hk * kv.z};
-      if (k < kc) continue;  // settled by the bound in the light phase
-      const uint4 o = draw_words(id, seed, step, (uint32_t)k, kDraw);
-      if (k > kc && !below_bound<MIXED>(o, st.pbound)) {
-        ++cnt.early;
-        continue;
-      }
-      if (pair_decision<MIXED>(a, ser64, ser32, o, st.chi, st.pref, cnt, &r1)) {
-        pair = true;
-        kpair = k;
-        done = k + 1;
-        break;
-      }
-    }
-    cnt.subs += done - kc;  // sub-steps 0..kc-1 were counted in the light phase
-    if (a.push_photons) {
-      S.x[s] = x.x;
-      S.y[s] = x.y;
-      S.z[s] = x.z;
-    }
-    if (pair) S.id[s] = QED_ID_DEAD;
-  }
-  // ---- stage pair creations; reserve e-/e+ slots once per batch ----
-  const uint64_t pm = wave_ballot(pair);
-  if (pm) {
-    const int n_new = __popcll(pm);
-    wc.events += n_new;
-    if (staged + n_new > kStageCap) {
-      flush_pairs(a, ps, staged, step, cnt);
-      staged = 0;
-    }
-    if (pair) {
-      const int r = staged + __popcll(pm & below);
-      ps.x[r] = x.x;
-      ps.y[r] = x.y;
-      ps.z[r] = x.z;
-      ps.kx[r] = kv.x;
-      ps.ky[r] = kv.y;
-      ps.kz[r] = kv.z;
-      ps.r1[r] = r1;
-      ps.w[r] = S.w[s];
-      ps.parent[r] = id;
-      ps.sub[r] = (unsigned)kpair;
-      ps.inst[r] = inst;
-    }
-    staged += n_new;
+  unsigned long long base = 0;
+  if (lane_id() == 0) base = atomicAdd(&a.hdr->n_cand, (unsigned long long)ncand);
+  base = wave_bcast(base, 0);
+  for (int j = lane_id(); j < ncand; j += 64) {
+    const unsigned long long pos = base + (unsigned long long)j;
+    if (pos < (unsigned long long)a.cand_cap) a.cand[pos] = cl[j];
+    else block_count(bs, kPfDropped);  // unreachable when the workspace is sized as documented
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
@@ -890,8 +824,7 @@ __device__ __forceinline__ void photon_exact_phase(const StepArgs& a, const Fiel
 template <bool MIXED, int FMODE>
 __global__ void __launch_bounds__(256) photon_kernel(StepArgs a) {
   __shared__ BlockStats bs;
-  __shared__ PairStage pstage[kWavesPerBlock];
-  __shared__ Candidates cands[kWavesPerBlock];
+  __shared__ unsigned long long cands[kWavesPerBlock][kCandCap];
   WorkHdr* hdr = a.hdr;
   const long long N = hdr->pho_total;
   block_stats_init(bs);
@@ -906,8 +839,7 @@ __global__ void __launch_bounds__(256) photon_kernel(StepArgs a) {
   const uint64_t below = lanes_below();
   const int lane = lane_id();
   const qed_soa& S = a.sp[QED_PHOTON];
-  PairStage& ps = pstage[threadIdx.x >> 6];
-  Candidates& cd = cands[threadIdx.x >> 6];
+  unsigned long long* cl = cands[threadIdx.x >> 6];
 
   LaneCounters cnt;
   cnt.bs = &bs;
@@ -915,7 +847,7 @@ __global__ void __launch_bounds__(256) photon_kernel(StepArgs a) {
   TileCursor tc;
   WaveRange wr;
   wr.init(N, a.tile);
-  int staged = 0, ncand = 0;
+  int ncand = 0;
 
   while (wr.next(a, a.pho_pref, a.n_inst, false, tc)) {
     const int inst = tc.inst;
@@ -959,53 +891,139 @@ __global__ void __launch_bounds__(256) photon_kernel(StepArgs a) {
             S.z[s] = x.z;
           }
         } else {
-          cnt.subs += kcand;
+          cnt.subs += kcand;  // the exact kernel counts the rest
         }
       }
-      // ---- record candidates; settle them exactly once enough have gathered ----
+      // ---- record candidates (photon index, sub-step); hand them over in batches ----
       const uint64_t cm = wave_ballot(cand);
       if (cm) {
         if (cand) {
-          const int r = ncand + __popcll(cm & below);
-          cd.slot[r] = s;
-          cd.sub[r] = kcand;
-          cd.inst[r] = inst;
+          const long long g = tc.g + (s - tc.cur);
+          cl[ncand + __popcll(cm & below)] =
+              ((unsigned long long)g << 16) | (unsigned long long)kcand;
         }
         ncand += __popcll(cm);
         if (ncand > 32) {
-          for (int c0 = 0; c0 < ncand; c0 += 64) {
-            // shift the next 64 records to the front for the exact phase
-            photon_exact_phase<MIXED, FMODE>(a, fld, cd, min(ncand - c0, 64), ps, staged, step,
-                                             bs, cnt, wc);
-            if (ncand - c0 > 64) {
-              __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-              const int j = c0 + 64 + lane;
-              long long sl = 0;
-              int su = 0, in = 0;
-              if (j < ncand) {
-                sl = cd.slot[j];
-                su = cd.sub[j];
-                in = cd.inst[j];
-              }
-              __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-              if (j < ncand) {
-                cd.slot[lane] = sl;
-                cd.sub[lane] = su;
-                cd.inst[lane] = in;
-              }
-            }
-          }
+          flush_candidates(a, cl, ncand, bs);
           ncand = 0;
         }
       }
     }
   }
-  if (ncand > 0)
-    photon_exact_phase<MIXED, FMODE>(a, fld, cd, ncand, ps, staged, step, bs, cnt, wc);
-  if (staged > 0) flush_pairs(a, ps, staged, step, cnt);
+  if (ncand > 0) flush_candidates(a, cl, ncand, bs);
   wave_to_block(bs, cnt, wc);
   __syncthreads();
   block_stats_store(bs, a.pho_part);
+}
+
+template <bool MIXED, int FMODE>
+__global__ void __launch_bounds__(256) photon_exact_kernel(StepArgs a) {
+  __shared__ BlockStats bs;
+  __shared__ PairStage pstage[kWavesPerBlock];
+  WorkHdr* hdr = a.hdr;
+  block_stats_init(bs);
+  __syncthreads();
+  long long n = (long long)hdr->n_cand;
+  if (n > a.cand_cap) n = a.cand_cap;
+  const uint32_t step = (uint32_t)hdr->step;
+  FieldArgs fld = a.field;
+  fld.tn = hdr->tn;
+  const Series64 ser64 = {a.tables->series[0], a.tables->series[1], a.tables->series[2],
+                          a.tables->series[3], a.tables->series[4]};
+  const Series32 ser32 = {(float)ser64.b0, (float)ser64.b1, (float)ser64.c0, (float)ser64.c1,
+                          (float)ser64.c2};
+  const uint64_t below = lanes_below();
+  const int lane = lane_id();
+  const qed_soa& S = a.sp[QED_PHOTON];
+  PairStage& ps = pstage[threadIdx.x >> 6];
+  LaneCounters cnt;
+  cnt.bs = &bs;
+  WaveCounters wc;
+  int staged = 0;
+  const long long wave0 = (long long)blockIdx.x * (blockDim.x >> 6) +
+                          __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const long long stride = (long long)gridDim.x * blockDim.x;
+
+  for (long long i0 = wave0 * 64; i0 < n; i0 += stride) {
+    const long long i = i0 + lane;
+    bool pair = false;
+    double r1 = 0.0;
+    int kpair = 0, inst = 0;
+    long long s = 0;
+    V3 x{}, kv{};
+    uint64_t id = 0;
+    if (i < n) {
+      const unsigned long long e = a.cand[i];
+      const long long g = (long long)(e >> 16);
+      const int kc = (int)(e & 0xFFFFull);
+      int lo = 0, hi = a.n_inst;  // pho_pref[lo] <= g < pho_pref[hi]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (a.pho_pref[mid] <= g) lo = mid;
+        else hi = mid;
+      }
+      inst = lo;
+      s = a.inst[inst].base[QED_PHOTON] + (g - a.pho_pref[inst]);
+      id = S.id[s];
+      x = {S.x[s], S.y[s], S.z[s]};
+      kv = {S.px[s], S.py[s], S.pz[s]};
+      const double kabs = sqrt(dot(kv, kv));
+      const uint64_t seed = a.inst[inst].seed;
+      const PhotonSetup st = photon_setup<MIXED, FMODE>(a, fld, inst, x, kv, kabs, nullptr);
+      int done = st.nsub;
+      for (int k = 0; k < st.nsub; ++k) {
+        if (a.push_photons) x = {x.x + st.hk * kv.x, x.y + st.hk * kv.y, x.z + st.hk * kv.z};
+        if (k < kc) continue;  // settled by the bound in photon_kernel
+        const uint4 o = draw_words(id, seed, step, (uint32_t)k, kDraw);
+        if (k > kc && !below_bound<MIXED>(o, st.pbound)) {
+          ++cnt.early;
+          continue;
+        }
+        if (pair_decision<MIXED>(a, ser64, ser32, o, st.chi, st.pref, cnt, &r1)) {
+          pair = true;
+          kpair = k;
+          done = k + 1;
+          break;
+        }
+      }
+      cnt.subs += done - kc;
+      if (a.push_photons) {
+        S.x[s] = x.x;
+        S.y[s] = x.y;
+        S.z[s] = x.z;
+      }
+      if (pair) S.id[s] = QED_ID_DEAD;
+    }
+    // ---- stage pair creations; reserve e-/e+ slots once per batch ----
+    const uint64_t pm = wave_ballot(pair);
+    if (pm) {
+      const int n_new = __popcll(pm);
+      wc.events += n_new;
+      if (staged + n_new > kStageCap) {
+        flush_pairs(a, ps, staged, step, cnt);
+        staged = 0;
+      }
+      if (pair) {
+        const int r = staged + __popcll(pm & below);
+        ps.x[r] = x.x;
+        ps.y[r] = x.y;
+        ps.z[r] = x.z;
+        ps.kx[r] = kv.x;
+        ps.ky[r] = kv.y;
+        ps.kz[r] = kv.z;
+        ps.r1[r] = r1;
+        ps.w[r] = S.w[s];
+        ps.parent[r] = id;
+        ps.sub[r] = (unsigned)kpair;
+        ps.inst[r] = inst;
+      }
+      staged += n_new;
+    }
+  }
+  if (staged > 0) flush_pairs(a, ps, staged, step, cnt);
+  wave_to_block(bs, cnt, wc);
+  __syncthreads();
+  block_stats_store(bs, a.ex_part);
 }
 
 #undef LEPTON_COL
@@ -1020,6 +1038,8 @@ static void launch_persistent(const StepArgs& a, LaunchShape lep, LaunchShape ph
   if (run_photons) {
     if (a.events[2]) (void)hipEventRecord(a.events[2], s);
     hipLaunchKernelGGL((photon_kernel<MIXED, FMODE>), dim3(pho.grid), dim3(pho.block), 0, s, a);
+    if (a.ex_grid > 0)
+      hipLaunchKernelGGL((photon_exact_kernel<MIXED, FMODE>), dim3(a.ex_grid), dim3(256), 0, s, a);
     if (a.events[3]) (void)hipEventRecord(a.events[3], s);
   }
 }

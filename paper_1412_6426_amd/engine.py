@@ -60,7 +60,7 @@ class Engine:
         self._inst_init = np.frombuffer(bytes(inst), dtype=np.uint8).copy()
         self.inst = torch.from_numpy(self._inst_init.copy()).to(self.device)
         self.tables = torch.zeros(Q.qed_table_bytes(), dtype=torch.uint8, device=self.device)
-        self.work_bytes = Q.qed_work_bytes(self.n_inst)
+        self.work_bytes = Q.qed_work_bytes(self.n_inst, int(self.cols[2]["x"].numel()))
         self.work = torch.zeros(self.work_bytes, dtype=torch.uint8, device=self.device)
         self.stats_buf = torch.zeros(C.sizeof(Q.qed_stats), dtype=torch.uint8, device=self.device)
         self.step_ctr = torch.zeros(1, dtype=torch.int64, device=self.device)
@@ -74,6 +74,8 @@ class Engine:
             soa.parent = C.cast(C.c_void_p(d["parent"].data_ptr()), Q._u64p)
             soa.birth = C.cast(C.c_void_p(d["birth"].data_ptr()), Q._u32p)
             soa.n_events = C.cast(C.c_void_p(d["n_events"].data_ptr()), Q._u32p)
+        for s in range(3):
+            self.stores.slots[s] = int(self.cols[s]["x"].numel())
         self.stores.d_instances = self.inst.data_ptr()
         self.stores.n_instances = self.n_inst
 

@@ -47,7 +47,8 @@ class qed_instance(C.Structure):
 
 
 class qed_stores(C.Structure):
-    _fields_ = [("species", qed_soa * 3), ("d_instances", C.c_void_p), ("n_instances", C.c_int)]
+    _fields_ = [("species", qed_soa * 3), ("slots", C.c_int64 * 3), ("d_instances", C.c_void_p),
+                ("n_instances", C.c_int)]
 
 
 class qed_field(C.Structure):
@@ -110,7 +111,7 @@ def lib():
         L.qed_build_tables.restype = C.c_int
         L.qed_build_tables.argtypes = [C.c_void_p, C.c_size_t, C.c_void_p]
         L.qed_work_bytes.restype = C.c_size_t
-        L.qed_work_bytes.argtypes = [C.c_int]
+        L.qed_work_bytes.argtypes = [C.c_int, C.c_int64]
         L.qed_step.restype = C.c_int
         L.qed_step.argtypes = [C.c_void_p, C.POINTER(qed_stores), C.POINTER(qed_field),
                                C.POINTER(qed_params), C.c_void_p, C.c_void_p, C.c_void_p,
@@ -147,8 +148,8 @@ def qed_build_tables(d_tables: int, nbytes: int, stream: int) -> None:
     _check(lib().qed_build_tables(d_tables, nbytes, stream), "qed_build_tables")
 
 
-def qed_work_bytes(n_instances: int) -> int:
-    return int(lib().qed_work_bytes(n_instances))
+def qed_work_bytes(n_instances: int, photon_slots: int) -> int:
+    return int(lib().qed_work_bytes(n_instances, photon_slots))
 
 
 def qed_step(d_tables: int, stores: qed_stores, field: qed_field, params: qed_params,

@@ -66,9 +66,12 @@ def test_ctypes_layout_matches_header(Q, tmp_path):
 
 def test_host_side_queries(Q):
     assert Q.qed_version() >= 100
-    assert Q.qed_work_bytes(0) == 0
-    w1, w64 = Q.qed_work_bytes(1), Q.qed_work_bytes(64)
+    assert Q.qed_work_bytes(0, 10) == 0
+    assert Q.qed_work_bytes(1, -1) == 0
+    w1, w64 = Q.qed_work_bytes(1, 1000), Q.qed_work_bytes(64, 1000)
     assert 64 <= w1 < w64
+    # one candidate-list entry (8 bytes) per photon slot
+    assert abs(Q.qed_work_bytes(1, 2000) - w1 - 8000) < 256
     assert Q.lib().qed_status_string(1) == b"invalid argument"
 
 
