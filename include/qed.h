@@ -198,17 +198,26 @@ typedef struct {
   uint32_t reserved;
 } qed_stats;
 
-/* Size of the workspace qed_step needs for n_instances instances and a photon store of
- * photon_slots slots (it holds the per-step list of photons whose pair decision needs the
- * exact rate, at most one entry per photon). */
-size_t qed_work_bytes(int n_instances, int64_t photon_slots);
+/* Size of a qed_step workspace for n_instances instances, a photon store of photon_slots
+ * slots and child arenas of arena_records records.  The workspace holds the per-step lists
+ * of photons whose pair decision needs the exact rate (at most one entry per photon) and,
+ * when arena_records > 0 and n_instances <= 1024, the child arenas: each wavefront writes
+ * the photons (and pair records, a quarter of arena_records) it creates into its own share
+ * of an arena, and after the particle kernels a scan and a copy kernel move them into the
+ * stores, so no wavefront reserves store slots on a shared counter.  A wavefront whose
+ * share is full reserves slots directly (correct, slower).  arena_records = 0 gives the
+ * smallest valid workspace.  Returns 0 for n_instances < 1 or negative sizes. */
+size_t qed_work_bytes(int n_instances, int64_t photon_slots, int64_t arena_records);
 
 /* One global step n = *d_step of every non-frozen instance (Sec. IV.H):
  *   for each lepton and photon alive at the step start: fields at the start position
  *   (once per step), chi, n_sub, then n_sub times {push, chi, one event decision}; children
  *   are appended at the end of their instance's segment and are processed from step n+1.
  * Increments *d_step and overwrites *d_stats.  d_work: at least
- * qed_work_bytes(n_instances, stores->slots[QED_PHOTON]) bytes, 256-byte aligned.
+ * qed_work_bytes(n_instances, stores->slots[QED_PHOTON], 0) bytes, 256-byte aligned; the
+ * largest child arena that fits in work_bytes is used.  The order in which children land
+ * in a store follows the work distribution (instance, wavefront, creation order) and does
+ * not depend on timing when the arenas are in use.
  * QED_ERR_ARG on null or inconsistent arguments.  If d_tables does not hold built tables
  * the kernels do nothing and set QED_STATUS_NO_TABLES. */
 qed_status qed_step(const void *d_tables, const qed_stores *stores, const qed_field *field,

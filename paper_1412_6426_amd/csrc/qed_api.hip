@@ -68,10 +68,41 @@ qed_status qed_build_tables(void* d_tables, size_t bytes, void* stream) {
   return e == hipSuccess ? QED_OK : QED_ERR_HIP;
 }
 
-size_t qed_work_bytes(int n_instances, int64_t photon_slots) {
-  if (n_instances < 1 || photon_slots < 0) return 0;
-  return WorkLayout::make(n_instances, photon_slots).total;
+size_t qed_work_bytes(int n_instances, int64_t photon_slots, int64_t arena_records) {
+  if (n_instances < 1 || photon_slots < 0 || arena_records < 0) return 0;
+  return WorkLayout::make(n_instances, photon_slots, arena_records).total;
 }
+
+namespace {
+
+// Column pointers of a child arena inside the workspace.
+ChildArena arena_at(uint8_t* w, size_t cols, size_t cnt, size_t nrec, size_t base, long long cap,
+                    bool pair, int n_inst, int waves) {
+  ChildArena A{};
+  if (cap <= 0 || waves <= 0) return A;
+  const size_t col8 = ((size_t)cap * 8 + 255) & ~(size_t)255;
+  const size_t col4 = ((size_t)cap * 4 + 255) & ~(size_t)255;
+  uint8_t* p = w + cols;
+  double** dcols[8] = {&A.x, &A.y, &A.z, &A.px, &A.py, &A.pz, &A.w, &A.r1};
+  for (int c = 0; c < (pair ? 8 : 7); ++c) {
+    *dcols[c] = reinterpret_cast<double*>(p);
+    p += col8;
+  }
+  A.parent = reinterpret_cast<unsigned long long*>(p);
+  p += col8;
+  A.sub = reinterpret_cast<unsigned int*>(p);
+  p += col4;
+  A.inst = reinterpret_cast<unsigned int*>(p);
+  A.cnt = reinterpret_cast<unsigned int*>(w + cnt);
+  A.nrec = reinterpret_cast<unsigned int*>(w + nrec);
+  A.base = reinterpret_cast<long long*>(w + base);
+  A.waves = waves;
+  A.per_wave = cap / waves;
+  (void)n_inst;
+  return A;
+}
+
+}  // namespace
 
 qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_field* field,
                     const qed_params* params, int64_t* d_step, qed_stats* d_stats, void* d_work,
@@ -82,7 +113,7 @@ qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_fi
   const int ni = stores->n_instances;
   if (ni < 1 || !stores->d_instances) return QED_ERR_ARG;
   if (stores->slots[0] < 0 || stores->slots[1] < 0 || stores->slots[2] < 0) return QED_ERR_ARG;
-  if (work_bytes < qed_work_bytes(ni, stores->slots[QED_PHOTON]) ||
+  if (work_bytes < qed_work_bytes(ni, stores->slots[QED_PHOTON], 0) ||
       (reinterpret_cast<uintptr_t>(d_work) & 255u))
     return QED_ERR_ARG;
   if (!soa_ok(stores->species[QED_ELECTRON], true) || !soa_ok(stores->species[QED_POSITRON], true))
@@ -149,7 +180,23 @@ qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_fi
   a.push_photons = P.push_photons;
   a.freeze_on_drop = P.freeze_on_drop;
   a.tile = P.tile;
-  const WorkLayout L = WorkLayout::make(ni, stores->slots[QED_PHOTON]);
+  // the largest child arena the workspace holds (sizes are monotonic in the record count)
+  long long arena = 0;
+  if (ni <= kArenaMaxInstances &&
+      work_bytes >= qed_work_bytes(ni, stores->slots[QED_PHOTON], 1024)) {
+    long long lo = 1024, hi = 1024;
+    // record offsets are 32-bit: at most 2^31 records per arena
+    while (work_bytes >= qed_work_bytes(ni, stores->slots[QED_PHOTON], hi * 2) && hi < (1ll << 30))
+      hi *= 2;
+    long long top = hi * 2;
+    while (top - lo > 1) {  // largest r in [lo, top) with work_bytes >= size(r)
+      const long long mid = lo + (top - lo) / 2;
+      if (work_bytes >= qed_work_bytes(ni, stores->slots[QED_PHOTON], mid)) lo = mid;
+      else top = mid;
+    }
+    arena = lo;
+  }
+  const WorkLayout L = WorkLayout::make(ni, stores->slots[QED_PHOTON], arena);
   uint8_t* w = static_cast<uint8_t*>(d_work);
   a.hdr = reinterpret_cast<WorkHdr*>(w);
   a.n0 = reinterpret_cast<long long*>(w + L.n0);
@@ -160,7 +207,9 @@ qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_fi
   a.pho_part = reinterpret_cast<unsigned long long*>(w + L.pho_part);
   a.ex_part = reinterpret_cast<unsigned long long*>(w + L.ex_part);
   a.cand = reinterpret_cast<unsigned long long*>(w + L.cand);
-  a.cand_cap = (long long)((work_bytes - L.cand) / sizeof(unsigned long long));
+  a.cand_cap = stores->slots[QED_PHOTON] > 0 ? stores->slots[QED_PHOTON] : 1;
+  a.candw = reinterpret_cast<unsigned long long*>(w + L.candw);
+  a.candn = reinterpret_cast<unsigned int*>(w + L.candn);
   a.stats = d_stats;
   a.d_step = reinterpret_cast<long long*>(d_step);
   for (int i = 0; i < 4; ++i) a.events[i] = static_cast<hipEvent_t>(P.events[i]);
@@ -176,6 +225,17 @@ qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_fi
   a.lep_grid = lep.grid;
   a.pho_grid = run_photons ? pho.grid : 0;
   a.ex_grid = (run_photons && P.pairs) ? kExactGridBlocks : 0;
+  const int lep_waves = lep.grid * (block / 64);
+  const int pho_waves = pho.grid * (block / 64);
+  a.pho_waves = run_photons ? pho_waves : 0;
+  a.cand_per_wave = (long long)((stores->slots[QED_PHOTON] > 0 ? stores->slots[QED_PHOTON] : 1) +
+                                (long long)kMaxWaves * kCandSlack) / pho_waves;
+  if (arena > 0) {
+    a.pa = arena_at(w, L.ph_cols, L.ph_cnt, L.ph_nrec, L.ph_base, L.ph_cap, false, ni, lep_waves);
+    if (a.ex_grid > 0)
+      a.qa = arena_at(w, L.pr_cols, L.pr_cnt, L.pr_nrec, L.pr_base, L.pr_cap, true, ni,
+                      a.ex_grid * 4);
+  }
   const hipError_t e =
       launch_step(a, P.precision, lep, pho, run_photons, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? QED_OK : QED_ERR_HIP;

@@ -12,8 +12,15 @@ namespace qedk {
 // Upper bound of workgroups per persistent kernel (the workspace holds one partial stats
 // record per workgroup).
 constexpr int kMaxGridBlocks = 4096;
+// Upper bound of wavefronts per kernel (workgroups of at most 256 threads).
+constexpr int kMaxWaves = kMaxGridBlocks * 4;
 // Workgroups of the exact pair-decision kernel (a grid-stride loop over the candidates).
 constexpr int kExactGridBlocks = 512;
+// Child arenas are used for up to this many instances (their count matrices hold one
+// word per (instance, wavefront)); above it every append reserves store slots directly.
+constexpr int kArenaMaxInstances = 1024;
+// Candidate entries per photon wavefront beyond its even share of the photon slots.
+constexpr int kCandSlack = 64;
 
 // Per-workgroup partial stats: 64-bit words, stored field-major ([field][block]) so that
 // the finalize kernel reduces each field with coalesced loads.
@@ -38,6 +45,23 @@ struct alignas(64) WorkHdr {
   uint32_t reserved[5];
 };
 
+// Deferred children: a wavefront writes each child it creates into its own run of
+// `per_wave` records (no reservation on a shared counter) and counts them per instance;
+// after the step's particle kernels a scan turns the counts into store offsets and a copy
+// kernel moves the records into the stores.  Structure of arrays, `cap` records each.
+struct ChildArena {
+  double *x, *y, *z, *px, *py, *pz, *w;  // position; momentum (photon) or k (pair record)
+  double* r1;                            // pair records: electron share of k
+  unsigned long long* parent;            // id of the emitting lepton / converting photon
+  unsigned int* sub;                     // sub-step of the event
+  unsigned int* inst;                    // instance of the event
+  unsigned int* cnt;    // [n_inst][waves]: records per (instance, wavefront); offsets after the scan
+  unsigned int* nrec;   // [waves]: records written by each wavefront
+  long long* base;      // [n_inst][2]: store counts before the append (photon or e-, e+)
+  long long per_wave;   // records per wavefront; 0: arena off, appends reserve directly
+  int waves;            // wavefronts of the producing kernel (row length of cnt)
+};
+
 struct WorkLayout {
   size_t n0;        // long long [n_inst * 3]: live slots at step start (0 when frozen)
   size_t lep_pref;  // long long [2 n_inst + 1]: particle prefix over (instance, e-/e+)
@@ -46,16 +70,23 @@ struct WorkLayout {
   size_t lep_part;  // uint64 [kPfCount][kMaxGridBlocks]
   size_t pho_part;  // uint64 [kPfCount][kMaxGridBlocks]
   size_t ex_part;   // uint64 [kPfCount][kMaxGridBlocks]
-  size_t cand;      // uint64 [photon slots]: (photon index << 16) | sub-step
+  size_t candn;     // uint32 [kMaxWaves]: candidates per photon wavefront
+  size_t candw;     // uint64 [photon slots + kMaxWaves kCandSlack]: per-wavefront lists
+  size_t cand;      // uint64 [photon slots]: overflow list, (photon index << 16) | sub-step
+  // child arenas (present when arena_records > 0 and n_inst <= kArenaMaxInstances)
+  size_t ph_cols, ph_cnt, ph_nrec, ph_base;  // photons emitted by leptons
+  size_t pr_cols, pr_cnt, pr_nrec, pr_base;  // pair records
+  long long ph_cap, pr_cap;
   size_t total;
-  static WorkLayout make(int n_inst, long long photon_slots) {
-    WorkLayout L;
+  static WorkLayout make(int n_inst, long long photon_slots, long long arena_records) {
+    WorkLayout L{};
     size_t off = sizeof(WorkHdr);
     auto take = [&off](size_t bytes) {
       size_t o = off;
       off += (bytes + 255) & ~(size_t)255;
       return o;
     };
+    const size_t slots = (size_t)(photon_slots > 0 ? photon_slots : 1);
     L.n0 = take(sizeof(long long) * 3 * (size_t)n_inst);
     L.lep_pref = take(sizeof(long long) * (2 * (size_t)n_inst + 1));
     L.pho_pref = take(sizeof(long long) * ((size_t)n_inst + 1));
@@ -63,9 +94,30 @@ struct WorkLayout {
     L.lep_part = take(sizeof(unsigned long long) * kPfCount * kMaxGridBlocks);
     L.pho_part = take(sizeof(unsigned long long) * kPfCount * kMaxGridBlocks);
     L.ex_part = take(sizeof(unsigned long long) * kPfCount * kMaxGridBlocks);
-    L.cand = take(sizeof(unsigned long long) * (size_t)(photon_slots > 0 ? photon_slots : 1));
+    L.candn = take(sizeof(unsigned int) * kMaxWaves);
+    L.candw = take(sizeof(unsigned long long) * (slots + (size_t)kMaxWaves * kCandSlack));
+    L.cand = take(sizeof(unsigned long long) * slots);
+    if (arena_records > 0 && n_inst <= kArenaMaxInstances) {
+      L.ph_cap = arena_records;
+      L.pr_cap = arena_records / 4 > 4096 ? arena_records / 4 : 4096;
+      const size_t mat = sizeof(unsigned int) * (size_t)n_inst * kMaxWaves;
+      L.ph_cols = take(ChildArenaBytes(L.ph_cap, false));
+      L.ph_cnt = take(mat);
+      L.ph_nrec = take(sizeof(unsigned int) * kMaxWaves);
+      L.ph_base = take(sizeof(long long) * 2 * (size_t)n_inst);
+      L.pr_cols = take(ChildArenaBytes(L.pr_cap, true));
+      L.pr_cnt = take(mat);
+      L.pr_nrec = take(sizeof(unsigned int) * kMaxWaves);
+      L.pr_base = take(sizeof(long long) * 2 * (size_t)n_inst);
+    }
     L.total = off;
     return L;
+  }
+  // Column block of an arena: 7 (+1 for pairs) doubles, parent, sub, inst per record, each
+  // column 256-byte aligned.
+  static size_t ChildArenaBytes(long long cap, bool pair) {
+    auto col = [cap](size_t b) { return ((size_t)cap * b + 255) & ~(size_t)255; };
+    return col(8) * (pair ? 8 : 7) + col(8) + col(4) * 2;
   }
 };
 
@@ -90,9 +142,15 @@ struct StepArgs {
   unsigned long long* lep_part;
   unsigned long long* pho_part;
   unsigned long long* ex_part;
-  unsigned long long* cand;
+  unsigned long long* cand;  // overflow candidate list
   long long cand_cap;
+  unsigned long long* candw;  // per-wavefront candidate lists
+  unsigned int* candn;
+  long long cand_per_wave;
+  ChildArena pa;  // photons emitted by the lepton kernel
+  ChildArena qa;  // pair records of the exact kernel
   int lep_grid, pho_grid, ex_grid;  // workgroups of the lepton, photon and exact-pair kernels
+  int pho_waves;                    // wavefronts of the photon kernel
   qed_stats* stats;
   long long* d_step;
   hipEvent_t events[4];

@@ -1,14 +1,17 @@
 // qed_step.hip -- the per-step kernels of the QED step (Sec. IV.H adaptive event generator
 // of Gonoskov et al., arXiv:1412.6426, with the Sec. V.A pair generator).
 //
-// One step is five launches on the caller's stream:
-//   prep     (1 workgroup)  snapshot live counts, particle prefix sums over the
+// One step is up to seven launches on the caller's stream:
+//   prep     (1 + k wgs)    snapshot live counts, particle prefix sums over the
 //                           (instance, species) segments, space-independent fields at t_n,
-//                           zero the stats record;
-//   leptons  (persistent)   electrons and positrons: push, chi, emission, photon append;
+//                           zero the stats record and the arenas' count matrices;
+//   leptons  (persistent)   electrons and positrons: push, chi, emission; emitted photons
+//                           go to the wavefront's share of the photon arena;
 //   photons  (persistent)   photons: push, chi_gamma, pair-rate bound; draws below the
-//                           bound are listed for
-//   exact    (grid-stride)  the exact pair decision and the e-/e+ append;
+//                           bound go to the wavefront's candidate list for
+//   exact    (grid-stride)  the exact pair decision; pair records go to the pair arena;
+//   scan     (1 wg/instance) arena counts -> store offsets, instance counts raised;
+//   copy     (1 wave/source wave) arena records -> photon, electron, positron stores;
 //   finalize (1 workgroup)  reduce per-workgroup partial stats, clamp counts, status bits,
 //                           step index + 1.
 // Children land after the step-start counts, so they are first processed at step n+1.
@@ -20,9 +23,15 @@
 // work queue"): one wavefront iteration advances every active lane by one sub-step, so
 // lanes with n_sub = 1 and n_sub = 20 share a wavefront without idling.
 //
-// Appends: emitted photons and created pairs are staged per wavefront in LDS and reserved
-// in batches of up to 32 with one atomic per (batch, instance, species).  Statistics are reduced per workgroup in LDS and written as
-// partials; the finalize kernel sums them, so no global atomic is issued per wavefront.
+// Appends: a wavefront writes the children it creates into its own share of an arena in
+// the workspace (ballot + prefix popcount for the positions, no shared counter) and tallies
+// them per instance; a scan per instance turns the tallies into store offsets and a copy
+// kernel writes the children to the stores in (instance, wavefront, creation) order.  A
+// device-wide counter takes one atomic per reservation and serialises every wavefront of
+// the GPU on one address; the arenas avoid that.  Without arena space (or with more than
+// kArenaMaxInstances instances) children are staged per wavefront in LDS and reserved in
+// batches of up to 32 with one atomic per (batch, instance, species).  Statistics are
+// reduced per workgroup in LDS and written as partials; the finalize kernel sums them.
 #include "qed_internal.h"
 
 namespace qedk {
@@ -35,6 +44,18 @@ constexpr int kStageCap = 32;      // staged photon children per wavefront
 // ------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) prep_kernel(StepArgs a, int run_photons) {
   __shared__ int s_ok;
+  if (blockIdx.x > 0) {
+    // workgroups 1.. clear the per-(instance, wavefront) child counts of the arenas
+    const long long n1 = a.pa.per_wave > 0 ? (long long)a.n_inst * a.pa.waves : 0;
+    const long long n2 = a.qa.per_wave > 0 ? (long long)a.n_inst * a.qa.waves : 0;
+    const long long stride = (long long)(gridDim.x - 1) * blockDim.x;
+    for (long long i = (long long)(blockIdx.x - 1) * blockDim.x + threadIdx.x; i < n1 + n2;
+         i += stride) {
+      if (i < n1) a.pa.cnt[i] = 0u;
+      else a.qa.cnt[i - n1] = 0u;
+    }
+    return;
+  }
   WorkHdr* hdr = a.hdr;
   const long long n = *a.d_step;
   const double tn = a.t0 + (double)n * a.dt;
@@ -296,19 +317,54 @@ __device__ __forceinline__ void wave_append(const StepArgs& a, bool flag, int in
       base = (long long)atomicAdd(reinterpret_cast<unsigned long long*>(&a.inst[li].count[SP]),
                                   (unsigned long long)__popcll(same));
     base = wave_bcast(base, leader);
-    if (mine) {
-      const long long pos = base + __popcll(same & below);
-      const qed_instance& I = a.inst[li];
-      if (pos < I.capacity[SP]) {
-        write(a.sp[SP], I.base[SP] + pos);
-      } else {
-        atomicAdd(reinterpret_cast<unsigned long long*>(&a.inst[li].dropped), 1ull);
-        block_count(*cnt.bs, kPfDropped);
-      }
+    const long long cap = a.inst[li].capacity[SP];
+    const long long pos = base + __popcll(same & below);
+    const bool fits = pos < cap;
+    if (mine && fits) write(a.sp[SP], a.inst[li].base[SP] + pos);
+    // children beyond the capacity are dropped and counted, once per wavefront
+    const uint64_t lost = wave_ballot(mine && !fits);
+    if (lost != 0 && lane_id() == leader) {
+      atomicAdd(reinterpret_cast<unsigned long long*>(&a.inst[li].dropped),
+                (unsigned long long)__popcll(lost));
+      atomicAdd(&cnt.bs->w[kPfDropped], (unsigned long long)__popcll(lost));
     }
     m &= ~same;
   }
 }
+
+// Wavefront index within the launch (wavefront-uniform).
+__device__ __forceinline__ int wave_index() {
+  return (int)blockIdx.x * (int)(blockDim.x >> 6) +
+         __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+}
+
+// Per-wavefront tally of arena records per instance.  Records are counted for the instance
+// `cur` in a register; when another instance shows up the tally goes to the wavefront's own
+// word of the count matrix (a private address, so the add never waits on other waves).
+struct ArenaTally {
+  int cur = -1;
+  unsigned n = 0;
+  __device__ __forceinline__ void flush(const ChildArena& A, int wid) {
+    if (n != 0 && lane_id() == 0)
+      atomicAdd(&A.cnt[(size_t)cur * A.waves + wid], n);
+    n = 0;
+  }
+  // Count the flagged lanes (mask m) by instance.  All lanes call it.
+  __device__ __forceinline__ void add(const ChildArena& A, int wid, uint64_t m, bool flag,
+                                      int inst) {
+    while (m) {
+      const int leader = __ffsll((unsigned long long)m) - 1;
+      const int li = wave_bcast(inst, leader);
+      const uint64_t same = wave_ballot(flag && inst == li);
+      if (li != cur) {
+        flush(A, wid);
+        cur = li;
+      }
+      n += (unsigned)__popcll(same);
+      m &= ~same;
+    }
+  }
+};
 
 // Current piece of a wavefront's work: slots [cur, end) of one (instance, species) segment.
 struct TileCursor {
@@ -476,8 +532,10 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
   __shared__ PhotonStage stage[kWavesPerBlock];
   WorkHdr* hdr = a.hdr;
   const long long N = hdr->lep_total;
+  const int wid = wave_index();
   block_stats_init(bs);
   if (!block_has_work(N, a.tile)) {
+    if (a.pa.per_wave > 0 && lane_id() == 0) a.pa.nrec[wid] = 0u;
     __syncthreads();
     block_stats_store(bs, a.lep_part);
     return;
@@ -508,6 +566,11 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
   wr.init(N, a.tile);
   bool open = true;
   int staged = 0;
+  // arena: this wavefront's records start at rbase; nrec written so far
+  const ChildArena& pa = a.pa;
+  const long long rbase = (long long)wid * pa.per_wave;
+  long long nrec = 0;
+  ArenaTally tally;
 
   // lane state
   long long slot = -1;
@@ -515,7 +578,7 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
   V3 x{}, p{}, E{}, B{};
   uint64_t id = 0, seed = 0;
   uint32_t nev = 0;
-  double qh2 = 0.0, h = 0.0, dtfac = 0.0;
+  double qh2 = 0.0, h = 0.0, dtfac = 0.0, wgt = 0.0;
 
   while (true) {
     // ---- refill idle lanes from the wavefront's share ----
@@ -536,6 +599,7 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
         x = {LEPTON_COL(x, sp)[slot], LEPTON_COL(y, sp)[slot], LEPTON_COL(z, sp)[slot]};
         p = {LEPTON_COL(px, sp)[slot], LEPTON_COL(py, sp)[slot], LEPTON_COL(pz, sp)[slot]};
         id = LEPTON_COL(id, sp)[slot];
+        wgt = LEPTON_COL(w, sp)[slot];
         uint32_t* ne = LEPTON_COL(n_events, sp);
         nev = ne ? ne[slot] : 0u;
         seed = a.inst[inst].seed;
@@ -631,8 +695,7 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
             const float lb = (__log10f((float)eps) + 8.0f) * 10.0f;
             if (lb >= 0.0f && lb < (float)QED_SPECTRUM_BINS)
               atomicAdd(&bs.w[kPfHist + (int)lb], 1ull);
-            const double w = LEPTON_COL(w, sp)[slot];
-            cnt.energy += w * eps;
+            cnt.energy += wgt * eps;
           } else {
             emit = false;
             block_count(bs, kPfNonfinite);
@@ -641,9 +704,27 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
       }
     }
 
-    // ---- stage the emitted photons; reserve store slots once per batch ----
+    // ---- emitted photons: into the wavefront's arena share, else staged and reserved ----
     const uint64_t em = wave_ballot(emit);
-    if (em) {
+    if (em && nrec + __popcll(em) <= pa.per_wave) {
+      const int n_new = __popcll(em);
+      wc.events += n_new;
+      tally.add(pa, wid, em, emit, inst);
+      if (emit) {
+        const long long r = rbase + nrec + __popcll(em & below);
+        pa.x[r] = x.x;
+        pa.y[r] = x.y;
+        pa.z[r] = x.z;
+        pa.px[r] = f * p.x;
+        pa.py[r] = f * p.y;
+        pa.pz[r] = f * p.z;
+        pa.w[r] = wgt;
+        pa.parent[r] = id;
+        pa.sub[r] = (unsigned)k;
+        pa.inst[r] = (unsigned)inst;
+      }
+      nrec += n_new;
+    } else if (em) {
       const int n_new = __popcll(em);
       wc.events += n_new;
       if (staged + n_new > kStageCap) {
@@ -658,7 +739,7 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
           o.px[s] = f * p.x;
           o.py[s] = f * p.y;
           o.pz[s] = f * p.z;
-          o.w[s] = LEPTON_COL(w, sp)[slot];
+          o.w[s] = wgt;
           o.id[s] = child_id(id, seed, step, (uint32_t)k, kPhotonChild);
           o.parent[s] = id;
           o.birth[s] = birth_code(step, (uint32_t)k);
@@ -673,7 +754,7 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
           sg.px[r] = f * p.x;
           sg.py[r] = f * p.y;
           sg.pz[r] = f * p.z;
-          sg.w[r] = LEPTON_COL(w, sp)[slot];
+          sg.w[r] = wgt;
           sg.id[r] = child_id(id, seed, step, (uint32_t)k, kPhotonChild);
           sg.parent[r] = id;
           sg.birth[r] = birth_code(step, (uint32_t)k);
@@ -702,6 +783,10 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
     }
   }
   if (staged > 0) flush_stage(a, sg, staged, cnt);
+  if (pa.per_wave > 0) {
+    tally.flush(pa, wid);
+    if (lane_id() == 0) pa.nrec[wid] = (unsigned)nrec;
+  }
 
   wave_to_block(bs, cnt, wc);
   __syncthreads();
@@ -723,7 +808,6 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
 //             recorded sub-step, finishes the photon's sub-steps and stages the pairs.
 // The table lookups, logarithms and exponentials stay out of the bulk kernel, whose small
 // register footprint lets many wavefronts stay resident to hide HBM latency.
-constexpr int kCandCap = 96;  // candidates gathered per wavefront before a flush (> 32)
 
 struct PhotonSetup {
   double chi, hk, pref, pbound;
@@ -806,30 +890,16 @@ __device__ __forceinline__ bool pair_decision(const StepArgs& a, const Series64&
   return r2 < P;
 }
 
-// Move the wavefront's gathered candidates to the workspace list (one reservation).
-__device__ __forceinline__ void flush_candidates(const StepArgs& a, unsigned long long* cl,
-                                                 int ncand, BlockStats& bs) {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  unsigned long long base = 0;
-  if (lane_id() == 0) base = atomicAdd(&a.hdr->n_cand, (unsigned long long)ncand);
-  base = wave_bcast(base, 0);
-  for (int j = lane_id(); j < ncand; j += 64) {
-    const unsigned long long pos = base + (unsigned long long)j;
-    if (pos < (unsigned long long)a.cand_cap) a.cand[pos] = cl[j];
-    else block_count(bs, kPfDropped);  // unreachable when the workspace is sized as documented
-  }
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-}
-
 template <bool MIXED, int FMODE>
 __global__ void __launch_bounds__(256) photon_kernel(StepArgs a) {
   __shared__ BlockStats bs;
-  __shared__ unsigned long long cands[kWavesPerBlock][kCandCap];
   WorkHdr* hdr = a.hdr;
   const long long N = hdr->pho_total;
+  const int wid = wave_index();
   block_stats_init(bs);
   __syncthreads();
   if (!block_has_work(N, a.tile)) {
+    if (lane_id() == 0) a.candn[wid] = 0u;
     block_stats_store(bs, a.pho_part);
     return;
   }
@@ -839,7 +909,9 @@ __global__ void __launch_bounds__(256) photon_kernel(StepArgs a) {
   const uint64_t below = lanes_below();
   const int lane = lane_id();
   const qed_soa& S = a.sp[QED_PHOTON];
-  unsigned long long* cl = cands[threadIdx.x >> 6];
+  // this wavefront's candidate list; a full list spills to the shared overflow list
+  unsigned long long* clist = a.candw + (size_t)wid * a.cand_per_wave;
+  long long ncand = 0;
 
   LaneCounters cnt;
   cnt.bs = &bs;
@@ -847,7 +919,6 @@ __global__ void __launch_bounds__(256) photon_kernel(StepArgs a) {
   TileCursor tc;
   WaveRange wr;
   wr.init(N, a.tile);
-  int ncand = 0;
 
   while (wr.next(a, a.pho_pref, a.n_inst, false, tc)) {
     const int inst = tc.inst;
@@ -894,26 +965,145 @@ __global__ void __launch_bounds__(256) photon_kernel(StepArgs a) {
           cnt.subs += kcand;  // the exact kernel counts the rest
         }
       }
-      // ---- record candidates (photon index, sub-step); hand them over in batches ----
+      // ---- record candidates: (photon index << 16) | sub-step ----
       const uint64_t cm = wave_ballot(cand);
       if (cm) {
-        if (cand) {
-          const long long g = tc.g + (s - tc.cur);
-          cl[ncand + __popcll(cm & below)] =
-              ((unsigned long long)g << 16) | (unsigned long long)kcand;
-        }
-        ncand += __popcll(cm);
-        if (ncand > 32) {
-          flush_candidates(a, cl, ncand, bs);
-          ncand = 0;
+        const int nc = __popcll(cm);
+        const unsigned long long e =
+            ((unsigned long long)(tc.g + (s - tc.cur)) << 16) | (unsigned long long)kcand;
+        if (ncand + nc <= a.cand_per_wave) {
+          if (cand) clist[ncand + __popcll(cm & below)] = e;
+          ncand += nc;
+        } else {
+          unsigned long long pos = 0;
+          if (lane == 0) pos = atomicAdd(&hdr->n_cand, (unsigned long long)nc);
+          pos = wave_bcast(pos, 0) + (unsigned long long)__popcll(cm & below);
+          // the overflow list holds one entry per photon slot: never full
+          if (cand && pos < (unsigned long long)a.cand_cap) a.cand[pos] = e;
         }
       }
     }
   }
-  if (ncand > 0) flush_candidates(a, cl, ncand, bs);
+  if (lane == 0) a.candn[wid] = (unsigned)ncand;
   wave_to_block(bs, cnt, wc);
   __syncthreads();
   block_stats_store(bs, a.pho_part);
+}
+
+// State of one wavefront of the exact pair-decision kernel.
+struct ExactCtx {
+  Series64 ser64;
+  Series32 ser32;
+  FieldArgs fld;
+  uint32_t step;
+  int wid;
+  int staged;
+  long long nrec;   // records in this wavefront's pair-arena share
+  ArenaTally tally;
+};
+
+// Exact pair decision for the candidates list[i0 + lane] (i0 + lane < n); all lanes call.
+template <bool MIXED, int FMODE>
+__device__ __forceinline__ void exact_batch(const StepArgs& a, ExactCtx& c, PairStage& ps,
+                                            LaneCounters& cnt, WaveCounters& wc,
+                                            const unsigned long long* list, long long i0,
+                                            long long n) {
+  const uint64_t below = lanes_below();
+  const qed_soa& S = a.sp[QED_PHOTON];
+  const long long i = i0 + lane_id();
+  bool pair = false;
+  double r1 = 0.0;
+  int kpair = 0, inst = 0;
+  long long s = 0;
+  V3 x{}, kv{};
+  uint64_t id = 0;
+  if (i < n) {
+    const unsigned long long e = list[i];
+    const long long g = (long long)(e >> 16);
+    const int kc = (int)(e & 0xFFFFull);
+    int lo = 0, hi = a.n_inst;  // pho_pref[lo] <= g < pho_pref[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (a.pho_pref[mid] <= g) lo = mid;
+      else hi = mid;
+    }
+    inst = lo;
+    s = a.inst[inst].base[QED_PHOTON] + (g - a.pho_pref[inst]);
+    id = S.id[s];
+    x = {S.x[s], S.y[s], S.z[s]};
+    kv = {S.px[s], S.py[s], S.pz[s]};
+    const double kabs = sqrt(dot(kv, kv));
+    const uint64_t seed = a.inst[inst].seed;
+    const PhotonSetup st = photon_setup<MIXED, FMODE>(a, c.fld, inst, x, kv, kabs, nullptr);
+    int done = st.nsub;
+    for (int k = 0; k < st.nsub; ++k) {
+      if (a.push_photons) x = {x.x + st.hk * kv.x, x.y + st.hk * kv.y, x.z + st.hk * kv.z};
+      if (k < kc) continue;  // settled by the bound in photon_kernel
+      const uint4 o = draw_words(id, seed, c.step, (uint32_t)k, kDraw);
+      if (k > kc && !below_bound<MIXED>(o, st.pbound)) {
+        ++cnt.early;
+        continue;
+      }
+      if (pair_decision<MIXED>(a, c.ser64, c.ser32, o, st.chi, st.pref, cnt, &r1)) {
+        pair = true;
+        kpair = k;
+        done = k + 1;
+        break;
+      }
+    }
+    cnt.subs += done - kc;
+    if (a.push_photons) {
+      S.x[s] = x.x;
+      S.y[s] = x.y;
+      S.z[s] = x.z;
+    }
+    if (pair) S.id[s] = QED_ID_DEAD;
+  }
+  const uint64_t pm = wave_ballot(pair);
+  if (!pm) return;
+  const int n_new = __popcll(pm);
+  wc.events += n_new;
+  const ChildArena& qa = a.qa;
+  if (c.nrec + n_new <= qa.per_wave) {
+    // ---- pair records into the wavefront's arena share ----
+    c.tally.add(qa, c.wid, pm, pair, inst);
+    if (pair) {
+      const long long r = (long long)c.wid * qa.per_wave + c.nrec + __popcll(pm & below);
+      qa.x[r] = x.x;
+      qa.y[r] = x.y;
+      qa.z[r] = x.z;
+      qa.px[r] = kv.x;
+      qa.py[r] = kv.y;
+      qa.pz[r] = kv.z;
+      qa.r1[r] = r1;
+      qa.w[r] = S.w[s];
+      qa.parent[r] = id;
+      qa.sub[r] = (unsigned)kpair;
+      qa.inst[r] = (unsigned)inst;
+    }
+    c.nrec += n_new;
+    return;
+  }
+  // ---- else stage them and reserve e-/e+ slots once per batch ----
+  if (c.staged + n_new > kStageCap) {
+    flush_pairs(a, ps, c.staged, c.step, cnt);
+    c.staged = 0;
+  }
+  if (pair) {
+    const int r = c.staged + __popcll(pm & below);
+    ps.x[r] = x.x;
+    ps.y[r] = x.y;
+    ps.z[r] = x.z;
+    ps.kx[r] = kv.x;
+    ps.ky[r] = kv.y;
+    ps.kz[r] = kv.z;
+    ps.r1[r] = r1;
+    ps.w[r] = S.w[s];
+    ps.parent[r] = id;
+    ps.sub[r] = (unsigned)kpair;
+    ps.inst[r] = inst;
+  }
+  c.staged += n_new;
 }
 
 template <bool MIXED, int FMODE>
@@ -923,107 +1113,232 @@ __global__ void __launch_bounds__(256) photon_exact_kernel(StepArgs a) {
   WorkHdr* hdr = a.hdr;
   block_stats_init(bs);
   __syncthreads();
-  long long n = (long long)hdr->n_cand;
-  if (n > a.cand_cap) n = a.cand_cap;
-  const uint32_t step = (uint32_t)hdr->step;
-  FieldArgs fld = a.field;
-  fld.tn = hdr->tn;
-  const Series64 ser64 = {a.tables->series[0], a.tables->series[1], a.tables->series[2],
-                          a.tables->series[3], a.tables->series[4]};
-  const Series32 ser32 = {(float)ser64.b0, (float)ser64.b1, (float)ser64.c0, (float)ser64.c1,
-                          (float)ser64.c2};
-  const uint64_t below = lanes_below();
-  const int lane = lane_id();
-  const qed_soa& S = a.sp[QED_PHOTON];
+  ExactCtx c;
+  c.ser64 = {a.tables->series[0], a.tables->series[1], a.tables->series[2], a.tables->series[3],
+             a.tables->series[4]};
+  c.ser32 = {(float)c.ser64.b0, (float)c.ser64.b1, (float)c.ser64.c0, (float)c.ser64.c1,
+             (float)c.ser64.c2};
+  c.fld = a.field;
+  c.fld.tn = hdr->tn;
+  c.step = (uint32_t)hdr->step;
+  c.wid = wave_index();
+  c.staged = 0;
+  c.nrec = 0;
   PairStage& ps = pstage[threadIdx.x >> 6];
   LaneCounters cnt;
   cnt.bs = &bs;
   WaveCounters wc;
-  int staged = 0;
-  const long long wave0 = (long long)blockIdx.x * (blockDim.x >> 6) +
-                          __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const long long stride = (long long)gridDim.x * blockDim.x;
+  const int V = (int)gridDim.x * (int)(blockDim.x >> 6);
 
-  for (long long i0 = wave0 * 64; i0 < n; i0 += stride) {
-    const long long i = i0 + lane;
-    bool pair = false;
-    double r1 = 0.0;
-    int kpair = 0, inst = 0;
-    long long s = 0;
-    V3 x{}, kv{};
-    uint64_t id = 0;
-    if (i < n) {
-      const unsigned long long e = a.cand[i];
-      const long long g = (long long)(e >> 16);
-      const int kc = (int)(e & 0xFFFFull);
-      int lo = 0, hi = a.n_inst;  // pho_pref[lo] <= g < pho_pref[hi]
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (a.pho_pref[mid] <= g) lo = mid;
-        else hi = mid;
-      }
-      inst = lo;
-      s = a.inst[inst].base[QED_PHOTON] + (g - a.pho_pref[inst]);
-      id = S.id[s];
-      x = {S.x[s], S.y[s], S.z[s]};
-      kv = {S.px[s], S.py[s], S.pz[s]};
-      const double kabs = sqrt(dot(kv, kv));
-      const uint64_t seed = a.inst[inst].seed;
-      const PhotonSetup st = photon_setup<MIXED, FMODE>(a, fld, inst, x, kv, kabs, nullptr);
-      int done = st.nsub;
-      for (int k = 0; k < st.nsub; ++k) {
-        if (a.push_photons) x = {x.x + st.hk * kv.x, x.y + st.hk * kv.y, x.z + st.hk * kv.z};
-        if (k < kc) continue;  // settled by the bound in photon_kernel
-        const uint4 o = draw_words(id, seed, step, (uint32_t)k, kDraw);
-        if (k > kc && !below_bound<MIXED>(o, st.pbound)) {
-          ++cnt.early;
-          continue;
-        }
-        if (pair_decision<MIXED>(a, ser64, ser32, o, st.chi, st.pref, cnt, &r1)) {
-          pair = true;
-          kpair = k;
-          done = k + 1;
-          break;
-        }
-      }
-      cnt.subs += done - kc;
-      if (a.push_photons) {
-        S.x[s] = x.x;
-        S.y[s] = x.y;
-        S.z[s] = x.z;
-      }
-      if (pair) S.id[s] = QED_ID_DEAD;
-    }
-    // ---- stage pair creations; reserve e-/e+ slots once per batch ----
-    const uint64_t pm = wave_ballot(pair);
-    if (pm) {
-      const int n_new = __popcll(pm);
-      wc.events += n_new;
-      if (staged + n_new > kStageCap) {
-        flush_pairs(a, ps, staged, step, cnt);
-        staged = 0;
-      }
-      if (pair) {
-        const int r = staged + __popcll(pm & below);
-        ps.x[r] = x.x;
-        ps.y[r] = x.y;
-        ps.z[r] = x.z;
-        ps.kx[r] = kv.x;
-        ps.ky[r] = kv.y;
-        ps.kz[r] = kv.z;
-        ps.r1[r] = r1;
-        ps.w[r] = S.w[s];
-        ps.parent[r] = id;
-        ps.sub[r] = (unsigned)kpair;
-        ps.inst[r] = inst;
-      }
-      staged += n_new;
-    }
+  // the photon kernel's per-wavefront lists, one list per wavefront at a time
+  for (int sw = c.wid; sw < a.pho_waves; sw += V) {
+    const long long n = (long long)a.candn[sw];
+    const unsigned long long* list = a.candw + (size_t)sw * a.cand_per_wave;
+    for (long long i0 = 0; i0 < n; i0 += 64)
+      exact_batch<MIXED, FMODE>(a, c, ps, cnt, wc, list, i0, n);
   }
-  if (staged > 0) flush_pairs(a, ps, staged, step, cnt);
+  // then the overflow list
+  long long n = (long long)hdr->n_cand;
+  if (n > a.cand_cap) n = a.cand_cap;
+  for (long long i0 = (long long)c.wid * 64; i0 < n; i0 += (long long)V * 64)
+    exact_batch<MIXED, FMODE>(a, c, ps, cnt, wc, a.cand, i0, n);
+
+  if (c.staged > 0) flush_pairs(a, ps, c.staged, c.step, cnt);
+  if (a.qa.per_wave > 0) {
+    c.tally.flush(a.qa, c.wid);
+    if (lane_id() == 0) a.qa.nrec[c.wid] = (unsigned)c.nrec;
+  }
   wave_to_block(bs, cnt, wc);
   __syncthreads();
   block_stats_store(bs, a.ex_part);
+}
+
+// ------------------------------------------------------------------------------------
+// arena append: scan of the per-(instance, wavefront) counts, then the copy into the stores
+// ------------------------------------------------------------------------------------
+// One workgroup per instance: exclusive prefix over the wavefronts of each arena's counts
+// (in place), the store count before the append into base[], and the counts raised by the
+// totals.  Counts above the capacity are clamped by the finalize kernel; the copy kernel
+// drops and counts the children that land beyond it.
+__global__ void __launch_bounds__(1024) arena_scan_kernel(StepArgs a) {
+  __shared__ unsigned long long wsum[16];
+  const int i = blockIdx.x;
+  const int lane = lane_id();
+  const int wv = (int)(threadIdx.x >> 6);
+  const int nw = (int)(blockDim.x >> 6);
+  for (int kind = 0; kind < 2; ++kind) {
+    const ChildArena& A = kind == 0 ? a.pa : a.qa;
+    if (A.per_wave <= 0) continue;
+    unsigned int* row = A.cnt + (size_t)i * A.waves;
+    unsigned long long carry = 0;
+    for (int b0 = 0; b0 < A.waves; b0 += (int)blockDim.x) {
+      const int j = b0 + (int)threadIdx.x;
+      const unsigned long long v = j < A.waves ? row[j] : 0ull;
+      unsigned long long x = v;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const unsigned long long y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+      }
+      if (lane == 63) wsum[wv] = x;
+      __syncthreads();
+      unsigned long long before = carry;
+      for (int q = 0; q < wv; ++q) before += wsum[q];
+      unsigned long long chunk = 0;
+      for (int q = 0; q < nw; ++q) chunk += wsum[q];
+      if (j < A.waves) row[j] = (unsigned)(before + x - v);
+      carry += chunk;
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      qed_instance& I = a.inst[i];
+      if (kind == 0) {
+        A.base[2 * i] = I.count[QED_PHOTON];
+        I.count[QED_PHOTON] += (long long)carry;
+      } else {
+        A.base[2 * i] = I.count[QED_ELECTRON];
+        A.base[2 * i + 1] = I.count[QED_POSITRON];
+        I.count[QED_ELECTRON] += (long long)carry;
+        I.count[QED_POSITRON] += (long long)carry;
+      }
+    }
+  }
+}
+
+// Count n children dropped for lack of capacity (rare: only at a full store).
+__device__ __forceinline__ void count_drops(const StepArgs& a, int inst, bool lost) {
+  uint64_t m = wave_ballot(lost);
+  while (m) {
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    const int li = wave_bcast(inst, leader);
+    const uint64_t same = wave_ballot(lost && inst == li);
+    if (lane_id() == leader) {
+      atomicAdd(reinterpret_cast<unsigned long long*>(&a.inst[li].dropped),
+                (unsigned long long)__popcll(same));
+      atomicAdd(reinterpret_cast<unsigned long long*>(&a.stats->dropped),
+                (unsigned long long)__popcll(same));
+    }
+    m &= ~same;
+  }
+}
+
+// One wavefront per producing wavefront: walks its records in order and gives each the
+// next store slot of its instance after the offsets of the scan (a per-instance running
+// count in LDS), then writes the child (photon) or both children (pair record).
+__global__ void __launch_bounds__(256) arena_copy_kernel(StepArgs a) {
+  __shared__ unsigned int lcnt[kWavesPerBlock][kArenaMaxInstances];
+  unsigned int* run = lcnt[threadIdx.x >> 6];
+  const uint64_t below = lanes_below();
+  const int lane = lane_id();
+  const uint32_t step = (uint32_t)a.hdr->step;
+  const int npa = a.pa.per_wave > 0 ? a.pa.waves : 0;
+  const int nqa = a.qa.per_wave > 0 ? a.qa.waves : 0;
+  const int V = (int)gridDim.x * (int)(blockDim.x >> 6);
+  for (int t = wave_index(); t < npa + nqa; t += V) {
+    const bool pair = t >= npa;
+    const ChildArena& A = pair ? a.qa : a.pa;
+    const int sw = pair ? t - npa : t;
+    const long long n = (long long)A.nrec[sw];
+    if (n == 0) continue;
+    for (int q = lane; q < a.n_inst; q += 64) run[q] = 0u;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const long long r0 = (long long)sw * A.per_wave;
+    for (long long j0 = 0; j0 < n; j0 += 64) {
+      const long long j = j0 + lane;
+      const bool has = j < n;
+      const long long r = r0 + (has ? j : 0);
+      const int li = has ? (int)A.inst[r] : -1;
+      unsigned local = 0;
+      uint64_t m = wave_ballot(has);
+      while (m) {
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        const int lj = wave_bcast(li, leader);
+        const uint64_t same = wave_ballot(has && li == lj);
+        const unsigned c0 = run[lj];
+        if (has && li == lj) local = c0 + (unsigned)__popcll(same & below);
+        __builtin_amdgcn_wave_barrier();
+        if (lane == leader) run[lj] = c0 + (unsigned)__popcll(same);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        m &= ~same;
+      }
+      bool lost0 = false, lost1 = false;
+      if (has) {
+        const qed_instance& I = a.inst[li];
+        const long long off = (long long)A.cnt[(size_t)li * A.waves + sw] + local;
+        const uint64_t seed = I.seed;
+        const uint32_t sub = A.sub[r];
+        const uint64_t parent = A.parent[r];
+        const double x = A.x[r], y = A.y[r], z = A.z[r];
+        const double px = A.px[r], py = A.py[r], pz = A.pz[r], w = A.w[r];
+        if (!pair) {
+          const long long d = A.base[2 * li] + off;
+          if (d < I.capacity[QED_PHOTON]) {
+            const qed_soa& o = a.sp[QED_PHOTON];
+            const long long q = I.base[QED_PHOTON] + d;
+            o.x[q] = x;
+            o.y[q] = y;
+            o.z[q] = z;
+            o.px[q] = px;
+            o.py[q] = py;
+            o.pz[q] = pz;
+            o.w[q] = w;
+            o.id[q] = child_id(parent, seed, step, sub, kPhotonChild);
+            o.parent[q] = parent;
+            o.birth[q] = birth_code(step, sub);
+            if (o.n_events) o.n_events[q] = 0u;
+          } else {
+            lost0 = true;
+          }
+        } else {
+          // electron takes r1 of the photon momentum, positron the rest (Sec. V.A)
+          const double r1 = A.r1[r];
+          const double r1c = 1.0 - r1;
+          const long long de = A.base[2 * li] + off;
+          if (de < I.capacity[QED_ELECTRON]) {
+            const qed_soa& o = a.sp[QED_ELECTRON];
+            const long long q = I.base[QED_ELECTRON] + de;
+            o.x[q] = x;
+            o.y[q] = y;
+            o.z[q] = z;
+            o.px[q] = r1 * px;
+            o.py[q] = r1 * py;
+            o.pz[q] = r1 * pz;
+            o.w[q] = w;
+            o.id[q] = child_id(parent, seed, step, sub, kElectronChild);
+            o.parent[q] = parent;
+            o.birth[q] = birth_code(step, sub);
+            if (o.n_events) o.n_events[q] = 0u;
+          } else {
+            lost0 = true;
+          }
+          const long long dp = A.base[2 * li + 1] + off;
+          if (dp < I.capacity[QED_POSITRON]) {
+            const qed_soa& o = a.sp[QED_POSITRON];
+            const long long q = I.base[QED_POSITRON] + dp;
+            o.x[q] = x;
+            o.y[q] = y;
+            o.z[q] = z;
+            o.px[q] = r1c * px;
+            o.py[q] = r1c * py;
+            o.pz[q] = r1c * pz;
+            o.w[q] = w;
+            o.id[q] = child_id(parent, seed, step, sub, kPositronChild);
+            o.parent[q] = parent;
+            o.birth[q] = birth_code(step, sub);
+            if (o.n_events) o.n_events[q] = 0u;
+          } else {
+            lost1 = true;
+          }
+        }
+      }
+      if (wave_ballot(lost0 || lost1)) {
+        count_drops(a, li, lost0);
+        count_drops(a, li, lost1);
+      }
+    }
+  }
 }
 
 #undef LEPTON_COL
@@ -1042,6 +1357,12 @@ static void launch_persistent(const StepArgs& a, LaunchShape lep, LaunchShape ph
       hipLaunchKernelGGL((photon_exact_kernel<MIXED, FMODE>), dim3(a.ex_grid), dim3(256), 0, s, a);
     if (a.events[3]) (void)hipEventRecord(a.events[3], s);
   }
+  const int src = (a.pa.per_wave > 0 ? a.pa.waves : 0) + (a.qa.per_wave > 0 ? a.qa.waves : 0);
+  if (src > 0) {
+    hipLaunchKernelGGL(arena_scan_kernel, dim3(a.n_inst), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(arena_copy_kernel, dim3((src + kWavesPerBlock - 1) / kWavesPerBlock),
+                       dim3(256), 0, s, a);
+  }
 }
 
 static int field_mode(int kind) {
@@ -1052,7 +1373,11 @@ static int field_mode(int kind) {
 
 hipError_t launch_step(const StepArgs& a, int precision, LaunchShape lep, LaunchShape pho,
                        bool run_photons, hipStream_t s) {
-  hipLaunchKernelGGL(prep_kernel, dim3(1), dim3(256), 0, s, a, run_photons ? 1 : 0);
+  const long long zero_words = (a.pa.per_wave > 0 ? (long long)a.n_inst * a.pa.waves : 0) +
+                              (a.qa.per_wave > 0 ? (long long)a.n_inst * a.qa.waves : 0);
+  long long zb = (zero_words + 2047) / 2048;
+  if (zb > 1024) zb = 1024;
+  hipLaunchKernelGGL(prep_kernel, dim3(1 + (int)zb), dim3(256), 0, s, a, run_photons ? 1 : 0);
   const int fm = field_mode(a.field.kind);
   if (precision == QED_MIXED) {
     if (fm == kFieldEB) launch_persistent<true, kFieldEB>(a, lep, pho, run_photons, s);

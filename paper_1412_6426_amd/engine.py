@@ -25,7 +25,8 @@ class Engine:
     """SoA stores for n instances, each owning a segment of every species store."""
 
     def __init__(self, capacities: Sequence[Tuple[int, int, int]], seeds: Sequence[int],
-                 amps: Optional[Sequence[float]] = None, device: str = "cuda:0"):
+                 amps: Optional[Sequence[float]] = None, device: str = "cuda:0",
+                 arena_records: Optional[int] = None):
         torch = _torch()
         if not torch.cuda.is_available():
             raise Q.QedError("no HIP device visible: the QED step runs only on the GPU")
@@ -60,7 +61,11 @@ class Engine:
         self._inst_init = np.frombuffer(bytes(inst), dtype=np.uint8).copy()
         self.inst = torch.from_numpy(self._inst_init.copy()).to(self.device)
         self.tables = torch.zeros(Q.qed_table_bytes(), dtype=torch.uint8, device=self.device)
-        self.work_bytes = Q.qed_work_bytes(self.n_inst, int(self.cols[2]["x"].numel()))
+        pslots = int(self.cols[2]["x"].numel())
+        if arena_records is None:
+            arena_records = min(max(pslots // 8, 1 << 16), 1 << 26)
+        self.arena_records = int(arena_records)
+        self.work_bytes = Q.qed_work_bytes(self.n_inst, pslots, self.arena_records)
         self.work = torch.zeros(self.work_bytes, dtype=torch.uint8, device=self.device)
         self.stats_buf = torch.zeros(C.sizeof(Q.qed_stats), dtype=torch.uint8, device=self.device)
         self.step_ctr = torch.zeros(1, dtype=torch.int64, device=self.device)

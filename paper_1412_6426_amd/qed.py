@@ -111,7 +111,7 @@ def lib():
         L.qed_build_tables.restype = C.c_int
         L.qed_build_tables.argtypes = [C.c_void_p, C.c_size_t, C.c_void_p]
         L.qed_work_bytes.restype = C.c_size_t
-        L.qed_work_bytes.argtypes = [C.c_int, C.c_int64]
+        L.qed_work_bytes.argtypes = [C.c_int, C.c_int64, C.c_int64]
         L.qed_step.restype = C.c_int
         L.qed_step.argtypes = [C.c_void_p, C.POINTER(qed_stores), C.POINTER(qed_field),
                                C.POINTER(qed_params), C.c_void_p, C.c_void_p, C.c_void_p,
@@ -148,8 +148,8 @@ def qed_build_tables(d_tables: int, nbytes: int, stream: int) -> None:
     _check(lib().qed_build_tables(d_tables, nbytes, stream), "qed_build_tables")
 
 
-def qed_work_bytes(n_instances: int, photon_slots: int) -> int:
-    return int(lib().qed_work_bytes(n_instances, photon_slots))
+def qed_work_bytes(n_instances: int, photon_slots: int, arena_records: int = 0) -> int:
+    return int(lib().qed_work_bytes(n_instances, photon_slots, arena_records))
 
 
 def qed_step(d_tables: int, stores: qed_stores, field: qed_field, params: qed_params,

@@ -68,10 +68,19 @@ def test_host_side_queries(Q):
     assert Q.qed_version() >= 100
     assert Q.qed_work_bytes(0, 10) == 0
     assert Q.qed_work_bytes(1, -1) == 0
+    assert Q.qed_work_bytes(1, 10, -1) == 0
     w1, w64 = Q.qed_work_bytes(1, 1000), Q.qed_work_bytes(64, 1000)
     assert 64 <= w1 < w64
-    # one candidate-list entry (8 bytes) per photon slot
-    assert abs(Q.qed_work_bytes(1, 2000) - w1 - 8000) < 256
+    # two candidate-list entries (8 bytes each) per photon slot: per-wavefront lists and
+    # the overflow list
+    assert abs(Q.qed_work_bytes(1, 2000) - w1 - 16000) < 512
+    # arenas: 72 bytes per photon record, 80 per pair record (a quarter of the records,
+    # at least 4096), plus the count matrices and per-wavefront totals
+    a0 = Q.qed_work_bytes(1, 1000, 1 << 20)
+    a1 = Q.qed_work_bytes(1, 1000, 1 << 21)
+    assert a0 > w1 and abs((a1 - a0) - (72 + 20) * (1 << 20)) < 8192
+    # no arenas above 1024 instances
+    assert Q.qed_work_bytes(1025, 1000, 1 << 20) == Q.qed_work_bytes(1025, 1000)
     assert Q.lib().qed_status_string(1) == b"invalid argument"
 
 

@@ -77,14 +77,19 @@ def test_uniform_b_full_size_parity(orc):
     assert sum(s["saturated"] for s in stats) == 0 and stats[-1]["status"] == 0
 
 
-@pytest.mark.parametrize("precision_check", ["f64"])
-def test_rotating_cascade_parity(orc, precision_check):
+# Child appends: through the per-wavefront arenas (default), with an arena so small that
+# most children take the direct-reservation path, and with no arena at all.
+ARENA_MODES = {"arena": None, "tiny_arena": 5000, "no_arena": 0}
+
+
+@pytest.mark.parametrize("arena", list(ARENA_MODES))
+def test_rotating_cascade_parity(orc, arena):
     """Rotating-E cascade (a0 = 1000, lambda = 0.8 um, dt = T/200) from 300 seeds through
     300 steps: emission, pairs, photon push; every store compared."""
     w = W.rotating_e(n=300, periods=1.5, capacity=400_000, lepton_capacity=40_000)
     init = W.rotating_e_initial(300, seed=3)
-    _note(f"rotating cascade: {w.description}")
-    e = R.engine_single(w, init)
+    _note(f"rotating cascade ({arena}): {w.description}")
+    e = R.engine_single(w, init, arena_records=ARENA_MODES[arena])
     stats = R.run(e, R.field_of(w), R.params_of(w), w.n_steps)
     os_ = oracle_stores(orc, init, w.capacity)
     ostats = orc.run(os_, oracle_field(orc, w), oracle_params(orc, w), w.n_steps)
@@ -124,13 +129,14 @@ def test_empty_and_single_particle(orc):
     compare_all(e, os_, label="single")
 
 
-def test_capacity_overflow_is_counted_and_contained(orc):
+@pytest.mark.parametrize("arena", list(ARENA_MODES))
+def test_capacity_overflow_is_counted_and_contained(orc, arena):
     """Tiny photon capacity: drops counted, count clamped, nothing written past the
     instance's segment (a guard instance after it keeps its contents)."""
     w = W.uniform_b(n=500, steps=2)
     init = W.uniform_b_initial(w)
-    _note("capacity overflow")
-    e = Engine([(500, 1, 40), (1, 1, 64)], [0, 1])
+    _note(f"capacity overflow ({arena})")
+    e = Engine([(500, 1, 40), (1, 1, 64)], [0, 1], arena_records=ARENA_MODES[arena])
     e.build_tables()
     for s in range(3):
         e.load(0, s, init[s])
@@ -174,15 +180,16 @@ def _batched_oracle(orc, w, inits, i, periods):
     return os_, ost
 
 
-def test_batched_instances_match_single_runs(orc):
+@pytest.mark.parametrize("arena", ["arena", "no_arena"])
+def test_batched_instances_match_single_runs(orc, arena):
     """Five instances of different size, amplitude and seed (one empty) in one launch:
     each equals its own oracle run."""
     w = W.batched_rotating(instances=5, a_lo=600.0, a_hi=2400.0, periods=0.75,
                            n_override=[37, 0, 129, 64, 200], total_capacity=5 * 400_000,
                            precision="f64")
     inits = W.batched_initial(w)
-    _note(f"batched: {w.description}")
-    e = R.engine_batched(w, inits)
+    _note(f"batched ({arena}): {w.description}")
+    e = R.engine_batched(w, inits, arena_records=ARENA_MODES[arena])
     st = R.run(e, R.field_of(w), R.params_of(w), w.n_steps, stop_on_drop=False)
     assert sum(s["dropped"] for s in st) == 0
     for i in range(w.instances):
@@ -221,13 +228,16 @@ def test_runs_are_reproducible(orc):
     w = W.rotating_e(n=500, periods=0.6, capacity=100_000, lepton_capacity=10_000)
     init = W.rotating_e_initial(500, seed=4)
     outs = []
-    for rep in range(2):
+    for rep, tile in enumerate((64, 128, 64)):
         _note(f"determinism run {rep}")
         e = R.engine_single(w, init)
-        R.run(e, R.field_of(w), R.params_of(w, tile=64 * (rep + 1)), w.n_steps)
+        R.run(e, R.field_of(w), R.params_of(w, tile=tile), w.n_steps)
         outs.append([e.read(0, s) for s in range(3)])
     for s in range(3):
         compare_species(outs[0][s], outs[1][s], s, rtol=0.0, label="rerun")
+        # with the child arenas the store order itself is fixed by the work distribution
+        for c, v in outs[0][s].items():
+            assert np.array_equal(v, outs[2][s][c], equal_nan=True), (s, c)
 
 
 def test_stats_log_and_graph_replay(orc):
