@@ -10,11 +10,18 @@ store is full; from then on the instance is frozen (its steps do nothing) and th
 particle-step count stops growing.
 
 Prints one JSON line: particle-steps/s over the timed steps, the roofline of the dominant
-kernel (algorithmic bytes / its event-timed duration vs 8 TB/s), and the FP64 CPU
-oracle's rate on a bounded sample of the same workload on this host.
+kernel (algorithmic bytes / its event-timed duration vs 8 TB/s), the same run in mixed
+precision with its photon-spectrum L1 distance and pair yield against the FP64 run, and
+the FP64 CPU oracle's rate on a bounded sample of the same workload on this host.
+
+HBM traffic of the dominant kernel comes from the rocprofv3 counter summary committed
+under profiles/ (FETCH_SIZE and WRITE_SIZE scaled by the same counters' reading for a copy
+kernel of known size); it is reported only while the kernel source still has the hash
+recorded there, else null.
 """
 import argparse
 import ctypes as C
+import hashlib
 import json
 import math
 import os
@@ -25,13 +32,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+METRIC = "QED particle-steps/s + HBM roofline %, mixed vs FP64 at fixed spectrum error"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+KERNEL_SRC = os.path.join(ROOT, "paper_1412_6426_amd", "csrc", "qed_step.hip")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "photon_kernel_rotating_cascade_hbm_counters.md")
 # algorithmic bytes (per unit of work) of the two persistent kernels
 LEPTON_STEP_BYTES = 112   # read x,p (48) id (8) n_events (4); write x,p (48) n_events (4)
 PHOTON_STEP_BYTES = 80    # read x,k (48) id (8); write x (24)
 DEAD_SLOT_BYTES = 8       # id of a removed photon, read and skipped
 EMISSION_BYTES = 84       # photon child written (x,k,w,id,parent,birth = 76) + parent w read (8)
-PAIR_BYTES = 176          # two lepton children (2 x 80) + photon w read (8) + tombstone id (8)
 
 
 class HipEvents:
@@ -63,7 +72,16 @@ class HipEvents:
             self.lib.hipEventDestroy(e)
 
 
+def _stats_records(raw, K):
+    from paper_1412_6426_amd import qed as Q
+    n = C.sizeof(Q.qed_stats)
+    return [Q.qed_stats.from_buffer_copy(raw[i * n:(i + 1) * n]) for i in range(K)]
+
+
 def gpu_run(args, precision):
+    """The cascade twice from the same seeds: K graph-replayed steps timed as a whole
+    (value), then K eager steps with HIP events around the lepton and photon kernels
+    (per-kernel durations for the roofline).  Both runs are the same computation."""
     import numpy as np
     import torch
     from paper_1412_6426_amd import qed as Q
@@ -76,74 +94,141 @@ def gpu_run(args, precision):
     e = R.engine_single(w, init)
     field = R.field_of(w)
     params = R.params_of(w, freeze_on_drop=1, tile=args.tile, grid_blocks=args.grid_blocks)
-    torch.cuda.synchronize()
-
-    # warm-up steps on the same stores, then back to the seed state
-    for _ in range(args.warmup):
-        e.step(field, params)
-    torch.cuda.synchronize()
-    e.reset_instances()
-    for s in range(3):
-        e.load(0, s, init[s])
-    e.set_step(0)
-    torch.cuda.synchronize()
-
     K = args.steps if args.steps is not None else w.n_steps
-    hip = HipEvents()
-    evs = hip.create(4 * K)
+    stream = torch.cuda.Stream()
+    sp = stream.cuda_stream
     log = torch.zeros(K * e.stats_buf.numel(), dtype=torch.uint8, device=e.device)
     cnt = torch.zeros(1, dtype=torch.int64, device=e.device)
-    stream = e.stream
+
+    def restart():
+        torch.cuda.synchronize()
+        e.reset_instances()
+        for s in range(3):
+            e.load(0, s, init[s])
+        e.set_step(0)
+        cnt.zero_()
+        torch.cuda.synchronize()
+
+    # warm-up steps on the same stores, then back to the seed state
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            e.step(field, params, stream=sp)
+    restart()
+
+    # ---- timed: one step (and its stats record) captured once, replayed K times ----
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        e.step(field, params, stream=sp)
+        Q.qed_append_stats(e.stats_buf.data_ptr(), log.data_ptr(), K, cnt.data_ptr(), sp)
+    restart()
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     wall0 = time.perf_counter()
-    t_start.record()
-    for n in range(K):
-        for j in range(4):
-            params.events[j] = evs[4 * n + j]
-        e.step(field, params)
-        Q.qed_append_stats(e.stats_buf.data_ptr(), log.data_ptr(), K, cnt.data_ptr(), stream)
-    t_end.record()
+    with torch.cuda.stream(stream):  # replay() launches on the current stream
+        t_start.record(stream)
+        for _ in range(K):
+            graph.replay()
+        t_end.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     ms = t_start.elapsed_time(t_end)
+    recs = _stats_records(log.cpu().numpy().tobytes(), K)
+    counts = e.counts()[0].tolist()
+    hist = None
+    if args.spectrum:
+        hist = torch.zeros(W.SPECTRUM_BINS, dtype=torch.float64, device=e.device)
+        Q.qed_photon_spectrum(e.stores, W.SPECTRUM_LO, W.SPECTRUM_HI, W.SPECTRUM_BINS,
+                              hist.data_ptr(), sp)
+        torch.cuda.synchronize()
+        hist = hist.cpu().numpy()
+    del graph
 
-    raw = log.cpu().numpy().tobytes()
-    recs = [Q.qed_stats.from_buffer_copy(raw[i * C.sizeof(Q.qed_stats):(i + 1) * C.sizeof(Q.qed_stats)])
-            for i in range(K)]
-    lep_ms = sum(hip.elapsed_ms(evs[4 * n], evs[4 * n + 1]) for n in range(K))
-    pho_ms = sum(hip.elapsed_ms(evs[4 * n + 2], evs[4 * n + 3]) for n in range(K))
+    # ---- per-kernel durations: the same K steps eagerly, HIP events on our stream ----
+    restart()
+    hip = HipEvents()
+    evs = hip.create(4 * K)
+    with torch.cuda.stream(stream):
+        for n in range(K):
+            for j in range(4):
+                params.events[j] = evs[4 * n + j]
+            e.step(field, params, stream=sp)
+            Q.qed_append_stats(e.stats_buf.data_ptr(), log.data_ptr(), K, cnt.data_ptr(), sp)
+    torch.cuda.synchronize()
+    lep_t = [hip.elapsed_ms(evs[4 * n], evs[4 * n + 1]) for n in range(K)]
+    pho_t = [hip.elapsed_ms(evs[4 * n + 2], evs[4 * n + 3]) for n in range(K)]
     hip.destroy(evs)
+    recs2 = _stats_records(log.cpu().numpy().tobytes(), K)
+    same = all(a.emitted == b.emitted and a.pairs == b.pairs and
+               list(a.advanced) == list(b.advanced) for a, b in zip(recs, recs2))
+
     adv = [sum(r.advanced[s] for r in recs) for s in range(3)]
     dead_slots = sum(r.n_start[2] - r.advanced[2] for r in recs)
     emitted = sum(r.emitted for r in recs)
     pairs = sum(r.pairs for r in recs)
     lep_bytes = LEPTON_STEP_BYTES * (adv[0] + adv[1]) + EMISSION_BYTES * emitted
-    pho_bytes = PHOTON_STEP_BYTES * adv[2] + DEAD_SLOT_BYTES * dead_slots + PAIR_BYTES * pairs
+    pho_bytes = PHOTON_STEP_BYTES * adv[2] + DEAD_SLOT_BYTES * dead_slots
     active = sum(1 for r in recs if sum(r.advanced) > 0)
     first_drop = next((r.step for r in recs if r.dropped > 0), None)
     out = dict(
         ms=ms, wall_s=wall, steps=K, active_steps=active, first_drop_step=first_drop,
         particle_steps=int(sum(adv)), advanced=[int(a) for a in adv], emitted=int(emitted),
-        pairs=int(pairs), lep_ms=lep_ms, pho_ms=pho_ms, lep_bytes=lep_bytes,
-        pho_bytes=pho_bytes, final_counts=e.counts()[0].tolist(),
+        pairs=int(pairs), lep_ms=sum(lep_t), pho_ms=sum(pho_t), lep_bytes=lep_bytes,
+        pho_bytes=pho_bytes, final_counts=counts, eager_matches_graph=bool(same),
         substeps=int(sum(r.substeps for r in recs)),
         low_occupancy_iters=int(sum(r.low_occupancy_iters for r in recs)),
         wave_iters=int(sum(r.wave_iters for r in recs)),
         near_threshold=int(sum(r.near_threshold for r in recs)),
         saturated=int(sum(r.saturated for r in recs)),
         early_out=int(sum(r.early_out for r in recs)),
+        # per step, for the precision comparison
+        step_pairs=[int(r.pairs) for r in recs], step_emitted=[int(r.emitted) for r in recs],
+        step_hist=np.array([list(r.photon_hist) for r in recs], dtype=np.float64),
+        step_dropped=[int(r.dropped) for r in recs], spectrum=hist,
     )
-    if args.spectrum:
-        hist = torch.zeros(W.SPECTRUM_BINS, dtype=torch.float64, device=e.device)
-        Q.qed_photon_spectrum(e.stores, W.SPECTRUM_LO, W.SPECTRUM_HI, W.SPECTRUM_BINS,
-                              hist.data_ptr(), stream)
-        torch.cuda.synchronize()
-        out["spectrum"] = hist.cpu().numpy()
     del e
     torch.cuda.empty_cache()
     return out
+
+
+def precision_compare(r64, rmx):
+    """Mixed vs FP64 over the steps before either run first drops a child: L1 distance of
+    the emitted-photon spectra (130 log bins of eps in [1e-8, 1e5]) and the pair yield."""
+    import numpy as np
+    K = len(r64["step_pairs"])
+    d = [k for k in range(K) if r64["step_dropped"][k] or rmx["step_dropped"][k]]
+    upto = d[0] if d else K
+    h64 = r64["step_hist"][:upto].sum(axis=0)
+    hmx = rmx["step_hist"][:upto].sum(axis=0)
+    p64 = sum(r64["step_pairs"][:upto])
+    pmx = sum(rmx["step_pairs"][:upto])
+    return {
+        "steps_compared": upto,
+        "spectrum_l1_vs_f64": float(np.abs(hmx - h64).sum() / max(h64.sum(), 1.0)),
+        "photons_f64": int(h64.sum()), "photons_mixed": int(hmx.sum()),
+        "pairs_f64": int(p64), "pairs_mixed": int(pmx),
+        "pair_yield_rel_diff": (pmx - p64) / max(p64, 1),
+    }
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if the kernel
+    source is unchanged since the counters were taken."""
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if vals.get("kernel") != kernel or vals.get("kernel_source_sha256") != src:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(args):
@@ -153,8 +238,10 @@ def cpu_baseline(args):
     from paper_1412_6426_amd import workloads as W
     from tests.parity_util import oracle_field, oracle_params, oracle_stores
 
-    w = W.rotating_e(n=args.cpu_seeds, a0=args.a0, periods=3.0, capacity=4_000_000,
-                     lepton_capacity=400_000)
+    # same per-seed capacity as the GPU run (10^8 slots per store for 10^5 seeds)
+    cap = max(1000, args.capacity * args.cpu_seeds // args.seeds)
+    w = W.rotating_e(n=args.cpu_seeds, a0=args.a0, periods=3.0, capacity=cap,
+                     lepton_capacity=cap)
     init = W.rotating_e_initial(args.cpu_seeds, seed=0)
     st = oracle_stores(orc, init, w.capacity)
     fld, par = oracle_field(orc, w), oracle_params(orc, w)
@@ -188,12 +275,13 @@ def main():
     ap.add_argument("--capacity", type=int, default=100_000_000)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--grid-blocks", type=int, default=0)
-    ap.add_argument("--cpu-seeds", type=int, default=200)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seeds", type=int, default=20000)
+    ap.add_argument("--cpu-seconds", type=float, default=25.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--compare-mixed", action="store_true",
-                    help="also run the mixed-precision form and report its rate and accuracy")
-    ap.add_argument("--spectrum", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-precision run and its accuracy comparison")
+    ap.add_argument("--spectrum", action="store_true",
+                    help="also histogram the final photon stores")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -204,19 +292,22 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
-    if args.compare_mixed:
-        args.spectrum = True
     print(f"bench: rotating-E cascade, {args.seeds} seeds, precision {args.precision}",
           file=sys.stderr, flush=True)
     r = gpu_run(args, args.precision)
+    print(f"bench: {r['particle_steps']} particle-steps in {r['ms']:.1f} ms", file=sys.stderr,
+          flush=True)
     secs = r["ms"] / 1e3
     value = r["particle_steps"] / secs
     dom = "photon" if r["pho_ms"] >= r["lep_ms"] else "lepton"
     kbytes = r["pho_bytes"] if dom == "photon" else r["lep_bytes"]
     kms = r["pho_ms"] if dom == "photon" else r["lep_ms"]
+    launches = r["steps"]
     achieved = kbytes / (kms / 1e3) / 1e9 if kms > 0 else 0.0
+    # the rotating-field specialisation of the kernel, FP64 or mixed
+    traffic = measured_traffic(f"{dom}_kernel<{'true' if args.precision == 'mixed' else 'false'}, 1>")
     line = {
-        "metric": "QED particle-steps/s (rotating-E cascade)",
+        "metric": METRIC,
         "value": value,
         "unit": "particle-steps/s",
         "n_gpus": 1,
@@ -226,7 +317,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "f64" else "f64+f32 (mixed)",
+        "dtype": "f64" if args.precision == "f64" else "f64+f32",
         "data": "synthetic (seeded)",
         "config": {
             "workload": "rotating_e_cascade",
@@ -241,28 +332,30 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch (mean over the run's launches)",
+            "algorithmic_bytes_per_launch": kbytes / launches,
+            "avg_launch_us": kms * 1e3 / launches,
         },
         "detail": {k: r[k] for k in ("active_steps", "first_drop_step", "particle_steps",
                                      "advanced", "emitted", "pairs", "final_counts",
                                      "lep_ms", "pho_ms", "substeps", "wave_iters",
                                      "low_occupancy_iters", "near_threshold", "saturated",
-                                     "early_out")},
+                                     "early_out", "eager_matches_graph")},
     }
-    if args.compare_mixed:
-        import numpy as np
-        m = gpu_run(args, "mixed")
-        h64, hm = r["spectrum"], m["spectrum"]
-        l1 = float(np.abs(hm - h64).sum() / max(h64.sum(), 1e-300))
-        line["mixed"] = {
-            "value": m["particle_steps"] / (m["ms"] / 1e3),
-            "speedup_vs_f64": (m["particle_steps"] / m["ms"]) / (r["particle_steps"] / r["ms"]),
-            "spectrum_l1_vs_f64": l1,
-            "pairs_f64": r["pairs"], "pairs_mixed": m["pairs"],
-            "pair_yield_rel_diff": (m["pairs"] - r["pairs"]) / max(r["pairs"], 1),
-            "lep_ms": m["lep_ms"], "pho_ms": m["pho_ms"],
-        }
+    if not args.no_mixed:
+        other = "mixed" if args.precision == "f64" else "f64"
+        print(f"bench: the same run in {other}", file=sys.stderr, flush=True)
+        m = gpu_run(args, other)
+        r64, rmx = (r, m) if args.precision == "f64" else (m, r)
+        v64 = r64["particle_steps"] / (r64["ms"] / 1e3)
+        vmx = rmx["particle_steps"] / (rmx["ms"] / 1e3)
+        line["mixed_vs_f64"] = dict(
+            value_f64=v64, value_mixed=vmx, speedup_mixed=vmx / v64,
+            lep_ms_mixed=rmx["lep_ms"], pho_ms_mixed=rmx["pho_ms"],
+            **precision_compare(r64, rmx))
     if not args.no_cpu_baseline:
+        print("bench: oracle sample on the host", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(line), flush=True)
 

@@ -168,8 +168,9 @@ typedef struct {
   int grid_blocks;      /* persistent workgroups per kernel (<= 4096); 0 = resident
                            workgroups per CU times the CU count */
   void *events[4];      /* optional hipEvent_t recorded on `stream` right before/after the
-                           lepton kernel ([0], [1]) and the photon kernel ([2], [3]); NULL
-                           entries are skipped.  Owned by the caller. */
+                           lepton kernel ([0], [1]) and the photon bound kernel ([2], [3]),
+                           for timing those two kernels alone; NULL entries are skipped.
+                           Owned by the caller. */
 } qed_params;
 
 /* Per-step record written by qed_step (device memory). */

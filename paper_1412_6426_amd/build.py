@@ -1,7 +1,8 @@
 """Build libqed.so for gfx950 in-tree (paper_1412_6426_amd/lib/libqed.so).
 
 ``python -m paper_1412_6426_amd.build`` runs one hipcc command over the HIP sources in
-``csrc/``.  Packed-FP32 instructions are disabled for all device code.
+``csrc/`` and a second one for the HBM counter-calibration program ``calib/hbm_copy.hip``
+(``lib/hbm_copy``).  Packed-FP32 instructions are disabled for all device code.
 """
 import glob
 import os
@@ -13,6 +14,7 @@ ROOT = os.path.dirname(HERE)
 SRC_DIR = os.path.join(HERE, "csrc")
 LIB_DIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIB_DIR, "libqed.so")
+COPY_PROBE = os.path.join(LIB_DIR, "hbm_copy")
 ARCH = os.environ.get("QED_OFFLOAD_ARCH", "gfx950")
 
 
@@ -28,14 +30,20 @@ def hipcc_command(out: str, extra=()):
             *extra, "-o", out, *sources()]
 
 
+def copy_probe_command(out: str):
+    return ["hipcc", f"--offload-arch={ARCH}", "-O3", "-std=c++17",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-o", out, os.path.join(HERE, "calib", "hbm_copy.hip")]
+
+
 def build(verbose: bool = False, extra=()) -> str:
     os.makedirs(LIB_DIR, exist_ok=True)
-    tmp = LIB + ".tmp"
-    cmd = hipcc_command(tmp, extra)
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    for out, cmd in ((LIB, hipcc_command(LIB + ".tmp", extra)),
+                     (COPY_PROBE, copy_probe_command(COPY_PROBE + ".tmp"))):
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        os.replace(out + ".tmp", out)
     return LIB
 
 

@@ -1,7 +1,7 @@
 // qed_step.hip -- the per-step kernels of the QED step (Sec. IV.H adaptive event generator
 // of Gonoskov et al., arXiv:1412.6426, with the Sec. V.A pair generator).
 //
-// One step is up to seven launches on the caller's stream:
+// One step is up to eight launches on the caller's stream:
 //   prep     (1 + k wgs)    snapshot live counts, particle prefix sums over the
 //                           (instance, species) segments, space-independent fields at t_n,
 //                           zero the stats record and the arenas' count matrices;
@@ -12,8 +12,8 @@
 //   exact    (grid-stride)  the exact pair decision; pair records go to the pair arena;
 //   scan     (1 wg/instance) arena counts -> store offsets, instance counts raised;
 //   copy     (1 wave/source wave) arena records -> photon, electron, positron stores;
-//   finalize (1 workgroup)  reduce per-workgroup partial stats, clamp counts, status bits,
-//                           step index + 1.
+//   reduce   (1 wave/field) per-workgroup partial stats -> the stats record;
+//   finalize (1 workgroup)  clamp counts, status bits, step index + 1.
 // Children land after the step-start counts, so they are first processed at step n+1.
 //
 // Work distribution: the particles alive at the step start form one index space per kernel
@@ -123,74 +123,86 @@ __device__ __forceinline__ void stats_add(int64_t* p, unsigned long long v) {
   if (v) atomicAdd(reinterpret_cast<unsigned long long*>(p), v);
 }
 
-__global__ void __launch_bounds__(1024) finalize_kernel(StepArgs a) {
+// Partial-stats reduction: one wavefront per (partial set, field).  The lepton set has all
+// kPfCount fields; the photon and exact-pair sets only the counters below kPfNsub (their
+// histogram fields stay zero).  Sums go into the zeroed stats record with atomics on
+// distinct addresses.
+constexpr int kReduceJobs = kPfCount + 2 * kPfNsub;
+
+__global__ void __launch_bounds__(256) reduce_kernel(StepArgs a) {
+  const int job = (int)blockIdx.x * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6);
+  if (job >= kReduceJobs) return;
+  const int lane = (int)(threadIdx.x & 63u);
+  int kind, f;
+  if (job < kPfCount) {
+    kind = 0;
+    f = job;
+  } else {
+    kind = 1 + (job - kPfCount) / kPfNsub;
+    f = (job - kPfCount) % kPfNsub;
+  }
+  const bool pho = kind > 0;
+  const int G = kind == 0 ? a.lep_grid : (kind == 1 ? a.pho_grid : a.ex_grid);
+  if (G <= 0) return;
+  const unsigned long long* col =
+      (kind == 0 ? a.lep_part : (kind == 1 ? a.pho_part : a.ex_part)) + (size_t)f * kMaxGridBlocks;
+  qed_stats* st = a.stats;
+  if (f == kPfEnergy || f == kPfMaxP) {
+    double v = 0.0;
+    for (int b = lane; b < G; b += 64) {
+      const double x = __longlong_as_double((long long)col[b]);
+      v = (f == kPfEnergy) ? v + x : fmax(v, x);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double y = __shfl_xor(v, o, 64);
+      v = (f == kPfEnergy) ? v + y : fmax(v, y);
+    }
+    if (lane == 0 && v != 0.0) {
+      if (f == kPfEnergy) {
+        if (!pho) atomicAdd(&st->photon_energy, v);
+      } else {
+        atomic_max_nonneg(pho ? &st->max_p_pair : &st->max_p_emit, v);
+      }
+    }
+    return;
+  }
+  unsigned long long v = 0ull;
+#pragma unroll 4
+  for (int b = lane; b < G; b += 64) v += col[b];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if (lane != 0 || v == 0ull) return;
+  switch (f) {
+    case kPfSubsteps: stats_add(&st->substeps, v); break;
+    case kPfEvents: stats_add(pho ? &st->pairs : &st->emitted, v); break;
+    case kPfSaturated: stats_add(&st->saturated, v); break;
+    case kPfNear: stats_add(&st->near_threshold, v); break;
+    case kPfNonfinite: stats_add(&st->nonfinite, v); break;
+    case kPfNearInt: stats_add(&st->nsub_near_int, v); break;
+    case kPfClamped: stats_add(&st->nsub_clamped, v); break;
+    case kPfDropped: stats_add(&st->dropped, v); break;
+    case kPfEarly: stats_add(&st->early_out, v); break;
+    case kPfAdv0: stats_add(&st->advanced[pho ? QED_PHOTON : QED_ELECTRON], v); break;
+    case kPfAdv1: stats_add(&st->advanced[QED_POSITRON], v); break;
+    case kPfWaveIters: stats_add(&st->wave_iters, v); break;
+    case kPfLowOcc: stats_add(&st->low_occupancy_iters, v); break;
+    default:
+      if (f >= kPfNsub && f < kPfNsub + QED_NSUB_HIST)
+        st->nsub_hist[f - kPfNsub] = (int64_t)v;
+      else if (f >= kPfHist)
+        st->photon_hist[f - kPfHist] = (int64_t)v;
+  }
+}
+
+__global__ void __launch_bounds__(256) finalize_kernel(StepArgs a) {
   for (int i = threadIdx.x; i < a.n_inst; i += blockDim.x) {
     qed_instance& I = a.inst[i];
     for (int s = 0; s < 3; ++s)
       if (I.count[s] > I.capacity[s]) I.count[s] = I.capacity[s];
   }
-  qed_stats* st = a.stats;
-  const int lane = (int)(threadIdx.x & 63u);
-  const int wave = (int)(threadIdx.x >> 6);
-  const int nw = (int)(blockDim.x >> 6);
-  // partial sets: 0 lepton kernel, 1 photon kernel, 2 exact pair-decision kernel
-  for (int job = wave; job < 3 * kPfCount; job += nw) {
-    const int kind = job / kPfCount;
-    const int f = job - kind * kPfCount;
-    const bool pho = kind > 0;
-    const int G = kind == 0 ? a.lep_grid : (kind == 1 ? a.pho_grid : a.ex_grid);
-    const unsigned long long* base =
-        kind == 0 ? a.lep_part : (kind == 1 ? a.pho_part : a.ex_part);
-    const unsigned long long* col = base + (size_t)f * kMaxGridBlocks;
-    if (f == kPfEnergy || f == kPfMaxP) {
-      double v = 0.0;
-      for (int b = lane; b < G; b += 64) {
-        const double x = __longlong_as_double((long long)col[b]);
-        v = (f == kPfEnergy) ? v + x : fmax(v, x);
-      }
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        const double y = __shfl_xor(v, o, 64);
-        v = (f == kPfEnergy) ? v + y : fmax(v, y);
-      }
-      if (lane == 0 && v != 0.0) {
-        if (f == kPfEnergy) {
-          if (!pho) atomicAdd(&st->photon_energy, v);
-        } else {
-          atomic_max_nonneg(pho ? &st->max_p_pair : &st->max_p_emit, v);
-        }
-      }
-      continue;
-    }
-    unsigned long long v = 0ull;
-    for (int b = lane; b < G; b += 64) v += col[b];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    if (lane != 0 || v == 0ull) continue;
-    switch (f) {
-      case kPfSubsteps: stats_add(&st->substeps, v); break;
-      case kPfEvents: stats_add(pho ? &st->pairs : &st->emitted, v); break;
-      case kPfSaturated: stats_add(&st->saturated, v); break;
-      case kPfNear: stats_add(&st->near_threshold, v); break;
-      case kPfNonfinite: stats_add(&st->nonfinite, v); break;
-      case kPfNearInt: stats_add(&st->nsub_near_int, v); break;
-      case kPfClamped: stats_add(&st->nsub_clamped, v); break;
-      case kPfDropped: stats_add(&st->dropped, v); break;
-      case kPfEarly: stats_add(&st->early_out, v); break;
-      case kPfAdv0: stats_add(&st->advanced[pho ? QED_PHOTON : QED_ELECTRON], v); break;
-      case kPfAdv1: stats_add(&st->advanced[QED_POSITRON], v); break;
-      case kPfWaveIters: stats_add(&st->wave_iters, v); break;
-      case kPfLowOcc: stats_add(&st->low_occupancy_iters, v); break;
-      default:
-        if (!pho && f >= kPfNsub && f < kPfNsub + QED_NSUB_HIST)
-          st->nsub_hist[f - kPfNsub] = (int64_t)v;
-        else if (!pho && f >= kPfHist)
-          st->photon_hist[f - kPfHist] = (int64_t)v;
-    }
-  }
-  __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
+    qed_stats* st = a.stats;
     uint32_t status = st->status;
     if (st->dropped > 0) status |= QED_STATUS_DROPPED;
     if (st->nonfinite > 0) status |= QED_STATUS_NONFINITE;
@@ -1353,9 +1365,9 @@ static void launch_persistent(const StepArgs& a, LaunchShape lep, LaunchShape ph
   if (run_photons) {
     if (a.events[2]) (void)hipEventRecord(a.events[2], s);
     hipLaunchKernelGGL((photon_kernel<MIXED, FMODE>), dim3(pho.grid), dim3(pho.block), 0, s, a);
+    if (a.events[3]) (void)hipEventRecord(a.events[3], s);
     if (a.ex_grid > 0)
       hipLaunchKernelGGL((photon_exact_kernel<MIXED, FMODE>), dim3(a.ex_grid), dim3(256), 0, s, a);
-    if (a.events[3]) (void)hipEventRecord(a.events[3], s);
   }
   const int src = (a.pa.per_wave > 0 ? a.pa.waves : 0) + (a.qa.per_wave > 0 ? a.qa.waves : 0);
   if (src > 0) {
@@ -1388,7 +1400,8 @@ hipError_t launch_step(const StepArgs& a, int precision, LaunchShape lep, Launch
     else if (fm == kFieldE) launch_persistent<false, kFieldE>(a, lep, pho, run_photons, s);
     else launch_persistent<false, kFieldLocal>(a, lep, pho, run_photons, s);
   }
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(1024), 0, s, a);
+  hipLaunchKernelGGL(reduce_kernel, dim3((kReduceJobs + 3) / 4), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
