@@ -162,8 +162,9 @@ typedef struct {
   int precision;        /* qed_precision */
   int freeze_on_drop;   /* 1: an instance that dropped children is frozen from the next step */
   int tile;             /* work split: each wavefront takes chunks of `tile` consecutive
-                           particles, dealt round-robin; 0 = one contiguous chunk per
-                           wavefront (N / wavefronts) */
+                           particles, dealt round-robin, so that at any moment the
+                           wavefronts stream through neighbouring memory; 0 = 128.  A tile of
+                           at least N / wavefronts gives one contiguous chunk per wavefront */
   int block;            /* threads per workgroup (64..256, multiple of 64); 0 = 256 */
   int grid_blocks;      /* persistent workgroups per kernel (<= 4096); 0 = resident
                            workgroups per CU times the CU count */

@@ -38,6 +38,10 @@ namespace qedk {
 
 constexpr int kWavesPerBlock = 4;  // launch bound 256 threads
 constexpr int kStageCap = 32;      // staged photon children per wavefront
+// Default work chunk: 128 particles dealt round-robin, so the wavefronts of the GPU read
+// neighbouring 512-byte pieces of every column at any moment (measured faster than one
+// contiguous range per wavefront, which scatters the reads over the whole store).
+constexpr long long kDefaultTile = 128;
 
 // ------------------------------------------------------------------------------------
 // prep / finalize
@@ -344,6 +348,13 @@ __device__ __forceinline__ void wave_append(const StepArgs& a, bool flag, int in
   }
 }
 
+// A wavefront-uniform 64-bit value moved to scalar registers (lane 0's copy).
+__device__ __forceinline__ long long wave_uniform(long long v) {
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(unsigned long long)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)((unsigned long long)v >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
 // Wavefront index within the launch (wavefront-uniform).
 __device__ __forceinline__ int wave_index() {
   return (int)blockIdx.x * (int)(blockDim.x >> 6) +
@@ -395,7 +406,7 @@ struct WaveRange {
     const long long wv = (long long)blockIdx.x * wpb +
                          __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     N = n;
-    T = tile > 0 ? tile : (n + W - 1) / W;
+    T = tile > 0 ? tile : kDefaultTile;
     if (T < 1) T = 1;
     chunk = wv - W;
     g = gend = 0;
@@ -434,7 +445,7 @@ struct WaveRange {
 __device__ __forceinline__ bool block_has_work(long long N, long long tile) {
   const long long wpb = blockDim.x >> 6;
   const long long W = (long long)gridDim.x * wpb;
-  long long T = tile > 0 ? tile : (N + W - 1) / W;
+  long long T = tile > 0 ? tile : kDefaultTile;
   if (T < 1) T = 1;
   return (long long)blockIdx.x * wpb * T < N;
 }
@@ -826,21 +837,14 @@ struct PhotonSetup {
   int nsub;
 };
 
-// Fields, chi_gamma, n_sub and the rate prefactors of one photon (identical in both kernels).
-template <bool MIXED, int FMODE>
-__device__ __forceinline__ PhotonSetup photon_setup(const StepArgs& a, const FieldArgs& fld,
-                                                    int inst, const V3& x, const V3& kv,
-                                                    double kabs, BlockStats* bs) {
+// chi_gamma, n_sub and the rate prefactors of one photon in the fields E, B (identical in
+// both photon kernels).  `bound` holds the per-octave pair-rate bounds (staged in LDS).
+template <bool MIXED>
+__device__ __forceinline__ PhotonSetup photon_setup(const StepArgs& a, const V3& E, const V3& B,
+                                                    const V3& kv, double kabs,
+                                                    const double* bound, BlockStats* bs) {
   PhotonSetup ps;
   const double inv_k = 1.0 / kabs;
-  V3 E, B{0.0, 0.0, 0.0};
-  if (FMODE == kFieldLocal) {
-    field_at_position(fld, a.inst[inst].amp, x, E, B);
-  } else {
-    const double* eb = a.eb + 6 * inst;
-    E = {eb[0], eb[1], eb[2]};
-    if (FMODE == kFieldEB) B = {eb[3], eb[4], eb[5]};
-  }
   // chi_gamma (Eqs. (31), (32))
   ps.chi = chi_of(kv, kabs, E, B, a.eps_r);
   ps.nsub = 1;
@@ -866,10 +870,24 @@ __device__ __forceinline__ PhotonSetup photon_setup(const StepArgs& a, const Fie
     frexp(ps.chi, &e2);  // chi < 2^e2
     const int oi = e2 + kBoundOffset;
     if (oi >= kBoundOctaves) ps.pbound = __builtin_inf();
-    else if (oi >= 0)
-      ps.pbound = ps.pref * (MIXED ? (double)a.tables->pair_bound32[oi] : a.tables->pair_bound64[oi]);
+    else if (oi >= 0) ps.pbound = ps.pref * bound[oi];
   }
   return ps;
+}
+
+// The per-octave pair-rate bounds into LDS (FP32 values widened in the mixed form).
+template <bool MIXED>
+__device__ __forceinline__ void stage_bounds(const StepArgs& a, double* sb) {
+  for (int i = threadIdx.x; i < kBoundOctaves; i += blockDim.x)
+    sb[i] = MIXED ? (double)a.tables->pair_bound32[i] : a.tables->pair_bound64[i];
+}
+
+// Space-independent fields of a (wavefront-uniform) instance.
+template <int FMODE>
+__device__ __forceinline__ void instance_fields(const StepArgs& a, int inst, V3& E, V3& B) {
+  const double* eb = a.eb + 6 * inst;
+  E = {eb[0], eb[1], eb[2]};
+  B = FMODE == kFieldEB ? V3{eb[3], eb[4], eb[5]} : V3{0.0, 0.0, 0.0};
 }
 
 // Below the bound?  (the mixed path compares in FP32, as its exact evaluation does)
@@ -902,13 +920,33 @@ __device__ __forceinline__ bool pair_decision(const StepArgs& a, const Series64&
   return r2 < P;
 }
 
+// Columns of up to 64 photon slots [base, end) for one wavefront (lane i takes base + i;
+// lanes past the end get a dead id).  `base` is wavefront-uniform, so every column is
+// addressed by one scalar base and a lane offset.
+struct PhotonIn {
+  uint64_t id;
+  V3 x, k;
+};
+__device__ __forceinline__ PhotonIn load_photons(const qed_soa& S, long long base, long long end,
+                                                 int lane) {
+  PhotonIn r{QED_ID_DEAD, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+  if (lane < end - base) {
+    r.id = S.id[base + lane];
+    r.x = {S.x[base + lane], S.y[base + lane], S.z[base + lane]};
+    r.k = {S.px[base + lane], S.py[base + lane], S.pz[base + lane]};
+  }
+  return r;
+}
+
 template <bool MIXED, int FMODE>
 __global__ void __launch_bounds__(256) photon_kernel(StepArgs a) {
   __shared__ BlockStats bs;
+  __shared__ double sbound[kBoundOctaves];
   WorkHdr* hdr = a.hdr;
   const long long N = hdr->pho_total;
   const int wid = wave_index();
   block_stats_init(bs);
+  stage_bounds<MIXED>(a, sbound);
   __syncthreads();
   if (!block_has_work(N, a.tile)) {
     if (lane_id() == 0) a.candn[wid] = 0u;
@@ -932,28 +970,45 @@ __global__ void __launch_bounds__(256) photon_kernel(StepArgs a) {
   WaveRange wr;
   wr.init(N, a.tile);
 
-  while (wr.next(a, a.pho_pref, a.n_inst, false, tc)) {
-    const int inst = tc.inst;
+  // Software pipeline: the next 64 photons' columns (in this piece or the next one) are
+  // requested before the current ones are processed, so each wavefront keeps a load batch
+  // in flight while it computes.
+  bool has = wr.next(a, a.pho_pref, a.n_inst, false, tc);
+  PhotonIn nxt{};
+  if (has) nxt = load_photons(S, wave_uniform(tc.cur), wave_uniform(tc.end), lane);
+  while (has) {
+    const int inst = __builtin_amdgcn_readfirstlane(tc.inst);
     const uint64_t seed = a.inst[inst].seed;
-    for (long long base = tc.cur; base < tc.end; base += 64) {
-      const long long s = base + lane;
+    V3 E{}, B{};
+    if (FMODE != kFieldLocal) instance_fields<FMODE>(a, inst, E, B);
+    const long long cur = wave_uniform(tc.cur), end = wave_uniform(tc.end);
+    const long long g0 = wave_uniform(tc.g);
+    TileCursor tn;
+    bool has_next = false;
+    for (long long base = cur; base < end; base += 64) {
+      const PhotonIn in = nxt;
+      if (base + 64 < end) {
+        nxt = load_photons(S, base + 64, end, lane);
+      } else {
+        has_next = wr.next(a, a.pho_pref, a.n_inst, false, tn);
+        if (has_next) nxt = load_photons(S, wave_uniform(tn.cur), wave_uniform(tn.end), lane);
+      }
+      double* X = S.x + base;
+      double* Y = S.y + base;
+      double* Z = S.z + base;
       bool cand = false;
       int kcand = 0;
-      V3 x{}, kv{};
-      uint64_t id = QED_ID_DEAD;
-      if (s < tc.end) {
-        // one round trip: id, position and momentum together
-        id = S.id[s];
-        x = {S.x[s], S.y[s], S.z[s]};
-        kv = {S.px[s], S.py[s], S.pz[s]};
-      }
+      const uint64_t id = in.id;
+      V3 x = in.x;
+      const V3 kv = in.k;
       const double kabs = sqrt(dot(kv, kv));
       const bool live = id != QED_ID_DEAD;
       const bool ok = live && kabs > 0.0 && isfinite(kabs);
       if (live && !ok) block_count(bs, kPfNonfinite);
       wc.adv0 += __popcll(wave_ballot(ok));
       if (ok) {
-        const PhotonSetup st = photon_setup<MIXED, FMODE>(a, fld, inst, x, kv, kabs, &bs);
+        if (FMODE == kFieldLocal) field_at_position(fld, a.inst[inst].amp, x, E, B);
+        const PhotonSetup st = photon_setup<MIXED>(a, E, B, kv, kabs, sbound, &bs);
         int k = 0;
         for (; k < st.nsub; ++k) {
           if (a.push_photons) x = {x.x + st.hk * kv.x, x.y + st.hk * kv.y, x.z + st.hk * kv.z};
@@ -969,9 +1024,9 @@ __global__ void __launch_bounds__(256) photon_kernel(StepArgs a) {
         if (!cand) {
           cnt.subs += st.nsub;
           if (a.push_photons) {
-            S.x[s] = x.x;
-            S.y[s] = x.y;
-            S.z[s] = x.z;
+            X[lane] = x.x;
+            Y[lane] = x.y;
+            Z[lane] = x.z;
           }
         } else {
           cnt.subs += kcand;  // the exact kernel counts the rest
@@ -982,7 +1037,7 @@ __global__ void __launch_bounds__(256) photon_kernel(StepArgs a) {
       if (cm) {
         const int nc = __popcll(cm);
         const unsigned long long e =
-            ((unsigned long long)(tc.g + (s - tc.cur)) << 16) | (unsigned long long)kcand;
+            ((unsigned long long)(g0 + (base - cur) + lane) << 16) | (unsigned long long)kcand;
         if (ncand + nc <= a.cand_per_wave) {
           if (cand) clist[ncand + __popcll(cm & below)] = e;
           ncand += nc;
@@ -995,6 +1050,8 @@ __global__ void __launch_bounds__(256) photon_kernel(StepArgs a) {
         }
       }
     }
+    tc = tn;
+    has = has_next;
   }
   if (lane == 0) a.candn[wid] = (unsigned)ncand;
   wave_to_block(bs, cnt, wc);
@@ -1012,6 +1069,7 @@ struct ExactCtx {
   int staged;
   long long nrec;   // records in this wavefront's pair-arena share
   ArenaTally tally;
+  const double* bound;  // per-octave pair-rate bounds (LDS)
 };
 
 // Exact pair decision for the candidates list[i0 + lane] (i0 + lane < n); all lanes call.
@@ -1046,7 +1104,10 @@ __device__ __forceinline__ void exact_batch(const StepArgs& a, ExactCtx& c, Pair
     kv = {S.px[s], S.py[s], S.pz[s]};
     const double kabs = sqrt(dot(kv, kv));
     const uint64_t seed = a.inst[inst].seed;
-    const PhotonSetup st = photon_setup<MIXED, FMODE>(a, c.fld, inst, x, kv, kabs, nullptr);
+    V3 E, B;
+    if (FMODE == kFieldLocal) field_at_position(c.fld, a.inst[inst].amp, x, E, B);
+    else instance_fields<FMODE>(a, inst, E, B);
+    const PhotonSetup st = photon_setup<MIXED>(a, E, B, kv, kabs, c.bound, nullptr);
     int done = st.nsub;
     for (int k = 0; k < st.nsub; ++k) {
       if (a.push_photons) x = {x.x + st.hk * kv.x, x.y + st.hk * kv.y, x.z + st.hk * kv.z};
@@ -1122,10 +1183,13 @@ template <bool MIXED, int FMODE>
 __global__ void __launch_bounds__(256) photon_exact_kernel(StepArgs a) {
   __shared__ BlockStats bs;
   __shared__ PairStage pstage[kWavesPerBlock];
+  __shared__ double sbound[kBoundOctaves];
   WorkHdr* hdr = a.hdr;
   block_stats_init(bs);
+  stage_bounds<MIXED>(a, sbound);
   __syncthreads();
   ExactCtx c;
+  c.bound = sbound;
   c.ser64 = {a.tables->series[0], a.tables->series[1], a.tables->series[2], a.tables->series[3],
              a.tables->series[4]};
   c.ser32 = {(float)c.ser64.b0, (float)c.ser64.b1, (float)c.ser64.c0, (float)c.ser64.c1,
