@@ -311,3 +311,131 @@ def test_fill_standing_wave_matches_numpy():
     want = W.standing_wave_grid_values(w.field, t)
     for g, v in zip(grid.g, want):
         np.testing.assert_allclose(g.cpu().numpy(), v, rtol=2e-7, atol=1e-3)
+
+
+# ---------------------------------------------------------------------------------------
+# Full size: the rotating-field cascade of the benchmark (10^5 seeds, 10^8 slots per store,
+# the benchmark's launch configuration) advanced to step 400 on the GPU; then one more step,
+# checked on a random sample of particles that the oracle steps one by one.  Particles are
+# independent given the fields, and every draw and child id is keyed by the particle, so
+# the sample's next state and its children do not depend on the rest of the store.
+def _gather(e, sp, idx):
+    t = torch.as_tensor(idx, dtype=torch.int64, device=e.device)
+    d = e.cols[sp]
+    out = {c: d[c][t].cpu().numpy() for c in ("x", "y", "z", "px", "py", "pz", "w")}
+    out["id"] = d["id"][t].cpu().numpy().view(np.uint64)
+    out["parent"] = d["parent"][t].cpu().numpy().view(np.uint64)
+    out["birth"] = d["birth"][t].cpu().numpy().view(np.uint32)
+    out["n_events"] = d["n_events"][t].cpu().numpy().view(np.uint32)
+    return out
+
+
+def test_full_size_sampled_parity(orc):
+    w = W.rotating_e(n=100_000, a0=1000.0, periods=3.0, capacity=100_000_000)
+    init = W.rotating_e_initial(100_000, seed=0)
+    _note("full size: 400 steps of the benchmark cascade")
+    e = R.engine_single(w, init)
+    field, params = R.field_of(w), R.params_of(w, freeze_on_drop=1)
+    n = 400
+    st = R.run(e, field, params, n)
+    assert sum(s["dropped"] for s in st) == 0
+    c0 = e.counts()[0]
+    assert c0[0] > 1_000_000 and c0[2] > 10_000_000
+    rng = np.random.default_rng(2024)
+    sample = {}
+    for sp, k in ((0, 3000), (1, 3000), (2, 30000)):
+        idx = np.sort(rng.choice(int(c0[sp]), size=k, replace=False))
+        cols = _gather(e, sp, idx)
+        if sp == 2:
+            live = cols["id"] != W.NO_PARENT
+            idx = idx[live]
+            cols = {c: v[live] for c, v in cols.items()}
+        sample[sp] = (idx, cols)
+    _note("full size: step 400 and the sample's oracle step")
+    e.step(field, params)
+    torch.cuda.synchronize()
+    c1 = e.counts()[0]
+    os_ = [orc.Store(200_000), orc.Store(200_000), orc.Store(400_000, with_events=False)]
+    for sp in range(3):
+        cols = dict(sample[sp][1])
+        if sp == 2:
+            cols.pop("n_events")
+        os_[sp].load(cols)
+    p = oracle_params(orc, w)
+    p.step = n
+    orc.step(os_, oracle_field(orc, w), p)
+    for sp in range(3):
+        idx, before = sample[sp]
+        m = len(idx)
+        got = _gather(e, sp, idx)
+        want = os_[sp].view()
+        want = {c: (v[:m] if v is not None else None) for c, v in want.items()}
+        if sp == 2:
+            got.pop("n_events")
+            want.pop("n_events", None)
+            assert np.array_equal(got["id"], want["id"]), "photons removed by pairs differ"
+        compare_species(got, want, sp, label=f"sampled species {sp}")
+    # children of the sampled particles, created during step 400
+    parents = {0: set(), 2: set()}
+    parents[0] = set(sample[0][1]["id"].tolist()) | set(sample[1][1]["id"].tolist())
+    parents[2] = set(sample[2][1]["id"].tolist())
+    for sp in range(3):
+        lo, hi = int(c0[sp]), int(c1[sp])
+        region = _gather(e, sp, np.arange(lo, hi))
+        keep = np.isin(region["parent"], np.array(sorted(parents[0 if sp == 2 else 2]),
+                                                   dtype=np.uint64))
+        got = {c: v[keep] for c, v in region.items()}
+        m = len(sample[sp][0])
+        wv = os_[sp].view()
+        want = {c: (v[m:] if v is not None else None) for c, v in wv.items()}
+        if sp == 2:
+            got.pop("n_events")
+            want.pop("n_events", None)
+        assert len(got["id"]) == len(want["id"]), f"children of species {sp}"
+        compare_species(got, want, sp, label=f"children species {sp}")
+    assert len(os_[2].view()["id"]) > len(sample[2][0])  # the sample did emit
+
+
+def _spectrum(cols, lo=W.SPECTRUM_LO, hi=W.SPECTRUM_HI, bins=W.SPECTRUM_BINS):
+    live = cols["id"] != W.NO_PARENT
+    e = np.sqrt(cols["px"][live] ** 2 + cols["py"][live] ** 2 + cols["pz"][live] ** 2)
+    u = (np.log10(e) - math.log10(lo)) * bins / (math.log10(hi) - math.log10(lo))
+    ok = (u >= 0) & (u < bins)
+    return np.bincount(u[ok].astype(np.int64), weights=cols["w"][live][ok], minlength=bins)
+
+
+def test_mixed_precision_spectrum_and_pair_yield(orc):
+    """Mixed precision (FP32 tables and sampling, FP64 chi and push) against the FP64
+    oracle on the rotating-field cascade from 10^3 seeds over two periods: photon spectrum
+    (130 log bins of eps in [1e-8, 1e5]) within L1 1e-3 and pair yield within 1%.  The FP64
+    GPU run gives the oracle's spectrum and pair count, and qed_photon_spectrum agrees with
+    the histogram of the stores read back."""
+    w = W.rotating_e(n=1000, periods=2.0, capacity=4_000_000, lepton_capacity=400_000)
+    init = W.rotating_e_initial(1000, seed=21)
+    os_ = oracle_stores(orc, init, w.capacity)
+    ost = orc.run(os_, oracle_field(orc, w), oracle_params(orc, w), w.n_steps)
+    assert sum(s["dropped"] for s in ost) == 0
+    h_or = _spectrum(os_[2].view())
+    p_or = sum(s["pairs"] for s in ost)
+    assert p_or > 1000
+    for prec in ("f64", "mixed"):
+        _note(f"precision {prec}")
+        wp = W.rotating_e(n=1000, periods=2.0, capacity=4_000_000, lepton_capacity=400_000,
+                          precision=prec)
+        e = R.engine_single(wp, init)
+        st = R.run(e, R.field_of(wp), R.params_of(wp), wp.n_steps)
+        cols = e.read(0, 2)
+        h = _spectrum(cols)
+        d = torch.zeros(W.SPECTRUM_BINS, dtype=torch.float64, device="cuda")
+        Q.qed_photon_spectrum(e.stores, W.SPECTRUM_LO, W.SPECTRUM_HI, W.SPECTRUM_BINS,
+                              d.data_ptr(), e.stream)
+        torch.cuda.synchronize()
+        assert np.allclose(d.cpu().numpy(), h, rtol=1e-12, atol=0)
+        l1 = float(np.abs(h - h_or).sum() / h_or.sum())
+        pairs = sum(s["pairs"] for s in st)
+        _note(f"{prec}: L1 {l1:.3e}, pairs {pairs} vs {p_or}")
+        if prec == "f64":
+            assert l1 <= 1e-9 and pairs == p_or
+        else:
+            assert l1 <= 1e-3
+            assert abs(pairs - p_or) <= 0.01 * p_or
