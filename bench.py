@@ -9,10 +9,17 @@ emission and pair decisions, append) over every live particle.  The cascade grow
 store is full; from then on the instance is frozen (its steps do nothing) and the run's
 particle-step count stops growing.
 
+Each GPU job runs three times from the same seeds: an untimed tuning run that picks the
+launch shape (work-chunk size, persistent grid) per size class of the live count, the
+timed run (one captured step graph per chosen shape, replayed step by step), and an eager
+run with HIP events around the lepton and photon kernels.
+
 Prints one JSON line: particle-steps/s over the timed steps, the roofline of the dominant
 kernel (algorithmic bytes / its event-timed duration vs 8 TB/s), the same run in mixed
-precision with its photon-spectrum L1 distance and pair yield against the FP64 run, and
-the FP64 CPU oracle's rate on a bounded sample of the same workload on this host.
+precision with its photon-spectrum L1 distance and pair yield against the FP64 run, the
+batched ensemble (64 rotating-field cascades, a0 log-spaced over 500-3000, 10^3-10^5 seeds
+each, 2 periods, 2*10^8 slots split evenly) in mixed precision and in FP64, and the FP64
+CPU oracle's rate on a bounded sample of the rotating-field workload on this host.
 
 HBM traffic of the dominant kernel comes from the rocprofv3 counter summary committed
 under profiles/ (FETCH_SIZE and WRITE_SIZE scaled by the same counters' reading for a copy
@@ -78,20 +85,43 @@ def _stats_records(raw, K):
     return [Q.qed_stats.from_buffer_copy(raw[i * n:(i + 1) * n]) for i in range(K)]
 
 
-def gpu_run(args, precision):
-    """The cascade twice from the same seeds: K graph-replayed steps timed as a whole
-    (value), then K eager steps with HIP events around the lepton and photon kernels
-    (per-kernel durations for the roofline).  Both runs are the same computation."""
+def make_job(kind, args, precision):
+    """The workload, its engine (inputs loaded) and a function that reloads the seeds."""
+    from paper_1412_6426_amd import runner as R
+    from paper_1412_6426_amd import workloads as W
+    if kind == "rotating":
+        w = W.rotating_e(n=args.seeds, a0=args.a0, periods=3.0, capacity=args.capacity,
+                         precision=precision)
+        inits = [W.rotating_e_initial(args.seeds, seed=0)]
+        e = R.engine_single(w, inits[0])
+    else:
+        w = W.batched_rotating(precision=precision)
+        inits = W.batched_initial(w)
+        e = R.engine_batched(w, inits)
+
+    def reload():
+        e.reset_instances()
+        for i, init in enumerate(inits):
+            for s in range(3):
+                e.load(i, s, init[s])
+        e.set_step(0)
+    return w, e, reload
+
+
+def gpu_run(args, precision, kind="rotating"):
+    """One job three times from the same seeds: a tuning run that picks the launch shape
+    per size class (untimed), K steps replayed from one captured graph per chosen shape
+    and timed as a whole (value), and K eager steps with HIP events around the lepton and
+    photon kernels (per-kernel durations for the roofline).  The three runs compute the
+    same thing."""
     import numpy as np
     import torch
+    from paper_1412_6426_amd import autotune as AT
     from paper_1412_6426_amd import qed as Q
     from paper_1412_6426_amd import runner as R
     from paper_1412_6426_amd import workloads as W
 
-    w = W.rotating_e(n=args.seeds, a0=args.a0, periods=3.0, capacity=args.capacity,
-                     precision=precision)
-    init = W.rotating_e_initial(args.seeds, seed=0)
-    e = R.engine_single(w, init)
+    w, e, reload = make_job(kind, args, precision)
     field = R.field_of(w)
     params = R.params_of(w, freeze_on_drop=1, tile=args.tile, grid_blocks=args.grid_blocks)
     K = args.steps if args.steps is not None else w.n_steps
@@ -102,10 +132,7 @@ def gpu_run(args, precision):
 
     def restart():
         torch.cuda.synchronize()
-        e.reset_instances()
-        for s in range(3):
-            e.load(0, s, init[s])
-        e.set_step(0)
+        reload()
         cnt.zero_()
         torch.cuda.synchronize()
 
@@ -113,27 +140,40 @@ def gpu_run(args, precision):
     with torch.cuda.stream(stream):
         for _ in range(args.warmup):
             e.step(field, params, stream=sp)
-    restart()
+    # ---- tuning run: launch shape per size class ----
+    if args.no_tune:
+        sched = AT.Schedule(steps=[0], shapes=[(args.tile, args.grid_blocks)])
+    else:
+        restart()
+        cus = torch.cuda.get_device_properties(0).multi_processor_count
+        with torch.cuda.stream(stream):
+            sched = AT.tune_run(e, field, params, K, AT.default_candidates(cus))
+    shape_of = [sched.shape_at(n) for n in range(K)]
 
-    # ---- timed: one step (and its stats record) captured once, replayed K times ----
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph, stream=stream):
-        e.step(field, params, stream=sp)
-        Q.qed_append_stats(e.stats_buf.data_ptr(), log.data_ptr(), K, cnt.data_ptr(), sp)
+    # ---- timed: one captured step (and its stats record) per shape, replayed K times ----
+    graphs = {}
+    for shape in sched.distinct():
+        params.tile, params.grid_blocks = shape
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            e.step(field, params, stream=sp)
+            Q.qed_append_stats(e.stats_buf.data_ptr(), log.data_ptr(), K, cnt.data_ptr(), sp)
+        graphs[shape] = g
+    plan = [graphs[s] for s in shape_of]
     restart()
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     wall0 = time.perf_counter()
     with torch.cuda.stream(stream):  # replay() launches on the current stream
         t_start.record(stream)
-        for _ in range(K):
-            graph.replay()
+        for g in plan:
+            g.replay()
         t_end.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     ms = t_start.elapsed_time(t_end)
     recs = _stats_records(log.cpu().numpy().tobytes(), K)
-    counts = e.counts()[0].tolist()
+    counts = e.counts().tolist()
     hist = None
     if args.spectrum:
         hist = torch.zeros(W.SPECTRUM_BINS, dtype=torch.float64, device=e.device)
@@ -141,7 +181,7 @@ def gpu_run(args, precision):
                               hist.data_ptr(), sp)
         torch.cuda.synchronize()
         hist = hist.cpu().numpy()
-    del graph
+    del plan, graphs
 
     # ---- per-kernel durations: the same K steps eagerly, HIP events on our stream ----
     restart()
@@ -149,6 +189,7 @@ def gpu_run(args, precision):
     evs = hip.create(4 * K)
     with torch.cuda.stream(stream):
         for n in range(K):
+            params.tile, params.grid_blocks = shape_of[n]
             for j in range(4):
                 params.events[j] = evs[4 * n + j]
             e.step(field, params, stream=sp)
@@ -170,16 +211,21 @@ def gpu_run(args, precision):
     active = sum(1 for r in recs if sum(r.advanced) > 0)
     first_drop = next((r.step for r in recs if r.dropped > 0), None)
     out = dict(
-        ms=ms, wall_s=wall, steps=K, active_steps=active, first_drop_step=first_drop,
+        workload=w.description, ms=ms, wall_s=wall, steps=K, active_steps=active,
+        first_drop_step=first_drop,
         particle_steps=int(sum(adv)), advanced=[int(a) for a in adv], emitted=int(emitted),
         pairs=int(pairs), lep_ms=sum(lep_t), pho_ms=sum(pho_t), lep_bytes=lep_bytes,
-        pho_bytes=pho_bytes, final_counts=counts, eager_matches_graph=bool(same),
+        pho_bytes=pho_bytes, final_counts=[int(sum(c[s] for c in counts)) for s in range(3)],
+        eager_matches_graph=bool(same),
+        schedule=[dict(from_step=k, tile=t, grid_blocks=g)
+                  for k, (t, g) in zip(sched.steps, sched.shapes)],
         substeps=int(sum(r.substeps for r in recs)),
         low_occupancy_iters=int(sum(r.low_occupancy_iters for r in recs)),
         wave_iters=int(sum(r.wave_iters for r in recs)),
         near_threshold=int(sum(r.near_threshold for r in recs)),
         saturated=int(sum(r.saturated for r in recs)),
         early_out=int(sum(r.early_out for r in recs)),
+        dropped=int(sum(r.dropped for r in recs)),
         # per step, for the precision comparison
         step_pairs=[int(r.pairs) for r in recs], step_emitted=[int(r.emitted) for r in recs],
         step_hist=np.array([list(r.photon_hist) for r in recs], dtype=np.float64),
@@ -188,6 +234,14 @@ def gpu_run(args, precision):
     del e
     torch.cuda.empty_cache()
     return out
+
+
+def roofline_of(r):
+    dom = "photon" if r["pho_ms"] >= r["lep_ms"] else "lepton"
+    kbytes = r["pho_bytes"] if dom == "photon" else r["lep_bytes"]
+    kms = r["pho_ms"] if dom == "photon" else r["lep_ms"]
+    achieved = kbytes / (kms / 1e3) / 1e9 if kms > 0 else 0.0
+    return dom, kbytes, kms, achieved
 
 
 def precision_compare(r64, rmx):
@@ -282,6 +336,10 @@ def main():
                     help="skip the mixed-precision run and its accuracy comparison")
     ap.add_argument("--spectrum", action="store_true",
                     help="also histogram the final photon stores")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-ensemble runs (64 cascades, mixed and FP64)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="use --tile / --grid-blocks for every step instead of tuning")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -299,11 +357,8 @@ def main():
           flush=True)
     secs = r["ms"] / 1e3
     value = r["particle_steps"] / secs
-    dom = "photon" if r["pho_ms"] >= r["lep_ms"] else "lepton"
-    kbytes = r["pho_bytes"] if dom == "photon" else r["lep_bytes"]
-    kms = r["pho_ms"] if dom == "photon" else r["lep_ms"]
+    dom, kbytes, kms, achieved = roofline_of(r)
     launches = r["steps"]
-    achieved = kbytes / (kms / 1e3) / 1e9 if kms > 0 else 0.0
     # the rotating-field specialisation of the kernel, FP64 or mixed
     traffic = measured_traffic(f"{dom}_kernel<{'true' if args.precision == 'mixed' else 'false'}, 1>")
     line = {
@@ -341,7 +396,7 @@ def main():
                                      "advanced", "emitted", "pairs", "final_counts",
                                      "lep_ms", "pho_ms", "substeps", "wave_iters",
                                      "low_occupancy_iters", "near_threshold", "saturated",
-                                     "early_out", "eager_matches_graph")},
+                                     "early_out", "eager_matches_graph", "schedule")},
     }
     if not args.no_mixed:
         other = "mixed" if args.precision == "f64" else "f64"
@@ -354,6 +409,23 @@ def main():
             value_f64=v64, value_mixed=vmx, speedup_mixed=vmx / v64,
             lep_ms_mixed=rmx["lep_ms"], pho_ms_mixed=rmx["pho_ms"],
             **precision_compare(r64, rmx))
+    if not args.no_batched:
+        # batched ensemble: 64 independent cascades in one step, mixed and FP64
+        b = {}
+        for prec in ("mixed", "f64"):
+            print(f"bench: batched ensemble, {prec}", file=sys.stderr, flush=True)
+            rb = gpu_run(args, prec, kind="batched")
+            bdom, bbytes, bms, bach = roofline_of(rb)
+            b[prec] = dict(
+                value=rb["particle_steps"] / (rb["ms"] / 1e3), ms=rb["ms"],
+                particle_steps=rb["particle_steps"], pairs=rb["pairs"], emitted=rb["emitted"],
+                dropped=rb["dropped"], lep_ms=rb["lep_ms"], pho_ms=rb["pho_ms"],
+                roofline={"kernel": f"{bdom}_kernel", "achieved": bach, "peak": HBM_PEAK_GBS,
+                          "unit": "GB/s", "frac": bach / HBM_PEAK_GBS},
+                schedule=rb["schedule"], eager_matches_graph=rb["eager_matches_graph"])
+        line["batched"] = dict(
+            workload=rb["workload"],
+            speedup_mixed_vs_f64=b["mixed"]["value"] / b["f64"]["value"], **b)
     if not args.no_cpu_baseline:
         print("bench: oracle sample on the host", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(args)
