@@ -18,8 +18,9 @@ Prints one JSON line: particle-steps/s over the timed steps, the roofline of the
 kernel (algorithmic bytes / its event-timed duration vs 8 TB/s), the same run in mixed
 precision with its photon-spectrum L1 distance and pair yield against the FP64 run, the
 batched ensemble (64 rotating-field cascades, a0 log-spaced over 500-3000, 10^3-10^5 seeds
-each, 2 periods, 2*10^8 slots split evenly) in mixed precision and in FP64, and the FP64
-CPU oracle's rate on a bounded sample of the rotating-field workload on this host.
+each, 2 periods, 2*10^8 slots split evenly) in mixed precision and in FP64, the
+standing-wave cascade on a 256^3 Yee grid (field fill timed apart), and the FP64 CPU
+oracle's rate on a bounded sample of the rotating-field workload on this host.
 
 HBM traffic of the dominant kernel comes from the rocprofv3 counter summary committed
 under profiles/ (FETCH_SIZE and WRITE_SIZE scaled by the same counters' reading for a copy
@@ -58,6 +59,7 @@ class HipEvents:
         self.lib.hipEventCreate.argtypes = [C.POINTER(C.c_void_p)]
         self.lib.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
         self.lib.hipEventDestroy.argtypes = [C.c_void_p]
+        self.lib.hipEventRecord.argtypes = [C.c_void_p, C.c_void_p]
 
     def create(self, n):
         out = []
@@ -236,6 +238,75 @@ def gpu_run(args, precision, kind="rotating"):
     return out
 
 
+def gpu_run_yee(args, precision):
+    """Standing-wave cascade on a 256^3 Yee grid (two counter-propagating CP waves, a0 =
+    2000 each, cells of lambda/32, 10^6 seeds Gaussian sigma = 0.1 lambda about the node,
+    dt = T/100, 2*10^8 photon slots).  The grid is refilled with the analytic wave before
+    every step (a stand-in for the field solver, timed separately); steps run eagerly with
+    HIP events around the fill, the whole step, and the lepton and photon kernels."""
+    import torch
+    from paper_1412_6426_amd import qed as Q
+    from paper_1412_6426_amd import runner as R
+    from paper_1412_6426_amd import workloads as W
+
+    w = W.standing_wave_grid(precision=precision)
+    init = W.standing_wave_initial(w.n_seed, seed=0)
+    e = R.engine_single(w, init)
+    grid = R.YeeGrid(w)
+    field = R.field_of(w, grid=grid.g)
+    params = R.params_of(w, freeze_on_drop=1, tile=args.tile, grid_blocks=args.grid_blocks)
+    K = w.n_steps
+    stream = torch.cuda.Stream()
+    sp = stream.cuda_stream
+    log = torch.zeros(K * e.stats_buf.numel(), dtype=torch.uint8, device=e.device)
+    cnt = torch.zeros(1, dtype=torch.int64, device=e.device)
+    hip = HipEvents()
+    evs = hip.create(7 * K)
+    torch.cuda.synchronize()
+    e.set_step(0)
+    with torch.cuda.stream(stream):
+        for n in range(K):
+            ev = evs[7 * n:7 * n + 7]
+            hip.lib.hipEventRecord(C.c_void_p(ev[0]), C.c_void_p(sp))
+            grid.fill(w.t0 + n * w.dt, sp)
+            hip.lib.hipEventRecord(C.c_void_p(ev[1]), C.c_void_p(sp))
+            for j in range(4):
+                params.events[j] = ev[2 + j]
+            e.step(field, params, stream=sp)
+            hip.lib.hipEventRecord(C.c_void_p(ev[6]), C.c_void_p(sp))
+            Q.qed_append_stats(e.stats_buf.data_ptr(), log.data_ptr(), K, cnt.data_ptr(), sp)
+    torch.cuda.synchronize()
+    fill_ms = sum(hip.elapsed_ms(evs[7 * n], evs[7 * n + 1]) for n in range(K))
+    step_ms = sum(hip.elapsed_ms(evs[7 * n + 1], evs[7 * n + 6]) for n in range(K))
+    lep_ms = sum(hip.elapsed_ms(evs[7 * n + 2], evs[7 * n + 3]) for n in range(K))
+    pho_ms = sum(hip.elapsed_ms(evs[7 * n + 4], evs[7 * n + 5]) for n in range(K))
+    hip.destroy(evs)
+    recs = _stats_records(log.cpu().numpy().tobytes(), K)
+    adv = [sum(r.advanced[s] for r in recs) for s in range(3)]
+    emitted = sum(r.emitted for r in recs)
+    dead_slots = sum(r.n_start[2] - r.advanced[2] for r in recs)
+    out = dict(
+        workload=w.description, precision=precision, steps=K,
+        first_drop_step=next((r.step for r in recs if r.dropped > 0), None),
+        particle_steps=int(sum(adv)), advanced=[int(a) for a in adv], emitted=int(emitted),
+        pairs=int(sum(r.pairs for r in recs)), step_ms=step_ms, fill_ms=fill_ms,
+        lep_ms=lep_ms, pho_ms=pho_ms,
+        value=sum(adv) / (step_ms / 1e3),
+        substeps=int(sum(r.substeps for r in recs)),
+        nsub_max=max((k for r in recs for k in range(len(r.nsub_hist)) if r.nsub_hist[k]),
+                     default=0),
+        saturated=int(sum(r.saturated for r in recs)),
+        near_threshold=int(sum(r.near_threshold for r in recs)),
+        lepton_roofline_gbs=(LEPTON_STEP_BYTES * (adv[0] + adv[1]) + EMISSION_BYTES * emitted)
+        / (lep_ms / 1e3) / 1e9 if lep_ms > 0 else 0.0,
+        photon_roofline_gbs=(PHOTON_STEP_BYTES * adv[2] + DEAD_SLOT_BYTES * dead_slots)
+        / (pho_ms / 1e3) / 1e9 if pho_ms > 0 else 0.0,
+    )
+    del e, grid
+    torch.cuda.empty_cache()
+    return out
+
+
 def roofline_of(r):
     dom = "photon" if r["pho_ms"] >= r["lep_ms"] else "lepton"
     kbytes = r["pho_bytes"] if dom == "photon" else r["lep_bytes"]
@@ -338,6 +409,8 @@ def main():
                     help="also histogram the final photon stores")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-ensemble runs (64 cascades, mixed and FP64)")
+    ap.add_argument("--no-yee", action="store_true",
+                    help="skip the standing-wave cascade on the 256^3 Yee grid")
     ap.add_argument("--no-tune", action="store_true",
                     help="use --tile / --grid-blocks for every step instead of tuning")
     args = ap.parse_args()
@@ -426,6 +499,9 @@ def main():
         line["batched"] = dict(
             workload=rb["workload"],
             speedup_mixed_vs_f64=b["mixed"]["value"] / b["f64"]["value"], **b)
+    if not args.no_yee:
+        print("bench: standing-wave cascade on the Yee grid", file=sys.stderr, flush=True)
+        line["standing_wave_grid"] = gpu_run_yee(args, args.precision)
     if not args.no_cpu_baseline:
         print("bench: oracle sample on the host", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(args)

@@ -158,6 +158,8 @@ qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_fi
         a.field.inv_dx[d] = 1.0 / field->dx[d];
         a.field.origin[d] = field->origin[d];
       }
+      // node offsets are 32-bit: fewer than 2^31 values per component
+      if ((long long)field->n[0] * field->n[1] * field->n[2] > 2147483647ll) return QED_ERR_ARG;
       for (int c = 0; c < 6; ++c) a.field.grid[c] = field->grid[c];
       break;
     default:

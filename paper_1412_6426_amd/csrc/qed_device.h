@@ -276,27 +276,49 @@ __device__ __forceinline__ NsubInfo nsub_from_ratio(double r) {
   return o;
 }
 
-// ------------------------------------------------------------------------------------
-// Fields.
-// ------------------------------------------------------------------------------------
-// CIC (trilinear) gather of one Yee component from a periodic grid.
-__device__ __forceinline__ double cic_component(const float* __restrict__ g, int nx, int ny,
-                                                int nz, double sx, double sy, double sz) {
-  const double fx0 = floor(sx), fy0 = floor(sy), fz0 = floor(sz);
-  const double fx = sx - fx0, fy = sy - fy0, fz = sz - fz0;
-  long ix = (long)fx0 % nx, iy = (long)fy0 % ny, iz = (long)fz0 % nz;
-  if (ix < 0) ix += nx;
-  if (iy < 0) iy += ny;
-  if (iz < 0) iz += nz;
-  const long ix1 = ix + 1 == nx ? 0 : ix + 1;
-  const long iy1 = iy + 1 == ny ? 0 : iy + 1;
-  const long iz1 = iz + 1 == nz ? 0 : iz + 1;
-  const long r00 = (iz * ny + iy) * nx, r01 = (iz * ny + iy1) * nx;
-  const long r10 = (iz1 * ny + iy) * nx, r11 = (iz1 * ny + iy1) * nx;
-  const double v000 = g[r00 + ix], v100 = g[r00 + ix1];
-  const double v010 = g[r01 + ix], v110 = g[r01 + ix1];
-  const double v001 = g[r10 + ix], v101 = g[r10 + ix1];
-  const double v011 = g[r11 + ix], v111 = g[r11 + ix1];
+// Cell-in-cell (trilinear) interpolation on a periodic grid.  Per axis, one coordinate s
+// in cell units gives the lower node i0 = floor(s) (wrapped into [0, n)), the upper node
+// i1 and the fraction s - floor(s).  Each Yee component sits at node or half-node offsets
+// per axis, so six such axes (node and half-node for x, y, z) serve all six components.
+struct CicAxis {
+  int i0, i1;
+  double f;
+};
+
+__device__ __forceinline__ CicAxis cic_axis(double s, int n) {
+  const double fl = floor(s);
+  CicAxis a;
+  a.f = s - fl;
+  int i;
+  if (fabs(fl) < 1073741824.0) {
+    i = (int)fl;
+    if ((unsigned)i >= (unsigned)n) {  // outside the primary box: wrap
+      i %= n;
+      if (i < 0) i += n;
+    }
+  } else {
+    long long l = (long long)fl % n;
+    if (l < 0) l += n;
+    i = (int)l;
+  }
+  a.i0 = i;
+  a.i1 = i + 1 == n ? 0 : i + 1;
+  return a;
+}
+
+// One component: 8 grid values around the point, interpolated along x, then y, then z.
+// nxy = nx * ny; the grid holds fewer than 2^31 values.
+__device__ __forceinline__ double cic_component(const float* __restrict__ g, const CicAxis& ax,
+                                                const CicAxis& ay, const CicAxis& az, int nx,
+                                                int nxy) {
+  const int z0 = az.i0 * nxy, z1 = az.i1 * nxy;
+  const int y0 = ay.i0 * nx, y1 = ay.i1 * nx;
+  const int r00 = z0 + y0, r01 = z0 + y1, r10 = z1 + y0, r11 = z1 + y1;
+  const double v000 = g[r00 + ax.i0], v100 = g[r00 + ax.i1];
+  const double v010 = g[r01 + ax.i0], v110 = g[r01 + ax.i1];
+  const double v001 = g[r10 + ax.i0], v101 = g[r10 + ax.i1];
+  const double v011 = g[r11 + ax.i0], v111 = g[r11 + ax.i1];
+  const double fx = ax.f, fy = ay.f, fz = az.f;
   const double c00 = v000 + fx * (v100 - v000);
   const double c10 = v010 + fx * (v110 - v010);
   const double c01 = v001 + fx * (v101 - v001);
@@ -327,17 +349,21 @@ __device__ __forceinline__ void field_at_position(const FieldArgs& f, double ins
     B = {0.0, a2 * skx * cph, a2 * skx * sph};
     return;
   }
-  // QED_FIELD_YEE
+  // QED_FIELD_YEE: Ex at (i+1/2, j, k), Ey (i, j+1/2, k), Ez (i, j, k+1/2),
+  // Bx (i, j+1/2, k+1/2), By (i+1/2, j, k+1/2), Bz (i+1/2, j+1/2, k)
   const double sx = (x.x - f.origin[0]) * f.inv_dx[0];
   const double sy = (x.y - f.origin[1]) * f.inv_dx[1];
   const double sz = (x.z - f.origin[2]) * f.inv_dx[2];
-  const int nx = f.n[0], ny = f.n[1], nz = f.n[2];
-  E.x = cic_component(f.grid[0], nx, ny, nz, sx - 0.5, sy, sz);
-  E.y = cic_component(f.grid[1], nx, ny, nz, sx, sy - 0.5, sz);
-  E.z = cic_component(f.grid[2], nx, ny, nz, sx, sy, sz - 0.5);
-  B.x = cic_component(f.grid[3], nx, ny, nz, sx, sy - 0.5, sz - 0.5);
-  B.y = cic_component(f.grid[4], nx, ny, nz, sx - 0.5, sy, sz - 0.5);
-  B.z = cic_component(f.grid[5], nx, ny, nz, sx - 0.5, sy - 0.5, sz);
+  const int nx = f.n[0], ny = f.n[1], nz = f.n[2], nxy = nx * ny;
+  const CicAxis x0 = cic_axis(sx, nx), xh = cic_axis(sx - 0.5, nx);
+  const CicAxis y0 = cic_axis(sy, ny), yh = cic_axis(sy - 0.5, ny);
+  const CicAxis z0 = cic_axis(sz, nz), zh = cic_axis(sz - 0.5, nz);
+  E.x = cic_component(f.grid[0], xh, y0, z0, nx, nxy);
+  E.y = cic_component(f.grid[1], x0, yh, z0, nx, nxy);
+  E.z = cic_component(f.grid[2], x0, y0, zh, nx, nxy);
+  B.x = cic_component(f.grid[3], x0, yh, zh, nx, nxy);
+  B.y = cic_component(f.grid[4], xh, y0, zh, nx, nxy);
+  B.z = cic_component(f.grid[5], xh, yh, z0, nx, nxy);
 }
 
 // ------------------------------------------------------------------------------------

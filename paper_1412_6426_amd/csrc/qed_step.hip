@@ -890,6 +890,14 @@ __device__ __forceinline__ void instance_fields(const StepArgs& a, int inst, V3&
   B = FMODE == kFieldEB ? V3{eb[3], eb[4], eb[5]} : V3{0.0, 0.0, 0.0};
 }
 
+// Can a draw fall below the bound at all?  The smallest uniform is 2^-53 in FP64 and 2^-24
+// in FP32, so a smaller bound settles the decision without drawing.
+template <bool MIXED>
+__device__ __forceinline__ bool bound_reachable(double pbound) {
+  if (MIXED) return (float)pbound > 0x1p-24f;
+  return pbound > 0x1p-53;
+}
+
 // Below the bound?  (the mixed path compares in FP32, as its exact evaluation does)
 template <bool MIXED>
 __device__ __forceinline__ bool below_bound(const uint4& o, double pbound) {
@@ -1013,6 +1021,10 @@ __global__ void __launch_bounds__(256) photon_kernel(StepArgs a) {
         for (; k < st.nsub; ++k) {
           if (a.push_photons) x = {x.x + st.hk * kv.x, x.y + st.hk * kv.y, x.z + st.hk * kv.z};
           if (!a.pairs) continue;
+          if (!bound_reachable<MIXED>(st.pbound)) {
+            ++cnt.early;
+            continue;
+          }
           const uint4 o = draw_words(id, seed, step, (uint32_t)k, kDraw);
           if (below_bound<MIXED>(o, st.pbound)) {
             cand = true;
