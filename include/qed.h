@@ -90,11 +90,12 @@ typedef enum {
  *    65536  double[4096][2]  (e^z B, e^z C)
  *   131072  float[4096][2]   FP32 copy of the first block
  *   163840  float[4096][2]   FP32 copy of the second block
- *   196608  double[128]      pair bound: sup over delta_e of the bracket of Eq. (30) for
- *                            chi_gamma < 2^(j-64), j = 0..127
- *   197632  float[128]       FP32 copy
- *   198144  double[8]        b0, b1, c0, c1, c2 (small-z series), 0, 0, 0
- *   198208  uint32           0x51454454 once built
+ *   196608  double[2048]     pair bound: sup over delta_e of the bracket of Eq. (30) for
+ *                            chi_gamma < (1/2 + (j+1)/32) 2^(e-64), entry 16 e + j,
+ *                            e = 0..127, j = 0..15
+ *   212992  float[2048]      FP32 copy
+ *   221184  double[8]        b0, b1, c0, c1, c2 (small-z series), 0, 0, 0
+ *   221248  uint32           0x51454454 once built
  * Size in bytes of the device buffer qed_build_tables fills: */
 size_t qed_table_bytes(void);
 

@@ -23,6 +23,8 @@ constexpr double kNodesPerLog2 = (kTableN - 1) / (kLog2ZHi - kLog2ZLo);
 constexpr uint32_t kTableMagic = 0x51454454u;
 constexpr int kBoundOctaves = 128;  // pair-rate bound for chi in [2^(e-1), 2^e), e = -64..63
 constexpr int kBoundOffset = 64;
+constexpr int kBoundSub = 16;       // equal sub-intervals of each octave
+constexpr int kBoundEntries = kBoundOctaves * kBoundSub;
 constexpr double kNearThreshold = 1e-12;
 
 // Layout of the tables buffer (see qed_build_tables).
@@ -31,8 +33,8 @@ struct alignas(256) DevTables {
   double2 bc64[kTableN];  // (e^z B(z), e^z C(z))
   float2 ab32[kTableN];
   float2 bc32[kTableN];
-  double pair_bound64[kBoundOctaves];  // sup over delta of the pair-rate bracket
-  float pair_bound32[kBoundOctaves];
+  double pair_bound64[kBoundEntries];  // sup over delta of the pair-rate bracket
+  float pair_bound32[kBoundEntries];
   double series[8];  // b0, b1, c0, c1, c2: small-z series of K_{2/3} and int K_{1/3}
   uint32_t magic;
   uint32_t reserved[63];

@@ -863,14 +863,19 @@ __device__ __forceinline__ PhotonSetup photon_setup(const StepArgs& a, const V3&
   const double h = ps.nsub == 1 ? a.dt : a.dt / (double)ps.nsub;
   ps.hk = h * inv_k;
   ps.pref = h * (a.dtfac_per_h * kInvSqrt3Pi) * inv_k;
-  // upper bound of the pair probability over delta_e for this chi octave
+  // upper bound of the pair probability over delta_e for this chi's sub-octave
   ps.pbound = 0.0;
   if (ps.chi > 0.0) {
     int e2;
-    frexp(ps.chi, &e2);  // chi < 2^e2
+    const double m = frexp(ps.chi, &e2);  // chi = m 2^e2, m in [1/2, 1)
     const int oi = e2 + kBoundOffset;
-    if (oi >= kBoundOctaves) ps.pbound = __builtin_inf();
-    else if (oi >= 0) ps.pbound = ps.pref * bound[oi];
+    if (oi >= kBoundOctaves) {
+      ps.pbound = __builtin_inf();
+    } else if (oi >= 0) {
+      int j = (int)((2.0 * m - 1.0) * kBoundSub);  // exact: chi < (1/2 + (j+1)/32) 2^e2
+      j = j < kBoundSub - 1 ? j : kBoundSub - 1;
+      ps.pbound = ps.pref * bound[oi * kBoundSub + j];
+    }
   }
   return ps;
 }
@@ -878,7 +883,7 @@ __device__ __forceinline__ PhotonSetup photon_setup(const StepArgs& a, const V3&
 // The per-octave pair-rate bounds into LDS (FP32 values widened in the mixed form).
 template <bool MIXED>
 __device__ __forceinline__ void stage_bounds(const StepArgs& a, double* sb) {
-  for (int i = threadIdx.x; i < kBoundOctaves; i += blockDim.x)
+  for (int i = threadIdx.x; i < kBoundEntries; i += blockDim.x)
     sb[i] = MIXED ? (double)a.tables->pair_bound32[i] : a.tables->pair_bound64[i];
 }
 
@@ -949,7 +954,7 @@ __device__ __forceinline__ PhotonIn load_photons(const qed_soa& S, long long bas
 template <bool MIXED, int FMODE>
 __global__ void __launch_bounds__(256) photon_kernel(StepArgs a) {
   __shared__ BlockStats bs;
-  __shared__ double sbound[kBoundOctaves];
+  __shared__ double sbound[kBoundEntries];
   WorkHdr* hdr = a.hdr;
   const long long N = hdr->pho_total;
   const int wid = wave_index();
@@ -1195,7 +1200,7 @@ template <bool MIXED, int FMODE>
 __global__ void __launch_bounds__(256) photon_exact_kernel(StepArgs a) {
   __shared__ BlockStats bs;
   __shared__ PairStage pstage[kWavesPerBlock];
-  __shared__ double sbound[kBoundOctaves];
+  __shared__ double sbound[kBoundEntries];
   WorkHdr* hdr = a.hdr;
   block_stats_init(bs);
   stage_bounds<MIXED>(a, sbound);

@@ -59,13 +59,15 @@ __global__ void __launch_bounds__(256) table_nodes_kernel(DevTables* t) {
   }
 }
 
-// FP32 copies, the per-octave pair-rate bound and the series constants.
+// FP32 copies, the pair-rate bounds and the series constants.
 // Bound: with z = 2/(3 chi d(1-d)) >= z_min = 8/(3 chi), the bracket of Eq. (30) is
 //   (d/(1-d) + (1-d)/d) B(z) + C(z) <= 1.5 chi z B(z) + C(z) <= 1.5 chi F2sup + C(z_min),
 // F2 = z K_{2/3}(z) rising to max 0.60705 at z = 0.416 then falling: F2sup = F2(z_min) when
-// z_min >= 0.45, else 0.61.  Both terms grow with chi, so the bound at the octave's top
-// chi = 2^e holds for the whole octave [2^(e-1), 2^e).  A 1.001 margin covers table
-// interpolation (~1e-6) and FP32 rounding.
+// z_min >= 0.45, else 0.61.  Both terms grow with chi, so the bound at an interval's top
+// chi holds for the whole interval.  Octave [2^(e-1), 2^e) is split into kBoundSub equal
+// intervals [(1/2 + j/32) 2^e, (1/2 + (j+1)/32) 2^e); for small chi the rate grows like
+// exp(-8/(3 chi)), so a whole octave's bound would overstate its lower part many times.
+// A 1.001 margin covers table interpolation (~1e-6) and FP32 rounding.
 __global__ void __launch_bounds__(256) table_finish_kernel(DevTables* t, Series64 s) {
   const int tid = (int)(blockIdx.x * blockDim.x + threadIdx.x);
   const int nthreads = (int)(gridDim.x * blockDim.x);
@@ -76,8 +78,9 @@ __global__ void __launch_bounds__(256) table_finish_kernel(DevTables* t, Series6
   const int wave = tid >> 6;
   const int lane = tid & 63;
   const int nwaves = nthreads >> 6;
-  for (int o = wave; o < kBoundOctaves; o += nwaves) {
-    const double chi_hi = ldexp(1.0, o - kBoundOffset);
+  for (int o = wave; o < kBoundEntries; o += nwaves) {
+    const int oct = o / kBoundSub, sub = o - oct * kBoundSub;
+    const double chi_hi = ldexp(0.5 + (double)(sub + 1) / (2.0 * kBoundSub), oct - kBoundOffset);
     const double zmin = 8.0 / (3.0 * chi_hi);
     double bound = 0.0;
     if (zmin < kZHi) {
@@ -109,7 +112,7 @@ __global__ void table_seal_kernel(DevTables* t) {
 hipError_t launch_build_tables(DevTables* t, const Series64& s, hipStream_t st) {
   const int waves = 3 * kTableN;
   hipLaunchKernelGGL(table_nodes_kernel, dim3((waves * 64 + 255) / 256), dim3(256), 0, st, t);
-  hipLaunchKernelGGL(table_finish_kernel, dim3(32), dim3(256), 0, st, t, s);
+  hipLaunchKernelGGL(table_finish_kernel, dim3(128), dim3(256), 0, st, t, s);
   hipLaunchKernelGGL(table_seal_kernel, dim3(1), dim3(64), 0, st, t);
   return hipGetLastError();
 }

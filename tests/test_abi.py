@@ -61,7 +61,7 @@ def test_ctypes_layout_matches_header(Q, tmp_path):
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
                                           check=True).stdout.split()]
     assert got == expect
-    assert Q.qed_table_bytes() == 198656
+    assert Q.qed_table_bytes() == 221696
 
 
 def test_host_side_queries(Q):

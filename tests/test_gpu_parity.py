@@ -40,9 +40,10 @@ def test_tables_match_oracle(orc):
     ab = raw[0:65536].view(np.float64).reshape(4096, 2)
     bc = raw[65536:131072].view(np.float64).reshape(4096, 2)
     ab32 = raw[131072:163840].view(np.float32).reshape(4096, 2)
-    bound = raw[196608:197632].view(np.float64)
-    series = raw[198144:198208].view(np.float64)
-    magic = raw[198208:198212].view(np.uint32)[0]
+    bound = raw[196608:212992].view(np.float64).reshape(128, 16)
+    bound32 = raw[212992:221184].view(np.float32).reshape(128, 16)
+    series = raw[221184:221248].view(np.float64)
+    magic = raw[221248:221252].view(np.uint32)[0]
     gA, gB, gC = orc.table_arrays()
     np.testing.assert_allclose(ab[:, 0], gA, rtol=1e-13, atol=0)
     np.testing.assert_allclose(ab[:, 1], gB, rtol=1e-13, atol=0)
@@ -52,12 +53,18 @@ def test_tables_match_oracle(orc):
     t = orc.tables()
     np.testing.assert_allclose(series[:5], [t.s_b0, t.s_b1, t.s_c0, t.s_c1, t.s_c2], rtol=1e-14)
     assert magic == 0x51454454
-    # the per-octave bound really bounds the pair bracket (oracle, exact rates)
-    for j in (40, 55, 62, 64, 66, 70, 80):
-        chi = 2.0 ** (j - 64)
-        d = np.linspace(1e-4, 0.5, 2000)
-        brk = [orc.rate_pair(x, chi, 1.0, 1.0, orc.EXACT) * math.sqrt(3) * math.pi for x in d]
-        assert max(brk) <= bound[j]
+    assert np.array_equal(bound32, bound.astype(np.float32))
+    # each sub-octave bound really bounds the pair bracket at its interval's top chi
+    # (oracle, exact rates), and the bounds grow with chi
+    d = np.linspace(1e-4, 0.5, 2000)
+    for e in (40, 55, 62, 64, 66, 70, 80):
+        for j in (0, 7, 15):
+            chi = (0.5 + (j + 1) / 32.0) * 2.0 ** (e - 64)
+            brk = [orc.rate_pair(x, chi, 1.0, 1.0, orc.EXACT) * math.sqrt(3) * math.pi
+                   for x in d]
+            assert max(brk) <= bound[e, j]
+    flat = bound.reshape(-1)
+    assert np.all(np.diff(flat[flat > 0]) >= 0)
 
 
 def test_uniform_b_full_size_parity(orc):
