@@ -44,6 +44,11 @@ class OrStore(C.Structure):
                 ("n_events", _u32p), ("count", C.c_int64), ("capacity", C.c_int64)]
 
 
+class OrThinRecord(C.Structure):
+    _fields_ = [("live_before", C.c_int64), ("kept", C.c_int64), ("weight_before", C.c_double),
+                ("weight_after", C.c_double), ("factor", C.c_double)]
+
+
 class OrField(C.Structure):
     _fields_ = [("kind", C.c_int), ("e0", C.c_double * 3), ("b0", C.c_double * 3),
                 ("amp", C.c_double), ("omega", C.c_double), ("phase", C.c_double),
@@ -116,6 +121,9 @@ def lib():
         L.or_step.argtypes = [C.POINTER(OrTables), C.POINTER(OrStore), C.POINTER(OrField),
                               C.POINTER(OrParams), C.POINTER(OrStats)]
         L.or_step.restype = C.c_int
+        L.or_thin.argtypes = [C.POINTER(OrStore), C.c_int64, C.c_int64, C.c_uint64, C.c_int64,
+                              C.POINTER(OrThinRecord)]
+        L.or_thin.restype = C.c_int
         for fn in ("or_emission_trials", "or_pair_trials"):
             getattr(L, fn).argtypes = [C.POINTER(OrTables), C.c_int, C.c_double, C.c_double,
                                        C.c_double, C.c_uint64, C.c_int64, _dp]
@@ -383,6 +391,18 @@ def step(stores: Sequence[Store], fld: Field, params: Params) -> Dict:
     for i, s in enumerate(stores):
         s.count = int(arr[i].count)
     return st.as_dict()
+
+
+def thin(store: "Store", trigger: int, target: int, seed: int, step: int) -> Dict:
+    """Thinning by global even redistribution (Sec. VI) of one store, in place."""
+    cs = store._cstruct()
+    rec = OrThinRecord()
+    rc = lib().or_thin(C.byref(cs), int(trigger), int(target), int(seed), int(step),
+                       C.byref(rec))
+    if rc < 0:
+        raise RuntimeError("oracle thinning failed")
+    store.count = int(cs.count)
+    return {k: getattr(rec, k) for k, _ in OrThinRecord._fields_} | {"thinned": rc == 1}
 
 
 def run(stores: Sequence[Store], fld: Field, params: Params, n_steps: int,

@@ -642,6 +642,72 @@ int or_step(const or_tables *t, or_store *st, const or_field *f, const or_params
 }
 
 /* ------------------------------------------------------------------------------------
+ * Thinning (Sec. VI, global even redistribution): remove random super-particles and share
+ * their weight among all the remaining ones by the factor sum f / (sum f - f_r).
+ * ------------------------------------------------------------------------------------ */
+int or_thin(or_store *s, int64_t trigger, int64_t target, uint64_t seed, int64_t step,
+            or_thin_record *rec) {
+  int64_t live = 0;
+  double w_live = 0.0;
+  for (int64_t i = 0; i < s->count; ++i)
+    if (s->id[i] != OR_ID_DEAD) {
+      ++live;
+      w_live += s->w[i];
+    }
+  rec->live_before = live;
+  rec->weight_before = w_live;
+  rec->kept = live;
+  rec->weight_after = w_live;
+  rec->factor = 1.0;
+  if (live <= trigger || target >= live) return 0;
+  const double q = (double)target / (double)live;
+  /* which particles stay: u < q with u from the particle's own draw */
+  int64_t kept = 0;
+  double w_kept = 0.0;
+  unsigned char *keep = (unsigned char *)malloc((size_t)(s->count > 0 ? s->count : 1));
+  if (!keep) return -1;
+  for (int64_t i = 0; i < s->count; ++i) {
+    keep[i] = 0;
+    if (s->id[i] == OR_ID_DEAD) continue;
+    uint32_t ctr[4] = {(uint32_t)step, 4u << 16, (uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t key[2] = {(uint32_t)s->id[i], (uint32_t)(s->id[i] >> 32)};
+    uint32_t o[4];
+    or_philox4x32_10(ctr, key, o);
+    if (or_uniform(o[0], o[1]) < q) {
+      keep[i] = 1;
+      ++kept;
+      w_kept += s->w[i];
+    }
+  }
+  /* the removed weight goes to every survivor in proportion to its own weight */
+  const double factor = kept > 0 ? w_live / w_kept : 0.0;
+  int64_t j = 0;
+  for (int64_t i = 0; i < s->count; ++i) {
+    if (!keep[i]) continue;
+    s->x[j] = s->x[i];
+    s->y[j] = s->y[i];
+    s->z[j] = s->z[i];
+    s->px[j] = s->px[i];
+    s->py[j] = s->py[i];
+    s->pz[j] = s->pz[i];
+    s->w[j] = s->w[i] * factor;
+    s->id[j] = s->id[i];
+    s->parent[j] = s->parent[i];
+    s->birth[j] = s->birth[i];
+    if (s->n_events) s->n_events[j] = s->n_events[i];
+    ++j;
+  }
+  free(keep);
+  s->count = kept;
+  rec->kept = kept;
+  rec->factor = factor;
+  double w_after = 0.0;
+  for (int64_t i = 0; i < kept; ++i) w_after += s->w[i];
+  rec->weight_after = w_after;
+  return 1;
+}
+
+/* ------------------------------------------------------------------------------------
  * Generator trials for the statistical pins: trial i draws (r1, r2) from Philox with
  * counter (i, i>>32, 0, 0) and the given key, then applies the generator decision.
  * ------------------------------------------------------------------------------------ */
