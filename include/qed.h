@@ -227,6 +227,37 @@ qed_status qed_step(const void *d_tables, const qed_stores *stores, const qed_fi
                     const qed_params *params, int64_t *d_step, qed_stats *d_stats, void *d_work,
                     size_t work_bytes, void *stream);
 
+/* Result of qed_thin for one instance (device memory, one record per instance).  A store
+ * at or below the trigger is not examined: all fields 0, factor 1. */
+typedef struct {
+  int64_t live_before;   /* live particles of the store before (removed photons excluded) */
+  int64_t kept;          /* live particles after */
+  double weight_before;  /* sum of w over the live particles before (= after, up to rounding) */
+  double factor;         /* factor applied to the survivors' weights (1 if not thinned) */
+  int32_t thinned;       /* 1 if the store was thinned */
+  int32_t reserved;
+} qed_thin_record;
+
+/* Workspace size of qed_thin for n_instances instances and a species store of
+ * species_slots slots (a hole list of 4 bytes per slot and per-instance partial sums). */
+size_t qed_thin_work_bytes(int n_instances, int64_t species_slots);
+
+/* Thinning by global even redistribution (Sec. VI), for one species of every instance.
+ * An instance whose segment holds more than `trigger` slots (live particles and removed
+ * photons) and more than `target` live particles is thinned: each live particle survives
+ * with probability q = target / live, decided by the Philox draw keyed by its id with
+ * counter (*d_step, 4 << 16, instance seed lo, hi), survival iff the first two words as a
+ * uniform in (0, 1) are below q; the survivors' weights are multiplied by the live weight
+ * over the surviving weight (sum f / (sum f - f_r)), which conserves the total weight; the
+ * segment is compacted (survivors past the new count fill the holes below it; removed
+ * photons go too) and its count set to the number of survivors.  Instances at or below the
+ * trigger are left as they are.  d_records[n_instances] receives one record per instance.
+ * Graph-capturable; no host synchronisation.  QED_ERR_ARG on bad arguments,
+ * QED_ERR_UNSUPPORTED if the store has 2^32 or more slots. */
+qed_status qed_thin(const qed_stores *stores, int species, int64_t trigger, int64_t target,
+                    const int64_t *d_step, qed_thin_record *d_records, void *d_work,
+                    size_t work_bytes, void *stream);
+
 /* Append the record *d_stats to d_log[*d_log_count] and increment *d_log_count, unless
  * *d_log_count >= log_capacity (then the record is discarded and the count still grows,
  * so the caller sees the overflow).  Graph-capturable. */

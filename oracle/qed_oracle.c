@@ -647,6 +647,10 @@ int or_step(const or_tables *t, or_store *st, const or_field *f, const or_params
  * ------------------------------------------------------------------------------------ */
 int or_thin(or_store *s, int64_t trigger, int64_t target, uint64_t seed, int64_t step,
             or_thin_record *rec) {
+  rec->live_before = rec->kept = 0;
+  rec->weight_before = rec->weight_after = 0.0;
+  rec->factor = 1.0;
+  if (s->count <= trigger) return 0; /* not examined */
   int64_t live = 0;
   double w_live = 0.0;
   for (int64_t i = 0; i < s->count; ++i)
@@ -659,7 +663,7 @@ int or_thin(or_store *s, int64_t trigger, int64_t target, uint64_t seed, int64_t
   rec->kept = live;
   rec->weight_after = w_live;
   rec->factor = 1.0;
-  if (live <= trigger || target >= live) return 0;
+  if (target >= live) return 0;
   const double q = (double)target / (double)live;
   /* which particles stay: u < q with u from the particle's own draw */
   int64_t kept = 0;

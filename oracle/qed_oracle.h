@@ -109,13 +109,16 @@ uint64_t or_child_id(uint64_t parent, uint64_t seed, int64_t step, int substep, 
 int or_step(const or_tables *t, or_store *st /* [3] */, const or_field *f, const or_params *p,
             or_stats *s);
 
-/* Thinning by global even redistribution (Sec. VI): when the live particles of a store
- * number more than `trigger`, each is kept with probability q = target / live, decided by
+/* Thinning by global even redistribution (Sec. VI): when a store's count (live particles
+ * and removed-photon slots) exceeds `trigger` and `target` is below the number of live
+ * particles, each live particle is kept with probability q = target / live, decided by
  * the Philox draw keyed by its id with counter (step, 4 << 16, seed lo, seed hi) (first two
  * words as the uniform u; kept iff u < q), and the survivors' weights are multiplied by
  * sum(w of live) / sum(w of kept), so the total weight is unchanged.  Survivors keep their
- * order; removed photons (dead ids) go too.  Parity unpinned for the store order (the GPU
- * fills holes from the tail); the set of survivors and their weights are compared. */
+ * order; removed photons (dead ids) go too.  A store at or below the trigger is not
+ * examined (record all zero, factor 1); one examined but not thinned reports its live count
+ * and weight.  Parity unpinned for the store order (the GPU fills holes from the tail);
+ * the set of survivors and their weights are compared. */
 typedef struct {
   int64_t live_before, kept;
   double weight_before, weight_after, factor;

@@ -243,6 +243,31 @@ qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_fi
   return e == hipSuccess ? QED_OK : QED_ERR_HIP;
 }
 
+size_t qed_thin_work_bytes(int n_instances, int64_t species_slots) {
+  if (n_instances < 1 || species_slots < 0) return 0;
+  return ThinLayout::make(n_instances, species_slots).total;
+}
+
+qed_status qed_thin(const qed_stores* stores, int species, int64_t trigger, int64_t target,
+                    const int64_t* d_step, qed_thin_record* d_records, void* d_work,
+                    size_t work_bytes, void* stream) {
+  if (!stores || !d_step || !d_records || !d_work || !stores->d_instances) return QED_ERR_ARG;
+  if (species < QED_ELECTRON || species > QED_PHOTON || trigger < 0 || target < 1)
+    return QED_ERR_ARG;
+  const int ni = stores->n_instances;
+  const int64_t slots = stores->slots[species];
+  if (ni < 1 || ni > 65535 || slots < 0) return QED_ERR_ARG;  // instances are grid rows
+  if (slots >= (1ll << 32)) return QED_ERR_UNSUPPORTED;
+  if (work_bytes < qed_thin_work_bytes(ni, slots) || (reinterpret_cast<uintptr_t>(d_work) & 255u))
+    return QED_ERR_ARG;
+  if (!soa_ok(stores->species[species], species != QED_PHOTON)) return QED_ERR_ARG;
+  const hipError_t e = launch_thin(stores->species[species], species, stores->d_instances, ni,
+                                   (long long)trigger, (long long)target,
+                                   reinterpret_cast<const long long*>(d_step), d_records, d_work,
+                                   static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? QED_OK : QED_ERR_HIP;
+}
+
 qed_status qed_append_stats(const qed_stats* d_stats, qed_stats* d_log, int64_t log_capacity,
                             int64_t* d_log_count, void* stream) {
   if (!d_stats || !d_log || !d_log_count || log_capacity < 0) return QED_ERR_ARG;

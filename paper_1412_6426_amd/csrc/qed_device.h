@@ -72,7 +72,9 @@ __device__ __forceinline__ float uniform32(uint32_t hi) {
 
 // Counter layout shared by the event draw and the child ids:
 //   key = particle id, counter = (step, sub-step | purpose << 16, seed lo, seed hi).
-enum Purpose : uint32_t { kDraw = 0, kPhotonChild = 1, kElectronChild = 2, kPositronChild = 3 };
+enum Purpose : uint32_t {
+  kDraw = 0, kPhotonChild = 1, kElectronChild = 2, kPositronChild = 3, kThin = 4
+};
 
 __device__ __forceinline__ uint4 draw_words(uint64_t id, uint64_t seed, uint32_t step, uint32_t sub,
                                             uint32_t purpose) {

@@ -121,6 +121,30 @@ struct WorkLayout {
   }
 };
 
+// Thinning (qed_thin): workgroups per instance and the workspace layout.
+constexpr int kThinBlocks = 256;
+struct ThinLayout {
+  size_t plan, part_n, part_w, hole_off, surv_off, holes, total;
+  static ThinLayout make(int n_inst, long long slots = 0) {
+    ThinLayout L{};
+    size_t off = 0;
+    auto take = [&off](size_t bytes) {
+      size_t o = off;
+      off += (bytes + 255) & ~(size_t)255;
+      return o;
+    };
+    const size_t nb = (size_t)n_inst * kThinBlocks;
+    L.plan = take(64 * (size_t)n_inst);
+    L.part_n = take(8 * nb);
+    L.part_w = take(8 * nb);
+    L.hole_off = take(8 * nb);
+    L.surv_off = take(8 * nb);
+    L.holes = take(4 * (size_t)(slots > 0 ? slots : 1));
+    L.total = off;
+    return L;
+  }
+};
+
 struct StepArgs {
   qed_soa sp[3];
   qed_instance* inst;
@@ -172,6 +196,9 @@ hipError_t launch_spectrum(const qed_soa& ph, qed_instance* inst, int n_inst, do
 hipError_t launch_fill_standing(float* const g[6], const int n[3], const double dx[3],
                                 const double org[3], double amp, double omega, double phase,
                                 double t, hipStream_t s);
+hipError_t launch_thin(const qed_soa& s, int species, qed_instance* inst, int n_inst,
+                       long long trigger, long long target, const long long* d_step,
+                       qed_thin_record* rec, void* work, hipStream_t st);
 // Persistent-grid sizing: resident workgroups per CU for the step kernels.
 int step_blocks_per_cu(int precision, bool photon, int block);
 

@@ -444,7 +444,6 @@ struct WaveRange {
 // Does this workgroup own any work?  (its first wavefront's first chunk starts below N)
 __device__ __forceinline__ bool block_has_work(long long N, long long tile) {
   const long long wpb = blockDim.x >> 6;
-  const long long W = (long long)gridDim.x * wpb;
   long long T = tile > 0 ? tile : kDefaultTile;
   if (T < 1) T = 1;
   return (long long)blockIdx.x * wpb * T < N;

@@ -154,6 +154,27 @@ class Engine:
         raw = self.stats_buf.cpu().numpy().tobytes()
         return Q.qed_stats.from_buffer_copy(raw).as_dict()
 
+    # ------------------------------------------------------------------ thinning
+    def thin(self, species: int, trigger: int, target: int, stream: Optional[int] = None):
+        """qed_thin on one species of every instance; records stay on the device until
+        thin_records() reads them."""
+        torch = _torch()
+        slots = int(self.cols[species]["x"].numel())
+        need = Q.qed_thin_work_bytes(self.n_inst, slots)
+        if getattr(self, "_thin_work", None) is None or self._thin_work.numel() < need:
+            self._thin_work = torch.zeros(need, dtype=torch.uint8, device=self.device)
+            self._thin_rec = torch.zeros(self.n_inst * C.sizeof(Q.qed_thin_record),
+                                         dtype=torch.uint8, device=self.device)
+        Q.qed_thin(self.stores, species, int(trigger), int(target), self.step_ctr.data_ptr(),
+                   self._thin_rec.data_ptr(), self._thin_work.data_ptr(),
+                   self._thin_work.numel(), self.stream if stream is None else stream)
+
+    def thin_records(self) -> List[Dict]:
+        raw = self._thin_rec.cpu().numpy().tobytes()
+        n = C.sizeof(Q.qed_thin_record)
+        return [Q.qed_thin_record.from_buffer_copy(raw[i * n:(i + 1) * n]).as_dict()
+                for i in range(self.n_inst)]
+
     # ------------------------------------------------------------------ the step
     @staticmethod
     def make_field(kind: int, e0=(0, 0, 0), b0=(0, 0, 0), amp=0.0, omega=1.0, phase=0.0,

@@ -87,8 +87,17 @@ class qed_stats(C.Structure):
         return out
 
 
+class qed_thin_record(C.Structure):
+    _fields_ = [("live_before", C.c_int64), ("kept", C.c_int64), ("weight_before", C.c_double),
+                ("factor", C.c_double), ("thinned", C.c_int32), ("reserved", C.c_int32)]
+
+    def as_dict(self) -> Dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 #: every symbol include/qed.h declares
 EXPORTS = ("qed_table_bytes", "qed_build_tables", "qed_work_bytes", "qed_step",
+           "qed_thin_work_bytes", "qed_thin",
            "qed_append_stats", "qed_photon_spectrum", "qed_fill_standing_wave",
            "qed_status_string", "qed_version")
 
@@ -117,6 +126,11 @@ def lib():
                                C.POINTER(qed_params), C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_size_t, C.c_void_p]
         L.qed_append_stats.restype = C.c_int
+        L.qed_thin_work_bytes.restype = C.c_size_t
+        L.qed_thin_work_bytes.argtypes = [C.c_int, C.c_int64]
+        L.qed_thin.restype = C.c_int
+        L.qed_thin.argtypes = [C.POINTER(qed_stores), C.c_int, C.c_int64, C.c_int64, C.c_void_p,
+                               C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
         L.qed_append_stats.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
                                        C.c_void_p]
         L.qed_photon_spectrum.restype = C.c_int
@@ -156,6 +170,16 @@ def qed_step(d_tables: int, stores: qed_stores, field: qed_field, params: qed_pa
              d_step: int, d_stats: int, d_work: int, work_bytes: int, stream: int) -> None:
     _check(lib().qed_step(d_tables, C.byref(stores), C.byref(field), C.byref(params), d_step,
                           d_stats, d_work, work_bytes, stream), "qed_step")
+
+
+def qed_thin_work_bytes(n_instances: int, species_slots: int) -> int:
+    return int(lib().qed_thin_work_bytes(n_instances, species_slots))
+
+
+def qed_thin(stores: qed_stores, species: int, trigger: int, target: int, d_step: int,
+             d_records: int, d_work: int, work_bytes: int, stream: int) -> None:
+    _check(lib().qed_thin(C.byref(stores), species, trigger, target, d_step, d_records, d_work,
+                          work_bytes, stream), "qed_thin")
 
 
 def qed_append_stats(d_stats: int, d_log: int, log_capacity: int, d_log_count: int,

@@ -34,9 +34,11 @@ def _sorted(c):
     return {k: (v[order] if v is not None else None) for k, v in c.items()}
 
 
-def compare_species(gpu, orc_cols, species, rtol=1e-12, label=""):
+def compare_species(gpu, orc_cols, species, rtol=1e-12, label="", wtol=0.0):
     """Bit-exact ids, parents, births (and event counts for leptons); momenta and positions
-    within rtol of max(|v|, 1); weights exact.  Removed photons are compared by count."""
+    within rtol of max(|v|, 1); weights exact, or within wtol relative where thinning has
+    rescaled them (its factor is a ratio of sums taken in different orders on the two
+    sides).  Removed photons are compared by count."""
     g = dict(gpu)
     o = dict(orc_cols)
     if species == PHOTON:
@@ -51,7 +53,10 @@ def compare_species(gpu, orc_cols, species, rtol=1e-12, label=""):
     assert np.array_equal(g["birth"], o["birth"]), f"{label}: births differ"
     if species != PHOTON and o.get("n_events") is not None:
         assert np.array_equal(g["n_events"], o["n_events"]), f"{label}: event counts differ"
-    assert np.array_equal(g["w"], o["w"]), f"{label}: weights differ"
+    if wtol == 0.0:
+        assert np.array_equal(g["w"], o["w"]), f"{label}: weights differ"
+    else:
+        np.testing.assert_allclose(g["w"], o["w"], rtol=wtol, atol=0, err_msg=label)
     worst = {}
     for grp in (("px", "py", "pz"), ("x", "y", "z")):
         a = np.stack([g[c] for c in grp], 1)
@@ -63,9 +68,9 @@ def compare_species(gpu, orc_cols, species, rtol=1e-12, label=""):
     return worst
 
 
-def compare_all(engine, ostores, inst=0, rtol=1e-12, label=""):
+def compare_all(engine, ostores, inst=0, rtol=1e-12, label="", wtol=0.0):
     out = {}
     for s in range(3):
         out[s] = compare_species(engine.read(inst, s), ostores[s].view(), s, rtol,
-                                 f"{label} species {s}")
+                                 f"{label} species {s}", wtol=wtol)
     return out

@@ -42,7 +42,8 @@ def test_every_declared_symbol_is_exported(Q):
 def test_ctypes_layout_matches_header(Q, tmp_path):
     """Compile a probe against include/qed.h with gcc and compare every struct's size and
     every field's offset with the ctypes mirror."""
-    structs = [Q.qed_soa, Q.qed_instance, Q.qed_stores, Q.qed_field, Q.qed_params, Q.qed_stats]
+    structs = [Q.qed_soa, Q.qed_instance, Q.qed_stores, Q.qed_field, Q.qed_params, Q.qed_stats,
+               Q.qed_thin_record]
     lines = ['#include "qed.h"', "#include <stdio.h>", "#include <stddef.h>", "int main(void){"]
     expect = []
     for S in structs:
@@ -82,6 +83,29 @@ def test_host_side_queries(Q):
     # no arenas above 1024 instances
     assert Q.qed_work_bytes(1025, 1000, 1 << 20) == Q.qed_work_bytes(1025, 1000)
     assert Q.lib().qed_status_string(1) == b"invalid argument"
+    # thinning: per-instance plan and partial sums plus a 4-byte hole list per slot
+    t1, t2 = Q.qed_thin_work_bytes(1, 1000), Q.qed_thin_work_bytes(1, 2000)
+    assert t1 > 0 and abs((t2 - t1) - 4000) < 512
+    assert Q.qed_thin_work_bytes(0, 10) == 0 and Q.qed_thin_work_bytes(1, -1) == 0
+
+
+def test_thin_argument_validation_without_device(Q):
+    L = Q.lib()
+    st = Q.qed_stores()
+    fake = C.c_void_p(4096)
+    assert L.qed_thin(None, 2, 10, 5, fake, fake, fake, 1 << 20, None) == Q.QED_ERR_ARG
+    st.n_instances = 1
+    st.d_instances = 4096
+    st.slots[2] = 1000
+    # bad species, trigger, target; too small a workspace; store columns missing
+    assert L.qed_thin(C.byref(st), 3, 10, 5, fake, fake, fake, 1 << 20, None) == Q.QED_ERR_ARG
+    assert L.qed_thin(C.byref(st), 2, -1, 5, fake, fake, fake, 1 << 20, None) == Q.QED_ERR_ARG
+    assert L.qed_thin(C.byref(st), 2, 10, 0, fake, fake, fake, 1 << 20, None) == Q.QED_ERR_ARG
+    assert L.qed_thin(C.byref(st), 2, 10, 5, fake, fake, fake, 16, None) == Q.QED_ERR_ARG
+    assert L.qed_thin(C.byref(st), 2, 10, 5, fake, fake, fake, 1 << 20, None) == Q.QED_ERR_ARG
+    st.slots[2] = 1 << 32
+    assert L.qed_thin(C.byref(st), 2, 10, 5, fake, fake, fake, 1 << 40,
+                      None) == Q.QED_ERR_UNSUPPORTED
 
 
 def test_argument_validation_without_device(Q):

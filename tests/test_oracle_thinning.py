@@ -79,9 +79,12 @@ def test_draws_are_independent_across_steps(orc):
 
 def test_no_change_at_or_below_trigger(orc):
     st, cols = _store(orc, 1000, 5)
-    for trig, tgt in ((1000, 10), (5000, 10), (10, 2000)):
+    for trig, tgt in ((1000, 10), (5000, 10)):  # not examined
         rec = orc.thin(st, trigger=trig, target=tgt, seed=1, step=1)
-        assert not rec["thinned"] and rec["kept"] == 1000 and rec["factor"] == 1.0
+        assert not rec["thinned"] and rec["live_before"] == 0 and rec["factor"] == 1.0
+    rec = orc.thin(st, trigger=10, target=2000, seed=1, step=1)  # examined, target above live
+    assert not rec["thinned"] and rec["live_before"] == rec["kept"] == 1000
+    assert rec["factor"] == 1.0
     v = st.view()
     for c in cols:
         assert np.array_equal(v[c], cols[c])
