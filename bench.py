@@ -19,8 +19,9 @@ kernel (algorithmic bytes / its event-timed duration vs 8 TB/s), the same run in
 precision with its photon-spectrum L1 distance and pair yield against the FP64 run, the
 batched ensemble (64 rotating-field cascades, a0 log-spaced over 500-3000, 10^3-10^5 seeds
 each, 2 periods, 2*10^8 slots split evenly) in mixed precision and in FP64, the
-standing-wave cascade on a 256^3 Yee grid (field fill timed apart), and the FP64 CPU
-oracle's rate on a bounded sample of the rotating-field workload on this host.
+standing-wave cascade on a 256^3 Yee grid (field fill timed apart), the rotating-field
+cascade carried past its capacity by thinning, and the FP64 CPU oracle's rate on a bounded
+sample of the rotating-field workload on this host.
 
 HBM traffic of the dominant kernel comes from the rocprofv3 counter summary committed
 under profiles/ (FETCH_SIZE and WRITE_SIZE scaled by the same counters' reading for a copy
@@ -110,12 +111,13 @@ def make_job(kind, args, precision):
     return w, e, reload
 
 
-def gpu_run(args, precision, kind="rotating"):
+def gpu_run(args, precision, kind="rotating", thin=None):
     """One job three times from the same seeds: a tuning run that picks the launch shape
     per size class (untimed), K steps replayed from one captured graph per chosen shape
     and timed as a whole (value), and K eager steps with HIP events around the lepton and
     photon kernels (per-kernel durations for the roofline).  The three runs compute the
-    same thing."""
+    same thing.  thin = (trigger, target): qed_thin on the photon store after every step
+    (timed with the step)."""
     import numpy as np
     import torch
     from paper_1412_6426_amd import autotune as AT
@@ -138,10 +140,15 @@ def gpu_run(args, precision, kind="rotating"):
         cnt.zero_()
         torch.cuda.synchronize()
 
+    def thin_now():
+        if thin is not None:
+            e.thin(Q.QED_PHOTON, thin[0], thin[1], stream=sp)
+
     # warm-up steps on the same stores, then back to the seed state
     with torch.cuda.stream(stream):
         for _ in range(args.warmup):
             e.step(field, params, stream=sp)
+            thin_now()
     # ---- tuning run: launch shape per size class ----
     if args.no_tune:
         sched = AT.Schedule(steps=[0], shapes=[(args.tile, args.grid_blocks)])
@@ -149,7 +156,8 @@ def gpu_run(args, precision, kind="rotating"):
         restart()
         cus = torch.cuda.get_device_properties(0).multi_processor_count
         with torch.cuda.stream(stream):
-            sched = AT.tune_run(e, field, params, K, AT.default_candidates(cus))
+            sched = AT.tune_run(e, field, params, K, AT.default_candidates(cus),
+                                after_step=thin_now)
     shape_of = [sched.shape_at(n) for n in range(K)]
 
     # ---- timed: one captured step (and its stats record) per shape, replayed K times ----
@@ -159,6 +167,7 @@ def gpu_run(args, precision, kind="rotating"):
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g, stream=stream):
             e.step(field, params, stream=sp)
+            thin_now()
             Q.qed_append_stats(e.stats_buf.data_ptr(), log.data_ptr(), K, cnt.data_ptr(), sp)
         graphs[shape] = g
     plan = [graphs[s] for s in shape_of]
@@ -189,17 +198,24 @@ def gpu_run(args, precision, kind="rotating"):
     restart()
     hip = HipEvents()
     evs = hip.create(4 * K)
+    tev = hip.create(2 * K) if thin is not None else []
     with torch.cuda.stream(stream):
         for n in range(K):
             params.tile, params.grid_blocks = shape_of[n]
             for j in range(4):
                 params.events[j] = evs[4 * n + j]
             e.step(field, params, stream=sp)
+            if thin is not None:
+                hip.lib.hipEventRecord(C.c_void_p(tev[2 * n]), C.c_void_p(sp))
+                thin_now()
+                hip.lib.hipEventRecord(C.c_void_p(tev[2 * n + 1]), C.c_void_p(sp))
             Q.qed_append_stats(e.stats_buf.data_ptr(), log.data_ptr(), K, cnt.data_ptr(), sp)
     torch.cuda.synchronize()
     lep_t = [hip.elapsed_ms(evs[4 * n], evs[4 * n + 1]) for n in range(K)]
     pho_t = [hip.elapsed_ms(evs[4 * n + 2], evs[4 * n + 3]) for n in range(K)]
+    thin_t = [hip.elapsed_ms(tev[2 * n], tev[2 * n + 1]) for n in range(K)] if thin else []
     hip.destroy(evs)
+    hip.destroy(tev)
     recs2 = _stats_records(log.cpu().numpy().tobytes(), K)
     same = all(a.emitted == b.emitted and a.pairs == b.pairs and
                list(a.advanced) == list(b.advanced) for a, b in zip(recs, recs2))
@@ -216,7 +232,8 @@ def gpu_run(args, precision, kind="rotating"):
         workload=w.description, ms=ms, wall_s=wall, steps=K, active_steps=active,
         first_drop_step=first_drop,
         particle_steps=int(sum(adv)), advanced=[int(a) for a in adv], emitted=int(emitted),
-        pairs=int(pairs), lep_ms=sum(lep_t), pho_ms=sum(pho_t), lep_bytes=lep_bytes,
+        pairs=int(pairs), lep_ms=sum(lep_t), pho_ms=sum(pho_t), thin_ms=sum(thin_t),
+        lep_bytes=lep_bytes,
         pho_bytes=pho_bytes, final_counts=[int(sum(c[s] for c in counts)) for s in range(3)],
         eager_matches_graph=bool(same),
         schedule=[dict(from_step=k, tile=t, grid_blocks=g)
@@ -409,6 +426,8 @@ def main():
                     help="also histogram the final photon stores")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-ensemble runs (64 cascades, mixed and FP64)")
+    ap.add_argument("--no-thin", action="store_true",
+                    help="skip the cascade run past the capacity with thinning")
     ap.add_argument("--no-yee", action="store_true",
                     help="skip the standing-wave cascade on the 256^3 Yee grid")
     ap.add_argument("--no-tune", action="store_true",
@@ -499,6 +518,19 @@ def main():
         line["batched"] = dict(
             workload=rb["workload"],
             speedup_mixed_vs_f64=b["mixed"]["value"] / b["f64"]["value"], **b)
+    if not args.no_thin:
+        # the same cascade past the capacity: the photon store is thinned to 40% of its
+        # slots whenever it holds more than 80% (global even redistribution)
+        cap = args.capacity
+        print("bench: rotating-E cascade with thinning", file=sys.stderr, flush=True)
+        rt = gpu_run(args, args.precision, thin=(int(0.8 * cap), int(0.4 * cap)))
+        line["thinned_cascade"] = dict(
+            value=rt["particle_steps"] / (rt["ms"] / 1e3), ms=rt["ms"], steps=rt["steps"],
+            particle_steps=rt["particle_steps"], dropped=rt["dropped"],
+            thin_ms=rt["thin_ms"], lep_ms=rt["lep_ms"], pho_ms=rt["pho_ms"],
+            final_counts=rt["final_counts"], pairs=rt["pairs"], emitted=rt["emitted"],
+            trigger=int(0.8 * cap), target=int(0.4 * cap),
+            eager_matches_graph=rt["eager_matches_graph"])
     if not args.no_yee:
         print("bench: standing-wave cascade on the Yee grid", file=sys.stderr, flush=True)
         line["standing_wave_grid"] = gpu_run_yee(args, args.precision)

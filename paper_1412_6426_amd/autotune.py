@@ -83,12 +83,14 @@ class Schedule:
 
 def tune_run(e, field, params: Q.qed_params, n_steps: int, candidates: Sequence[Shape],
              rounds: int = 2, class_factor: float = 4.0, min_live: int = 1 << 16,
-             stop_on_drop: bool = False) -> Schedule:
+             stop_on_drop: bool = False, after_step=None) -> Schedule:
     """Run n_steps steps of the job on engine `e`, tuning the shape per size class.
 
     Below `min_live` live particles the library default shape is used untimed (those steps
     are launch-bound).  The returned schedule gives every step the best shape of its size
-    class (trial steps included).  `e` ends in the state after the run."""
+    class (trial steps included).  `after_step()`, if given, runs after every step (on the
+    engine's stream) as part of the job, for instance thinning.  `e` ends in the state
+    after the run."""
     import torch
 
     ev = _Events()
@@ -123,6 +125,8 @@ def tune_run(e, field, params: Q.qed_params, n_steps: int, candidates: Sequence[
         ev.start(stream)
         e.step(field, params)
         ms = ev.stop_ms(stream)
+        if after_step is not None:
+            after_step()
         st = e.stats()
         done = sum(st["advanced"])
         live = int(e.counts().sum())
