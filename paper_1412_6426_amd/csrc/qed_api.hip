@@ -262,7 +262,7 @@ qed_status qed_thin(const qed_stores* stores, int species, int64_t trigger, int6
     return QED_ERR_ARG;
   if (!soa_ok(stores->species[species], species != QED_PHOTON)) return QED_ERR_ARG;
   const hipError_t e = launch_thin(stores->species[species], species, stores->d_instances, ni,
-                                   (long long)trigger, (long long)target,
+                                   (long long)slots, (long long)trigger, (long long)target,
                                    reinterpret_cast<const long long*>(d_step), d_records, d_work,
                                    static_cast<hipStream_t>(stream));
   return e == hipSuccess ? QED_OK : QED_ERR_HIP;

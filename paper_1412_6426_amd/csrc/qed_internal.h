@@ -121,11 +121,20 @@ struct WorkLayout {
   }
 };
 
-// Thinning (qed_thin): workgroups per instance and the workspace layout.
-constexpr int kThinBlocks = 256;
+// Thinning (qed_thin): ranges (workgroups) per instance and the workspace layout.  An
+// instance's segment is cut into nb ranges of about kThinSlotsPerRange slots of the mean
+// segment (slots / n_inst), at most kThinBlocks.
+constexpr int kThinBlocks = 2048;  // a multiple of the 256 threads of the plan kernels
+constexpr long long kThinSlotsPerRange = 8192;
 struct ThinLayout {
+  int nb;
   size_t plan, part_n, part_w, hole_off, surv_off, holes, total;
-  static ThinLayout make(int n_inst, long long slots = 0) {
+  static int ranges(int n_inst, long long slots) {
+    const long long seg = n_inst > 0 ? (slots + n_inst - 1) / n_inst : 0;
+    const long long want = (seg + kThinSlotsPerRange - 1) / kThinSlotsPerRange;
+    return (int)(want < 1 ? 1 : want > kThinBlocks ? kThinBlocks : want);
+  }
+  static ThinLayout make(int n_inst, long long slots) {
     ThinLayout L{};
     size_t off = 0;
     auto take = [&off](size_t bytes) {
@@ -133,7 +142,8 @@ struct ThinLayout {
       off += (bytes + 255) & ~(size_t)255;
       return o;
     };
-    const size_t nb = (size_t)n_inst * kThinBlocks;
+    L.nb = ranges(n_inst, slots);
+    const size_t nb = (size_t)n_inst * L.nb;
     L.plan = take(64 * (size_t)n_inst);
     L.part_n = take(8 * nb);
     L.part_w = take(8 * nb);
@@ -197,8 +207,9 @@ hipError_t launch_fill_standing(float* const g[6], const int n[3], const double 
                                 const double org[3], double amp, double omega, double phase,
                                 double t, hipStream_t s);
 hipError_t launch_thin(const qed_soa& s, int species, qed_instance* inst, int n_inst,
-                       long long trigger, long long target, const long long* d_step,
-                       qed_thin_record* rec, void* work, hipStream_t st);
+                       long long slots, long long trigger, long long target,
+                       const long long* d_step, qed_thin_record* rec, void* work,
+                       hipStream_t st);
 // Persistent-grid sizing: resident workgroups per CU for the step kernels.
 int step_blocks_per_cu(int precision, bool photon, int block);
 

@@ -4,8 +4,9 @@
 // by its id), and the survivors' weights are multiplied by sum f / (sum f - f_r), the total
 // live weight over the surviving weight, so charge (total weight) is conserved.
 //
-// Seven launches on the caller's stream, each a grid of (kThinBlocks, n_instances) or one
-// workgroup per instance; workgroup b of an instance owns a contiguous range of its segment:
+// Seven launches on the caller's stream, each a grid of (nb, n_instances) or one workgroup
+// per instance (nb ranges per instance, about 8192 slots each of the mean segment, at most
+// kThinBlocks); workgroup b of an instance owns a contiguous range of its segment:
 //   count  live particles and their weight per range;
 //   plan   sums (in a fixed order), q, whether to thin;
 //   keep   survivors and their weight per range;
@@ -25,6 +26,7 @@ namespace qedk {
 namespace {
 
 constexpr int kThinThreads = 256;
+static_assert(kThinBlocks % kThinThreads == 0, "plan kernels give each thread whole ranges");
 
 struct ThinPlan {
   long long n;      // slots of the segment when thinning started
@@ -43,18 +45,20 @@ struct ThinArgs {
   qed_instance* inst;
   int n_inst;
   long long trigger, target;
+  int nb;                      // ranges per instance, 1..kThinBlocks
   const long long* d_step;
   ThinPlan* plan;              // [n_inst]
-  long long* part_n;           // [n_inst][kThinBlocks] live, then kept
-  double* part_w;              // [n_inst][kThinBlocks] live weight, then kept weight
-  long long* hole_off;         // [n_inst][kThinBlocks]
-  long long* surv_off;         // [n_inst][kThinBlocks]
+  long long* part_n;           // [n_inst][nb] live, then kept
+  double* part_w;              // [n_inst][nb] live weight, then kept weight
+  long long* hole_off;         // [n_inst][nb]
+  long long* surv_off;         // [n_inst][nb]
   unsigned int* holes;         // [slots]: hole positions, relative to the segment base
   qed_thin_record* rec;        // [n_inst]
 };
 
-__device__ __forceinline__ void range_of(long long n, int b, long long& lo, long long& hi) {
-  const long long len = (n + kThinBlocks - 1) / kThinBlocks;
+__device__ __forceinline__ void range_of(long long n, int nb, int b, long long& lo,
+                                         long long& hi) {
+  const long long len = (n + nb - 1) / nb;
   lo = (long long)b * len;
   hi = lo + len < n ? lo + len : n;
   if (lo > n) lo = n;
@@ -107,7 +111,7 @@ __global__ void __launch_bounds__(kThinThreads) thin_count_kernel(ThinArgs a) {
   double w = 0.0;
   if (n > a.trigger) {
     long long lo, hi;
-    range_of(n, b, lo, hi);
+    range_of(n, a.nb, b, lo, hi);
     const long long base = I.base[a.species];
     for (long long j = lo + threadIdx.x; j < hi; j += blockDim.x)
       if (is_live(a, base + j)) {
@@ -117,22 +121,34 @@ __global__ void __launch_bounds__(kThinThreads) thin_count_kernel(ThinArgs a) {
   }
   block_sum(live, w, sn, sw);
   if (threadIdx.x == 0) {
-    a.part_n[(size_t)i * kThinBlocks + b] = live;
-    a.part_w[(size_t)i * kThinBlocks + b] = w;
+    a.part_n[(size_t)i * a.nb + b] = live;
+    a.part_w[(size_t)i * a.nb + b] = w;
     if (b == 0) a.plan[i].n = n;
   }
 }
 
-__global__ void __launch_bounds__(64) thin_plan_kernel(ThinArgs a) {
+// Sum of an instance's per-range partials in a fixed order: thread t takes ranges t, t + 256,
+// ... in turn, then the workgroup tree.  Result in thread 0.
+__device__ __forceinline__ void sum_partials(const ThinArgs& a, int i, long long& n, double& w,
+                                             long long* sn, double* sw) {
+  n = 0;
+  w = 0.0;
+  for (int b = threadIdx.x; b < a.nb; b += blockDim.x) {
+    n += a.part_n[(size_t)i * a.nb + b];
+    w += a.part_w[(size_t)i * a.nb + b];
+  }
+  block_sum(n, w, sn, sw);
+}
+
+__global__ void __launch_bounds__(kThinThreads) thin_plan_kernel(ThinArgs a) {
+  __shared__ long long sn[kThinThreads / 64];
+  __shared__ double sw[kThinThreads / 64];
   const int i = blockIdx.x;
+  long long live;
+  double w;
+  sum_partials(a, i, live, w, sn, sw);
   if (threadIdx.x != 0) return;
   ThinPlan& P = a.plan[i];
-  long long live = 0;
-  double w = 0.0;
-  for (int b = 0; b < kThinBlocks; ++b) {
-    live += a.part_n[(size_t)i * kThinBlocks + b];
-    w += a.part_w[(size_t)i * kThinBlocks + b];
-  }
   P.live = live;
   P.w_live = w;
   P.thin = (P.n > a.trigger && a.target < live) ? 1 : 0;
@@ -153,7 +169,7 @@ __global__ void __launch_bounds__(kThinThreads) thin_keep_kernel(ThinArgs a) {
   const uint64_t seed = I.seed;
   const uint32_t step = (uint32_t)*a.d_step;
   long long lo, hi;
-  range_of(P.n, b, lo, hi);
+  range_of(P.n, a.nb, b, lo, hi);
   long long kept = 0;
   double w = 0.0;
   for (long long j = lo + threadIdx.x; j < hi; j += blockDim.x)
@@ -163,9 +179,32 @@ __global__ void __launch_bounds__(kThinThreads) thin_keep_kernel(ThinArgs a) {
     }
   block_sum(kept, w, sn, sw);
   if (threadIdx.x == 0) {
-    a.part_n[(size_t)i * kThinBlocks + b] = kept;
-    a.part_w[(size_t)i * kThinBlocks + b] = w;
+    a.part_n[(size_t)i * a.nb + b] = kept;
+    a.part_w[(size_t)i * a.nb + b] = w;
   }
+}
+
+// Exclusive prefix over the workgroup's threads of v (thread order), and the total.
+__device__ __forceinline__ long long block_excl_scan(long long v, long long* sn,
+                                                     long long& total) {
+  long long x = v;
+  const int lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const long long y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  const int wv = (int)(threadIdx.x >> 6);
+  if (lane == 63) sn[wv] = x;
+  __syncthreads();
+  long long before = 0;
+  total = 0;
+  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+    if (k < wv) before += sn[k];
+    total += sn[k];
+  }
+  __syncthreads();
+  return before + x - v;
 }
 
 // One workgroup per instance.  Survivors in [lo, K) of the range that straddles K are
@@ -173,17 +212,14 @@ __global__ void __launch_bounds__(kThinThreads) thin_keep_kernel(ThinArgs a) {
 __global__ void __launch_bounds__(kThinThreads) thin_plan2_kernel(ThinArgs a) {
   __shared__ long long sn[kThinThreads / 64];
   __shared__ double sw[kThinThreads / 64];
-  __shared__ long long s_k;
+  __shared__ long long s_k, s_below;
   const int i = blockIdx.x;
   ThinPlan& P = a.plan[i];
   if (!P.thin) return;
+  long long k;
+  double w;
+  sum_partials(a, i, k, w, sn, sw);
   if (threadIdx.x == 0) {
-    long long k = 0;
-    double w = 0.0;
-    for (int b = 0; b < kThinBlocks; ++b) {
-      k += a.part_n[(size_t)i * kThinBlocks + b];
-      w += a.part_w[(size_t)i * kThinBlocks + b];
-    }
     P.kept = k;
     P.w_kept = w;
     P.factor = k > 0 ? P.w_live / w : 0.0;
@@ -195,45 +231,58 @@ __global__ void __launch_bounds__(kThinThreads) thin_plan2_kernel(ThinArgs a) {
   const long long base = I.base[a.species];
   const uint64_t seed = I.seed;
   const uint32_t step = (uint32_t)*a.d_step;
-  // the range containing K: survivors below K
-  int bk = -1;
-  long long lo_k = 0;
-  for (int b = 0; b < kThinBlocks; ++b) {
-    long long lo, hi;
-    range_of(P.n, b, lo, hi);
-    if (lo < K && K < hi) {
-      bk = b;
-      lo_k = lo;
-    }
-  }
+  // the range containing K strictly inside it: survivors below K
+  const long long len = (P.n + a.nb - 1) / a.nb;
+  const int bk = len > 0 ? (int)(K / len) : 0;
+  long long lo_k, hi_k;
+  range_of(P.n, a.nb, bk, lo_k, hi_k);
+  const bool straddle = len > 0 && bk < a.nb && lo_k < K && K < hi_k;
   long long below = 0;
   double unused = 0.0;
-  if (bk >= 0)
+  if (straddle)
     for (long long j = lo_k + threadIdx.x; j < K; j += blockDim.x)
       below += keeps(a, base + j, seed, step, P.q) ? 1 : 0;
   block_sum(below, unused, sn, sw);
-  if (threadIdx.x == 0) {
-    long long h = 0, sv = 0;
-    for (int b = 0; b < kThinBlocks; ++b) {
-      long long lo, hi;
-      range_of(P.n, b, lo, hi);
-      const long long kb = a.part_n[(size_t)i * kThinBlocks + b];
-      long long holes_b, surv_b;
-      if (hi <= K) {
-        holes_b = (hi - lo) - kb;
-        surv_b = 0;
-      } else if (lo >= K) {
-        holes_b = 0;
-        surv_b = kb;
-      } else {
-        holes_b = (K - lo) - below;
-        surv_b = kb - below;
-      }
-      a.hole_off[(size_t)i * kThinBlocks + b] = h;
-      a.surv_off[(size_t)i * kThinBlocks + b] = sv;
-      h += holes_b;
-      sv += surv_b;
+  if (threadIdx.x == 0) s_below = below;
+  __syncthreads();
+  below = s_below;
+  // holes below K and survivors at or above K per range; thread t owns a contiguous group
+  // of ranges, so a thread-order scan of the group sums gives range-order prefixes
+  constexpr int kMaxPer = kThinBlocks / kThinThreads;
+  const int per = (a.nb + kThinThreads - 1) / kThinThreads;
+  long long hb[kMaxPer], sb[kMaxPer], hsum = 0, ssum = 0;
+#pragma unroll
+  for (int m = 0; m < kMaxPer; ++m) {
+    const int b = (int)threadIdx.x * per + m;
+    hb[m] = sb[m] = 0;
+    if (m >= per || b >= a.nb) continue;
+    long long lo, hi;
+    range_of(P.n, a.nb, b, lo, hi);
+    const long long kb = a.part_n[(size_t)i * a.nb + b];
+    if (hi <= K) {
+      hb[m] = (hi - lo) - kb;
+      sb[m] = 0;
+    } else if (lo >= K) {
+      hb[m] = 0;
+      sb[m] = kb;
+    } else {
+      hb[m] = (K - lo) - below;
+      sb[m] = kb - below;
     }
+    hsum += hb[m];
+    ssum += sb[m];
+  }
+  long long tot;
+  long long h = block_excl_scan(hsum, sn, tot);
+  long long sv = block_excl_scan(ssum, sn, tot);
+#pragma unroll
+  for (int m = 0; m < kMaxPer; ++m) {
+    const int b = (int)threadIdx.x * per + m;
+    if (m >= per || b >= a.nb) continue;
+    a.hole_off[(size_t)i * a.nb + b] = h;
+    a.surv_off[(size_t)i * a.nb + b] = sv;
+    h += hb[m];
+    sv += sb[m];
   }
 }
 
@@ -263,9 +312,9 @@ __global__ void __launch_bounds__(kThinThreads) thin_holes_kernel(ThinArgs a) {
   const uint64_t seed = I.seed;
   const uint32_t step = (uint32_t)*a.d_step;
   long long lo, hi;
-  range_of(P.n, b, lo, hi);
+  range_of(P.n, a.nb, b, lo, hi);
   if (hi > P.kept) hi = P.kept;
-  long long off = a.hole_off[(size_t)i * kThinBlocks + b];
+  long long off = a.hole_off[(size_t)i * a.nb + b];
   const double f = P.factor;
   for (long long j0 = lo; j0 < hi; j0 += blockDim.x) {
     const long long j = j0 + threadIdx.x;
@@ -302,9 +351,9 @@ __global__ void __launch_bounds__(kThinThreads) thin_move_kernel(ThinArgs a) {
   const double f = P.factor;
   const qed_soa& S = a.s;
   long long lo, hi;
-  range_of(P.n, b, lo, hi);
+  range_of(P.n, a.nb, b, lo, hi);
   if (lo < K) lo = K;  // only the range at or above K is read here
-  long long off = a.surv_off[(size_t)i * kThinBlocks + b];
+  long long off = a.surv_off[(size_t)i * a.nb + b];
   for (long long j0 = lo; j0 < hi; j0 += blockDim.x) {
     const long long j = j0 + threadIdx.x;
     const bool mover = j < hi && keeps(a, base + j, seed, step, P.q);
@@ -338,9 +387,10 @@ __global__ void thin_count_set_kernel(ThinArgs a) {
 }  // namespace
 
 hipError_t launch_thin(const qed_soa& s, int species, qed_instance* inst, int n_inst,
-                       long long trigger, long long target, const long long* d_step,
-                       qed_thin_record* rec, void* work, hipStream_t st) {
-  const ThinLayout L = ThinLayout::make(n_inst);
+                       long long slots, long long trigger, long long target,
+                       const long long* d_step, qed_thin_record* rec, void* work,
+                       hipStream_t st) {
+  const ThinLayout L = ThinLayout::make(n_inst, slots);
   uint8_t* w = static_cast<uint8_t*>(work);
   ThinArgs a;
   a.s = s;
@@ -349,6 +399,7 @@ hipError_t launch_thin(const qed_soa& s, int species, qed_instance* inst, int n_
   a.n_inst = n_inst;
   a.trigger = trigger;
   a.target = target;
+  a.nb = L.nb;
   a.d_step = d_step;
   a.plan = reinterpret_cast<ThinPlan*>(w + L.plan);
   a.part_n = reinterpret_cast<long long*>(w + L.part_n);
@@ -357,9 +408,9 @@ hipError_t launch_thin(const qed_soa& s, int species, qed_instance* inst, int n_
   a.surv_off = reinterpret_cast<long long*>(w + L.surv_off);
   a.holes = reinterpret_cast<unsigned int*>(w + L.holes);
   a.rec = rec;
-  const dim3 grid(kThinBlocks, n_inst);
+  const dim3 grid(a.nb, n_inst);
   hipLaunchKernelGGL(thin_count_kernel, grid, dim3(kThinThreads), 0, st, a);
-  hipLaunchKernelGGL(thin_plan_kernel, dim3(n_inst), dim3(64), 0, st, a);
+  hipLaunchKernelGGL(thin_plan_kernel, dim3(n_inst), dim3(kThinThreads), 0, st, a);
   hipLaunchKernelGGL(thin_keep_kernel, grid, dim3(kThinThreads), 0, st, a);
   hipLaunchKernelGGL(thin_plan2_kernel, dim3(n_inst), dim3(kThinThreads), 0, st, a);
   hipLaunchKernelGGL(thin_holes_kernel, grid, dim3(kThinThreads), 0, st, a);

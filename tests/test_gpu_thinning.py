@@ -53,7 +53,7 @@ def _columns(n, seed, dead_every=0, photon=False):
 @pytest.mark.parametrize("species", [0, 2])
 def test_thin_matches_oracle(orc, species):
     """Four instances: three above the trigger (thinned to the same target from different
-    sizes) and one below it; segments span all 256 ranges with ragged ends."""
+    sizes) and one below it; each segment is cut into 24 ranges with ragged ends."""
     photon = species == 2
     sizes = [300_001, 257_777, 90_000, 120_000]
     caps = [(n, n, n) for n in sizes]
@@ -93,6 +93,33 @@ def test_thin_matches_oracle(orc, species):
             assert not np.any(got["id"] == DEAD)
             assert got["w"].sum() == pytest.approx(orec["weight_before"], rel=1e-12)
     assert [r["thinned"] for r in recs] == [1, 1, 0, 1]
+
+
+@pytest.mark.parametrize("n", [3_000_017, 16_789_561])
+def test_thin_large_segment(orc, n):
+    """One instance whose segment is cut into 367 ranges (two per thread of the plan
+    kernels, the last thread's group short) or into the maximum of 2048 ranges of 8198
+    slots (the last one short)."""
+    cols = _columns(n, 21, dead_every=5, photon=True)
+    full = dict(cols)
+    full["n_events"] = np.zeros(n, np.uint32)
+    e = Engine([(1, 1, n)], seeds=[17])
+    e.load(0, 2, full)
+    del full
+    e.set_step(77)
+    _note(f"thinning one segment of {n} photons")
+    e.thin(2, 0, n // 3)
+    torch.cuda.synchronize()
+    r = e.thin_records()[0]
+    st = orc.Store(n, with_events=False)
+    st.load(cols)
+    orec = orc.thin(st, 0, n // 3, seed=17, step=77)
+    assert r["thinned"] == 1 and orec["thinned"]
+    assert r["live_before"] == orec["live_before"] and r["kept"] == orec["kept"]
+    assert r["factor"] == pytest.approx(orec["factor"], rel=WTOL)
+    got = e.read(0, 2)
+    got.pop("n_events")
+    compare_species(got, st.view(), 2, rtol=0.0, label=f"{n} photons", wtol=WTOL)
 
 
 def test_thin_small_and_degenerate_stores(orc):
