@@ -60,7 +60,8 @@ class OrParams(C.Structure):
     _fields_ = [("dt", C.c_double), ("eps_r", C.c_double), ("kappa", C.c_double),
                 ("t0", C.c_double), ("adaptive", C.c_int), ("forced_substeps", C.c_int),
                 ("emission", C.c_int), ("pairs", C.c_int), ("push_photons", C.c_int),
-                ("backend", C.c_int), ("seed", C.c_uint64), ("step", C.c_int64)]
+                ("backend", C.c_int), ("seed", C.c_uint64), ("step", C.c_int64),
+                ("f_photon", C.c_double), ("f_pair", C.c_double)]
 
 
 class OrStats(C.Structure):
@@ -362,11 +363,13 @@ class Params:
     backend: int = TABLE
     seed: int = 0
     step: int = 0
+    f_photon: float = 1.0  # generator factors of Sec. VI (<= 1: off)
+    f_pair: float = 1.0
 
     def cstruct(self) -> OrParams:
         p = OrParams()
         for k in ("dt", "eps_r", "kappa", "t0", "adaptive", "forced_substeps", "emission",
-                  "pairs", "push_photons", "backend", "seed", "step"):
+                  "pairs", "push_photons", "backend", "seed", "step", "f_photon", "f_pair"):
             setattr(p, k, getattr(self, k))
         return p
 

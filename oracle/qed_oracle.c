@@ -391,6 +391,22 @@ static void or_draw(uint64_t id, uint64_t seed, int64_t step, int substep, doubl
   *r2 = or_uniform(o[2], o[3]);
 }
 
+/* Sec. VI, tunable generator factor: are the children of an event that fired created?  With
+ * f_g > 1 the generator runs with probability 1/f_g (its own draw, purpose 5 or 6). */
+static int or_generator_runs(uint64_t parent, uint64_t seed, int64_t step, int substep,
+                             int purpose, double fg) {
+  if (!(fg > 1.0)) return 1;
+  uint32_t ctr[4] = {(uint32_t)step, ((uint32_t)substep & 0xFFFFu) | ((uint32_t)purpose << 16),
+                     (uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t key[2] = {(uint32_t)parent, (uint32_t)(parent >> 32)};
+  uint32_t o[4];
+  or_philox4x32_10(ctr, key, o);
+  return or_uniform(o[0], o[1]) < 1.0 / fg;
+}
+
+/* The weight factor of children created by a generator with factor fg. */
+static double or_generator_weight(double fg) { return fg > 1.0 ? fg : 1.0; }
+
 /* ------------------------------------------------------------------------------------
  * The step.
  * ------------------------------------------------------------------------------------ */
@@ -496,16 +512,19 @@ static void or_lepton_advance(const or_tables *t, or_store *st, int species, int
         c.p[d] = (eps / pabs) * mom[d];
         c.x[d] = x[d];
       }
+      /* the lepton recoils at every event, whether or not the photon is created */
       for (int d = 0; d < 3; ++d) mom[d] = mom[d] - c.p[d];
-      c.w = st->w[j];
-      c.id = or_child_id(id, p->seed, p->step, k, 1);
-      c.parent = id;
-      c.birth = (uint32_t)(((uint64_t)(p->step + 1) << 14) | (uint32_t)k);
-      c.species = 2;
-      or_push_child(cb, &c);
       nev++;
-      s->emitted++;
       s->photon_energy += st->w[j] * eps;
+      if (or_generator_runs(id, p->seed, p->step, k, 5, p->f_photon)) {
+        c.w = st->w[j] * or_generator_weight(p->f_photon);
+        c.id = or_child_id(id, p->seed, p->step, k, 1);
+        c.parent = id;
+        c.birth = (uint32_t)(((uint64_t)(p->step + 1) << 14) | (uint32_t)k);
+        c.species = 2;
+        or_push_child(cb, &c);
+        s->emitted++;
+      }
     }
   }
   st->x[j] = x[0];
@@ -555,6 +574,9 @@ static void or_photon_advance(const or_tables *t, or_store *st, int64_t j, const
     double Pp = or_rate_pair(t, p->backend, r1, chi_g, kabs, dtfac);
     or_note_decision(s, Pp, r2, 1);
     if (r2 < Pp) {
+      /* the photon decays at every event, whether or not the pair is created */
+      dead = 1;
+      if (!or_generator_runs(id, p->seed, p->step, kk, 6, p->f_pair)) break;
       or_child e, pos;
       for (int d = 0; d < 3; ++d) {
         e.x[d] = x[d];
@@ -562,7 +584,7 @@ static void or_photon_advance(const or_tables *t, or_store *st, int64_t j, const
         e.p[d] = r1 * k[d];
         pos.p[d] = (1.0 - r1) * k[d];
       }
-      e.w = pos.w = st->w[j];
+      e.w = pos.w = st->w[j] * or_generator_weight(p->f_pair);
       e.parent = pos.parent = id;
       e.birth = pos.birth = (uint32_t)(((uint64_t)(p->step + 1) << 14) | (uint32_t)kk);
       e.id = or_child_id(id, p->seed, p->step, kk, 2);
@@ -572,7 +594,6 @@ static void or_photon_advance(const or_tables *t, or_store *st, int64_t j, const
       or_push_child(cb, &e);
       or_push_child(cb, &pos);
       s->pairs++;
-      dead = 1;
       break;
     }
   }

@@ -65,6 +65,14 @@ typedef struct {
   int backend;
   uint64_t seed;
   int64_t step;
+  /* Tunable generator factors f_g of Sec. VI for photon emission and pair creation (a value
+   * of at most 1 means off).  The event still acts on its parent every time it fires (the
+   * lepton recoils, the photon decays); the children of that event are created only with
+   * probability 1/f_g, decided by the Philox draw keyed by the parent's id with counter
+   * (step, substep | purpose << 16, seed lo, seed hi), purpose 5 (photon) or 6 (pair), first
+   * two words as the uniform u, created iff u < 1/f_g, and then carry f_g times the
+   * parent's weight. */
+  double f_photon, f_pair;
 } or_params;
 
 typedef struct {
