@@ -173,6 +173,14 @@ typedef struct {
                            lepton kernel ([0], [1]) and the photon bound kernel ([2], [3]),
                            for timing those two kernels alone; NULL entries are skipped.
                            Owned by the caller. */
+  double f_photon;      /* tunable generator factors f_g of Sec. VI for photon emission and */
+  double f_pair;        /* pair creation; a value <= 1 means off.  An event still acts on its
+                           parent every time it fires (the lepton recoils, the photon decays);
+                           its children are created only with probability 1/f_g (a Philox draw
+                           keyed by the parent id, counter (step, sub-step | p << 16, seed),
+                           p = 5 for photons, 6 for pairs; first two words as the uniform u,
+                           created iff u < 1/f_g) and carry f_g times the parent's weight.
+                           Must be finite. */
 } qed_params;
 
 /* Per-step record written by qed_step (device memory). */

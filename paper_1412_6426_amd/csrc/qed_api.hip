@@ -121,6 +121,7 @@ qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_fi
   const bool run_photons = P.pairs || P.push_photons;
   if ((P.emission || run_photons) && !soa_ok(stores->species[QED_PHOTON], false))
     return QED_ERR_ARG;
+  if (!isfinite(P.f_photon) || !isfinite(P.f_pair)) return QED_ERR_ARG;
   if (!finite_pos(P.dt) || !finite_pos(P.eps_r) || !finite_pos(P.kappa) || !isfinite(P.t0))
     return QED_ERR_ARG;
   if (P.precision != QED_FP64 && P.precision != QED_MIXED) return QED_ERR_ARG;
@@ -175,6 +176,10 @@ qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_fi
   a.inv_lep_scale = 1.0 / (P.kappa * 28.0 * kPi * P.eps_r);
   a.inv_pho_scale = 1.0 / (P.kappa * 260.0 * kPi * P.eps_r);
   a.dtfac_per_h = kAlpha / P.eps_r;
+  a.fg_photon = P.f_photon > 1.0 ? P.f_photon : 1.0;
+  a.inv_fg_photon = 1.0 / a.fg_photon;
+  a.fg_pair = P.f_pair > 1.0 ? P.f_pair : 1.0;
+  a.inv_fg_pair = 1.0 / a.fg_pair;
   a.adaptive = P.adaptive;
   a.forced = P.forced_substeps;
   a.emission = P.emission;

@@ -73,7 +73,8 @@ __device__ __forceinline__ float uniform32(uint32_t hi) {
 // Counter layout shared by the event draw and the child ids:
 //   key = particle id, counter = (step, sub-step | purpose << 16, seed lo, seed hi).
 enum Purpose : uint32_t {
-  kDraw = 0, kPhotonChild = 1, kElectronChild = 2, kPositronChild = 3, kThin = 4
+  kDraw = 0, kPhotonChild = 1, kElectronChild = 2, kPositronChild = 3, kThin = 4,
+  kGenPhoton = 5, kGenPair = 6  // generator-factor draws (Sec. VI)
 };
 
 __device__ __forceinline__ uint4 draw_words(uint64_t id, uint64_t seed, uint32_t step, uint32_t sub,
@@ -92,6 +93,15 @@ __device__ __forceinline__ uint64_t child_id(uint64_t parent, uint64_t seed, uin
 
 __device__ __forceinline__ uint32_t birth_code(uint32_t step, uint32_t sub) {
   return ((step + 1u) << 14) | sub;
+}
+
+// Tunable generator factor (Sec. VI): does the generator that fired for `parent` at this
+// sub-step create its children?  Probability inv_fg = 1 / f_g, from the parent's own draw
+// for `purpose` (kGenPhoton, kGenPair), independent of the event's (r1, r2).
+__device__ __forceinline__ bool generator_runs(uint64_t parent, uint64_t seed, uint32_t step,
+                                               uint32_t sub, uint32_t purpose, double inv_fg) {
+  const uint4 o = draw_words(parent, seed, step, sub, purpose);
+  return uniform64(o.x, o.y) < inv_fg;
 }
 
 // ------------------------------------------------------------------------------------

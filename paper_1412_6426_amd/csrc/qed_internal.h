@@ -166,6 +166,8 @@ struct StepArgs {
   double inv_lep_scale;  // 1 / (kappa 28 pi eps_r)
   double inv_pho_scale;  // 1 / (kappa 260 pi eps_r)
   double dtfac_per_h;    // alpha / eps_r
+  // generator factors (Sec. VI): fg = f_g when f_g > 1, else 1 (off); inv_fg = 1 / f_g
+  double fg_photon, inv_fg_photon, fg_pair, inv_fg_pair;
   int adaptive, forced, emission, pairs, push_photons, freeze_on_drop;
   long long tile;  // particles per work chunk (0: one chunk per wavefront)
   WorkHdr* hdr;

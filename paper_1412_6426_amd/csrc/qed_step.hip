@@ -727,12 +727,19 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
     }
 
     // ---- emitted photons: into the wavefront's arena share, else staged and reserved ----
-    const uint64_t em = wave_ballot(emit);
+    // With a generator factor f_g (Sec. VI) the photon of an event is created with
+    // probability 1 / f_g and carries f_g times the lepton's weight; the recoil below
+    // happens at every event.
+    bool child = emit;
+    if (emit && a.fg_photon > 1.0)
+      child = generator_runs(id, seed, step, (uint32_t)k, kGenPhoton, a.inv_fg_photon);
+    const double cw = wgt * a.fg_photon;
+    const uint64_t em = wave_ballot(child);
     if (em && nrec + __popcll(em) <= pa.per_wave) {
       const int n_new = __popcll(em);
       wc.events += n_new;
-      tally.add(pa, wid, em, emit, inst);
-      if (emit) {
+      tally.add(pa, wid, em, child, inst);
+      if (child) {
         const long long r = rbase + nrec + __popcll(em & below);
         pa.x[r] = x.x;
         pa.y[r] = x.y;
@@ -740,7 +747,7 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
         pa.px[r] = f * p.x;
         pa.py[r] = f * p.y;
         pa.pz[r] = f * p.z;
-        pa.w[r] = wgt;
+        pa.w[r] = cw;
         pa.parent[r] = id;
         pa.sub[r] = (unsigned)k;
         pa.inst[r] = (unsigned)inst;
@@ -754,21 +761,21 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
         staged = 0;
       }
       if (n_new > kStageCap) {
-        wave_append<QED_PHOTON>(a, emit, inst, cnt, [&](const qed_soa& o, long long s) {
+        wave_append<QED_PHOTON>(a, child, inst, cnt, [&](const qed_soa& o, long long s) {
           o.x[s] = x.x;
           o.y[s] = x.y;
           o.z[s] = x.z;
           o.px[s] = f * p.x;
           o.py[s] = f * p.y;
           o.pz[s] = f * p.z;
-          o.w[s] = wgt;
+          o.w[s] = cw;
           o.id[s] = child_id(id, seed, step, (uint32_t)k, kPhotonChild);
           o.parent[s] = id;
           o.birth[s] = birth_code(step, (uint32_t)k);
           if (o.n_events) o.n_events[s] = 0u;
         });
       } else {
-        if (emit) {
+        if (child) {
           const int r = staged + __popcll(em & below);
           sg.x[r] = x.x;
           sg.y[r] = x.y;
@@ -776,7 +783,7 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
           sg.px[r] = f * p.x;
           sg.py[r] = f * p.y;
           sg.pz[r] = f * p.z;
-          sg.w[r] = wgt;
+          sg.w[r] = cw;
           sg.id[r] = child_id(id, seed, step, (uint32_t)k, kPhotonChild);
           sg.parent[r] = id;
           sg.birth[r] = birth_code(step, (uint32_t)k);
@@ -1097,8 +1104,8 @@ __device__ __forceinline__ void exact_batch(const StepArgs& a, ExactCtx& c, Pair
   const uint64_t below = lanes_below();
   const qed_soa& S = a.sp[QED_PHOTON];
   const long long i = i0 + lane_id();
-  bool pair = false;
-  double r1 = 0.0;
+  bool pair = false, make = false;
+  double r1 = 0.0, wp = 0.0;
   int kpair = 0, inst = 0;
   long long s = 0;
   V3 x{}, kv{};
@@ -1146,17 +1153,25 @@ __device__ __forceinline__ void exact_batch(const StepArgs& a, ExactCtx& c, Pair
       S.y[s] = x.y;
       S.z[s] = x.z;
     }
-    if (pair) S.id[s] = QED_ID_DEAD;
+    if (pair) {
+      // the photon decays at every event; with a generator factor f_g (Sec. VI) the pair is
+      // created with probability 1 / f_g and carries f_g times the photon's weight
+      S.id[s] = QED_ID_DEAD;
+      make = a.fg_pair > 1.0
+                 ? generator_runs(id, seed, c.step, (uint32_t)kpair, kGenPair, a.inv_fg_pair)
+                 : true;
+      wp = S.w[s] * a.fg_pair;
+    }
   }
-  const uint64_t pm = wave_ballot(pair);
+  const uint64_t pm = wave_ballot(make);
   if (!pm) return;
   const int n_new = __popcll(pm);
   wc.events += n_new;
   const ChildArena& qa = a.qa;
   if (c.nrec + n_new <= qa.per_wave) {
     // ---- pair records into the wavefront's arena share ----
-    c.tally.add(qa, c.wid, pm, pair, inst);
-    if (pair) {
+    c.tally.add(qa, c.wid, pm, make, inst);
+    if (make) {
       const long long r = (long long)c.wid * qa.per_wave + c.nrec + __popcll(pm & below);
       qa.x[r] = x.x;
       qa.y[r] = x.y;
@@ -1165,7 +1180,7 @@ __device__ __forceinline__ void exact_batch(const StepArgs& a, ExactCtx& c, Pair
       qa.py[r] = kv.y;
       qa.pz[r] = kv.z;
       qa.r1[r] = r1;
-      qa.w[r] = S.w[s];
+      qa.w[r] = wp;
       qa.parent[r] = id;
       qa.sub[r] = (unsigned)kpair;
       qa.inst[r] = (unsigned)inst;
@@ -1178,7 +1193,7 @@ __device__ __forceinline__ void exact_batch(const StepArgs& a, ExactCtx& c, Pair
     flush_pairs(a, ps, c.staged, c.step, cnt);
     c.staged = 0;
   }
-  if (pair) {
+  if (make) {
     const int r = c.staged + __popcll(pm & below);
     ps.x[r] = x.x;
     ps.y[r] = x.y;
@@ -1187,7 +1202,7 @@ __device__ __forceinline__ void exact_batch(const StepArgs& a, ExactCtx& c, Pair
     ps.ky[r] = kv.y;
     ps.kz[r] = kv.z;
     ps.r1[r] = r1;
-    ps.w[r] = S.w[s];
+    ps.w[r] = wp;
     ps.parent[r] = id;
     ps.sub[r] = (unsigned)kpair;
     ps.inst[r] = inst;

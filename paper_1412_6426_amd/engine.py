@@ -195,8 +195,9 @@ class Engine:
     @staticmethod
     def make_params(dt, eps_r, kappa=1.0, t0=0.0, adaptive=1, forced_substeps=0, emission=1,
                     pairs=1, push_photons=1, precision=Q.QED_FP64, freeze_on_drop=0, tile=0,
-                    block=0, grid_blocks=0) -> Q.qed_params:
+                    block=0, grid_blocks=0, f_photon=1.0, f_pair=1.0) -> Q.qed_params:
         p = Q.qed_params()
+        p.f_photon, p.f_pair = float(f_photon), float(f_pair)
         p.dt, p.eps_r, p.kappa, p.t0 = float(dt), float(eps_r), float(kappa), float(t0)
         p.adaptive, p.forced_substeps = int(adaptive), int(forced_substeps)
         p.emission, p.pairs, p.push_photons = int(emission), int(pairs), int(push_photons)

@@ -63,7 +63,8 @@ class qed_params(C.Structure):
                 ("t0", C.c_double), ("adaptive", C.c_int), ("forced_substeps", C.c_int),
                 ("emission", C.c_int), ("pairs", C.c_int), ("push_photons", C.c_int),
                 ("precision", C.c_int), ("freeze_on_drop", C.c_int), ("tile", C.c_int),
-                ("block", C.c_int), ("grid_blocks", C.c_int), ("events", C.c_void_p * 4)]
+                ("block", C.c_int), ("grid_blocks", C.c_int), ("events", C.c_void_p * 4),
+                ("f_photon", C.c_double), ("f_pair", C.c_double)]
 
 
 class qed_stats(C.Structure):

@@ -108,6 +108,33 @@ def test_rotating_cascade_parity(orc, arena):
     compare_all(e, os_, label="rotating")
 
 
+@pytest.mark.parametrize("arena", ["arena", "no_arena"])
+def test_generator_factor_cascade_parity(orc, arena):
+    """The rotating-E cascade with generator factors f_g = 3 for photons and 2 for pairs
+    (Sec. VI): every store bit-exact against the oracle (weights too: f_g times the
+    parent's), per-step created photons and pairs equal, and fewer photons than events."""
+    w = W.rotating_e(n=300, periods=1.5, capacity=400_000, lepton_capacity=40_000)
+    init = W.rotating_e_initial(300, seed=3)
+    over = dict(f_photon=3.0, f_pair=2.0)
+    _note(f"generator factors {over} ({arena})")
+    e = R.engine_single(w, init, arena_records=ARENA_MODES[arena])
+    stats = R.run(e, R.field_of(w), R.params_of(w, **over), w.n_steps)
+    os_ = oracle_stores(orc, init, w.capacity)
+    ostats = orc.run(os_, oracle_field(orc, w), oracle_params(orc, w, **over), w.n_steps)
+    assert len(stats) == len(ostats) == w.n_steps
+    assert sum(s["pairs"] for s in stats) > 5
+    assert [s["pairs"] for s in stats] == [s["pairs"] for s in ostats]
+    assert [s["emitted"] for s in stats] == [s["emitted"] for s in ostats]
+    compare_all(e, os_, label="generator factors")
+    lep = [e.read(0, s) for s in (0, 1)]
+    events = int(sum(v["n_events"].sum() for v in lep))
+    created = len(e.read(0, 2)["id"])
+    assert created < events  # some events created no photon
+    g = e.read(0, 2)
+    seeds = g["parent"] < np.uint64(300)
+    assert np.all(g["w"][seeds] == 3.0)  # seeds have weight 1
+
+
 def test_forced_substeps_and_nonadaptive(orc):
     w = W.rotating_e(n=97, periods=0.25, capacity=50_000, lepton_capacity=5000)
     init = W.rotating_e_initial(97, seed=9)
