@@ -111,13 +111,13 @@ def make_job(kind, args, precision):
     return w, e, reload
 
 
-def gpu_run(args, precision, kind="rotating", thin=None):
+def gpu_run(args, precision, kind="rotating", thin=None, fg=None):
     """One job three times from the same seeds: a tuning run that picks the launch shape
     per size class (untimed), K steps replayed from one captured graph per chosen shape
     and timed as a whole (value), and K eager steps with HIP events around the lepton and
     photon kernels (per-kernel durations for the roofline).  The three runs compute the
     same thing.  thin = (trigger, target): qed_thin on the photon store after every step
-    (timed with the step)."""
+    (timed with the step).  fg = (f_photon, f_pair): the generator factors of Sec. VI."""
     import numpy as np
     import torch
     from paper_1412_6426_amd import autotune as AT
@@ -128,6 +128,8 @@ def gpu_run(args, precision, kind="rotating", thin=None):
     w, e, reload = make_job(kind, args, precision)
     field = R.field_of(w)
     params = R.params_of(w, freeze_on_drop=1, tile=args.tile, grid_blocks=args.grid_blocks)
+    if fg is not None:
+        params.f_photon, params.f_pair = fg
     K = args.steps if args.steps is not None else w.n_steps
     stream = torch.cuda.Stream()
     sp = stream.cuda_stream
@@ -531,6 +533,18 @@ def main():
             final_counts=rt["final_counts"], pairs=rt["pairs"], emitted=rt["emitted"],
             trigger=int(0.8 * cap), target=int(0.4 * cap),
             eager_matches_graph=rt["eager_matches_graph"])
+        # both cost controls of Sec. VI: photons created with probability 1/4 at four times
+        # the weight, and the same thinning
+        print("bench: rotating-E cascade with f_g = 4 for photons and thinning",
+              file=sys.stderr, flush=True)
+        rf = gpu_run(args, args.precision, thin=(int(0.8 * cap), int(0.4 * cap)),
+                     fg=(4.0, 1.0))
+        line["generator_factor_cascade"] = dict(
+            value=rf["particle_steps"] / (rf["ms"] / 1e3), ms=rf["ms"], steps=rf["steps"],
+            particle_steps=rf["particle_steps"], dropped=rf["dropped"],
+            thin_ms=rf["thin_ms"], lep_ms=rf["lep_ms"], pho_ms=rf["pho_ms"],
+            final_counts=rf["final_counts"], pairs=rf["pairs"], emitted=rf["emitted"],
+            f_photon=4.0, f_pair=1.0, eager_matches_graph=rf["eager_matches_graph"])
     if not args.no_yee:
         print("bench: standing-wave cascade on the Yee grid", file=sys.stderr, flush=True)
         line["standing_wave_grid"] = gpu_run_yee(args, args.precision)
