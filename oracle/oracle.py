@@ -61,7 +61,8 @@ class OrParams(C.Structure):
                 ("t0", C.c_double), ("adaptive", C.c_int), ("forced_substeps", C.c_int),
                 ("emission", C.c_int), ("pairs", C.c_int), ("push_photons", C.c_int),
                 ("backend", C.c_int), ("seed", C.c_uint64), ("step", C.c_int64),
-                ("f_photon", C.c_double), ("f_pair", C.c_double)]
+                ("f_photon", C.c_double), ("f_pair", C.c_double),
+                ("same_step_generations", C.c_int)]
 
 
 class OrStats(C.Structure):
@@ -69,6 +70,7 @@ class OrStats(C.Structure):
                 ("saturated", C.c_int64), ("near_threshold", C.c_int64),
                 ("nsub_near_int", C.c_int64), ("nsub_clamped", C.c_int64),
                 ("nonfinite", C.c_int64), ("substeps", C.c_int64),
+                ("children_advanced", C.c_int64), ("deferred", C.c_int64),
                 ("photon_energy", C.c_double), ("max_p_emit", C.c_double),
                 ("max_p_pair", C.c_double), ("nsub_hist", C.c_int64 * NSUB_HIST)]
 
@@ -365,11 +367,13 @@ class Params:
     step: int = 0
     f_photon: float = 1.0  # generator factors of Sec. VI (<= 1: off)
     f_pair: float = 1.0
+    same_step_generations: int = 0  # children advanced in their birth step, generations
 
     def cstruct(self) -> OrParams:
         p = OrParams()
         for k in ("dt", "eps_r", "kappa", "t0", "adaptive", "forced_substeps", "emission",
-                  "pairs", "push_photons", "backend", "seed", "step", "f_photon", "f_pair"):
+                  "pairs", "push_photons", "backend", "seed", "step", "f_photon", "f_pair",
+                  "same_step_generations"):
             setattr(p, k, getattr(self, k))
         return p
 

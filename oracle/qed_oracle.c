@@ -415,7 +415,18 @@ typedef struct {
   uint64_t id, parent;
   uint32_t birth;
   int species;
+  double tau;        /* rest of the birth step after the event */
+  double E[3], B[3]; /* the parent's frozen fields, inherited */
 } or_child;
+
+/* What a particle is advanced through in this step: the whole step from its state at the
+ * step start, with the fields evaluated once at its position and t_n (Sec. IV.H), or, for a
+ * child in its birth step, the rest of the step with its parent's fields. */
+typedef struct {
+  double T;
+  int inherited;
+  double E[3], B[3];
+} or_span;
 
 typedef struct {
   or_child *v;
@@ -457,6 +468,8 @@ static void or_stats_merge(or_stats *a, const or_stats *b) {
   a->nsub_clamped += b->nsub_clamped;
   a->nonfinite += b->nonfinite;
   a->substeps += b->substeps;
+  a->children_advanced += b->children_advanced;
+  a->deferred += b->deferred;
   a->photon_energy += b->photon_energy;
   if (b->max_p_emit > a->max_p_emit) a->max_p_emit = b->max_p_emit;
   if (b->max_p_pair > a->max_p_pair) a->max_p_pair = b->max_p_pair;
@@ -464,28 +477,35 @@ static void or_stats_merge(or_stats *a, const or_stats *b) {
 }
 
 static void or_lepton_advance(const or_tables *t, or_store *st, int species, int64_t j,
-                              const or_field *f, const or_params *p, double tn, or_childbuf *cb,
-                              or_stats *s) {
+                              const or_field *f, const or_params *p, double tn,
+                              const or_span *span, or_childbuf *cb, or_stats *s) {
   double q = (species == 0) ? -1.0 : 1.0;
   double x[3] = {st->x[j], st->y[j], st->z[j]};
   double mom[3] = {st->px[j], st->py[j], st->pz[j]};
   uint64_t id = st->id[j];
   double E[3], B[3];
-  or_field_at(f, x, tn, E, B); /* once per step (Sec. IV.H) */
+  if (span->inherited) {
+    for (int d = 0; d < 3; ++d) {
+      E[d] = span->E[d];
+      B[d] = span->B[d];
+    }
+  } else {
+    or_field_at(f, x, tn, E, B); /* once per step (Sec. IV.H) */
+  }
   double gamma = sqrt(1.0 + mom[0] * mom[0] + mom[1] * mom[1] + mom[2] * mom[2]);
   double chi = or_chi_lepton(mom, E, B, p->eps_r);
   int nsub = 1, near_int = 0, clamped = 0;
   if (p->forced_substeps > 0) {
     nsub = p->forced_substeps;
   } else if (p->adaptive && chi > 0.0) {
-    nsub = or_substeps(p->dt, or_dtq_lepton(chi, gamma, p->eps_r, p->kappa), &near_int,
+    nsub = or_substeps(span->T, or_dtq_lepton(chi, gamma, p->eps_r, p->kappa), &near_int,
                        &clamped);
   }
   if (!isfinite(chi)) s->nonfinite++;
   s->nsub_near_int += near_int;
   s->nsub_clamped += clamped;
-  s->nsub_hist[nsub < OR_NSUB_HIST ? nsub : OR_NSUB_HIST - 1]++;
-  double h = p->dt / (double)nsub;
+  if (!span->inherited) s->nsub_hist[nsub < OR_NSUB_HIST ? nsub : OR_NSUB_HIST - 1]++;
+  double h = span->T / (double)nsub;
   double dtfac = h * OR_ALPHA / p->eps_r;
   uint32_t nev = st->n_events ? st->n_events[j] : 0;
   for (int k = 0; k < nsub; ++k) {
@@ -522,6 +542,11 @@ static void or_lepton_advance(const or_tables *t, or_store *st, int species, int
         c.parent = id;
         c.birth = (uint32_t)(((uint64_t)(p->step + 1) << 14) | (uint32_t)k);
         c.species = 2;
+        c.tau = (double)(nsub - k - 1) * h;
+        for (int d = 0; d < 3; ++d) {
+          c.E[d] = E[d];
+          c.B[d] = B[d];
+        }
         or_push_child(cb, &c);
         s->emitted++;
       }
@@ -537,7 +562,8 @@ static void or_lepton_advance(const or_tables *t, or_store *st, int species, int
 }
 
 static void or_photon_advance(const or_tables *t, or_store *st, int64_t j, const or_field *f,
-                              const or_params *p, double tn, or_childbuf *cb, or_stats *s) {
+                              const or_params *p, double tn, const or_span *span,
+                              or_childbuf *cb, or_stats *s) {
   uint64_t id = st->id[j];
   if (id == OR_ID_DEAD) return;
   double x[3] = {st->x[j], st->y[j], st->z[j]};
@@ -548,19 +574,26 @@ static void or_photon_advance(const or_tables *t, or_store *st, int64_t j, const
     return;
   }
   double E[3], B[3];
-  or_field_at(f, x, tn, E, B);
+  if (span->inherited) {
+    for (int d = 0; d < 3; ++d) {
+      E[d] = span->E[d];
+      B[d] = span->B[d];
+    }
+  } else {
+    or_field_at(f, x, tn, E, B);
+  }
   double chi_g = or_chi_photon(k, E, B, p->eps_r);
   int nsub = 1, near_int = 0, clamped = 0;
   if (p->forced_substeps > 0) {
     nsub = p->forced_substeps;
   } else if (p->adaptive && chi_g > 0.0) {
-    nsub = or_substeps(p->dt, or_dtq_photon(chi_g, kabs, p->eps_r, p->kappa), &near_int,
+    nsub = or_substeps(span->T, or_dtq_photon(chi_g, kabs, p->eps_r, p->kappa), &near_int,
                        &clamped);
   }
   if (!isfinite(chi_g)) s->nonfinite++;
   s->nsub_near_int += near_int;
   s->nsub_clamped += clamped;
-  double h = p->dt / (double)nsub;
+  double h = span->T / (double)nsub;
   double dtfac = h * OR_ALPHA / p->eps_r;
   int dead = 0;
   for (int kk = 0; kk < nsub; ++kk) {
@@ -591,6 +624,11 @@ static void or_photon_advance(const or_tables *t, or_store *st, int64_t j, const
       pos.id = or_child_id(id, p->seed, p->step, kk, 3);
       e.species = 0;
       pos.species = 1;
+      e.tau = pos.tau = (double)(nsub - kk - 1) * h;
+      for (int d = 0; d < 3; ++d) {
+        e.E[d] = pos.E[d] = E[d];
+        e.B[d] = pos.B[d] = B[d];
+      }
       or_push_child(cb, &e);
       or_push_child(cb, &pos);
       s->pairs++;
@@ -603,11 +641,12 @@ static void or_photon_advance(const or_tables *t, or_store *st, int64_t j, const
   if (dead) st->id[j] = OR_ID_DEAD;
 }
 
-static void or_append(or_store *st, const or_child *c, or_stats *s) {
+/* Appends a child to its store; returns its slot, or -1 when the store is full. */
+static int64_t or_append(or_store *st, const or_child *c, or_stats *s) {
   or_store *d = &st[c->species];
   if (d->count >= d->capacity) {
     s->dropped++;
-    return;
+    return -1;
   }
   int64_t i = d->count++;
   d->x[i] = c->x[0];
@@ -621,6 +660,50 @@ static void or_append(or_store *st, const or_child *c, or_stats *s) {
   d->parent[i] = c->parent;
   d->birth[i] = c->birth;
   if (d->n_events) d->n_events[i] = 0;
+  return i;
+}
+
+/* A child appended in this step that is still to be advanced through the rest of it. */
+typedef struct {
+  int species;
+  int64_t slot;
+  or_span span;
+} or_pending;
+
+/* Appends every thread's children in thread order.  With `next` non-NULL the appended
+ * children with time left in the step are listed there; `*n_next` counts them. */
+static int or_append_all(or_store *st, or_childbuf *bufs, int nthreads, or_stats *s,
+                         or_pending **next, int64_t *n_next) {
+  int64_t total = 0, m = 0;
+  for (int i = 0; i < nthreads; ++i) total += bufs[i].n;
+  or_pending *list = NULL;
+  if (next && total > 0) {
+    list = (or_pending *)malloc(sizeof(or_pending) * (size_t)total);
+    if (!list) return -1;
+  }
+  for (int i = 0; i < nthreads; ++i) {
+    for (int64_t c = 0; c < bufs[i].n; ++c) {
+      const or_child *ch = &bufs[i].v[c];
+      int64_t slot = or_append(st, ch, s);
+      if (list && slot >= 0 && ch->tau > 0.0) {
+        or_pending *q = &list[m++];
+        q->species = ch->species;
+        q->slot = slot;
+        q->span.T = ch->tau;
+        q->span.inherited = 1;
+        for (int d = 0; d < 3; ++d) {
+          q->span.E[d] = ch->E[d];
+          q->span.B[d] = ch->B[d];
+        }
+      }
+    }
+    bufs[i].n = 0;
+  }
+  if (next) {
+    *next = list;
+    *n_next = m;
+  }
+  return 0;
 }
 
 int or_step(const or_tables *t, or_store *st, const or_field *f, const or_params *p,
@@ -628,6 +711,8 @@ int or_step(const or_tables *t, or_store *st, const or_field *f, const or_params
   memset(s, 0, sizeof(*s));
   const int64_t n0[3] = {st[0].count, st[1].count, st[2].count};
   const double tn = p->t0 + (double)p->step * p->dt;
+  const int G = p->same_step_generations > 0 ? p->same_step_generations : 0;
+  const int photons = p->push_photons || p->pairs;
   int nthreads = 1;
 #ifdef _OPENMP
   nthreads = omp_get_max_threads();
@@ -635,6 +720,8 @@ int or_step(const or_tables *t, or_store *st, const or_field *f, const or_params
   or_childbuf *bufs = (or_childbuf *)calloc((size_t)nthreads, sizeof(or_childbuf));
   or_stats *ts = (or_stats *)calloc((size_t)nthreads, sizeof(or_stats));
   if (!bufs || !ts) return -1;
+  const or_span whole = {p->dt, 0, {0, 0, 0}, {0, 0, 0}};
+  /* the particles alive at the step start, through the whole step */
 #pragma omp parallel num_threads(nthreads)
   {
     int tid = 0;
@@ -644,22 +731,57 @@ int or_step(const or_tables *t, or_store *st, const or_field *f, const or_params
     for (int sp = 0; sp < 2; ++sp) {
 #pragma omp for schedule(static)
       for (int64_t j = 0; j < n0[sp]; ++j)
-        or_lepton_advance(t, &st[sp], sp, j, f, p, tn, &bufs[tid], &ts[tid]);
+        or_lepton_advance(t, &st[sp], sp, j, f, p, tn, &whole, &bufs[tid], &ts[tid]);
     }
-    if (p->push_photons || p->pairs) {
+    if (photons) {
 #pragma omp for schedule(static)
       for (int64_t j = 0; j < n0[2]; ++j)
-        or_photon_advance(t, &st[2], j, f, p, tn, &bufs[tid], &ts[tid]);
+        or_photon_advance(t, &st[2], j, f, p, tn, &whole, &bufs[tid], &ts[tid]);
     }
   }
   for (int i = 0; i < nthreads; ++i) {
     or_stats_merge(s, &ts[i]);
-    for (int64_t c = 0; c < bufs[i].n; ++c) or_append(st, &bufs[i].v[c], s);
-    free(bufs[i].v);
+    memset(&ts[i], 0, sizeof(or_stats));
   }
+  or_pending *list = NULL;
+  int64_t n_list = 0;
+  int rc = or_append_all(st, bufs, nthreads, s, G > 0 ? &list : NULL, &n_list);
+  /* children through the rest of their birth step, one generation at a time */
+  for (int g = 1; rc == 0 && g <= G && n_list > 0; ++g) {
+    s->children_advanced += n_list;
+#pragma omp parallel num_threads(nthreads)
+    {
+      int tid = 0;
+#ifdef _OPENMP
+      tid = omp_get_thread_num();
+#endif
+#pragma omp for schedule(static)
+      for (int64_t c = 0; c < n_list; ++c) {
+        const or_pending *q = &list[c];
+        if (q->species == 2) {
+          if (photons)
+            or_photon_advance(t, &st[2], q->slot, f, p, tn, &q->span, &bufs[tid], &ts[tid]);
+        } else {
+          or_lepton_advance(t, &st[q->species], q->species, q->slot, f, p, tn, &q->span,
+                            &bufs[tid], &ts[tid]);
+        }
+      }
+    }
+    for (int i = 0; i < nthreads; ++i) {
+      or_stats_merge(s, &ts[i]);
+      memset(&ts[i], 0, sizeof(or_stats));
+    }
+    free(list);
+    list = NULL;
+    n_list = 0;
+    rc = or_append_all(st, bufs, nthreads, s, &list, &n_list);
+    if (g == G) s->deferred += n_list; /* generation G + 1: advanced from the next step */
+  }
+  free(list);
+  for (int i = 0; i < nthreads; ++i) free(bufs[i].v);
   free(bufs);
   free(ts);
-  return 0;
+  return rc;
 }
 
 /* ------------------------------------------------------------------------------------

@@ -73,11 +73,20 @@ typedef struct {
    * two words as the uniform u, created iff u < 1/f_g, and then carry f_g times the
    * parent's weight. */
   double f_photon, f_pair;
+  /* Children in their birth step (Sec. IV.H: several events per iteration).  0: children
+   * join the store and are first advanced at the next step.  G > 0: a child born at
+   * sub-step k of a parent advanced through T with n_sub sub-steps is advanced in the same
+   * step through the rest of it, tau = (n_sub - k - 1) (T / n_sub), with the parent's frozen
+   * E, B, its own n_sub over tau, and its own events; children of children likewise, up to G
+   * generations.  Children of generation G + 1 wait for the next step. */
+  int same_step_generations;
 } or_params;
 
 typedef struct {
   int64_t emitted, pairs, dropped, saturated, near_threshold, nsub_near_int, nsub_clamped,
       nonfinite, substeps;
+  int64_t children_advanced; /* children advanced in their birth step (tau > 0) */
+  int64_t deferred;          /* children of generation G + 1 with tau > 0, left for the next step */
   double photon_energy, max_p_emit, max_p_pair;
   int64_t nsub_hist[OR_NSUB_HIST];
 } or_stats;
