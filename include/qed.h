@@ -181,6 +181,15 @@ typedef struct {
                            p = 5 for photons, 6 for pairs; first two words as the uniform u,
                            created iff u < 1/f_g) and carry f_g times the parent's weight.
                            Must be finite. */
+  int same_step_generations; /* children in their birth step (Sec. IV.H: several events per
+                           step).  0: children join the stores and are first advanced at
+                           step n+1.  G in 1..64: a child born at sub-step k of a parent
+                           advanced through T in n_sub sub-steps is advanced in the same step
+                           through tau = (n_sub - k - 1) (T / n_sub), with the parent's
+                           frozen E, B and its own n_sub over tau; its children likewise, up
+                           to G generations (generation G + 1 waits for step n+1).  Needs
+                           child arenas (at most 1024 instances, arena space in the
+                           workspace, sized with same_step set in qed_work_bytes). */
 } qed_params;
 
 /* Per-step record written by qed_step (device memory). */
@@ -200,10 +209,15 @@ typedef struct {
   int64_t wave_iters;           /* lepton-kernel wavefront iterations */
   int64_t low_occupancy_iters;  /* of which fewer than half the lanes held a particle */
   int64_t early_out;            /* photon decisions settled by the pair-rate bound */
+  int64_t children_advanced;    /* children advanced in their birth step (time left > 0) */
+  int64_t deferred;             /* children with time left in their birth step that wait
+                                   for the next step: generation G + 1, or children whose
+                                   wavefront's arena share was full */
   double photon_energy;         /* sum of w * eps of the emitted photons */
   double max_p_emit;            /* largest evaluated emission probability */
   double max_p_pair;            /* largest evaluated pair probability */
-  int64_t nsub_hist[QED_NSUB_HIST];          /* leptons per n_sub (last bin: >= 31) */
+  int64_t nsub_hist[QED_NSUB_HIST];          /* particles alive at the step start per n_sub
+                                                (leptons; last bin: >= 31) */
   int64_t photon_hist[QED_SPECTRUM_BINS];    /* emitted photons per log10(eps) bin */
   uint32_t status;              /* QED_STATUS_* bits */
   uint32_t reserved;
@@ -216,17 +230,25 @@ typedef struct {
  * the photons (and pair records, a quarter of arena_records) it creates into its own share
  * of an arena, and after the particle kernels a scan and a copy kernel move them into the
  * stores, so no wavefront reserves store slots on a shared counter.  A wavefront whose
- * share is full reserves slots directly (correct, slower).  arena_records = 0 gives the
- * smallest valid workspace.  Returns 0 for n_instances < 1 or negative sizes. */
-size_t qed_work_bytes(int n_instances, int64_t photon_slots, int64_t arena_records);
+ * share is full reserves slots directly (correct, slower).  same_step nonzero adds what
+ * same-step processing of children needs: per record the time left in the step, the
+ * parent's fields and the children's slots (64 more bytes a photon record, 72 a pair
+ * record), a second set of arenas for alternating generations, and partial statistics.
+ * arena_records = 0 gives the smallest valid workspace.  Returns 0 for n_instances < 1 or
+ * negative sizes. */
+size_t qed_work_bytes(int n_instances, int64_t photon_slots, int64_t arena_records,
+                      int same_step);
 
 /* One global step n = *d_step of every non-frozen instance (Sec. IV.H):
  *   for each lepton and photon alive at the step start: fields at the start position
  *   (once per step), chi, n_sub, then n_sub times {push, chi, one event decision}; children
- *   are appended at the end of their instance's segment and are processed from step n+1.
+ *   are appended at the end of their instance's segment and are processed from step n+1,
+ *   or, with params->same_step_generations > 0, also through the rest of step n.
  * Increments *d_step and overwrites *d_stats.  d_work: at least
- * qed_work_bytes(n_instances, stores->slots[QED_PHOTON], 0) bytes, 256-byte aligned; the
- * largest child arena that fits in work_bytes is used.  The order in which children land
+ * qed_work_bytes(n_instances, stores->slots[QED_PHOTON], 0, same_step) bytes, 256-byte
+ * aligned, same_step = (params->same_step_generations > 0); the largest child arena that
+ * fits in work_bytes is used.  QED_ERR_UNSUPPORTED for same-step processing without child
+ * arenas (more than 1024 instances, or no arena space).  The order in which children land
  * in a store follows the work distribution (instance, wavefront, creation order) and does
  * not depend on timing when the arenas are in use.
  * QED_ERR_ARG on null or inconsistent arguments.  If d_tables does not hold built tables

@@ -671,10 +671,11 @@ typedef struct {
 } or_pending;
 
 /* Appends every thread's children in thread order.  With `next` non-NULL the appended
- * children with time left in the step are listed there; `*n_next` counts them. */
+ * children with time left in the step are listed there; `*n_next` counts them, and
+ * `*n_later` counts every child created with time left (appended or dropped). */
 static int or_append_all(or_store *st, or_childbuf *bufs, int nthreads, or_stats *s,
-                         or_pending **next, int64_t *n_next) {
-  int64_t total = 0, m = 0;
+                         or_pending **next, int64_t *n_next, int64_t *n_later) {
+  int64_t total = 0, m = 0, later = 0;
   for (int i = 0; i < nthreads; ++i) total += bufs[i].n;
   or_pending *list = NULL;
   if (next && total > 0) {
@@ -684,6 +685,7 @@ static int or_append_all(or_store *st, or_childbuf *bufs, int nthreads, or_stats
   for (int i = 0; i < nthreads; ++i) {
     for (int64_t c = 0; c < bufs[i].n; ++c) {
       const or_child *ch = &bufs[i].v[c];
+      if (ch->tau > 0.0) ++later;
       int64_t slot = or_append(st, ch, s);
       if (list && slot >= 0 && ch->tau > 0.0) {
         or_pending *q = &list[m++];
@@ -703,6 +705,7 @@ static int or_append_all(or_store *st, or_childbuf *bufs, int nthreads, or_stats
     *next = list;
     *n_next = m;
   }
+  if (n_later) *n_later = later;
   return 0;
 }
 
@@ -744,8 +747,8 @@ int or_step(const or_tables *t, or_store *st, const or_field *f, const or_params
     memset(&ts[i], 0, sizeof(or_stats));
   }
   or_pending *list = NULL;
-  int64_t n_list = 0;
-  int rc = or_append_all(st, bufs, nthreads, s, G > 0 ? &list : NULL, &n_list);
+  int64_t n_list = 0, n_later = 0;
+  int rc = or_append_all(st, bufs, nthreads, s, G > 0 ? &list : NULL, &n_list, &n_later);
   /* children through the rest of their birth step, one generation at a time */
   for (int g = 1; rc == 0 && g <= G && n_list > 0; ++g) {
     s->children_advanced += n_list;
@@ -774,8 +777,8 @@ int or_step(const or_tables *t, or_store *st, const or_field *f, const or_params
     free(list);
     list = NULL;
     n_list = 0;
-    rc = or_append_all(st, bufs, nthreads, s, &list, &n_list);
-    if (g == G) s->deferred += n_list; /* generation G + 1: advanced from the next step */
+    rc = or_append_all(st, bufs, nthreads, s, &list, &n_list, &n_later);
+    if (g == G) s->deferred += n_later; /* generation G + 1: advanced from the next step */
   }
   free(list);
   for (int i = 0; i < nthreads; ++i) free(bufs[i].v);

@@ -86,7 +86,8 @@ typedef struct {
   int64_t emitted, pairs, dropped, saturated, near_threshold, nsub_near_int, nsub_clamped,
       nonfinite, substeps;
   int64_t children_advanced; /* children advanced in their birth step (tau > 0) */
-  int64_t deferred;          /* children of generation G + 1 with tau > 0, left for the next step */
+  int64_t deferred;          /* children of generation G + 1 created with tau > 0 (dropped ones
+                                included), left for the next step */
   double photon_energy, max_p_emit, max_p_pair;
   int64_t nsub_hist[OR_NSUB_HIST];
 } or_stats;

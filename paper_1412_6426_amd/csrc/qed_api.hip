@@ -68,16 +68,20 @@ qed_status qed_build_tables(void* d_tables, size_t bytes, void* stream) {
   return e == hipSuccess ? QED_OK : QED_ERR_HIP;
 }
 
-size_t qed_work_bytes(int n_instances, int64_t photon_slots, int64_t arena_records) {
+size_t qed_work_bytes(int n_instances, int64_t photon_slots, int64_t arena_records,
+                      int same_step) {
   if (n_instances < 1 || photon_slots < 0 || arena_records < 0) return 0;
-  return WorkLayout::make(n_instances, photon_slots, arena_records).total;
+  return WorkLayout::make(n_instances, photon_slots, arena_records, same_step != 0).total;
 }
 
 namespace {
 
-// Column pointers of a child arena inside the workspace.
-ChildArena arena_at(uint8_t* w, size_t cols, size_t cnt, size_t nrec, size_t base, long long cap,
-                    bool pair, int n_inst, int waves) {
+// Column pointers of a child arena inside the workspace, as seen by a producing kernel of
+// `waves` wavefronts: half the records are the wavefronts' shares (a multiple of 64 each),
+// the rest a pool of chunks.  same_step: the layout has the same-step columns;
+// use_same_step: point at them (else they stay null).
+ChildArena arena_at(uint8_t* w, size_t cols, size_t cnt, size_t nrec, size_t base, size_t chain,
+                    long long cap, bool pair, int waves, bool same_step, bool use_same_step) {
   ChildArena A{};
   if (cap <= 0 || waves <= 0) return A;
   const size_t col8 = ((size_t)cap * 8 + 255) & ~(size_t)255;
@@ -93,12 +97,28 @@ ChildArena arena_at(uint8_t* w, size_t cols, size_t cnt, size_t nrec, size_t bas
   A.sub = reinterpret_cast<unsigned int*>(p);
   p += col4;
   A.inst = reinterpret_cast<unsigned int*>(p);
+  p += col4;
+  if (same_step && use_same_step) {
+    A.tau = reinterpret_cast<double*>(p);
+    p += col8;
+    A.fe = reinterpret_cast<double*>(p);
+    p += 6 * col8;
+    A.slot = reinterpret_cast<long long*>(p);
+    p += col8;
+    if (pair) A.slot2 = reinterpret_cast<long long*>(p);
+  }
+  A.cap = cap;
   A.cnt = reinterpret_cast<unsigned int*>(w + cnt);
   A.nrec = reinterpret_cast<unsigned int*>(w + nrec);
   A.base = reinterpret_cast<long long*>(w + base);
+  A.used = reinterpret_cast<unsigned int*>(w + chain);
+  A.first = reinterpret_cast<unsigned int*>(w + chain + 256);
+  A.next = reinterpret_cast<unsigned int*>(w + chain + 256 +
+                                           ((sizeof(unsigned int) * kMaxWaves + 255) & ~(size_t)255));
   A.waves = waves;
-  A.per_wave = cap / waves;
-  (void)n_inst;
+  A.per_wave = ((cap / 2) / waves) & ~63ll;
+  A.pool0 = A.per_wave * waves;
+  A.nchunks = (cap - A.pool0) / kArenaChunk;
   return A;
 }
 
@@ -113,7 +133,10 @@ qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_fi
   const int ni = stores->n_instances;
   if (ni < 1 || !stores->d_instances) return QED_ERR_ARG;
   if (stores->slots[0] < 0 || stores->slots[1] < 0 || stores->slots[2] < 0) return QED_ERR_ARG;
-  if (work_bytes < qed_work_bytes(ni, stores->slots[QED_PHOTON], 0) ||
+  const int G = P.same_step_generations;
+  if (G < 0 || G > kMaxGenerations) return QED_ERR_ARG;
+  const int ss = G > 0 ? 1 : 0;
+  if (work_bytes < qed_work_bytes(ni, stores->slots[QED_PHOTON], 0, ss) ||
       (reinterpret_cast<uintptr_t>(d_work) & 255u))
     return QED_ERR_ARG;
   if (!soa_ok(stores->species[QED_ELECTRON], true) || !soa_ok(stores->species[QED_POSITRON], true))
@@ -190,20 +213,23 @@ qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_fi
   // the largest child arena the workspace holds (sizes are monotonic in the record count)
   long long arena = 0;
   if (ni <= kArenaMaxInstances &&
-      work_bytes >= qed_work_bytes(ni, stores->slots[QED_PHOTON], 1024)) {
+      work_bytes >= qed_work_bytes(ni, stores->slots[QED_PHOTON], 1024, ss)) {
     long long lo = 1024, hi = 1024;
     // record offsets are 32-bit: at most 2^31 records per arena
-    while (work_bytes >= qed_work_bytes(ni, stores->slots[QED_PHOTON], hi * 2) && hi < (1ll << 30))
+    while (work_bytes >= qed_work_bytes(ni, stores->slots[QED_PHOTON], hi * 2, ss) &&
+           hi < (1ll << 30))
       hi *= 2;
     long long top = hi * 2;
     while (top - lo > 1) {  // largest r in [lo, top) with work_bytes >= size(r)
       const long long mid = lo + (top - lo) / 2;
-      if (work_bytes >= qed_work_bytes(ni, stores->slots[QED_PHOTON], mid)) lo = mid;
+      if (work_bytes >= qed_work_bytes(ni, stores->slots[QED_PHOTON], mid, ss)) lo = mid;
       else top = mid;
     }
     arena = lo;
   }
-  const WorkLayout L = WorkLayout::make(ni, stores->slots[QED_PHOTON], arena);
+  // same-step processing moves children through the arenas
+  if (G > 0 && arena == 0) return QED_ERR_UNSUPPORTED;
+  const WorkLayout L = WorkLayout::make(ni, stores->slots[QED_PHOTON], arena, ss != 0);
   uint8_t* w = static_cast<uint8_t*>(d_work);
   a.hdr = reinterpret_cast<WorkHdr*>(w);
   a.n0 = reinterpret_cast<long long*>(w + L.n0);
@@ -238,10 +264,24 @@ qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_fi
   a.cand_per_wave = (long long)((stores->slots[QED_PHOTON] > 0 ? stores->slots[QED_PHOTON] : 1) +
                                 (long long)kMaxWaves * kCandSlack) / pho_waves;
   if (arena > 0) {
-    a.pa = arena_at(w, L.ph_cols, L.ph_cnt, L.ph_nrec, L.ph_base, L.ph_cap, false, ni, lep_waves);
+    const bool on = G > 0;
+    a.pa = arena_at(w, L.ph_cols[0], L.ph_cnt[0], L.ph_nrec[0], L.ph_base[0], L.ph_chain[0],
+                    L.ph_cap, false, lep_waves, L.same_step, on);
     if (a.ex_grid > 0)
-      a.qa = arena_at(w, L.pr_cols, L.pr_cnt, L.pr_nrec, L.pr_base, L.pr_cap, true, ni,
-                      a.ex_grid * 4);
+      a.qa = arena_at(w, L.pr_cols[0], L.pr_cnt[0], L.pr_nrec[0], L.pr_base[0], L.pr_chain[0],
+                      L.pr_cap, true, a.ex_grid * 4, L.same_step, on);
+    if (on) {
+      a.generations = G;
+      a.gen_grid = kGenGridBlocks;
+      a.gen_part = reinterpret_cast<unsigned long long*>(w + L.gen_part);
+      const int gen_waves = kGenGridBlocks * 4;
+      for (int s2 = 0; s2 < 2; ++s2) {
+        a.gpa[s2] = arena_at(w, L.ph_cols[s2], L.ph_cnt[s2], L.ph_nrec[s2], L.ph_base[s2],
+                             L.ph_chain[s2], L.ph_cap, false, gen_waves, true, true);
+        a.gqa[s2] = arena_at(w, L.pr_cols[s2], L.pr_cnt[s2], L.pr_nrec[s2], L.pr_base[s2],
+                             L.pr_chain[s2], L.pr_cap, true, gen_waves, true, true);
+      }
+    }
   }
   const hipError_t e =
       launch_step(a, P.precision, lep, pho, run_photons, static_cast<hipStream_t>(stream));

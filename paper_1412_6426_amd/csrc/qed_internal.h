@@ -19,6 +19,8 @@ constexpr int kExactGridBlocks = 512;
 // Child arenas are used for up to this many instances (their count matrices hold one
 // word per (instance, wavefront)); above it every append reserves store slots directly.
 constexpr int kArenaMaxInstances = 1024;
+// Workgroups of the generation kernel (same-step processing of children).
+constexpr int kGenGridBlocks = 256;
 // Candidate entries per photon wavefront beyond its even share of the photon slots.
 constexpr int kCandSlack = 64;
 
@@ -27,6 +29,9 @@ constexpr int kCandSlack = 64;
 enum PartialField : int {
   kPfSubsteps = 0, kPfEvents, kPfSaturated, kPfNear, kPfNonfinite, kPfNearInt, kPfClamped,
   kPfDropped, kPfEarly, kPfAdv0, kPfAdv1, kPfWaveIters, kPfLowOcc,
+  kPfPairs,     // pairs created by the generation kernel (its kPfEvents are photons)
+  kPfChildren,  // children advanced in their birth step
+  kPfDeferred,  // children with time left in the step that wait for the next step
   kPfEnergy,  // double bits
   kPfMaxP,    // double bits
   kPfNsub,    // QED_NSUB_HIST words
@@ -45,22 +50,41 @@ struct alignas(64) WorkHdr {
   uint32_t reserved[5];
 };
 
-// Deferred children: a wavefront writes each child it creates into its own run of
-// `per_wave` records (no reservation on a shared counter) and counts them per instance;
-// after the step's particle kernels a scan turns the counts into store offsets and a copy
-// kernel moves the records into the stores.  Structure of arrays, `cap` records each.
+// Deferred children: a wavefront writes each child it creates into its own share of
+// `per_wave` records (no reservation on a shared counter) and, once that is full, into
+// chunks of kArenaChunk records taken from a pool with one atomic per chunk and chained
+// (`first`, `next`); it counts its records per instance.  After the step's particle kernels
+// a scan turns the counts into store offsets and a copy kernel moves the records into the
+// stores, in (instance, wavefront, creation) order.  Structure of arrays, `cap` records:
+// the shares [0, pool0), then the pool.
+// With same-step processing the records also carry the time left in the step, the parent's
+// frozen fields and (written by the copy kernel) the store slots the children landed in.
 struct ChildArena {
   double *x, *y, *z, *px, *py, *pz, *w;  // position; momentum (photon) or k (pair record)
   double* r1;                            // pair records: electron share of k
   unsigned long long* parent;            // id of the emitting lepton / converting photon
   unsigned int* sub;                     // sub-step of the event
   unsigned int* inst;                    // instance of the event
+  double* tau;        // same-step: time left in the step after the event (else null)
+  double* fe;         // same-step, space-dependent fields: Ex..Bz of the parent, [6][cap]
+  long long* slot;    // same-step: store slot of the (electron) child, -1 if dropped
+  long long* slot2;   // same-step, pair records: store slot of the positron
+  long long cap;      // records (row length of fe)
   unsigned int* cnt;    // [n_inst][waves]: records per (instance, wavefront); offsets after the scan
   unsigned int* nrec;   // [waves]: records written by each wavefront
   long long* base;      // [n_inst][2]: store counts before the append (photon or e-, e+)
-  long long per_wave;   // records per wavefront; 0: arena off, appends reserve directly
-  int waves;            // wavefronts of the producing kernel (row length of cnt)
+  unsigned int* first;  // [waves]: a wavefront's first pool chunk
+  unsigned int* next;   // [nchunks]: the chunk after this one in its wavefront's chain
+  unsigned int* used;   // pool chunks handed out (zeroed before each producing kernel)
+  long long per_wave;   // share of each wavefront (a multiple of 64 records)
+  long long pool0;      // first pool record (waves * per_wave)
+  long long nchunks;    // pool chunks
+  int waves;            // wavefronts of the producing kernel (row length of cnt); 0: arena off
 };
+constexpr long long kArenaChunk = 256;  // records per pool chunk (a multiple of 64)
+
+// Upper bound of generations advanced in their birth step (qed_params.same_step_generations).
+constexpr int kMaxGenerations = 64;
 
 struct WorkLayout {
   size_t n0;        // long long [n_inst * 3]: live slots at step start (0 when frozen)
@@ -73,12 +97,16 @@ struct WorkLayout {
   size_t candn;     // uint32 [kMaxWaves]: candidates per photon wavefront
   size_t candw;     // uint64 [photon slots + kMaxWaves kCandSlack]: per-wavefront lists
   size_t cand;      // uint64 [photon slots]: overflow list, (photon index << 16) | sub-step
-  // child arenas (present when arena_records > 0 and n_inst <= kArenaMaxInstances)
-  size_t ph_cols, ph_cnt, ph_nrec, ph_base;  // photons emitted by leptons
-  size_t pr_cols, pr_cnt, pr_nrec, pr_base;  // pair records
+  size_t gen_part;  // uint64 [kPfCount][kMaxGridBlocks]: the generation kernel's partials
+  // child arenas (present when arena_records > 0 and n_inst <= kArenaMaxInstances); set 1
+  // only with same-step processing (generations alternate between the two sets)
+  size_t ph_cols[2], ph_cnt[2], ph_nrec[2], ph_base[2], ph_chain[2];  // photons from leptons
+  size_t pr_cols[2], pr_cnt[2], pr_nrec[2], pr_base[2], pr_chain[2];  // pair records
   long long ph_cap, pr_cap;
+  bool same_step;
   size_t total;
-  static WorkLayout make(int n_inst, long long photon_slots, long long arena_records) {
+  static WorkLayout make(int n_inst, long long photon_slots, long long arena_records,
+                         bool same_step = false) {
     WorkLayout L{};
     size_t off = sizeof(WorkHdr);
     auto take = [&off](size_t bytes) {
@@ -97,27 +125,43 @@ struct WorkLayout {
     L.candn = take(sizeof(unsigned int) * kMaxWaves);
     L.candw = take(sizeof(unsigned long long) * (slots + (size_t)kMaxWaves * kCandSlack));
     L.cand = take(sizeof(unsigned long long) * slots);
+    L.same_step = same_step;
     if (arena_records > 0 && n_inst <= kArenaMaxInstances) {
       L.ph_cap = arena_records;
       L.pr_cap = arena_records / 4 > 4096 ? arena_records / 4 : 4096;
       const size_t mat = sizeof(unsigned int) * (size_t)n_inst * kMaxWaves;
-      L.ph_cols = take(ChildArenaBytes(L.ph_cap, false));
-      L.ph_cnt = take(mat);
-      L.ph_nrec = take(sizeof(unsigned int) * kMaxWaves);
-      L.ph_base = take(sizeof(long long) * 2 * (size_t)n_inst);
-      L.pr_cols = take(ChildArenaBytes(L.pr_cap, true));
-      L.pr_cnt = take(mat);
-      L.pr_nrec = take(sizeof(unsigned int) * kMaxWaves);
-      L.pr_base = take(sizeof(long long) * 2 * (size_t)n_inst);
+      for (int s = 0; s < (same_step ? 2 : 1); ++s) {
+        L.ph_cols[s] = take(ChildArenaBytes(L.ph_cap, false, same_step));
+        L.ph_cnt[s] = take(mat);
+        L.ph_nrec[s] = take(sizeof(unsigned int) * kMaxWaves);
+        L.ph_base[s] = take(sizeof(long long) * 2 * (size_t)n_inst);
+        L.ph_chain[s] = take(ChainBytes(L.ph_cap));
+        L.pr_cols[s] = take(ChildArenaBytes(L.pr_cap, true, same_step));
+        L.pr_cnt[s] = take(mat);
+        L.pr_nrec[s] = take(sizeof(unsigned int) * kMaxWaves);
+        L.pr_base[s] = take(sizeof(long long) * 2 * (size_t)n_inst);
+        L.pr_chain[s] = take(ChainBytes(L.pr_cap));
+      }
+      if (same_step)
+        L.gen_part = take(sizeof(unsigned long long) * kPfCount * kMaxGridBlocks);
     }
     L.total = off;
     return L;
   }
-  // Column block of an arena: 7 (+1 for pairs) doubles, parent, sub, inst per record, each
+  // Column block of an arena: 7 (+1 for pairs) doubles, parent, sub, inst per record, and
+  // with same-step processing tau, six field components and one (two for pairs) slots; each
   // column 256-byte aligned.
-  static size_t ChildArenaBytes(long long cap, bool pair) {
+  // Pool bookkeeping: `used` (256 bytes), `first` per wavefront, `next` per chunk.
+  static size_t ChainBytes(long long cap) {
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    return 256 + al(sizeof(unsigned int) * kMaxWaves) +
+           al(sizeof(unsigned int) * ((size_t)cap / kArenaChunk + 1));
+  }
+  static size_t ChildArenaBytes(long long cap, bool pair, bool same_step) {
     auto col = [cap](size_t b) { return ((size_t)cap * b + 255) & ~(size_t)255; };
-    return col(8) * (pair ? 8 : 7) + col(8) + col(4) * 2;
+    size_t n = col(8) * (pair ? 8 : 7) + col(8) + col(4) * 2;
+    if (same_step) n += col(8) * (1 + 6 + (pair ? 2 : 1));
+    return n;
   }
 };
 
@@ -169,6 +213,7 @@ struct StepArgs {
   // generator factors (Sec. VI): fg = f_g when f_g > 1, else 1 (off); inv_fg = 1 / f_g
   double fg_photon, inv_fg_photon, fg_pair, inv_fg_pair;
   int adaptive, forced, emission, pairs, push_photons, freeze_on_drop;
+  int generations;  // children advanced in their birth step: generations (0: none)
   long long tile;  // particles per work chunk (0: one chunk per wavefront)
   WorkHdr* hdr;
   long long* n0;
@@ -185,6 +230,11 @@ struct StepArgs {
   long long cand_per_wave;
   ChildArena pa;  // photons emitted by the lepton kernel
   ChildArena qa;  // pair records of the exact kernel
+  // same-step processing: both arena sets as written by the generation kernel (gen_waves
+  // producing wavefronts), and its partial stats
+  ChildArena gpa[2], gqa[2];
+  unsigned long long* gen_part;
+  int gen_grid;
   int lep_grid, pho_grid, ex_grid;  // workgroups of the lepton, photon and exact-pair kernels
   int pho_waves;                    // wavefronts of the photon kernel
   qed_stats* stats;

@@ -49,14 +49,19 @@ constexpr long long kDefaultTile = 128;
 __global__ void __launch_bounds__(256) prep_kernel(StepArgs a, int run_photons) {
   __shared__ int s_ok;
   if (blockIdx.x > 0) {
-    // workgroups 1.. clear the per-(instance, wavefront) child counts of the arenas
-    const long long n1 = a.pa.per_wave > 0 ? (long long)a.n_inst * a.pa.waves : 0;
-    const long long n2 = a.qa.per_wave > 0 ? (long long)a.n_inst * a.qa.waves : 0;
+    // workgroups 1.. clear the per-(instance, wavefront) child counts of the arenas and
+    // their pool counters
+    const long long n1 = a.pa.waves > 0 ? (long long)a.n_inst * a.pa.waves : 0;
+    const long long n2 = a.qa.waves > 0 ? (long long)a.n_inst * a.qa.waves : 0;
     const long long stride = (long long)(gridDim.x - 1) * blockDim.x;
     for (long long i = (long long)(blockIdx.x - 1) * blockDim.x + threadIdx.x; i < n1 + n2;
          i += stride) {
       if (i < n1) a.pa.cnt[i] = 0u;
       else a.qa.cnt[i - n1] = 0u;
+    }
+    if (blockIdx.x == 1 && threadIdx.x == 0) {
+      if (a.pa.waves > 0) *a.pa.used = 0u;
+      if (a.qa.waves > 0) *a.qa.used = 0u;
     }
     return;
   }
@@ -127,29 +132,34 @@ __device__ __forceinline__ void stats_add(int64_t* p, unsigned long long v) {
   if (v) atomicAdd(reinterpret_cast<unsigned long long*>(p), v);
 }
 
-// Partial-stats reduction: one wavefront per (partial set, field).  The lepton set has all
-// kPfCount fields; the photon and exact-pair sets only the counters below kPfNsub (their
-// histogram fields stay zero).  Sums go into the zeroed stats record with atomics on
-// distinct addresses.
-constexpr int kReduceJobs = kPfCount + 2 * kPfNsub;
+// Partial-stats reduction: one wavefront per (partial set, field).  The lepton and
+// generation sets have all kPfCount fields; the photon and exact-pair sets only the
+// counters below kPfNsub (their histogram fields stay zero).  Sums go into the zeroed stats
+// record with atomics.
+constexpr int kReduceJobs = 2 * kPfCount + 2 * kPfNsub;
 
 __global__ void __launch_bounds__(256) reduce_kernel(StepArgs a) {
   const int job = (int)blockIdx.x * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6);
   if (job >= kReduceJobs) return;
   const int lane = (int)(threadIdx.x & 63u);
-  int kind, f;
+  int kind, f;  // kind 0 leptons, 1 photons, 2 exact pairs, 3 generations
   if (job < kPfCount) {
     kind = 0;
     f = job;
-  } else {
+  } else if (job < kPfCount + 2 * kPfNsub) {
     kind = 1 + (job - kPfCount) / kPfNsub;
     f = (job - kPfCount) % kPfNsub;
+  } else {
+    kind = 3;
+    f = job - kPfCount - 2 * kPfNsub;
   }
-  const bool pho = kind > 0;
-  const int G = kind == 0 ? a.lep_grid : (kind == 1 ? a.pho_grid : a.ex_grid);
+  const bool pho = kind == 1 || kind == 2;
+  const int G = kind == 0 ? a.lep_grid
+                          : (kind == 1 ? a.pho_grid : (kind == 2 ? a.ex_grid : a.gen_grid));
   if (G <= 0) return;
-  const unsigned long long* col =
-      (kind == 0 ? a.lep_part : (kind == 1 ? a.pho_part : a.ex_part)) + (size_t)f * kMaxGridBlocks;
+  const unsigned long long* part =
+      kind == 0 ? a.lep_part : (kind == 1 ? a.pho_part : (kind == 2 ? a.ex_part : a.gen_part));
+  const unsigned long long* col = part + (size_t)f * kMaxGridBlocks;
   qed_stats* st = a.stats;
   if (f == kPfEnergy || f == kPfMaxP) {
     double v = 0.0;
@@ -191,11 +201,14 @@ __global__ void __launch_bounds__(256) reduce_kernel(StepArgs a) {
     case kPfAdv1: stats_add(&st->advanced[QED_POSITRON], v); break;
     case kPfWaveIters: stats_add(&st->wave_iters, v); break;
     case kPfLowOcc: stats_add(&st->low_occupancy_iters, v); break;
+    case kPfPairs: stats_add(&st->pairs, v); break;
+    case kPfChildren: stats_add(&st->children_advanced, v); break;
+    case kPfDeferred: stats_add(&st->deferred, v); break;
     default:
       if (f >= kPfNsub && f < kPfNsub + QED_NSUB_HIST)
-        st->nsub_hist[f - kPfNsub] = (int64_t)v;
+        stats_add(&st->nsub_hist[f - kPfNsub], v);
       else if (f >= kPfHist)
-        st->photon_hist[f - kPfHist] = (int64_t)v;
+        stats_add(&st->photon_hist[f - kPfHist], v);
   }
 }
 
@@ -253,6 +266,7 @@ struct LaneCounters {
 // Wavefront-uniform counts.
 struct WaveCounters {
   long long substeps = 0, events = 0, adv0 = 0, adv1 = 0, wave_iters = 0, low_occ = 0;
+  long long pairs = 0, children = 0, deferred = 0;  // same-step processing
 };
 
 template <typename T>
@@ -292,11 +306,12 @@ __device__ void wave_to_block(BlockStats& bs, const LaneCounters& c, const WaveC
   const double en = wave_sum(c.energy);
   const double mp = wave_max(c.maxp);
   if (lane_id() == 0) {
-    const long long vals[7] = {wc.substeps + subs, wc.events, wc.adv0, wc.adv1, wc.wave_iters,
-                               wc.low_occ, early};
-    const int fields[7] = {kPfSubsteps, kPfEvents, kPfAdv0, kPfAdv1, kPfWaveIters, kPfLowOcc,
-                           kPfEarly};
-    for (int i = 0; i < 7; ++i)
+    const long long vals[10] = {wc.substeps + subs, wc.events, wc.adv0, wc.adv1,
+                                wc.wave_iters, wc.low_occ, early, wc.pairs, wc.children,
+                                wc.deferred};
+    const int fields[10] = {kPfSubsteps, kPfEvents, kPfAdv0, kPfAdv1, kPfWaveIters, kPfLowOcc,
+                            kPfEarly, kPfPairs, kPfChildren, kPfDeferred};
+    for (int i = 0; i < 10; ++i)
       if (vals[i]) atomicAdd(&bs.w[fields[i]], (unsigned long long)vals[i]);
     if (en != 0.0) atomicAdd(&bs.energy, en);
     if (mp > 0.0)
@@ -312,6 +327,26 @@ __device__ __forceinline__ void block_stats_store(const BlockStats& bs, unsigned
     if (i == kPfEnergy) v = (unsigned long long)__double_as_longlong(bs.energy);
     if (i == kPfMaxP) v = (unsigned long long)__double_as_longlong(bs.maxp);
     part[(size_t)i * kMaxGridBlocks + blockIdx.x] = v;
+  }
+}
+
+// The same, added to what earlier launches of the kernel stored (first: store).
+__device__ __forceinline__ void block_stats_accumulate(const BlockStats& bs,
+                                                       unsigned long long* part, bool first) {
+  for (int i = threadIdx.x; i < kPfCount; i += blockDim.x) {
+    const size_t at = (size_t)i * kMaxGridBlocks + blockIdx.x;
+    const unsigned long long old = first ? 0ull : part[at];
+    unsigned long long v;
+    if (i == kPfEnergy) {
+      v = (unsigned long long)__double_as_longlong(
+          bs.energy + (first ? 0.0 : __longlong_as_double((long long)old)));
+    } else if (i == kPfMaxP) {
+      v = (unsigned long long)__double_as_longlong(
+          first ? bs.maxp : fmax(bs.maxp, __longlong_as_double((long long)old)));
+    } else {
+      v = bs.w[i] + old;
+    }
+    part[at] = v;
   }
 }
 
@@ -389,6 +424,85 @@ struct ArenaTally {
   }
 };
 
+// A producing wavefront's position in an arena: records written, and the pool chunk it
+// fills once its share is full.
+struct ArenaCursor {
+  long long n = 0;
+  unsigned cur = 0xFFFFFFFFu;  // current pool chunk (none yet)
+  unsigned fill = (unsigned)kArenaChunk;
+};
+
+// Where the ranks of one ballot go: [0, k0) to the share from `share`, [k0, k1) to the
+// current chunk from c0, [k1, n) to a new chunk from c1.
+struct ArenaSpan {
+  long long share, c0, c1;
+  int k0, k1;
+  __device__ __forceinline__ long long at(int rank) const {
+    return rank < k0 ? share + rank : (rank < k1 ? c0 + (rank - k0) : c1 + (rank - k1));
+  }
+};
+
+// Reserve n_new (1..64) records for one ballot of wavefront wid: the rest of its share,
+// then its current chunk, then one new chunk from the pool (one atomic).  False, with
+// nothing reserved, when the pool is exhausted.  Wavefront-uniform arguments; all lanes call.
+__device__ __forceinline__ bool arena_reserve(const ChildArena& A, int wid, ArenaCursor& c,
+                                              int n_new, ArenaSpan& s) {
+  const long long room_share = A.per_wave > c.n ? A.per_wave - c.n : 0;
+  s.share = (long long)wid * A.per_wave + c.n;
+  if (n_new <= room_share) {
+    s.k0 = s.k1 = n_new;
+    s.c0 = s.c1 = 0;
+    c.n += n_new;
+    return true;
+  }
+  s.k0 = (int)room_share;
+  const int rest = n_new - s.k0;
+  const int room = (int)(kArenaChunk - c.fill);
+  s.c0 = A.pool0 + (long long)c.cur * kArenaChunk + c.fill;  // used only if room > 0
+  if (rest <= room) {
+    s.k1 = n_new;
+    s.c1 = 0;
+    c.fill += (unsigned)rest;
+    c.n += n_new;
+    return true;
+  }
+  unsigned long long nc = 0;
+  if (lane_id() == 0) nc = atomicAdd(A.used, 1u);
+  nc = (unsigned long long)wave_bcast((long long)nc, 0);
+  if (nc >= (unsigned long long)A.nchunks) return false;
+  if (lane_id() == 0) {
+    if (c.cur == 0xFFFFFFFFu) A.first[wid] = (unsigned)nc;
+    else A.next[c.cur] = (unsigned)nc;
+  }
+  s.k1 = s.k0 + room;
+  s.c1 = A.pool0 + (long long)nc * kArenaChunk;
+  c.cur = (unsigned)nc;
+  c.fill = (unsigned)(rest - room);
+  c.n += n_new;
+  return true;
+}
+
+// Record index of the j-th record of producing wavefront sw, for j visited in increasing
+// order in wavefront-uniform steps that are multiples of 32 (so a batch of 64 records, or
+// of 32 pair records, lies within one share or chunk).
+struct ArenaWalk {
+  unsigned chunk = 0xFFFFFFFFu;
+  long long start = 0;  // the chunk holds pool records [start, start + kArenaChunk) of sw
+  __device__ __forceinline__ long long at(const ChildArena& A, int sw, long long j) {
+    if (j < A.per_wave) return (long long)sw * A.per_wave + j;
+    const long long jp = j - A.per_wave;
+    if (chunk == 0xFFFFFFFFu) {
+      chunk = A.first[sw];
+      start = 0;
+    }
+    while (jp >= start + kArenaChunk) {
+      chunk = A.next[chunk];
+      start += kArenaChunk;
+    }
+    return A.pool0 + (long long)chunk * kArenaChunk + (jp - start);
+  }
+};
+
 // Current piece of a wavefront's work: slots [cur, end) of one (instance, species) segment.
 struct TileCursor {
   long long cur = 0, end = 0;  // slots
@@ -457,6 +571,73 @@ template <>
 struct TabType<true> {
   using T = float2;
 };
+
+// Emission decision of the modified generator (Sec. IV.G, Eqs. (24), (25)) for draw o:
+// delta = r1^3, emit iff r2 < 3 r1^2 P(r1^3).  The mixed form evaluates the rate and the
+// comparison in FP32.
+template <bool MIXED>
+__device__ __forceinline__ bool emission_decision(const typename TabType<MIXED>::T* tab,
+                                                  const Series64& ser64, const Series32& ser32,
+                                                  const uint4& o, double chi, double g,
+                                                  double dtfac, LaneCounters& cnt,
+                                                  double& delta) {
+  if (MIXED) {
+    const float r1 = uniform32(o.y), r2 = uniform32(o.w);
+    const float d = r1 * r1 * r1, omd = 1.0f - d;
+    const float z = (2.0f / 3.0f) * d / (omd * (float)chi);
+    const float P = 3.0f * r1 * r1 * ((float)(dtfac * kInvSqrt3Pi) / (float)g) *
+                    emission_bracket32(reinterpret_cast<const float2*>(tab), ser32, z,
+                                       d * d / omd);
+    cnt.note((double)P, (double)r2);
+    delta = (double)d;
+    return r2 < P;
+  }
+  const double r1 = uniform64(o.x, o.y), r2 = uniform64(o.z, o.w);
+  const double d = r1 * r1 * r1, omd = 1.0 - d;
+  const double z = (2.0 / 3.0) * d / (omd * chi);
+  const double P = 3.0 * r1 * r1 * (dtfac * kInvSqrt3Pi / g) *
+                   emission_bracket64(reinterpret_cast<const double2*>(tab), ser64, z,
+                                      d * d / omd);
+  cnt.note(P, r2);
+  delta = d;
+  return r2 < P;
+}
+
+// The photon of an emission: energy delta gamma m c^2 along p (Sec. IV.F), as the factor
+// f = |k| / |p|.  Counts the event's spectrum bin and radiated energy; false (and a
+// non-finite count) if p = 0.
+__device__ __forceinline__ bool emission_photon(const V3& p, double g, double delta, double wgt,
+                                                BlockStats& bs, LaneCounters& cnt, double& f) {
+  const double pabs = sqrt(dot(p, p));
+  if (!(pabs > 0.0)) {
+    block_count(bs, kPfNonfinite);
+    return false;
+  }
+  const double eps = delta * g;
+  f = eps / pabs;
+  const float lb = (__log10f((float)eps) + 8.0f) * 10.0f;
+  if (lb >= 0.0f && lb < (float)QED_SPECTRUM_BINS) atomicAdd(&bs.w[kPfHist + (int)lb], 1ull);
+  cnt.energy += wgt * eps;
+  return true;
+}
+
+// Same-step processing: the time a child has left in the step and its parent's fields,
+// stored with its arena record r (the fields only where they depend on position).
+template <int FMODE>
+__device__ __forceinline__ void record_same_step(const ChildArena& A, long long r, double tau,
+                                                 const V3& E, const V3& B) {
+  A.tau[r] = tau;
+  if (FMODE == kFieldLocal) {
+    const long long c = A.cap;
+    double* f = A.fe;
+    f[r] = E.x;
+    f[c + r] = E.y;
+    f[2 * c + r] = E.z;
+    f[3 * c + r] = B.x;
+    f[4 * c + r] = B.y;
+    f[5 * c + r] = B.z;
+  }
+}
 
 // Column pointer of electrons or positrons without indexing the kernel-argument array.
 #define LEPTON_COL(col, sp) ((sp) == QED_ELECTRON ? a.sp[QED_ELECTRON].col : a.sp[QED_POSITRON].col)
@@ -557,7 +738,7 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
   const int wid = wave_index();
   block_stats_init(bs);
   if (!block_has_work(N, a.tile)) {
-    if (a.pa.per_wave > 0 && lane_id() == 0) a.pa.nrec[wid] = 0u;
+    if (a.pa.waves > 0 && lane_id() == 0) a.pa.nrec[wid] = 0u;
     __syncthreads();
     block_stats_store(bs, a.lep_part);
     return;
@@ -588,10 +769,9 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
   wr.init(N, a.tile);
   bool open = true;
   int staged = 0;
-  // arena: this wavefront's records start at rbase; nrec written so far
+  // arena: this wavefront's share, then pool chunks
   const ChildArena& pa = a.pa;
-  const long long rbase = (long long)wid * pa.per_wave;
-  long long nrec = 0;
+  ArenaCursor acur;
   ArenaTally tally;
 
   // lane state
@@ -686,42 +866,10 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
       if (a.emission) {
         const uint4 o = draw_words(id, seed, step, (uint32_t)k, kDraw);
         double delta;
-        if (MIXED) {
-          const float r1 = uniform32(o.y), r2 = uniform32(o.w);
-          const float d = r1 * r1 * r1, omd = 1.0f - d;
-          const float z = (2.0f / 3.0f) * d / (omd * (float)chi);
-          const float P = 3.0f * r1 * r1 * ((float)(dtfac * kInvSqrt3Pi) / (float)g) *
-                          emission_bracket32(reinterpret_cast<const float2*>(tab), ser32, z,
-                                             d * d / omd);
-          cnt.note((double)P, (double)r2);
-          emit = r2 < P;
-          delta = (double)d;
-        } else {
-          const double r1 = uniform64(o.x, o.y), r2 = uniform64(o.z, o.w);
-          const double d = r1 * r1 * r1, omd = 1.0 - d;
-          const double z = (2.0 / 3.0) * d / (omd * chi);
-          const double P = 3.0 * r1 * r1 * (dtfac * kInvSqrt3Pi / g) *
-                           emission_bracket64(reinterpret_cast<const double2*>(tab), ser64, z,
-                                              d * d / omd);
-          cnt.note(P, r2);
-          emit = r2 < P;
-          delta = d;
-        }
+        emit = emission_decision<MIXED>(tab, ser64, ser32, o, chi, g, dtfac, cnt, delta);
         if (emit) {
-          // photon of energy delta gamma m c^2 along p (Sec. IV.F)
-          const double pabs = sqrt(dot(p, p));
-          if (pabs > 0.0) {
-            const double eps = delta * g;
-            f = eps / pabs;
-            ++nev;
-            const float lb = (__log10f((float)eps) + 8.0f) * 10.0f;
-            if (lb >= 0.0f && lb < (float)QED_SPECTRUM_BINS)
-              atomicAdd(&bs.w[kPfHist + (int)lb], 1ull);
-            cnt.energy += wgt * eps;
-          } else {
-            emit = false;
-            block_count(bs, kPfNonfinite);
-          }
+          emit = emission_photon(p, g, delta, wgt, bs, cnt, f);
+          if (emit) ++nev;
         }
       }
     }
@@ -735,12 +883,13 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
       child = generator_runs(id, seed, step, (uint32_t)k, kGenPhoton, a.inv_fg_photon);
     const double cw = wgt * a.fg_photon;
     const uint64_t em = wave_ballot(child);
-    if (em && nrec + __popcll(em) <= pa.per_wave) {
+    ArenaSpan span;
+    if (em && pa.waves > 0 && arena_reserve(pa, wid, acur, __popcll(em), span)) {
       const int n_new = __popcll(em);
       wc.events += n_new;
       tally.add(pa, wid, em, child, inst);
       if (child) {
-        const long long r = rbase + nrec + __popcll(em & below);
+        const long long r = span.at(__popcll(em & below));
         pa.x[r] = x.x;
         pa.y[r] = x.y;
         pa.z[r] = x.z;
@@ -751,11 +900,13 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
         pa.parent[r] = id;
         pa.sub[r] = (unsigned)k;
         pa.inst[r] = (unsigned)inst;
+        if (a.generations > 0) record_same_step<FMODE>(pa, r, (double)(nsub - k - 1) * h, E, B);
       }
-      nrec += n_new;
     } else if (em) {
       const int n_new = __popcll(em);
       wc.events += n_new;
+      // reserved directly in the stores: not advanced in this step
+      if (a.generations > 0) wc.deferred += __popcll(wave_ballot(child && k < nsub - 1));
       if (staged + n_new > kStageCap) {
         flush_stage(a, sg, staged, cnt);
         staged = 0;
@@ -812,9 +963,9 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
     }
   }
   if (staged > 0) flush_stage(a, sg, staged, cnt);
-  if (pa.per_wave > 0) {
+  if (pa.waves > 0) {
     tally.flush(pa, wid);
-    if (lane_id() == 0) pa.nrec[wid] = (unsigned)nrec;
+    if (lane_id() == 0) pa.nrec[wid] = (unsigned)acur.n;
   }
 
   wave_to_block(bs, cnt, wc);
@@ -839,7 +990,7 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
 // register footprint lets many wavefronts stay resident to hide HBM latency.
 
 struct PhotonSetup {
-  double chi, hk, pref, pbound;
+  double chi, h, hk, pref, pbound;
   int nsub;
 };
 
@@ -867,6 +1018,7 @@ __device__ __forceinline__ PhotonSetup photon_setup(const StepArgs& a, const V3&
   }
   if (bs && !isfinite(ps.chi)) block_count(*bs, kPfNonfinite);
   const double h = ps.nsub == 1 ? a.dt : a.dt / (double)ps.nsub;
+  ps.h = h;
   ps.hk = h * inv_k;
   ps.pref = h * (a.dtfac_per_h * kInvSqrt3Pi) * inv_k;
   // upper bound of the pair probability over delta_e for this chi's sub-octave
@@ -1090,7 +1242,7 @@ struct ExactCtx {
   uint32_t step;
   int wid;
   int staged;
-  long long nrec;   // records in this wavefront's pair-arena share
+  ArenaCursor acur;  // this wavefront's place in the pair arena
   ArenaTally tally;
   const double* bound;  // per-octave pair-rate bounds (LDS)
 };
@@ -1105,10 +1257,10 @@ __device__ __forceinline__ void exact_batch(const StepArgs& a, ExactCtx& c, Pair
   const qed_soa& S = a.sp[QED_PHOTON];
   const long long i = i0 + lane_id();
   bool pair = false, make = false;
-  double r1 = 0.0, wp = 0.0;
-  int kpair = 0, inst = 0;
+  double r1 = 0.0, wp = 0.0, tau = 0.0;
+  int kpair = 0, inst = 0, nsub = 0;
   long long s = 0;
-  V3 x{}, kv{};
+  V3 x{}, kv{}, Ef{}, Bf{};
   uint64_t id = 0;
   if (i < n) {
     const unsigned long long e = list[i];
@@ -1161,6 +1313,10 @@ __device__ __forceinline__ void exact_batch(const StepArgs& a, ExactCtx& c, Pair
                  ? generator_runs(id, seed, c.step, (uint32_t)kpair, kGenPair, a.inv_fg_pair)
                  : true;
       wp = S.w[s] * a.fg_pair;
+      nsub = st.nsub;
+      tau = (double)(st.nsub - kpair - 1) * st.h;
+      Ef = E;
+      Bf = B;
     }
   }
   const uint64_t pm = wave_ballot(make);
@@ -1168,11 +1324,12 @@ __device__ __forceinline__ void exact_batch(const StepArgs& a, ExactCtx& c, Pair
   const int n_new = __popcll(pm);
   wc.events += n_new;
   const ChildArena& qa = a.qa;
-  if (c.nrec + n_new <= qa.per_wave) {
-    // ---- pair records into the wavefront's arena share ----
+  ArenaSpan span;
+  if (qa.waves > 0 && arena_reserve(qa, c.wid, c.acur, n_new, span)) {
+    // ---- pair records into the wavefront's arena share or pool chunks ----
     c.tally.add(qa, c.wid, pm, make, inst);
     if (make) {
-      const long long r = (long long)c.wid * qa.per_wave + c.nrec + __popcll(pm & below);
+      const long long r = span.at(__popcll(pm & below));
       qa.x[r] = x.x;
       qa.y[r] = x.y;
       qa.z[r] = x.z;
@@ -1184,10 +1341,12 @@ __device__ __forceinline__ void exact_batch(const StepArgs& a, ExactCtx& c, Pair
       qa.parent[r] = id;
       qa.sub[r] = (unsigned)kpair;
       qa.inst[r] = (unsigned)inst;
+      if (a.generations > 0) record_same_step<FMODE>(qa, r, tau, Ef, Bf);
     }
-    c.nrec += n_new;
     return;
   }
+  // reserved directly in the stores: not advanced in this step (an electron and a positron)
+  if (a.generations > 0) wc.deferred += 2 * __popcll(wave_ballot(make && kpair < nsub - 1));
   // ---- else stage them and reserve e-/e+ slots once per batch ----
   if (c.staged + n_new > kStageCap) {
     flush_pairs(a, ps, c.staged, c.step, cnt);
@@ -1230,7 +1389,7 @@ __global__ void __launch_bounds__(256) photon_exact_kernel(StepArgs a) {
   c.step = (uint32_t)hdr->step;
   c.wid = wave_index();
   c.staged = 0;
-  c.nrec = 0;
+  c.acur = ArenaCursor{};
   PairStage& ps = pstage[threadIdx.x >> 6];
   LaneCounters cnt;
   cnt.bs = &bs;
@@ -1251,9 +1410,9 @@ __global__ void __launch_bounds__(256) photon_exact_kernel(StepArgs a) {
     exact_batch<MIXED, FMODE>(a, c, ps, cnt, wc, a.cand, i0, n);
 
   if (c.staged > 0) flush_pairs(a, ps, c.staged, c.step, cnt);
-  if (a.qa.per_wave > 0) {
+  if (a.qa.waves > 0) {
     c.tally.flush(a.qa, c.wid);
-    if (lane_id() == 0) a.qa.nrec[c.wid] = (unsigned)c.nrec;
+    if (lane_id() == 0) a.qa.nrec[c.wid] = (unsigned)c.acur.n;
   }
   wave_to_block(bs, cnt, wc);
   __syncthreads();
@@ -1267,15 +1426,16 @@ __global__ void __launch_bounds__(256) photon_exact_kernel(StepArgs a) {
 // (in place), the store count before the append into base[], and the counts raised by the
 // totals.  Counts above the capacity are clamped by the finalize kernel; the copy kernel
 // drops and counts the children that land beyond it.
-__global__ void __launch_bounds__(1024) arena_scan_kernel(StepArgs a) {
+__global__ void __launch_bounds__(1024) arena_scan_kernel(StepArgs a, ChildArena pa,
+                                                          ChildArena qa) {
   __shared__ unsigned long long wsum[16];
   const int i = blockIdx.x;
   const int lane = lane_id();
   const int wv = (int)(threadIdx.x >> 6);
   const int nw = (int)(blockDim.x >> 6);
   for (int kind = 0; kind < 2; ++kind) {
-    const ChildArena& A = kind == 0 ? a.pa : a.qa;
-    if (A.per_wave <= 0) continue;
+    const ChildArena& A = kind == 0 ? pa : qa;
+    if (A.waves <= 0) continue;
     unsigned int* row = A.cnt + (size_t)i * A.waves;
     unsigned long long carry = 0;
     for (int b0 = 0; b0 < A.waves; b0 += (int)blockDim.x) {
@@ -1331,30 +1491,48 @@ __device__ __forceinline__ void count_drops(const StepArgs& a, int inst, bool lo
 
 // One wavefront per producing wavefront: walks its records in order and gives each the
 // next store slot of its instance after the offsets of the scan (a per-instance running
-// count in LDS), then writes the child (photon) or both children (pair record).
-__global__ void __launch_bounds__(256) arena_copy_kernel(StepArgs a) {
+// count in LDS), then writes the child (photon) or both children (pair record), and, for
+// same-step processing, the slots into the record.  The launch also clears the count
+// matrices of the arenas zpa, zqa (the next generation's, whose readers are done).
+__global__ void __launch_bounds__(256) arena_copy_kernel(StepArgs a, ChildArena pa,
+                                                         ChildArena qa, ChildArena zpa,
+                                                         ChildArena zqa) {
   __shared__ unsigned int lcnt[kWavesPerBlock][kArenaMaxInstances];
+  {
+    const long long n1 = zpa.waves > 0 ? (long long)a.n_inst * zpa.waves : 0;
+    const long long n2 = zqa.waves > 0 ? (long long)a.n_inst * zqa.waves : 0;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n1 + n2;
+         i += stride) {
+      if (i < n1) zpa.cnt[i] = 0u;
+      else zqa.cnt[i - n1] = 0u;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (zpa.waves > 0) *zpa.used = 0u;
+      if (zqa.waves > 0) *zqa.used = 0u;
+    }
+  }
   unsigned int* run = lcnt[threadIdx.x >> 6];
   const uint64_t below = lanes_below();
   const int lane = lane_id();
   const uint32_t step = (uint32_t)a.hdr->step;
-  const int npa = a.pa.per_wave > 0 ? a.pa.waves : 0;
-  const int nqa = a.qa.per_wave > 0 ? a.qa.waves : 0;
+  const int npa = pa.waves;
+  const int nqa = qa.waves;
   const int V = (int)gridDim.x * (int)(blockDim.x >> 6);
   for (int t = wave_index(); t < npa + nqa; t += V) {
     const bool pair = t >= npa;
-    const ChildArena& A = pair ? a.qa : a.pa;
+    const ChildArena& A = pair ? qa : pa;
     const int sw = pair ? t - npa : t;
     const long long n = (long long)A.nrec[sw];
     if (n == 0) continue;
     for (int q = lane; q < a.n_inst; q += 64) run[q] = 0u;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    const long long r0 = (long long)sw * A.per_wave;
+    ArenaWalk walk;
     for (long long j0 = 0; j0 < n; j0 += 64) {
       const long long j = j0 + lane;
       const bool has = j < n;
-      const long long r = r0 + (has ? j : 0);
+      const long long r = walk.at(A, sw, j0) + (has ? lane : 0);
       const int li = has ? (int)A.inst[r] : -1;
       unsigned local = 0;
       uint64_t m = wave_ballot(has);
@@ -1395,8 +1573,10 @@ __global__ void __launch_bounds__(256) arena_copy_kernel(StepArgs a) {
             o.parent[q] = parent;
             o.birth[q] = birth_code(step, sub);
             if (o.n_events) o.n_events[q] = 0u;
+            if (A.slot) A.slot[r] = q;
           } else {
             lost0 = true;
+            if (A.slot) A.slot[r] = -1;
           }
         } else {
           // electron takes r1 of the photon momentum, positron the rest (Sec. V.A)
@@ -1417,8 +1597,10 @@ __global__ void __launch_bounds__(256) arena_copy_kernel(StepArgs a) {
             o.parent[q] = parent;
             o.birth[q] = birth_code(step, sub);
             if (o.n_events) o.n_events[q] = 0u;
+            if (A.slot) A.slot[r] = q;
           } else {
             lost0 = true;
+            if (A.slot) A.slot[r] = -1;
           }
           const long long dp = A.base[2 * li + 1] + off;
           if (dp < I.capacity[QED_POSITRON]) {
@@ -1435,8 +1617,10 @@ __global__ void __launch_bounds__(256) arena_copy_kernel(StepArgs a) {
             o.parent[q] = parent;
             o.birth[q] = birth_code(step, sub);
             if (o.n_events) o.n_events[q] = 0u;
+            if (A.slot2) A.slot2[r] = q;
           } else {
             lost1 = true;
+            if (A.slot2) A.slot2[r] = -1;
           }
         }
       }
@@ -1446,6 +1630,383 @@ __global__ void __launch_bounds__(256) arena_copy_kernel(StepArgs a) {
       }
     }
   }
+}
+
+// ------------------------------------------------------------------------------------
+// children in their birth step (same-step processing)
+// ------------------------------------------------------------------------------------
+// A generation pass reads the records the previous pass (or the step's particle kernels)
+// wrote and the copy kernel placed in the stores, advances each child in its store slot
+// through the time it has left in the step, with its parent's frozen fields, and writes the
+// children it creates to the other arena set (with their own time left), from where the
+// next scan and copy place them.  Generations alternate between the two sets.
+struct GenArgs {
+  ChildArena ipa, iqa;  // input: photon records and pair records of the previous pass
+  ChildArena opa, oqa;  // output: this kernel's wavefronts write their children here
+  int pass;             // 1 .. G
+  int last;             // 1 on pass G: what it creates waits for the next step
+};
+// kernel arguments stay within the 4 KB the launch passes
+static_assert(sizeof(StepArgs) + sizeof(GenArgs) <= 4096, "generation kernel arguments");
+static_assert(sizeof(StepArgs) + 4 * sizeof(ChildArena) <= 4096, "copy kernel arguments");
+
+// Fields a child inherited from its parent (record r of A).
+template <int FMODE>
+__device__ __forceinline__ void inherited_fields(const StepArgs& a, const ChildArena& A,
+                                                 long long r, int inst, V3& E, V3& B) {
+  if (FMODE == kFieldLocal) {
+    const long long c = A.cap;
+    const double* f = A.fe;
+    E = {f[r], f[c + r], f[2 * c + r]};
+    B = {f[3 * c + r], f[4 * c + r], f[5 * c + r]};
+  } else {
+    instance_fields<FMODE>(a, inst, E, B);
+  }
+}
+
+struct GenWave {
+  int wid;
+  ArenaCursor cp, cq;  // this wavefront's place in opa, oqa
+  ArenaTally tp, tq;
+};
+
+// Leptons of 64 pair records' electrons and positrons (lane: record r, species sp), each
+// through its tau.  All 64 lanes call.
+template <bool MIXED, int FMODE>
+__device__ __forceinline__ void gen_leptons(const StepArgs& a, const GenArgs& q, GenWave& gw,
+                                            const ChildArena& A, long long r, int sp, int inst,
+                                            long long slot, double tau, bool act,
+                                            const typename TabType<MIXED>::T* tab,
+                                            const Series64& ser64, const Series32& ser32,
+                                            BlockStats& bs, LaneCounters& cnt, WaveCounters& wc) {
+  const uint64_t below = lanes_below();
+  const uint32_t step = (uint32_t)a.hdr->step;
+  V3 x{}, p{}, E{}, B{};
+  uint64_t id = 0, seed = 0;
+  double wgt = 0.0, h = 0.0, dtfac = 0.0, qh2 = 0.0;
+  uint32_t nev = 0;
+  int nsub = 0;
+  if (act) {
+    x = {LEPTON_COL(x, sp)[slot], LEPTON_COL(y, sp)[slot], LEPTON_COL(z, sp)[slot]};
+    p = {LEPTON_COL(px, sp)[slot], LEPTON_COL(py, sp)[slot], LEPTON_COL(pz, sp)[slot]};
+    id = LEPTON_COL(id, sp)[slot];
+    wgt = LEPTON_COL(w, sp)[slot];
+    uint32_t* ne = LEPTON_COL(n_events, sp);
+    nev = ne ? ne[slot] : 0u;
+    seed = a.inst[inst].seed;
+    inherited_fields<FMODE>(a, A, r, inst, E, B);
+    const double g = sqrt(1.0 + dot(p, p));
+    const double chi = chi_of(p, g, E, FMODE == kFieldE ? V3{0.0, 0.0, 0.0} : B, a.eps_r);
+    nsub = 1;
+    if (a.forced > 0) {
+      nsub = a.forced;
+    } else if (a.adaptive && chi > 0.0) {
+      NsubInfo ni;
+      if (MIXED) {
+        const float rr = (float)(chi / g);
+        const float ratio = (float)tau * cbrtf(rr * rr) * (float)a.inv_lep_scale;
+        ni = nsub_from_ratio((double)ratio);
+      } else {
+        ni = nsub_from_ratio(substep_ratio_lepton(tau, chi, g, a.inv_lep_scale));
+      }
+      nsub = ni.n;
+      if (ni.near_int) block_count(bs, kPfNearInt);
+      if (ni.clamped) block_count(bs, kPfClamped);
+    }
+    if (!isfinite(chi)) block_count(bs, kPfNonfinite);
+    h = tau / (double)nsub;
+    dtfac = h * a.dtfac_per_h;
+    qh2 = (sp == QED_ELECTRON ? -0.5 : 0.5) * h;
+  }
+  bool busy = act;
+  int k = 0;
+  const ChildArena& O = q.opa;
+  while (wave_ballot(busy)) {
+    bool emit = false;
+    double f = 0.0;
+    if (busy) {
+      if (FMODE == kFieldE) {
+        p = {p.x + 2.0 * qh2 * E.x, p.y + 2.0 * qh2 * E.y, p.z + 2.0 * qh2 * E.z};
+      } else {
+        boris(p, qh2, E, B);
+      }
+      const double g = sqrt(1.0 + dot(p, p));
+      const double hg = h / g;
+      x = {x.x + hg * p.x, x.y + hg * p.y, x.z + hg * p.z};
+      const double chi = chi_of(p, g, E, FMODE == kFieldE ? V3{0.0, 0.0, 0.0} : B, a.eps_r);
+      ++cnt.subs;
+      if (a.emission) {
+        const uint4 o = draw_words(id, seed, step, (uint32_t)k, kDraw);
+        double delta;
+        emit = emission_decision<MIXED>(tab, ser64, ser32, o, chi, g, dtfac, cnt, delta);
+        if (emit) {
+          emit = emission_photon(p, g, delta, wgt, bs, cnt, f);
+          if (emit) ++nev;
+        }
+      }
+    }
+    bool child = emit;
+    if (emit && a.fg_photon > 1.0)
+      child = generator_runs(id, seed, step, (uint32_t)k, kGenPhoton, a.inv_fg_photon);
+    const uint64_t em = wave_ballot(child);
+    if (em) {
+      const int n_new = __popcll(em);
+      wc.events += n_new;
+      const double cw = wgt * a.fg_photon;
+      const bool later = child && k < nsub - 1;  // the photon has time left in the step
+      ArenaSpan span;
+      if (O.waves > 0 && arena_reserve(O, gw.wid, gw.cp, n_new, span)) {
+        gw.tp.add(O, gw.wid, em, child, inst);
+        if (child) {
+          const long long rr = span.at(__popcll(em & below));
+          O.x[rr] = x.x;
+          O.y[rr] = x.y;
+          O.z[rr] = x.z;
+          O.px[rr] = f * p.x;
+          O.py[rr] = f * p.y;
+          O.pz[rr] = f * p.z;
+          O.w[rr] = cw;
+          O.parent[rr] = id;
+          O.sub[rr] = (unsigned)k;
+          O.inst[rr] = (unsigned)inst;
+          record_same_step<FMODE>(O, rr, (double)(nsub - k - 1) * h, E, B);
+        }
+        if (q.last) wc.deferred += __popcll(wave_ballot(later));
+      } else {
+        // the arena is full: reserved directly, not advanced in this step
+        wave_append<QED_PHOTON>(a, child, inst, cnt, [&](const qed_soa& o, long long s2) {
+          o.x[s2] = x.x;
+          o.y[s2] = x.y;
+          o.z[s2] = x.z;
+          o.px[s2] = f * p.x;
+          o.py[s2] = f * p.y;
+          o.pz[s2] = f * p.z;
+          o.w[s2] = cw;
+          o.id[s2] = child_id(id, seed, step, (uint32_t)k, kPhotonChild);
+          o.parent[s2] = id;
+          o.birth[s2] = birth_code(step, (uint32_t)k);
+          if (o.n_events) o.n_events[s2] = 0u;
+        });
+        wc.deferred += __popcll(wave_ballot(later));
+      }
+    }
+    if (emit) {
+      // recoil: the lepton keeps p - k (momentum conservation, Sec. IV.F)
+      p = {p.x - f * p.x, p.y - f * p.y, p.z - f * p.z};
+    }
+    if (busy && ++k == nsub) {
+      LEPTON_COL(x, sp)[slot] = x.x;
+      LEPTON_COL(y, sp)[slot] = x.y;
+      LEPTON_COL(z, sp)[slot] = x.z;
+      LEPTON_COL(px, sp)[slot] = p.x;
+      LEPTON_COL(py, sp)[slot] = p.y;
+      LEPTON_COL(pz, sp)[slot] = p.z;
+      uint32_t* ne = LEPTON_COL(n_events, sp);
+      if (ne) ne[slot] = nev;
+      busy = false;
+    }
+  }
+}
+
+// Photons of 64 photon records (lane: record r), each through its tau.  All lanes call.
+template <bool MIXED, int FMODE>
+__device__ __forceinline__ void gen_photons(const StepArgs& a, const GenArgs& q, GenWave& gw,
+                                            const ChildArena& A, long long r, int inst,
+                                            long long slot, double tau, bool act,
+                                            const Series64& ser64, const Series32& ser32,
+                                            BlockStats& bs, LaneCounters& cnt,
+                                            LaneCounters& pcnt, WaveCounters& wc) {
+  const uint64_t below = lanes_below();
+  const uint32_t step = (uint32_t)a.hdr->step;
+  const qed_soa& S = a.sp[QED_PHOTON];
+  uint64_t id = 0, seed = 0;
+  V3 x{}, kv{}, E{}, B{};
+  double chi = 0.0, h = 0.0, hk = 0.0, pref = 0.0;
+  int nsub = 0;
+  bool busy = false;
+  if (act && (a.push_photons || a.pairs)) {
+    id = S.id[slot];
+    x = {S.x[slot], S.y[slot], S.z[slot]};
+    kv = {S.px[slot], S.py[slot], S.pz[slot]};
+    const double kabs = sqrt(dot(kv, kv));
+    if (!(kabs > 0.0) || !isfinite(kabs)) {
+      block_count(bs, kPfNonfinite);
+    } else {
+      seed = a.inst[inst].seed;
+      inherited_fields<FMODE>(a, A, r, inst, E, B);
+      const double inv_k = 1.0 / kabs;
+      chi = chi_of(kv, kabs, E, B, a.eps_r);
+      nsub = 1;
+      if (a.forced > 0) {
+        nsub = a.forced;
+      } else if (a.adaptive && chi > 0.0) {
+        // tau / dt_q with dt_q of Eq. (33)
+        const NsubInfo ni = nsub_from_ratio(tau * (chi * inv_k) * a.inv_pho_scale);
+        nsub = ni.n;
+        if (ni.near_int) block_count(bs, kPfNearInt);
+        if (ni.clamped) block_count(bs, kPfClamped);
+      }
+      if (!isfinite(chi)) block_count(bs, kPfNonfinite);
+      h = nsub == 1 ? tau : tau / (double)nsub;
+      hk = h * inv_k;
+      pref = h * (a.dtfac_per_h * kInvSqrt3Pi) * inv_k;
+      busy = true;
+    }
+  }
+  int k = 0;
+  const ChildArena& O = q.oqa;
+  while (wave_ballot(busy)) {
+    bool pair = false, make = false;
+    double r1 = 0.0, wp = 0.0;
+    if (busy) {
+      if (a.push_photons) x = {x.x + hk * kv.x, x.y + hk * kv.y, x.z + hk * kv.z};
+      ++cnt.subs;
+      if (a.pairs) {
+        const uint4 o = draw_words(id, seed, step, (uint32_t)k, kDraw);
+        pair = pair_decision<MIXED>(a, ser64, ser32, o, chi, pref, pcnt, &r1);
+      }
+      if (pair) {
+        // the photon decays; its pair is created with probability 1 / f_g (Sec. VI)
+        make = a.fg_pair > 1.0
+                   ? generator_runs(id, seed, step, (uint32_t)k, kGenPair, a.inv_fg_pair)
+                   : true;
+        wp = S.w[slot] * a.fg_pair;
+      }
+    }
+    const uint64_t pm = wave_ballot(make);
+    if (pm) {
+      const int n_new = __popcll(pm);
+      wc.pairs += n_new;
+      const bool later = make && k < nsub - 1;
+      ArenaSpan span;
+      if (O.waves > 0 && arena_reserve(O, gw.wid, gw.cq, n_new, span)) {
+        gw.tq.add(O, gw.wid, pm, make, inst);
+        if (make) {
+          const long long rr = span.at(__popcll(pm & below));
+          O.x[rr] = x.x;
+          O.y[rr] = x.y;
+          O.z[rr] = x.z;
+          O.px[rr] = kv.x;
+          O.py[rr] = kv.y;
+          O.pz[rr] = kv.z;
+          O.r1[rr] = r1;
+          O.w[rr] = wp;
+          O.parent[rr] = id;
+          O.sub[rr] = (unsigned)k;
+          O.inst[rr] = (unsigned)inst;
+          record_same_step<FMODE>(O, rr, (double)(nsub - k - 1) * h, E, B);
+        }
+        if (q.last) wc.deferred += 2 * __popcll(wave_ballot(later));
+      } else {
+        // the arena is full: reserved directly, not advanced in this step
+        const double r1c = 1.0 - r1;
+        wave_append<QED_ELECTRON>(a, make, inst, cnt, [&](const qed_soa& o, long long s2) {
+          o.x[s2] = x.x;
+          o.y[s2] = x.y;
+          o.z[s2] = x.z;
+          o.px[s2] = r1 * kv.x;
+          o.py[s2] = r1 * kv.y;
+          o.pz[s2] = r1 * kv.z;
+          o.w[s2] = wp;
+          o.id[s2] = child_id(id, seed, step, (uint32_t)k, kElectronChild);
+          o.parent[s2] = id;
+          o.birth[s2] = birth_code(step, (uint32_t)k);
+          if (o.n_events) o.n_events[s2] = 0u;
+        });
+        wave_append<QED_POSITRON>(a, make, inst, cnt, [&](const qed_soa& o, long long s2) {
+          o.x[s2] = x.x;
+          o.y[s2] = x.y;
+          o.z[s2] = x.z;
+          o.px[s2] = r1c * kv.x;
+          o.py[s2] = r1c * kv.y;
+          o.pz[s2] = r1c * kv.z;
+          o.w[s2] = wp;
+          o.id[s2] = child_id(id, seed, step, (uint32_t)k, kPositronChild);
+          o.parent[s2] = id;
+          o.birth[s2] = birth_code(step, (uint32_t)k);
+          if (o.n_events) o.n_events[s2] = 0u;
+        });
+        wc.deferred += 2 * __popcll(wave_ballot(later));
+      }
+    }
+    if (busy && (pair || ++k == nsub)) {
+      if (a.push_photons) {
+        S.x[slot] = x.x;
+        S.y[slot] = x.y;
+        S.z[slot] = x.z;
+      }
+      if (pair) S.id[slot] = QED_ID_DEAD;
+      busy = false;
+    }
+  }
+}
+
+template <bool MIXED, int FMODE>
+__global__ void __launch_bounds__(256) gen_kernel(StepArgs a, GenArgs q) {
+  using Tab = typename TabType<MIXED>::T;
+  __shared__ BlockStats bs;
+  block_stats_init(bs);
+  __syncthreads();
+  const Tab* tab = MIXED ? reinterpret_cast<const Tab*>(a.tables->ab32)
+                         : reinterpret_cast<const Tab*>(a.tables->ab64);
+  const Series64 ser64 = {a.tables->series[0], a.tables->series[1], a.tables->series[2],
+                          a.tables->series[3], a.tables->series[4]};
+  const Series32 ser32 = {(float)ser64.b0, (float)ser64.b1, (float)ser64.c0, (float)ser64.c1,
+                          (float)ser64.c2};
+  const int lane = lane_id();
+  const int V = (int)gridDim.x * (int)(blockDim.x >> 6);
+  GenWave gw;
+  gw.wid = wave_index();
+  LaneCounters cnt, pcnt;  // pcnt: pair decisions (their largest P is not reduced)
+  cnt.bs = &bs;
+  pcnt.bs = &bs;
+  WaveCounters wc;
+  const int npa = q.ipa.waves;
+  const int nqa = q.iqa.waves;
+  // one producing wavefront's records at a time; a pair record holds two leptons
+  for (int t = gw.wid; t < npa + nqa; t += V) {
+    const bool pairrec = t >= npa;
+    const ChildArena& A = pairrec ? q.iqa : q.ipa;
+    const int sw = pairrec ? t - npa : t;
+    const long long n = (long long)A.nrec[sw];
+    const long long items = pairrec ? 2 * n : n;
+    ArenaWalk walk;
+    for (long long j0 = 0; j0 < items; j0 += 64) {
+      const long long j = j0 + lane;
+      const bool has = j < items;
+      // 64 photon records, or 32 pair records (two leptons each), per batch
+      const long long rb = walk.at(A, sw, pairrec ? (j0 >> 1) : j0);
+      const long long r = rb + (has ? (pairrec ? (lane >> 1) : lane) : 0);
+      const int which = (int)(j & 1);
+      long long slot = -1;
+      double tau = 0.0;
+      int inst = 0;
+      if (has) {
+        slot = (pairrec && which) ? A.slot2[r] : A.slot[r];
+        tau = A.tau[r];
+        inst = (int)A.inst[r];
+      }
+      const bool act = has && slot >= 0 && tau > 0.0;
+      wc.children += __popcll(wave_ballot(act));
+      if (pairrec)
+        gen_leptons<MIXED, FMODE>(a, q, gw, A, r, which ? QED_POSITRON : QED_ELECTRON, inst,
+                                  slot, tau, act, tab, ser64, ser32, bs, cnt, wc);
+      else
+        gen_photons<MIXED, FMODE>(a, q, gw, A, r, inst, slot, tau, act, ser64, ser32, bs, cnt,
+                                  pcnt, wc);
+    }
+  }
+  if (q.opa.waves > 0) {
+    gw.tp.flush(q.opa, gw.wid);
+    if (lane == 0) q.opa.nrec[gw.wid] = (unsigned)gw.cp.n;
+  }
+  if (q.oqa.waves > 0) {
+    gw.tq.flush(q.oqa, gw.wid);
+    if (lane == 0) q.oqa.nrec[gw.wid] = (unsigned)gw.cq.n;
+  }
+  wave_to_block(bs, cnt, wc);
+  __syncthreads();
+  block_stats_accumulate(bs, a.gen_part, q.pass == 1);
 }
 
 #undef LEPTON_COL
@@ -1464,11 +2025,33 @@ static void launch_persistent(const StepArgs& a, LaunchShape lep, LaunchShape ph
     if (a.ex_grid > 0)
       hipLaunchKernelGGL((photon_exact_kernel<MIXED, FMODE>), dim3(a.ex_grid), dim3(256), 0, s, a);
   }
-  const int src = (a.pa.per_wave > 0 ? a.pa.waves : 0) + (a.qa.per_wave > 0 ? a.qa.waves : 0);
+  const int src = a.pa.waves + a.qa.waves;
+  const ChildArena none{};
   if (src > 0) {
-    hipLaunchKernelGGL(arena_scan_kernel, dim3(a.n_inst), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(arena_scan_kernel, dim3(a.n_inst), dim3(1024), 0, s, a, a.pa, a.qa);
+    // with same-step processing the copy also clears generation 1's count matrices
+    const bool gen = a.generations > 0;
     hipLaunchKernelGGL(arena_copy_kernel, dim3((src + kWavesPerBlock - 1) / kWavesPerBlock),
-                       dim3(256), 0, s, a);
+                       dim3(256), 0, s, a, a.pa, a.qa, gen ? a.gpa[1] : none,
+                       gen ? a.gqa[1] : none);
+  }
+  // children through the rest of the step: generation g reads set (g - 1) % 2 (set 0 as the
+  // particle kernels wrote it for g = 1) and writes set g % 2
+  for (int g = 1; g <= a.generations; ++g) {
+    GenArgs q;
+    q.ipa = g == 1 ? a.pa : a.gpa[(g - 1) % 2];
+    q.iqa = g == 1 ? a.qa : a.gqa[(g - 1) % 2];
+    q.opa = a.gpa[g % 2];
+    q.oqa = a.gqa[g % 2];
+    q.pass = g;
+    q.last = g == a.generations ? 1 : 0;
+    hipLaunchKernelGGL((gen_kernel<MIXED, FMODE>), dim3(a.gen_grid), dim3(256), 0, s, a, q);
+    const int gsrc = q.opa.waves + q.oqa.waves;
+    const bool more = g < a.generations;
+    hipLaunchKernelGGL(arena_scan_kernel, dim3(a.n_inst), dim3(1024), 0, s, a, q.opa, q.oqa);
+    hipLaunchKernelGGL(arena_copy_kernel, dim3((gsrc + kWavesPerBlock - 1) / kWavesPerBlock),
+                       dim3(256), 0, s, a, q.opa, q.oqa, more ? a.gpa[(g + 1) % 2] : none,
+                       more ? a.gqa[(g + 1) % 2] : none);
   }
 }
 
@@ -1480,8 +2063,7 @@ static int field_mode(int kind) {
 
 hipError_t launch_step(const StepArgs& a, int precision, LaunchShape lep, LaunchShape pho,
                        bool run_photons, hipStream_t s) {
-  const long long zero_words = (a.pa.per_wave > 0 ? (long long)a.n_inst * a.pa.waves : 0) +
-                              (a.qa.per_wave > 0 ? (long long)a.n_inst * a.qa.waves : 0);
+  const long long zero_words = (long long)a.n_inst * (a.pa.waves + a.qa.waves);
   long long zb = (zero_words + 2047) / 2048;
   if (zb > 1024) zb = 1024;
   hipLaunchKernelGGL(prep_kernel, dim3(1 + (int)zb), dim3(256), 0, s, a, run_photons ? 1 : 0);

@@ -26,7 +26,7 @@ class Engine:
 
     def __init__(self, capacities: Sequence[Tuple[int, int, int]], seeds: Sequence[int],
                  amps: Optional[Sequence[float]] = None, device: str = "cuda:0",
-                 arena_records: Optional[int] = None):
+                 arena_records: Optional[int] = None, same_step: bool = False):
         torch = _torch()
         if not torch.cuda.is_available():
             raise Q.QedError("no HIP device visible: the QED step runs only on the GPU")
@@ -63,9 +63,14 @@ class Engine:
         self.tables = torch.zeros(Q.qed_table_bytes(), dtype=torch.uint8, device=self.device)
         pslots = int(self.cols[2]["x"].numel())
         if arena_records is None:
-            arena_records = min(max(pslots // 8, 1 << 16), 1 << 26)
+            # same-step processing advances only the children that reach an arena (a full
+            # wavefront share defers them), so it gets roomier arenas
+            floor = 1 << 20 if same_step else 1 << 16
+            arena_records = min(max(pslots // 8, floor), 1 << 26)
         self.arena_records = int(arena_records)
-        self.work_bytes = Q.qed_work_bytes(self.n_inst, pslots, self.arena_records)
+        # same_step: room for advancing children in their birth step
+        # (qed_params.same_step_generations > 0)
+        self.work_bytes = Q.qed_work_bytes(self.n_inst, pslots, self.arena_records, same_step)
         self.work = torch.zeros(self.work_bytes, dtype=torch.uint8, device=self.device)
         self.stats_buf = torch.zeros(C.sizeof(Q.qed_stats), dtype=torch.uint8, device=self.device)
         self.step_ctr = torch.zeros(1, dtype=torch.int64, device=self.device)
@@ -195,9 +200,11 @@ class Engine:
     @staticmethod
     def make_params(dt, eps_r, kappa=1.0, t0=0.0, adaptive=1, forced_substeps=0, emission=1,
                     pairs=1, push_photons=1, precision=Q.QED_FP64, freeze_on_drop=0, tile=0,
-                    block=0, grid_blocks=0, f_photon=1.0, f_pair=1.0) -> Q.qed_params:
+                    block=0, grid_blocks=0, f_photon=1.0, f_pair=1.0,
+                    same_step_generations=0) -> Q.qed_params:
         p = Q.qed_params()
         p.f_photon, p.f_pair = float(f_photon), float(f_pair)
+        p.same_step_generations = int(same_step_generations)
         p.dt, p.eps_r, p.kappa, p.t0 = float(dt), float(eps_r), float(kappa), float(t0)
         p.adaptive, p.forced_substeps = int(adaptive), int(forced_substeps)
         p.emission, p.pairs, p.push_photons = int(emission), int(pairs), int(push_photons)

@@ -64,7 +64,8 @@ class qed_params(C.Structure):
                 ("emission", C.c_int), ("pairs", C.c_int), ("push_photons", C.c_int),
                 ("precision", C.c_int), ("freeze_on_drop", C.c_int), ("tile", C.c_int),
                 ("block", C.c_int), ("grid_blocks", C.c_int), ("events", C.c_void_p * 4),
-                ("f_photon", C.c_double), ("f_pair", C.c_double)]
+                ("f_photon", C.c_double), ("f_pair", C.c_double),
+                ("same_step_generations", C.c_int)]
 
 
 class qed_stats(C.Structure):
@@ -74,7 +75,8 @@ class qed_stats(C.Structure):
                 ("near_threshold", C.c_int64), ("nsub_near_int", C.c_int64),
                 ("nsub_clamped", C.c_int64), ("nonfinite", C.c_int64), ("substeps", C.c_int64),
                 ("wave_iters", C.c_int64), ("low_occupancy_iters", C.c_int64),
-                ("early_out", C.c_int64), ("photon_energy", C.c_double),
+                ("early_out", C.c_int64), ("children_advanced", C.c_int64),
+                ("deferred", C.c_int64), ("photon_energy", C.c_double),
                 ("max_p_emit", C.c_double), ("max_p_pair", C.c_double),
                 ("nsub_hist", C.c_int64 * QED_NSUB_HIST),
                 ("photon_hist", C.c_int64 * QED_SPECTRUM_BINS),
@@ -121,7 +123,7 @@ def lib():
         L.qed_build_tables.restype = C.c_int
         L.qed_build_tables.argtypes = [C.c_void_p, C.c_size_t, C.c_void_p]
         L.qed_work_bytes.restype = C.c_size_t
-        L.qed_work_bytes.argtypes = [C.c_int, C.c_int64, C.c_int64]
+        L.qed_work_bytes.argtypes = [C.c_int, C.c_int64, C.c_int64, C.c_int]
         L.qed_step.restype = C.c_int
         L.qed_step.argtypes = [C.c_void_p, C.POINTER(qed_stores), C.POINTER(qed_field),
                                C.POINTER(qed_params), C.c_void_p, C.c_void_p, C.c_void_p,
@@ -163,8 +165,10 @@ def qed_build_tables(d_tables: int, nbytes: int, stream: int) -> None:
     _check(lib().qed_build_tables(d_tables, nbytes, stream), "qed_build_tables")
 
 
-def qed_work_bytes(n_instances: int, photon_slots: int, arena_records: int = 0) -> int:
-    return int(lib().qed_work_bytes(n_instances, photon_slots, arena_records))
+def qed_work_bytes(n_instances: int, photon_slots: int, arena_records: int = 0,
+                   same_step: bool = False) -> int:
+    return int(lib().qed_work_bytes(n_instances, photon_slots, arena_records,
+                                    1 if same_step else 0))
 
 
 def qed_step(d_tables: int, stores: qed_stores, field: qed_field, params: qed_params,

@@ -30,9 +30,11 @@ def params_of(w: W.Workload, **over) -> Q.qed_params:
 
 def engine_single(w: W.Workload, init: Sequence[Dict[str, np.ndarray]],
                   capacity: Optional[Sequence[int]] = None, seed: Optional[int] = None,
-                  build_tables: bool = True, arena_records: Optional[int] = None) -> Engine:
+                  build_tables: bool = True, arena_records: Optional[int] = None,
+                  same_step: bool = False) -> Engine:
     cap = tuple(capacity) if capacity is not None else tuple(w.capacity)
-    e = Engine([cap], [w.seed if seed is None else seed], arena_records=arena_records)
+    e = Engine([cap], [w.seed if seed is None else seed], arena_records=arena_records,
+               same_step=same_step)
     if build_tables:
         e.build_tables()
     for s in range(3):
@@ -41,10 +43,11 @@ def engine_single(w: W.Workload, init: Sequence[Dict[str, np.ndarray]],
 
 
 def engine_batched(w: W.Workload, inits: Sequence[Sequence[Dict[str, np.ndarray]]],
-                   build_tables: bool = True, arena_records: Optional[int] = None) -> Engine:
+                   build_tables: bool = True, arena_records: Optional[int] = None,
+                   same_step: bool = False) -> Engine:
     caps = [tuple(w.instance_capacity)] * w.instances
     e = Engine(caps, list(range(w.instances)), amps=w.instance_amp,
-               arena_records=arena_records)
+               arena_records=arena_records, same_step=same_step)
     if build_tables:
         e.build_tables()
     for i, init in enumerate(inits):

@@ -250,6 +250,44 @@ def batched_initial(w: Workload, lam_m: float = 0.8e-6) -> List[List[Dict[str, n
 
 
 # ---------------------------------------------------------------------------------------
+# Sec. VII cascade development (shower): electrons of gamma_0 = 2e5 moving across a static
+# uniform B of 0.2 E_S; time unit hbar / (m c^2), fields in units of E_S (eps_r = 1)
+# ---------------------------------------------------------------------------------------
+SHOWER_GAMMA0 = 2e5
+SHOWER_B = 0.2
+FINE_STRUCTURE = 7.2973525693e-3
+
+
+def shower_t_rad(gamma0: float = SHOWER_GAMMA0, b: float = SHOWER_B) -> float:
+    """The shower's radiation time 3.85 gamma_0^(1/3) (E_S / H_0)^(2/3) hbar^2 / (m c e^2),
+    in units of hbar / (m c^2) (hbar^2 / (m c e^2) = (hbar / m c^2) / alpha)."""
+    return 3.85 * gamma0 ** (1.0 / 3.0) * (1.0 / b) ** (2.0 / 3.0) / FINE_STRUCTURE
+
+
+def shower(n: int = 1000, dt: float = 25_000.0, steps: int = 3, kappa: float = 0.25,
+           seed: int = 0, capacity: Optional[tuple] = None,
+           precision: str = "f64") -> Workload:
+    """n seed electrons at the origin with p = sqrt(gamma_0^2 - 1) along x, B along z.
+    At dt = 25000 (0.28 t_rad) and kappa = 0.25 the seeds take about 400 sub-steps a step;
+    the children of a step need about 16 generations of same-step processing."""
+    cap = capacity if capacity is not None else (2000 * n, 2000 * n, 40_000 * n)
+    return Workload(
+        name="shower", eps_r=1.0, dt=dt, n_steps=steps,
+        field=FieldSpec(kind=FIELD_UNIFORM, b0=(0.0, 0.0, SHOWER_B)),
+        capacity=tuple(cap), seed=seed, kappa=kappa, n_seed=n, precision=precision,
+        description=f"{n} e-, gamma0={SHOWER_GAMMA0:g} across B={SHOWER_B} E_S, dt={dt:g} "
+                    f"hbar/mc^2 ({dt / shower_t_rad():.3f} t_rad), kappa={kappa}, "
+                    f"{steps} steps")
+
+
+def shower_initial(w: Workload) -> List[Dict[str, np.ndarray]]:
+    n = w.n_seed
+    zero = np.zeros(n)
+    pabs = np.full(n, math.sqrt(SHOWER_GAMMA0 * SHOWER_GAMMA0 - 1.0))
+    return [_seed_columns(zero, zero, zero, pabs, zero, zero), empty_columns(), empty_columns()]
+
+
+# ---------------------------------------------------------------------------------------
 # Photon-energy binning used for spectra (130 log bins of eps/mc^2 in [1e-8, 1e5])
 # ---------------------------------------------------------------------------------------
 SPECTRUM_BINS = 130

@@ -34,11 +34,12 @@ def _sorted(c):
     return {k: (v[order] if v is not None else None) for k, v in c.items()}
 
 
-def compare_species(gpu, orc_cols, species, rtol=1e-12, label="", wtol=0.0):
+def compare_species(gpu, orc_cols, species, rtol=1e-12, label="", wtol=0.0, floor=(1.0, 1.0)):
     """Bit-exact ids, parents, births (and event counts for leptons); momenta and positions
-    within rtol of max(|v|, 1); weights exact, or within wtol relative where thinning has
-    rescaled them (its factor is a ratio of sums taken in different orders on the two
-    sides).  Removed photons are compared by count."""
+    within rtol of max(|v|, floor) (floor: momentum and position scales, 1 by default);
+    weights exact, or within wtol relative where thinning has rescaled them (its factor is
+    a ratio of sums taken in different orders on the two sides).  Removed photons are
+    compared by count."""
     g = dict(gpu)
     o = dict(orc_cols)
     if species == PHOTON:
@@ -58,19 +59,19 @@ def compare_species(gpu, orc_cols, species, rtol=1e-12, label="", wtol=0.0):
     else:
         np.testing.assert_allclose(g["w"], o["w"], rtol=wtol, atol=0, err_msg=label)
     worst = {}
-    for grp in (("px", "py", "pz"), ("x", "y", "z")):
+    for grp, fl in ((("px", "py", "pz"), floor[0]), (("x", "y", "z"), floor[1])):
         a = np.stack([g[c] for c in grp], 1)
         b = np.stack([o[c] for c in grp], 1)
-        scale = np.maximum(np.linalg.norm(b, axis=1), 1.0)
+        scale = np.maximum(np.linalg.norm(b, axis=1), fl)
         err = (np.abs(a - b).max(1) / scale) if len(a) else np.zeros(0)
         worst[grp[0]] = float(err.max()) if len(err) else 0.0
         assert worst[grp[0]] <= rtol, f"{label}: {grp} rel err {worst[grp[0]]:.3e}"
     return worst
 
 
-def compare_all(engine, ostores, inst=0, rtol=1e-12, label="", wtol=0.0):
+def compare_all(engine, ostores, inst=0, rtol=1e-12, label="", wtol=0.0, floor=(1.0, 1.0)):
     out = {}
     for s in range(3):
         out[s] = compare_species(engine.read(inst, s), ostores[s].view(), s, rtol,
-                                 f"{label} species {s}", wtol=wtol)
+                                 f"{label} species {s}", wtol=wtol, floor=floor)
     return out

@@ -76,12 +76,19 @@ def test_host_side_queries(Q):
     # the overflow list
     assert abs(Q.qed_work_bytes(1, 2000) - w1 - 16000) < 512
     # arenas: 72 bytes per photon record, 80 per pair record (a quarter of the records,
-    # at least 4096), plus the count matrices and per-wavefront totals
+    # at least 4096), plus the count matrices, per-wavefront totals and 4 bytes per pool
+    # chunk of 256 records
     a0 = Q.qed_work_bytes(1, 1000, 1 << 20)
     a1 = Q.qed_work_bytes(1, 1000, 1 << 21)
-    assert a0 > w1 and abs((a1 - a0) - (72 + 20) * (1 << 20)) < 8192
+    assert a0 > w1 and abs((a1 - a0) - (72 + 20) * (1 << 20)) < 32768
     # no arenas above 1024 instances
     assert Q.qed_work_bytes(1025, 1000, 1 << 20) == Q.qed_work_bytes(1025, 1000)
+    # same-step processing: per record 64 (photon) and 72 (pair) bytes more, and a second
+    # set of arenas
+    s0 = Q.qed_work_bytes(1, 1000, 1 << 20, True)
+    s1 = Q.qed_work_bytes(1, 1000, 1 << 21, True)
+    assert abs((s1 - s0) - 2 * (136 + 152 // 4) * (1 << 20)) < 65536
+    assert Q.qed_work_bytes(1, 1000, 0, True) == Q.qed_work_bytes(1, 1000)
     assert Q.lib().qed_status_string(1) == b"invalid argument"
     # thinning: per-instance plan and partial sums plus a 4-byte hole list per slot
     t1, t2 = Q.qed_thin_work_bytes(1, 1000), Q.qed_thin_work_bytes(1, 2000)
