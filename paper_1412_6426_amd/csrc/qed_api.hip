@@ -77,11 +77,12 @@ size_t qed_work_bytes(int n_instances, int64_t photon_slots, int64_t arena_recor
 namespace {
 
 // Column pointers of a child arena inside the workspace, as seen by a producing kernel of
-// `waves` wavefronts: half the records are the wavefronts' shares (a multiple of 64 each),
-// the rest a pool of chunks.  same_step: the layout has the same-step columns;
-// use_same_step: point at them (else they stay null).
+// `waves` wavefronts: with a pool, half the records are the wavefronts' equal shares and
+// the rest a pool of chunks; without, all are shares.  same_step: the layout has the
+// same-step columns; use_same_step: point at them (else they stay null).
 ChildArena arena_at(uint8_t* w, size_t cols, size_t cnt, size_t nrec, size_t base, size_t chain,
-                    long long cap, bool pair, int waves, bool same_step, bool use_same_step) {
+                    long long cap, bool pair, int waves, bool same_step, bool use_same_step,
+                    bool pool) {
   ChildArena A{};
   if (cap <= 0 || waves <= 0) return A;
   const size_t col8 = ((size_t)cap * 8 + 255) & ~(size_t)255;
@@ -116,7 +117,7 @@ ChildArena arena_at(uint8_t* w, size_t cols, size_t cnt, size_t nrec, size_t bas
   A.next = reinterpret_cast<unsigned int*>(w + chain + 256 +
                                            ((sizeof(unsigned int) * kMaxWaves + 255) & ~(size_t)255));
   A.waves = waves;
-  A.per_wave = ((cap / 2) / waves) & ~63ll;
+  A.per_wave = (pool ? cap / 2 : cap) / waves;
   A.pool0 = A.per_wave * waves;
   A.nchunks = (cap - A.pool0) / kArenaChunk;
   return A;
@@ -265,11 +266,14 @@ qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_fi
                                 (long long)kMaxWaves * kCandSlack) / pho_waves;
   if (arena > 0) {
     const bool on = G > 0;
+    // the lepton kernel continues in the pool only in its extended form (same-step
+    // processing or a generator factor); the pair and generation producers always do
+    const bool lep_pool = on || P.f_photon > 1.0;
     a.pa = arena_at(w, L.ph_cols[0], L.ph_cnt[0], L.ph_nrec[0], L.ph_base[0], L.ph_chain[0],
-                    L.ph_cap, false, lep_waves, L.same_step, on);
+                    L.ph_cap, false, lep_waves, L.same_step, on, lep_pool);
     if (a.ex_grid > 0)
       a.qa = arena_at(w, L.pr_cols[0], L.pr_cnt[0], L.pr_nrec[0], L.pr_base[0], L.pr_chain[0],
-                      L.pr_cap, true, a.ex_grid * 4, L.same_step, on);
+                      L.pr_cap, true, a.ex_grid * 4, L.same_step, on, true);
     if (on) {
       a.generations = G;
       a.gen_grid = kGenGridBlocks;
@@ -277,9 +281,9 @@ qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_fi
       const int gen_waves = kGenGridBlocks * 4;
       for (int s2 = 0; s2 < 2; ++s2) {
         a.gpa[s2] = arena_at(w, L.ph_cols[s2], L.ph_cnt[s2], L.ph_nrec[s2], L.ph_base[s2],
-                             L.ph_chain[s2], L.ph_cap, false, gen_waves, true, true);
+                             L.ph_chain[s2], L.ph_cap, false, gen_waves, true, true, true);
         a.gqa[s2] = arena_at(w, L.pr_cols[s2], L.pr_cnt[s2], L.pr_nrec[s2], L.pr_base[s2],
-                             L.pr_chain[s2], L.pr_cap, true, gen_waves, true, true);
+                             L.pr_chain[s2], L.pr_cap, true, gen_waves, true, true, true);
       }
     }
   }

@@ -482,15 +482,28 @@ __device__ __forceinline__ bool arena_reserve(const ChildArena& A, int wid, Aren
   return true;
 }
 
-// Record index of the j-th record of producing wavefront sw, for j visited in increasing
-// order in wavefront-uniform steps that are multiples of 32 (so a batch of 64 records, or
-// of 32 pair records, lies within one share or chunk).
+// The share-only form: false once the ballot does not fit in the rest of the share.
+__device__ __forceinline__ bool share_reserve(const ChildArena& A, int wid, ArenaCursor& c,
+                                              int n_new, ArenaSpan& s) {
+  if (c.n + n_new > A.per_wave) return false;
+  s.share = (long long)wid * A.per_wave + c.n;
+  s.k0 = s.k1 = n_new;
+  s.c0 = s.c1 = 0;
+  c.n += n_new;
+  return true;
+}
+
+// Record indices of producing wavefront sw's records, read in batches [j0, j0 + m) with
+// m <= 64 and j0 increasing: advance() (wavefront-uniform) moves to the pool chunk that
+// holds the batch's first pool record; index() gives a lane's record j of the batch (below
+// n, the wavefront's record count), which lies in the share, that chunk or the next one.
 struct ArenaWalk {
   unsigned chunk = 0xFFFFFFFFu;
   long long start = 0;  // the chunk holds pool records [start, start + kArenaChunk) of sw
-  __device__ __forceinline__ long long at(const ChildArena& A, int sw, long long j) {
-    if (j < A.per_wave) return (long long)sw * A.per_wave + j;
-    const long long jp = j - A.per_wave;
+  __device__ __forceinline__ void advance(const ChildArena& A, int sw, long long j0, long long m,
+                                          long long n) {
+    if (n <= A.per_wave || j0 + m <= A.per_wave) return;  // the batch is all in the share
+    const long long jp = j0 > A.per_wave ? j0 - A.per_wave : 0;
     if (chunk == 0xFFFFFFFFu) {
       chunk = A.first[sw];
       start = 0;
@@ -499,7 +512,12 @@ struct ArenaWalk {
       chunk = A.next[chunk];
       start += kArenaChunk;
     }
-    return A.pool0 + (long long)chunk * kArenaChunk + (jp - start);
+  }
+  __device__ __forceinline__ long long index(const ChildArena& A, int sw, long long j) const {
+    if (j < A.per_wave) return (long long)sw * A.per_wave + j;
+    const long long jp = j - A.per_wave;
+    if (jp < start + kArenaChunk) return A.pool0 + (long long)chunk * kArenaChunk + (jp - start);
+    return A.pool0 + (long long)A.next[chunk] * kArenaChunk + (jp - start - kArenaChunk);
   }
 };
 
@@ -727,7 +745,11 @@ __device__ __forceinline__ void flush_pairs(const StepArgs& a, PairStage& sg, in
 // ------------------------------------------------------------------------------------
 // leptons
 // ------------------------------------------------------------------------------------
-template <bool MIXED, int FMODE>
+// EXT: the extensions are compiled in -- the generator factor, and same-step processing
+// (children also get their time left and the parent's fields; a full share continues in
+// pool chunks).  Without them a full share falls back to direct reservation, and the plain
+// step's kernel stays lean.
+template <bool MIXED, int FMODE, bool EXT>
 __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
   using Tab = typename TabType<MIXED>::T;
   __shared__ Tab tab[kTableN];
@@ -879,12 +901,15 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
     // probability 1 / f_g and carries f_g times the lepton's weight; the recoil below
     // happens at every event.
     bool child = emit;
-    if (emit && a.fg_photon > 1.0)
+    if (EXT && emit && a.fg_photon > 1.0)
       child = generator_runs(id, seed, step, (uint32_t)k, kGenPhoton, a.inv_fg_photon);
-    const double cw = wgt * a.fg_photon;
+    const double cw = EXT ? wgt * a.fg_photon : wgt;
+    const bool ss = EXT && a.generations > 0;
     const uint64_t em = wave_ballot(child);
     ArenaSpan span;
-    if (em && pa.waves > 0 && arena_reserve(pa, wid, acur, __popcll(em), span)) {
+    if (em && pa.waves > 0 &&
+        (EXT ? arena_reserve(pa, wid, acur, __popcll(em), span)
+             : share_reserve(pa, wid, acur, __popcll(em), span))) {
       const int n_new = __popcll(em);
       wc.events += n_new;
       tally.add(pa, wid, em, child, inst);
@@ -900,13 +925,13 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
         pa.parent[r] = id;
         pa.sub[r] = (unsigned)k;
         pa.inst[r] = (unsigned)inst;
-        if (a.generations > 0) record_same_step<FMODE>(pa, r, (double)(nsub - k - 1) * h, E, B);
+        if (ss) record_same_step<FMODE>(pa, r, (double)(nsub - k - 1) * h, E, B);
       }
     } else if (em) {
       const int n_new = __popcll(em);
       wc.events += n_new;
       // reserved directly in the stores: not advanced in this step
-      if (a.generations > 0) wc.deferred += __popcll(wave_ballot(child && k < nsub - 1));
+      if (ss) wc.deferred += __popcll(wave_ballot(child && k < nsub - 1));
       if (staged + n_new > kStageCap) {
         flush_stage(a, sg, staged, cnt);
         staged = 0;
@@ -1532,7 +1557,8 @@ __global__ void __launch_bounds__(256) arena_copy_kernel(StepArgs a, ChildArena 
     for (long long j0 = 0; j0 < n; j0 += 64) {
       const long long j = j0 + lane;
       const bool has = j < n;
-      const long long r = walk.at(A, sw, j0) + (has ? lane : 0);
+      walk.advance(A, sw, j0, 64, n);
+      const long long r = has ? walk.index(A, sw, j) : 0;
       const int li = has ? (int)A.inst[r] : -1;
       unsigned local = 0;
       uint64_t m = wave_ballot(has);
@@ -1975,8 +2001,8 @@ __global__ void __launch_bounds__(256) gen_kernel(StepArgs a, GenArgs q) {
       const long long j = j0 + lane;
       const bool has = j < items;
       // 64 photon records, or 32 pair records (two leptons each), per batch
-      const long long rb = walk.at(A, sw, pairrec ? (j0 >> 1) : j0);
-      const long long r = rb + (has ? (pairrec ? (lane >> 1) : lane) : 0);
+      walk.advance(A, sw, pairrec ? (j0 >> 1) : j0, pairrec ? 32 : 64, n);
+      const long long r = has ? walk.index(A, sw, pairrec ? (j >> 1) : j) : 0;
       const int which = (int)(j & 1);
       long long slot = -1;
       double tau = 0.0;
@@ -2016,7 +2042,12 @@ template <bool MIXED, int FMODE>
 static void launch_persistent(const StepArgs& a, LaunchShape lep, LaunchShape pho,
                               bool run_photons, hipStream_t s) {
   if (a.events[0]) (void)hipEventRecord(a.events[0], s);
-  hipLaunchKernelGGL((lepton_kernel<MIXED, FMODE>), dim3(lep.grid), dim3(lep.block), 0, s, a);
+  if (a.generations > 0 || a.fg_photon > 1.0)
+    hipLaunchKernelGGL((lepton_kernel<MIXED, FMODE, true>), dim3(lep.grid), dim3(lep.block), 0,
+                       s, a);
+  else
+    hipLaunchKernelGGL((lepton_kernel<MIXED, FMODE, false>), dim3(lep.grid), dim3(lep.block), 0,
+                       s, a);
   if (a.events[1]) (void)hipEventRecord(a.events[1], s);
   if (run_photons) {
     if (a.events[2]) (void)hipEventRecord(a.events[2], s);
@@ -2087,7 +2118,8 @@ static int occupancy(bool photon, int block) {
   int nb = 0;
   const hipError_t e =
       photon ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, photon_kernel<MIXED, FMODE>, block, 0)
-             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lepton_kernel<MIXED, FMODE>, block, 0);
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lepton_kernel<MIXED, FMODE, false>,
+                                                            block, 0);
   return (e != hipSuccess || nb < 1) ? 1 : nb;
 }
 

@@ -65,7 +65,7 @@ class Engine:
         if arena_records is None:
             # same-step processing advances only the children that reach an arena (a full
             # wavefront share defers them), so it gets roomier arenas
-            floor = 1 << 20 if same_step else 1 << 16
+            floor = 1 << 20 if same_step else 1 << 18
             arena_records = min(max(pslots // 8, floor), 1 << 26)
         self.arena_records = int(arena_records)
         # same_step: room for advancing children in their birth step
