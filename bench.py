@@ -408,6 +408,122 @@ def cpu_baseline(args):
                        f"{dt:.1f} s), FP64 C oracle, OpenMP over particles")
 
 
+def gpu_shower(args):
+    """Sec. VII cascade development (the shower) at the paper's scale: 10^3 runs, as 8
+    instances of 125 seed electrons (gamma_0 = 2e5 across B = 0.2 E_S), counted every 25000
+    hbar / m c^2 up to `shower_samples` times that (1.39 t_rad for 5): the particles of each
+    species above 1e-3 gamma_0 m c^2, weighted, per instance.  Three runs:
+      small_dt            dt = 62.5, one sub-step per particle (the reference);
+      large_dt_same_step  dt = 25000, about 400 lepton sub-steps a step at kappa = 0.25,
+                          children advanced in their birth step (16 generations);
+      ..._kappa_0.1       the same with sub-steps 2.5 times shorter;
+      large_dt_next_step  the same large step with children left for the next step.
+    Each run's steps are timed with HIP events on the engine's stream (the counting is
+    not), and its counts are compared with the reference's as z-scores over the 8
+    instances."""
+    import math
+    import numpy as np
+    import torch
+    from paper_1412_6426_amd import qed as Q
+    from paper_1412_6426_amd import runner as R
+    from paper_1412_6426_amd import workloads as W
+    from paper_1412_6426_amd.engine import Engine
+
+    n_inst = 8
+    per = max(args.shower_seeds // n_inst, 1)
+    interval = 25_000.0
+    thr = 1e-3 * W.SHOWER_GAMMA0
+    caps = (args.shower_lepton_cap // n_inst, args.shower_lepton_cap // n_inst,
+            args.shower_photon_cap // n_inst)
+    dead = -1  # the removed-photon id 2^64 - 1, as the int64 the id column holds
+    runs = {}
+    for name, dt, kappa, G in (("small_dt", 62.5, 1.0, 0),
+                               ("large_dt_same_step", interval, 0.25, 16),
+                               ("large_dt_same_step_kappa_0.1", interval, 0.1, 16),
+                               ("large_dt_next_step", interval, 0.25, 0)):
+        print(f"bench: shower, {name}", file=sys.stderr, flush=True)
+        sps = int(round(interval / dt))
+        w = W.shower(n=per, dt=dt, steps=sps * args.shower_samples, kappa=kappa, capacity=caps)
+        # a large step's children (all generations) pass through the arenas: size them
+        # for the step's photons
+        arena = min(args.shower_photon_cap // 2, 1 << 27) if G > 0 else None
+        e = Engine([caps] * n_inst, seeds=list(range(n_inst)), same_step=G > 0,
+                   arena_records=arena)
+        e.build_tables()
+        init = W.shower_initial(w)
+        for i in range(n_inst):
+            for s in range(3):
+                e.load(i, s, init[s])
+        field = R.field_of(w)
+        params = R.params_of(w, same_step_generations=G)
+        K = sps * args.shower_samples
+        log = torch.zeros(K * e.stats_buf.numel(), dtype=torch.uint8, device=e.device)
+        cnt = torch.zeros(1, dtype=torch.int64, device=e.device)
+        stream = torch.cuda.Stream()
+        sp = stream.cuda_stream
+        hip = HipEvents()
+        evs = hip.create(2 * args.shower_samples)
+        counts = np.zeros((args.shower_samples, n_inst, 3))
+        e.set_step(0)
+        torch.cuda.synchronize()
+        for m in range(args.shower_samples):
+            with torch.cuda.stream(stream):
+                hip.lib.hipEventRecord(C.c_void_p(evs[2 * m]), C.c_void_p(sp))
+                for _ in range(sps):
+                    e.step(field, params, stream=sp)
+                    Q.qed_append_stats(e.stats_buf.data_ptr(), log.data_ptr(), K, cnt.data_ptr(),
+                                       sp)
+                hip.lib.hipEventRecord(C.c_void_p(evs[2 * m + 1]), C.c_void_p(sp))
+            torch.cuda.synchronize()
+            live = e.counts()
+            for i in range(n_inst):
+                for s in range(3):
+                    b, n = int(e.base[i, s]), int(live[i, s])
+                    if n == 0:
+                        continue
+                    col = e.cols[s]
+                    p2 = (col["px"][b:b + n] ** 2 + col["py"][b:b + n] ** 2 +
+                          col["pz"][b:b + n] ** 2)
+                    wgt = col["w"][b:b + n]
+                    if s == Q.QED_PHOTON:
+                        above = (p2 > thr * thr) & (col["id"][b:b + n] != dead)
+                    else:
+                        above = (1.0 + p2) > thr * thr
+                    counts[m, i, s] = float((wgt * above).sum().item())
+        step_ms = sum(hip.elapsed_ms(evs[2 * m], evs[2 * m + 1])
+                      for m in range(args.shower_samples))
+        hip.destroy(evs)
+        recs = _stats_records(log.cpu().numpy().tobytes(), K)
+        runs[name] = dict(
+            dt=dt, kappa=kappa, generations=G, steps=K, step_ms=step_ms,
+            substeps=int(sum(r.substeps for r in recs)),
+            particle_steps=int(sum(sum(r.advanced) for r in recs)),
+            children_advanced=int(sum(r.children_advanced for r in recs)),
+            deferred=int(sum(r.deferred for r in recs)),
+            dropped=int(sum(r.dropped for r in recs)),
+            saturated=int(sum(r.saturated for r in recs)),
+            final_counts=[int(x) for x in e.counts().sum(0)],
+            counts=counts)
+        del e, log
+        torch.cuda.empty_cache()
+    ref = runs["small_dt"]["counts"]
+    out = dict(workload=f"{n_inst} x {per} e-, gamma0 = {W.SHOWER_GAMMA0:g} across "
+                        f"B = {W.SHOWER_B} E_S; counts above {thr:g} m c^2 every "
+                        f"{interval:g} hbar/mc^2 (t_rad = {W.shower_t_rad():.4g})",
+               t=[interval * (m + 1) for m in range(args.shower_samples)])
+    for name, r in runs.items():
+        c = r.pop("counts")
+        r["mean_counts"] = c.mean(1).round(2).tolist()  # [sample][species], per instance
+        if name != "small_dt":
+            se = np.sqrt(c.var(1, ddof=1) / n_inst + ref.var(1, ddof=1) / n_inst)
+            z = (c.mean(1) - ref.mean(1)) / np.where(se > 0, se, np.inf)
+            r["z_vs_small_dt"] = z.round(2).tolist()
+            r["max_abs_z"] = float(np.abs(z).max())
+            r["speedup_vs_small_dt"] = runs["small_dt"]["step_ms"] / r["step_ms"]
+        out[name] = r
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -432,6 +548,12 @@ def main():
                     help="skip the cascade run past the capacity with thinning")
     ap.add_argument("--no-yee", action="store_true",
                     help="skip the standing-wave cascade on the 256^3 Yee grid")
+    ap.add_argument("--no-shower", action="store_true",
+                    help="skip the Sec. VII shower at small and large time steps")
+    ap.add_argument("--shower-seeds", type=int, default=1000)
+    ap.add_argument("--shower-samples", type=int, default=5)
+    ap.add_argument("--shower-photon-cap", type=int, default=300_000_000)
+    ap.add_argument("--shower-lepton-cap", type=int, default=20_000_000)
     ap.add_argument("--no-tune", action="store_true",
                     help="use --tile / --grid-blocks for every step instead of tuning")
     args = ap.parse_args()
@@ -545,6 +667,8 @@ def main():
             thin_ms=rf["thin_ms"], lep_ms=rf["lep_ms"], pho_ms=rf["pho_ms"],
             final_counts=rf["final_counts"], pairs=rf["pairs"], emitted=rf["emitted"],
             f_photon=4.0, f_pair=1.0, eager_matches_graph=rf["eager_matches_graph"])
+    if not args.no_shower:
+        line["shower_time_step_invariance"] = gpu_shower(args)
     if not args.no_yee:
         print("bench: standing-wave cascade on the Yee grid", file=sys.stderr, flush=True)
         line["standing_wave_grid"] = gpu_run_yee(args, args.precision)
