@@ -550,6 +550,8 @@ def main():
                     help="skip the standing-wave cascade on the 256^3 Yee grid")
     ap.add_argument("--no-shower", action="store_true",
                     help="skip the Sec. VII shower at small and large time steps")
+    ap.add_argument("--shower-only", action="store_true",
+                    help="run only the shower comparison and print its record (profiling)")
     ap.add_argument("--shower-seeds", type=int, default=1000)
     ap.add_argument("--shower-samples", type=int, default=5)
     ap.add_argument("--shower-photon-cap", type=int, default=300_000_000)
@@ -566,6 +568,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
+    if args.shower_only:
+        print(json.dumps({"shower_time_step_invariance": gpu_shower(args)}), flush=True)
+        return
     print(f"bench: rotating-E cascade, {args.seeds} seeds, precision {args.precision}",
           file=sys.stderr, flush=True)
     r = gpu_run(args, args.precision)

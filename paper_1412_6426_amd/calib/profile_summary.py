@@ -26,7 +26,7 @@ COPY_BYTES = 800_000_000  # hbm_copy: 10^8 doubles read and 10^8 written per lau
 
 
 def _short(name: str) -> str:
-    n = name.replace("void ", "")
+    n = name.replace("void ", "").replace("(anonymous namespace)::", "")
     n = n.split("(")[0]
     return n.replace("qedk::", "")
 
