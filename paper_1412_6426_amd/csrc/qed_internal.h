@@ -20,7 +20,7 @@ constexpr int kExactGridBlocks = 512;
 // word per (instance, wavefront)); above it every append reserves store slots directly.
 constexpr int kArenaMaxInstances = 1024;
 // Workgroups of the generation kernel (same-step processing of children).
-constexpr int kGenGridBlocks = 256;
+constexpr int kGenGridBlocks = 512;  // 2 wavefronts per SIMD on 256 CUs
 // Candidate entries per photon wavefront beyond its even share of the photon slots.
 constexpr int kCandSlack = 64;
 

@@ -1696,61 +1696,132 @@ struct GenWave {
   ArenaTally tp, tq;
 };
 
-// Leptons of 64 pair records' electrons and positrons (lane: record r, species sp), each
-// through its tau.  All 64 lanes call.
+// A wavefront's stream of children: the records of producing wavefronts wid, wid + V, ...
+// of arena A, one item per photon record or two (electron, positron) per pair record,
+// handed out in pieces of consecutive items of one producing wavefront.
+struct GenStream {
+  int t = 0, V = 1;
+  long long j = 0, n = 0;  // next item, items of producing wavefront t
+  bool pair = false, open = false;
+  ArenaWalk walk;
+  __device__ __forceinline__ void init(const ChildArena& A, int wid, int v, bool is_pair) {
+    t = wid;
+    V = v;
+    pair = is_pair;
+    open = A.waves > 0 && t < A.waves;
+    n = open ? (pair ? 2 : 1) * (long long)A.nrec[t] : 0;
+    j = 0;
+  }
+  // The next piece [j0, j0 + take), take <= want <= 64; false once the stream is exhausted.
+  // Wavefront-uniform; all lanes call.
+  __device__ __forceinline__ bool next(const ChildArena& A, int want, long long& j0, int& take) {
+    while (open && j >= n) {
+      t += V;
+      if (t >= A.waves) {
+        open = false;
+        break;
+      }
+      n = (pair ? 2 : 1) * (long long)A.nrec[t];
+      j = 0;
+      walk = ArenaWalk{};
+    }
+    if (!open) return false;
+    take = (int)((long long)want < n - j ? (long long)want : n - j);
+    j0 = j;
+    const long long rec0 = pair ? (j0 >> 1) : j0;
+    const long long rec1 = pair ? ((j0 + take + 1) >> 1) : j0 + take;
+    walk.advance(A, t, rec0, rec1 - rec0, pair ? (n >> 1) : n);
+    j += take;
+    return true;
+  }
+  // Record holding item jj of the current piece.
+  __device__ __forceinline__ long long record(const ChildArena& A, long long jj) const {
+    return walk.index(A, t, pair ? (jj >> 1) : jj);
+  }
+};
+
+// Electrons and positrons of the input pair records, each advanced through its tau; a lane
+// whose lepton has done all its sub-steps takes the next one from the wavefront's stream.
 template <bool MIXED, int FMODE>
-__device__ __forceinline__ void gen_leptons(const StepArgs& a, const GenArgs& q, GenWave& gw,
-                                            const ChildArena& A, long long r, int sp, int inst,
-                                            long long slot, double tau, bool act,
-                                            const typename TabType<MIXED>::T* tab,
-                                            const Series64& ser64, const Series32& ser32,
-                                            BlockStats& bs, LaneCounters& cnt, WaveCounters& wc) {
+__device__ __forceinline__ void gen_lepton_phase(const StepArgs& a, const GenArgs& q,
+                                                 GenWave& gw, int V,
+                                                 const typename TabType<MIXED>::T* tab,
+                                                 const Series64& ser64, const Series32& ser32,
+                                                 BlockStats& bs, LaneCounters& cnt,
+                                                 WaveCounters& wc) {
+  const ChildArena& A = q.iqa;
+  const ChildArena& O = q.opa;
   const uint64_t below = lanes_below();
   const uint32_t step = (uint32_t)a.hdr->step;
+  GenStream st;
+  st.init(A, gw.wid, V, true);
+  long long slot = -1;
+  int sp = 0, inst = 0, nsub = 0, k = 0;
   V3 x{}, p{}, E{}, B{};
   uint64_t id = 0, seed = 0;
   double wgt = 0.0, h = 0.0, dtfac = 0.0, qh2 = 0.0;
   uint32_t nev = 0;
-  int nsub = 0;
-  if (act) {
-    x = {LEPTON_COL(x, sp)[slot], LEPTON_COL(y, sp)[slot], LEPTON_COL(z, sp)[slot]};
-    p = {LEPTON_COL(px, sp)[slot], LEPTON_COL(py, sp)[slot], LEPTON_COL(pz, sp)[slot]};
-    id = LEPTON_COL(id, sp)[slot];
-    wgt = LEPTON_COL(w, sp)[slot];
-    uint32_t* ne = LEPTON_COL(n_events, sp);
-    nev = ne ? ne[slot] : 0u;
-    seed = a.inst[inst].seed;
-    inherited_fields<FMODE>(a, A, r, inst, E, B);
-    const double g = sqrt(1.0 + dot(p, p));
-    const double chi = chi_of(p, g, E, FMODE == kFieldE ? V3{0.0, 0.0, 0.0} : B, a.eps_r);
-    nsub = 1;
-    if (a.forced > 0) {
-      nsub = a.forced;
-    } else if (a.adaptive && chi > 0.0) {
-      NsubInfo ni;
-      if (MIXED) {
-        const float rr = (float)(chi / g);
-        const float ratio = (float)tau * cbrtf(rr * rr) * (float)a.inv_lep_scale;
-        ni = nsub_from_ratio((double)ratio);
-      } else {
-        ni = nsub_from_ratio(substep_ratio_lepton(tau, chi, g, a.inv_lep_scale));
+  while (true) {
+    // ---- refill idle lanes ----
+    uint64_t freem = wave_ballot(slot < 0);
+    while (freem) {
+      long long j0;
+      int take;
+      if (!st.next(A, __popcll(freem), j0, take)) break;
+      const int rank = __popcll(freem & below);
+      bool act = false;
+      if (slot < 0 && rank < take) {
+        const long long jj = j0 + rank;
+        const long long r = st.record(A, jj);
+        const long long sl = (jj & 1) ? A.slot2[r] : A.slot[r];
+        const double tau = A.tau[r];
+        if (sl >= 0 && tau > 0.0) {
+          act = true;
+          sp = (jj & 1) ? QED_POSITRON : QED_ELECTRON;
+          inst = (int)A.inst[r];
+          x = {LEPTON_COL(x, sp)[sl], LEPTON_COL(y, sp)[sl], LEPTON_COL(z, sp)[sl]};
+          p = {LEPTON_COL(px, sp)[sl], LEPTON_COL(py, sp)[sl], LEPTON_COL(pz, sp)[sl]};
+          id = LEPTON_COL(id, sp)[sl];
+          wgt = LEPTON_COL(w, sp)[sl];
+          uint32_t* ne = LEPTON_COL(n_events, sp);
+          nev = ne ? ne[sl] : 0u;
+          seed = a.inst[inst].seed;
+          inherited_fields<FMODE>(a, A, r, inst, E, B);
+          const double g = sqrt(1.0 + dot(p, p));
+          const double chi = chi_of(p, g, E, FMODE == kFieldE ? V3{0.0, 0.0, 0.0} : B, a.eps_r);
+          nsub = 1;
+          if (a.forced > 0) {
+            nsub = a.forced;
+          } else if (a.adaptive && chi > 0.0) {
+            NsubInfo ni;
+            if (MIXED) {
+              const float rr = (float)(chi / g);
+              const float ratio = (float)tau * cbrtf(rr * rr) * (float)a.inv_lep_scale;
+              ni = nsub_from_ratio((double)ratio);
+            } else {
+              ni = nsub_from_ratio(substep_ratio_lepton(tau, chi, g, a.inv_lep_scale));
+            }
+            nsub = ni.n;
+            if (ni.near_int) block_count(bs, kPfNearInt);
+            if (ni.clamped) block_count(bs, kPfClamped);
+          }
+          if (!isfinite(chi)) block_count(bs, kPfNonfinite);
+          h = tau / (double)nsub;
+          dtfac = h * a.dtfac_per_h;
+          qh2 = (sp == QED_ELECTRON ? -0.5 : 0.5) * h;
+          k = 0;
+          slot = sl;
+        }
       }
-      nsub = ni.n;
-      if (ni.near_int) block_count(bs, kPfNearInt);
-      if (ni.clamped) block_count(bs, kPfClamped);
+      wc.children += __popcll(wave_ballot(act));
+      freem = wave_ballot(slot < 0);
     }
-    if (!isfinite(chi)) block_count(bs, kPfNonfinite);
-    h = tau / (double)nsub;
-    dtfac = h * a.dtfac_per_h;
-    qh2 = (sp == QED_ELECTRON ? -0.5 : 0.5) * h;
-  }
-  bool busy = act;
-  int k = 0;
-  const ChildArena& O = q.opa;
-  while (wave_ballot(busy)) {
+    if (wave_ballot(slot >= 0) == 0) break;
+
+    // ---- one sub-step ----
     bool emit = false;
     double f = 0.0;
-    if (busy) {
+    if (slot >= 0) {
       if (FMODE == kFieldE) {
         p = {p.x + 2.0 * qh2 * E.x, p.y + 2.0 * qh2 * E.y, p.z + 2.0 * qh2 * E.z};
       } else {
@@ -1820,7 +1891,7 @@ __device__ __forceinline__ void gen_leptons(const StepArgs& a, const GenArgs& q,
       // recoil: the lepton keeps p - k (momentum conservation, Sec. IV.F)
       p = {p.x - f * p.x, p.y - f * p.y, p.z - f * p.z};
     }
-    if (busy && ++k == nsub) {
+    if (slot >= 0 && ++k == nsub) {
       LEPTON_COL(x, sp)[slot] = x.x;
       LEPTON_COL(y, sp)[slot] = x.y;
       LEPTON_COL(z, sp)[slot] = x.z;
@@ -1829,62 +1900,87 @@ __device__ __forceinline__ void gen_leptons(const StepArgs& a, const GenArgs& q,
       LEPTON_COL(pz, sp)[slot] = p.z;
       uint32_t* ne = LEPTON_COL(n_events, sp);
       if (ne) ne[slot] = nev;
-      busy = false;
+      slot = -1;
     }
   }
 }
 
-// Photons of 64 photon records (lane: record r), each through its tau.  All lanes call.
+// Photons of the input photon records, each advanced through its tau (lane refill as for
+// the leptons).
 template <bool MIXED, int FMODE>
-__device__ __forceinline__ void gen_photons(const StepArgs& a, const GenArgs& q, GenWave& gw,
-                                            const ChildArena& A, long long r, int inst,
-                                            long long slot, double tau, bool act,
-                                            const Series64& ser64, const Series32& ser32,
-                                            BlockStats& bs, LaneCounters& cnt,
-                                            LaneCounters& pcnt, WaveCounters& wc) {
+__device__ __forceinline__ void gen_photon_phase(const StepArgs& a, const GenArgs& q,
+                                                 GenWave& gw, int V, const Series64& ser64,
+                                                 const Series32& ser32, BlockStats& bs,
+                                                 LaneCounters& cnt, LaneCounters& pcnt,
+                                                 WaveCounters& wc) {
+  const ChildArena& A = q.ipa;
+  const ChildArena& O = q.oqa;
   const uint64_t below = lanes_below();
   const uint32_t step = (uint32_t)a.hdr->step;
   const qed_soa& S = a.sp[QED_PHOTON];
+  const bool photons = a.push_photons || a.pairs;
+  GenStream st;
+  st.init(A, gw.wid, V, false);
+  long long slot = -1;
+  int inst = 0, nsub = 0, k = 0;
   uint64_t id = 0, seed = 0;
   V3 x{}, kv{}, E{}, B{};
   double chi = 0.0, h = 0.0, hk = 0.0, pref = 0.0;
-  int nsub = 0;
-  bool busy = false;
-  if (act && (a.push_photons || a.pairs)) {
-    id = S.id[slot];
-    x = {S.x[slot], S.y[slot], S.z[slot]};
-    kv = {S.px[slot], S.py[slot], S.pz[slot]};
-    const double kabs = sqrt(dot(kv, kv));
-    if (!(kabs > 0.0) || !isfinite(kabs)) {
-      block_count(bs, kPfNonfinite);
-    } else {
-      seed = a.inst[inst].seed;
-      inherited_fields<FMODE>(a, A, r, inst, E, B);
-      const double inv_k = 1.0 / kabs;
-      chi = chi_of(kv, kabs, E, B, a.eps_r);
-      nsub = 1;
-      if (a.forced > 0) {
-        nsub = a.forced;
-      } else if (a.adaptive && chi > 0.0) {
-        // tau / dt_q with dt_q of Eq. (33)
-        const NsubInfo ni = nsub_from_ratio(tau * (chi * inv_k) * a.inv_pho_scale);
-        nsub = ni.n;
-        if (ni.near_int) block_count(bs, kPfNearInt);
-        if (ni.clamped) block_count(bs, kPfClamped);
+  while (true) {
+    // ---- refill idle lanes ----
+    uint64_t freem = wave_ballot(slot < 0);
+    while (freem) {
+      long long j0;
+      int take;
+      if (!st.next(A, __popcll(freem), j0, take)) break;
+      const int rank = __popcll(freem & below);
+      bool act = false;
+      if (slot < 0 && rank < take) {
+        const long long r = st.record(A, j0 + rank);
+        const long long sl = A.slot[r];
+        const double tau = A.tau[r];
+        act = sl >= 0 && tau > 0.0;
+        if (act && photons) {
+          id = S.id[sl];
+          x = {S.x[sl], S.y[sl], S.z[sl]};
+          kv = {S.px[sl], S.py[sl], S.pz[sl]};
+          const double kabs = sqrt(dot(kv, kv));
+          if (!(kabs > 0.0) || !isfinite(kabs)) {
+            block_count(bs, kPfNonfinite);
+          } else {
+            inst = (int)A.inst[r];
+            seed = a.inst[inst].seed;
+            inherited_fields<FMODE>(a, A, r, inst, E, B);
+            const double inv_k = 1.0 / kabs;
+            chi = chi_of(kv, kabs, E, B, a.eps_r);
+            nsub = 1;
+            if (a.forced > 0) {
+              nsub = a.forced;
+            } else if (a.adaptive && chi > 0.0) {
+              // tau / dt_q with dt_q of Eq. (33)
+              const NsubInfo ni = nsub_from_ratio(tau * (chi * inv_k) * a.inv_pho_scale);
+              nsub = ni.n;
+              if (ni.near_int) block_count(bs, kPfNearInt);
+              if (ni.clamped) block_count(bs, kPfClamped);
+            }
+            if (!isfinite(chi)) block_count(bs, kPfNonfinite);
+            h = nsub == 1 ? tau : tau / (double)nsub;
+            hk = h * inv_k;
+            pref = h * (a.dtfac_per_h * kInvSqrt3Pi) * inv_k;
+            k = 0;
+            slot = sl;
+          }
+        }
       }
-      if (!isfinite(chi)) block_count(bs, kPfNonfinite);
-      h = nsub == 1 ? tau : tau / (double)nsub;
-      hk = h * inv_k;
-      pref = h * (a.dtfac_per_h * kInvSqrt3Pi) * inv_k;
-      busy = true;
+      wc.children += __popcll(wave_ballot(act));
+      freem = wave_ballot(slot < 0);
     }
-  }
-  int k = 0;
-  const ChildArena& O = q.oqa;
-  while (wave_ballot(busy)) {
+    if (wave_ballot(slot >= 0) == 0) break;
+
+    // ---- one sub-step ----
     bool pair = false, make = false;
     double r1 = 0.0, wp = 0.0;
-    if (busy) {
+    if (slot >= 0) {
       if (a.push_photons) x = {x.x + hk * kv.x, x.y + hk * kv.y, x.z + hk * kv.z};
       ++cnt.subs;
       if (a.pairs) {
@@ -1955,14 +2051,14 @@ __device__ __forceinline__ void gen_photons(const StepArgs& a, const GenArgs& q,
         wc.deferred += 2 * __popcll(wave_ballot(later));
       }
     }
-    if (busy && (pair || ++k == nsub)) {
+    if (slot >= 0 && (pair || ++k == nsub)) {
       if (a.push_photons) {
         S.x[slot] = x.x;
         S.y[slot] = x.y;
         S.z[slot] = x.z;
       }
       if (pair) S.id[slot] = QED_ID_DEAD;
-      busy = false;
+      slot = -1;
     }
   }
 }
@@ -1971,10 +2067,14 @@ template <bool MIXED, int FMODE>
 __global__ void __launch_bounds__(256) gen_kernel(StepArgs a, GenArgs q) {
   using Tab = typename TabType<MIXED>::T;
   __shared__ BlockStats bs;
+  __shared__ Tab tab[kTableN];  // the emission table, as in the lepton kernel
   block_stats_init(bs);
+  {
+    const Tab* src = MIXED ? reinterpret_cast<const Tab*>(a.tables->ab32)
+                           : reinterpret_cast<const Tab*>(a.tables->ab64);
+    for (int i = threadIdx.x; i < kTableN; i += blockDim.x) tab[i] = src[i];
+  }
   __syncthreads();
-  const Tab* tab = MIXED ? reinterpret_cast<const Tab*>(a.tables->ab32)
-                         : reinterpret_cast<const Tab*>(a.tables->ab64);
   const Series64 ser64 = {a.tables->series[0], a.tables->series[1], a.tables->series[2],
                           a.tables->series[3], a.tables->series[4]};
   const Series32 ser32 = {(float)ser64.b0, (float)ser64.b1, (float)ser64.c0, (float)ser64.c1,
@@ -1987,41 +2087,9 @@ __global__ void __launch_bounds__(256) gen_kernel(StepArgs a, GenArgs q) {
   cnt.bs = &bs;
   pcnt.bs = &bs;
   WaveCounters wc;
-  const int npa = q.ipa.waves;
-  const int nqa = q.iqa.waves;
-  // one producing wavefront's records at a time; a pair record holds two leptons
-  for (int t = gw.wid; t < npa + nqa; t += V) {
-    const bool pairrec = t >= npa;
-    const ChildArena& A = pairrec ? q.iqa : q.ipa;
-    const int sw = pairrec ? t - npa : t;
-    const long long n = (long long)A.nrec[sw];
-    const long long items = pairrec ? 2 * n : n;
-    ArenaWalk walk;
-    for (long long j0 = 0; j0 < items; j0 += 64) {
-      const long long j = j0 + lane;
-      const bool has = j < items;
-      // 64 photon records, or 32 pair records (two leptons each), per batch
-      walk.advance(A, sw, pairrec ? (j0 >> 1) : j0, pairrec ? 32 : 64, n);
-      const long long r = has ? walk.index(A, sw, pairrec ? (j >> 1) : j) : 0;
-      const int which = (int)(j & 1);
-      long long slot = -1;
-      double tau = 0.0;
-      int inst = 0;
-      if (has) {
-        slot = (pairrec && which) ? A.slot2[r] : A.slot[r];
-        tau = A.tau[r];
-        inst = (int)A.inst[r];
-      }
-      const bool act = has && slot >= 0 && tau > 0.0;
-      wc.children += __popcll(wave_ballot(act));
-      if (pairrec)
-        gen_leptons<MIXED, FMODE>(a, q, gw, A, r, which ? QED_POSITRON : QED_ELECTRON, inst,
-                                  slot, tau, act, tab, ser64, ser32, bs, cnt, wc);
-      else
-        gen_photons<MIXED, FMODE>(a, q, gw, A, r, inst, slot, tau, act, ser64, ser32, bs, cnt,
-                                  pcnt, wc);
-    }
-  }
+  // photons of the previous generation, then its electrons and positrons
+  gen_photon_phase<MIXED, FMODE>(a, q, gw, V, ser64, ser32, bs, cnt, pcnt, wc);
+  gen_lepton_phase<MIXED, FMODE>(a, q, gw, V, tab, ser64, ser32, bs, cnt, wc);
   if (q.opa.waves > 0) {
     gw.tp.flush(q.opa, gw.wid);
     if (lane == 0) q.opa.nrec[gw.wid] = (unsigned)gw.cp.n;
