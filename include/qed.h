@@ -56,7 +56,11 @@ typedef enum {
   QED_FIELD_ROTATING_E = 1,  /* E = amp*amp_i (cos phi, sin phi, 0), B = 0, phi = omega t + phase */
   QED_FIELD_CP_STANDING = 2, /* E = 2 a cos(omega x) (0, cos phi, sin phi),
                                 B = 2 a sin(omega x) (0, cos phi, sin phi), a = amp*amp_i */
-  QED_FIELD_YEE = 3          /* CIC (trilinear) gather from a periodic FP32 Yee grid */
+  QED_FIELD_YEE = 3,         /* CIC (trilinear) gather from a periodic FP32 Yee grid */
+  QED_FIELD_LP_STANDING = 4  /* plane standing wave of two counter-propagating linearly
+                                polarised waves: E = a (0, sin(omega x) cos phi, 0),
+                                B = a (0, 0, -cos(omega x) sin phi), a = amp*amp_i,
+                                phi = omega t + phase (Sec. VII avalanche) */
 } qed_field_kind;
 
 #define QED_TABLE_N 4096
@@ -142,7 +146,7 @@ typedef struct {
 typedef struct {
   int kind;                 /* qed_field_kind */
   double e0[3], b0[3];      /* QED_FIELD_UNIFORM */
-  double amp, omega, phase; /* QED_FIELD_ROTATING_E / QED_FIELD_CP_STANDING */
+  double amp, omega, phase; /* QED_FIELD_ROTATING_E / QED_FIELD_CP_STANDING / _LP_STANDING */
   const float *grid[6];     /* QED_FIELD_YEE: device Ex, Ey, Ez, Bx, By, Bz, each n[2]*n[1]*n[0]
                                floats, x fastest; component c sits at origin + (i + off_c) dx,
                                off = (1/2,0,0) (0,1/2,0) (0,0,1/2) (0,1/2,1/2) (1/2,0,1/2) (1/2,1/2,0) */

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 EXACT, TABLE = 0, 1
 FIELD_UNIFORM, FIELD_ROTATING_E, FIELD_CP_STANDING, FIELD_YEE = 0, 1, 2, 3
+FIELD_LP_STANDING = 4
 ID_DEAD = 0xFFFFFFFFFFFFFFFF
 NO_PARENT = 0xFFFFFFFFFFFFFFFF
 TABLE_N = 4096

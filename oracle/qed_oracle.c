@@ -327,6 +327,16 @@ void or_field_at(const or_field *f, const double x[3], double t, double E[3], do
       B[2] = cb * sin(ph);
       break;
     }
+    case OR_FIELD_LP_STANDING: {
+      /* two counter-propagating linearly polarised waves: E_y = amp sin(kx) cos(ph),
+       * B_z = -amp cos(kx) sin(ph), k = omega (Sec. VII avalanche) */
+      double ph = f->omega * t + f->phase;
+      E[0] = E[2] = 0.0;
+      E[1] = f->amp * sin(f->omega * x[0]) * cos(ph);
+      B[0] = B[1] = 0.0;
+      B[2] = -f->amp * cos(f->omega * x[0]) * sin(ph);
+      break;
+    }
     case OR_FIELD_YEE: {
       static const double off[6][3] = {{0.5, 0, 0},   {0, 0.5, 0},   {0, 0, 0.5},
                                        {0, 0.5, 0.5}, {0.5, 0, 0.5}, {0.5, 0.5, 0}};

@@ -33,7 +33,13 @@ extern "C" {
 #define OR_NSUB_HIST 32
 
 enum { OR_EXACT = 0, OR_TABLE = 1 };
-enum { OR_FIELD_UNIFORM = 0, OR_FIELD_ROTATING_E = 1, OR_FIELD_CP_STANDING = 2, OR_FIELD_YEE = 3 };
+enum {
+  OR_FIELD_UNIFORM = 0,
+  OR_FIELD_ROTATING_E = 1,
+  OR_FIELD_CP_STANDING = 2,
+  OR_FIELD_YEE = 3,
+  OR_FIELD_LP_STANDING = 4
+};
 
 typedef struct {
   int n;

@@ -170,6 +170,7 @@ qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_fi
       break;
     case QED_FIELD_ROTATING_E:
     case QED_FIELD_CP_STANDING:
+    case QED_FIELD_LP_STANDING:
       if (!isfinite(field->amp) || !isfinite(field->omega) || !isfinite(field->phase))
         return QED_ERR_ARG;
       break;

@@ -354,6 +354,15 @@ struct FieldArgs {
 // Space-independent kinds are evaluated once per instance by the step's prep kernel.
 __device__ __forceinline__ void field_at_position(const FieldArgs& f, double inst_amp, const V3& x,
                                                   V3& E, V3& B) {
+  if (f.kind == QED_FIELD_LP_STANDING) {
+    const double a1 = f.amp * inst_amp;
+    double sph, cph, skx, ckx;
+    sincos(f.omega * f.tn + f.phase, &sph, &cph);
+    sincos(f.omega * x.x, &skx, &ckx);
+    E = {0.0, a1 * skx * cph, 0.0};
+    B = {0.0, 0.0, -a1 * ckx * sph};
+    return;
+  }
   if (f.kind == QED_FIELD_CP_STANDING) {
     const double a2 = 2.0 * f.amp * inst_amp;
     double sph, cph, skx, ckx;

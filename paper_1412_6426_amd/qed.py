@@ -19,6 +19,7 @@ QED_OK, QED_ERR_ARG, QED_ERR_HIP, QED_ERR_UNSUPPORTED = 0, 1, 2, 3
 QED_FP64, QED_MIXED = 0, 1
 QED_ELECTRON, QED_POSITRON, QED_PHOTON = 0, 1, 2
 QED_FIELD_UNIFORM, QED_FIELD_ROTATING_E, QED_FIELD_CP_STANDING, QED_FIELD_YEE = 0, 1, 2, 3
+QED_FIELD_LP_STANDING = 4
 QED_TABLE_N = 4096
 QED_ID_DEAD = 0xFFFFFFFFFFFFFFFF
 QED_NO_PARENT = 0xFFFFFFFFFFFFFFFF

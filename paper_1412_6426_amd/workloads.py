@@ -21,6 +21,7 @@ LAMBDA_COMPTON_M = 2.42631023867e-12
 NO_PARENT = np.uint64(0xFFFFFFFFFFFFFFFF)
 
 FIELD_UNIFORM, FIELD_ROTATING_E, FIELD_CP_STANDING, FIELD_YEE = 0, 1, 2, 3
+FIELD_LP_STANDING = 4
 
 
 def eps_r_for_wavelength(lam_m: float) -> float:
@@ -285,6 +286,50 @@ def shower_initial(w: Workload) -> List[Dict[str, np.ndarray]]:
     zero = np.zeros(n)
     pabs = np.full(n, math.sqrt(SHOWER_GAMMA0 * SHOWER_GAMMA0 - 1.0))
     return [_seed_columns(zero, zero, zero, pabs, zero, zero), empty_columns(), empty_columns()]
+
+
+# ---------------------------------------------------------------------------------------
+# Sec. VII avalanche-type cascade: a plane standing wave E_y(t = 0) = 1e-2 E_S sin(2 pi x /
+# lambda), lambda = 1 um, seeded by electrons at x = lambda / 8 with p_y = 1000 m c; time
+# unit 1 / omega, lengths c / omega, fields as a = e E / (m c omega)
+# ---------------------------------------------------------------------------------------
+AVALANCHE_LAMBDA_M = 1e-6
+AVALANCHE_E0 = 1e-2  # in units of E_S
+AVALANCHE_P0 = 1000.0
+
+
+def avalanche_t_rad(lam_m: float = AVALANCHE_LAMBDA_M, e0: float = AVALANCHE_E0) -> float:
+    """t_rad = 14 (E_S / H_0)^(2/3) lambda_C / c with H_0 = e0 E_S, in units of 1 / omega
+    (omega lambda_C / c = 2 pi eps_r)."""
+    eps_r = eps_r_for_wavelength(lam_m)
+    return 14.0 * (1.0 / e0) ** (2.0 / 3.0) * 2.0 * math.pi * eps_r
+
+
+def avalanche(n: int = 100, dt_over_t_rad: float = 173.0, periods: float = 3.0,
+              kappa: float = 0.25, seed: int = 0, capacity: Optional[tuple] = None,
+              precision: str = "f64") -> Workload:
+    """n seed electrons (independent runs) in the standing wave; dt in units of t_rad
+    (0.17 and 173 in the paper's comparison, the latter about T / 8)."""
+    eps_r = eps_r_for_wavelength(AVALANCHE_LAMBDA_M)
+    dt = dt_over_t_rad * avalanche_t_rad()
+    steps = int(math.ceil(periods * 2.0 * math.pi / dt))
+    cap = capacity if capacity is not None else (20_000 * n, 20_000 * n, 200_000 * n)
+    return Workload(
+        name="avalanche", eps_r=eps_r, dt=dt, n_steps=steps,
+        field=FieldSpec(kind=FIELD_LP_STANDING, amp=AVALANCHE_E0 / eps_r, omega=1.0),
+        capacity=tuple(cap), seed=seed, kappa=kappa, n_seed=n, precision=precision,
+        description=f"{n} e- at x = lambda/8 with p_y = {AVALANCHE_P0:g} m c in a standing "
+                    f"wave E_y(0) = {AVALANCHE_E0:g} E_S sin(kx), lambda = 1 um; "
+                    f"dt = {dt_over_t_rad:g} t_rad, {steps} steps ({periods:g} periods), "
+                    f"kappa = {kappa}")
+
+
+def avalanche_initial(w: Workload) -> List[Dict[str, np.ndarray]]:
+    n = w.n_seed
+    zero = np.zeros(n)
+    x = np.full(n, math.pi / 4.0)  # lambda / 8 in units of c / omega
+    py = np.full(n, AVALANCHE_P0)
+    return [_seed_columns(x, zero, zero, zero, py, zero), empty_columns(), empty_columns()]
 
 
 # ---------------------------------------------------------------------------------------

@@ -7,7 +7,8 @@ import numpy as np
 import pytest
 
 from tests.conftest import gpu_available
-from tests.parity_util import compare_all, oracle_field, oracle_params, oracle_stores
+from tests.parity_util import (compare_all, compare_species, oracle_field, oracle_params,
+                               oracle_stores)
 
 pytestmark = pytest.mark.gpu
 
@@ -112,3 +113,36 @@ def test_generations_zero_is_unchanged(orc):
     _check_steps(stats, ostats)
     assert sum(s["children_advanced"] for s in stats) == 0
     compare_all(e, os_, label="G=0")
+
+
+def test_avalanche_same_step_parity(orc):
+    """The Sec. VII avalanche at its large step (20 seeds, dt = 173 t_rad, about T / 8, in
+    the linearly polarised standing wave): position-dependent fields that children
+    inherit, a cascade that grows tenfold per period.  The avalanche is chaotic: a change of
+    one ulp in the field amplitude changes the oracle's own event counts at the eighth step
+    and its momenta by up to about 1e-8 (photons 1e-6) after six (device sincos and libm
+    sin, cos differ by about an ulp).  So six steps, with every decision, id and weight
+    bit-exact, and momenta and positions within ten times the spread that the one-ulp
+    change makes in the oracle itself (at least 1e-12)."""
+    w = W.avalanche(n=20, dt_over_t_rad=173.0, periods=0.75)
+    assert w.n_steps == 6
+    init = W.avalanche_initial(w)
+    _note(f"avalanche: {w.description}")
+    e = R.engine_single(w, init, same_step=True)
+    stats = R.run(e, R.field_of(w), R.params_of(w, same_step_generations=16), w.n_steps)
+    op = oracle_params(orc, w, same_step_generations=16)
+    os_ = oracle_stores(orc, init, w.capacity)
+    ostats = orc.run(os_, oracle_field(orc, w), op, w.n_steps)
+    # the problem's own conditioning: the oracle again with the amplitude one ulp larger
+    f_ulp = oracle_field(orc, w)
+    f_ulp.amp = f_ulp.amp * (1.0 + 2.0 ** -52)
+    ou = oracle_stores(orc, init, w.capacity)
+    ustats = orc.run(ou, f_ulp, oracle_params(orc, w, same_step_generations=16), w.n_steps)
+    _check_steps(stats, ostats)
+    _check_steps(ustats, ostats)
+    assert sum(s["pairs"] for s in stats) > 200
+    for sp in range(3):
+        spread = compare_species(ou[sp].view(), os_[sp].view(), sp, rtol=1.0, label="ulp")
+        tol = max(1e-12, 10.0 * max(spread.values()))
+        _note(f"species {sp}: one-ulp spread {max(spread.values()):.2e}, tolerance {tol:.2e}")
+        compare_species(e.read(0, sp), os_[sp].view(), sp, rtol=tol, label=f"avalanche {sp}")

@@ -136,6 +136,28 @@ def test_standing_wave_satisfies_maxwell(orc):
         assert np.linalg.norm(E) == pytest.approx(4.0 * abs(math.cos(x)), abs=1e-12)
 
 
+def test_linear_standing_wave_satisfies_maxwell(orc):
+    """The plane standing wave of the Sec. VII avalanche: E_y(t = 0) = a sin(kx), and the
+    curl equations dB/dt = -curl E, dE/dt = curl B hold (finite differences)."""
+    f = orc.Field(kind=orc.FIELD_LP_STANDING, amp=3.0, omega=1.0)
+    d = 1e-5
+    for x, t in ((0.3, 0.1), (1.7, 2.2), (-0.4, 5.0), (math.pi / 4, 0.0)):
+        E, B = orc.field_at(f, [x, 0.2, -0.7], t)
+        Exp, Bxp = orc.field_at(f, [x + d, 0.2, -0.7], t)
+        Exm, Bxm = orc.field_at(f, [x - d, 0.2, -0.7], t)
+        Etp, Btp = orc.field_at(f, [x, 0.2, -0.7], t + d)
+        Etm, Btm = orc.field_at(f, [x, 0.2, -0.7], t - d)
+        dEdx, dBdx = (Exp - Exm) / (2 * d), (Bxp - Bxm) / (2 * d)
+        dEdt, dBdt = (Etp - Etm) / (2 * d), (Btp - Btm) / (2 * d)
+        curlE = np.array([0.0, -dEdx[2], dEdx[1]])
+        curlB = np.array([0.0, -dBdx[2], dBdx[1]])
+        assert np.allclose(curlE, -dBdt, atol=1e-7)
+        assert np.allclose(curlB, dEdt, atol=1e-7)
+        assert E[0] == E[2] == 0.0 and B[0] == B[1] == 0.0
+    E0, B0 = orc.field_at(f, [math.pi / 4, 0, 0], 0.0)
+    assert E0[1] == pytest.approx(3.0 * math.sin(math.pi / 4), rel=1e-15) and B0[2] == 0.0
+
+
 def test_rotating_field(orc):
     f = orc.Field(kind=orc.FIELD_ROTATING_E, amp=1000.0, omega=1.0)
     E, B = orc.field_at(f, [1, 2, 3], math.pi / 3)
