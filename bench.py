@@ -408,65 +408,42 @@ def cpu_baseline(args):
                        f"{dt:.1f} s), FP64 C oracle, OpenMP over particles")
 
 
-def gpu_shower(args):
-    """Sec. VII cascade development (the shower) at the paper's scale: 10^3 runs, as 8
-    instances of 125 seed electrons (gamma_0 = 2e5 across B = 0.2 E_S), counted every 25000
-    hbar / m c^2 up to `shower_samples` times that (1.39 t_rad for 5): the particles of each
-    species above 1e-3 gamma_0 m c^2, weighted, per instance.  Three runs:
-      small_dt            dt = 62.5, one sub-step per particle (the reference);
-      large_dt_same_step  dt = 25000, about 400 lepton sub-steps a step at kappa = 0.25,
-                          children advanced in their birth step (16 generations);
-      ..._kappa_0.1       the same with sub-steps 2.5 times shorter;
-      large_dt_next_step  the same large step with children left for the next step.
-    Each run's steps are timed with HIP events on the engine's stream (the counting is
-    not), and its counts are compared with the reference's as z-scores over the 8
-    instances."""
-    import math
+def _time_step_runs(runs_spec, n_inst, samples, count, label):
+    """Run each (name, workload, generations, steps_per_sample, arena_records) of runs_spec
+    on n_inst instances (instance i seeded with i, the same initial particles) for
+    `samples` intervals, timing the steps of each interval with HIP events on the engine's
+    stream.  count(engine) gives per-instance quantities [n_inst, q] after each interval.
+    The first run is the reference: the others get z-scores of their interval means over
+    the instances against it."""
     import numpy as np
     import torch
     from paper_1412_6426_amd import qed as Q
     from paper_1412_6426_amd import runner as R
-    from paper_1412_6426_amd import workloads as W
     from paper_1412_6426_amd.engine import Engine
 
-    n_inst = 8
-    per = max(args.shower_seeds // n_inst, 1)
-    interval = 25_000.0
-    thr = 1e-3 * W.SHOWER_GAMMA0
-    caps = (args.shower_lepton_cap // n_inst, args.shower_lepton_cap // n_inst,
-            args.shower_photon_cap // n_inst)
-    dead = -1  # the removed-photon id 2^64 - 1, as the int64 the id column holds
     runs = {}
-    for name, dt, kappa, G in (("small_dt", 62.5, 1.0, 0),
-                               ("large_dt_same_step", interval, 0.25, 16),
-                               ("large_dt_same_step_kappa_0.1", interval, 0.1, 16),
-                               ("large_dt_next_step", interval, 0.25, 0)):
-        print(f"bench: shower, {name}", file=sys.stderr, flush=True)
-        sps = int(round(interval / dt))
-        w = W.shower(n=per, dt=dt, steps=sps * args.shower_samples, kappa=kappa, capacity=caps)
-        # a large step's children (all generations) pass through the arenas: size them
-        # for the step's photons
-        arena = min(args.shower_photon_cap // 2, 1 << 27) if G > 0 else None
+    for name, w, init, G, sps, arena in runs_spec:
+        print(f"bench: {label}, {name}", file=sys.stderr, flush=True)
+        caps = tuple(w.capacity)
         e = Engine([caps] * n_inst, seeds=list(range(n_inst)), same_step=G > 0,
                    arena_records=arena)
         e.build_tables()
-        init = W.shower_initial(w)
         for i in range(n_inst):
             for s in range(3):
                 e.load(i, s, init[s])
         field = R.field_of(w)
         params = R.params_of(w, same_step_generations=G)
-        K = sps * args.shower_samples
+        K = sps * samples
         log = torch.zeros(K * e.stats_buf.numel(), dtype=torch.uint8, device=e.device)
         cnt = torch.zeros(1, dtype=torch.int64, device=e.device)
         stream = torch.cuda.Stream()
         sp = stream.cuda_stream
         hip = HipEvents()
-        evs = hip.create(2 * args.shower_samples)
-        counts = np.zeros((args.shower_samples, n_inst, 3))
+        evs = hip.create(2 * samples)
+        counts = []
         e.set_step(0)
         torch.cuda.synchronize()
-        for m in range(args.shower_samples):
+        for m in range(samples):
             with torch.cuda.stream(stream):
                 hip.lib.hipEventRecord(C.c_void_p(evs[2 * m]), C.c_void_p(sp))
                 for _ in range(sps):
@@ -475,27 +452,12 @@ def gpu_shower(args):
                                        sp)
                 hip.lib.hipEventRecord(C.c_void_p(evs[2 * m + 1]), C.c_void_p(sp))
             torch.cuda.synchronize()
-            live = e.counts()
-            for i in range(n_inst):
-                for s in range(3):
-                    b, n = int(e.base[i, s]), int(live[i, s])
-                    if n == 0:
-                        continue
-                    col = e.cols[s]
-                    p2 = (col["px"][b:b + n] ** 2 + col["py"][b:b + n] ** 2 +
-                          col["pz"][b:b + n] ** 2)
-                    wgt = col["w"][b:b + n]
-                    if s == Q.QED_PHOTON:
-                        above = (p2 > thr * thr) & (col["id"][b:b + n] != dead)
-                    else:
-                        above = (1.0 + p2) > thr * thr
-                    counts[m, i, s] = float((wgt * above).sum().item())
-        step_ms = sum(hip.elapsed_ms(evs[2 * m], evs[2 * m + 1])
-                      for m in range(args.shower_samples))
+            counts.append(count(e))
+        step_ms = sum(hip.elapsed_ms(evs[2 * m], evs[2 * m + 1]) for m in range(samples))
         hip.destroy(evs)
         recs = _stats_records(log.cpu().numpy().tobytes(), K)
         runs[name] = dict(
-            dt=dt, kappa=kappa, generations=G, steps=K, step_ms=step_ms,
+            dt=w.dt, kappa=w.kappa, generations=G, steps=K, step_ms=step_ms,
             substeps=int(sum(r.substeps for r in recs)),
             particle_steps=int(sum(sum(r.advanced) for r in recs)),
             children_advanced=int(sum(r.children_advanced for r in recs)),
@@ -503,24 +465,138 @@ def gpu_shower(args):
             dropped=int(sum(r.dropped for r in recs)),
             saturated=int(sum(r.saturated for r in recs)),
             final_counts=[int(x) for x in e.counts().sum(0)],
-            counts=counts)
+            counts=np.array(counts))  # [sample, instance, quantity]
         del e, log
         torch.cuda.empty_cache()
-    ref = runs["small_dt"]["counts"]
-    out = dict(workload=f"{n_inst} x {per} e-, gamma0 = {W.SHOWER_GAMMA0:g} across "
-                        f"B = {W.SHOWER_B} E_S; counts above {thr:g} m c^2 every "
-                        f"{interval:g} hbar/mc^2 (t_rad = {W.shower_t_rad():.4g})",
-               t=[interval * (m + 1) for m in range(args.shower_samples)])
-    for name, r in runs.items():
+    names = list(runs)
+    ref = runs[names[0]]["counts"]
+    out = {}
+    for name in names:
+        r = runs[name]
         c = r.pop("counts")
-        r["mean_counts"] = c.mean(1).round(2).tolist()  # [sample][species], per instance
-        if name != "small_dt":
+        r["mean_counts"] = c.mean(1).round(2).tolist()  # [sample][quantity], per instance
+        if name != names[0]:
             se = np.sqrt(c.var(1, ddof=1) / n_inst + ref.var(1, ddof=1) / n_inst)
             z = (c.mean(1) - ref.mean(1)) / np.where(se > 0, se, np.inf)
-            r["z_vs_small_dt"] = z.round(2).tolist()
+            r["z_vs_" + names[0]] = z.round(2).tolist()
             r["max_abs_z"] = float(np.abs(z).max())
-            r["speedup_vs_small_dt"] = runs["small_dt"]["step_ms"] / r["step_ms"]
+            r["ratio_vs_" + names[0]] = (c.mean(1) / np.where(ref.mean(1) > 0, ref.mean(1),
+                                                               np.nan)).round(3).tolist()
+            r["speedup_vs_" + names[0]] = runs[names[0]]["step_ms"] / r["step_ms"]
         out[name] = r
+    return out
+
+
+def gpu_shower(args):
+    """Sec. VII cascade development (the shower) at the paper's scale: 10^3 runs, as 8
+    instances of 125 seed electrons (gamma_0 = 2e5 across B = 0.2 E_S), counted every 25000
+    hbar / m c^2 up to `shower_samples` times that (1.39 t_rad for 5): the particles of each
+    species above 1e-3 gamma_0 m c^2, weighted, per instance.  Runs:
+      small_dt            dt = 62.5, one sub-step per particle (the reference);
+      large_dt_same_step  dt = 25000, about 400 lepton sub-steps a step at kappa = 0.25,
+                          children advanced in their birth step (16 generations);
+      ..._kappa_0.1       the same with sub-steps 2.5 times shorter;
+      large_dt_next_step  the same large step with children left for the next step."""
+    import numpy as np
+    from paper_1412_6426_amd import qed as Q
+    from paper_1412_6426_amd import workloads as W
+
+    n_inst = 8
+    per = max(args.shower_seeds // n_inst, 1)
+    interval = 25_000.0
+    thr = 1e-3 * W.SHOWER_GAMMA0
+    caps = (args.shower_lepton_cap // n_inst, args.shower_lepton_cap // n_inst,
+            args.shower_photon_cap // n_inst)
+    dead = -1  # the removed-photon id 2^64 - 1, as the int64 the id column holds
+
+    def count(e):
+        live = e.counts()
+        out = np.zeros((n_inst, 3))
+        for i in range(n_inst):
+            for s in range(3):
+                b, n = int(e.base[i, s]), int(live[i, s])
+                if n == 0:
+                    continue
+                col = e.cols[s]
+                p2 = (col["px"][b:b + n] ** 2 + col["py"][b:b + n] ** 2 +
+                      col["pz"][b:b + n] ** 2)
+                if s == Q.QED_PHOTON:
+                    above = (p2 > thr * thr) & (col["id"][b:b + n] != dead)
+                else:
+                    above = (1.0 + p2) > thr * thr
+                out[i, s] = float((col["w"][b:b + n] * above).sum().item())
+        return out
+
+    spec = []
+    for name, dt, kappa, G in (("small_dt", 62.5, 1.0, 0),
+                               ("large_dt_same_step", interval, 0.25, 16),
+                               ("large_dt_same_step_kappa_0.1", interval, 0.1, 16),
+                               ("large_dt_next_step", interval, 0.25, 0)):
+        sps = int(round(interval / dt))
+        w = W.shower(n=per, dt=dt, steps=sps * args.shower_samples, kappa=kappa, capacity=caps)
+        # a large step's children (all generations) pass through the arenas: size them
+        # for the step's photons
+        arena = min(args.shower_photon_cap // 2, 1 << 27) if G > 0 else None
+        spec.append((name, w, W.shower_initial(w), G, sps, arena))
+    out = dict(workload=f"{n_inst} x {per} e-, gamma0 = {W.SHOWER_GAMMA0:g} across "
+                        f"B = {W.SHOWER_B} E_S; counts (e-, e+, photons) above {thr:g} m c^2 "
+                        f"every {interval:g} hbar/mc^2 (t_rad = {W.shower_t_rad():.4g})",
+               t=[interval * (m + 1) for m in range(args.shower_samples)])
+    out.update(_time_step_runs(spec, n_inst, args.shower_samples, count, "shower"))
+    return out
+
+
+def gpu_avalanche(args):
+    """Sec. VII avalanche-type cascade: electrons at x = lambda/8 with p_y = 1000 m c in the
+    plane standing wave E_y(0) = 1e-2 E_S sin(kx), lambda = 1 um, as 8 instances of
+    `avalanche_seeds` / 8 independent runs; the pairs created so far (positrons, weighted)
+    and the photons, per instance, every two large steps (about T / 4) for
+    `avalanche_samples` intervals.  Runs:
+      small_dt            dt = 173/1018 t_rad (about 0.17 t_rad: no sub-division);
+      large_dt_same_step  dt = 173 t_rad (about T / 8; the field is sampled 8 times a
+                          period), kappa = 0.25, children in their birth step;
+      large_dt_next_step  the same large step with children left for the next step."""
+    import numpy as np
+    from paper_1412_6426_amd import workloads as W
+
+    n_inst = 8
+    per = max(args.avalanche_seeds // n_inst, 1)
+    periods = args.avalanche_samples * 2 * 173.0 * W.avalanche_t_rad() / (2 * np.pi)
+    caps = (args.avalanche_lepton_cap // n_inst, args.avalanche_lepton_cap // n_inst,
+            args.avalanche_photon_cap // n_inst)
+
+    def count(e):
+        live = e.counts()
+        out = np.zeros((n_inst, 2))
+        for i in range(n_inst):
+            b, n = int(e.base[i, 1]), int(live[i, 1])
+            if n:
+                out[i, 0] = float(e.cols[1]["w"][b:b + n].sum().item())
+            out[i, 1] = float(live[i, 2])
+        return out
+
+    spec = []
+    for name, ratio, kappa, G, sps in (("small_dt", 173.0 / 1018.0, 1.0, 0, 2 * 1018),
+                                       ("large_dt_same_step", 173.0, 0.25, 16, 2),
+                                       ("large_dt_next_step", 173.0, 0.25, 0, 2)):
+        w = W.avalanche(n=per, dt_over_t_rad=ratio, periods=periods, kappa=kappa,
+                        capacity=caps)
+        arena = min(args.avalanche_photon_cap // 2, 1 << 27) if G > 0 else None
+        spec.append((name, w, W.avalanche_initial(w), G, sps, arena))
+    T_large = 173.0 * W.avalanche_t_rad()
+    out = dict(workload=f"{n_inst} x {per} e- at lambda/8, p_y = {W.AVALANCHE_P0:g} m c, "
+                        f"standing wave E_y(0) = {W.AVALANCHE_E0:g} E_S sin(kx), lambda = 1 um; "
+                        "per instance: pairs created, photon slots",
+               t_over_period=[round((m + 1) * 2 * T_large / (2 * np.pi), 4)
+                              for m in range(args.avalanche_samples)])
+    out.update(_time_step_runs(spec, n_inst, args.avalanche_samples, count, "avalanche"))
+    # growth of the pair count (e-folds per period) over the second half of the interval
+    t = out["t_over_period"]
+    k = len(t) // 2
+    for name, _, _, _, _, _ in spec:
+        c = [row[0] for row in out[name]["mean_counts"]]
+        if c[k] > 0 and c[-1] > 0 and t[-1] > t[k]:
+            out[name]["pair_growth_per_period"] = round(np.log(c[-1] / c[k]) / (t[-1] - t[k]), 3)
     return out
 
 
@@ -556,6 +632,14 @@ def main():
     ap.add_argument("--shower-samples", type=int, default=5)
     ap.add_argument("--shower-photon-cap", type=int, default=300_000_000)
     ap.add_argument("--shower-lepton-cap", type=int, default=20_000_000)
+    ap.add_argument("--no-avalanche", action="store_true",
+                    help="skip the Sec. VII avalanche at small and large time steps")
+    ap.add_argument("--avalanche-only", action="store_true",
+                    help="run only the avalanche comparison and print its record (profiling)")
+    ap.add_argument("--avalanche-seeds", type=int, default=200)
+    ap.add_argument("--avalanche-samples", type=int, default=6)
+    ap.add_argument("--avalanche-photon-cap", type=int, default=200_000_000)
+    ap.add_argument("--avalanche-lepton-cap", type=int, default=40_000_000)
     ap.add_argument("--no-tune", action="store_true",
                     help="use --tile / --grid-blocks for every step instead of tuning")
     args = ap.parse_args()
@@ -570,6 +654,9 @@ def main():
         sys.exit(1)
     if args.shower_only:
         print(json.dumps({"shower_time_step_invariance": gpu_shower(args)}), flush=True)
+        return
+    if args.avalanche_only:
+        print(json.dumps({"avalanche_time_step_invariance": gpu_avalanche(args)}), flush=True)
         return
     print(f"bench: rotating-E cascade, {args.seeds} seeds, precision {args.precision}",
           file=sys.stderr, flush=True)
@@ -674,6 +761,8 @@ def main():
             f_photon=4.0, f_pair=1.0, eager_matches_graph=rf["eager_matches_graph"])
     if not args.no_shower:
         line["shower_time_step_invariance"] = gpu_shower(args)
+    if not args.no_avalanche:
+        line["avalanche_time_step_invariance"] = gpu_avalanche(args)
     if not args.no_yee:
         print("bench: standing-wave cascade on the Yee grid", file=sys.stderr, flush=True)
         line["standing_wave_grid"] = gpu_run_yee(args, args.precision)
