@@ -66,6 +66,11 @@ class OrParams(C.Structure):
                 ("same_step_generations", C.c_int)]
 
 
+class OrSchwingerRecord(C.Structure):
+    _fields_ = [("cells", C.c_int64), ("pairs", C.c_int64), ("dropped", C.c_int64),
+                ("saturated", C.c_int64), ("expected", C.c_double)]
+
+
 class OrStats(C.Structure):
     _fields_ = [("emitted", C.c_int64), ("pairs", C.c_int64), ("dropped", C.c_int64),
                 ("saturated", C.c_int64), ("near_threshold", C.c_int64),
@@ -128,6 +133,10 @@ def lib():
         L.or_thin.argtypes = [C.POINTER(OrStore), C.c_int64, C.c_int64, C.c_uint64, C.c_int64,
                               C.POINTER(OrThinRecord)]
         L.or_thin.restype = C.c_int
+        L.or_schwinger.argtypes = [C.POINTER(OrStore), C.POINTER(OrField), C.c_double,
+                                   C.c_double, C.c_double, C.c_uint64, C.c_int64,
+                                   C.POINTER(OrSchwingerRecord)]
+        L.or_schwinger.restype = C.c_int
         for fn in ("or_emission_trials", "or_pair_trials"):
             getattr(L, fn).argtypes = [C.POINTER(OrTables), C.c_int, C.c_double, C.c_double,
                                        C.c_double, C.c_uint64, C.c_int64, _dp]
@@ -399,6 +408,20 @@ def step(stores: Sequence[Store], fld: Field, params: Params) -> Dict:
     for i, s in enumerate(stores):
         s.count = int(arr[i].count)
     return st.as_dict()
+
+
+def schwinger(stores: Sequence["Store"], fld: "Field", dt: float, eps_r: float, weight: float,
+              seed: int, step: int) -> Dict:
+    """Non-perturbative pairs of Sec. V.B from a Yee-grid field, one step, appended to the
+    electron and positron stores in place."""
+    arr = (OrStore * 3)(*[s._cstruct() for s in stores])
+    cf = fld.cstruct()
+    rec = OrSchwingerRecord()
+    lib().or_schwinger(arr, C.byref(cf), float(dt), float(eps_r), float(weight), int(seed),
+                       int(step), C.byref(rec))
+    for i, s in enumerate(stores):
+        s.count = int(arr[i].count)
+    return {k: getattr(rec, k) for k, _ in OrSchwingerRecord._fields_}
 
 
 def thin(store: "Store", trigger: int, target: int, seed: int, step: int) -> Dict:

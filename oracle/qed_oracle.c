@@ -868,6 +868,78 @@ int or_thin(or_store *s, int64_t trigger, int64_t target, uint64_t seed, int64_t
 }
 
 /* ------------------------------------------------------------------------------------
+ * Non-perturbative pair production (Sec. V.B): per grid cell and step, a pair with
+ * probability R_S V c dt from the cell's field.
+ * ------------------------------------------------------------------------------------ */
+static double or_grid_at(const float *g, const int n[3], int64_t i, int64_t j, int64_t k) {
+  i = ((i % n[0]) + n[0]) % n[0];
+  j = ((j % n[1]) + n[1]) % n[1];
+  k = ((k % n[2]) + n[2]) % n[2];
+  return (double)g[i + (int64_t)n[0] * (j + (int64_t)n[1] * k)];
+}
+
+int or_schwinger(or_store *st, const or_field *f, double dt, double eps_r, double weight,
+                 uint64_t seed, int64_t step, or_schwinger_record *rec) {
+  memset(rec, 0, sizeof(*rec));
+  const double vol = f->dx[0] * f->dx[1] * f->dx[2];
+  const double pref = vol * dt / (4.0 * OR_PI * OR_PI * OR_PI * pow(eps_r, 4.0));
+  for (int64_t k = 0; k < f->n[2]; ++k)
+    for (int64_t j = 0; j < f->n[1]; ++j)
+      for (int64_t i = 0; i < f->n[0]; ++i) {
+        const uint64_t c = (uint64_t)(i + (int64_t)f->n[0] * (j + (int64_t)f->n[1] * k));
+        rec->cells++;
+        /* the cell's field: each component the mean of its four samples on the cell */
+        const double ex = 0.25 * (or_grid_at(f->grid[0], f->n, i, j, k) +
+                                  or_grid_at(f->grid[0], f->n, i, j + 1, k) +
+                                  or_grid_at(f->grid[0], f->n, i, j, k + 1) +
+                                  or_grid_at(f->grid[0], f->n, i, j + 1, k + 1));
+        const double ey = 0.25 * (or_grid_at(f->grid[1], f->n, i, j, k) +
+                                  or_grid_at(f->grid[1], f->n, i + 1, j, k) +
+                                  or_grid_at(f->grid[1], f->n, i, j, k + 1) +
+                                  or_grid_at(f->grid[1], f->n, i + 1, j, k + 1));
+        const double ez = 0.25 * (or_grid_at(f->grid[2], f->n, i, j, k) +
+                                  or_grid_at(f->grid[2], f->n, i + 1, j, k) +
+                                  or_grid_at(f->grid[2], f->n, i, j + 1, k) +
+                                  or_grid_at(f->grid[2], f->n, i + 1, j + 1, k));
+        const double e = sqrt(ex * ex + ey * ey + ez * ez) * eps_r; /* E / E_S */
+        if (!(e > 0.0)) continue;
+        const double P = pref * e * e * exp(-OR_PI / e);
+        rec->expected += P < 1.0 ? P : 1.0;
+        if (P >= 1.0) rec->saturated++;
+        uint32_t key[2] = {(uint32_t)c, (uint32_t)(c >> 32)};
+        uint32_t ctr[4] = {(uint32_t)step, 7u << 16, (uint32_t)seed, (uint32_t)(seed >> 32)};
+        uint32_t o[4];
+        or_philox4x32_10(ctr, key, o);
+        if (!(or_uniform(o[0], o[1]) < P)) continue;
+        ctr[1] = 8u << 16;
+        or_philox4x32_10(ctr, key, o);
+        const double u[3] = {((double)o[0] + 0.5) * 0x1p-32, ((double)o[1] + 0.5) * 0x1p-32,
+                             ((double)o[2] + 0.5) * 0x1p-32};
+        or_child e_, p_;
+        const int64_t cell[3] = {i, j, k};
+        for (int d = 0; d < 3; ++d) {
+          e_.x[d] = p_.x[d] = f->origin[d] + ((double)cell[d] + u[d]) * f->dx[d];
+          e_.p[d] = p_.p[d] = 0.0;
+        }
+        e_.w = p_.w = weight;
+        e_.parent = p_.parent = OR_NO_PARENT;
+        e_.birth = p_.birth = (uint32_t)((uint64_t)(step + 1) << 14);
+        e_.id = or_child_id(c, seed, step, 0, 9);
+        p_.id = or_child_id(c, seed, step, 0, 10);
+        e_.species = 0;
+        p_.species = 1;
+        e_.tau = p_.tau = 0.0;
+        or_stats s;
+        memset(&s, 0, sizeof(s));
+        or_append(st, &e_, &s);
+        or_append(st, &p_, &s);
+        rec->dropped += s.dropped;
+        rec->pairs++;
+      }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------------------
  * Generator trials for the statistical pins: trial i draws (r1, r2) from Philox with
  * counter (i, i>>32, 0, 0) and the given key, then applies the generator decision.
  * ------------------------------------------------------------------------------------ */

@@ -150,6 +150,30 @@ typedef struct {
 int or_thin(or_store *s, int64_t trigger, int64_t target, uint64_t seed, int64_t step,
             or_thin_record *rec);
 
+/* Non-perturbative (Schwinger) pairs of Sec. V.B on a periodic Yee grid (f->kind ==
+ * OR_FIELD_YEE), one global step n = step of length dt.  The field of cell (i, j, k), the
+ * box [i, i+1) x [j, j+1) x [k, k+1) in units of dx from the origin, is taken as constant:
+ * each E component is the mean of its four staggered samples on the cell (Ex at (i+1/2,
+ * j..j+1, k..k+1), Ey at (i..i+1, j+1/2, k..k+1), Ez at (i..i+1, j..j+1, k+1/2)); the
+ * magnetic field is neglected.  With e = |E| eps_r = E / E_S the probability of a pair in
+ * the cell during the step is P = R_S V dt, R_S = e^2 exp(-pi / e) / (4 pi^3 eps_r^4) (the
+ * reduced Compton length is eps_r in units of c / omega), V = dx0 dx1 dx2.  The cells are
+ * visited in index order c = i + n0 (j + n1 k); cell c creates a pair iff u < P, u the first
+ * two words of the Philox draw keyed by c with counter (step, 7 << 16, seed lo, seed hi);
+ * the pair sits at origin + (i + u_x, j + u_y, k + u_z) dx, u_x..u_z = (w_m + 1/2) 2^-32 from
+ * the first three words of the draw with purpose 8; both have zero momentum, weight
+ * `weight`, no parent, birth ((step + 1) << 14), ids or_child_id(c, seed, step, 0, 9) and
+ * (..., 10).  Returns 0. */
+typedef struct {
+  int64_t cells;      /* cells visited */
+  int64_t pairs;      /* pairs created (dropped ones included) */
+  int64_t dropped;    /* leptons beyond a store's capacity */
+  int64_t saturated;  /* cells with P >= 1 (at most one pair per cell and step) */
+  double expected;    /* sum of min(P, 1) over the cells */
+} or_schwinger_record;
+int or_schwinger(or_store *st /* [3] */, const or_field *f, double dt, double eps_r,
+                 double weight, uint64_t seed, int64_t step, or_schwinger_record *rec);
+
 /* Batch helpers for statistical pins: run the generators on Philox draws keyed by `key`. */
 int64_t or_emission_trials(const or_tables *t, int backend, double chi, double gamma, double dtfac,
                            uint64_t key, int64_t n, double *delta_out);

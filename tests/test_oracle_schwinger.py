@@ -1,0 +1,144 @@
+"""Pins of the oracle's non-perturbative (Schwinger) pair production (Sec. V.B).
+
+Per grid cell and step a pair appears with probability P = R_S V c dt, with
+R_S = (E/E_S)^2 exp(-pi E_S / E) / (4 pi^3 lambdabar_C^4), the field taken as constant over
+the cell and the magnetic field neglected; electron and positron start at rest at the same
+random point of the cell.  The rate is the paper's definition; what these tests check is
+the generator around it:
+* counts are binomial around the sum of the cells' probabilities;
+* fields far below E_S give no pairs at all (exponential suppression), and no NaN at E = 0;
+* each pair sits uniformly inside its own cell, at rest, with both leptons together;
+* the magnetic field changes nothing;
+* the cell's field is the mean of its staggered samples: a field that grows along y gives
+  each row of cells the count of its mean value, not of a node value."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1412_6426_amd import workloads as W
+
+N = 16  # cells per axis
+
+
+def _grid(ex=0.0, ey=0.0, ez=0.0, b=0.0, n=N):
+    shape = (n, n, n)  # [k][j][i], x fastest
+    g = [np.full(shape, v, np.float32) for v in (ex, ey, ez)]
+    g += [np.full(shape, b, np.float32) for _ in range(3)]
+    return [np.ascontiguousarray(a) for a in g]
+
+
+def _field(orc, grids, dx=1.0):
+    return orc.Field(kind=orc.FIELD_YEE, grid=grids, dx=(dx, dx, dx), origin=(0.0, 0.0, 0.0))
+
+
+def _stores(orc, cap=200_000):
+    st = [orc.Store(cap), orc.Store(cap), orc.Store(16, with_events=False)]
+    for s in st:
+        s.load(W.empty_columns())
+    return st
+
+
+def _p(e, vol_dt, eps_r=1.0):
+    return vol_dt * e * e * math.exp(-math.pi / e) / (4.0 * math.pi ** 3 * eps_r ** 4)
+
+
+def test_counts_are_binomial_in_a_uniform_field(orc):
+    """|E| = 3 E_S on 16^3 cells of unit volume, dt = 1 (eps_r = 1): P = 0.0255 per cell."""
+    grids = _grid(ex=3.0 / math.sqrt(2), ey=3.0 / math.sqrt(2))
+    fld = _field(orc, grids)
+    total = 0
+    for step in range(8):
+        st = _stores(orc)
+        r = orc.schwinger(st, fld, dt=1.0, eps_r=1.0, weight=1.0, seed=11, step=step)
+        assert r["cells"] == N ** 3 and r["saturated"] == 0
+        total += r["pairs"]
+        assert st[0].count == st[1].count == r["pairs"]
+    p = _p(3.0, 1.0)
+    n = 8 * N ** 3
+    assert r["expected"] == pytest.approx(N ** 3 * p, rel=1e-6)
+    assert abs(total - n * p) < 4.0 * math.sqrt(n * p * (1 - p))
+
+
+def test_weak_fields_make_nothing(orc):
+    st = _stores(orc)
+    r = orc.schwinger(st, _field(orc, _grid(ez=0.02)), dt=1.0, eps_r=1.0, weight=1.0, seed=1,
+                      step=0)
+    assert r["pairs"] == 0 and r["expected"] < 1e-60
+    r = orc.schwinger(st, _field(orc, _grid()), dt=1.0, eps_r=1.0, weight=1.0, seed=1, step=0)
+    assert r["pairs"] == 0 and r["expected"] == 0.0
+
+
+def test_pairs_sit_at_rest_uniformly_inside_their_cells(orc):
+    """A strong field (P near 0.5 per cell, dx = 0.5) over several steps."""
+    grids = _grid(ez=2.0)
+    dx = 0.5
+    fld = _field(orc, grids, dx=dx)
+    dt = 0.5 / _p(2.0, dx ** 3)  # P = 0.5
+    xs = []
+    for step in range(4):
+        st = _stores(orc)
+        r = orc.schwinger(st, fld, dt=dt, eps_r=1.0, weight=2.5, seed=3, step=step)
+        e, p = st[0].view(), st[1].view()
+        assert len(e["id"]) == len(p["id"]) == r["pairs"] > 800
+        for c in ("x", "y", "z"):
+            assert np.array_equal(e[c], p[c])  # created together
+        for c in ("px", "py", "pz"):
+            assert np.all(e[c] == 0.0) and np.all(p[c] == 0.0)
+        assert np.all(e["w"] == 2.5) and np.all(p["w"] == 2.5)
+        assert np.all(e["birth"] == (step + 1) << 14)
+        assert len(set(e["id"].tolist()) | set(p["id"].tolist())) == 2 * r["pairs"]
+        xs.append(np.stack([e["x"], e["y"], e["z"]], 1) / dx)
+    frac = np.concatenate(xs) % 1.0
+    assert np.all((frac > 0.0) & (frac < 1.0))
+    m = len(frac)
+    # uniform in the cell: mean 1/2 and variance 1/12 per axis
+    assert np.all(np.abs(frac.mean(0) - 0.5) < 4.0 * math.sqrt(1.0 / 12.0 / m))
+    assert np.all(np.abs(frac.var(0) - 1.0 / 12.0) < 4.0 * math.sqrt(1.0 / 180.0 / m))
+
+
+def test_magnetic_field_changes_nothing(orc):
+    grids = _grid(ex=3.0)
+    a = _stores(orc)
+    b = _stores(orc)
+    ra = orc.schwinger(a, _field(orc, grids), 1.0, 1.0, 1.0, seed=5, step=2)
+    rb = orc.schwinger(b, _field(orc, _grid(ex=3.0, b=7.0)), 1.0, 1.0, 1.0, seed=5, step=2)
+    assert ra == rb
+    for s in range(2):
+        va, vb = a[s].view(), b[s].view()
+        for c in va:
+            assert np.array_equal(va[c], vb[c]), c
+
+
+def test_cell_field_is_the_mean_of_its_samples(orc):
+    """E_x sampled at (i + 1/2, j, k) grows along y as s j, so cell row j has the mean
+    s (j + 1/2): the pairs per row follow P(s (j + 1/2)), far from P(s j) or P(s (j + 1)).
+    Fields of 0.6 to 1.5 E_S, where exp(-pi E_S / E) changes fast, and dt = 150."""
+    s_ = 0.1
+    dt = 150.0
+    shape = (N, N, N)
+    ex = np.zeros(shape, np.float32)
+    for j in range(N):
+        ex[:, j, :] = s_ * j
+    # the periodic wrap makes the last row's mean s (N - 1) / 2: keep it out of the check
+    grids = [ex, np.zeros(shape, np.float32), np.zeros(shape, np.float32)] + \
+        [np.zeros(shape, np.float32) for _ in range(3)]
+    fld = _field(orc, grids)
+    rows = np.zeros(N)
+    steps = 40
+    for step in range(steps):
+        st = _stores(orc)
+        orc.schwinger(st, fld, dt, 1.0, 1.0, seed=9, step=step)
+        y = st[0].view()["y"]
+        rows += np.bincount(np.floor(y).astype(int), minlength=N)[:N]
+    checked = 0
+    for j in range(8, N - 1):  # rows whose neighbouring node values differ by > 4.5 sd
+        n = steps * N * N
+        p_mean = _p(s_ * (j + 0.5), dt)
+        p_lo, p_hi = _p(s_ * j, dt), _p(s_ * (j + 1), dt)
+        sd = math.sqrt(n * p_mean * (1 - p_mean))
+        assert abs(rows[j] - n * p_mean) < 4.0 * sd, j
+        # the node values would be told apart
+        assert abs(n * p_lo - n * p_mean) > 4.0 * sd and abs(n * p_hi - n * p_mean) > 4.0 * sd
+        checked += 1
+    assert checked == N - 9
