@@ -292,6 +292,37 @@ qed_status qed_thin(const qed_stores *stores, int species, int64_t trigger, int6
                     const int64_t *d_step, qed_thin_record *d_records, void *d_work,
                     size_t work_bytes, void *stream);
 
+/* Counters of one qed_schwinger call (device memory; overwritten by each call). */
+typedef struct {
+  int64_t cells;      /* (cell, instance) pairs visited */
+  int64_t pairs;      /* pairs created (dropped ones included) */
+  int64_t dropped;    /* leptons beyond a store's capacity */
+  int64_t saturated;  /* cells with P >= 1 (at most one pair per cell, instance and step) */
+  double expected;    /* sum of min(P, 1) over the visited cells */
+  int64_t reserved;
+} qed_schwinger_record;
+
+/* Non-perturbative (Schwinger) pair production of Sec. V.B for step n = *d_step, from the
+ * Yee-grid field `field` (kind QED_FIELD_YEE; cells of dx[0] dx[1] dx[2] with corners at
+ * origin + (i, j, k) dx).  The field of a cell is taken as constant: each E component is the
+ * mean of its four staggered samples on the cell (Ex at (i + 1/2, j..j+1, k..k+1), Ey at
+ * (i..i+1, j + 1/2, k..k+1), Ez at (i..i+1, j..j+1, k + 1/2), periodic); the magnetic field is
+ * neglected.  With e = |E| eps_r = E / E_S, every non-frozen instance gets a pair in the
+ * cell with probability P = R_S V dt, R_S = e^2 exp(-pi / e) / (4 pi^3 eps_r^4) (the reduced
+ * Compton length is eps_r in units of c / omega), decided by the Philox draw keyed by the cell
+ * index c = i + n0 (j + n1 k) with counter (n, 7 << 16, seed lo, seed hi) of the instance
+ * (first two words as u, a pair iff u < P).  The electron and the positron start at rest at
+ * origin + (i + u_x, j + u_y, k + u_z) dx, u_x..u_z = (w_m + 1/2) 2^-32 from the first three
+ * words of the draw with purpose 8, with weight `weight`, no parent, birth (n + 1) << 14 and
+ * ids from the key c with purposes 9 (electron) and 10 (positron); they are appended to the
+ * instance's stores (beyond the capacity: dropped and counted).  Call it before qed_step of
+ * the same n for the pairs to move in that step.  Writes *d_record; asynchronous on
+ * `stream`.  QED_ERR_ARG for a field that is not a Yee grid, fewer than 1 cell per axis,
+ * 2^31 cells or more, non-positive dt, eps_r or weight, or missing lepton columns. */
+qed_status qed_schwinger(const qed_stores *stores, const qed_field *field, double dt,
+                         double eps_r, double weight, const int64_t *d_step,
+                         qed_schwinger_record *d_record, void *stream);
+
 /* Append the record *d_stats to d_log[*d_log_count] and increment *d_log_count, unless
  * *d_log_count >= log_capacity (then the record is discarded and the count still grows,
  * so the caller sees the overflow).  Graph-capturable. */

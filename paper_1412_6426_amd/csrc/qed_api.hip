@@ -293,6 +293,27 @@ qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_fi
   return e == hipSuccess ? QED_OK : QED_ERR_HIP;
 }
 
+qed_status qed_schwinger(const qed_stores* stores, const qed_field* field, double dt,
+                         double eps_r, double weight, const int64_t* d_step,
+                         qed_schwinger_record* d_record, void* stream) {
+  if (!stores || !field || !d_step || !d_record || !stores->d_instances) return QED_ERR_ARG;
+  if (stores->n_instances < 1 || field->kind != QED_FIELD_YEE) return QED_ERR_ARG;
+  if (!finite_pos(dt) || !finite_pos(eps_r) || !finite_pos(weight)) return QED_ERR_ARG;
+  for (int c = 0; c < 3; ++c)
+    if (!field->grid[c]) return QED_ERR_ARG;
+  for (int d = 0; d < 3; ++d)
+    if (field->n[d] < 1 || !finite_pos(field->dx[d]) || !isfinite(field->origin[d]))
+      return QED_ERR_ARG;
+  // cell indices are 32-bit in the kernel's index arithmetic
+  if ((long long)field->n[0] * field->n[1] * field->n[2] > 2147483647ll) return QED_ERR_ARG;
+  if (!soa_ok(stores->species[QED_ELECTRON], false) || !soa_ok(stores->species[QED_POSITRON], false))
+    return QED_ERR_ARG;
+  const hipError_t e = launch_schwinger(*stores, field->grid, field->n, field->dx, field->origin,
+                                        dt, eps_r, weight, reinterpret_cast<const long long*>(d_step),
+                                        d_record, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? QED_OK : QED_ERR_HIP;
+}
+
 size_t qed_thin_work_bytes(int n_instances, int64_t species_slots) {
   if (n_instances < 1 || species_slots < 0) return 0;
   return ThinLayout::make(n_instances, species_slots).total;

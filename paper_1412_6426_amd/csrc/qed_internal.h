@@ -262,6 +262,10 @@ hipError_t launch_thin(const qed_soa& s, int species, qed_instance* inst, int n_
                        long long slots, long long trigger, long long target,
                        const long long* d_step, qed_thin_record* rec, void* work,
                        hipStream_t st);
+hipError_t launch_schwinger(const qed_stores& st, const float* const grid[3], const int n[3],
+                            const double dx[3], const double origin[3], double dt, double eps_r,
+                            double weight, const long long* d_step, qed_schwinger_record* rec,
+                            hipStream_t s);
 // Persistent-grid sizing: resident workgroups per CU for the step kernels.
 int step_blocks_per_cu(int precision, bool photon, int block);
 

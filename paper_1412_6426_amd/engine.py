@@ -132,6 +132,13 @@ class Engine:
         self.inst[off:off + 8] = _torch().from_numpy(
             np.frombuffer(np.int64(n).tobytes(), dtype=np.uint8).copy()).to(self.device)
 
+    def set_frozen(self, inst: int, frozen: bool = True):
+        """Freeze (skip) or release one instance."""
+        off = inst * C.sizeof(Q.qed_instance) + Q.qed_instance.frozen.offset
+        self.inst[off:off + 4] = _torch().from_numpy(
+            np.frombuffer(np.int32(1 if frozen else 0).tobytes(), dtype=np.uint8).copy()).to(
+                self.device)
+
     def instances(self) -> List[Dict]:
         out = []
         for r in self._instances_host():
@@ -179,6 +186,23 @@ class Engine:
         n = C.sizeof(Q.qed_thin_record)
         return [Q.qed_thin_record.from_buffer_copy(raw[i * n:(i + 1) * n]).as_dict()
                 for i in range(self.n_inst)]
+
+    # ------------------------------------------------------------------ Schwinger pairs
+    def schwinger(self, field: Q.qed_field, dt: float, eps_r: float, weight: float = 1.0,
+                  stream: Optional[int] = None):
+        """qed_schwinger for step n = the step counter, on every instance; the record stays
+        on the device until schwinger_record() reads it."""
+        torch = _torch()
+        if not hasattr(self, "_sch_rec"):
+            self._sch_rec = torch.zeros(C.sizeof(Q.qed_schwinger_record), dtype=torch.uint8,
+                                        device=self.device)
+        Q.qed_schwinger(self.stores, field, float(dt), float(eps_r), float(weight),
+                        self.step_ctr.data_ptr(), self._sch_rec.data_ptr(),
+                        self.stream if stream is None else stream)
+
+    def schwinger_record(self) -> Dict:
+        raw = self._sch_rec.cpu().numpy().tobytes()
+        return Q.qed_schwinger_record.from_buffer_copy(raw).as_dict()
 
     # ------------------------------------------------------------------ the step
     @staticmethod

@@ -99,9 +99,17 @@ class qed_thin_record(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
+class qed_schwinger_record(C.Structure):
+    _fields_ = [("cells", C.c_int64), ("pairs", C.c_int64), ("dropped", C.c_int64),
+                ("saturated", C.c_int64), ("expected", C.c_double), ("reserved", C.c_int64)]
+
+    def as_dict(self) -> Dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 #: every symbol include/qed.h declares
 EXPORTS = ("qed_table_bytes", "qed_build_tables", "qed_work_bytes", "qed_step",
-           "qed_thin_work_bytes", "qed_thin",
+           "qed_thin_work_bytes", "qed_thin", "qed_schwinger",
            "qed_append_stats", "qed_photon_spectrum", "qed_fill_standing_wave",
            "qed_status_string", "qed_version")
 
@@ -137,6 +145,10 @@ def lib():
                                C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
         L.qed_append_stats.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
                                        C.c_void_p]
+        L.qed_schwinger.restype = C.c_int
+        L.qed_schwinger.argtypes = [C.POINTER(qed_stores), C.POINTER(qed_field), C.c_double,
+                                    C.c_double, C.c_double, C.c_void_p, C.c_void_p,
+                                    C.c_void_p]
         L.qed_photon_spectrum.restype = C.c_int
         L.qed_photon_spectrum.argtypes = [C.POINTER(qed_stores), C.c_double, C.c_double,
                                           C.c_int, C.c_void_p, C.c_void_p]
@@ -186,6 +198,12 @@ def qed_thin(stores: qed_stores, species: int, trigger: int, target: int, d_step
              d_records: int, d_work: int, work_bytes: int, stream: int) -> None:
     _check(lib().qed_thin(C.byref(stores), species, trigger, target, d_step, d_records, d_work,
                           work_bytes, stream), "qed_thin")
+
+
+def qed_schwinger(stores: qed_stores, field: qed_field, dt: float, eps_r: float,
+                  weight: float, d_step: int, d_record: int, stream: int) -> None:
+    _check(lib().qed_schwinger(C.byref(stores), C.byref(field), dt, eps_r, weight, d_step,
+                               d_record, stream), "qed_schwinger")
 
 
 def qed_append_stats(d_stats: int, d_log: int, log_capacity: int, d_log_count: int,

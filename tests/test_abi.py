@@ -43,7 +43,7 @@ def test_ctypes_layout_matches_header(Q, tmp_path):
     """Compile a probe against include/qed.h with gcc and compare every struct's size and
     every field's offset with the ctypes mirror."""
     structs = [Q.qed_soa, Q.qed_instance, Q.qed_stores, Q.qed_field, Q.qed_params, Q.qed_stats,
-               Q.qed_thin_record]
+               Q.qed_thin_record, Q.qed_schwinger_record]
     lines = ['#include "qed.h"', "#include <stdio.h>", "#include <stddef.h>", "int main(void){"]
     expect = []
     for S in structs:
@@ -113,6 +113,30 @@ def test_thin_argument_validation_without_device(Q):
     st.slots[2] = 1 << 32
     assert L.qed_thin(C.byref(st), 2, 10, 5, fake, fake, fake, 1 << 40,
                       None) == Q.QED_ERR_UNSUPPORTED
+
+
+def test_schwinger_argument_validation_without_device(Q):
+    L = Q.lib()
+    st = Q.qed_stores()
+    st.n_instances = 1
+    st.d_instances = 4096
+    fake = C.c_void_p(4096)
+    f = Q.qed_field()
+    f.kind = Q.QED_FIELD_UNIFORM
+    assert L.qed_schwinger(C.byref(st), C.byref(f), 1.0, 1.0, 1.0, fake, fake,
+                           None) == Q.QED_ERR_ARG  # not a grid
+    f.kind = Q.QED_FIELD_YEE
+    for c in range(6):
+        f.grid[c] = C.cast(C.c_void_p(4096), Q._fp)
+    f.n = (C.c_int * 3)(4, 4, 4)
+    f.dx = (C.c_double * 3)(1.0, 1.0, 1.0)
+    assert L.qed_schwinger(C.byref(st), C.byref(f), 0.0, 1.0, 1.0, fake, fake,
+                           None) == Q.QED_ERR_ARG  # dt
+    assert L.qed_schwinger(C.byref(st), C.byref(f), 1.0, 1.0, 1.0, fake, fake,
+                           None) == Q.QED_ERR_ARG  # lepton columns missing
+    f.n = (C.c_int * 3)(2048, 2048, 1024)
+    assert L.qed_schwinger(C.byref(st), C.byref(f), 1.0, 1.0, 1.0, fake, fake,
+                           None) == Q.QED_ERR_ARG  # 2^32 cells
 
 
 def test_argument_validation_without_device(Q):
