@@ -5,15 +5,20 @@
 // four staggered samples on the cell; the magnetic field is neglected, as in the paper's
 // presentation).  The pair starts at rest at a random point of the cell.
 //
-// One launch: a grid-stride loop over the cells, one lane per cell.  The field of a cell is
-// read once and serves every instance; each instance draws with its own seed.  Pairs are
-// rare, so they reserve store slots directly (one atomic per wavefront, instance and
-// species), and the store order of created pairs follows the reservations.
+// One launch: a wavefront takes 64 consecutive cells of one (j, k) row of the grid at a time
+// (a grid-stride loop over those pieces), so its loads coalesce and the row indices are
+// wavefront-uniform.  The field of a cell is read once and serves every instance; each
+// instance draws with its own seed.  A probability at or below 2^-53, the smallest uniform
+// the draw can give, decides without drawing.  Pairs are rare, so they reserve store slots
+// directly (one atomic per wavefront, instance and species), and the store order of created
+// pairs follows the reservations.
 #include "qed_internal.h"
 
 namespace qedk {
 
 namespace {
+
+constexpr int kXcds = 8;  // accelerator complex dies of the GPU, each with its own L2
 
 struct SchwingerArgs {
   const float* g[3];  // Ex, Ey, Ez
@@ -29,11 +34,11 @@ struct SchwingerArgs {
   qed_schwinger_record* rec;
 };
 
-__device__ __forceinline__ double grid_at(const float* g, const int n[3], int i, int j, int k) {
-  i = i == n[0] ? 0 : i;
+// Row (j, k) of a component, with the periodic wrap of j and k (wavefront-uniform).
+__device__ __forceinline__ const float* grid_row(const float* g, const int n[3], int j, int k) {
   j = j == n[1] ? 0 : j;
   k = k == n[2] ? 0 : k;
-  return (double)g[i + (long long)n[0] * (j + (long long)n[1] * k)];
+  return g + (long long)n[0] * (j + (long long)n[1] * k);
 }
 
 // Reserve slots of species store S of instance li for the flagged lanes (all lanes call);
@@ -60,78 +65,175 @@ __device__ __forceinline__ long long reserve(const SchwingerArgs& a, int sp, boo
   return (flag && fits) ? a.inst[li].base[sp] + pos : -1;
 }
 
+// 64 consecutive cells of one row (lane i0 + lane) and their twelve field samples: Ex at
+// rows (j, k), (j+1, k), (j, k+1), (j+1, k+1) of column i; Ey at (j, k) and (j, k+1) of
+// columns i, i+1; Ez at (j, k) and (j+1, k) of columns i, i+1 (periodic).
+struct Piece {
+  int i, j, k;
+  bool has;
+  long long c;  // cell index i + n0 (j + n1 k)
+  float v[12];
+};
+
+__device__ __forceinline__ Piece load_piece(const SchwingerArgs& a, int piece, int ppr,
+                                            int lane) {
+  Piece q{};
+  const int row = piece / ppr;
+  q.i = ((piece - row * ppr) << 6) + lane;
+  q.j = row % a.n[1];
+  q.k = row / a.n[1];
+  q.has = q.i < a.n[0];
+  q.c = (long long)q.i + (long long)a.n[0] * row;
+  const float* x00 = grid_row(a.g[0], a.n, q.j, q.k);
+  const float* x10 = grid_row(a.g[0], a.n, q.j + 1, q.k);
+  const float* x01 = grid_row(a.g[0], a.n, q.j, q.k + 1);
+  const float* x11 = grid_row(a.g[0], a.n, q.j + 1, q.k + 1);
+  const float* y00 = grid_row(a.g[1], a.n, q.j, q.k);
+  const float* y01 = grid_row(a.g[1], a.n, q.j, q.k + 1);
+  const float* z00 = grid_row(a.g[2], a.n, q.j, q.k);
+  const float* z10 = grid_row(a.g[2], a.n, q.j + 1, q.k);
+  if (q.has) {
+    const int i = q.i;
+    const int i1 = i + 1 == a.n[0] ? 0 : i + 1;
+    q.v[0] = x00[i];
+    q.v[1] = x10[i];
+    q.v[2] = x01[i];
+    q.v[3] = x11[i];
+    q.v[4] = y00[i];
+    q.v[5] = y00[i1];
+    q.v[6] = y01[i];
+    q.v[7] = y01[i1];
+    q.v[8] = z00[i];
+    q.v[9] = z00[i1];
+    q.v[10] = z10[i];
+    q.v[11] = z10[i1];
+  }
+  return q;
+}
+
+// Orders a wavefront's LDS stores before its following LDS loads (other lanes' slots).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Draws of one lane's cell c with probability P for every non-frozen instance (all lanes
+// call; lanes with has == false take part in the ballots only), and the pairs they make.
+__device__ __forceinline__ void draw_cells(const SchwingerArgs& a, long long c, double P, bool has,
+                                           uint32_t step, unsigned long long& pairs,
+                                           unsigned long long& dropped) {
+  for (int li = 0; li < a.n_inst; ++li) {
+    const qed_instance& I = a.inst[li];
+    if (I.frozen) continue;  // instance-uniform
+    const uint64_t seed = I.seed;
+    bool make = false;
+    if (has) {
+      const uint4 o = draw_words((uint64_t)c, seed, step, 0u, kSchwinger);
+      make = uniform64(o.x, o.y) < P;
+    }
+    if (!wave_ballot(make)) continue;
+    pairs += make ? 1u : 0u;
+    uint4 w{};
+    long long i = 0, j = 0, k = 0;
+    if (make) {
+      w = draw_words((uint64_t)c, seed, step, 0u, kSchwingerPos);
+      const long long row = c / a.n[0];
+      i = c - row * a.n[0];
+      j = row % a.n[1];
+      k = row / a.n[1];
+    }
+    const double x = a.origin[0] + ((double)i + ((double)w.x + 0.5) * 0x1p-32) * a.dx[0];
+    const double y = a.origin[1] + ((double)j + ((double)w.y + 0.5) * 0x1p-32) * a.dx[1];
+    const double z = a.origin[2] + ((double)k + ((double)w.z + 0.5) * 0x1p-32) * a.dx[2];
+    for (int sp = 0; sp < 2; ++sp) {
+      const long long q = reserve(a, sp, make, li, dropped);
+      if (q < 0) continue;
+      const qed_soa& S = sp == 0 ? a.e : a.p;
+      S.x[q] = x;
+      S.y[q] = y;
+      S.z[q] = z;
+      S.px[q] = 0.0;
+      S.py[q] = 0.0;
+      S.pz[q] = 0.0;
+      S.w[q] = a.weight;
+      S.id[q] = child_id((uint64_t)c, seed, step, 0u,
+                         sp == 0 ? kSchwingerElectron : kSchwingerPositron);
+      S.parent[q] = QED_NO_PARENT;
+      S.birth[q] = birth_code(step, 0u);
+      if (S.n_events) S.n_events[q] = 0u;
+    }
+  }
+}
+
 __global__ void __launch_bounds__(256) schwinger_kernel(SchwingerArgs a) {
+  __shared__ long long s_qc[4][128];  // per-wavefront queue of cells to draw for
+  __shared__ double s_qp[4][128];     // and their probabilities
   __shared__ double s_exp[4];
   __shared__ unsigned long long s_cnt[4][4];
   const int lane = lane_id();
-  const int wv = (int)(threadIdx.x >> 6);
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // uniform: scalar indexing
   const uint32_t step = (uint32_t)*a.d_step;
-  const long long stride = (long long)gridDim.x * blockDim.x;
+  const int pieces_per_row = (a.n[0] + 63) >> 6;
+  const int rows = a.n[1] * a.n[2];
+  const int pieces = rows * pieces_per_row;
+  // Workgroups go to the 8 XCDs in turn (workgroup b to XCD b % 8).  XCD x takes the x-th
+  // eighth of the pieces, in row order, so that a row's neighbours in j and k, which its
+  // cells also read, are read through the same L2.
+  const int xcd = (int)(blockIdx.x & (kXcds - 1));
+  const int per_xcd = (pieces + kXcds - 1) / kXcds;
+  const int p_lo = xcd * per_xcd;
+  const int p_hi = p_lo + per_xcd < pieces ? p_lo + per_xcd : pieces;
+  const int V = (int)(gridDim.x / kXcds) * (int)(blockDim.x >> 6);  // wavefronts of this XCD
   double expected = 0.0;
   unsigned long long visited = 0, pairs = 0, sat = 0, dropped = 0;
-  // the loop bound is wavefront-uniform so that every lane reaches the ballots
-  for (long long c0 = (long long)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); c0 < a.cells;
-       c0 += stride) {
-    const long long c = c0 + lane;
-    const bool has = c < a.cells;
+  int n_active = 0;
+  for (int li = 0; li < a.n_inst; ++li) n_active += a.inst[li].frozen ? 0 : 1;
+  // Cells whose probability needs a draw wait in this wavefront's queue, and are drawn for 64
+  // at a time, so that the Philox rounds run with full wavefronts wherever the field puts the
+  // drawing cells (a row of 64 cells can mix strong and weak fields).
+  long long* const qc = s_qc[wv];
+  double* const qp = s_qp[wv];
+  int qn = 0;  // wavefront-uniform
+  // wavefront-uniform loop, so that every lane reaches the ballots
+  for (int piece = p_lo + (int)(blockIdx.x / kXcds) * (int)(blockDim.x >> 6) + wv; piece < p_hi;
+       piece += V) {
+    const Piece cur = load_piece(a, piece, pieces_per_row, lane);
     double P = 0.0;
-    int i = 0, j = 0, k = 0;
-    if (has) {
-      i = (int)(c % a.n[0]);
-      const long long r = c / a.n[0];
-      j = (int)(r % a.n[1]);
-      k = (int)(r / a.n[1]);
-      const double ex = 0.25 * (grid_at(a.g[0], a.n, i, j, k) + grid_at(a.g[0], a.n, i, j + 1, k) +
-                                grid_at(a.g[0], a.n, i, j, k + 1) +
-                                grid_at(a.g[0], a.n, i, j + 1, k + 1));
-      const double ey = 0.25 * (grid_at(a.g[1], a.n, i, j, k) + grid_at(a.g[1], a.n, i + 1, j, k) +
-                                grid_at(a.g[1], a.n, i, j, k + 1) +
-                                grid_at(a.g[1], a.n, i + 1, j, k + 1));
-      const double ez = 0.25 * (grid_at(a.g[2], a.n, i, j, k) + grid_at(a.g[2], a.n, i + 1, j, k) +
-                                grid_at(a.g[2], a.n, i, j + 1, k) +
-                                grid_at(a.g[2], a.n, i + 1, j + 1, k));
+    if (cur.has) {
+      // each component the mean of its four samples on the cell, summed in this order
+      const float* v = cur.v;
+      const double ex = 0.25 * ((double)v[0] + (double)v[1] + (double)v[2] + (double)v[3]);
+      const double ey = 0.25 * ((double)v[4] + (double)v[5] + (double)v[6] + (double)v[7]);
+      const double ez = 0.25 * ((double)v[8] + (double)v[9] + (double)v[10] + (double)v[11]);
       const double e = sqrt(ex * ex + ey * ey + ez * ez) * a.eps_r;  // E / E_S
       if (e > 0.0) P = a.pref * e * e * exp(-kPi / e);
-    }
-    for (int li = 0; li < a.n_inst; ++li) {
-      const qed_instance& I = a.inst[li];
-      if (I.frozen) continue;  // instance-uniform
-      const uint64_t seed = I.seed;
-      if (has) {
+      for (int li = 0; li < n_active; ++li) {  // once per drawing instance
         ++visited;
         expected += P < 1.0 ? P : 1.0;
         sat += P >= 1.0 ? 1u : 0u;
       }
-      bool make = false;
-      uint4 w{};
-      if (has && P > 0.0) {
-        const uint4 o = draw_words((uint64_t)c, seed, step, 0u, kSchwinger);
-        make = uniform64(o.x, o.y) < P;
-        if (make) w = draw_words((uint64_t)c, seed, step, 0u, kSchwingerPos);
-      }
-      if (!wave_ballot(make)) continue;
-      pairs += make ? 1u : 0u;
-      const double x = a.origin[0] + ((double)i + ((double)w.x + 0.5) * 0x1p-32) * a.dx[0];
-      const double y = a.origin[1] + ((double)j + ((double)w.y + 0.5) * 0x1p-32) * a.dx[1];
-      const double z = a.origin[2] + ((double)k + ((double)w.z + 0.5) * 0x1p-32) * a.dx[2];
-      for (int sp = 0; sp < 2; ++sp) {
-        const long long q = reserve(a, sp, make, li, dropped);
-        if (q < 0) continue;
-        const qed_soa& S = sp == 0 ? a.e : a.p;
-        S.x[q] = x;
-        S.y[q] = y;
-        S.z[q] = z;
-        S.px[q] = 0.0;
-        S.py[q] = 0.0;
-        S.pz[q] = 0.0;
-        S.w[q] = a.weight;
-        S.id[q] = child_id((uint64_t)c, seed, step, 0u,
-                           sp == 0 ? kSchwingerElectron : kSchwingerPositron);
-        S.parent[q] = QED_NO_PARENT;
-        S.birth[q] = birth_code(step, 0u);
-        if (S.n_events) S.n_events[q] = 0u;
-      }
     }
+    // below 2^-53 (the smallest uniform the draw gives) a cell decides without drawing
+    const bool need = cur.has && n_active > 0 && P > 0x1p-53;
+    const uint64_t m = wave_ballot(need);
+    if (need) {
+      const int at = qn + __popcll(m & lanes_below());
+      qc[at] = cur.c;
+      qp[at] = P;
+    }
+    qn += __popcll(m);
+    if (qn >= 64) {
+      qn -= 64;
+      wave_lds_sync();
+      draw_cells(a, qc[qn + lane], qp[qn + lane], true, step, pairs, dropped);
+      wave_lds_sync();
+    }
+  }
+  if (qn > 0) {
+    wave_lds_sync();
+    const bool has = lane < qn;
+    draw_cells(a, has ? qc[lane] : 0, has ? qp[lane] : 0.0, has, step, pairs, dropped);
   }
   // workgroup totals (fixed order within a workgroup), then one atomic each
 #pragma unroll
@@ -160,16 +262,24 @@ __global__ void __launch_bounds__(256) schwinger_kernel(SchwingerArgs a) {
       s += s_cnt[q][2];
       d += s_cnt[q][3];
     }
+    (void)v;  // the cells visited are counted by the clearing kernel
     if (e != 0.0) atomicAdd(&a.rec->expected, e);
-    if (v) atomicAdd(reinterpret_cast<unsigned long long*>(&a.rec->cells), v);
     if (p) atomicAdd(reinterpret_cast<unsigned long long*>(&a.rec->pairs), p);
     if (s) atomicAdd(reinterpret_cast<unsigned long long*>(&a.rec->saturated), s);
     if (d) atomicAdd(reinterpret_cast<unsigned long long*>(&a.rec->dropped), d);
   }
 }
 
-__global__ void schwinger_clear_kernel(qed_schwinger_record* rec) {
-  if (threadIdx.x == 0) *rec = qed_schwinger_record{};
+// Clears the record and counts the cells to visit (cells times non-frozen instances), so
+// that the main kernel's workgroups add only what they found (one atomic each, mostly).
+__global__ void schwinger_clear_kernel(qed_schwinger_record* rec, const qed_instance* inst,
+                                       int n_inst, long long cells) {
+  if (threadIdx.x != 0) return;
+  long long active = 0;
+  for (int i = 0; i < n_inst; ++i) active += inst[i].frozen ? 0 : 1;
+  qed_schwinger_record r{};
+  r.cells = active * cells;
+  *rec = r;
 }
 
 }  // namespace
@@ -195,9 +305,13 @@ hipError_t launch_schwinger(const qed_stores& st, const float* const grid[3], co
   a.cells = (long long)n[0] * n[1] * n[2];
   a.d_step = d_step;
   a.rec = rec;
+  // 4 wavefronts per SIMD on 256 CUs (each workgroup ends with a few atomics on the record,
+  // so not more), a multiple of the XCD count so that every XCD gets the same number
   long long blocks = (a.cells + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(schwinger_clear_kernel, dim3(1), dim3(64), 0, s, rec);
+  if (blocks > 1024) blocks = 1024;
+  blocks = ((blocks + kXcds - 1) / kXcds) * kXcds;
+  hipLaunchKernelGGL(schwinger_clear_kernel, dim3(1), dim3(64), 0, s, rec, a.inst, a.n_inst,
+                     a.cells);
   hipLaunchKernelGGL(schwinger_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }

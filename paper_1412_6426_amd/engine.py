@@ -192,17 +192,24 @@ class Engine:
                   stream: Optional[int] = None):
         """qed_schwinger for step n = the step counter, on every instance; the record stays
         on the device until schwinger_record() reads it."""
-        torch = _torch()
-        if not hasattr(self, "_sch_rec"):
-            self._sch_rec = torch.zeros(C.sizeof(Q.qed_schwinger_record), dtype=torch.uint8,
-                                        device=self.device)
         Q.qed_schwinger(self.stores, field, float(dt), float(eps_r), float(weight),
-                        self.step_ctr.data_ptr(), self._sch_rec.data_ptr(),
+                        self.step_ctr.data_ptr(), self.schwinger_record_buffer().data_ptr(),
                         self.stream if stream is None else stream)
 
-    def schwinger_record(self) -> Dict:
-        raw = self._sch_rec.cpu().numpy().tobytes()
+    def schwinger_record_buffer(self):
+        """The device bytes of the last qed_schwinger record (allocated on first use)."""
+        if not hasattr(self, "_sch_rec"):
+            torch = _torch()
+            self._sch_rec = torch.zeros(C.sizeof(Q.qed_schwinger_record), dtype=torch.uint8,
+                                        device=self.device)
+        return self._sch_rec
+
+    @staticmethod
+    def decode_schwinger_record(raw: bytes) -> Dict:
         return Q.qed_schwinger_record.from_buffer_copy(raw).as_dict()
+
+    def schwinger_record(self) -> Dict:
+        return self.decode_schwinger_record(self.schwinger_record_buffer().cpu().numpy().tobytes())
 
     # ------------------------------------------------------------------ the step
     @staticmethod
