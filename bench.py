@@ -706,6 +706,8 @@ def main():
     ap.add_argument("--avalanche-lepton-cap", type=int, default=40_000_000)
     ap.add_argument("--no-schwinger", action="store_true",
                     help="skip Schwinger pair production on the 256^3 grid")
+    ap.add_argument("--schwinger-only", action="store_true",
+                    help="run only the Schwinger leg and print its record (profiling)")
     ap.add_argument("--no-tune", action="store_true",
                     help="use --tile / --grid-blocks for every step instead of tuning")
     args = ap.parse_args()
@@ -723,6 +725,9 @@ def main():
         return
     if args.avalanche_only:
         print(json.dumps({"avalanche_time_step_invariance": gpu_avalanche(args)}), flush=True)
+        return
+    if args.schwinger_only:
+        print(json.dumps({"schwinger_grid": gpu_schwinger_grid(args)}), flush=True)
         return
     print(f"bench: rotating-E cascade, {args.seeds} seeds, precision {args.precision}",
           file=sys.stderr, flush=True)

@@ -4,12 +4,16 @@
         per-kernel dispatch count, total and average duration from a --kernel-trace run
         (the rocpd database rocprofv3 writes, or its *kernel_stats.csv).
 
-    python -m paper_1412_6426_amd.calib.profile_summary hbm --kernel NAME \\
+    python -m paper_1412_6426_amd.calib.profile_summary hbm --kernel NAME [--source FILE] \\
         --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR --out FILE --command CMD
         HBM bytes per launch of NAME from a FETCH_SIZE and a WRITE_SIZE pass, each scaled by
         the same counter's reading for lib/hbm_copy (800 MB read and 800 MB written per
         launch).  The summary records the sha256 of the kernel source so that a reader can
         tell whether the figure still describes the current kernel.
+
+    python -m paper_1412_6426_amd.calib.profile_summary pmc --kernel NAME DIR [DIR ...] \\
+        --out FILE --command CMD
+        mean per dispatch of every counter collected for NAME in the --pmc output dirs.
 """
 import argparse
 import collections
@@ -95,7 +99,7 @@ def cmd_hbm(a):
     fw = COPY_BYTES / (statistics.median(cw) * 1024.0)
     fetch_b = statistics.mean(f) * 1024.0 * ff
     write_b = statistics.mean(w) * 1024.0 * fw
-    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    sha = hashlib.sha256(open(a.source, "rb").read()).hexdigest()
     lines = [f"# {a.title}", "", "Commands (from the repository root):", "", "```",
              a.command, "```", "",
              f"- kernel: {a.kernel}",
@@ -117,12 +121,42 @@ def cmd_hbm(a):
     print("\n".join(lines))
 
 
+def cmd_pmc(a):
+    rows = collections.defaultdict(list)
+    for d in a.dirs:
+        for db in _dbs(d):
+            c = sqlite3.connect(db)
+            acc = collections.defaultdict(float)
+            for disp, name, cname, value in c.execute(
+                    "select dispatch_id, kernel_name, counter_name, value "
+                    "from counters_collection"):
+                if _short(name) == a.kernel:
+                    acc[(disp, cname)] += value
+            for (_, cname), v in acc.items():
+                rows[cname].append(v)
+    if not rows:
+        raise SystemExit(f"no dispatches of {a.kernel} in the counter output")
+    lines = [f"# {a.title}", "", "Commands (from the repository root):", "", "```",
+             a.command, "```", "", f"- kernel: {a.kernel}",
+             "", "| counter | dispatches | mean per dispatch |", "|---|---:|---:|"]
+    for cname in sorted(rows):
+        v = rows[cname]
+        lines.append(f"| {cname} | {len(v)} | {statistics.mean(v):.6g} |")
+    if a.note:
+        lines += ["", a.note]
+    open(a.out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
     t = sub.add_parser("trace")
     t.add_argument("dir")
-    for p in (t, sub.add_parser("hbm")):
+    m = sub.add_parser("pmc")
+    m.add_argument("dirs", nargs="+")
+    m.add_argument("--kernel", required=True)
+    for p in (t, sub.add_parser("hbm"), m):
         p.add_argument("--out", required=True)
         p.add_argument("--command", required=True)
         p.add_argument("--title", default="rocprofv3 summary")
@@ -133,8 +167,10 @@ def main():
     h.add_argument("--write", required=True)
     h.add_argument("--copy-fetch", required=True)
     h.add_argument("--copy-write", required=True)
+    h.add_argument("--source", default=KERNEL_SRC,
+                   help="kernel source whose sha256 the summary records")
     a = ap.parse_args()
-    (cmd_trace if a.cmd == "trace" else cmd_hbm)(a)
+    {"trace": cmd_trace, "hbm": cmd_hbm, "pmc": cmd_pmc}[a.cmd](a)
 
 
 if __name__ == "__main__":

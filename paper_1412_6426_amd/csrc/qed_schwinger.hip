@@ -43,7 +43,7 @@ __device__ __forceinline__ const float* grid_row(const float* g, const int n[3],
 
 // Reserve slots of species store S of instance li for the flagged lanes (all lanes call);
 // returns the lane's slot or -1.  Drops are counted in the instance and added to the
-// leader lane's `dropped`.
+// wavefront-uniform `dropped`.
 __device__ __forceinline__ long long reserve(const SchwingerArgs& a, int sp, bool flag, int li,
                                              unsigned long long& dropped) {
   const uint64_t m = wave_ballot(flag);
@@ -60,9 +60,13 @@ __device__ __forceinline__ long long reserve(const SchwingerArgs& a, int sp, boo
   if (lost && lane_id() == leader) {
     atomicAdd(reinterpret_cast<unsigned long long*>(&a.inst[li].dropped),
               (unsigned long long)__popcll(lost));
-    dropped += (unsigned long long)__popcll(lost);
   }
+  dropped += (unsigned long long)__popcll(lost);
   return (flag && fits) ? a.inst[li].base[sp] + pos : -1;
+}
+
+__device__ __forceinline__ float at_offset(const float* row, uint32_t byte_offset) {
+  return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(row) + byte_offset);
 }
 
 // 64 consecutive cells of one row (lane i0 + lane) and their twelve field samples: Ex at
@@ -93,20 +97,22 @@ __device__ __forceinline__ Piece load_piece(const SchwingerArgs& a, int piece, i
   const float* z00 = grid_row(a.g[2], a.n, q.j, q.k);
   const float* z10 = grid_row(a.g[2], a.n, q.j + 1, q.k);
   if (q.has) {
-    const int i = q.i;
-    const int i1 = i + 1 == a.n[0] ? 0 : i + 1;
-    q.v[0] = x00[i];
-    q.v[1] = x10[i];
-    q.v[2] = x01[i];
-    q.v[3] = x11[i];
-    q.v[4] = y00[i];
-    q.v[5] = y00[i1];
-    q.v[6] = y01[i];
-    q.v[7] = y01[i1];
-    q.v[8] = z00[i];
-    q.v[9] = z00[i1];
-    q.v[10] = z10[i];
-    q.v[11] = z10[i1];
+    // 32-bit byte offsets from the wavefront-uniform row pointers (a scalar base and one
+    // offset register per load)
+    const uint32_t o = (uint32_t)q.i << 2;
+    const uint32_t o1 = q.i + 1 == a.n[0] ? 0u : o + 4u;
+    q.v[0] = at_offset(x00, o);
+    q.v[1] = at_offset(x10, o);
+    q.v[2] = at_offset(x01, o);
+    q.v[3] = at_offset(x11, o);
+    q.v[4] = at_offset(y00, o);
+    q.v[5] = at_offset(y00, o1);
+    q.v[6] = at_offset(y01, o);
+    q.v[7] = at_offset(y01, o1);
+    q.v[8] = at_offset(z00, o);
+    q.v[9] = at_offset(z00, o1);
+    q.v[10] = at_offset(z10, o);
+    q.v[11] = at_offset(z10, o1);
   }
   return q;
 }
@@ -120,6 +126,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // Draws of one lane's cell c with probability P for every non-frozen instance (all lanes
 // call; lanes with has == false take part in the ballots only), and the pairs they make.
+// `pairs` and `dropped` are wavefront-uniform counts.
 __device__ __forceinline__ void draw_cells(const SchwingerArgs& a, long long c, double P, bool has,
                                            uint32_t step, unsigned long long& pairs,
                                            unsigned long long& dropped) {
@@ -132,8 +139,9 @@ __device__ __forceinline__ void draw_cells(const SchwingerArgs& a, long long c, 
       const uint4 o = draw_words((uint64_t)c, seed, step, 0u, kSchwinger);
       make = uniform64(o.x, o.y) < P;
     }
-    if (!wave_ballot(make)) continue;
-    pairs += make ? 1u : 0u;
+    const uint64_t made = wave_ballot(make);
+    if (!made) continue;
+    pairs += (unsigned long long)__popcll(made);
     uint4 w{};
     long long i = 0, j = 0, k = 0;
     if (make) {
@@ -170,7 +178,7 @@ __global__ void __launch_bounds__(256) schwinger_kernel(SchwingerArgs a) {
   __shared__ long long s_qc[4][128];  // per-wavefront queue of cells to draw for
   __shared__ double s_qp[4][128];     // and their probabilities
   __shared__ double s_exp[4];
-  __shared__ unsigned long long s_cnt[4][4];
+  __shared__ unsigned long long s_cnt[4][3];
   const int lane = lane_id();
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // uniform: scalar indexing
   const uint32_t step = (uint32_t)*a.d_step;
@@ -186,7 +194,8 @@ __global__ void __launch_bounds__(256) schwinger_kernel(SchwingerArgs a) {
   const int p_hi = p_lo + per_xcd < pieces ? p_lo + per_xcd : pieces;
   const int V = (int)(gridDim.x / kXcds) * (int)(blockDim.x >> 6);  // wavefronts of this XCD
   double expected = 0.0;
-  unsigned long long visited = 0, pairs = 0, sat = 0, dropped = 0;
+  // per lane: the expected count; per wavefront (uniform): pairs, saturated cells, drops
+  unsigned long long pairs = 0, sat = 0, dropped = 0;
   int n_active = 0;
   for (int li = 0; li < a.n_inst; ++li) n_active += a.inst[li].frozen ? 0 : 1;
   // Cells whose probability needs a draw wait in this wavefront's queue, and are drawn for 64
@@ -209,11 +218,10 @@ __global__ void __launch_bounds__(256) schwinger_kernel(SchwingerArgs a) {
       const double e = sqrt(ex * ex + ey * ey + ez * ez) * a.eps_r;  // E / E_S
       if (e > 0.0) P = a.pref * e * e * exp(-kPi / e);
       for (int li = 0; li < n_active; ++li) {  // once per drawing instance
-        ++visited;
         expected += P < 1.0 ? P : 1.0;
-        sat += P >= 1.0 ? 1u : 0u;
       }
     }
+    sat += (unsigned long long)__popcll(wave_ballot(P >= 1.0)) * (unsigned long long)n_active;
     // below 2^-53 (the smallest uniform the draw gives) a cell decides without drawing
     const bool need = cur.has && n_active > 0 && P > 0x1p-53;
     const uint64_t m = wave_ballot(need);
@@ -237,32 +245,24 @@ __global__ void __launch_bounds__(256) schwinger_kernel(SchwingerArgs a) {
   }
   // workgroup totals (fixed order within a workgroup), then one atomic each
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    expected += __shfl_xor(expected, o, 64);
-    visited += __shfl_xor(visited, o, 64);
-    pairs += __shfl_xor(pairs, o, 64);
-    sat += __shfl_xor(sat, o, 64);
-    dropped += __shfl_xor(dropped, o, 64);
-  }
+  for (int o = 32; o > 0; o >>= 1) expected += __shfl_xor(expected, o, 64);
   if (lane == 0) {
     s_exp[wv] = expected;
-    s_cnt[wv][0] = visited;
-    s_cnt[wv][1] = pairs;
-    s_cnt[wv][2] = sat;
-    s_cnt[wv][3] = dropped;
+    s_cnt[wv][0] = pairs;
+    s_cnt[wv][1] = sat;
+    s_cnt[wv][2] = dropped;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     double e = 0.0;
-    unsigned long long v = 0, p = 0, s = 0, d = 0;
+    unsigned long long p = 0, s = 0, d = 0;
     for (int q = 0; q < (int)(blockDim.x >> 6); ++q) {
       e += s_exp[q];
-      v += s_cnt[q][0];
-      p += s_cnt[q][1];
-      s += s_cnt[q][2];
-      d += s_cnt[q][3];
+      p += s_cnt[q][0];
+      s += s_cnt[q][1];
+      d += s_cnt[q][2];
     }
-    (void)v;  // the cells visited are counted by the clearing kernel
+    // the cells visited are counted by the clearing kernel
     if (e != 0.0) atomicAdd(&a.rec->expected, e);
     if (p) atomicAdd(reinterpret_cast<unsigned long long*>(&a.rec->pairs), p);
     if (s) atomicAdd(reinterpret_cast<unsigned long long*>(&a.rec->saturated), s);
