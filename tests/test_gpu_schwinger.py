@@ -32,12 +32,13 @@ def _note(msg):
     print(msg, flush=True)
 
 
-def _grids(seed):
+def _grids(seed, n=N, widths=(6.0, 5.0, 4.0)):
     """A field blob up to |E| = 4 E_S (eps_r = 1) with random directions, and a random B."""
     rng = np.random.default_rng(seed)
-    nx, ny, nz = N
+    nx, ny, nz = n
     k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
-    r2 = ((i - nx / 2) / 6.0) ** 2 + ((j - ny / 2) / 5.0) ** 2 + ((k - nz / 2) / 4.0) ** 2
+    r2 = (((i - nx / 2) / widths[0]) ** 2 + ((j - ny / 2) / widths[1]) ** 2 +
+          ((k - nz / 2) / widths[2]) ** 2)
     mag = 4.0 * np.exp(-r2)
     out = []
     for d in (0.48, 0.6, 0.64):  # a unit direction, with 10% noise per sample
@@ -59,9 +60,9 @@ def _engine(caps, seeds):
     return e
 
 
-def _field(grids):
+def _field(grids, n=N):
     dev = [torch.from_numpy(g).to("cuda") for g in grids]
-    f = Engine.make_field(Q.QED_FIELD_YEE, grid=dev, n=N, dx=(DX, DX, DX), origin=(-1.0, 0.5, 2.0))
+    f = Engine.make_field(Q.QED_FIELD_YEE, grid=dev, n=n, dx=(DX, DX, DX), origin=(-1.0, 0.5, 2.0))
     return f, dev
 
 
@@ -115,10 +116,56 @@ def test_schwinger_instances_draw_their_own_pairs(orc):
             got = e.read(i, s)
             if i == 2:
                 # the store keeps 10 of the instance's pairs (which ones depends on the order
-                # of the reservations): they are a subset of the oracle's pairs
+                # of the reservations): they are a subset of the oracle's pairs, field for field
                 assert len(got["id"]) == 10
+                want = ost[s].view()
+                at = {int(v): q for q, v in enumerate(want["id"])}
+                rows = [at[int(v)] for v in got["id"]]
+                for c in ("parent", "birth", "w", "px", "py", "pz"):
+                    assert np.array_equal(got[c], want[c][rows]), c
+                for c in ("x", "y", "z"):
+                    np.testing.assert_allclose(got[c], want[c][rows], rtol=1e-12, atol=1e-12)
                 continue
             compare_species(got, ost[s].view(), s, rtol=1e-12, label=f"instance {i} sp {s}")
         assert inst[i]["dropped"] == o["dropped"]
     assert r["pairs"] == want_pairs and r["dropped"] == want_drop and r["cells"] == want_cells
     assert want_drop > 0
+
+
+def test_schwinger_rows_of_several_pieces(orc):
+    """150 x 12 x 10 cells: each row is two full 64-cell pieces and a ragged 22-cell tail,
+    the pieces split unevenly over the workgroups, and the drawing cells of the blob fill the
+    per-wavefront draw queues several times over, with a partial queue left at the end."""
+    n = (150, 12, 10)
+    grids = _grids(3, n=n, widths=(40.0, 4.0, 3.5))
+    f, keep = _field(grids, n=n)
+    ofld = orc.Field(kind=orc.FIELD_YEE, grid=grids, dx=(DX, DX, DX), origin=(-1.0, 0.5, 2.0))
+    dt = 400.0
+    e = _engine([400_000], [11])
+    ost = _oracle_stores(orc, 400_000)
+    for step in range(3):
+        _note(f"schwinger rows step {step}")
+        e.set_step(step)
+        e.schwinger(f, dt, 1.0, weight=0.5)
+        torch.cuda.synchronize()
+        r = e.schwinger_record()
+        o = orc.schwinger(ost, ofld, dt, 1.0, 0.5, seed=11, step=step)
+        for c in ("cells", "pairs", "dropped", "saturated"):
+            assert r[c] == o[c], (step, c)
+        assert r["expected"] == pytest.approx(o["expected"], rel=1e-12)
+    assert r["pairs"] > 1000
+    for s in range(2):
+        compare_species(e.read(0, s), ost[s].view(), s, rtol=1e-12, label=f"species {s}")
+
+
+def test_schwinger_without_field_makes_nothing(orc):
+    grids = [np.zeros(N[::-1], np.float32) for _ in range(6)]
+    f, keep = _field(grids)
+    e = _engine([1000], [1])
+    e.set_step(0)
+    e.schwinger(f, 400.0, 1.0)
+    torch.cuda.synchronize()
+    r = e.schwinger_record()
+    assert r["cells"] == N[0] * N[1] * N[2]
+    assert r["pairs"] == 0 and r["expected"] == 0.0 and r["saturated"] == 0
+    assert e.instances()[0]["count"][:2] == [0, 0]
