@@ -78,7 +78,7 @@ typedef enum {
 #define QED_STATUS_NO_TABLES 16u  /* d_tables was not filled by qed_build_tables: nothing done */
 
 /* ---------------------------------------------------------------------------------------
- * Rate tables (Sec. IV.F: "tabulate in advance and use interpolation").
+ * Rate tables (Sec. IV.F: the rates are tabulated once and interpolated during the step).
  *
  * Three functions of z are tabulated, from which the emission rate of Eq. (24) and the
  * pair rate of Eq. (30) follow once their explicit delta and chi factors are pulled out:

@@ -137,6 +137,12 @@ def lib():
                                    C.c_double, C.c_double, C.c_uint64, C.c_int64,
                                    C.POINTER(OrSchwingerRecord)]
         L.or_schwinger.restype = C.c_int
+        L.or_generator_trials.argtypes = [C.POINTER(OrTables), C.c_int, C.c_int, C.c_double,
+                                          C.c_double, C.c_double, C.c_double, C.c_uint64,
+                                          C.c_int64, C.c_int64, _dp]
+        L.or_generator_trials.restype = C.c_int64
+        L.or_standard_w.argtypes = [C.POINTER(OrTables), C.c_int] + [C.c_double] * 5
+        L.or_standard_w.restype = C.c_double
         for fn in ("or_emission_trials", "or_pair_trials"):
             getattr(L, fn).argtypes = [C.POINTER(OrTables), C.c_int, C.c_double, C.c_double,
                                        C.c_double, C.c_uint64, C.c_int64, _dp]
@@ -265,6 +271,26 @@ def emission_trials(chi, gamma, dtfac, key, n, backend=TABLE):
     m = lib().or_emission_trials(C.byref(tables()), backend, chi, gamma, dtfac, key, int(n),
                                  out.ctypes.data_as(_dp))
     return out[:m]
+
+
+GEN_MODIFIED, GEN_ALTERNATIVE, GEN_STANDARD = 0, 1, 2
+
+
+def generator_trials(generator, chi, gamma, dtfac, key, n, first=0, delta_min=1e-3,
+                     backend=TABLE):
+    """Per-trial delta of one emission generator of Sec. IV.G (0: no emission)."""
+    out = np.empty(int(n), dtype=np.float64)
+    m = lib().or_generator_trials(C.byref(tables()), backend, int(generator), chi, gamma,
+                                  dtfac, float(delta_min), key, int(first), int(n),
+                                  out.ctypes.data_as(_dp))
+    if m < 0:
+        raise ValueError("unknown generator or delta_min outside (0, 1)")
+    return out
+
+
+def standard_w(x, chi, gamma, dtfac, delta_min, backend=TABLE):
+    """W(x) of the standard generator, Eq. (23)."""
+    return lib().or_standard_w(C.byref(tables()), backend, chi, gamma, dtfac, delta_min, x)
 
 
 def pair_trials(chi_g, kabs, dtfac, key, n, backend=TABLE):

@@ -18,7 +18,7 @@
  *  - children are stored at once but processed from the next step on;
  *  - emission recoil conserves momentum: k = delta*gamma*p/|p|, p <- p - k (Sec. IV.F);
  *  - pair split: electron r1*k, positron (1-r1)*k (Sec. V.A);
- *  - the rates are tabulated as in Sec. IV.F ("tabulate ... and use interpolation"):
+ *  - the rates are tabulated once and interpolated, as Sec. IV.F suggests:
  *    three 1-D tables in z = 2^u of e^z*F(z) for F = int K_{5/3}, K_{2/3}, int K_{1/3},
  *    4096 nodes uniform in u on [-20, 7], linear interpolation in u, a small-z series
  *    below z = 2^-20 and zero above z = 2^7.
@@ -954,6 +954,146 @@ int64_t or_emission_trials(const or_tables *t, int backend, double chi, double g
     double r2 = or_uniform(o[2], o[3]);
     if (r2 < or_rate_modified(t, backend, r1, chi, gamma, dtfac)) delta_out[m++] = r1 * r1 * r1;
   }
+  return m;
+}
+
+/* ------------------------------------------------------------------------------------
+ * The three emission generators of Sec. IV.G as independent trials (the setting of the
+ * paper's comparison of their spectra).
+ *
+ * W(x) of the standard generator (Eq. (23)) is integrated in u = log2 z, with
+ * z = (2/3) delta / (chi (1 - delta)) the argument of Eq. (21)'s functions, so
+ *   delta(u) = q / (1 + q),  q = 1.5 chi 2^u,  d delta / du = ln 2 delta (1 - delta).
+ * The panels are the rate table's own intervals in u (the integrand is smooth inside each,
+ * the interpolation's kinks sit on the panel ends), each integrated by 5-point
+ * Gauss-Legendre; above z = 2^u_hi the rate is zero.  W at the panel ends is summed once,
+ * as the paper suggests tabulating W, and Eq. (22)'s root is found by bisection in u inside
+ * the panel that holds it.
+ * ------------------------------------------------------------------------------------ */
+typedef struct {
+  const or_tables *t;
+  int backend;
+  double chi, gamma, dtfac;
+} or_w_args;
+
+static double or_w_integrand(const or_w_args *a, double u) {
+  const double q = 1.5 * a->chi * exp2(u);
+  const double d = q / (1.0 + q);
+  return or_rate_emission(a->t, a->backend, d, a->chi, a->gamma, a->dtfac) * log(2.0) * d /
+         (1.0 + q);
+}
+
+/* 5-point Gauss-Legendre on [lo, hi]: nodes 0, +-sqrt(5 -+ 2 sqrt(10/7)) / 3 */
+static double or_gl5(const or_w_args *a, double lo, double hi) {
+  const double x1 = sqrt(5.0 - 2.0 * sqrt(10.0 / 7.0)) / 3.0;
+  const double x2 = sqrt(5.0 + 2.0 * sqrt(10.0 / 7.0)) / 3.0;
+  const double w0 = 128.0 / 225.0;
+  const double w1 = (322.0 + 13.0 * sqrt(70.0)) / 900.0;
+  const double w2 = (322.0 - 13.0 * sqrt(70.0)) / 900.0;
+  const double c = 0.5 * (lo + hi), h = 0.5 * (hi - lo);
+  return h * (w0 * or_w_integrand(a, c) +
+              w1 * (or_w_integrand(a, c - h * x1) + or_w_integrand(a, c + h * x1)) +
+              w2 * (or_w_integrand(a, c - h * x2) + or_w_integrand(a, c + h * x2)));
+}
+
+typedef struct {
+  int n;         /* panels */
+  double *edge;  /* n + 1 panel ends in u */
+  double *cum;   /* W at the panel ends */
+} or_w_table;
+
+/* panels from u(delta_min) to u_hi on the table's grid u_lo + k du (continued below u_lo) */
+static int or_w_table_build(const or_w_args *a, double delta_min, or_w_table *w) {
+  const or_tables *t = a->t;
+  const double u0 = log2((2.0 / 3.0) * delta_min / (a->chi * (1.0 - delta_min)));
+  const double top = t->u_hi;
+  w->n = 0;
+  w->edge = w->cum = NULL;
+  if (!(u0 < top)) return 0; /* no rate above delta_min */
+  const double k0 = floor((u0 - t->u_lo) / t->du) + 1.0; /* first grid point above u0 */
+  const int n = 1 + (int)ceil((top - (t->u_lo + k0 * t->du)) / t->du);
+  w->edge = (double *)malloc((size_t)(n + 1) * sizeof(double));
+  w->cum = (double *)malloc((size_t)(n + 1) * sizeof(double));
+  if (!w->edge || !w->cum) return -1;
+  w->edge[0] = u0;
+  for (int k = 1; k <= n; ++k) {
+    const double e = t->u_lo + (k0 + k - 1) * t->du;
+    w->edge[k] = e < top ? e : top;
+  }
+  w->cum[0] = 0.0;
+  for (int k = 0; k < n; ++k) w->cum[k + 1] = w->cum[k] + or_gl5(a, w->edge[k], w->edge[k + 1]);
+  w->n = n;
+  return 0;
+}
+
+static void or_w_table_free(or_w_table *w) {
+  free(w->edge);
+  free(w->cum);
+}
+
+/* W at u, inside the table's range */
+static double or_w_at(const or_w_args *a, const or_w_table *w, double u) {
+  if (w->n == 0 || u <= w->edge[0]) return 0.0;
+  if (u >= w->edge[w->n]) return w->cum[w->n];
+  int k = 0;
+  while (w->edge[k + 1] <= u) ++k;
+  return w->cum[k] + or_gl5(a, w->edge[k], u);
+}
+
+double or_standard_w(const or_tables *t, int backend, double chi, double gamma, double dtfac,
+                     double delta_min, double x) {
+  const or_w_args a = {t, backend, chi, gamma, dtfac};
+  or_w_table w;
+  if (or_w_table_build(&a, delta_min, &w) != 0) return NAN;
+  const double r = or_w_at(&a, &w, log2((2.0 / 3.0) * x / (chi * (1.0 - x))));
+  or_w_table_free(&w);
+  return r;
+}
+
+int64_t or_generator_trials(const or_tables *t, int backend, int generator, double chi,
+                            double gamma, double dtfac, double delta_min, uint64_t key,
+                            int64_t first, int64_t n, double *delta_out) {
+  if (generator < OR_GEN_MODIFIED || generator > OR_GEN_STANDARD) return -1;
+  if (generator == OR_GEN_STANDARD && !(delta_min > 0.0 && delta_min < 1.0)) return -1;
+  const or_w_args a = {t, backend, chi, gamma, dtfac};
+  or_w_table wt = {0, NULL, NULL};
+  if (generator == OR_GEN_STANDARD && or_w_table_build(&a, delta_min, &wt) != 0) return -1;
+  const double w1 = wt.n ? wt.cum[wt.n] : 0.0; /* W(1), the total probability */
+  int64_t m = 0;
+  const uint32_t kk[2] = {(uint32_t)key, (uint32_t)(key >> 32)};
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : m)
+  for (int64_t i = 0; i < n; ++i) {
+    const uint64_t trial = (uint64_t)(first + i);
+    uint32_t ctr[4] = {(uint32_t)trial, (uint32_t)(trial >> 32), 0u, 0u}, o[4];
+    or_philox4x32_10(ctr, kk, o);
+    const double r1 = or_uniform(o[0], o[1]);
+    const double r2 = or_uniform(o[2], o[3]);
+    double delta = 0.0;
+    if (generator == OR_GEN_MODIFIED) {
+      if (r2 < or_rate_modified(t, backend, r1, chi, gamma, dtfac)) delta = r1 * r1 * r1;
+    } else if (generator == OR_GEN_ALTERNATIVE) {
+      if (r2 < or_rate_emission(t, backend, r1, chi, gamma, dtfac)) delta = r1;
+    } else if (r1 < w1) {
+      /* the panel with W(edge k) <= r2 W(1) < W(edge k+1), then bisection in u inside it */
+      const double target = r2 * w1;
+      int lo_k = 0, hi_k = wt.n;
+      while (hi_k - lo_k > 1) {
+        const int mid = (lo_k + hi_k) / 2;
+        if (wt.cum[mid] <= target) lo_k = mid; else hi_k = mid;
+      }
+      double lo = wt.edge[lo_k], hi = wt.edge[lo_k + 1];
+      for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (!(mid > lo && mid < hi)) break; /* the bracket is down to adjacent doubles */
+        if (wt.cum[lo_k] + or_gl5(&a, wt.edge[lo_k], mid) <= target) lo = mid; else hi = mid;
+      }
+      const double q = 1.5 * chi * exp2(0.5 * (lo + hi));
+      delta = q / (1.0 + q);
+    }
+    delta_out[i] = delta;
+    m += delta > 0.0 ? 1 : 0;
+  }
+  or_w_table_free(&wt);
   return m;
 }
 

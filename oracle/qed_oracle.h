@@ -180,6 +180,26 @@ int64_t or_emission_trials(const or_tables *t, int backend, double chi, double g
 int64_t or_pair_trials(const or_tables *t, int backend, double chi_g, double kabs, double dtfac,
                        uint64_t key, int64_t n, double *delta_out);
 
+/* The emission event generators of Sec. IV.G, as independent trials for one lepton state
+ * (chi, gamma) over one interval of rate prefactor dtfac: trial first + i (i < n) draws
+ * (r1, r2) from Philox, counter (trial, trial >> 32, 0, 0) and key, and writes the emitted
+ * photon's delta to delta_out[i], or 0 when it emits nothing.
+ *   OR_GEN_MODIFIED     Eq. (25): delta = r1^3, emission iff r2 < P_m(r1)
+ *   OR_GEN_ALTERNATIVE  Eq. (24): delta = r1, emission iff r2 < P(r1)
+ *   OR_GEN_STANDARD     Eqs. (22)-(23): emission iff r1 < W(1), delta the root of
+ *                       W(delta) = r2 W(1), W(x) = int_{delta_min}^{x} P(delta) d delta
+ * Returns the number of emissions, or -1 for an unknown generator or, for the standard
+ * one, delta_min outside (0, 1). */
+#define OR_GEN_MODIFIED 0
+#define OR_GEN_ALTERNATIVE 1
+#define OR_GEN_STANDARD 2
+int64_t or_generator_trials(const or_tables *t, int backend, int generator, double chi,
+                            double gamma, double dtfac, double delta_min, uint64_t key,
+                            int64_t first, int64_t n, double *delta_out);
+/* W(x) of the standard generator (Eq. (23)), for x in [delta_min, 1]. */
+double or_standard_w(const or_tables *t, int backend, double chi, double gamma, double dtfac,
+                     double delta_min, double x);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,8 +1,8 @@
 """Statistical pins of the event generators (Sec. IV.G, Sec. V.A).
 
 The modified generator draws r1, r2, takes delta = r1^3 and accepts when
-r2 < 3 r1^2 P(r1^3); the accepted deltas must follow the density P(delta) of Eq. (24)
-("the resulting spectrum agrees perfectly with the analytic expression").  Setup of the
+r2 < 3 r1^2 P(r1^3); the accepted deltas must follow the density P(delta) of Eq. (24),
+which is what the paper claims for it (no cutoff, no deficit).  Setup of the
 paper's generator comparison: gamma = 100, chi = 1, 10^7 trials.  Expected counts per bin
 come from the exact rate integrated with scipy; every bin must lie within 3 sigma.
 """
