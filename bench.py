@@ -390,6 +390,57 @@ def gpu_schwinger_grid(args):
     return out
 
 
+def gpu_generator_comparison(args):
+    """The three emission generators of Sec. IV.G as independent trials in the setting of
+    the paper's comparison of their spectra: gamma = 100, chi = 1, 10^7 trials per
+    generator, an interval with dtfac = 31.25 (the modified generator's P_m stays below
+    about 0.5) and the standard generator's cutoff delta_min = 10^-3.  Each generator's
+    launch (for the standard one: its W table and the trials) is timed with HIP events over
+    5 repetitions; the emitted deltas are then counted per decade (untimed)."""
+    import torch
+    from paper_1412_6426_amd import qed as Q
+
+    gamma, chi, dtfac, dmin, n, reps = 100.0, 1.0, 0.5 * 100.0 / 1.6, 1e-3, 10_000_000, 5
+    tab = torch.zeros(Q.qed_table_bytes() + 256, dtype=torch.uint8, device="cuda")
+    tp = tab.data_ptr() + ((-tab.data_ptr()) % 256)
+    stream = torch.cuda.Stream()
+    sp = stream.cuda_stream
+    Q.qed_build_tables(tp, Q.qed_table_bytes(), sp)
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    hip = HipEvents()
+    res = {}
+    edges = [10.0 ** k for k in range(-9, 1)]  # decades 1e-9 .. 1
+    for name, gen in (("modified", Q.QED_GEN_MODIFIED), ("alternative", Q.QED_GEN_ALTERNATIVE),
+                      ("standard", Q.QED_GEN_STANDARD)):
+        wb = Q.qed_generator_work_bytes(gen, chi, dmin)
+        work = torch.empty(wb + 256, dtype=torch.uint8, device="cuda") if wb else None
+        wp = work.data_ptr() + ((-work.data_ptr()) % 256) if wb else None
+        evs = hip.create(2 * reps)
+        torch.cuda.synchronize()
+        Q.qed_generator_trials(tp, gen, chi, gamma, dtfac, dmin, 0xE4, 0, n, out.data_ptr(),
+                               wp, wb, sp)  # warm-up
+        for r in range(reps):
+            hip.lib.hipEventRecord(C.c_void_p(evs[2 * r]), C.c_void_p(sp))
+            Q.qed_generator_trials(tp, gen, chi, gamma, dtfac, dmin, 0xE4, 0, n,
+                                   out.data_ptr(), wp, wb, sp)
+            hip.lib.hipEventRecord(C.c_void_p(evs[2 * r + 1]), C.c_void_p(sp))
+        torch.cuda.synchronize()
+        ms = sum(hip.elapsed_ms(evs[2 * r], evs[2 * r + 1]) for r in range(reps)) / reps
+        hip.destroy(evs)
+        d = out[out > 0]
+        counts = torch.histc(torch.log10(d), bins=9, min=-9.0, max=0.0).long().tolist()
+        res[name] = dict(ms_per_launch=ms, trials_per_s=n / (ms / 1e3),
+                         emitted=int(d.numel()), emitted_per_decade=dict(
+                             zip([f"{edges[k]:.0e}-{edges[k + 1]:.0e}" for k in range(9)],
+                                 counts)))
+        del work
+    del out, tab
+    torch.cuda.empty_cache()
+    return dict(workload=f"gamma = {gamma:g}, chi = {chi:g}, dtfac = {dtfac:g}, "
+                         f"delta_min = {dmin:g} (standard), {n} trials per generator",
+                generators=res)
+
+
 def roofline_of(r):
     dom = "photon" if r["pho_ms"] >= r["lep_ms"] else "lepton"
     kbytes = r["pho_bytes"] if dom == "photon" else r["lep_bytes"]
@@ -708,6 +759,10 @@ def main():
                     help="skip Schwinger pair production on the 256^3 grid")
     ap.add_argument("--schwinger-only", action="store_true",
                     help="run only the Schwinger leg and print its record (profiling)")
+    ap.add_argument("--no-generators", action="store_true",
+                    help="skip the comparison of the three emission generators")
+    ap.add_argument("--generators-only", action="store_true",
+                    help="run only the generator comparison and print its record (profiling)")
     ap.add_argument("--no-tune", action="store_true",
                     help="use --tile / --grid-blocks for every step instead of tuning")
     args = ap.parse_args()
@@ -728,6 +783,9 @@ def main():
         return
     if args.schwinger_only:
         print(json.dumps({"schwinger_grid": gpu_schwinger_grid(args)}), flush=True)
+        return
+    if args.generators_only:
+        print(json.dumps({"generator_comparison": gpu_generator_comparison(args)}), flush=True)
         return
     print(f"bench: rotating-E cascade, {args.seeds} seeds, precision {args.precision}",
           file=sys.stderr, flush=True)
@@ -840,6 +898,9 @@ def main():
     if not args.no_schwinger:
         print("bench: Schwinger pairs on the Yee grid", file=sys.stderr, flush=True)
         line["schwinger_grid"] = gpu_schwinger_grid(args)
+    if not args.no_generators:
+        print("bench: the three emission generators", file=sys.stderr, flush=True)
+        line["generator_comparison"] = gpu_generator_comparison(args)
     if not args.no_cpu_baseline:
         print("bench: oracle sample on the host", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(args)

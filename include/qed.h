@@ -323,6 +323,37 @@ qed_status qed_schwinger(const qed_stores *stores, const qed_field *field, doubl
                          double eps_r, double weight, const int64_t *d_step,
                          qed_schwinger_record *d_record, void *stream);
 
+/* ---------------------------------------------------------------------------------------
+ * The emission event generators of Sec. IV.G as independent trials: the setting of the
+ * paper's comparison of their spectra, for one lepton state (chi, gamma) over one interval
+ * whose rate prefactor is dtfac = dt e^2 m c / hbar^2 (dt alpha / eps_r in the units here).
+ * P(delta) is the emission density of Eq. (24), evaluated in FP64 from the rate tables.
+ * Trial j = first + i (0 <= i < n) draws (r1, r2) from Philox4x32-10 with key (key lo,
+ * key hi) and counter (j lo, j hi, 0, 0), r1 from the first two words and r2 from the last
+ * two (open-interval uniforms as in the step), and d_delta[i] receives the emitted photon's
+ * energy fraction delta, or 0 when the trial emits nothing:
+ *   QED_GEN_MODIFIED     Eq. (25): delta = r1^3, emission iff r2 < 3 r1^2 P(r1^3) (the
+ *                        decision qed_step makes)
+ *   QED_GEN_ALTERNATIVE  Eq. (24): delta = r1, emission iff r2 < P(r1)
+ *   QED_GEN_STANDARD     Eqs. (22)-(23): emission iff r1 < W(1), delta the root of
+ *                        W(delta) = r2 W(1), W(x) = int_{delta_min}^{x} P(delta) d delta
+ * For the standard generator W is tabulated for the given state in d_work (at least
+ * qed_generator_work_bytes(QED_GEN_STANDARD, chi, delta_min) bytes, 256-byte aligned; the
+ * other generators need none and take d_work = NULL) at the ends of the rate table's
+ * intervals, and each trial inverts it inside one interval.  d_delta: n doubles, device.
+ * If d_tables was not filled by qed_build_tables every d_delta is NaN.  Asynchronous on
+ * `stream`.  QED_ERR_ARG for NULL tables or output, n < 0, first < 0, chi <= 0,
+ * gamma < 1, dtfac < 0, an unknown generator, or (standard) delta_min outside (0, 1) or a
+ * workspace that is missing, misaligned or too small. */
+#define QED_GEN_MODIFIED 0
+#define QED_GEN_ALTERNATIVE 1
+#define QED_GEN_STANDARD 2
+size_t qed_generator_work_bytes(int generator, double chi, double delta_min);
+qed_status qed_generator_trials(const void *d_tables, int generator, double chi, double gamma,
+                                double dtfac, double delta_min, uint64_t key, int64_t first,
+                                int64_t n, double *d_delta, void *d_work, size_t work_bytes,
+                                void *stream);
+
 /* Append the record *d_stats to d_log[*d_log_count] and increment *d_log_count, unless
  * *d_log_count >= log_capacity (then the record is discarded and the count still grows,
  * so the caller sees the overflow).  Graph-capturable. */

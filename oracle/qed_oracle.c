@@ -103,7 +103,7 @@ double or_F1(double x) { return x * or_A(x); }
 double or_F2(double x) { return x * or_B(x); }
 
 /* ------------------------------------------------------------------------------------
- * Tables (the paper's "tabulate in advance and interpolate", Sec. IV.F).
+ * Tables (tabulated once and interpolated, as Sec. IV.F suggests).
  * Small-z series (below z = 2^-20), from K_nu = (1/2)Gamma(nu)(z/2)^-nu (1 + (z/2)^2/(1-nu)
  * + ...) + (1/2)Gamma(-nu)(z/2)^nu (1 + ...) (DLMF 10.27.4 with 10.25.2) and
  * int_0^inf K_{1/3} = pi/sqrt(3) (DLMF 10.43.19):

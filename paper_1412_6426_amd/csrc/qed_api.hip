@@ -314,6 +314,40 @@ qed_status qed_schwinger(const qed_stores* stores, const qed_field* field, doubl
   return e == hipSuccess ? QED_OK : QED_ERR_HIP;
 }
 
+size_t qed_generator_work_bytes(int generator, double chi, double delta_min) {
+  if (generator == QED_GEN_MODIFIED || generator == QED_GEN_ALTERNATIVE) return 0;
+  if (generator != QED_GEN_STANDARD || !finite_pos(chi) || !(delta_min > 0.0 && delta_min < 1.0))
+    return 0;
+  double u0, k0;
+  const long long panels = standard_panels(chi, delta_min, &u0, &k0);
+  if (panels > generator_max_panels()) return 0;
+  return generator_work_bytes(panels);
+}
+
+qed_status qed_generator_trials(const void* d_tables, int generator, double chi, double gamma,
+                                double dtfac, double delta_min, uint64_t key, int64_t first,
+                                int64_t n, double* d_delta, void* d_work, size_t work_bytes,
+                                void* stream) {
+  if (!d_tables || (reinterpret_cast<uintptr_t>(d_tables) & 255u)) return QED_ERR_ARG;
+  if (n < 0 || first < 0 || n > INT64_MAX - first || (n > 0 && !d_delta)) return QED_ERR_ARG;
+  if (!finite_pos(chi) || !(gamma >= 1.0) || !isfinite(gamma) || !(dtfac >= 0.0) ||
+      !isfinite(dtfac))
+    return QED_ERR_ARG;
+  if (generator != QED_GEN_MODIFIED && generator != QED_GEN_ALTERNATIVE &&
+      generator != QED_GEN_STANDARD)
+    return QED_ERR_ARG;
+  if (generator == QED_GEN_STANDARD) {
+    const size_t need = qed_generator_work_bytes(generator, chi, delta_min);
+    if (need == 0 || !d_work || (reinterpret_cast<uintptr_t>(d_work) & 255u) ||
+        work_bytes < need)
+      return QED_ERR_ARG;
+  }
+  const hipError_t e = launch_generator_trials(
+      static_cast<const DevTables*>(d_tables), generator, chi, gamma, dtfac, delta_min, key,
+      first, n, d_delta, d_work, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? QED_OK : QED_ERR_HIP;
+}
+
 size_t qed_thin_work_bytes(int n_instances, int64_t species_slots) {
   if (n_instances < 1 || species_slots < 0) return 0;
   return ThinLayout::make(n_instances, species_slots).total;

@@ -1,0 +1,265 @@
+// qed_generators.hip -- the emission event generators of Sec. IV.G of Gonoskov et al.,
+// arXiv:1412.6426, as independent trials for one lepton state (the setting of the paper's
+// comparison of their spectra): the modified generator of Eq. (25) that the step uses, the
+// alternative one of Eq. (24), and the standard one of Eqs. (22)-(23) with its cutoff.
+//
+// With q = 1.5 chi 2^u, delta(u) = q / (1 + q) maps u = log2 z (z the argument of the
+// synchrotron functions) to the photon's energy fraction, and d delta / du =
+// ln 2 delta (1 - delta).  The standard generator's W is integrated in u over the rate
+// table's own intervals (the interpolated rate is smooth inside each one) by 8-point
+// Gauss-Legendre, one interval per thread, and summed in a fixed order; a trial then finds
+// the interval that holds r2 W(1) by binary search and solves inside it by Newton steps on
+// the interval's quadrature, kept inside a shrinking bracket.
+#include <math.h>
+
+#include "qed_internal.h"
+
+namespace qedk {
+
+namespace {
+
+constexpr int kGl = 8;         // Gauss-Legendre points per interval
+constexpr int kScanThreads = 1024;
+constexpr long long kMaxPanels = 1ll << 22;
+
+struct TrialArgs {
+  const DevTables* tables;
+  int generator;
+  double chi, gamma, dtfac;
+  uint32_t key0, key1;
+  long long first, n;
+  double* out;
+  // standard generator: W at the interval ends, the intervals
+  const double* cum;
+  double* part;
+  long long panels;
+  double u0;  // log2 z at delta_min: the first interval's start
+  double k0;  // table node index of the first interval's end
+  double glx[kGl / 2], glw[kGl / 2];  // positive nodes on [-1, 1] and their weights
+};
+
+// Eq. (24)'s density P(delta) from the FP64 tables (global memory; L2-resident).
+__device__ __forceinline__ double density(const TrialArgs& a, const Series64& ser, double d) {
+  if (!(d > 0.0 && d < 1.0)) return 0.0;
+  const double omd = 1.0 - d;
+  const double z = (2.0 / 3.0) * d / (omd * a.chi);
+  return (a.dtfac * kInvSqrt3Pi / a.gamma) *
+         emission_bracket64(a.tables->ab64, ser, z, d * d / omd);
+}
+
+// W's integrand in u.
+__device__ __forceinline__ double integrand(const TrialArgs& a, const Series64& ser, double u) {
+  const double q = 1.5 * a.chi * exp2(u);
+  const double d = q / (1.0 + q);
+  return density(a, ser, d) * 0.6931471805599453 * d / (1.0 + q);
+}
+
+__device__ __forceinline__ double gauss_legendre(const TrialArgs& a, const Series64& ser,
+                                                 double lo, double hi) {
+  const double c = 0.5 * (lo + hi), h = 0.5 * (hi - lo);
+  double s = 0.0;
+#pragma unroll
+  for (int m = 0; m < kGl / 2; ++m)
+    s += a.glw[m] * (integrand(a, ser, c - h * a.glx[m]) + integrand(a, ser, c + h * a.glx[m]));
+  return h * s;
+}
+
+// End of interval k (k = 0..panels): u0, then table nodes, the last one at z = 2^7.
+__device__ __forceinline__ double edge(const TrialArgs& a, long long k) {
+  if (k == 0) return a.u0;
+  const double e = kLog2ZLo + (a.k0 + (double)(k - 1)) / kNodesPerLog2;
+  return k >= a.panels || e > kLog2ZHi ? kLog2ZHi : e;
+}
+
+__device__ __forceinline__ Series64 series_of(const DevTables* t) {
+  return Series64{t->series[0], t->series[1], t->series[2], t->series[3], t->series[4]};
+}
+
+__global__ void __launch_bounds__(256) w_panel_kernel(TrialArgs a) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= a.panels) return;
+  const Series64 ser = series_of(a.tables);
+  a.part[k] = gauss_legendre(a, ser, edge(a, k), edge(a, k + 1));
+}
+
+// cum[0] = 0, cum[k + 1] = cum[k] + part[k]: each thread sums one contiguous run, the run
+// totals are scanned in LDS, then each run is written out (a fixed order of additions).
+__global__ void __launch_bounds__(kScanThreads) w_scan_kernel(TrialArgs a) {
+  __shared__ double tot[kScanThreads];
+  const long long n = a.panels;
+  const long long per = (n + kScanThreads - 1) / kScanThreads;
+  const long long lo = per * threadIdx.x;
+  const long long hi = lo + per < n ? lo + per : n;
+  double s = 0.0;
+  for (long long k = lo; k < hi; ++k) s += a.part[k];
+  tot[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double run = 0.0;
+    for (int t = 0; t < kScanThreads; ++t) {
+      const double v = tot[t];
+      tot[t] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  double* cum = const_cast<double*>(a.cum);
+  double run = tot[threadIdx.x];
+  if (threadIdx.x == 0) cum[0] = 0.0;
+  for (long long k = lo; k < hi; ++k) {
+    run += a.part[k];
+    cum[k + 1] = run;
+  }
+}
+
+// Eq. (22): the root of W(delta) = target, W(1) >= target >= 0.
+__device__ double standard_delta(const TrialArgs& a, const Series64& ser, double target) {
+  long long lo = 0, hi = a.panels;
+  while (hi - lo > 1) {
+    const long long mid = (lo + hi) >> 1;
+    if (a.cum[mid] <= target) lo = mid; else hi = mid;
+  }
+  const double ua = edge(a, lo), ub = edge(a, lo + 1);
+  const double base = a.cum[lo], span = a.cum[lo + 1] - base;
+  const double want = target - base;
+  double blo = ua, bhi = ub;
+  double u = span > 0.0 ? ua + (ub - ua) * (want / span) : 0.5 * (ua + ub);
+  if (!(u > blo && u < bhi)) u = 0.5 * (blo + bhi);
+  for (int it = 0; it < 60; ++it) {
+    const double g = gauss_legendre(a, ser, ua, u) - want;
+    if (g > 0.0) bhi = u; else blo = u;
+    const double f = integrand(a, ser, u);
+    double un = f > 0.0 ? u - g / f : 0.5 * (blo + bhi);
+    if (!(un > blo && un < bhi)) un = 0.5 * (blo + bhi);
+    const bool done = fabs(un - u) <= 0x1p-50 * fmax(fabs(u), 1.0) || !(bhi > blo);
+    u = un;
+    if (done) break;
+  }
+  const double q = 1.5 * a.chi * exp2(u);
+  return q / (1.0 + q);
+}
+
+// One kernel per generator, so that the short ones keep their registers low.
+template <int GEN>
+__global__ void __launch_bounds__(256) trial_kernel(TrialArgs a) {
+  const bool ok = a.tables->magic == kTableMagic;
+  const Series64 ser = series_of(a.tables);
+  const double w1 = GEN == QED_GEN_STANDARD && a.panels > 0 ? a.cum[a.panels] : 0.0;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
+    if (!ok) {
+      a.out[i] = __builtin_nan("");
+      continue;
+    }
+    const uint64_t j = (uint64_t)(a.first + i);
+    const uint4 o = philox4x32_10(make_uint4((uint32_t)j, (uint32_t)(j >> 32), 0u, 0u), a.key0,
+                                  a.key1);
+    const double r1 = uniform64(o.x, o.y), r2 = uniform64(o.z, o.w);
+    double delta = 0.0;
+    if (GEN == QED_GEN_MODIFIED) {
+      const double d = r1 * r1 * r1;
+      if (r2 < 3.0 * r1 * r1 * density(a, ser, d)) delta = d;
+    } else if (GEN == QED_GEN_ALTERNATIVE) {
+      if (r2 < density(a, ser, r1)) delta = r1;
+    } else if (r1 < w1) {
+      delta = standard_delta(a, ser, r2 * w1);
+    }
+    a.out[i] = delta;
+  }
+}
+
+// Positive nodes and weights of n-point Gauss-Legendre on [-1, 1]: Newton's method on the
+// Legendre polynomial P_n from the asymptotic guesses cos(pi (i + 3/4) / (n + 1/2)), the
+// weights 2 / ((1 - x^2) P_n'(x)^2).
+void gauss_legendre_rule(int n, double* x, double* w) {
+  for (int i = 0; i < n / 2; ++i) {
+    double z = cos(kPi * (i + 0.75) / (n + 0.5)), dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = z;  // P_n' at the final node
+    for (int k = 2; k <= n; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = n * (z * p1 - p0) / (z * z - 1.0);
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+}  // namespace
+
+// Intervals of the standard generator's W for (chi, delta_min): from u0 = log2 z(delta_min)
+// to the first table node above it, then table intervals up to z = 2^7 (0: no rate).
+long long standard_panels(double chi, double delta_min, double* u0, double* k0) {
+  const double u = log2((2.0 / 3.0) * delta_min / (chi * (1.0 - delta_min)));
+  *u0 = u;
+  *k0 = 0.0;
+  if (!(u < kLog2ZHi)) return 0;
+  const double k = floor((u - kLog2ZLo) * kNodesPerLog2) + 1.0;
+  *k0 = k;
+  const double first_end = kLog2ZLo + k / kNodesPerLog2;
+  if (!(first_end < kLog2ZHi)) return 1;
+  return 1 + (long long)ceil((kLog2ZHi - first_end) * kNodesPerLog2);
+}
+
+size_t generator_work_bytes(long long panels) {
+  const size_t part = ((size_t)panels * sizeof(double) + 255) & ~(size_t)255;
+  return part + (size_t)(panels + 1) * sizeof(double);
+}
+
+long long generator_max_panels() { return kMaxPanels; }
+
+hipError_t launch_generator_trials(const DevTables* tables, int generator, double chi,
+                                   double gamma, double dtfac, double delta_min, uint64_t key,
+                                   long long first, long long n, double* out, void* work,
+                                   hipStream_t s) {
+  TrialArgs a{};
+  a.tables = tables;
+  a.generator = generator;
+  a.chi = chi;
+  a.gamma = gamma;
+  a.dtfac = dtfac;
+  a.key0 = (uint32_t)key;
+  a.key1 = (uint32_t)(key >> 32);
+  a.first = first;
+  a.n = n;
+  a.out = out;
+  if (generator == QED_GEN_STANDARD) {
+    a.panels = standard_panels(chi, delta_min, &a.u0, &a.k0);
+    char* w = static_cast<char*>(work);
+    a.part = reinterpret_cast<double*>(w);
+    a.cum = reinterpret_cast<const double*>(
+        w + (((size_t)a.panels * sizeof(double) + 255) & ~(size_t)255));
+    gauss_legendre_rule(kGl, a.glx, a.glw);
+    if (a.panels > 0) {
+      hipLaunchKernelGGL(w_panel_kernel, dim3((unsigned)((a.panels + 255) / 256)), dim3(256),
+                         0, s, a);
+      hipLaunchKernelGGL(w_scan_kernel, dim3(1), dim3(kScanThreads), 0, s, a);
+    }
+  }
+  if (n > 0) {
+    const long long blocks = (n + 255) / 256;
+    const dim3 grid((unsigned)(blocks < 2048 ? blocks : 2048));
+    if (generator == QED_GEN_MODIFIED)
+      hipLaunchKernelGGL(trial_kernel<QED_GEN_MODIFIED>, grid, dim3(256), 0, s, a);
+    else if (generator == QED_GEN_ALTERNATIVE)
+      hipLaunchKernelGGL(trial_kernel<QED_GEN_ALTERNATIVE>, grid, dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL(trial_kernel<QED_GEN_STANDARD>, grid, dim3(256), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace qedk

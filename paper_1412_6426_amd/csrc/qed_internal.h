@@ -266,6 +266,14 @@ hipError_t launch_schwinger(const qed_stores& st, const float* const grid[3], co
                             const double dx[3], const double origin[3], double dt, double eps_r,
                             double weight, const long long* d_step, qed_schwinger_record* rec,
                             hipStream_t s);
+// Emission generators as trials (qed_generators.hip).
+long long standard_panels(double chi, double delta_min, double* u0, double* k0);
+size_t generator_work_bytes(long long panels);
+long long generator_max_panels();
+hipError_t launch_generator_trials(const DevTables* tables, int generator, double chi,
+                                   double gamma, double dtfac, double delta_min, uint64_t key,
+                                   long long first, long long n, double* out, void* work,
+                                   hipStream_t s);
 // Persistent-grid sizing: resident workgroups per CU for the step kernels.
 int step_blocks_per_cu(int precision, bool photon, int block);
 

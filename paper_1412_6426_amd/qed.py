@@ -109,7 +109,8 @@ class qed_schwinger_record(C.Structure):
 
 #: every symbol include/qed.h declares
 EXPORTS = ("qed_table_bytes", "qed_build_tables", "qed_work_bytes", "qed_step",
-           "qed_thin_work_bytes", "qed_thin", "qed_schwinger",
+           "qed_thin_work_bytes", "qed_thin", "qed_schwinger", "qed_generator_work_bytes",
+           "qed_generator_trials",
            "qed_append_stats", "qed_photon_spectrum", "qed_fill_standing_wave",
            "qed_status_string", "qed_version")
 
@@ -149,6 +150,13 @@ def lib():
         L.qed_schwinger.argtypes = [C.POINTER(qed_stores), C.POINTER(qed_field), C.c_double,
                                     C.c_double, C.c_double, C.c_void_p, C.c_void_p,
                                     C.c_void_p]
+        L.qed_generator_work_bytes.restype = C.c_size_t
+        L.qed_generator_work_bytes.argtypes = [C.c_int, C.c_double, C.c_double]
+        L.qed_generator_trials.restype = C.c_int
+        L.qed_generator_trials.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double,
+                                           C.c_double, C.c_double, C.c_uint64, C.c_int64,
+                                           C.c_int64, C.c_void_p, C.c_void_p, C.c_size_t,
+                                           C.c_void_p]
         L.qed_photon_spectrum.restype = C.c_int
         L.qed_photon_spectrum.argtypes = [C.POINTER(qed_stores), C.c_double, C.c_double,
                                           C.c_int, C.c_void_p, C.c_void_p]
@@ -204,6 +212,21 @@ def qed_schwinger(stores: qed_stores, field: qed_field, dt: float, eps_r: float,
                   weight: float, d_step: int, d_record: int, stream: int) -> None:
     _check(lib().qed_schwinger(C.byref(stores), C.byref(field), dt, eps_r, weight, d_step,
                                d_record, stream), "qed_schwinger")
+
+
+QED_GEN_MODIFIED, QED_GEN_ALTERNATIVE, QED_GEN_STANDARD = 0, 1, 2
+
+
+def qed_generator_work_bytes(generator: int, chi: float, delta_min: float) -> int:
+    return int(lib().qed_generator_work_bytes(generator, chi, delta_min))
+
+
+def qed_generator_trials(d_tables: int, generator: int, chi: float, gamma: float, dtfac: float,
+                         delta_min: float, key: int, first: int, n: int, d_delta: int,
+                         d_work: int, work_bytes: int, stream: int) -> None:
+    _check(lib().qed_generator_trials(d_tables, generator, chi, gamma, dtfac, delta_min, key,
+                                      first, n, d_delta, d_work, work_bytes, stream),
+           "qed_generator_trials")
 
 
 def qed_append_stats(d_stats: int, d_log: int, log_capacity: int, d_log_count: int,

@@ -1,6 +1,7 @@
 """The C-ABI library loads, exports every symbol include/qed.h declares, and validates its
 arguments on the host (no GPU needed: no compute call is made)."""
 import ctypes as C
+import math
 import os
 import re
 
@@ -137,6 +138,41 @@ def test_schwinger_argument_validation_without_device(Q):
     f.n = (C.c_int * 3)(2048, 2048, 1024)
     assert L.qed_schwinger(C.byref(st), C.byref(f), 1.0, 1.0, 1.0, fake, fake,
                            None) == Q.QED_ERR_ARG  # 2^32 cells
+
+
+def test_generator_trials_validation_without_device(Q):
+    L = Q.lib()
+    tab = C.c_void_p(4096)
+    out = C.c_void_p(8192)
+    ok = dict(chi=1.0, gamma=100.0, dtfac=31.25, dmin=1e-3)
+
+    def call(gen=Q.QED_GEN_MODIFIED, chi=1.0, gamma=100.0, dtfac=31.25, dmin=1e-3, first=0,
+             n=10, d_out=out, work=None, wb=0, tables=tab):
+        return L.qed_generator_trials(tables, gen, chi, gamma, dtfac, dmin, 5, first, n, d_out,
+                                      work, wb, None)
+
+    assert call(tables=None) == Q.QED_ERR_ARG
+    assert call(tables=C.c_void_p(4100)) == Q.QED_ERR_ARG  # misaligned
+    assert call(gen=3) == Q.QED_ERR_ARG
+    assert call(n=-1) == Q.QED_ERR_ARG and call(first=-1) == Q.QED_ERR_ARG
+    assert call(first=(1 << 63) - 5, n=10) == Q.QED_ERR_ARG  # trial index overflows
+    assert call(d_out=None) == Q.QED_ERR_ARG
+    assert call(chi=0.0) == Q.QED_ERR_ARG and call(gamma=0.5) == Q.QED_ERR_ARG
+    assert call(dtfac=-1.0) == Q.QED_ERR_ARG and call(chi=float("nan")) == Q.QED_ERR_ARG
+    need = Q.qed_generator_work_bytes(Q.QED_GEN_STANDARD, ok["chi"], ok["dmin"])
+    # panels from z(1e-3) = 2^-10.5 to 2^7, 4095 / 27 per octave, plus W's n + 1 ends
+    panels = math.ceil((7 - math.log2((2 / 3) * 1e-3 / 0.999)) * 4095 / 27)
+    assert abs(need - 16 * panels) < 600
+    assert Q.qed_generator_work_bytes(Q.QED_GEN_MODIFIED, 1.0, 1e-3) == 0
+    assert Q.qed_generator_work_bytes(Q.QED_GEN_STANDARD, 1.0, 0.0) == 0
+    assert Q.qed_generator_work_bytes(Q.QED_GEN_STANDARD, 1.0, 1.0) == 0
+    assert Q.qed_generator_work_bytes(Q.QED_GEN_STANDARD, -1.0, 1e-3) == 0
+    w = C.c_void_p(1 << 20)
+    assert call(gen=Q.QED_GEN_STANDARD, work=None, wb=need) == Q.QED_ERR_ARG
+    assert call(gen=Q.QED_GEN_STANDARD, work=w, wb=need - 8) == Q.QED_ERR_ARG
+    assert call(gen=Q.QED_GEN_STANDARD, work=C.c_void_p((1 << 20) + 8), wb=need) == \
+        Q.QED_ERR_ARG
+    assert call(gen=Q.QED_GEN_STANDARD, dmin=0.0, work=w, wb=need) == Q.QED_ERR_ARG
 
 
 def test_argument_validation_without_device(Q):
