@@ -112,15 +112,17 @@ __global__ void __launch_bounds__(kScanThreads) w_scan_kernel(TrialArgs a) {
   }
 }
 
-// Eq. (22): the root of W(delta) = target, W(1) >= target >= 0.
-__device__ double standard_delta(const TrialArgs& a, const Series64& ser, double target) {
+// Eq. (22): the root of W(delta) = target, W(1) >= target >= 0 (cum: W at the interval
+// ends, in LDS or global memory).
+__device__ double standard_delta(const TrialArgs& a, const Series64& ser, const double* cum,
+                                 double target) {
   long long lo = 0, hi = a.panels;
   while (hi - lo > 1) {
     const long long mid = (lo + hi) >> 1;
-    if (a.cum[mid] <= target) lo = mid; else hi = mid;
+    if (cum[mid] <= target) lo = mid; else hi = mid;
   }
   const double ua = edge(a, lo), ub = edge(a, lo + 1);
-  const double base = a.cum[lo], span = a.cum[lo + 1] - base;
+  const double base = cum[lo], span = cum[lo + 1] - base;
   const double want = target - base;
   double blo = ua, bhi = ub;
   double u = span > 0.0 ? ua + (ub - ua) * (want / span) : 0.5 * (ua + ub);
@@ -139,12 +141,11 @@ __device__ double standard_delta(const TrialArgs& a, const Series64& ser, double
   return q / (1.0 + q);
 }
 
-// One kernel per generator, so that the short ones keep their registers low.
+// The modified and alternative generators (one kernel each, so that both stay lean).
 template <int GEN>
 __global__ void __launch_bounds__(256) trial_kernel(TrialArgs a) {
   const bool ok = a.tables->magic == kTableMagic;
   const Series64 ser = series_of(a.tables);
-  const double w1 = GEN == QED_GEN_STANDARD && a.panels > 0 ? a.cum[a.panels] : 0.0;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
     if (!ok) {
@@ -159,13 +160,78 @@ __global__ void __launch_bounds__(256) trial_kernel(TrialArgs a) {
     if (GEN == QED_GEN_MODIFIED) {
       const double d = r1 * r1 * r1;
       if (r2 < 3.0 * r1 * r1 * density(a, ser, d)) delta = d;
-    } else if (GEN == QED_GEN_ALTERNATIVE) {
+    } else {
       if (r2 < density(a, ser, r1)) delta = r1;
-    } else if (r1 < w1) {
-      delta = standard_delta(a, ser, r2 * w1);
     }
     a.out[i] = delta;
   }
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The standard generator.  W's interval ends are staged in LDS when they fit (the binary
+// search then stays on chip).  Only about W(1) of the trials emit, and their inversion is the
+// costly part, so a wavefront queues its emitting trials in LDS and inverts them 64 at a
+// time with every lane busy.
+constexpr int kLdsCumMax = 6144;  // 48 KB
+__global__ void __launch_bounds__(256) standard_kernel(TrialArgs a) {
+  extern __shared__ double s_cum[];
+  __shared__ long long s_qi[4][128];
+  __shared__ double s_qt[4][128];
+  const bool ok = a.tables->magic == kTableMagic;
+  const Series64 ser = series_of(a.tables);
+  const bool staged = a.panels + 1 <= kLdsCumMax;
+  if (staged)
+    for (long long k = threadIdx.x; k <= a.panels; k += blockDim.x) s_cum[k] = a.cum[k];
+  __syncthreads();
+  const double* cum = staged ? s_cum : a.cum;
+  const double w1 = a.panels > 0 ? cum[a.panels] : 0.0;
+  const int lane = lane_id();
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  long long* const qi = s_qi[wv];
+  double* const qt = s_qt[wv];
+  int qn = 0;  // wavefront-uniform
+  const long long waves = (long long)gridDim.x * (blockDim.x >> 6);
+  for (long long base = ((long long)blockIdx.x * (blockDim.x >> 6) + wv) * 64; base < a.n;
+       base += waves * 64) {
+    const long long i = base + lane;
+    bool emit = false;
+    double target = 0.0;
+    if (i < a.n) {
+      if (!ok) {
+        a.out[i] = __builtin_nan("");
+      } else {
+        const uint64_t j = (uint64_t)(a.first + i);
+        const uint4 o = philox4x32_10(make_uint4((uint32_t)j, (uint32_t)(j >> 32), 0u, 0u),
+                                      a.key0, a.key1);
+        const double r1 = uniform64(o.x, o.y), r2 = uniform64(o.z, o.w);
+        emit = r1 < w1;
+        target = r2 * w1;
+        if (!emit) a.out[i] = 0.0;
+      }
+    }
+    const uint64_t m = wave_ballot(emit);
+    if (emit) {
+      const int at = qn + __popcll(m & lanes_below());
+      qi[at] = i;
+      qt[at] = target;
+    }
+    qn += __popcll(m);
+    if (qn >= 64) {
+      qn -= 64;
+      wave_lds_sync();
+      const long long qi_l = qi[qn + lane];
+      const double qt_l = qt[qn + lane];
+      wave_lds_sync();
+      a.out[qi_l] = standard_delta(a, ser, cum, qt_l);
+    }
+  }
+  wave_lds_sync();
+  if (lane < qn) a.out[qi[lane]] = standard_delta(a, ser, cum, qt[lane]);
 }
 
 // Positive nodes and weights of n-point Gauss-Legendre on [-1, 1]: Newton's method on the
@@ -252,12 +318,14 @@ hipError_t launch_generator_trials(const DevTables* tables, int generator, doubl
   if (n > 0) {
     const long long blocks = (n + 255) / 256;
     const dim3 grid((unsigned)(blocks < 2048 ? blocks : 2048));
-    if (generator == QED_GEN_MODIFIED)
+    if (generator == QED_GEN_MODIFIED) {
       hipLaunchKernelGGL(trial_kernel<QED_GEN_MODIFIED>, grid, dim3(256), 0, s, a);
-    else if (generator == QED_GEN_ALTERNATIVE)
+    } else if (generator == QED_GEN_ALTERNATIVE) {
       hipLaunchKernelGGL(trial_kernel<QED_GEN_ALTERNATIVE>, grid, dim3(256), 0, s, a);
-    else
-      hipLaunchKernelGGL(trial_kernel<QED_GEN_STANDARD>, grid, dim3(256), 0, s, a);
+    } else {
+      const size_t lds = a.panels + 1 <= kLdsCumMax ? (size_t)(a.panels + 1) * sizeof(double) : 0;
+      hipLaunchKernelGGL(standard_kernel, grid, dim3(256), lds, s, a);
+    }
   }
   return hipGetLastError();
 }
