@@ -116,9 +116,12 @@ def test_schwinger_instances_draw_their_own_pairs(orc):
             got = e.read(i, s)
             if i == 2:
                 # the store keeps 10 of the instance's pairs (which ones depends on the order
-                # of the reservations): they are a subset of the oracle's pairs, field for field
+                # of the reservations; the oracle keeps the first 10 in cell order): they are
+                # a subset of all the pairs the oracle makes with room for them, field for field
                 assert len(got["id"]) == 10
-                want = ost[s].view()
+                full = _oracle_stores(orc, 100_000)
+                orc.schwinger(full, ofld, dt, 1.0, 1.0, seed=seed, step=5)
+                want = full[s].view()
                 at = {int(v): q for q, v in enumerate(want["id"])}
                 rows = [at[int(v)] for v in got["id"]]
                 for c in ("parent", "birth", "w", "px", "py", "pz"):
