@@ -127,15 +127,25 @@ __device__ double standard_delta(const TrialArgs& a, const Series64& ser, const 
   double blo = ua, bhi = ub;
   double u = span > 0.0 ? ua + (ub - ua) * (want / span) : 0.5 * (ua + ub);
   if (!(u > blo && u < bhi)) u = 0.5 * (blo + bhi);
+  const double tol = 0x1p-50 * fmax(fmax(fabs(ua), fabs(ub)), 1.0);
   for (int it = 0; it < 60; ++it) {
     const double g = gauss_legendre(a, ser, ua, u) - want;
     if (g > 0.0) bhi = u; else blo = u;
     const double f = integrand(a, ser, u);
-    double un = f > 0.0 ? u - g / f : 0.5 * (blo + bhi);
-    if (!(un > blo && un < bhi)) un = 0.5 * (blo + bhi);
-    const bool done = fabs(un - u) <= 0x1p-50 * fmax(fabs(u), 1.0) || !(bhi > blo);
-    u = un;
-    if (done) break;
+    if (f > 0.0) {
+      // converged once the Newton step is below the tolerance (it may then round to u, which
+      // is why this is tested before the bracket)
+      const double step = g / f;
+      if (fabs(step) <= tol) {
+        u -= step;
+        break;
+      }
+      u -= step;
+    } else {
+      u = 0.5 * (blo + bhi);
+    }
+    if (!(u > blo && u < bhi)) u = 0.5 * (blo + bhi);
+    if (!(bhi - blo > tol)) break;
   }
   const double q = 1.5 * a.chi * exp2(u);
   return q / (1.0 + q);
