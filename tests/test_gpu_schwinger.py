@@ -3,7 +3,9 @@
 The decisions and positions come from per-cell Philox draws on both sides, so the pairs,
 their ids, births and weights are bit-exact; positions agree within 1e-12 (the two sides
 may contract origin + (i + u) dx differently); the expected count (a sum of per-cell
-probabilities taken in different orders) within 1e-12 relative.  The store order follows
+probabilities taken in different orders) within 1e-12 relative on the small grids, and
+within (n + 2) 2^-53 relative for the n = 1.7e7 cells of the full grid (the bound for
+summing n positive terms in any order, plus an ulp of exp per term on each side).  The store order follows
 the GPU's reservations; multisets are compared."""
 import math
 
@@ -172,3 +174,37 @@ def test_schwinger_without_field_makes_nothing(orc):
     assert r["cells"] == N[0] * N[1] * N[2]
     assert r["pairs"] == 0 and r["expected"] == 0.0 and r["saturated"] == 0
     assert e.instances()[0]["count"][:2] == [0, 0]
+
+
+def test_schwinger_full_grid_parity(orc):
+    """The bench's Schwinger workload at full size, in the launch configuration it times: the
+    256^3 standing-wave grid (cells of lambda/32, dt = T/100) with the wave raised so that
+    the antinodes reach 0.075 E_S.  Two steps, each against the oracle over the whole grid
+    (about 260 pairs a step out of 1.7e7 cells, 42% of which draw)."""
+    w = W.standing_wave_grid(n=1)
+    w.field.grid_wave_amp = 0.075 / (2.0 * w.eps_r)
+    fs = w.field
+    e = _engine([100_000], [0])
+    ost = _oracle_stores(orc, 100_000)
+    for step in range(2):
+        t = w.t0 + step * w.dt
+        _note(f"schwinger full grid step {step}")
+        grids = [np.ascontiguousarray(g) for g in W.standing_wave_grid_values(fs, t)]
+        dev = [torch.from_numpy(g).to("cuda") for g in grids]
+        f = Engine.make_field(Q.QED_FIELD_YEE, grid=dev, n=fs.grid_n, dx=fs.grid_dx,
+                              origin=fs.grid_origin)
+        e.set_step(step)
+        e.schwinger(f, w.dt, w.eps_r, weight=1.0)
+        torch.cuda.synchronize()
+        r = e.schwinger_record()
+        ofld = orc.Field(kind=orc.FIELD_YEE, grid=grids, dx=fs.grid_dx, origin=fs.grid_origin)
+        o = orc.schwinger(ost, ofld, w.dt, w.eps_r, 1.0, seed=0, step=step)
+        for c in ("cells", "pairs", "dropped", "saturated"):
+            assert r[c] == o[c], (step, c)
+        # a sum of 1.7e7 positive terms in two orders: within (n - 1) u of each other, plus
+        # the per-term ulp of exp on each side
+        assert r["expected"] == pytest.approx(o["expected"], rel=(r["cells"] + 2) * 2.0 ** -53)
+        assert r["pairs"] > 100
+        del dev, grids
+    for s in range(2):
+        compare_species(e.read(0, s), ost[s].view(), s, rtol=1e-12, label=f"species {s}")
