@@ -342,9 +342,12 @@ qed_status qed_schwinger(const qed_stores *stores, const qed_field *field, doubl
  * other generators need none and take d_work = NULL) at the ends of the rate table's
  * intervals, and each trial inverts it inside one interval.  d_delta: n doubles, device.
  * If d_tables was not filled by qed_build_tables every d_delta is NaN.  Asynchronous on
- * `stream`.  QED_ERR_ARG for NULL tables or output, n < 0, first < 0, chi <= 0,
- * gamma < 1, dtfac < 0, an unknown generator, or (standard) delta_min outside (0, 1) or a
- * workspace that is missing, misaligned or too small. */
+ * `stream`.  QED_ERR_ARG for NULL or misaligned (not 256-byte) tables, a NULL output with
+ * n > 0, n < 0, first < 0, first + n beyond INT64_MAX, chi <= 0, gamma < 1, dtfac < 0,
+ * non-finite parameters, an unknown generator, or (standard) delta_min outside (0, 1), a
+ * cutoff that needs more than 2^22 table intervals, or a workspace that is missing,
+ * misaligned or too small.  qed_generator_work_bytes returns 0 for the generators that
+ * need no workspace and for invalid arguments. */
 #define QED_GEN_MODIFIED 0
 #define QED_GEN_ALTERNATIVE 1
 #define QED_GEN_STANDARD 2
