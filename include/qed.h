@@ -357,6 +357,17 @@ qed_status qed_generator_trials(const void *d_tables, int generator, double chi,
                                 int64_t n, double *d_delta, void *d_work, size_t work_bytes,
                                 void *stream);
 
+/* The standard generator's total emission probability tabulated over chi, as the paper
+ * suggests for that generator (Sec. IV.G, Eq. (23) at x = 1): d_w[i] = W(1) gamma / dtfac,
+ * which depends on chi and the cutoff only, for chi_i = chi_min (chi_max / chi_min)^(i/(n-1))
+ * (chi_0 = chi_min when n = 1), i < n, integrated over the rate table's intervals in log2 z
+ * like qed_generator_trials.  d_w: n doubles, device; NaN everywhere if d_tables was not
+ * filled by qed_build_tables.  Asynchronous on `stream`.  QED_ERR_ARG for NULL or misaligned
+ * tables, NULL d_w, n < 1 or n > 65535, chi_min <= 0, chi_max < chi_min, non-finite chi,
+ * or delta_min outside (0, 1). */
+qed_status qed_standard_w_table(const void *d_tables, double chi_min, double chi_max, int n,
+                                double delta_min, double *d_w, void *stream);
+
 /* Append the record *d_stats to d_log[*d_log_count] and increment *d_log_count, unless
  * *d_log_count >= log_capacity (then the record is discarded and the count still grows,
  * so the caller sees the overflow).  Graph-capturable. */

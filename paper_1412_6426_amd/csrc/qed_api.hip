@@ -348,6 +348,18 @@ qed_status qed_generator_trials(const void* d_tables, int generator, double chi,
   return e == hipSuccess ? QED_OK : QED_ERR_HIP;
 }
 
+qed_status qed_standard_w_table(const void* d_tables, double chi_min, double chi_max, int n,
+                                double delta_min, double* d_w, void* stream) {
+  if (!d_tables || (reinterpret_cast<uintptr_t>(d_tables) & 255u) || !d_w) return QED_ERR_ARG;
+  if (n < 1 || n > 65535 || !finite_pos(chi_min) || !isfinite(chi_max) || chi_max < chi_min)
+    return QED_ERR_ARG;
+  if (!(delta_min > 0.0 && delta_min < 1.0)) return QED_ERR_ARG;
+  const hipError_t e =
+      launch_standard_w_table(static_cast<const DevTables*>(d_tables), chi_min, chi_max, n,
+                              delta_min, d_w, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? QED_OK : QED_ERR_HIP;
+}
+
 size_t qed_thin_work_bytes(int n_instances, int64_t species_slots) {
   if (n_instances < 1 || species_slots < 0) return 0;
   return ThinLayout::make(n_instances, species_slots).total;

@@ -244,6 +244,57 @@ __global__ void __launch_bounds__(256) standard_kernel(TrialArgs a) {
   if (lane < qn) a.out[qi[lane]] = standard_delta(a, ser, cum, qt[lane]);
 }
 
+// W(1) gamma / dtfac for chi_i (one workgroup per chi): each thread integrates every 256th
+// interval, then the workgroup adds the threads' sums in a fixed tree order.
+struct WTableArgs {
+  const DevTables* tables;
+  double chi_min, log2_ratio, delta_min;
+  int n;
+  double* out;
+  double glx[kGl / 2], glw[kGl / 2];
+};
+
+__device__ __forceinline__ long long panels_for(double chi, double delta_min, double& u0,
+                                                double& k0) {
+  u0 = log2((2.0 / 3.0) * delta_min / (chi * (1.0 - delta_min)));
+  k0 = 0.0;
+  if (!(u0 < kLog2ZHi)) return 0;
+  k0 = floor((u0 - kLog2ZLo) * kNodesPerLog2) + 1.0;
+  const double first_end = kLog2ZLo + k0 / kNodesPerLog2;
+  if (!(first_end < kLog2ZHi)) return 1;
+  return 1 + (long long)ceil((kLog2ZHi - first_end) * kNodesPerLog2);
+}
+
+__global__ void __launch_bounds__(256) w_table_kernel(WTableArgs w) {
+  __shared__ double part[256];
+  const int i = blockIdx.x;
+  const double chi =
+      w.n > 1 ? w.chi_min * exp2(w.log2_ratio * (double)i / (double)(w.n - 1)) : w.chi_min;
+  TrialArgs a{};
+  a.tables = w.tables;
+  a.chi = chi;
+  a.gamma = 1.0;
+  a.dtfac = 1.0;
+  a.panels = panels_for(chi, w.delta_min, a.u0, a.k0);
+  for (int m = 0; m < kGl / 2; ++m) {
+    a.glx[m] = w.glx[m];
+    a.glw[m] = w.glw[m];
+  }
+  const bool ok = w.tables->magic == kTableMagic;
+  const Series64 ser = series_of(w.tables);
+  double s = 0.0;
+  if (ok)
+    for (long long k = threadIdx.x; k < a.panels; k += blockDim.x)
+      s += gauss_legendre(a, ser, edge(a, k), edge(a, k + 1));
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) w.out[i] = ok ? part[0] : __builtin_nan("");
+}
+
 // Positive nodes and weights of n-point Gauss-Legendre on [-1, 1]: Newton's method on the
 // Legendre polynomial P_n from the asymptotic guesses cos(pi (i + 3/4) / (n + 1/2)), the
 // weights 2 / ((1 - x^2) P_n'(x)^2).
@@ -275,6 +326,20 @@ void gauss_legendre_rule(int n, double* x, double* w) {
 }
 
 }  // namespace
+
+hipError_t launch_standard_w_table(const DevTables* tables, double chi_min, double chi_max,
+                                   int n, double delta_min, double* out, hipStream_t s) {
+  WTableArgs w{};
+  w.tables = tables;
+  w.chi_min = chi_min;
+  w.log2_ratio = log2(chi_max / chi_min);
+  w.delta_min = delta_min;
+  w.n = n;
+  w.out = out;
+  gauss_legendre_rule(kGl, w.glx, w.glw);
+  hipLaunchKernelGGL(w_table_kernel, dim3((unsigned)n), dim3(256), 0, s, w);
+  return hipGetLastError();
+}
 
 // Intervals of the standard generator's W for (chi, delta_min): from u0 = log2 z(delta_min)
 // to the first table node above it, then table intervals up to z = 2^7 (0: no rate).

@@ -270,6 +270,8 @@ hipError_t launch_schwinger(const qed_stores& st, const float* const grid[3], co
 long long standard_panels(double chi, double delta_min, double* u0, double* k0);
 size_t generator_work_bytes(long long panels);
 long long generator_max_panels();
+hipError_t launch_standard_w_table(const DevTables* tables, double chi_min, double chi_max,
+                                   int n, double delta_min, double* out, hipStream_t s);
 hipError_t launch_generator_trials(const DevTables* tables, int generator, double chi,
                                    double gamma, double dtfac, double delta_min, uint64_t key,
                                    long long first, long long n, double* out, void* work,

@@ -110,7 +110,7 @@ class qed_schwinger_record(C.Structure):
 #: every symbol include/qed.h declares
 EXPORTS = ("qed_table_bytes", "qed_build_tables", "qed_work_bytes", "qed_step",
            "qed_thin_work_bytes", "qed_thin", "qed_schwinger", "qed_generator_work_bytes",
-           "qed_generator_trials",
+           "qed_generator_trials", "qed_standard_w_table",
            "qed_append_stats", "qed_photon_spectrum", "qed_fill_standing_wave",
            "qed_status_string", "qed_version")
 
@@ -157,6 +157,9 @@ def lib():
                                            C.c_double, C.c_double, C.c_uint64, C.c_int64,
                                            C.c_int64, C.c_void_p, C.c_void_p, C.c_size_t,
                                            C.c_void_p]
+        L.qed_standard_w_table.restype = C.c_int
+        L.qed_standard_w_table.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_int,
+                                           C.c_double, C.c_void_p, C.c_void_p]
         L.qed_photon_spectrum.restype = C.c_int
         L.qed_photon_spectrum.argtypes = [C.POINTER(qed_stores), C.c_double, C.c_double,
                                           C.c_int, C.c_void_p, C.c_void_p]
@@ -227,6 +230,12 @@ def qed_generator_trials(d_tables: int, generator: int, chi: float, gamma: float
     _check(lib().qed_generator_trials(d_tables, generator, chi, gamma, dtfac, delta_min, key,
                                       first, n, d_delta, d_work, work_bytes, stream),
            "qed_generator_trials")
+
+
+def qed_standard_w_table(d_tables: int, chi_min: float, chi_max: float, n: int,
+                         delta_min: float, d_w: int, stream: int) -> None:
+    _check(lib().qed_standard_w_table(d_tables, chi_min, chi_max, n, delta_min, d_w, stream),
+           "qed_standard_w_table")
 
 
 def qed_append_stats(d_stats: int, d_log: int, log_capacity: int, d_log_count: int,

@@ -175,6 +175,17 @@ def test_generator_trials_validation_without_device(Q):
     assert call(gen=Q.QED_GEN_STANDARD, dmin=0.0, work=w, wb=need) == Q.QED_ERR_ARG
 
 
+def test_standard_w_table_validation_without_device(Q):
+    L = Q.lib()
+    tab, out = C.c_void_p(4096), C.c_void_p(8192)
+    ok = (tab, 1e-3, 1e3, 41, 1e-3, out, None)
+    for i, bad in ((0, None), (0, C.c_void_p(4100)), (5, None), (3, 0), (3, 65536),
+                   (1, 0.0), (1, -1.0), (2, 1e-4), (2, float("inf")), (4, 0.0), (4, 1.0)):
+        args = list(ok)
+        args[i] = bad
+        assert L.qed_standard_w_table(*args) == Q.QED_ERR_ARG, (i, bad)
+
+
 def test_argument_validation_without_device(Q):
     L = Q.lib()
     assert L.qed_build_tables(None, 0, None) == Q.QED_ERR_ARG

@@ -152,3 +152,28 @@ def test_empty_and_missing_tables(orc, tables):
     off = (-raw.data_ptr()) % 256
     out = _gpu((raw, raw.data_ptr() + off), Q.QED_GEN_MODIFIED, 1000)
     assert np.all(np.isnan(out))
+
+
+@pytest.mark.parametrize("dmin", [1e-3, 1e-9])
+def test_standard_w_table_matches_oracle(orc, tables, dmin):
+    """gamma W(1) / dtfac over chi in [1e-3, 1e3] (41 values): the GPU sums its 8-point rule
+    over the table intervals in a tree, the oracle its 5-point rule in order; both agree to
+    a few thousand additions' rounding."""
+    n, lo, hi = 41, 1e-3, 1e3
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    Q.qed_standard_w_table(tables[1], lo, hi, n, dmin, out.data_ptr(), 0)
+    torch.cuda.synchronize()
+    g = out.cpu().numpy()
+    chis = [lo * 2.0 ** (np.log2(hi / lo) * i / (n - 1)) for i in range(n)]
+    o = np.array([orc.standard_w(1.0 - 1e-15, c, 1.0, 1.0, dmin) for c in chis])
+    np.testing.assert_allclose(g, o, rtol=1e-12, atol=0)
+    assert np.all(np.diff(g) > 0)  # more emission at larger chi
+
+
+def test_standard_w_table_without_tables(tables):
+    raw = torch.zeros(Q.qed_table_bytes() + 256, dtype=torch.uint8, device="cuda")
+    off = (-raw.data_ptr()) % 256
+    out = torch.empty(3, dtype=torch.float64, device="cuda")
+    Q.qed_standard_w_table(raw.data_ptr() + off, 0.1, 10.0, 3, 1e-3, out.data_ptr(), 0)
+    torch.cuda.synchronize()
+    assert np.all(np.isnan(out.cpu().numpy()))

@@ -113,3 +113,14 @@ def test_bad_arguments(orc):
         orc.generator_trials(7, CHI, GAMMA, DTFAC, 1, 10)
     with pytest.raises(ValueError):
         orc.generator_trials(orc.GEN_STANDARD, CHI, GAMMA, DTFAC, 1, 10, delta_min=0.0)
+
+
+@pytest.mark.parametrize("chi", [1e-3, 0.1, 1.0, 10.0, 1e3])
+def test_standard_w_over_chi_is_the_photon_number_rate(orc, chi):
+    """gamma W(1) / dtfac with a cutoff of 1e-15 is the photon number rate int_0^1 P: what
+    the cutoff leaves out is about 3 x 0.52 chi^(2/3) delta_min^(1/3) (the small-delta form
+    printed after Eq. (24)), 1e-5 of it here."""
+    from tests.test_oracle_rates import photon_number_rate
+    w = orc.standard_w(1.0 - 1e-15, chi, 1.0, 1.0, 1e-15)
+    missing = 3.0 * 0.52 * chi ** (2.0 / 3.0) * 1e-5
+    assert w + missing == pytest.approx(photon_number_rate(orc, chi), rel=3e-5)
