@@ -44,7 +44,7 @@ typedef enum {
   QED_OK = 0,
   QED_ERR_ARG = 1,          /* invalid argument (null pointer, size, unknown enum value) */
   QED_ERR_HIP = 2,          /* a HIP runtime call or kernel launch failed */
-  QED_ERR_UNSUPPORTED = 3   /* valid request this build does not implement */
+  QED_ERR_UNSUPPORTED = 3   /* valid request the library does not implement */
 } qed_status;
 
 typedef enum { QED_FP64 = 0, QED_MIXED = 1 } qed_precision;
