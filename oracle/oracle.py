@@ -14,7 +14,9 @@ from typing import Dict, List, Optional, Sequence
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# QED_ORACLE_LIB: another build of qed_oracle.c to load instead (the mutation tests load
+# copies with a mistake planted, to show that the pins catch it)
+LIB_PATH = os.environ.get("QED_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 
 EXACT, TABLE = 0, 1
 FIELD_UNIFORM, FIELD_ROTATING_E, FIELD_CP_STANDING, FIELD_YEE = 0, 1, 2, 3

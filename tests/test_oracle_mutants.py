@@ -1,0 +1,68 @@
+"""The pins catch plausible mistakes: each case plants one mistake in a copy of the oracle's
+source (never in the oracle itself), builds it, and runs the pins that should notice, which
+must then fail.  This checks the pins, not the oracle: a pin that a wrong oracle passes would
+be no pin at all."""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ORACLE = os.path.join(ROOT, "oracle")
+
+# (what goes wrong, text in qed_oracle.c, its replacement, the pins that must fail)
+MUTANTS = [
+    ("emission density without its F2 term",
+     "(F1 + 1.5 * delta * chi * zq * F2);", "(F1);",
+     ["tests/test_oracle_rates.py"]),
+    ("pair density with the brace's sign flipped",
+     "(F1 - 1.5 * chi_g * zp * F2);", "(F1 + 1.5 * chi_g * zp * F2);",
+     ["tests/test_oracle_rates.py"]),
+    ("modified generator evaluating the density at r1 instead of r1^3",
+     "  double delta = r1 * r1 * r1;\n  return 3.0 * r1 * r1 *",
+     "  double delta = r1;\n  return 3.0 * r1 * r1 *",
+     ["tests/test_oracle_generators.py::test_modified_generator_reproduces_spectrum"]),
+    ("chi with (p.E)^2 added instead of subtracted",
+     "double r = v0 * v0 + v1 * v1 + v2 * v2 - pe * pe;",
+     "double r = v0 * v0 + v1 * v1 + v2 * v2 + pe * pe;",
+     ["tests/test_oracle_kinematics.py"]),
+    ("Boris rotation in the wrong sense",
+     "t[i] = q * 0.5 * h * B[i] / g;", "t[i] = -q * 0.5 * h * B[i] / g;",
+     ["tests/test_oracle_kinematics.py"]),
+    ("Boris push missing its second half step in E",
+     "for (int i = 0; i < 3; ++i) p[i] = pl[i] + q * 0.5 * h * E[i];",
+     "for (int i = 0; i < 3; ++i) p[i] = pl[i];",
+     ["tests/test_oracle_kinematics.py"]),
+    ("Philox multiplier mistyped",
+     "(uint64_t)0xD2511F53u * (uint64_t)c0", "(uint64_t)0xD2511F55u * (uint64_t)c0",
+     ["tests/test_oracle_rng.py"]),
+    ("Schwinger exponent exp(-pi E) instead of exp(-pi E_S / E)",
+     "exp(-OR_PI / e)", "exp(-OR_PI * e)",
+     ["tests/test_oracle_schwinger.py"]),
+    ("children left one sub-step too much of the step",
+     "c.tau = (double)(nsub - k - 1) * h;", "c.tau = (double)(nsub - k) * h;",
+     ["tests/test_oracle_same_step.py::test_photon_children_move_through_the_rest_of_the_step"]),
+    ("thinning factor inverted",
+     "w_live / w_kept", "w_kept / w_live",
+     ["tests/test_oracle_thinning.py::test_weight_conserved_and_survivors_untouched"]),
+]
+
+
+@pytest.mark.parametrize("what,old,new,pins", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_a_planted_mistake(tmp_path, what, old, new, pins):
+    src = open(os.path.join(ORACLE, "qed_oracle.c")).read()
+    assert src.count(old) == 1, "the mutation site must be unique"
+    (tmp_path / "qed_oracle.c").write_text(src.replace(old, new))
+    shutil.copy(os.path.join(ORACLE, "qed_oracle.h"), tmp_path / "qed_oracle.h")
+    lib = tmp_path / "libmutant.so"
+    subprocess.run(["gcc", "-std=c11", "-O2", "-fPIC", "-shared", "-fopenmp",
+                    "-ffp-contract=off", "-fno-fast-math", "-o", str(lib),
+                    str(tmp_path / "qed_oracle.c"), "-lm"], check=True)
+    env = dict(os.environ, QED_ORACLE_LIB=str(lib))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                        "-m", "not gpu", *pins], cwd=ROOT, env=env, capture_output=True,
+                       text=True, timeout=900)
+    assert r.returncode != 0, f"no pin noticed: {what}\n{r.stdout[-2000:]}"
+    assert "failed" in r.stdout or "error" in r.stdout.lower(), r.stdout[-2000:]
