@@ -47,6 +47,19 @@ MUTANTS = [
     ("thinning factor inverted",
      "w_live / w_kept", "w_kept / w_live",
      ["tests/test_oracle_thinning.py::test_weight_conserved_and_survivors_untouched"]),
+    ("lepton time-step bound with 140 for 14",
+     "kappa * 14.0 * (2.0 * OR_PI * eps_r)", "kappa * 140.0 * (2.0 * OR_PI * eps_r)",
+     ["tests/test_oracle_kinematics.py"]),
+    ("Ex sampled on the nodes instead of the half-nodes",
+     "{{0.5, 0, 0},   {0, 0.5, 0}", "{{0.0, 0, 0},   {0, 0.5, 0}",
+     ["tests/test_oracle_kinematics.py"]),
+    ("emission without recoil",
+     "for (int d = 0; d < 3; ++d) mom[d] = mom[d] - c.p[d];",
+     "for (int d = 0; d < 3; ++d) mom[d] = mom[d];",
+     ["tests/test_oracle_step.py"]),
+    ("generator factor not raising the children's weight",
+     "return fg > 1.0 ? fg : 1.0;", "return 1.0;",
+     ["tests/test_oracle_generator_factor.py"]),
 ]
 
 
