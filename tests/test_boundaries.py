@@ -51,3 +51,34 @@ def test_bench_reaches_the_oracle_only_from_its_cpu_baseline():
     for name, node in imps:
         if name.startswith("oracle") or name == "tests.parity_util":
             assert owners.get(id(node)) == "cpu_baseline", (name, owners.get(id(node)))
+
+
+def test_product_fails_loudly_without_its_library_or_device(tmp_path):
+    """No CPU fallback: a missing libqed.so and a missing device are errors, not detours."""
+    import subprocess
+    import sys
+    code = (
+        "import sys\n"
+        "from paper_1412_6426_amd import qed as Q\n"
+        f"Q.LIB_PATH = {str(tmp_path / 'absent.so')!r}\n"
+        "Q._lib = None\n"
+        "try:\n"
+        "    Q.lib()\n"
+        "except Q.QedError as e:\n"
+        "    print('library:', e)\n"
+        "else:\n"
+        "    sys.exit(3)\n"
+        "import torch\n"
+        "if not torch.cuda.is_available():\n"
+        "    from paper_1412_6426_amd.engine import Engine\n"
+        "    try:\n"
+        "        Engine([(10, 10, 10)], seeds=[0])\n"
+        "    except Q.QedError as e:\n"
+        "        print('device:', e)\n"
+        "    else:\n"
+        "        sys.exit(4)\n"
+    )
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "library:" in r.stdout
