@@ -146,3 +146,21 @@ def test_avalanche_same_step_parity(orc):
         tol = max(1e-12, 10.0 * max(spread.values()))
         _note(f"species {sp}: one-ulp spread {max(spread.values()):.2e}, tolerance {tol:.2e}")
         compare_species(e.read(0, sp), os_[sp].view(), sp, rtol=tol, label=f"avalanche {sp}")
+
+
+def test_same_step_with_generator_factors_parity(orc):
+    """Children advanced in their birth step (G = 3) together with generator factors f_g = 3
+    for photons and 2 for pairs (Sec. VI): the generation kernel samples its own children's
+    creation the way the step does, and the parents' weights carry through."""
+    w = W.rotating_e(n=300, periods=1.5, capacity=400_000, lepton_capacity=40_000)
+    init = W.rotating_e_initial(300, seed=3)
+    over = dict(same_step_generations=3, f_photon=3.0, f_pair=2.0)
+    _note(f"rotating cascade, {over}")
+    e = R.engine_single(w, init, same_step=True)
+    stats = R.run(e, R.field_of(w), R.params_of(w, **over), w.n_steps)
+    os_ = oracle_stores(orc, init, w.capacity)
+    ostats = orc.run(os_, oracle_field(orc, w), oracle_params(orc, w, **over), w.n_steps)
+    _check_steps(stats, ostats)
+    assert sum(s["children_advanced"] for s in stats) > 1000
+    assert sum(s["pairs"] for s in stats) > 5
+    compare_all(e, os_, label="same-step with generator factors")
