@@ -164,3 +164,27 @@ def test_same_step_with_generator_factors_parity(orc):
     assert sum(s["children_advanced"] for s in stats) > 1000
     assert sum(s["pairs"] for s in stats) > 5
     compare_all(e, os_, label="same-step with generator factors")
+
+
+def test_batched_instances_same_step_parity(orc):
+    """Four instances of different size, amplitude and seed (one empty) in one launch, with
+    children advanced in their birth step (G = 2): the generation passes keep every
+    instance's children in its own segment, and each instance equals its own oracle run."""
+    w = W.batched_rotating(instances=4, a_lo=600.0, a_hi=2400.0, periods=0.75,
+                           n_override=[37, 0, 129, 200], total_capacity=4 * 400_000,
+                           precision="f64")
+    inits = W.batched_initial(w)
+    _note(f"batched same-step: {w.description}")
+    e = R.engine_batched(w, inits, same_step=True)
+    st = R.run(e, R.field_of(w), R.params_of(w, same_step_generations=2), w.n_steps,
+               stop_on_drop=False)
+    assert sum(s["dropped"] for s in st) == 0
+    assert sum(s["children_advanced"] for s in st) > 100
+    for i in range(w.instances):
+        wi = W.rotating_e(n=w.instance_n[i], a0=w.instance_amp[i], periods=0.75, seed=i,
+                          capacity=w.instance_capacity[2],
+                          lepton_capacity=w.instance_capacity[1])
+        os_ = oracle_stores(orc, inits[i], w.instance_capacity)
+        orc.run(os_, oracle_field(orc, wi), oracle_params(orc, wi, same_step_generations=2),
+                w.n_steps)
+        compare_all(e, os_, inst=i, label=f"instance {i}")
