@@ -188,3 +188,22 @@ def test_batched_instances_same_step_parity(orc):
         orc.run(os_, oracle_field(orc, wi), oracle_params(orc, wi, same_step_generations=2),
                 w.n_steps)
         compare_all(e, os_, inst=i, label=f"instance {i}")
+
+
+def test_mixed_precision_same_step_follows_fp64():
+    """The mixed form (rate and decision in FP32) with same-step children (G = 2): both forms
+    draw the same numbers, so only decisions within FP32 rounding of the threshold can
+    differ, and the cascade's totals stay within 1% of the FP64 run's."""
+    w = W.rotating_e(n=300, periods=1.5, capacity=400_000, lepton_capacity=40_000)
+    init = W.rotating_e_initial(300, seed=3)
+    tot = {}
+    for prec in ("f64", "mixed"):
+        _note(f"same-step G = 2, {prec}")
+        e = R.engine_single(w, init, same_step=True)
+        st = R.run(e, R.field_of(w),
+                   R.params_of(w, same_step_generations=2, precision=R.PRECISION[prec]),
+                   w.n_steps)
+        tot[prec] = np.array([sum(s[c] for s in st)
+                              for c in ("emitted", "pairs", "children_advanced")], float)
+    assert tot["f64"][1] > 50
+    np.testing.assert_allclose(tot["mixed"], tot["f64"], rtol=1e-2)
