@@ -326,6 +326,52 @@ def gpu_run_yee(args, precision):
     return out
 
 
+def gpu_uniform_b(args):
+    """Config 1: 10^4 electrons at gamma = 1000 across a uniform B with chi = 1, eight
+    sub-steps each (dt = T_gyro/100), 100 steps, emission only, photons recorded and not
+    pushed.  Steps run eagerly on one stream with HIP events around each step and around its
+    lepton kernel.  10^4 electrons fill 157 wavefronts: this run shows the step's fixed cost
+    per launch, not a bandwidth."""
+    import torch
+    from paper_1412_6426_amd import runner as R
+    from paper_1412_6426_amd import workloads as W
+
+    w = W.uniform_b()
+    init = W.uniform_b_initial(w)
+    e = R.engine_single(w, init)
+    field = R.field_of(w)
+    params = R.params_of(w)
+    K = w.n_steps
+    stream = torch.cuda.Stream()
+    sp = stream.cuda_stream
+    hip = HipEvents()
+    evs = hip.create(4 * K)
+    torch.cuda.synchronize()
+    e.set_step(0)
+    with torch.cuda.stream(stream):
+        for n in range(K):
+            ev = evs[4 * n:4 * n + 4]
+            hip.lib.hipEventRecord(C.c_void_p(ev[0]), C.c_void_p(sp))
+            params.events[0] = ev[1]
+            params.events[1] = ev[2]
+            e.step(field, params, stream=sp)
+            hip.lib.hipEventRecord(C.c_void_p(ev[3]), C.c_void_p(sp))
+    torch.cuda.synchronize()
+    step_ms = sum(hip.elapsed_ms(evs[4 * n], evs[4 * n + 3]) for n in range(K))
+    lep_ms = sum(hip.elapsed_ms(evs[4 * n + 1], evs[4 * n + 2]) for n in range(K))
+    hip.destroy(evs)
+    photons = int(e.counts()[0, 2])
+    lepton_steps = w.n_seed * K
+    del e
+    torch.cuda.empty_cache()
+    return dict(workload=w.description, steps=K, lepton_steps=lepton_steps,
+                substeps=8 * lepton_steps, photons_emitted=photons,
+                us_per_step=1e3 * step_ms / K, lepton_kernel_us_per_step=1e3 * lep_ms / K,
+                lepton_steps_per_s=lepton_steps / (step_ms / 1e3),
+                lepton_kernel_gbs=(LEPTON_STEP_BYTES * lepton_steps + EMISSION_BYTES * photons)
+                / (lep_ms / 1e3) / 1e9)
+
+
 def gpu_schwinger_grid(args):
     """Schwinger pairs (Sec. V.B) on the 256^3 Yee grid of the standing-wave workload (cells of
     lambda/32, lambda = 0.8 um, dt = T/100), the wave's amplitude raised so that its antinodes
@@ -759,6 +805,8 @@ def main():
                     help="skip Schwinger pair production on the 256^3 grid")
     ap.add_argument("--schwinger-only", action="store_true",
                     help="run only the Schwinger leg and print its record (profiling)")
+    ap.add_argument("--no-uniform-b", action="store_true",
+                    help="skip config 1 (10^4 electrons in a uniform B)")
     ap.add_argument("--no-generators", action="store_true",
                     help="skip the comparison of the three emission generators")
     ap.add_argument("--generators-only", action="store_true",
@@ -895,6 +943,9 @@ def main():
     if not args.no_yee:
         print("bench: standing-wave cascade on the Yee grid", file=sys.stderr, flush=True)
         line["standing_wave_grid"] = gpu_run_yee(args, args.precision)
+    if not args.no_uniform_b:
+        print("bench: config 1, uniform B", file=sys.stderr, flush=True)
+        line["uniform_b"] = gpu_uniform_b(args)
     if not args.no_schwinger:
         print("bench: Schwinger pairs on the Yee grid", file=sys.stderr, flush=True)
         line["schwinger_grid"] = gpu_schwinger_grid(args)
