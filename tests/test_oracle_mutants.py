@@ -57,6 +57,9 @@ MUTANTS = [
      "for (int d = 0; d < 3; ++d) mom[d] = mom[d] - c.p[d];",
      "for (int d = 0; d < 3; ++d) mom[d] = mom[d];",
      ["tests/test_oracle_step.py"]),
+    ("Schwinger rate with the Compton length cubed instead of to the fourth",
+     "pow(eps_r, 4.0)", "pow(eps_r, 3.0)",
+     ["tests/test_oracle_schwinger.py"]),
     ("generator factor not raising the children's weight",
      "return fg > 1.0 ? fg : 1.0;", "return 1.0;",
      ["tests/test_oracle_generator_factor.py"]),

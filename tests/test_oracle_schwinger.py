@@ -142,3 +142,19 @@ def test_cell_field_is_the_mean_of_its_samples(orc):
         assert abs(n * p_lo - n * p_mean) > 4.0 * sd and abs(n * p_hi - n * p_mean) > 4.0 * sd
         checked += 1
     assert checked == N - 9
+
+
+def test_expected_count_scales_with_four_volume_and_units(orc):
+    """P = R_S V c dt: the expected count is linear in the cell volume and in dt, and at a
+    fixed E / E_S it scales as eps_r^-4 (the reduced Compton length is eps_r in units of
+    c / omega, and R_S is per unit four-volume)."""
+    def expected(dx, dt, eps_r, e_over_es=1.2):
+        grids = _grid(ex=e_over_es / eps_r)  # code units: E / E_S = eps_r |E|
+        st = _stores(orc)
+        return orc.schwinger(st, _field(orc, grids, dx=dx), dt, eps_r, 1.0, seed=1,
+                             step=0)["expected"]
+    base = expected(0.5, 1.0, 1.0)
+    assert base > 0.0
+    assert expected(1.0, 1.0, 1.0) == pytest.approx(8.0 * base, rel=1e-12)  # V x 8
+    assert expected(0.5, 3.0, 1.0) == pytest.approx(3.0 * base, rel=1e-12)
+    assert expected(0.5, 1.0, 0.5) == pytest.approx(16.0 * base, rel=1e-12)
