@@ -60,6 +60,19 @@ MUTANTS = [
     ("Schwinger rate with the Compton length cubed instead of to the fourth",
      "pow(eps_r, 4.0)", "pow(eps_r, 3.0)",
      ["tests/test_oracle_schwinger.py"]),
+    ("photon chi without the photon energy factor",
+     "return kabs * H * eps_r;", "return H * eps_r;",
+     ["tests/test_oracle_kinematics.py", "tests/test_oracle_rates.py"]),
+    ("pair probability scaled by |k| instead of divided",
+     "(chi_g / kabs) * (delta_e - 1.0)", "(chi_g * kabs) * (delta_e - 1.0)",
+     ["tests/test_oracle_rates.py"]),
+    ("pair leptons not inheriting the photon's magnetic field for the rest of the step",
+     "e.B[d] = pos.B[d] = B[d];", "e.B[d] = pos.B[d] = 0.0;",
+     ["tests/test_oracle_same_step.py::test_pair_leptons_turn_through_the_rest_of_the_step"]),
+    ("standard generator's W without the ln 2 of d delta / du",
+     "return or_rate_emission(a->t, a->backend, d, a->chi, a->gamma, a->dtfac) * log(2.0) * d /",
+     "return or_rate_emission(a->t, a->backend, d, a->chi, a->gamma, a->dtfac) * d /",
+     ["tests/test_oracle_generator_comparison.py"]),
     ("generator factor not raising the children's weight",
      "return fg > 1.0 ? fg : 1.0;", "return 1.0;",
      ["tests/test_oracle_generator_factor.py"]),
