@@ -73,6 +73,13 @@ MUTANTS = [
      "return or_rate_emission(a->t, a->backend, d, a->chi, a->gamma, a->dtfac) * log(2.0) * d /",
      "return or_rate_emission(a->t, a->backend, d, a->chi, a->gamma, a->dtfac) * d /",
      ["tests/test_oracle_generator_comparison.py"]),
+    ("lepton position advanced by p instead of p / gamma",
+     "x[d] += h * mom[d] / gamma;", "x[d] += h * mom[d];",
+     ["tests/test_oracle_step.py::test_leptons_gyrate_on_their_larmor_circle"]),
+    ("Schwinger pair placed on the cell's diagonal (one uniform for two axes)",
+     "((double)o[0] + 0.5) * 0x1p-32, ((double)o[1] + 0.5) * 0x1p-32,",
+     "((double)o[0] + 0.5) * 0x1p-32, ((double)o[0] + 0.5) * 0x1p-32,",
+     ["tests/test_oracle_schwinger.py"]),
     ("generator factor not raising the children's weight",
      "return fg > 1.0 ? fg : 1.0;", "return 1.0;",
      ["tests/test_oracle_generator_factor.py"]),

@@ -95,6 +95,10 @@ def test_pairs_sit_at_rest_uniformly_inside_their_cells(orc):
     # uniform in the cell: mean 1/2 and variance 1/12 per axis
     assert np.all(np.abs(frac.mean(0) - 0.5) < 4.0 * math.sqrt(1.0 / 12.0 / m))
     assert np.all(np.abs(frac.var(0) - 1.0 / 12.0) < 4.0 * math.sqrt(1.0 / 180.0 / m))
+    # and uniform over the cell, not along a line in it: the axes are uncorrelated
+    corr = np.corrcoef(frac.T)
+    for i, j in ((0, 1), (0, 2), (1, 2)):
+        assert abs(corr[i, j]) < 4.0 / math.sqrt(m), (i, j, corr[i, j])
 
 
 def test_magnetic_field_changes_nothing(orc):

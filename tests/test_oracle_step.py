@@ -212,3 +212,31 @@ def test_resume_is_bit_exact(orc):
         o1, o2 = np.argsort(v1["id"]), np.argsort(v2["id"])
         for k in v1:
             assert np.array_equal(v1[k][o1], v2[k][o2])
+
+
+def test_leptons_gyrate_on_their_larmor_circle(orc):
+    """Emission off: an electron of gamma = 10 across a uniform B moves below c along a circle
+    of radius p / B (the Larmor radius, in these units), closing it after one gyro period
+    2 pi gamma / B.  200 steps of one Boris sub-step each per period."""
+    g, B = 10.0, 1e-3
+    p = math.sqrt(g * g - 1.0)
+    zero = np.zeros(1)
+    init = [W._seed_columns(zero, zero, zero, [p], zero, zero), W.empty_columns(),
+            W.empty_columns()]
+    st = make_stores(orc, init, (10, 10, 10))
+    fld = orc.Field(kind=orc.FIELD_UNIFORM, b0=(0.0, 0.0, B))
+    dt = 2.0 * math.pi * g / B / 200
+    par = orc.Params(dt=dt, eps_r=1e-6, seed=1, emission=0, pairs=0, forced_substeps=1)
+    pts = [(0.0, 0.0)]
+    for n in range(200):
+        orc.run(st, fld, par, 1, first_step=n)
+        v = st[0].view()
+        pts.append((v["x"][0], v["y"][0]))
+    pts = np.array(pts)
+    step = np.linalg.norm(np.diff(pts, axis=0), axis=1)
+    assert np.all(step < dt)  # below c
+    assert step == pytest.approx(dt * p / g, rel=1e-3)  # at its speed v = p / gamma
+    centre = pts[:-1].mean(axis=0)  # 200 points spread evenly over the period
+    radius = np.linalg.norm(pts - centre, axis=1)
+    assert radius == pytest.approx(p / B, rel=1e-3)
+    assert np.linalg.norm(pts[-1] - pts[0]) < 2e-3 * p / B  # closed after one period
