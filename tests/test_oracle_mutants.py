@@ -80,6 +80,19 @@ MUTANTS = [
      "((double)o[0] + 0.5) * 0x1p-32, ((double)o[1] + 0.5) * 0x1p-32,",
      "((double)o[0] + 0.5) * 0x1p-32, ((double)o[0] + 0.5) * 0x1p-32,",
      ["tests/test_oracle_schwinger.py"]),
+    ("photon chi with the sign of k x B flipped in one component",
+     "double v0 = E[0] + (n1 * B[2] - n2 * B[1]);", "double v0 = E[0] - (n1 * B[2] - n2 * B[1]);",
+     ["tests/test_oracle_kinematics.py"]),
+    ("rotating field turning the other way",
+     "      E[1] = f->amp * sin(ph);", "      E[1] = -f->amp * sin(ph);",
+     ["tests/test_oracle_kinematics.py"]),
+    ("emitted photon along the lepton's x axis only",
+     "c.p[d] = (eps / pabs) * mom[d];", "c.p[d] = (eps / pabs) * mom[0];",
+     ["tests/test_oracle_step.py"]),
+    ("Schwinger cell field not averaged over its four samples",
+     "const double ex = 0.25 * (or_grid_at(f->grid[0]",
+     "const double ex = 0.5 * (or_grid_at(f->grid[0]",
+     ["tests/test_oracle_schwinger.py"]),
     ("generator factor not raising the children's weight",
      "return fg > 1.0 ? fg : 1.0;", "return 1.0;",
      ["tests/test_oracle_generator_factor.py"]),
