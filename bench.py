@@ -807,6 +807,8 @@ def main():
                     help="run only the Schwinger leg and print its record (profiling)")
     ap.add_argument("--no-uniform-b", action="store_true",
                     help="skip config 1 (10^4 electrons in a uniform B)")
+    ap.add_argument("--only", choices=("uniform-b", "yee", "batched"), default=None,
+                    help="run only this leg and print its record (profiling)")
     ap.add_argument("--no-generators", action="store_true",
                     help="skip the comparison of the three emission generators")
     ap.add_argument("--generators-only", action="store_true",
@@ -831,6 +833,20 @@ def main():
         return
     if args.schwinger_only:
         print(json.dumps({"schwinger_grid": gpu_schwinger_grid(args)}), flush=True)
+        return
+    if args.only == "uniform-b":
+        print(json.dumps({"uniform_b": gpu_uniform_b(args)}), flush=True)
+        return
+    if args.only == "yee":
+        print(json.dumps({"standing_wave_grid": gpu_run_yee(args, args.precision)}), flush=True)
+        return
+    if args.only == "batched":
+        out = {}
+        for prec in ("mixed", "f64"):
+            rb = gpu_run(args, prec, kind="batched")
+            out[prec] = dict(value=rb["particle_steps"] / (rb["ms"] / 1e3), ms=rb["ms"],
+                             lep_ms=rb["lep_ms"], pho_ms=rb["pho_ms"])
+        print(json.dumps({"batched": out}), flush=True)
         return
     if args.generators_only:
         print(json.dumps({"generator_comparison": gpu_generator_comparison(args)}), flush=True)
