@@ -321,18 +321,48 @@ __device__ __forceinline__ CicAxis cic_axis(double s, int n) {
   return a;
 }
 
+// The two x-neighbours g[r + i0] and g[r + i1] of one grid row (nx >= 2).  Rows are
+// contiguous in x, so the pair comes from one 8-byte buffer load (4-byte aligned, which
+// buffer loads allow): 4 loads per component instead of 8 in the scattered gathers that
+// bound the grid kernels.  Where the pair wraps round the periodic boundary (i0 = nx - 1,
+// i1 = 0) the load covers (nx - 2, nx - 1) instead, and g[r] is read on its own.  The
+// buffer descriptor spans the grid, so byte offsets are 32-bit: grids of 2^30 values or
+// more take the plain path below.  (A plain 8-byte load at 4-byte alignment is split into
+// two by the compiler; the buffer load is not.)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t cic_rsrc(const float* g, unsigned values) {
+  // word 3 0x00020000: raw 32-bit data format on gfx9-family targets
+  return __builtin_amdgcn_make_buffer_rsrc((void*)g, 0, (int)(values * 4u), 0x00020000);
+}
+
+__device__ __forceinline__ float2 cic_pair(__amdgpu_buffer_rsrc_t rs, const float* __restrict__ g,
+                                           int r, const CicAxis& ax) {
+  const bool wrap = ax.i1 == 0;
+  const unsigned b = (unsigned)(r + ax.i0 - (wrap ? 1 : 0));
+  const float2 p = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)(b * 4u), 0, 0));
+  float2 v = make_float2(wrap ? p.y : p.x, p.y);
+  if (wrap) v.y = g[r];
+  return v;
+}
+
 // One component: 8 grid values around the point, interpolated along x, then y, then z.
-// nxy = nx * ny; the grid holds fewer than 2^31 values.
+// nxy = nx * ny; the grid holds fewer than 2^31 values (nall of them).
 __device__ __forceinline__ double cic_component(const float* __restrict__ g, const CicAxis& ax,
                                                 const CicAxis& ay, const CicAxis& az, int nx,
-                                                int nxy) {
+                                                int nxy, int nall) {
   const int z0 = az.i0 * nxy, z1 = az.i1 * nxy;
   const int y0 = ay.i0 * nx, y1 = ay.i1 * nx;
   const int r00 = z0 + y0, r01 = z0 + y1, r10 = z1 + y0, r11 = z1 + y1;
-  const double v000 = g[r00 + ax.i0], v100 = g[r00 + ax.i1];
-  const double v010 = g[r01 + ax.i0], v110 = g[r01 + ax.i1];
-  const double v001 = g[r10 + ax.i0], v101 = g[r10 + ax.i1];
-  const double v011 = g[r11 + ax.i0], v111 = g[r11 + ax.i1];
+  double v000, v100, v010, v110, v001, v101, v011, v111;
+  if (nall < (1 << 30)) {
+    const __amdgpu_buffer_rsrc_t rs = cic_rsrc(g, (unsigned)nall);
+    const float2 p00 = cic_pair(rs, g, r00, ax), p01 = cic_pair(rs, g, r01, ax);
+    const float2 p10 = cic_pair(rs, g, r10, ax), p11 = cic_pair(rs, g, r11, ax);
+    v000 = p00.x, v100 = p00.y, v010 = p01.x, v110 = p01.y;
+    v001 = p10.x, v101 = p10.y, v011 = p11.x, v111 = p11.y;
+  } else {
+    v000 = g[r00 + ax.i0], v100 = g[r00 + ax.i1], v010 = g[r01 + ax.i0], v110 = g[r01 + ax.i1];
+    v001 = g[r10 + ax.i0], v101 = g[r10 + ax.i1], v011 = g[r11 + ax.i0], v111 = g[r11 + ax.i1];
+  }
   const double fx = ax.f, fy = ay.f, fz = az.f;
   const double c00 = v000 + fx * (v100 - v000);
   const double c10 = v010 + fx * (v110 - v010);
@@ -378,16 +408,16 @@ __device__ __forceinline__ void field_at_position(const FieldArgs& f, double ins
   const double sx = (x.x - f.origin[0]) * f.inv_dx[0];
   const double sy = (x.y - f.origin[1]) * f.inv_dx[1];
   const double sz = (x.z - f.origin[2]) * f.inv_dx[2];
-  const int nx = f.n[0], ny = f.n[1], nz = f.n[2], nxy = nx * ny;
+  const int nx = f.n[0], ny = f.n[1], nz = f.n[2], nxy = nx * ny, nall = nxy * nz;
   const CicAxis x0 = cic_axis(sx, nx), xh = cic_axis(sx - 0.5, nx);
   const CicAxis y0 = cic_axis(sy, ny), yh = cic_axis(sy - 0.5, ny);
   const CicAxis z0 = cic_axis(sz, nz), zh = cic_axis(sz - 0.5, nz);
-  E.x = cic_component(f.grid[0], xh, y0, z0, nx, nxy);
-  E.y = cic_component(f.grid[1], x0, yh, z0, nx, nxy);
-  E.z = cic_component(f.grid[2], x0, y0, zh, nx, nxy);
-  B.x = cic_component(f.grid[3], x0, yh, zh, nx, nxy);
-  B.y = cic_component(f.grid[4], xh, y0, zh, nx, nxy);
-  B.z = cic_component(f.grid[5], xh, yh, z0, nx, nxy);
+  E.x = cic_component(f.grid[0], xh, y0, z0, nx, nxy, nall);
+  E.y = cic_component(f.grid[1], x0, yh, z0, nx, nxy, nall);
+  E.z = cic_component(f.grid[2], x0, y0, zh, nx, nxy, nall);
+  B.x = cic_component(f.grid[3], x0, yh, zh, nx, nxy, nall);
+  B.y = cic_component(f.grid[4], xh, y0, zh, nx, nxy, nall);
+  B.z = cic_component(f.grid[5], xh, yh, z0, nx, nxy, nall);
 }
 
 // ------------------------------------------------------------------------------------

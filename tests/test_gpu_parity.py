@@ -336,6 +336,49 @@ def test_yee_grid_parity(orc):
     compare_all(e, os_, label="yee")
 
 
+def test_yee_grid_random_values_every_wrap(orc):
+    """A non-cubic 7x5x4 grid of seeded random values (so every node and every component
+    differs) and particles spread over three box lengths per axis, so that positions
+    inside, beyond and before the primary box all wrap, and many sit in the last cell of
+    a row, where the x-neighbour pair straddles the periodic boundary."""
+    import dataclasses
+    w = W.standing_wave_grid(n=400, cells=8, capacity=50_000, lepton_capacity=5_000,
+                             steps=3, a0=2000.0)
+    fs = dataclasses.replace(w.field, grid_n=(7, 5, 4), grid_origin=(-1.3, 0.4, 2.2))
+    w = dataclasses.replace(w, field=fs)
+    nx, ny, nz = fs.grid_n
+    rng = np.random.default_rng(11)
+    lo = np.array(fs.grid_origin) - np.array(fs.grid_n) * np.array(fs.grid_dx)
+    span = 3.0 * np.array(fs.grid_n) * np.array(fs.grid_dx)
+    n = 400
+    pos = lo[:, None] + span[:, None] * rng.random((3, n))
+    # a quarter of the particles in the last cell along x (the wrapping pair)
+    q = n // 4
+    pos[0, :q] = fs.grid_origin[0] + (nx - 1 + rng.random(q)) * fs.grid_dx[0]
+    init = W.standing_wave_initial(n, seed=3)
+    for k, c in enumerate(("x", "y", "z")):
+        init[0][c] = pos[k].copy()
+    init[0]["px"] = rng.normal(0.0, 300.0, n)
+    init[0]["py"] = rng.normal(0.0, 300.0, n)
+    init[0]["pz"] = rng.normal(0.0, 300.0, n)
+    _note(f"yee random grid {fs.grid_n}: {n} electrons, {w.n_steps} steps")
+    e = R.engine_single(w, init)
+    grid = R.YeeGrid(w)
+    f = R.field_of(w, grid=grid.g)
+    p = R.params_of(w)
+    os_ = oracle_stores(orc, init, w.capacity)
+    op = oracle_params(orc, w)
+    e.set_step(0)
+    for step in range(w.n_steps):
+        vals = [(1500.0 * rng.standard_normal((nz, ny, nx))).astype(np.float32) for _ in range(6)]
+        grid.load_numpy(vals)
+        e.step(f, p)
+        torch.cuda.synchronize()
+        op.step = step
+        orc.step(os_, oracle_field(orc, w, grids=vals), op)
+    compare_all(e, os_, label="yee-random")
+
+
 def test_fill_standing_wave_matches_numpy():
     w = W.standing_wave_grid(n=1, cells=16)
     grid = R.YeeGrid(w)
