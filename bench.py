@@ -30,7 +30,6 @@ recorded there, else null.
 """
 import argparse
 import ctypes as C
-import hashlib
 import json
 import math
 import os
@@ -527,7 +526,8 @@ def measured_traffic(kernel):
         if ":" in line and line.startswith("- "):
             k, v = line[2:].split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
-    src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    from paper_1412_6426_amd.calib.profile_summary import source_digest
+    src = source_digest(KERNEL_SRC)
     if vals.get("kernel") != kernel or vals.get("kernel_source_sha256") != src:
         return None
     try:

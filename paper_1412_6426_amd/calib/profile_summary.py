@@ -8,8 +8,9 @@
         --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR --out FILE --command CMD
         HBM bytes per launch of NAME from a FETCH_SIZE and a WRITE_SIZE pass, each scaled by
         the same counter's reading for lib/hbm_copy (800 MB read and 800 MB written per
-        launch).  The summary records the sha256 of the kernel source so that a reader can
-        tell whether the figure still describes the current kernel.
+        launch).  The summary records a sha256 of the kernel source and the headers it
+        includes, so that a reader can tell whether the figure still describes the current
+        kernel.
 
     python -m paper_1412_6426_amd.calib.profile_summary pmc --kernel NAME DIR [DIR ...] \\
         --out FILE --command CMD
@@ -26,6 +27,20 @@ import statistics
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SRC = os.path.join(os.path.dirname(HERE), "csrc", "qed_step.hip")
+# The headers every kernel source includes (device helpers, launch declarations, the C ABI).
+KERNEL_HEADERS = (os.path.join(os.path.dirname(HERE), "csrc", "qed_internal.h"),
+                  os.path.join(os.path.dirname(HERE), "csrc", "qed_device.h"),
+                  os.path.join(os.path.dirname(os.path.dirname(HERE)), "include", "qed.h"))
+
+
+def source_digest(path: str = KERNEL_SRC) -> str:
+    """sha256 over a kernel source followed by the headers it includes, so that a change
+    to either marks counters taken before it as stale."""
+    h = hashlib.sha256()
+    for f in (path,) + KERNEL_HEADERS:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 COPY_BYTES = 800_000_000  # hbm_copy: 10^8 doubles read and 10^8 written per launch
 
 
@@ -99,7 +114,7 @@ def cmd_hbm(a):
     fw = COPY_BYTES / (statistics.median(cw) * 1024.0)
     fetch_b = statistics.mean(f) * 1024.0 * ff
     write_b = statistics.mean(w) * 1024.0 * fw
-    sha = hashlib.sha256(open(a.source, "rb").read()).hexdigest()
+    sha = source_digest(a.source)
     lines = [f"# {a.title}", "", "Commands (from the repository root):", "", "```",
              a.command, "```", "",
              f"- kernel: {a.kernel}",
@@ -168,7 +183,7 @@ def main():
     h.add_argument("--copy-fetch", required=True)
     h.add_argument("--copy-write", required=True)
     h.add_argument("--source", default=KERNEL_SRC,
-                   help="kernel source whose sha256 the summary records")
+                   help="kernel source whose digest (with the headers it includes) the summary records")
     a = ap.parse_args()
     {"trace": cmd_trace, "hbm": cmd_hbm, "pmc": cmd_pmc}[a.cmd](a)
 

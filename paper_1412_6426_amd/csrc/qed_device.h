@@ -345,7 +345,11 @@ __device__ __forceinline__ float2 cic_pair(__amdgpu_buffer_rsrc_t rs, const floa
 }
 
 // One component: 8 grid values around the point, interpolated along x, then y, then z.
-// nxy = nx * ny; the grid holds fewer than 2^31 values (nall of them).
+// nxy = nx * ny; the grid holds fewer than 2^31 values (nall of them).  PAIRED takes the
+// x-neighbours in pairs (the photon kernels, which the gathers bound); the lepton kernel
+// gathers once per step between sub-steps that dominate its time, and the pairs' extra
+// registers in flight cost it more than they save.
+template <bool PAIRED>
 __device__ __forceinline__ double cic_component(const float* __restrict__ g, const CicAxis& ax,
                                                 const CicAxis& ay, const CicAxis& az, int nx,
                                                 int nxy, int nall) {
@@ -353,7 +357,7 @@ __device__ __forceinline__ double cic_component(const float* __restrict__ g, con
   const int y0 = ay.i0 * nx, y1 = ay.i1 * nx;
   const int r00 = z0 + y0, r01 = z0 + y1, r10 = z1 + y0, r11 = z1 + y1;
   double v000, v100, v010, v110, v001, v101, v011, v111;
-  if (nall < (1 << 30)) {
+  if (PAIRED && nall < (1 << 30)) {
     const __amdgpu_buffer_rsrc_t rs = cic_rsrc(g, (unsigned)nall);
     const float2 p00 = cic_pair(rs, g, r00, ax), p01 = cic_pair(rs, g, r01, ax);
     const float2 p10 = cic_pair(rs, g, r10, ax), p11 = cic_pair(rs, g, r11, ax);
@@ -383,6 +387,7 @@ struct FieldArgs {
 
 // Fields at position x for the kinds that depend on position (CP standing wave, Yee).
 // Space-independent kinds are evaluated once per instance by the step's prep kernel.
+template <bool PAIRED = false>
 __device__ __forceinline__ void field_at_position(const FieldArgs& f, double inst_amp, const V3& x,
                                                   V3& E, V3& B) {
   if (f.kind == QED_FIELD_LP_STANDING) {
@@ -412,12 +417,12 @@ __device__ __forceinline__ void field_at_position(const FieldArgs& f, double ins
   const CicAxis x0 = cic_axis(sx, nx), xh = cic_axis(sx - 0.5, nx);
   const CicAxis y0 = cic_axis(sy, ny), yh = cic_axis(sy - 0.5, ny);
   const CicAxis z0 = cic_axis(sz, nz), zh = cic_axis(sz - 0.5, nz);
-  E.x = cic_component(f.grid[0], xh, y0, z0, nx, nxy, nall);
-  E.y = cic_component(f.grid[1], x0, yh, z0, nx, nxy, nall);
-  E.z = cic_component(f.grid[2], x0, y0, zh, nx, nxy, nall);
-  B.x = cic_component(f.grid[3], x0, yh, zh, nx, nxy, nall);
-  B.y = cic_component(f.grid[4], xh, y0, zh, nx, nxy, nall);
-  B.z = cic_component(f.grid[5], xh, yh, z0, nx, nxy, nall);
+  E.x = cic_component<PAIRED>(f.grid[0], xh, y0, z0, nx, nxy, nall);
+  E.y = cic_component<PAIRED>(f.grid[1], x0, yh, z0, nx, nxy, nall);
+  E.z = cic_component<PAIRED>(f.grid[2], x0, y0, zh, nx, nxy, nall);
+  B.x = cic_component<PAIRED>(f.grid[3], x0, yh, zh, nx, nxy, nall);
+  B.y = cic_component<PAIRED>(f.grid[4], xh, y0, zh, nx, nxy, nall);
+  B.z = cic_component<PAIRED>(f.grid[5], xh, yh, z0, nx, nxy, nall);
 }
 
 // ------------------------------------------------------------------------------------

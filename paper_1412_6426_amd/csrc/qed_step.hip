@@ -1203,7 +1203,7 @@ __global__ void __launch_bounds__(256) photon_kernel(StepArgs a) {
       if (live && !ok) block_count(bs, kPfNonfinite);
       wc.adv0 += __popcll(wave_ballot(ok));
       if (ok) {
-        if (FMODE == kFieldLocal) field_at_position(fld, a.inst[inst].amp, x, E, B);
+        if (FMODE == kFieldLocal) field_at_position<true>(fld, a.inst[inst].amp, x, E, B);
         const PhotonSetup st = photon_setup<MIXED>(a, E, B, kv, kabs, sbound, &bs);
         int k = 0;
         for (; k < st.nsub; ++k) {
@@ -1305,7 +1305,7 @@ __device__ __forceinline__ void exact_batch(const StepArgs& a, ExactCtx& c, Pair
     const double kabs = sqrt(dot(kv, kv));
     const uint64_t seed = a.inst[inst].seed;
     V3 E, B;
-    if (FMODE == kFieldLocal) field_at_position(c.fld, a.inst[inst].amp, x, E, B);
+    if (FMODE == kFieldLocal) field_at_position<true>(c.fld, a.inst[inst].amp, x, E, B);
     else instance_fields<FMODE>(a, inst, E, B);
     const PhotonSetup st = photon_setup<MIXED>(a, E, B, kv, kabs, c.bound, nullptr);
     int done = st.nsub;
