@@ -330,7 +330,8 @@ __device__ __forceinline__ CicAxis cic_axis(double s, int n) {
 // more take the plain path below.  (A plain 8-byte load at 4-byte alignment is split into
 // two by the compiler; the buffer load is not.)
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t cic_rsrc(const float* g, unsigned values) {
-  // word 3 0x00020000: raw 32-bit data format on gfx9-family targets
+  // word 3 0x00020000: raw 32-bit data format on gfx9-family targets.  The size (bytes)
+  // and the offsets below are unsigned 32-bit in the descriptor; the int casts keep the bits.
   return __builtin_amdgcn_make_buffer_rsrc((void*)g, 0, (int)(values * 4u), 0x00020000);
 }
 

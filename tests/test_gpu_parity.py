@@ -518,6 +518,41 @@ def test_mixed_precision_spectrum_and_pair_yield(orc):
             assert abs(pairs - p_or) <= 0.01 * p_or
 
 
+def test_yee_grid_mixed_precision_follows_fp64_oracle(orc):
+    """The mixed form on the 32^3 Yee-grid cascade (its own photon and lepton kernels, with
+    the same FP32 grid gathers) against the FP64 oracle: both draw the same numbers, so only
+    decisions within FP32 rounding of a threshold differ; emissions and live photons within
+    1%, the photon spectrum within L1 1e-2."""
+    w = W.standing_wave_grid(n=300, cells=32, capacity=200_000, lepton_capacity=20_000,
+                             steps=40, a0=2000.0, precision="mixed")
+    init = W.standing_wave_initial(300, seed=2)
+    _note(f"yee grid, mixed: {w.description}")
+    e = R.engine_single(w, init)
+    grid = R.YeeGrid(w)
+    f = R.field_of(w, grid=grid.g)
+    p = R.params_of(w)
+    os_ = oracle_stores(orc, init, w.capacity)
+    op = oracle_params(orc, w)
+    emitted_gpu = emitted_or = 0
+    e.set_step(0)
+    for n in range(w.n_steps):
+        vals = W.standing_wave_grid_values(w.field, w.t0 + n * w.dt)
+        grid.load_numpy(vals)
+        e.step(f, p)
+        torch.cuda.synchronize()
+        emitted_gpu += e.stats()["emitted"]
+        op.step = n
+        emitted_or += orc.step(os_, oracle_field(orc, w, grids=vals), op)["emitted"]
+    assert emitted_or > 1000
+    assert abs(emitted_gpu - emitted_or) <= 0.01 * emitted_or
+    h_or = _spectrum(os_[2].view())
+    h = _spectrum(e.read(0, 2))
+    assert abs(h.sum() - h_or.sum()) <= 0.01 * h_or.sum()
+    l1 = float(np.abs(h - h_or).sum() / h_or.sum())
+    _note(f"mixed yee: emitted {emitted_gpu} vs {emitted_or}, L1 {l1:.3e}")
+    assert l1 <= 1e-2
+
+
 def test_checkpoint_resume_is_bit_exact(orc):
     """A cascade stopped after 60 steps, its stores read back to the host (the checkpoint)
     and loaded into a fresh engine that continues from step 60, ends bit-identical to the
