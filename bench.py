@@ -329,8 +329,9 @@ def gpu_uniform_b(args):
     """Config 1: 10^4 electrons at gamma = 1000 across a uniform B with chi = 1, eight
     sub-steps each (dt = T_gyro/100), 100 steps, emission only, photons recorded and not
     pushed.  Steps run eagerly on one stream with HIP events around each step and around its
-    lepton kernel.  10^4 electrons fill 157 wavefronts: this run shows the step's fixed cost
-    per launch, not a bandwidth."""
+    lepton kernel, then again from the seeds as one captured step replayed 100 times.  10^4
+    electrons fill 157 wavefronts: these runs show the step's fixed cost per launch, not a
+    bandwidth."""
     import torch
     from paper_1412_6426_amd import runner as R
     from paper_1412_6426_amd import workloads as W
@@ -360,12 +361,42 @@ def gpu_uniform_b(args):
     lep_ms = sum(hip.elapsed_ms(evs[4 * n + 1], evs[4 * n + 2]) for n in range(K))
     hip.destroy(evs)
     photons = int(e.counts()[0, 2])
+    # The same K steps again from the seeds, as one captured step replayed K times (the
+    # step index lives on the device, so each replay is the next step): the launch
+    # overheads of the eight kernels no longer add up step by step.
+    params.events[0] = params.events[1] = None
+    e.reset_instances()
+    for s in range(3):
+        e.load(0, s, init[s])
+    e.set_step(0)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        e.step(field, params, stream=sp)
+    e.reset_instances()
+    for s in range(3):
+        e.load(0, s, init[s])
+    e.set_step(0)
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        t0.record(stream)
+        for _ in range(K):
+            g.replay()
+        t1.record(stream)
+    torch.cuda.synchronize()
+    graph_ms = t0.elapsed_time(t1)
+    photons_graph = int(e.counts()[0, 2])
+    del g
     lepton_steps = w.n_seed * K
     del e
     torch.cuda.empty_cache()
     return dict(workload=w.description, steps=K, lepton_steps=lepton_steps,
                 substeps=8 * lepton_steps, photons_emitted=photons,
+                photons_emitted_graph=photons_graph,
                 us_per_step=1e3 * step_ms / K, lepton_kernel_us_per_step=1e3 * lep_ms / K,
+                us_per_step_graph=1e3 * graph_ms / K,
+                lepton_steps_per_s_graph=lepton_steps / (graph_ms / 1e3),
                 lepton_steps_per_s=lepton_steps / (step_ms / 1e3),
                 lepton_kernel_gbs=(LEPTON_STEP_BYTES * lepton_steps + EMISSION_BYTES * photons)
                 / (lep_ms / 1e3) / 1e9)
