@@ -206,7 +206,8 @@ typedef struct {
   int64_t dropped;              /* children not stored (capacity) */
   int64_t saturated;            /* decisions with probability >= 1 */
   int64_t near_threshold;       /* decisions with |r2 - P| < 1e-12 */
-  int64_t nsub_near_int;        /* dt/dt_q within 1e-12 (relative) of an integer */
+  int64_t nsub_near_int;        /* dt/dt_q within 1e-12 (relative) of an integer, at the
+                                   step start or when a sub-step is checked for refinement */
   int64_t nsub_clamped;         /* n_sub capped at QED_NSUB_MAX */
   int64_t nonfinite;            /* NaN/Inf met in chi, rates or momenta */
   int64_t substeps;             /* particle sub-steps executed */
@@ -217,12 +218,25 @@ typedef struct {
   int64_t deferred;             /* children with time left in their birth step that wait
                                    for the next step: generation G + 1, or children whose
                                    wavefront's arena share was full */
-  double photon_energy;         /* sum of w * eps of the emitted photons */
-  double max_p_emit;            /* largest evaluated emission probability */
-  double max_p_pair;            /* largest evaluated pair probability */
-  int64_t nsub_hist[QED_NSUB_HIST];          /* particles alive at the step start per n_sub
-                                                (leptons; last bin: >= 31) */
-  int64_t photon_hist[QED_SPECTRUM_BINS];    /* emitted photons per log10(eps) bin */
+  int64_t nsub_refined;         /* lepton sub-steps taken again at half the length: Sec. IV.H
+                                   wants every sub-interval to satisfy Eq. (29), and a lepton's
+                                   effective field can grow within the step (the field slows
+                                   it down, or it has radiated most of its energy), so a
+                                   sub-step of length h is kept only if h <= dt_q in the state
+                                   it ends in; otherwise the rest of the step is cut into
+                                   twice as many sub-steps of half the length (at most
+                                   QED_NSUB_MAX in all; a refinement beyond that is skipped
+                                   and counted in nsub_clamped) */
+  double photon_energy;         /* sum of w * eps over the emissions (every event, also those
+                                   whose photon a generator factor did not create) */
+  double max_p_emit;            /* largest emission probability evaluated */
+  double max_p_pair;            /* largest pair probability among the decisions that made a
+                                   pair (every probability >= 1 makes one) */
+  int64_t nsub_hist[QED_NSUB_HIST];          /* leptons alive at the step start per n_sub at
+                                                the step start (last bin: >= 31) */
+  int64_t photon_hist[QED_SPECTRUM_BINS];    /* emissions per photon-energy bin: bin b holds
+                                                floor(10 (log10(eps) + 8)) = b, eps = delta
+                                                gamma in m c^2, evaluated in FP64 */
   uint32_t status;              /* QED_STATUS_* bits */
   uint32_t reserved;
 } qed_stats;

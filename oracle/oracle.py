@@ -26,6 +26,7 @@ NO_PARENT = 0xFFFFFFFFFFFFFFFF
 TABLE_N = 4096
 U_LO, U_HI = -20.0, 7.0
 NSUB_HIST = 32
+SPECTRUM_BINS = 130
 ELECTRON, POSITRON, PHOTON = 0, 1, 2
 
 _dp = C.POINTER(C.c_double)
@@ -74,17 +75,21 @@ class OrSchwingerRecord(C.Structure):
 
 
 class OrStats(C.Structure):
-    _fields_ = [("emitted", C.c_int64), ("pairs", C.c_int64), ("dropped", C.c_int64),
+    _fields_ = [("n_start", C.c_int64 * 3), ("advanced", C.c_int64 * 3),
+                ("emitted", C.c_int64), ("pairs", C.c_int64), ("dropped", C.c_int64),
                 ("saturated", C.c_int64), ("near_threshold", C.c_int64),
                 ("nsub_near_int", C.c_int64), ("nsub_clamped", C.c_int64),
-                ("nonfinite", C.c_int64), ("substeps", C.c_int64),
+                ("nonfinite", C.c_int64), ("substeps", C.c_int64), ("nsub_refined", C.c_int64),
                 ("children_advanced", C.c_int64), ("deferred", C.c_int64),
                 ("photon_energy", C.c_double), ("max_p_emit", C.c_double),
-                ("max_p_pair", C.c_double), ("nsub_hist", C.c_int64 * NSUB_HIST)]
+                ("max_p_pair", C.c_double), ("nsub_hist", C.c_int64 * NSUB_HIST),
+                ("photon_hist", C.c_int64 * SPECTRUM_BINS)]
+    _arrays = ("n_start", "advanced", "nsub_hist", "photon_hist")
 
     def as_dict(self) -> Dict:
-        d = {name: getattr(self, name) for name, _ in self._fields_ if name != "nsub_hist"}
-        d["nsub_hist"] = list(self.nsub_hist)
+        d = {name: getattr(self, name) for name, _ in self._fields_ if name not in self._arrays}
+        for name in self._arrays:
+            d[name] = list(getattr(self, name))
         return d
 
 

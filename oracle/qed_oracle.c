@@ -460,7 +460,8 @@ static void or_note_decision(or_stats *s, double P, double r2, int is_pair) {
     return;
   }
   if (is_pair) {
-    if (P > s->max_p_pair) s->max_p_pair = P;
+    /* only decisions that made a pair: every probability >= 1 is among them */
+    if (r2 < P && P > s->max_p_pair) s->max_p_pair = P;
   } else {
     if (P > s->max_p_emit) s->max_p_emit = P;
   }
@@ -469,6 +470,10 @@ static void or_note_decision(or_stats *s, double P, double r2, int is_pair) {
 }
 
 static void or_stats_merge(or_stats *a, const or_stats *b) {
+  for (int i = 0; i < 3; ++i) {
+    a->n_start[i] += b->n_start[i];
+    a->advanced[i] += b->advanced[i];
+  }
   a->emitted += b->emitted;
   a->pairs += b->pairs;
   a->dropped += b->dropped;
@@ -478,12 +483,14 @@ static void or_stats_merge(or_stats *a, const or_stats *b) {
   a->nsub_clamped += b->nsub_clamped;
   a->nonfinite += b->nonfinite;
   a->substeps += b->substeps;
+  a->nsub_refined += b->nsub_refined;
   a->children_advanced += b->children_advanced;
   a->deferred += b->deferred;
   a->photon_energy += b->photon_energy;
   if (b->max_p_emit > a->max_p_emit) a->max_p_emit = b->max_p_emit;
   if (b->max_p_pair > a->max_p_pair) a->max_p_pair = b->max_p_pair;
   for (int i = 0; i < OR_NSUB_HIST; ++i) a->nsub_hist[i] += b->nsub_hist[i];
+  for (int i = 0; i < OR_SPECTRUM_BINS; ++i) a->photon_hist[i] += b->photon_hist[i];
 }
 
 static void or_lepton_advance(const or_tables *t, or_store *st, int species, int64_t j,
@@ -514,19 +521,49 @@ static void or_lepton_advance(const or_tables *t, or_store *st, int species, int
   if (!isfinite(chi)) s->nonfinite++;
   s->nsub_near_int += near_int;
   s->nsub_clamped += clamped;
-  if (!span->inherited) s->nsub_hist[nsub < OR_NSUB_HIST ? nsub : OR_NSUB_HIST - 1]++;
+  if (!span->inherited) {
+    s->nsub_hist[nsub < OR_NSUB_HIST ? nsub : OR_NSUB_HIST - 1]++;
+    s->advanced[species]++;
+  }
+  /* Sub-steps of length h, `left` of them still to go (the current one included).  Sec.
+   * IV.H asks every sub-interval to satisfy Eq. (29); the lepton's effective field can grow
+   * within the step (the field slows it down, or it has just radiated most of its energy), so
+   * a sub-step is kept only if h <= dt_q in the state it ends in, where its event is decided.
+   * Otherwise the rest of the step is cut into twice as many sub-steps of half the length and
+   * the sub-step is taken again from its start (at most OR_NSUB_MAX sub-steps in all). */
   double h = span->T / (double)nsub;
-  double dtfac = h * OR_ALPHA / p->eps_r;
+  const int refine = p->forced_substeps <= 0 && p->adaptive;
+  int left = nsub, k = 0;
   uint32_t nev = st->n_events ? st->n_events[j] : 0;
-  for (int k = 0; k < nsub; ++k) {
-    or_boris(mom, q, h, E, B);
-    gamma = sqrt(1.0 + mom[0] * mom[0] + mom[1] * mom[1] + mom[2] * mom[2]);
+  while (left > 0) {
+    double pn[3] = {mom[0], mom[1], mom[2]};
+    or_boris(pn, q, h, E, B);
+    double gn = sqrt(1.0 + pn[0] * pn[0] + pn[1] * pn[1] + pn[2] * pn[2]);
+    double chin = or_chi_lepton(pn, E, B, p->eps_r);
+    if (refine && chin > 0.0) {
+      double dtq = or_dtq_lepton(chin, gn, p->eps_r, p->kappa);
+      if (fabs(h / dtq - 1.0) <= 1e-12) s->nsub_near_int++;
+      if (h > dtq) {
+        if (k + 2 * left <= OR_NSUB_MAX) {
+          h *= 0.5;
+          left *= 2;
+          s->nsub_refined++;
+          continue;
+        }
+        s->nsub_clamped++;
+      }
+    }
+    for (int d = 0; d < 3; ++d) mom[d] = pn[d];
+    gamma = gn;
+    chi = chin;
     for (int d = 0; d < 3; ++d) x[d] += h * mom[d] / gamma;
-    chi = or_chi_lepton(mom, E, B, p->eps_r);
     s->substeps++;
+    const int kk = k++;
+    --left;
     if (!p->emission) continue;
+    double dtfac = h * OR_ALPHA / p->eps_r;
     double r1, r2;
-    or_draw(id, p->seed, p->step, k, &r1, &r2);
+    or_draw(id, p->seed, p->step, kk, &r1, &r2);
     double Pm = or_rate_modified(t, p->backend, r1, chi, gamma, dtfac);
     or_note_decision(s, Pm, r2, 0);
     if (r2 < Pm) {
@@ -546,13 +583,15 @@ static void or_lepton_advance(const or_tables *t, or_store *st, int species, int
       for (int d = 0; d < 3; ++d) mom[d] = mom[d] - c.p[d];
       nev++;
       s->photon_energy += st->w[j] * eps;
-      if (or_generator_runs(id, p->seed, p->step, k, 5, p->f_photon)) {
+      double bin = floor(10.0 * (log10(eps) + 8.0));
+      if (bin >= 0.0 && bin < (double)OR_SPECTRUM_BINS) s->photon_hist[(int)bin]++;
+      if (or_generator_runs(id, p->seed, p->step, kk, 5, p->f_photon)) {
         c.w = st->w[j] * or_generator_weight(p->f_photon);
-        c.id = or_child_id(id, p->seed, p->step, k, 1);
+        c.id = or_child_id(id, p->seed, p->step, kk, 1);
         c.parent = id;
-        c.birth = (uint32_t)(((uint64_t)(p->step + 1) << 14) | (uint32_t)k);
+        c.birth = (uint32_t)(((uint64_t)(p->step + 1) << 14) | (uint32_t)kk);
         c.species = 2;
-        c.tau = (double)(nsub - k - 1) * h;
+        c.tau = (double)(left) * h; /* the sub-steps after this one */
         for (int d = 0; d < 3; ++d) {
           c.E[d] = E[d];
           c.B[d] = B[d];
@@ -583,6 +622,7 @@ static void or_photon_advance(const or_tables *t, or_store *st, int64_t j, const
     s->nonfinite++;
     return;
   }
+  if (!span->inherited) s->advanced[2]++;
   double E[3], B[3];
   if (span->inherited) {
     for (int d = 0; d < 3; ++d) {
@@ -723,6 +763,7 @@ int or_step(const or_tables *t, or_store *st, const or_field *f, const or_params
             or_stats *s) {
   memset(s, 0, sizeof(*s));
   const int64_t n0[3] = {st[0].count, st[1].count, st[2].count};
+  for (int i = 0; i < 3; ++i) s->n_start[i] = n0[i];
   const double tn = p->t0 + (double)p->step * p->dt;
   const int G = p->same_step_generations > 0 ? p->same_step_generations : 0;
   const int photons = p->push_photons || p->pairs;

@@ -31,6 +31,7 @@ extern "C" {
 #define OR_NO_PARENT 0xFFFFFFFFFFFFFFFFull
 #define OR_NSUB_MAX 16383
 #define OR_NSUB_HIST 32
+#define OR_SPECTRUM_BINS 130 /* 10 bins per decade of eps / (m c^2) from 1e-8 */
 
 enum { OR_EXACT = 0, OR_TABLE = 1 };
 enum {
@@ -89,13 +90,24 @@ typedef struct {
 } or_params;
 
 typedef struct {
+  int64_t n_start[3];  /* slots of each store at the step start (removed photons included) */
+  int64_t advanced[3]; /* particles advanced from the step start: every lepton, and the photons
+                          that are alive and have k != 0 */
   int64_t emitted, pairs, dropped, saturated, near_threshold, nsub_near_int, nsub_clamped,
       nonfinite, substeps;
+  int64_t nsub_refined;      /* lepton sub-steps taken again at half the length (Sec. IV.H:
+                                their length broke Eq. (29) in the state they ended in) */
   int64_t children_advanced; /* children advanced in their birth step (tau > 0) */
   int64_t deferred;          /* children of generation G + 1 created with tau > 0 (dropped ones
                                 included), left for the next step */
-  double photon_energy, max_p_emit, max_p_pair;
-  int64_t nsub_hist[OR_NSUB_HIST];
+  double photon_energy;      /* sum of w eps over the emissions (every event, Sec. VI) */
+  double max_p_emit;         /* largest emission probability evaluated */
+  double max_p_pair;         /* largest pair probability among the decisions that made a pair
+                                (every probability >= 1 makes one, so this holds the largest
+                                such) */
+  int64_t nsub_hist[OR_NSUB_HIST];       /* leptons alive at the step start by n_sub */
+  int64_t photon_hist[OR_SPECTRUM_BINS]; /* emissions by photon energy: bin b holds
+                                            floor(10 (log10(eps) + 8)) = b, eps in m c^2 */
 } or_stats;
 
 /* counter-based generator (Salmon et al., SC'11) */

@@ -263,6 +263,12 @@ __device__ __forceinline__ double substep_ratio_lepton(double dt, double chi, do
   const double r = chi / gamma;
   return dt * cbrt(r * r) * inv_lep_scale;  // inv_lep_scale = 1/(kappa 28 pi eps_r)
 }
+// (h / (kappa 28 pi eps_r))^3: a sub-step of length h satisfies Eq. (29) in a state of
+// (chi, gamma) iff this times chi^2 is at most gamma^2 (no cube root on the sub-step path).
+__device__ __forceinline__ double substep_cube(double h, double inv_lep_scale) {
+  const double r = h * inv_lep_scale;
+  return r * r * r;
+}
 // dt / dt_q for photons: dt_q = kappa 130 (2 pi eps_r) |k| / chi_g (Eq. (33)).
 __device__ __forceinline__ double substep_ratio_photon(double dt, double chi_g, double kabs,
                                                        double inv_pho_scale) {

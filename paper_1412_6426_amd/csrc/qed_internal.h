@@ -32,8 +32,10 @@ enum PartialField : int {
   kPfPairs,     // pairs created by the generation kernel (its kPfEvents are photons)
   kPfChildren,  // children advanced in their birth step
   kPfDeferred,  // children with time left in the step that wait for the next step
+  kPfRefined,   // lepton sub-steps taken again at half the length
   kPfEnergy,  // double bits
-  kPfMaxP,    // double bits
+  kPfMaxP,    // double bits: largest probability (emission; pairs in the photon kernels)
+  kPfMaxQ,    // double bits: largest pair probability of the generation kernel
   kPfNsub,    // QED_NSUB_HIST words
   kPfHist = kPfNsub + QED_NSUB_HIST,  // QED_SPECTRUM_BINS words
   kPfCount = kPfHist + QED_SPECTRUM_BINS

@@ -282,6 +282,15 @@ __global__ void schwinger_clear_kernel(qed_schwinger_record* rec, const qed_inst
   *rec = r;
 }
 
+// Reservations raise an instance's count past its capacity when pairs are dropped; bring
+// every lepton count back to the capacity so that whatever reads the counts next (thinning,
+// the caller, the next step) sees only slots that hold particles.
+__global__ void schwinger_clamp_kernel(qed_instance* inst, int n_inst) {
+  for (int i = (int)threadIdx.x; i < n_inst; i += (int)blockDim.x)
+    for (int sp = 0; sp < 2; ++sp)
+      if (inst[i].count[sp] > inst[i].capacity[sp]) inst[i].count[sp] = inst[i].capacity[sp];
+}
+
 }  // namespace
 
 hipError_t launch_schwinger(const qed_stores& st, const float* const grid[3], const int n[3],
@@ -313,6 +322,7 @@ hipError_t launch_schwinger(const qed_stores& st, const float* const grid[3], co
   hipLaunchKernelGGL(schwinger_clear_kernel, dim3(1), dim3(64), 0, s, rec, a.inst, a.n_inst,
                      a.cells);
   hipLaunchKernelGGL(schwinger_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(schwinger_clamp_kernel, dim3(1), dim3(256), 0, s, a.inst, a.n_inst);
   return hipGetLastError();
 }
 

@@ -161,7 +161,7 @@ __global__ void __launch_bounds__(256) reduce_kernel(StepArgs a) {
       kind == 0 ? a.lep_part : (kind == 1 ? a.pho_part : (kind == 2 ? a.ex_part : a.gen_part));
   const unsigned long long* col = part + (size_t)f * kMaxGridBlocks;
   qed_stats* st = a.stats;
-  if (f == kPfEnergy || f == kPfMaxP) {
+  if (f == kPfEnergy || f == kPfMaxP || f == kPfMaxQ) {
     double v = 0.0;
     for (int b = lane; b < G; b += 64) {
       const double x = __longlong_as_double((long long)col[b]);
@@ -176,7 +176,7 @@ __global__ void __launch_bounds__(256) reduce_kernel(StepArgs a) {
       if (f == kPfEnergy) {
         if (!pho) atomicAdd(&st->photon_energy, v);
       } else {
-        atomic_max_nonneg(pho ? &st->max_p_pair : &st->max_p_emit, v);
+        atomic_max_nonneg((pho || f == kPfMaxQ) ? &st->max_p_pair : &st->max_p_emit, v);
       }
     }
     return;
@@ -204,6 +204,7 @@ __global__ void __launch_bounds__(256) reduce_kernel(StepArgs a) {
     case kPfPairs: stats_add(&st->pairs, v); break;
     case kPfChildren: stats_add(&st->children_advanced, v); break;
     case kPfDeferred: stats_add(&st->deferred, v); break;
+    case kPfRefined: stats_add(&st->nsub_refined, v); break;
     default:
       if (f >= kPfNsub && f < kPfNsub + QED_NSUB_HIST)
         stats_add(&st->nsub_hist[f - kPfNsub], v);
@@ -252,12 +253,14 @@ struct LaneCounters {
   int early = 0, subs = 0;
   double energy = 0.0, maxp = 0.0;
 
-  __device__ __forceinline__ void note(double P, double r2) {
+  // One decision r2 < P.  `fold`: P counts for the largest probability of the step (every
+  // emission decision; only the pair decisions that make a pair, which include every P >= 1).
+  __device__ __forceinline__ void note(double P, double r2, bool fold = true) {
     if (!isfinite(P)) {
       block_count(*bs, kPfNonfinite);
       return;
     }
-    maxp = fmax(maxp, P);
+    if (fold) maxp = fmax(maxp, P);
     if (P >= 1.0) block_count(*bs, kPfSaturated);
     if (fabs(r2 - P) < kNearThreshold) block_count(*bs, kPfNear);
   }
@@ -284,11 +287,32 @@ __device__ __forceinline__ double wave_max(double v) {
 // Workgroup-level partial stats in LDS.
 struct BlockStats {
   unsigned long long w[kPfCount];
-  double energy, maxp;
+  double energy, maxp, maxq;  // maxq: pair decisions of a kernel that also has emissions
 };
 
 __device__ __forceinline__ void block_count(BlockStats& bs, int field) {
   atomicAdd(&bs.w[field], 1ull);
+}
+
+// Sub-step refinement (Sec. IV.H asks every sub-interval to satisfy Eq. (29)): a sub-step of
+// length h that ends in the state (chi, gamma^2 = 1 + p2) is taken again at half the length
+// if h > dt_q there, i.e. if hs3 chi^2 > gamma^2 with hs3 = (h / (kappa 28 pi eps_r))^3 --
+// unless that would make more than QED_NSUB_MAX sub-steps (then it is kept and counted as
+// clamped).  h / dt_q within 1e-12 of 1 is counted with the near-integer sub-step ratios.
+__device__ __forceinline__ bool refine_substep(double hs3, double chi, double p2, double g,
+                                               double h, double inv_lep_scale, int k, int left,
+                                               BlockStats& bs) {
+  const double lhs = hs3 * (chi * chi), rhs = 1.0 + p2;
+  if (fabs(lhs - rhs) <= 4e-12 * rhs &&
+      fabs(substep_ratio_lepton(h, chi, g, inv_lep_scale) - 1.0) <= 1e-12)
+    block_count(bs, kPfNearInt);
+  if (!(lhs > rhs)) return false;
+  if (k + 2 * left > QED_NSUB_MAX) {
+    block_count(bs, kPfClamped);
+    return false;
+  }
+  block_count(bs, kPfRefined);
+  return true;
 }
 
 __device__ __forceinline__ void block_stats_init(BlockStats& bs) {
@@ -296,15 +320,19 @@ __device__ __forceinline__ void block_stats_init(BlockStats& bs) {
   if (threadIdx.x == 0) {
     bs.energy = 0.0;
     bs.maxp = 0.0;
+    bs.maxq = 0.0;
   }
 }
 
-// Wave totals of the counters into the workgroup's LDS record.
-__device__ void wave_to_block(BlockStats& bs, const LaneCounters& c, const WaveCounters& wc) {
+// Wave totals of the counters into the workgroup's LDS record; `pc` holds the pair decisions
+// of a kernel that also makes emission decisions (their largest probability is kept apart).
+__device__ void wave_to_block(BlockStats& bs, const LaneCounters& c, const WaveCounters& wc,
+                              const LaneCounters* pc = nullptr) {
   const long long early = wave_sum((long long)c.early);
   const long long subs = wave_sum((long long)c.subs);
   const double en = wave_sum(c.energy);
   const double mp = wave_max(c.maxp);
+  const double mq = pc ? wave_max(pc->maxp) : 0.0;
   if (lane_id() == 0) {
     const long long vals[10] = {wc.substeps + subs, wc.events, wc.adv0, wc.adv1,
                                 wc.wave_iters, wc.low_occ, early, wc.pairs, wc.children,
@@ -317,6 +345,9 @@ __device__ void wave_to_block(BlockStats& bs, const LaneCounters& c, const WaveC
     if (mp > 0.0)
       atomicMax(reinterpret_cast<unsigned long long*>(&bs.maxp),
                 (unsigned long long)__double_as_longlong(mp));
+    if (mq > 0.0)
+      atomicMax(reinterpret_cast<unsigned long long*>(&bs.maxq),
+                (unsigned long long)__double_as_longlong(mq));
   }
 }
 
@@ -326,6 +357,7 @@ __device__ __forceinline__ void block_stats_store(const BlockStats& bs, unsigned
     unsigned long long v = bs.w[i];
     if (i == kPfEnergy) v = (unsigned long long)__double_as_longlong(bs.energy);
     if (i == kPfMaxP) v = (unsigned long long)__double_as_longlong(bs.maxp);
+    if (i == kPfMaxQ) v = (unsigned long long)__double_as_longlong(bs.maxq);
     part[(size_t)i * kMaxGridBlocks + blockIdx.x] = v;
   }
 }
@@ -340,9 +372,10 @@ __device__ __forceinline__ void block_stats_accumulate(const BlockStats& bs,
     if (i == kPfEnergy) {
       v = (unsigned long long)__double_as_longlong(
           bs.energy + (first ? 0.0 : __longlong_as_double((long long)old)));
-    } else if (i == kPfMaxP) {
+    } else if (i == kPfMaxP || i == kPfMaxQ) {
+      const double m = i == kPfMaxP ? bs.maxp : bs.maxq;
       v = (unsigned long long)__double_as_longlong(
-          first ? bs.maxp : fmax(bs.maxp, __longlong_as_double((long long)old)));
+          first ? m : fmax(m, __longlong_as_double((long long)old)));
     } else {
       v = bs.w[i] + old;
     }
@@ -633,8 +666,10 @@ __device__ __forceinline__ bool emission_photon(const V3& p, double g, double de
   }
   const double eps = delta * g;
   f = eps / pabs;
-  const float lb = (__log10f((float)eps) + 8.0f) * 10.0f;
-  if (lb >= 0.0f && lb < (float)QED_SPECTRUM_BINS) atomicAdd(&bs.w[kPfHist + (int)lb], 1ull);
+  // bin floor(10 (log10 eps + 8)), in FP64 in both precisions (an emission is rare next to
+  // the sub-steps, and the bins then agree with an FP64 count of the same photons)
+  const double lb = floor(10.0 * (log10(eps) + 8.0));
+  if (lb >= 0.0 && lb < (double)QED_SPECTRUM_BINS) atomicAdd(&bs.w[kPfHist + (int)lb], 1ull);
   cnt.energy += wgt * eps;
   return true;
 }
@@ -796,13 +831,15 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
   ArenaCursor acur;
   ArenaTally tally;
 
-  // lane state
+  // lane state: sub-step k of the particle in `slot`, `left` sub-steps of length h to go
+  // (the current one included)
   long long slot = -1;
-  int inst = 0, sp = 0, k = 0, nsub = 0;
+  int inst = 0, sp = 0, k = 0, left = 0;
   V3 x{}, p{}, E{}, B{};
   uint64_t id = 0, seed = 0;
   uint32_t nev = 0;
-  double qh2 = 0.0, h = 0.0, dtfac = 0.0, wgt = 0.0;
+  double qh2 = 0.0, h = 0.0, dtfac = 0.0, wgt = 0.0, hs3 = 0.0;
+  const bool refine = a.forced <= 0 && a.adaptive;
 
   while (true) {
     // ---- refill idle lanes from the wavefront's share ----
@@ -837,18 +874,12 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
         // chi and the number of sub-steps, once per step from the step-start state
         const double g = sqrt(1.0 + dot(p, p));
         const double chi = chi_of(p, g, E, FMODE == kFieldE ? V3{0.0, 0.0, 0.0} : B, a.eps_r);
-        nsub = 1;
+        // (FP64 in both precisions: n_sub is no part of the FP32 rate evaluation)
+        int nsub = 1;
         if (a.forced > 0) {
           nsub = a.forced;
         } else if (a.adaptive && chi > 0.0) {
-          NsubInfo ni;
-          if (MIXED) {
-            const float r = (float)(chi / g);
-            const float ratio = (float)a.dt * cbrtf(r * r) * (float)a.inv_lep_scale;
-            ni = nsub_from_ratio((double)ratio);
-          } else {
-            ni = nsub_from_ratio(substep_ratio_lepton(a.dt, chi, g, a.inv_lep_scale));
-          }
+          const NsubInfo ni = nsub_from_ratio(substep_ratio_lepton(a.dt, chi, g, a.inv_lep_scale));
           nsub = ni.n;
           if (ni.near_int) block_count(bs, kPfNearInt);
           if (ni.clamped) block_count(bs, kPfClamped);
@@ -858,7 +889,9 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
         h = a.dt / (double)nsub;
         dtfac = h * a.dtfac_per_h;
         qh2 = (sp == QED_ELECTRON ? -0.5 : 0.5) * h;
+        hs3 = substep_cube(h, a.inv_lep_scale);
         k = 0;
+        left = nsub;
       }
       if (tc.species == QED_ELECTRON) wc.adv0 += take;
       else wc.adv1 += take;
@@ -869,23 +902,36 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
     if (act == 0) break;
     ++wc.wave_iters;
     wc.low_occ += (__popcll(act) < 32);
-    wc.substeps += __popcll(act);
 
     // ---- one sub-step: push, chi, emission decision (Sec. IV.G) ----
-    bool emit = false;
+    // A sub-step whose end state breaks Eq. (29) is taken again at half the length.
+    bool emit = false, redo = false;
     double f = 0.0, g = 1.0;
     if (slot >= 0) {
+      V3 pn = p;
       if (FMODE == kFieldE) {
         // B = 0: the Boris rotation is the identity and the push is p += q h E
-        p = {p.x + 2.0 * qh2 * E.x, p.y + 2.0 * qh2 * E.y, p.z + 2.0 * qh2 * E.z};
+        pn = {p.x + 2.0 * qh2 * E.x, p.y + 2.0 * qh2 * E.y, p.z + 2.0 * qh2 * E.z};
       } else {
-        boris(p, qh2, E, B);
+        boris(pn, qh2, E, B);
       }
-      g = sqrt(1.0 + dot(p, p));
-      const double hg = h / g;
-      x = {x.x + hg * p.x, x.y + hg * p.y, x.z + hg * p.z};
-      const double chi = chi_of(p, g, E, FMODE == kFieldE ? V3{0.0, 0.0, 0.0} : B, a.eps_r);
-      if (a.emission) {
+      const double p2 = dot(pn, pn);
+      g = sqrt(1.0 + p2);
+      const double chi = chi_of(pn, g, E, FMODE == kFieldE ? V3{0.0, 0.0, 0.0} : B, a.eps_r);
+      if (refine && chi > 0.0)
+        redo = refine_substep(hs3, chi, p2, g, h, a.inv_lep_scale, k, left, bs);
+      if (redo) {
+        h *= 0.5;
+        qh2 *= 0.5;
+        dtfac *= 0.5;
+        hs3 *= 0.125;
+        left *= 2;
+      } else {
+        p = pn;
+        const double hg = h / g;
+        x = {x.x + hg * p.x, x.y + hg * p.y, x.z + hg * p.z};
+      }
+      if (!redo && a.emission) {
         const uint4 o = draw_words(id, seed, step, (uint32_t)k, kDraw);
         double delta;
         emit = emission_decision<MIXED>(tab, ser64, ser32, o, chi, g, dtfac, cnt, delta);
@@ -900,6 +946,7 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
     // With a generator factor f_g (Sec. VI) the photon of an event is created with
     // probability 1 / f_g and carries f_g times the lepton's weight; the recoil below
     // happens at every event.
+    wc.substeps += __popcll(wave_ballot(slot >= 0 && !redo));
     bool child = emit;
     if (EXT && emit && a.fg_photon > 1.0)
       child = generator_runs(id, seed, step, (uint32_t)k, kGenPhoton, a.inv_fg_photon);
@@ -925,13 +972,13 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
         pa.parent[r] = id;
         pa.sub[r] = (unsigned)k;
         pa.inst[r] = (unsigned)inst;
-        if (ss) record_same_step<FMODE>(pa, r, (double)(nsub - k - 1) * h, E, B);
+        if (ss) record_same_step<FMODE>(pa, r, (double)(left - 1) * h, E, B);
       }
     } else if (em) {
       const int n_new = __popcll(em);
       wc.events += n_new;
       // reserved directly in the stores: not advanced in this step
-      if (ss) wc.deferred += __popcll(wave_ballot(child && k < nsub - 1));
+      if (ss) wc.deferred += __popcll(wave_ballot(child && left > 1));
       if (staged + n_new > kStageCap) {
         flush_stage(a, sg, staged, cnt);
         staged = 0;
@@ -975,7 +1022,7 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
     }
 
     // ---- lanes whose particle has done all its sub-steps write back and go idle ----
-    if (slot >= 0 && ++k == nsub) {
+    if (slot >= 0 && !redo && (++k, --left == 0)) {
       LEPTON_COL(x, sp)[slot] = x.x;
       LEPTON_COL(y, sp)[slot] = x.y;
       LEPTON_COL(z, sp)[slot] = x.z;
@@ -1103,7 +1150,7 @@ __device__ __forceinline__ bool pair_decision(const StepArgs& a, const Series64&
     const float omd = 1.0f - r1;
     const float z = (2.0f / 3.0f) / ((float)chi * r1 * omd);
     const float P = (float)pref * pair_bracket32(a.tables->bc32, s32, z, r1 / omd + omd / r1);
-    cnt.note((double)P, (double)r2);
+    cnt.note((double)P, (double)r2, r2 < P);
     *r1out = (double)r1;
     return r2 < P;
   }
@@ -1111,7 +1158,7 @@ __device__ __forceinline__ bool pair_decision(const StepArgs& a, const Series64&
   const double omd = 1.0 - r1;
   const double z = (2.0 / 3.0) / (chi * r1 * omd);
   const double P = pref * pair_bracket64(a.tables->bc64, s64, z, r1 / omd + omd / r1);
-  cnt.note(P, r2);
+  cnt.note(P, r2, r2 < P);
   *r1out = r1;
   return r2 < P;
 }
@@ -1756,11 +1803,12 @@ __device__ __forceinline__ void gen_lepton_phase(const StepArgs& a, const GenArg
   GenStream st;
   st.init(A, gw.wid, V, true);
   long long slot = -1;
-  int sp = 0, inst = 0, nsub = 0, k = 0;
+  int sp = 0, inst = 0, left = 0, k = 0;
   V3 x{}, p{}, E{}, B{};
   uint64_t id = 0, seed = 0;
-  double wgt = 0.0, h = 0.0, dtfac = 0.0, qh2 = 0.0;
+  double wgt = 0.0, h = 0.0, dtfac = 0.0, qh2 = 0.0, hs3 = 0.0;
   uint32_t nev = 0;
+  const bool refine = a.forced <= 0 && a.adaptive;
   while (true) {
     // ---- refill idle lanes ----
     uint64_t freem = wave_ballot(slot < 0);
@@ -1789,18 +1837,12 @@ __device__ __forceinline__ void gen_lepton_phase(const StepArgs& a, const GenArg
           inherited_fields<FMODE>(a, A, r, inst, E, B);
           const double g = sqrt(1.0 + dot(p, p));
           const double chi = chi_of(p, g, E, FMODE == kFieldE ? V3{0.0, 0.0, 0.0} : B, a.eps_r);
-          nsub = 1;
+          int nsub = 1;
           if (a.forced > 0) {
             nsub = a.forced;
           } else if (a.adaptive && chi > 0.0) {
-            NsubInfo ni;
-            if (MIXED) {
-              const float rr = (float)(chi / g);
-              const float ratio = (float)tau * cbrtf(rr * rr) * (float)a.inv_lep_scale;
-              ni = nsub_from_ratio((double)ratio);
-            } else {
-              ni = nsub_from_ratio(substep_ratio_lepton(tau, chi, g, a.inv_lep_scale));
-            }
+            const NsubInfo ni =
+                nsub_from_ratio(substep_ratio_lepton(tau, chi, g, a.inv_lep_scale));
             nsub = ni.n;
             if (ni.near_int) block_count(bs, kPfNearInt);
             if (ni.clamped) block_count(bs, kPfClamped);
@@ -1809,7 +1851,9 @@ __device__ __forceinline__ void gen_lepton_phase(const StepArgs& a, const GenArg
           h = tau / (double)nsub;
           dtfac = h * a.dtfac_per_h;
           qh2 = (sp == QED_ELECTRON ? -0.5 : 0.5) * h;
+          hs3 = substep_cube(h, a.inv_lep_scale);
           k = 0;
+          left = nsub;
           slot = sl;
         }
       }
@@ -1818,21 +1862,34 @@ __device__ __forceinline__ void gen_lepton_phase(const StepArgs& a, const GenArg
     }
     if (wave_ballot(slot >= 0) == 0) break;
 
-    // ---- one sub-step ----
-    bool emit = false;
+    // ---- one sub-step (taken again at half the length if its end state breaks Eq. (29)) ----
+    bool emit = false, redo = false;
     double f = 0.0;
     if (slot >= 0) {
+      V3 pn = p;
       if (FMODE == kFieldE) {
-        p = {p.x + 2.0 * qh2 * E.x, p.y + 2.0 * qh2 * E.y, p.z + 2.0 * qh2 * E.z};
+        pn = {p.x + 2.0 * qh2 * E.x, p.y + 2.0 * qh2 * E.y, p.z + 2.0 * qh2 * E.z};
       } else {
-        boris(p, qh2, E, B);
+        boris(pn, qh2, E, B);
       }
-      const double g = sqrt(1.0 + dot(p, p));
-      const double hg = h / g;
-      x = {x.x + hg * p.x, x.y + hg * p.y, x.z + hg * p.z};
-      const double chi = chi_of(p, g, E, FMODE == kFieldE ? V3{0.0, 0.0, 0.0} : B, a.eps_r);
-      ++cnt.subs;
-      if (a.emission) {
+      const double p2 = dot(pn, pn);
+      const double g = sqrt(1.0 + p2);
+      const double chi = chi_of(pn, g, E, FMODE == kFieldE ? V3{0.0, 0.0, 0.0} : B, a.eps_r);
+      if (refine && chi > 0.0)
+        redo = refine_substep(hs3, chi, p2, g, h, a.inv_lep_scale, k, left, bs);
+      if (redo) {
+        h *= 0.5;
+        qh2 *= 0.5;
+        dtfac *= 0.5;
+        hs3 *= 0.125;
+        left *= 2;
+      } else {
+        p = pn;
+        const double hg = h / g;
+        x = {x.x + hg * p.x, x.y + hg * p.y, x.z + hg * p.z};
+        ++cnt.subs;
+      }
+      if (!redo && a.emission) {
         const uint4 o = draw_words(id, seed, step, (uint32_t)k, kDraw);
         double delta;
         emit = emission_decision<MIXED>(tab, ser64, ser32, o, chi, g, dtfac, cnt, delta);
@@ -1850,7 +1907,7 @@ __device__ __forceinline__ void gen_lepton_phase(const StepArgs& a, const GenArg
       const int n_new = __popcll(em);
       wc.events += n_new;
       const double cw = wgt * a.fg_photon;
-      const bool later = child && k < nsub - 1;  // the photon has time left in the step
+      const bool later = child && left > 1;  // the photon has time left in the step
       ArenaSpan span;
       if (O.waves > 0 && arena_reserve(O, gw.wid, gw.cp, n_new, span)) {
         gw.tp.add(O, gw.wid, em, child, inst);
@@ -1866,7 +1923,7 @@ __device__ __forceinline__ void gen_lepton_phase(const StepArgs& a, const GenArg
           O.parent[rr] = id;
           O.sub[rr] = (unsigned)k;
           O.inst[rr] = (unsigned)inst;
-          record_same_step<FMODE>(O, rr, (double)(nsub - k - 1) * h, E, B);
+          record_same_step<FMODE>(O, rr, (double)(left - 1) * h, E, B);
         }
         if (q.last) wc.deferred += __popcll(wave_ballot(later));
       } else {
@@ -1891,7 +1948,7 @@ __device__ __forceinline__ void gen_lepton_phase(const StepArgs& a, const GenArg
       // recoil: the lepton keeps p - k (momentum conservation, Sec. IV.F)
       p = {p.x - f * p.x, p.y - f * p.y, p.z - f * p.z};
     }
-    if (slot >= 0 && ++k == nsub) {
+    if (slot >= 0 && !redo && (++k, --left == 0)) {
       LEPTON_COL(x, sp)[slot] = x.x;
       LEPTON_COL(y, sp)[slot] = x.y;
       LEPTON_COL(z, sp)[slot] = x.z;
@@ -2083,7 +2140,7 @@ __global__ void __launch_bounds__(256) gen_kernel(StepArgs a, GenArgs q) {
   const int V = (int)gridDim.x * (int)(blockDim.x >> 6);
   GenWave gw;
   gw.wid = wave_index();
-  LaneCounters cnt, pcnt;  // pcnt: pair decisions (their largest P is not reduced)
+  LaneCounters cnt, pcnt;  // pcnt: pair decisions
   cnt.bs = &bs;
   pcnt.bs = &bs;
   WaveCounters wc;
@@ -2098,7 +2155,7 @@ __global__ void __launch_bounds__(256) gen_kernel(StepArgs a, GenArgs q) {
     gw.tq.flush(q.oqa, gw.wid);
     if (lane == 0) q.oqa.nrec[gw.wid] = (unsigned)gw.cq.n;
   }
-  wave_to_block(bs, cnt, wc);
+  wave_to_block(bs, cnt, wc, &pcnt);
   __syncthreads();
   block_stats_accumulate(bs, a.gen_part, q.pass == 1);
 }

@@ -106,7 +106,9 @@ __global__ void __launch_bounds__(kThinThreads) thin_count_kernel(ThinArgs a) {
   __shared__ double sw[kThinThreads / 64];
   const int i = blockIdx.y, b = blockIdx.x;
   const qed_instance& I = a.inst[i];
-  const long long n = I.count[a.species];
+  // a count beyond the segment (left by an append that dropped) covers only its capacity
+  long long n = I.count[a.species];
+  n = n < 0 ? 0 : (n > I.capacity[a.species] ? I.capacity[a.species] : n);
   long long live = 0;
   double w = 0.0;
   if (n > a.trigger) {

@@ -77,7 +77,8 @@ class qed_stats(C.Structure):
                 ("nsub_clamped", C.c_int64), ("nonfinite", C.c_int64), ("substeps", C.c_int64),
                 ("wave_iters", C.c_int64), ("low_occupancy_iters", C.c_int64),
                 ("early_out", C.c_int64), ("children_advanced", C.c_int64),
-                ("deferred", C.c_int64), ("photon_energy", C.c_double),
+                ("deferred", C.c_int64), ("nsub_refined", C.c_int64),
+                ("photon_energy", C.c_double),
                 ("max_p_emit", C.c_double), ("max_p_pair", C.c_double),
                 ("nsub_hist", C.c_int64 * QED_NSUB_HIST),
                 ("photon_hist", C.c_int64 * QED_SPECTRUM_BINS),

@@ -91,23 +91,25 @@ def test_schwinger_matches_oracle(orc):
 
 
 def test_schwinger_instances_draw_their_own_pairs(orc):
-    """Three instances (seeds 2, 3, 4) on the same grid; the second is frozen, the third
-    has room for only ten pairs (drops counted)."""
+    """Three instances (seeds 2, 4, 3) on the same grid; the second has room for only ten
+    pairs (drops counted, its counts brought back to its capacity, so the instance after it
+    keeps its segment), the third is frozen."""
     grids = _grids(2)
     f, keep = _field(grids)
     ofld = orc.Field(kind=orc.FIELD_YEE, grid=grids, dx=(DX, DX, DX), origin=(-1.0, 0.5, 2.0))
     dt = 400.0
-    e = _engine([100_000, 100_000, 10], [2, 3, 4])
-    e.set_frozen(1)
+    e = _engine([100_000, 10, 100_000], [2, 4, 3])
+    e.set_frozen(2)
     e.set_step(5)
     e.schwinger(f, dt, 1.0)
     torch.cuda.synchronize()
     r = e.schwinger_record()
     inst = e.instances()
     want_pairs = want_drop = want_cells = 0
-    for i, (seed, cap) in enumerate(((2, 100_000), (3, 100_000), (4, 10))):
-        if i == 1:
-            assert inst[1]["count"][:2] == [0, 0]
+    assert inst[1]["count"][:2] == [10, 10]  # clamped to the capacity after the drops
+    for i, (seed, cap) in enumerate(((2, 100_000), (4, 10), (3, 100_000))):
+        if i == 2:
+            assert inst[2]["count"][:2] == [0, 0]
             continue
         ost = _oracle_stores(orc, cap)
         o = orc.schwinger(ost, ofld, dt, 1.0, 1.0, seed=seed, step=5)
@@ -116,7 +118,7 @@ def test_schwinger_instances_draw_their_own_pairs(orc):
         want_cells += o["cells"]
         for s in range(2):
             got = e.read(i, s)
-            if i == 2:
+            if i == 1:
                 # the store keeps 10 of the instance's pairs (which ones depends on the order
                 # of the reservations; the oracle keeps the first 10 in cell order): they are
                 # a subset of all the pairs the oracle makes with room for them, field for field

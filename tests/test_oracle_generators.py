@@ -45,7 +45,7 @@ def test_modified_generator_reproduces_spectrum(orc):
     zmax, pval = _check_bins(obs, exp, n)
     assert zmax < 3.0, f"worst bin {zmax:.2f} sigma"
     assert pval > 1e-3
-    # negative control: the reading delta = r1 (L416's wording) would put the accepted r1
+    # negative control: the reading delta = r1 (the generator's text in Sec. IV.G) would put the accepted r1
     # values, i.e. delta^(1/3), into the spectrum; that fails by a wide margin
     obs_bad, _ = np.histogram(np.cbrt(deltas), bins=edges)
     zbad, _ = _check_bins(obs_bad, exp, n)

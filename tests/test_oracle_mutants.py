@@ -42,7 +42,7 @@ MUTANTS = [
      "exp(-OR_PI / e)", "exp(-OR_PI * e)",
      ["tests/test_oracle_schwinger.py"]),
     ("children left one sub-step too much of the step",
-     "c.tau = (double)(nsub - k - 1) * h;", "c.tau = (double)(nsub - k) * h;",
+     "c.tau = (double)(left) * h;", "c.tau = (double)(left + 1) * h;",
      ["tests/test_oracle_same_step.py::test_photon_children_move_through_the_rest_of_the_step"]),
     ("thinning factor inverted",
      "w_live / w_kept", "w_kept / w_live",
@@ -96,6 +96,18 @@ MUTANTS = [
     ("generator factor not raising the children's weight",
      "return fg > 1.0 ? fg : 1.0;", "return 1.0;",
      ["tests/test_oracle_generator_factor.py"]),
+    ("a sub-step kept although its end state breaks Eq. (29)",
+     "      if (h > dtq) {\n", "      if (0 && h > dtq) {\n",
+     ["tests/test_oracle_stats.py::test_slowed_leptons_refine_their_substeps"]),
+    ("refined sub-steps that do not add up to the step",
+     "          left *= 2;", "          left *= 3;",
+     ["tests/test_oracle_stats.py::test_slowed_leptons_refine_their_substeps"]),
+    ("photon-energy histogram in natural logarithms",
+     "floor(10.0 * (log10(eps) + 8.0))", "floor(10.0 * (log(eps) + 8.0))",
+     ["tests/test_oracle_stats.py::test_photon_histogram_and_energy_match_the_emitted_photons"]),
+    ("largest pair probability taken over every decision",
+     "if (r2 < P && P > s->max_p_pair)", "if (P > s->max_p_pair)",
+     ["tests/test_oracle_stats.py::test_largest_pair_probability_is_that_of_a_pair_made"]),
 ]
 
 
