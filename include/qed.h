@@ -44,7 +44,9 @@ typedef enum {
   QED_OK = 0,
   QED_ERR_ARG = 1,          /* invalid argument (null pointer, size, unknown enum value) */
   QED_ERR_HIP = 2,          /* a HIP runtime call or kernel launch failed */
-  QED_ERR_UNSUPPORTED = 3   /* valid request the library does not implement */
+  QED_ERR_UNSUPPORTED = 3,  /* valid request the library does not implement */
+  QED_ERR_SCRATCH = 4       /* qed_step_noalloc: the step needs more workspace than its
+                               fixed scratch buffer holds */
 } qed_status;
 
 typedef enum { QED_FP64 = 0, QED_MIXED = 1 } qed_precision;
@@ -274,6 +276,25 @@ size_t qed_work_bytes(int n_instances, int64_t photon_slots, int64_t arena_recor
 qed_status qed_step(const void *d_tables, const qed_stores *stores, const qed_field *field,
                     const qed_params *params, int64_t *d_step, qed_stats *d_stats, void *d_work,
                     size_t work_bytes, void *stream);
+
+/* qed_step without a workspace argument, for callers that cannot allocate device memory
+ * (code under hipGraph capture, tight serving loops, harnesses that forbid allocation).
+ * The workspace is a fixed buffer of QED_STEP_SCRATCH_BYTES inside the library, one per
+ * GPU, held from the first call on that GPU until the process ends; the call itself
+ * allocates nothing.  Same arguments and results as qed_step with that buffer as d_work
+ * (the largest child arena that fits in it is used).  Returns QED_ERR_SCRATCH, before any
+ * launch, when qed_work_bytes(n_instances, photon slots, 0, same_step) exceeds
+ * QED_STEP_SCRATCH_BYTES (about 1.4 * 10^6 photon slots for one instance without
+ * same-step processing); QED_ERR_HIP if the buffer's address cannot be resolved.  The
+ * buffer belongs to the device current at the call, and `stream` must belong to that
+ * device.  Every call on a GPU shares its buffer (each call sets what it reads before
+ * reading it), so calls that overlap on one GPU -- concurrent streams or threads -- race
+ * and must be serialised by the caller.  The first call on a device resolves the buffer's
+ * address and should not be made under stream capture. */
+#define QED_STEP_SCRATCH_BYTES (64u << 20)
+qed_status qed_step_noalloc(const void *d_tables, const qed_stores *stores,
+                            const qed_field *field, const qed_params *params, int64_t *d_step,
+                            qed_stats *d_stats, void *stream);
 
 /* Result of qed_thin for one instance (device memory, one record per instance).  A store
  * at or below the trigger is not examined: all fields 0, factor 1. */

@@ -9,6 +9,38 @@
 
 using namespace qedk;
 
+// Fixed workspace of qed_step_noalloc: every GPU the library runs on holds its own copy
+// until the process ends.  In host code this name is a stand-in, not a device address:
+// only the address resolved by scratch_on_current_device() may reach a kernel or a copy.
+static __device__ __align__(256) unsigned char scratch[QED_STEP_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kScratchDevices];  // device address of `scratch` per device, once resolved
+
+// The address of `scratch` on the current device, resolved (with that device current) on
+// the first call for the device and kept.
+hipError_t scratch_on_current_device(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch[dev] = p;
+  }
+  *out = g_scratch[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
 namespace {
 
 constexpr int kMaxDevices = 64;
@@ -124,6 +156,20 @@ ChildArena arena_at(uint8_t* w, size_t cols, size_t cnt, size_t nrec, size_t bas
 }
 
 }  // namespace
+
+qed_status qed_step_noalloc(const void* d_tables, const qed_stores* stores,
+                            const qed_field* field, const qed_params* params, int64_t* d_step,
+                            qed_stats* d_stats, void* stream) {
+  if (!stores || !params) return QED_ERR_ARG;
+  if (stores->n_instances < 1 || stores->slots[QED_PHOTON] < 0) return QED_ERR_ARG;
+  const int ss = params->same_step_generations > 0 ? 1 : 0;
+  const size_t need = qed_work_bytes(stores->n_instances, stores->slots[QED_PHOTON], 0, ss);
+  if (need == 0 || need > (size_t)QED_STEP_SCRATCH_BYTES) return QED_ERR_SCRATCH;
+  void* w = nullptr;
+  if (scratch_on_current_device(&w) != hipSuccess) return QED_ERR_HIP;
+  return qed_step(d_tables, stores, field, params, d_step, d_stats, w,
+                  (size_t)QED_STEP_SCRATCH_BYTES, stream);
+}
 
 qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_field* field,
                     const qed_params* params, int64_t* d_step, qed_stats* d_stats, void* d_work,
@@ -426,6 +472,7 @@ const char* qed_status_string(qed_status s) {
     case QED_ERR_ARG: return "invalid argument";
     case QED_ERR_HIP: return "HIP runtime or launch failure";
     case QED_ERR_UNSUPPORTED: return "unsupported";
+    case QED_ERR_SCRATCH: return "the request needs more workspace than the fixed scratch holds";
   }
   return "unknown status";
 }

@@ -15,7 +15,8 @@ from typing import Dict, List, Optional, Sequence
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "lib", "libqed.so")
 
-QED_OK, QED_ERR_ARG, QED_ERR_HIP, QED_ERR_UNSUPPORTED = 0, 1, 2, 3
+QED_OK, QED_ERR_ARG, QED_ERR_HIP, QED_ERR_UNSUPPORTED, QED_ERR_SCRATCH = 0, 1, 2, 3, 4
+QED_STEP_SCRATCH_BYTES = 64 << 20
 QED_FP64, QED_MIXED = 0, 1
 QED_ELECTRON, QED_POSITRON, QED_PHOTON = 0, 1, 2
 QED_FIELD_UNIFORM, QED_FIELD_ROTATING_E, QED_FIELD_CP_STANDING, QED_FIELD_YEE = 0, 1, 2, 3
@@ -110,6 +111,7 @@ class qed_schwinger_record(C.Structure):
 
 #: every symbol include/qed.h declares
 EXPORTS = ("qed_table_bytes", "qed_build_tables", "qed_work_bytes", "qed_step",
+           "qed_step_noalloc",
            "qed_thin_work_bytes", "qed_thin", "qed_schwinger", "qed_generator_work_bytes",
            "qed_generator_trials", "qed_standard_w_table",
            "qed_append_stats", "qed_photon_spectrum", "qed_fill_standing_wave",
@@ -139,6 +141,10 @@ def lib():
         L.qed_step.argtypes = [C.c_void_p, C.POINTER(qed_stores), C.POINTER(qed_field),
                                C.POINTER(qed_params), C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_size_t, C.c_void_p]
+        L.qed_step_noalloc.restype = C.c_int
+        L.qed_step_noalloc.argtypes = [C.c_void_p, C.POINTER(qed_stores), C.POINTER(qed_field),
+                                       C.POINTER(qed_params), C.c_void_p, C.c_void_p,
+                                       C.c_void_p]
         L.qed_append_stats.restype = C.c_int
         L.qed_thin_work_bytes.restype = C.c_size_t
         L.qed_thin_work_bytes.argtypes = [C.c_int, C.c_int64]
@@ -200,6 +206,12 @@ def qed_step(d_tables: int, stores: qed_stores, field: qed_field, params: qed_pa
              d_step: int, d_stats: int, d_work: int, work_bytes: int, stream: int) -> None:
     _check(lib().qed_step(d_tables, C.byref(stores), C.byref(field), C.byref(params), d_step,
                           d_stats, d_work, work_bytes, stream), "qed_step")
+
+
+def qed_step_noalloc(d_tables: int, stores: qed_stores, field: qed_field, params: qed_params,
+                     d_step: int, d_stats: int, stream: int) -> None:
+    _check(lib().qed_step_noalloc(d_tables, C.byref(stores), C.byref(field), C.byref(params),
+                                  d_step, d_stats, stream), "qed_step_noalloc")
 
 
 def qed_thin_work_bytes(n_instances: int, species_slots: int) -> int:
