@@ -11,17 +11,26 @@ particle-step count stops growing.
 
 Each GPU job runs three times from the same seeds: an untimed tuning run that picks the
 launch shape (work-chunk size, persistent grid) per size class of the live count, the
-timed run (one captured step graph per chosen shape, replayed step by step), and an eager
-run with HIP events around the lepton and photon kernels.
+timed run (one captured step graph per chosen shape, replayed for every step of the job),
+and an eager run with HIP events around the lepton and photon kernels of every step.
 
-Prints one JSON line: particle-steps/s over the timed steps, the roofline of the dominant
-kernel (algorithmic bytes / its event-timed duration vs 8 TB/s), the same run in mixed
-precision with its photon-spectrum L1 distance and pair yield against the FP64 run, the
-batched ensemble (64 rotating-field cascades, a0 log-spaced over 500-3000, 10^3-10^5 seeds
-each, 2 periods, 2*10^8 slots split evenly) in mixed precision and in FP64, the
-standing-wave cascade on a 256^3 Yee grid (field fill timed apart), the rotating-field
-cascade carried past its capacity by thinning, and the FP64 CPU oracle's rate on a bounded
-sample of the rotating-field workload on this host.
+`--steps K` times K steps of the 600-step job, the middle step of each of K equal parts,
+with HIP events around each of them inside the timed run (the other steps replay untimed
+between them); `value` is their particle-steps over their summed time, and the config lists
+the steps.  Without --steps every step is timed.  The whole job's time and rate are in the
+config too.  The roofline is taken over every launch of the dominant kernel in the eager
+run.
+
+Prints one JSON line: the headline and its roofline, and a short summary per further leg:
+the same job in mixed precision with its photon-spectrum L1 distance and pair yield against
+the FP64 job, the batched ensemble (64 rotating-field cascades, a0 log-spaced over
+500-3000, 10^3-10^5 seeds each, 2 periods, 2*10^8 slots split evenly) as full jobs in mixed
+precision and in FP64 with the same comparison, the standing-wave cascade on a 256^3 Yee
+grid (field fill timed apart), the rotating-field cascade carried past its capacity by
+thinning, the Sec. VII shower and avalanche, config 1, Schwinger pairs, the three emission
+generators, and the FP64 CPU oracle's rate on a bounded sample of the rotating-field
+workload on this host.  Each leg's full record goes to stderr as a `bench-detail <leg>
+<json>` line.
 
 HBM traffic of the dominant kernel comes from the rocprofv3 counter summary committed
 under profiles/ (FETCH_SIZE and WRITE_SIZE scaled by the same counters' reading for a copy
@@ -110,13 +119,24 @@ def make_job(kind, args, precision):
     return w, e, reload
 
 
-def gpu_run(args, precision, kind="rotating", thin=None, fg=None):
-    """One job three times from the same seeds: a tuning run that picks the launch shape
-    per size class (untimed), K steps replayed from one captured graph per chosen shape
-    and timed as a whole (value), and K eager steps with HIP events around the lepton and
-    photon kernels (per-kernel durations for the roofline).  The three runs compute the
-    same thing.  thin = (trigger, target): qed_thin on the photon store after every step
-    (timed with the step).  fg = (f_photon, f_pair): the generator factors of Sec. VI."""
+def sampled_steps(n_steps, k):
+    """The steps timed for the headline: the middle step of each of k equal parts of the
+    job (all of them when k is None or at least the job's length)."""
+    if k is None or k >= n_steps:
+        return list(range(n_steps))
+    k = max(int(k), 1)
+    return sorted({int((i + 0.5) * n_steps / k) for i in range(k)})
+
+
+def gpu_run(args, precision, kind="rotating", thin=None, fg=None, sample=None):
+    """One job (every step of it) three times from the same seeds: a tuning run that picks
+    the launch shape per size class (untimed); the timed run, one captured graph per chosen
+    shape replayed step by step, with HIP events around the whole job and around each step
+    of `sample` (the steps sampled_steps() picks; None: every step); and an eager run with
+    HIP events around the lepton and photon kernels of every step (per-kernel durations for
+    the roofline).  The three runs compute the same thing.  thin = (trigger, target):
+    qed_thin on the photon store after every step (timed with the step).  fg = (f_photon,
+    f_pair): the generator factors of Sec. VI."""
     import numpy as np
     import torch
     from paper_1412_6426_amd import autotune as AT
@@ -129,7 +149,8 @@ def gpu_run(args, precision, kind="rotating", thin=None, fg=None):
     params = R.params_of(w, freeze_on_drop=1, tile=args.tile, grid_blocks=args.grid_blocks)
     if fg is not None:
         params.f_photon, params.f_pair = fg
-    K = args.steps if args.steps is not None else w.n_steps
+    K = w.n_steps
+    timed = sampled_steps(K, sample)
     stream = torch.cuda.Stream()
     sp = stream.cuda_stream
     log = torch.zeros(K * e.stats_buf.numel(), dtype=torch.uint8, device=e.device)
@@ -172,18 +193,28 @@ def gpu_run(args, precision, kind="rotating", thin=None, fg=None):
             Q.qed_append_stats(e.stats_buf.data_ptr(), log.data_ptr(), K, cnt.data_ptr(), sp)
         graphs[shape] = g
     plan = [graphs[s] for s in shape_of]
+    hip = HipEvents()
+    jev = hip.create(2)
+    sev = hip.create(2 * len(timed))
+    slot_of = {n: i for i, n in enumerate(timed)}
     restart()
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
     wall0 = time.perf_counter()
     with torch.cuda.stream(stream):  # replay() launches on the current stream
-        t_start.record(stream)
-        for g in plan:
+        hip.lib.hipEventRecord(C.c_void_p(jev[0]), C.c_void_p(sp))
+        for n, g in enumerate(plan):
+            i = slot_of.get(n)
+            if i is not None:
+                hip.lib.hipEventRecord(C.c_void_p(sev[2 * i]), C.c_void_p(sp))
             g.replay()
-        t_end.record(stream)
+            if i is not None:
+                hip.lib.hipEventRecord(C.c_void_p(sev[2 * i + 1]), C.c_void_p(sp))
+        hip.lib.hipEventRecord(C.c_void_p(jev[1]), C.c_void_p(sp))
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
-    ms = t_start.elapsed_time(t_end)
+    job_ms = hip.elapsed_ms(jev[0], jev[1])
+    step_ms = [hip.elapsed_ms(sev[2 * i], sev[2 * i + 1]) for i in range(len(timed))]
+    hip.destroy(jev)
+    hip.destroy(sev)
     recs = _stats_records(log.cpu().numpy().tobytes(), K)
     counts = e.counts().tolist()
     hist = None
@@ -197,7 +228,6 @@ def gpu_run(args, precision, kind="rotating", thin=None, fg=None):
 
     # ---- per-kernel durations: the same K steps eagerly, HIP events on our stream ----
     restart()
-    hip = HipEvents()
     evs = hip.create(4 * K)
     tev = hip.create(2 * K) if thin is not None else []
     with torch.cuda.stream(stream):
@@ -212,6 +242,8 @@ def gpu_run(args, precision, kind="rotating", thin=None, fg=None):
                 hip.lib.hipEventRecord(C.c_void_p(tev[2 * n + 1]), C.c_void_p(sp))
             Q.qed_append_stats(e.stats_buf.data_ptr(), log.data_ptr(), K, cnt.data_ptr(), sp)
     torch.cuda.synchronize()
+    for j in range(4):
+        params.events[j] = None
     lep_t = [hip.elapsed_ms(evs[4 * n], evs[4 * n + 1]) for n in range(K)]
     pho_t = [hip.elapsed_ms(evs[4 * n + 2], evs[4 * n + 3]) for n in range(K)]
     thin_t = [hip.elapsed_ms(tev[2 * n], tev[2 * n + 1]) for n in range(K)] if thin else []
@@ -221,6 +253,7 @@ def gpu_run(args, precision, kind="rotating", thin=None, fg=None):
     same = all(a.emitted == b.emitted and a.pairs == b.pairs and
                list(a.advanced) == list(b.advanced) for a, b in zip(recs, recs2))
 
+    step_ps = [int(sum(r.advanced)) for r in recs]
     adv = [sum(r.advanced[s] for r in recs) for s in range(3)]
     dead_slots = sum(r.n_start[2] - r.advanced[2] for r in recs)
     emitted = sum(r.emitted for r in recs)
@@ -229,21 +262,28 @@ def gpu_run(args, precision, kind="rotating", thin=None, fg=None):
     pho_bytes = PHOTON_STEP_BYTES * adv[2] + DEAD_SLOT_BYTES * dead_slots
     active = sum(1 for r in recs if sum(r.advanced) > 0)
     first_drop = next((r.step for r in recs if r.dropped > 0), None)
+    sampled_ps = sum(step_ps[n] for n in timed)
     out = dict(
-        workload=w.description, ms=ms, wall_s=wall, steps=K, active_steps=active,
-        first_drop_step=first_drop,
-        particle_steps=int(sum(adv)), advanced=[int(a) for a in adv], emitted=int(emitted),
+        workload=w.description, steps=K, active_steps=active, first_drop_step=first_drop,
+        job_ms=job_ms, wall_s=wall, particle_steps=int(sum(adv)),
+        value_job=sum(adv) / (job_ms / 1e3) if job_ms > 0 else 0.0,
+        timed_steps=timed, timed_ms=sum(step_ms), timed_particle_steps=int(sampled_ps),
+        value=sampled_ps / (sum(step_ms) / 1e3) if sum(step_ms) > 0 else 0.0,
+        advanced=[int(a) for a in adv], emitted=int(emitted),
         pairs=int(pairs), lep_ms=sum(lep_t), pho_ms=sum(pho_t), thin_ms=sum(thin_t),
-        lep_bytes=lep_bytes,
+        launches=K, lep_bytes=lep_bytes,
         pho_bytes=pho_bytes, final_counts=[int(sum(c[s] for c in counts)) for s in range(3)],
         eager_matches_graph=bool(same),
         schedule=[dict(from_step=k, tile=t, grid_blocks=g)
                   for k, (t, g) in zip(sched.steps, sched.shapes)],
         substeps=int(sum(r.substeps for r in recs)),
+        nsub_refined=int(sum(r.nsub_refined for r in recs)),
         low_occupancy_iters=int(sum(r.low_occupancy_iters for r in recs)),
         wave_iters=int(sum(r.wave_iters for r in recs)),
         near_threshold=int(sum(r.near_threshold for r in recs)),
         saturated=int(sum(r.saturated for r in recs)),
+        max_p_emit=float(max((r.max_p_emit for r in recs), default=0.0)),
+        max_p_pair=float(max((r.max_p_pair for r in recs), default=0.0)),
         early_out=int(sum(r.early_out for r in recs)),
         dropped=int(sum(r.dropped for r in recs)),
         # per step, for the precision comparison
@@ -545,11 +585,16 @@ def precision_compare(r64, rmx):
     }
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary, if the kernel
-    source is unchanged since the counters were taken."""
+def traffic_summary_path(dom):
+    """The counter summary of the dominant kernel on the rotating-field cascade."""
+    return os.path.join(ROOT, "profiles", f"{dom}_kernel_rotating_cascade_hbm_counters.md")
+
+
+def measured_traffic(dom, kernel):
+    """HBM bytes per launch of `kernel` (its full template name) from the committed counter
+    summary, if the kernel source is unchanged since the counters were taken."""
     try:
-        text = open(TRAFFIC_SUMMARY).read()
+        text = open(traffic_summary_path(dom)).read()
     except OSError:
         return None
     vals = {}
@@ -558,13 +603,28 @@ def measured_traffic(kernel):
             k, v = line[2:].split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
     from paper_1412_6426_amd.calib.profile_summary import source_digest
-    src = source_digest(KERNEL_SRC)
-    if vals.get("kernel") != kernel or vals.get("kernel_source_sha256") != src:
+    if vals.get("kernel") != kernel or vals.get("kernel_source_sha256") != source_digest():
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def kernel_name(dom, precision):
+    """Full template name of the rotating-field step kernel, as the profiler prints it."""
+    mixed = "true" if precision == "mixed" else "false"
+    return f"photon_kernel<{mixed}, 1>" if dom == "photon" else f"lepton_kernel<{mixed}, 1, false>"
+
+
+def detail(name, record):
+    """A leg's full record, on stderr (the JSON line on stdout keeps a summary)."""
+    def conv(v):
+        if hasattr(v, "tolist"):
+            return v.tolist()
+        return v
+    rec = {k: conv(v) for k, v in record.items()} if isinstance(record, dict) else record
+    print(f"bench-detail {name} " + json.dumps(rec, default=conv), file=sys.stderr, flush=True)
 
 
 def cpu_baseline(args):
@@ -795,7 +855,9 @@ def gpu_avalanche(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: 600)")
+    ap.add_argument("--steps", type=int, default=None,
+                    help="steps of the 600-step job timed for the headline, spread evenly "
+                         "over it (default: every step)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", choices=("f64", "mixed"), default="f64")
     ap.add_argument("--seeds", type=int, default=100_000)
@@ -875,7 +937,7 @@ def main():
         out = {}
         for prec in ("mixed", "f64"):
             rb = gpu_run(args, prec, kind="batched")
-            out[prec] = dict(value=rb["particle_steps"] / (rb["ms"] / 1e3), ms=rb["ms"],
+            out[prec] = dict(value=rb["value_job"], ms=rb["job_ms"],
                              lep_ms=rb["lep_ms"], pho_ms=rb["pho_ms"])
         print(json.dumps({"batched": out}), flush=True)
         return
@@ -884,23 +946,22 @@ def main():
         return
     print(f"bench: rotating-E cascade, {args.seeds} seeds, precision {args.precision}",
           file=sys.stderr, flush=True)
-    r = gpu_run(args, args.precision)
-    print(f"bench: {r['particle_steps']} particle-steps in {r['ms']:.1f} ms", file=sys.stderr,
-          flush=True)
-    secs = r["ms"] / 1e3
-    value = r["particle_steps"] / secs
+    r = gpu_run(args, args.precision, sample=args.steps)
+    nt = len(r["timed_steps"])
+    print(f"bench: {r['timed_particle_steps']} particle-steps in {r['timed_ms']:.1f} ms over "
+          f"{nt} timed steps; whole job {r['particle_steps']} in {r['job_ms']:.1f} ms",
+          file=sys.stderr, flush=True)
     dom, kbytes, kms, achieved = roofline_of(r)
-    launches = r["steps"]
-    # the rotating-field specialisation of the kernel, FP64 or mixed
-    traffic = measured_traffic(f"{dom}_kernel<{'true' if args.precision == 'mixed' else 'false'}, 1>")
+    launches = r["launches"]
+    traffic = measured_traffic(dom, kernel_name(dom, args.precision))
     line = {
         "metric": METRIC,
-        "value": value,
+        "value": r["value"],
         "unit": "particle-steps/s",
         "n_gpus": 1,
-        "steps": r["steps"],
+        "steps": nt,
         "warmup": args.warmup,
-        "ms_per_step": r["ms"] / r["steps"],
+        "ms_per_step": r["timed_ms"] / nt,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -909,96 +970,121 @@ def main():
         "config": {
             "workload": "rotating_e_cascade",
             "a0": args.a0, "lambda_um": 0.8, "seeds": args.seeds, "dt": "T/200",
-            "job_steps": 600, "capacity_per_species": args.capacity,
-            "precision": args.precision, "parallelism": "single GPU",
+            "capacity_per_species": args.capacity, "precision": args.precision,
+            "job_steps": r["steps"], "active_steps": r["active_steps"],
+            "first_drop_step": r["first_drop_step"],
+            "timed_steps": r["timed_steps"] if nt < r["steps"] else "all",
+            "timed_particle_steps": r["timed_particle_steps"],
+            "job_particle_steps": r["particle_steps"], "job_ms": round(r["job_ms"], 3),
+            "job_value": r["value_job"], "parallelism": "single GPU",
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": f"{dom}_kernel",
+            "kernel": kernel_name(dom, args.precision),
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "traffic_unit": "HBM bytes per launch (mean over the run's launches)",
+            "traffic_unit": "HBM bytes per launch",
             "algorithmic_bytes_per_launch": kbytes / launches,
             "avg_launch_us": kms * 1e3 / launches,
+            "launches": launches,
         },
-        "detail": {k: r[k] for k in ("active_steps", "first_drop_step", "particle_steps",
-                                     "advanced", "emitted", "pairs", "final_counts",
-                                     "lep_ms", "pho_ms", "substeps", "wave_iters",
-                                     "low_occupancy_iters", "near_threshold", "saturated",
-                                     "early_out", "eager_matches_graph", "schedule")},
     }
+    detail("rotating_e_cascade", {k: v for k, v in r.items() if not k.startswith("step_")})
+    line["detail"] = {k: r[k] for k in ("saturated", "max_p_emit", "max_p_pair",
+                                        "near_threshold", "nsub_refined", "dropped",
+                                        "eager_matches_graph")}
+    legs = {}
     if not args.no_mixed:
         other = "mixed" if args.precision == "f64" else "f64"
-        print(f"bench: the same run in {other}", file=sys.stderr, flush=True)
+        print(f"bench: the same job in {other}", file=sys.stderr, flush=True)
         m = gpu_run(args, other)
         r64, rmx = (r, m) if args.precision == "f64" else (m, r)
-        v64 = r64["particle_steps"] / (r64["ms"] / 1e3)
-        vmx = rmx["particle_steps"] / (rmx["ms"] / 1e3)
-        line["mixed_vs_f64"] = dict(
-            value_f64=v64, value_mixed=vmx, speedup_mixed=vmx / v64,
-            lep_ms_mixed=rmx["lep_ms"], pho_ms_mixed=rmx["pho_ms"],
-            **precision_compare(r64, rmx))
+        cmp_ = precision_compare(r64, rmx)
+        detail("mixed_vs_f64", dict(lep_ms_mixed=rmx["lep_ms"], pho_ms_mixed=rmx["pho_ms"],
+                                    lep_ms_f64=r64["lep_ms"], pho_ms_f64=r64["pho_ms"], **cmp_))
+        legs["mixed_vs_f64"] = dict(
+            value_f64=r64["value_job"], value_mixed=rmx["value_job"],
+            speedup=rmx["value_job"] / r64["value_job"],
+            spectrum_l1=cmp_["spectrum_l1_vs_f64"], pair_yield_rel=cmp_["pair_yield_rel_diff"],
+            steps_compared=cmp_["steps_compared"])
     if not args.no_batched:
-        # batched ensemble: 64 independent cascades in one step, mixed and FP64
+        # batched ensemble: 64 independent cascades in one step, mixed and FP64, full jobs
         b = {}
         for prec in ("mixed", "f64"):
             print(f"bench: batched ensemble, {prec}", file=sys.stderr, flush=True)
-            rb = gpu_run(args, prec, kind="batched")
-            bdom, bbytes, bms, bach = roofline_of(rb)
-            b[prec] = dict(
-                value=rb["particle_steps"] / (rb["ms"] / 1e3), ms=rb["ms"],
-                particle_steps=rb["particle_steps"], pairs=rb["pairs"], emitted=rb["emitted"],
-                dropped=rb["dropped"], lep_ms=rb["lep_ms"], pho_ms=rb["pho_ms"],
-                roofline={"kernel": f"{bdom}_kernel", "achieved": bach, "peak": HBM_PEAK_GBS,
-                          "unit": "GB/s", "frac": bach / HBM_PEAK_GBS},
-                schedule=rb["schedule"], eager_matches_graph=rb["eager_matches_graph"])
-        line["batched"] = dict(
-            workload=rb["workload"],
-            speedup_mixed_vs_f64=b["mixed"]["value"] / b["f64"]["value"], **b)
+            b[prec] = gpu_run(args, prec, kind="batched")
+        cmp_ = precision_compare(b["f64"], b["mixed"])
+        bdom, bbytes, bms, bach = roofline_of(b["mixed"])
+        for prec in ("mixed", "f64"):
+            detail(f"batched_{prec}", {k: v for k, v in b[prec].items()
+                                       if not k.startswith("step_")})
+        legs["batched"] = dict(
+            value_mixed=b["mixed"]["value_job"], value_f64=b["f64"]["value_job"],
+            speedup=b["mixed"]["value_job"] / b["f64"]["value_job"],
+            spectrum_l1=cmp_["spectrum_l1_vs_f64"], pair_yield_rel=cmp_["pair_yield_rel_diff"],
+            frac_mixed=bach / HBM_PEAK_GBS)
     if not args.no_thin:
         # the same cascade past the capacity: the photon store is thinned to 40% of its
         # slots whenever it holds more than 80% (global even redistribution)
         cap = args.capacity
         print("bench: rotating-E cascade with thinning", file=sys.stderr, flush=True)
         rt = gpu_run(args, args.precision, thin=(int(0.8 * cap), int(0.4 * cap)))
-        line["thinned_cascade"] = dict(
-            value=rt["particle_steps"] / (rt["ms"] / 1e3), ms=rt["ms"], steps=rt["steps"],
-            particle_steps=rt["particle_steps"], dropped=rt["dropped"],
-            thin_ms=rt["thin_ms"], lep_ms=rt["lep_ms"], pho_ms=rt["pho_ms"],
-            final_counts=rt["final_counts"], pairs=rt["pairs"], emitted=rt["emitted"],
-            trigger=int(0.8 * cap), target=int(0.4 * cap),
-            eager_matches_graph=rt["eager_matches_graph"])
+        detail("thinned_cascade", {k: v for k, v in rt.items() if not k.startswith("step_")})
+        legs["thinned_cascade"] = dict(value=rt["value_job"], thin_ms=rt["thin_ms"],
+                                       dropped=rt["dropped"])
         # both cost controls of Sec. VI: photons created with probability 1/4 at four times
         # the weight, and the same thinning
         print("bench: rotating-E cascade with f_g = 4 for photons and thinning",
               file=sys.stderr, flush=True)
         rf = gpu_run(args, args.precision, thin=(int(0.8 * cap), int(0.4 * cap)),
                      fg=(4.0, 1.0))
-        line["generator_factor_cascade"] = dict(
-            value=rf["particle_steps"] / (rf["ms"] / 1e3), ms=rf["ms"], steps=rf["steps"],
-            particle_steps=rf["particle_steps"], dropped=rf["dropped"],
-            thin_ms=rf["thin_ms"], lep_ms=rf["lep_ms"], pho_ms=rf["pho_ms"],
-            final_counts=rf["final_counts"], pairs=rf["pairs"], emitted=rf["emitted"],
-            f_photon=4.0, f_pair=1.0, eager_matches_graph=rf["eager_matches_graph"])
+        detail("generator_factor_cascade",
+               {k: v for k, v in rf.items() if not k.startswith("step_")})
+        legs["generator_factor_cascade"] = dict(value=rf["value_job"], dropped=rf["dropped"])
     if not args.no_shower:
-        line["shower_time_step_invariance"] = gpu_shower(args)
+        sh = gpu_shower(args)
+        detail("shower_time_step_invariance", sh)
+        big = sh["large_dt_same_step"]
+        legs["shower"] = dict(speedup=big["speedup_vs_small_dt"], max_abs_z=big["max_abs_z"],
+                              saturated=big["saturated"])
     if not args.no_avalanche:
-        line["avalanche_time_step_invariance"] = gpu_avalanche(args)
+        av = gpu_avalanche(args)
+        detail("avalanche_time_step_invariance", av)
+        legs["avalanche"] = dict(
+            speedup=av["large_dt_same_step"]["speedup_vs_small_dt"],
+            growth_large=av["large_dt_same_step"].get("pair_growth_per_period"),
+            growth_small=av["small_dt"].get("pair_growth_per_period"),
+            saturated=av["large_dt_same_step"]["saturated"])
     if not args.no_yee:
         print("bench: standing-wave cascade on the Yee grid", file=sys.stderr, flush=True)
-        line["standing_wave_grid"] = gpu_run_yee(args, args.precision)
+        y = gpu_run_yee(args, args.precision)
+        detail("standing_wave_grid", y)
+        legs["standing_wave_grid"] = dict(
+            value=y["value"], step_ms=y["step_ms"],
+            lepton_frac=y["lepton_roofline_gbs"] / HBM_PEAK_GBS,
+            photon_frac=y["photon_roofline_gbs"] / HBM_PEAK_GBS, saturated=y["saturated"])
     if not args.no_uniform_b:
         print("bench: config 1, uniform B", file=sys.stderr, flush=True)
-        line["uniform_b"] = gpu_uniform_b(args)
+        u = gpu_uniform_b(args)
+        detail("uniform_b", u)
+        legs["uniform_b"] = dict(us_per_step_graph=u["us_per_step_graph"],
+                                 lepton_steps_per_s_graph=u["lepton_steps_per_s_graph"])
     if not args.no_schwinger:
         print("bench: Schwinger pairs on the Yee grid", file=sys.stderr, flush=True)
-        line["schwinger_grid"] = gpu_schwinger_grid(args)
+        sc = gpu_schwinger_grid(args)
+        detail("schwinger_grid", sc)
+        legs["schwinger_grid"] = dict(avg_launch_us=sc["avg_launch_us"],
+                                      frac=sc["roofline"]["frac"])
     if not args.no_generators:
         print("bench: the three emission generators", file=sys.stderr, flush=True)
-        line["generator_comparison"] = gpu_generator_comparison(args)
+        gc = gpu_generator_comparison(args)
+        detail("generator_comparison", gc)
+        legs["generator_comparison"] = {k: round(v["ms_per_launch"], 4)
+                                        for k, v in gc["generators"].items()}
+    line["legs"] = legs
     if not args.no_cpu_baseline:
         print("bench: oracle sample on the host", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(args)

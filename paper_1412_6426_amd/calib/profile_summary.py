@@ -1,11 +1,14 @@
 """Turn rocprofv3 output into the short text summaries kept under profiles/.
 
-    python -m paper_1412_6426_amd.calib.profile_summary trace DIR --out FILE --command CMD
+    python -m paper_1412_6426_amd.calib.profile_summary trace DIR --out FILE --command CMD \
+        [--window "NAME:START:END" ...]
         per-kernel dispatch count, total and average duration from a --kernel-trace run
-        (the rocpd database rocprofv3 writes, or its *kernel_stats.csv).
+        (the rocpd database rocprofv3 writes, or its *kernel_stats.csv); a window adds the
+        average over dispatches START..END-1 of kernel NAME, in the order they ran.
 
     python -m paper_1412_6426_amd.calib.profile_summary hbm --kernel NAME [--source FILE] \\
         --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR --out FILE --command CMD
+        [--window START:END]
         HBM bytes per launch of NAME from a FETCH_SIZE and a WRITE_SIZE pass, each scaled by
         the same counter's reading for lib/hbm_copy (800 MB read and 800 MB written per
         launch).  The summary records a sha256 of the kernel source and the headers it
@@ -55,11 +58,12 @@ def _dbs(d):
 
 
 def kernel_durations(d):
-    """{kernel: [durations ns]} from a kernel-trace output directory."""
+    """{kernel: [durations ns]} from a kernel-trace output directory, in the order the
+    dispatches started."""
     out = collections.defaultdict(list)
     for db in _dbs(d):
         c = sqlite3.connect(db)
-        for name, start, end in c.execute("select name, start, end from kernels"):
+        for name, start, end in c.execute("select name, start, end from kernels order by start"):
             out[_short(name)].append(end - start)
     if not out:
         for f in glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True):
@@ -81,9 +85,14 @@ def counter_per_dispatch(d, counter):
                 acc[(db, disp)] += value
                 names[(db, disp)] = _short(name)
     out = collections.defaultdict(list)
-    for key, v in acc.items():
-        out[names[key]].append(v)
+    for key in sorted(acc):  # dispatch order within each database
+        out[names[key]].append(acc[key])
     return out
+
+
+def _window(spec):
+    lo, hi = spec.split(":")
+    return int(lo), int(hi)
 
 
 def cmd_trace(a):
@@ -97,6 +106,13 @@ def cmd_trace(a):
         lines.append(f"| {k} | {len(v)} | {sum(v) / 1e6:.3f} | {statistics.mean(v) / 1e3:.2f} | "
                      f"{min(v) / 1e3:.2f} | {max(v) / 1e3:.2f} | {100 * sum(v) / total:.1f}% |")
     lines += ["", f"Sum of kernel time: {total / 1e6:.3f} ms."]
+    for spec in a.window or []:
+        name, lo, hi = spec.rsplit(":", 2)
+        v = durs.get(name, [])[int(lo):int(hi)]
+        if v:
+            lines += ["", f"- window: {name} dispatches {lo}..{int(hi) - 1} "
+                          f"({len(v)}): total {sum(v) / 1e6:.3f} ms, "
+                          f"avg {statistics.mean(v) / 1e3:.2f} us"]
     if a.note:
         lines += ["", a.note]
     open(a.out, "w").write("\n".join(lines) + "\n")
@@ -106,6 +122,9 @@ def cmd_trace(a):
 def cmd_hbm(a):
     f = counter_per_dispatch(a.fetch, "FETCH_SIZE")[a.kernel]
     w = counter_per_dispatch(a.write, "WRITE_SIZE")[a.kernel]
+    if a.window:
+        lo, hi = _window(a.window)
+        f, w = f[lo:hi], w[lo:hi]
     cf = counter_per_dispatch(a.copy_fetch, "FETCH_SIZE")["hbm_copy"]
     cw = counter_per_dispatch(a.copy_write, "WRITE_SIZE")["hbm_copy"]
     if not (f and w and cf and cw):
@@ -118,6 +137,7 @@ def cmd_hbm(a):
     lines = [f"# {a.title}", "", "Commands (from the repository root):", "", "```",
              a.command, "```", "",
              f"- kernel: {a.kernel}",
+             f"- window: {a.window or 'every dispatch'}",
              f"- kernel_source_sha256: {sha}",
              f"- dispatches_fetch_pass: {len(f)}",
              f"- dispatches_write_pass: {len(w)}",
@@ -168,6 +188,8 @@ def main():
     sub = ap.add_subparsers(dest="cmd", required=True)
     t = sub.add_parser("trace")
     t.add_argument("dir")
+    t.add_argument("--window", action="append",
+                   help="NAME:START:END, dispatches START..END-1 of kernel NAME")
     m = sub.add_parser("pmc")
     m.add_argument("dirs", nargs="+")
     m.add_argument("--kernel", required=True)
@@ -182,6 +204,7 @@ def main():
     h.add_argument("--write", required=True)
     h.add_argument("--copy-fetch", required=True)
     h.add_argument("--copy-write", required=True)
+    h.add_argument("--window", default=None, help="START:END, dispatches START..END-1")
     h.add_argument("--source", default=KERNEL_SRC,
                    help="kernel source whose digest (with the headers it includes) the summary records")
     a = ap.parse_args()

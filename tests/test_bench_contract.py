@@ -51,3 +51,19 @@ def test_roofline_picks_the_dominant_kernel():
     assert achieved == pytest.approx(6.6e11 / 0.150 / 1e9)
     r = dict(pho_ms=10.0, lep_ms=70.0, pho_bytes=1e10, lep_bytes=1e11)
     assert bench.roofline_of(r)[0] == "lepton"
+
+
+def test_timed_steps_spread_over_the_job():
+    s = bench.sampled_steps(600, 20)
+    assert s == [15 + 30 * i for i in range(20)]
+    assert bench.sampled_steps(600, None) == list(range(600))
+    assert bench.sampled_steps(600, 600) == list(range(600))
+    assert bench.sampled_steps(600, 1000) == list(range(600))
+    assert bench.sampled_steps(7, 3) == [1, 3, 5]
+    assert bench.sampled_steps(600, 0) == [300]
+
+
+def test_kernel_names_match_the_profiler():
+    assert bench.kernel_name("photon", "f64") == "photon_kernel<false, 1>"
+    assert bench.kernel_name("lepton", "f64") == "lepton_kernel<false, 1, false>"
+    assert bench.kernel_name("photon", "mixed") == "photon_kernel<true, 1>"
