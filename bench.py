@@ -173,19 +173,25 @@ def gpu_run(args, precision, kind="rotating", thin=None, fg=None, sample=None):
             thin_now()
     # ---- tuning run: launch shape per size class ----
     if args.no_tune:
-        sched = AT.Schedule(steps=[0], shapes=[(args.tile, args.grid_blocks)])
+        sched = AT.Schedule(steps=[0], shapes=[(args.tile, args.grid_blocks, 0)])
     else:
         restart()
-        cus = torch.cuda.get_device_properties(0).multi_processor_count
+        props = torch.cuda.get_device_properties(0)
+        cache = AT.TuneCache(args.tune_cache) if args.tune_cache else None
+        key = AT.TuneCache.key(getattr(props, "gcnArchName", "gpu"), precision, w.description)
         with torch.cuda.stream(stream):
-            sched = AT.tune_run(e, field, params, K, AT.default_candidates(cus),
-                                after_step=thin_now)
+            sched = AT.tune_run(e, field, params, K,
+                                AT.default_candidates(props.multi_processor_count),
+                                after_step=thin_now,
+                                known=cache.get(key) if cache else None)
+        if cache is not None:
+            cache.put(key, sched.choices)
     shape_of = [sched.shape_at(n) for n in range(K)]
 
     # ---- timed: one captured step (and its stats record) per shape, replayed K times ----
     graphs = {}
     for shape in sched.distinct():
-        params.tile, params.grid_blocks = shape
+        AT.apply_shape(e, params, shape)
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g, stream=stream):
             e.step(field, params, stream=sp)
@@ -232,7 +238,7 @@ def gpu_run(args, precision, kind="rotating", thin=None, fg=None, sample=None):
     tev = hip.create(2 * K) if thin is not None else []
     with torch.cuda.stream(stream):
         for n in range(K):
-            params.tile, params.grid_blocks = shape_of[n]
+            AT.apply_shape(e, params, shape_of[n])
             for j in range(4):
                 params.events[j] = evs[4 * n + j]
             e.step(field, params, stream=sp)
@@ -274,8 +280,8 @@ def gpu_run(args, precision, kind="rotating", thin=None, fg=None, sample=None):
         launches=K, lep_bytes=lep_bytes,
         pho_bytes=pho_bytes, final_counts=[int(sum(c[s] for c in counts)) for s in range(3)],
         eager_matches_graph=bool(same),
-        schedule=[dict(from_step=k, tile=t, grid_blocks=g)
-                  for k, (t, g) in zip(sched.steps, sched.shapes)],
+        schedule=[dict(from_step=k, tile=t, grid_blocks=g, arena_div=a)
+                  for k, (t, g, a) in zip(sched.steps, sched.shapes)],
         substeps=int(sum(r.substeps for r in recs)),
         nsub_refined=int(sum(r.nsub_refined for r in recs)),
         low_occupancy_iters=int(sum(r.low_occupancy_iters for r in recs)),
@@ -906,6 +912,9 @@ def main():
                     help="skip the comparison of the three emission generators")
     ap.add_argument("--generators-only", action="store_true",
                     help="run only the generator comparison and print its record (profiling)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON file of tuned shapes per (arch, precision, workload): read "
+                         "before tuning (known size classes are not tried again), written after")
     ap.add_argument("--no-tune", action="store_true",
                     help="use --tile / --grid-blocks for every step instead of tuning")
     args = ap.parse_args()

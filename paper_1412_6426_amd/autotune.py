@@ -1,38 +1,53 @@
-"""Launch-shape tuner for qed_step: work-chunk size (`tile`) and persistent grid.
+"""Launch tuner for qed_step: work-chunk size (`tile`), persistent grid and child-arena size.
 
-What a step decides does not depend on the launch shape (every draw and child id is keyed
-by the particle), only how fast it runs does, and that depends mostly on how many
-particles are alive.  The tuner therefore works inside a run of the real job:
+What a step decides does not depend on these (every draw and child id is keyed by the
+particle), only how fast it runs does, and that depends mostly on how many particles are
+alive.  The tuner therefore works inside a run of the real job:
 
 * the live count is split into size classes (a factor `class_factor` apart);
-* when the run enters a new class, the next steps cycle through the candidate shapes,
-  each step timed with HIP events around the whole qed_step on the engine's stream, and
-  the shape with the lowest time per particle-step becomes the class's choice;
-* the result is a schedule: (first step, shape) pairs.
+* when the run enters a new class, the next steps try the candidates, each step timed
+  around the whole qed_step on the engine's stream.  First the launch shapes (the
+  per-wavefront work queue's chunk size and the persistent grid) with the engine's own
+  arena; then, with the best of those, the child-arena sizes (records = photon slots /
+  divisor: the per-wavefront shares and pool the lepton and pair producers write their
+  children into before the ordered copy).  The lowest time per particle-step wins;
+* the result is a schedule: (first step, shape) pairs, shape = (tile, grid, arena divisor).
 
-A cascade is deterministic, so a second run of the same job from the same seeds reaches
-the same counts at the same steps and can replay the schedule without synchronising,
-for instance with one captured graph per shape.
+A cascade is deterministic, so a second run of the same job from the same seeds reaches the
+same counts at the same steps and can replay the schedule without synchronising, for
+instance with one captured graph per shape.  Choices can be kept in a JSON file keyed by
+(GPU architecture, precision, workload) and reused by later runs, which then skip the
+trials for the size classes they know.
 """
 from __future__ import annotations
 
 import ctypes as C
+import json
 import math
+import os
 from dataclasses import dataclass, field
-from typing import Dict, List, Optional, Sequence, Tuple
+from typing import Callable, Dict, List, Optional, Sequence, Tuple
 
 from . import qed as Q
 
-Shape = Tuple[int, int]  # (tile, grid_blocks); 0 = library default
+# (tile, grid_blocks, arena divisor); 0 = the library's or the engine's default
+Shape = Tuple[int, int, int]
 
 
 def default_candidates(cu_count: int) -> List[Shape]:
     """Chunks of 64..512 particles on the library's resident grid, and 128-particle chunks
     on smaller and larger grids."""
-    return [(64, 0), (128, 0), (256, 0), (512, 0), (128, 2 * cu_count), (128, 8 * cu_count)]
+    return [(64, 0, 0), (128, 0, 0), (256, 0, 0), (512, 0, 0), (128, 2 * cu_count, 0),
+            (128, 8 * cu_count, 0)]
 
 
-class _Events:
+# Child-arena sizes tried with the best launch shape: photon slots / divisor records.
+DEFAULT_ARENA_DIVISORS = (32, 8, 2)
+
+
+class HipTimer:
+    """HIP events around one step on a stream."""
+
     def __init__(self):
         self.lib = C.CDLL("libamdhip64.so")
         self.lib.hipEventCreate.argtypes = [C.POINTER(C.c_void_p)]
@@ -61,13 +76,14 @@ class _Events:
 
 @dataclass
 class Schedule:
-    """Launch shape per step: shapes[i] applies from steps[i] on."""
+    """Shape per step: shapes[i] applies from steps[i] on."""
     steps: List[int] = field(default_factory=list)
     shapes: List[Shape] = field(default_factory=list)
     trials: List[Dict] = field(default_factory=list)
+    choices: Dict[int, Shape] = field(default_factory=dict)  # size class -> shape
 
     def shape_at(self, n: int) -> Shape:
-        s = self.shapes[0] if self.shapes else (0, 0)
+        s = self.shapes[0] if self.shapes else (0, 0, 0)
         for k, sh in zip(self.steps, self.shapes):
             if n >= k:
                 s = sh
@@ -78,32 +94,91 @@ class Schedule:
         for s in self.shapes:
             if s not in out:
                 out.append(s)
-        return out or [(0, 0)]
+        return out or [(0, 0, 0)]
+
+
+class TuneCache:
+    """Size-class choices kept in a JSON file, keyed by (arch, precision, workload)."""
+
+    def __init__(self, path: str):
+        self.path = path
+        self.data: Dict[str, Dict[str, List[int]]] = {}
+        if os.path.exists(path):
+            with open(path) as f:
+                self.data = json.load(f)
+
+    @staticmethod
+    def key(arch: str, precision: str, workload: str) -> str:
+        return f"{arch}|{precision}|{workload}"
+
+    def get(self, key: str) -> Dict[int, Shape]:
+        return {int(c): tuple(s) for c, s in self.data.get(key, {}).items()}
+
+    def put(self, key: str, choices: Dict[int, Shape]):
+        self.data[key] = {str(c): list(s) for c, s in sorted(choices.items())}
+        tmp = self.path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(self.data, f, indent=1, sort_keys=True)
+        os.replace(tmp, self.path)
+
+
+def apply_shape(e, params: Q.qed_params, shape: Shape):
+    """Set the launch shape in the step parameters and the arena size on the engine."""
+    params.tile, params.grid_blocks = int(shape[0]), int(shape[1])
+    e.set_arena(int(shape[2]))
 
 
 def tune_run(e, field, params: Q.qed_params, n_steps: int, candidates: Sequence[Shape],
-             rounds: int = 2, class_factor: float = 4.0, min_live: int = 1 << 16,
-             stop_on_drop: bool = False, after_step=None) -> Schedule:
+             arena_divisors: Sequence[int] = DEFAULT_ARENA_DIVISORS, rounds: int = 2,
+             class_factor: float = 4.0, min_live: int = 1 << 16, stop_on_drop: bool = False,
+             after_step: Optional[Callable[[], None]] = None, timer=None,
+             known: Optional[Dict[int, Shape]] = None,
+             sync: Optional[Callable[[], None]] = None) -> Schedule:
     """Run n_steps steps of the job on engine `e`, tuning the shape per size class.
 
-    Below `min_live` live particles the library default shape is used untimed (those steps
-    are launch-bound).  The returned schedule gives every step the best shape of its size
-    class (trial steps included).  `after_step()`, if given, runs after every step (on the
-    engine's stream) as part of the job, for instance thinning.  `e` ends in the state
-    after the run."""
-    import torch
-
-    ev = _Events()
+    Below `min_live` live particles the default shape is used untimed (those steps are
+    launch-bound).  `known` holds choices for size classes from an earlier run (a
+    TuneCache); those classes are not tried again.  The returned schedule gives every step
+    the best shape of its size class (trial steps included), and its `choices` every class
+    chosen.  `after_step()`, if given, runs after every step (on the engine's stream) as
+    part of the job, for instance thinning.  `timer` times one step on a stream (HipTimer by
+    default); `sync` waits for the device at the end (torch.cuda.synchronize by default).
+    `e` ends in the state after the run."""
+    if sync is None:
+        import torch
+        sync = torch.cuda.synchronize
+    ev = timer if timer is not None else HipTimer()
     trials: List[Dict] = []
-    best: Dict[int, Shape] = {}
+    best: Dict[int, Shape] = dict(known or {})
     pending: List[Shape] = []
     timings: Dict[Shape, List[float]] = {}
+    phase = 0  # 0: launch shapes, 1: arena sizes
     cls_of_step: List[int] = []
     tuning: Optional[int] = None  # class whose trials are running
 
+    def fastest():
+        live = {s: v for s, v in timings.items() if v}
+        return min(live, key=lambda s: min(live[s])) if live else None
+
+    def start_phase(ph, base: Optional[Shape]):
+        nonlocal phase, pending, timings
+        phase = ph
+        if ph == 0:
+            cands = list(candidates)
+        else:
+            cands = [(base[0], base[1], d) for d in arena_divisors]
+            if base not in cands:
+                cands.append(base)
+        pending = [s for _ in range(rounds) for s in cands]
+        timings = {s: [] for s in cands}
+
     def settle(c):
-        if c is not None and c not in best and any(timings.values()):
-            best[c] = min(timings, key=lambda s: min(timings[s]) if timings[s] else math.inf)
+        """End the trials of class c: keep the best of what was timed."""
+        if c is None or c in best:
+            return
+        b = fastest()
+        if b is not None:
+            best[c] = b
 
     live = int(e.counts().sum())
     stream = e.stream
@@ -113,15 +188,14 @@ def tune_run(e, field, params: Q.qed_params, n_steps: int, candidates: Sequence[
         if cls >= 0 and cls not in best and cls != tuning:
             settle(tuning)  # a class left before its trials ended keeps its best so far
             tuning = cls
-            pending = [c for _ in range(rounds) for c in candidates]
-            timings = {c: [] for c in candidates}
+            start_phase(0, None)
         if cls < 0:
-            shape = (0, 0)
+            shape = (0, 0, 0)
         elif cls in best:
             shape = best[cls]
         else:
             shape = pending.pop(0)
-        params.tile, params.grid_blocks = shape
+        apply_shape(e, params, shape)
         ev.start(stream)
         e.step(field, params)
         ms = ev.stop_ms(stream)
@@ -133,18 +207,26 @@ def tune_run(e, field, params: Q.qed_params, n_steps: int, candidates: Sequence[
         if cls >= 0 and cls not in best:
             if done > 0:
                 timings[shape].append(ms / done)
-            trials.append(dict(step=n, cls=cls, tile=shape[0], grid=shape[1], ms=ms,
-                               particle_steps=done))
+            trials.append(dict(step=n, cls=cls, tile=shape[0], grid=shape[1],
+                               arena_div=shape[2], ms=ms, particle_steps=done))
             if not pending:
-                settle(cls)
+                if phase == 0:
+                    b = fastest()
+                    if b is None or not arena_divisors:
+                        settle(cls)
+                    else:
+                        start_phase(1, b)
+                else:
+                    settle(cls)
         if stop_on_drop and st["dropped"] > 0:
             break
     settle(tuning)
-    torch.cuda.synchronize()
-    ev.close()
-    sched = Schedule(trials=trials)
+    sync()
+    if timer is None:
+        ev.close()
+    sched = Schedule(trials=trials, choices=dict(best))
     for n, cls in enumerate(cls_of_step):
-        shape = best.get(cls, (0, 0)) if cls >= 0 else (0, 0)
+        shape = best.get(cls, (0, 0, 0)) if cls >= 0 else (0, 0, 0)
         if not sched.shapes or sched.shapes[-1] != shape:
             sched.steps.append(n)
             sched.shapes.append(shape)

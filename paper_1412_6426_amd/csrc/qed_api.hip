@@ -149,9 +149,10 @@ ChildArena arena_at(uint8_t* w, size_t cols, size_t cnt, size_t nrec, size_t bas
   A.next = reinterpret_cast<unsigned int*>(w + chain + 256 +
                                            ((sizeof(unsigned int) * kMaxWaves + 255) & ~(size_t)255));
   A.waves = waves;
-  A.per_wave = (pool ? cap / 2 : cap) / waves;
-  A.pool0 = A.per_wave * waves;
-  A.nchunks = (cap - A.pool0) / kArenaChunk;
+  const ArenaGeometry g = arena_geometry(cap, waves, pool);
+  A.per_wave = g.per_wave;
+  A.pool0 = g.pool0;
+  A.nchunks = g.nchunks;
   return A;
 }
 
@@ -309,8 +310,7 @@ qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_fi
   const int lep_waves = lep.grid * (block / 64);
   const int pho_waves = pho.grid * (block / 64);
   a.pho_waves = run_photons ? pho_waves : 0;
-  a.cand_per_wave = (long long)((stores->slots[QED_PHOTON] > 0 ? stores->slots[QED_PHOTON] : 1) +
-                                (long long)kMaxWaves * kCandSlack) / pho_waves;
+  a.cand_per_wave = cand_list_entries(stores->slots[QED_PHOTON], pho_waves);
   if (arena > 0) {
     const bool on = G > 0;
     // the lepton kernel continues in the pool only in its extended form (same-step

@@ -24,6 +24,13 @@ constexpr int kGenGridBlocks = 512;  // 2 wavefronts per SIMD on 256 CUs
 // Candidate entries per photon wavefront beyond its even share of the photon slots.
 constexpr int kCandSlack = 64;
 
+// Entries of each of `pho_waves` photon wavefronts' candidate lists: an even share of the
+// workspace's photon_slots + kMaxWaves kCandSlack entries (pho_waves <= kMaxWaves).
+inline long long cand_list_entries(long long photon_slots, int pho_waves) {
+  const long long slots = photon_slots > 0 ? photon_slots : 1;
+  return pho_waves > 0 ? (slots + (long long)kMaxWaves * kCandSlack) / pho_waves : 0;
+}
+
 // Per-workgroup partial stats: 64-bit words, stored field-major ([field][block]) so that
 // the finalize kernel reduces each field with coalesced loads.
 enum PartialField : int {
@@ -78,12 +85,28 @@ struct ChildArena {
   unsigned int* first;  // [waves]: a wavefront's first pool chunk
   unsigned int* next;   // [nchunks]: the chunk after this one in its wavefront's chain
   unsigned int* used;   // pool chunks handed out (zeroed before each producing kernel)
-  long long per_wave;   // share of each wavefront (a multiple of 64 records)
+  long long per_wave;   // share of each wavefront (records)
   long long pool0;      // first pool record (waves * per_wave)
   long long nchunks;    // pool chunks
   int waves;            // wavefronts of the producing kernel (row length of cnt); 0: arena off
 };
 constexpr long long kArenaChunk = 256;  // records per pool chunk (a multiple of 64)
+
+// How an arena of `cap` records is cut for `waves` producing wavefronts: with a pool, half
+// the records are the wavefronts' equal shares and the rest chunks of kArenaChunk records
+// taken on demand; without, all are shares.  Records [0, pool0) are the shares, the pool
+// chunks follow and end at pool0 + nchunks kArenaChunk <= cap.
+struct ArenaGeometry {
+  long long per_wave, pool0, nchunks;
+};
+inline ArenaGeometry arena_geometry(long long cap, int waves, bool pool) {
+  ArenaGeometry g{};
+  if (cap <= 0 || waves <= 0) return g;
+  g.per_wave = (pool ? cap / 2 : cap) / waves;
+  g.pool0 = g.per_wave * waves;
+  g.nchunks = (cap - g.pool0) / kArenaChunk;
+  return g;
+}
 
 // Upper bound of generations advanced in their birth step (qed_params.same_step_generations).
 constexpr int kMaxGenerations = 64;
@@ -110,7 +133,7 @@ struct WorkLayout {
   static WorkLayout make(int n_inst, long long photon_slots, long long arena_records,
                          bool same_step = false) {
     WorkLayout L{};
-    size_t off = sizeof(WorkHdr);
+    size_t off = (sizeof(WorkHdr) + 255) & ~(size_t)255;  // every region 256-byte aligned
     auto take = [&off](size_t bytes) {
       size_t o = off;
       off += (bytes + 255) & ~(size_t)255;

@@ -72,6 +72,8 @@ class Engine:
         # (qed_params.same_step_generations > 0)
         self.work_bytes = Q.qed_work_bytes(self.n_inst, pslots, self.arena_records, same_step)
         self.work = torch.zeros(self.work_bytes, dtype=torch.uint8, device=self.device)
+        self._pslots, self._same_step = pslots, same_step
+        self.step_work_bytes = self.work_bytes  # what qed_step is told (set_arena)
         self.stats_buf = torch.zeros(C.sizeof(Q.qed_stats), dtype=torch.uint8, device=self.device)
         self.step_ctr = torch.zeros(1, dtype=torch.int64, device=self.device)
         self.stores = Q.qed_stores()
@@ -243,7 +245,18 @@ class Engine:
         p.tile, p.block, p.grid_blocks = int(tile), int(block), int(grid_blocks)
         return p
 
+    def set_arena(self, divisor: int = 0):
+        """Child arenas of photon slots / divisor records for the following steps (within
+        the workspace allocated at construction; qed_step uses the largest arena that fits
+        in the bytes it is given); 0: the whole workspace."""
+        if divisor <= 0:
+            self.step_work_bytes = self.work_bytes
+            return
+        records = max(self._pslots // int(divisor), 1024)
+        need = Q.qed_work_bytes(self.n_inst, self._pslots, records, self._same_step)
+        self.step_work_bytes = min(need, self.work_bytes)
+
     def step(self, field: Q.qed_field, params: Q.qed_params, stream: Optional[int] = None):
         Q.qed_step(self.tables.data_ptr(), self.stores, field, params, self.step_ctr.data_ptr(),
-                   self.stats_buf.data_ptr(), self.work.data_ptr(), self.work_bytes,
+                   self.stats_buf.data_ptr(), self.work.data_ptr(), self.step_work_bytes,
                    self.stream if stream is None else stream)

@@ -1,0 +1,137 @@
+"""The launch tuner (autotune.tune_run, Schedule, TuneCache) on a stand-in engine whose step
+times are scripted: per size class it must pick the fastest launch shape, then the fastest
+child-arena size with that shape, give every step its class's choice, skip the classes a
+cache already knows, and keep the best so far for a class the run leaves early.  No GPU."""
+import math
+from types import SimpleNamespace
+
+import numpy as np
+
+from paper_1412_6426_amd import autotune as AT
+
+MIN_LIVE = 1 << 10
+
+
+class FakeEngine:
+    """Live count growing by `growth` per step; a step's time is live particles times a
+    per-particle cost that depends on the shape and the size class."""
+
+    def __init__(self, cost, n0=100, growth=1.25, cap=None):
+        self.cost, self.live, self.growth, self.cap = cost, n0, growth, cap
+        self.arena = 0
+        self.stream = 0
+        self.last_ms = 0.0
+        self.done = 0
+        self.shapes = []
+
+    def counts(self):
+        return np.array([[self.live, 0, 0]], dtype=np.int64)
+
+    def set_arena(self, divisor):
+        self.arena = divisor
+
+    def step(self, field, params):
+        shape = (params.tile, params.grid_blocks, self.arena)
+        self.shapes.append(shape)
+        self.done = self.live
+        self.last_ms = self.live * self.cost(shape, self.live)
+        grown = int(math.ceil(self.live * self.growth))
+        self.live = grown if self.cap is None else min(grown, self.cap)
+
+    def stats(self):
+        return {"advanced": [self.done, 0, 0], "dropped": 0}
+
+
+class FakeTimer:
+    def __init__(self, engine):
+        self.e = engine
+
+    def start(self, stream):
+        pass
+
+    def stop_ms(self, stream):
+        return self.e.last_ms
+
+
+CANDS = AT.default_candidates(256)
+
+
+def cls_of(live):
+    return -1 if live < MIN_LIVE else int(math.log(live / MIN_LIVE, 4.0))
+
+
+def scripted_cost(shape, live):
+    """Small classes like 64-particle chunks, large ones 512; arena divisor 8 is best at
+    every size; the default grid beats the smaller and larger ones."""
+    tile, grid, arena = shape
+    want_tile = 64 if cls_of(live) < 2 else 512
+    c = 1.0 + 0.1 * abs(math.log2(max(tile, 1) / want_tile))
+    c += 0.05 if grid else 0.0
+    c += {0: 0.02, 2: 0.03, 8: 0.0, 32: 0.04}[arena]
+    return c
+
+
+def _tune(e, steps, **kw):
+    params = SimpleNamespace(tile=0, grid_blocks=0)
+    return AT.tune_run(e, None, params, steps, CANDS, min_live=MIN_LIVE, timer=FakeTimer(e),
+                       sync=lambda: None, **kw)
+
+
+def test_each_class_gets_its_fastest_launch_shape_then_arena():
+    e = FakeEngine(scripted_cost, growth=1.08)
+    sched = _tune(e, 160)
+    lives = [100]
+    for _ in range(159):
+        lives.append(int(math.ceil(lives[-1] * 1.08)))
+    classes = sorted({cls_of(v) for v in lives if cls_of(v) >= 0})
+    assert len(classes) >= 3
+    for c in classes[:-1]:  # the last class may be cut short by the end of the run
+        want_tile = 64 if c < 2 else 512
+        assert sched.choices[c] == (want_tile, 0, 8), c
+    # every step follows its class's choice (trial steps included), the default below
+    # min_live, and the trials tried both phases
+    for n, live in enumerate(lives):
+        c = cls_of(live)
+        assert sched.shape_at(n) == (sched.choices.get(c, (0, 0, 0)) if c >= 0 else (0, 0, 0))
+    tried = {(t["tile"], t["grid"], t["arena_div"]) for t in sched.trials}
+    assert set(CANDS) <= tried and {(64, 0, 2), (64, 0, 32)} <= tried
+    assert sched.distinct()[0] == (0, 0, 0)
+    # the engine really ran the trial shapes, and each class's choice afterwards
+    assert e.shapes[0] == (0, 0, 0)
+    assert (512, 0, 8) in e.shapes
+
+
+def test_known_classes_skip_their_trials(tmp_path):
+    e = FakeEngine(scripted_cost, growth=1.08)
+    first = _tune(e, 160)
+    path = str(tmp_path / "tune.json")
+    cache = AT.TuneCache(path)
+    key = AT.TuneCache.key("gfx950", "f64", "rotating-E cascade")
+    cache.put(key, first.choices)
+    again = AT.TuneCache(path)
+    assert again.get(key) == first.choices
+    assert again.get(AT.TuneCache.key("gfx950", "mixed", "rotating-E cascade")) == {}
+    e2 = FakeEngine(scripted_cost, growth=1.08)
+    second = _tune(e2, 160, known=again.get(key))
+    known_classes = set(first.choices)
+    assert not [t for t in second.trials if t["cls"] in known_classes]
+    assert second.shapes == first.shapes and second.steps == first.steps
+
+
+def test_a_class_left_early_keeps_its_best_so_far():
+    # growth so fast that each class lasts only a few steps: fewer than its trials
+    e = FakeEngine(scripted_cost, growth=2.5)
+    sched = _tune(e, 12)
+    for c, shape in sched.choices.items():
+        timed = [t for t in sched.trials if t["cls"] == c]
+        assert timed, c
+        best = min(timed, key=lambda t: t["ms"] / t["particle_steps"])
+        assert shape == (best["tile"], best["grid"], best["arena_div"])
+
+
+def test_schedule_lookup():
+    s = AT.Schedule(steps=[0, 5, 9], shapes=[(0, 0, 0), (64, 0, 8), (512, 0, 2)])
+    assert [s.shape_at(n) for n in (0, 4, 5, 8, 9, 100)] == \
+        [(0, 0, 0), (0, 0, 0), (64, 0, 8), (64, 0, 8), (512, 0, 2), (512, 0, 2)]
+    assert s.distinct() == [(0, 0, 0), (64, 0, 8), (512, 0, 2)]
+    assert AT.Schedule().distinct() == [(0, 0, 0)]
