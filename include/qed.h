@@ -327,6 +327,29 @@ qed_status qed_thin(const qed_stores *stores, int species, int64_t trigger, int6
                     const int64_t *d_step, qed_thin_record *d_records, void *d_work,
                     size_t work_bytes, void *stream);
 
+/* Workspace size of qed_sort_cells for n_instances instances and a species store of
+ * species_slots slots: two 4-byte keys and two 4-byte indices per slot, a copy of the
+ * columns (80 bytes per slot) and the per-tile digit counts.  0 for invalid arguments. */
+size_t qed_sort_work_bytes(int n_instances, int64_t species_slots);
+
+/* Reorders the live slots [0, count) of every instance's segment of one species store by
+ * the grid cell that holds each particle, for position-dependent fields gathered from a
+ * grid (Appendix A: the field of a particle comes from the eight nodes around it; Sec. IV.H:
+ * this interpolation is usually the costliest part of the update).  Particles of one cell
+ * then sit in neighbouring slots and a wavefront's gathers share cache lines.  The key is
+ * the block of 2^s x 2^s x 2^s cells of `field` (kind QED_FIELD_YEE: n, dx, origin; cell
+ * (i, j, k) = floor((x - origin) / dx) per axis, periodic) that holds the particle, blocks
+ * numbered x fastest, with s the smallest shift that leaves at most 65534 blocks (s = 0 up
+ * to 40^3 cells; 3 for 256^3).  Removed photons go to the end of their segment.  The sort
+ * is stable (particles of one block keep their order), so the result is deterministic;
+ * counts, contents and every particle's state are unchanged, only the slots move.  d_work:
+ * qed_sort_work_bytes(n_instances, slots of the species) bytes, 256-byte aligned.
+ * Asynchronous on `stream`, graph-capturable.  QED_ERR_ARG for a field that is not a Yee
+ * grid, bad sizes or pointers, a missing column (n_events may be NULL); QED_ERR_UNSUPPORTED
+ * for 2^32 or more slots. */
+qed_status qed_sort_cells(const qed_stores *stores, int species, const qed_field *field,
+                          void *d_work, size_t work_bytes, void *stream);
+
 /* Counters of one qed_schwinger call (device memory; overwritten by each call). */
 typedef struct {
   int64_t cells;      /* (cell, instance) pairs visited */

@@ -339,6 +339,33 @@ qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_fi
   return e == hipSuccess ? QED_OK : QED_ERR_HIP;
 }
 
+size_t qed_sort_work_bytes(int n_instances, int64_t species_slots) {
+  if (n_instances < 1 || species_slots < 0) return 0;
+  return SortLayout::make(n_instances, species_slots).total;
+}
+
+qed_status qed_sort_cells(const qed_stores* stores, int species, const qed_field* field,
+                          void* d_work, size_t work_bytes, void* stream) {
+  if (!stores || !field || !d_work || !stores->d_instances) return QED_ERR_ARG;
+  if (species < 0 || species >= QED_NSPECIES || stores->n_instances < 1) return QED_ERR_ARG;
+  if (field->kind != QED_FIELD_YEE) return QED_ERR_ARG;
+  const long long slots = stores->slots[species];
+  if (slots < 0) return QED_ERR_ARG;
+  if (slots >= (1ll << 32)) return QED_ERR_UNSUPPORTED;
+  for (int d = 0; d < 3; ++d)
+    if (field->n[d] < 1 || !finite_pos(field->dx[d]) || !isfinite(field->origin[d]))
+      return QED_ERR_ARG;
+  const qed_soa& s = stores->species[species];
+  if (!soa_ok(s, false)) return QED_ERR_ARG;
+  if (work_bytes < qed_sort_work_bytes(stores->n_instances, slots) ||
+      (reinterpret_cast<uintptr_t>(d_work) & 255u))
+    return QED_ERR_ARG;
+  const hipError_t e = launch_sort_cells(s, species, stores->d_instances, stores->n_instances,
+                                         slots, field->n, field->dx, field->origin, d_work,
+                                         static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? QED_OK : QED_ERR_HIP;
+}
+
 qed_status qed_schwinger(const qed_stores* stores, const qed_field* field, double dt,
                          double eps_r, double weight, const int64_t* d_step,
                          qed_schwinger_record* d_record, void* stream) {

@@ -224,6 +224,46 @@ struct ThinLayout {
   }
 };
 
+// Cell sort (qed_sort_cells): tiles of kSortTile slots, 16-bit keys (cell blocks; removed
+// photons kSortDeadKey), and the workspace layout.
+constexpr int kSortTile = 4096;
+constexpr unsigned kSortDeadKey = 65535u;
+struct alignas(64) SortHdr {
+  long long n;      // live slots of the species, all instances
+  long long tiles;  // tiles of the instance-ordered tile list
+  long long reserved[6];
+};
+struct SortLayout {
+  size_t hdr, gpref, tpref, key[2], val[2], cnt, sums, cols, total;
+  long long tiles_max, cap;
+  static SortLayout make(int n_inst, long long slots) {
+    SortLayout L{};
+    size_t off = 0;
+    auto take = [&off](size_t bytes) {
+      size_t o = off;
+      off += (bytes + 255) & ~(size_t)255;
+      return o;
+    };
+    L.cap = slots > 0 ? slots : 1;
+    // each instance's last tile may be partial: one more tile per instance at most
+    L.tiles_max = (L.cap + kSortTile - 1) / kSortTile + n_inst;
+    const size_t cap = (size_t)L.cap;
+    L.hdr = take(sizeof(SortHdr));
+    L.gpref = take(sizeof(long long) * ((size_t)n_inst + 1));
+    L.tpref = take(sizeof(long long) * ((size_t)n_inst + 1));
+    for (int k = 0; k < 2; ++k) {
+      L.key[k] = take(sizeof(unsigned) * cap);
+      L.val[k] = take(sizeof(unsigned) * cap);
+    }
+    L.cnt = take(sizeof(unsigned) * 256 * (size_t)L.tiles_max);
+    L.sums = take(sizeof(unsigned) * (((size_t)L.tiles_max * 256 + 4095) / 4096));
+    const size_t col8 = (cap * 8 + 255) & ~(size_t)255, col4 = (cap * 4 + 255) & ~(size_t)255;
+    L.cols = take(col8 * 9 + col4 * 2);  // x..w, id, parent; birth, n_events
+    L.total = off;
+    return L;
+  }
+};
+
 struct StepArgs {
   qed_soa sp[3];
   qed_instance* inst;
@@ -291,6 +331,11 @@ hipError_t launch_schwinger(const qed_stores& st, const float* const grid[3], co
                             const double dx[3], const double origin[3], double dt, double eps_r,
                             double weight, const long long* d_step, qed_schwinger_record* rec,
                             hipStream_t s);
+hipError_t launch_sort_cells(const qed_soa& s, int species, qed_instance* inst, int n_inst,
+                             long long slots, const int n[3], const double dx[3],
+                             const double origin[3], void* work, hipStream_t st);
+// Smallest shift such that blocks of 2^shift cells per axis number at most kSortDeadKey - 1.
+int sort_block_shift(const int n[3]);
 // Emission generators as trials (qed_generators.hip).
 long long standard_panels(double chi, double delta_min, double* u0, double* k0);
 size_t generator_work_bytes(long long panels);

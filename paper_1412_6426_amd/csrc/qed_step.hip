@@ -904,34 +904,36 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
     wc.low_occ += (__popcll(act) < 32);
 
     // ---- one sub-step: push, chi, emission decision (Sec. IV.G) ----
-    // A sub-step whose end state breaks Eq. (29) is taken again at half the length.
-    bool emit = false, redo = false;
+    // A sub-step whose end state breaks Eq. (29) is taken again from its start at half the
+    // length (rare: such lanes repeat the push while the others wait).
+    bool emit = false;
     double f = 0.0, g = 1.0;
     if (slot >= 0) {
-      V3 pn = p;
-      if (FMODE == kFieldE) {
-        // B = 0: the Boris rotation is the identity and the push is p += q h E
-        pn = {p.x + 2.0 * qh2 * E.x, p.y + 2.0 * qh2 * E.y, p.z + 2.0 * qh2 * E.z};
-      } else {
-        boris(pn, qh2, E, B);
-      }
-      const double p2 = dot(pn, pn);
-      g = sqrt(1.0 + p2);
-      const double chi = chi_of(pn, g, E, FMODE == kFieldE ? V3{0.0, 0.0, 0.0} : B, a.eps_r);
-      if (refine && chi > 0.0)
-        redo = refine_substep(hs3, chi, p2, g, h, a.inv_lep_scale, k, left, bs);
-      if (redo) {
+      const V3 p0 = p;
+      double chi;
+      for (;;) {
+        if (FMODE == kFieldE) {
+          // B = 0: the Boris rotation is the identity and the push is p += q h E
+          p = {p0.x + 2.0 * qh2 * E.x, p0.y + 2.0 * qh2 * E.y, p0.z + 2.0 * qh2 * E.z};
+        } else {
+          p = p0;
+          boris(p, qh2, E, B);
+        }
+        const double p2 = dot(p, p);
+        g = sqrt(1.0 + p2);
+        chi = chi_of(p, g, E, FMODE == kFieldE ? V3{0.0, 0.0, 0.0} : B, a.eps_r);
+        if (!(refine && chi > 0.0) ||
+            !refine_substep(hs3, chi, p2, g, h, a.inv_lep_scale, k, left, bs))
+          break;
         h *= 0.5;
         qh2 *= 0.5;
         dtfac *= 0.5;
         hs3 *= 0.125;
         left *= 2;
-      } else {
-        p = pn;
-        const double hg = h / g;
-        x = {x.x + hg * p.x, x.y + hg * p.y, x.z + hg * p.z};
       }
-      if (!redo && a.emission) {
+      const double hg = h / g;
+      x = {x.x + hg * p.x, x.y + hg * p.y, x.z + hg * p.z};
+      if (a.emission) {
         const uint4 o = draw_words(id, seed, step, (uint32_t)k, kDraw);
         double delta;
         emit = emission_decision<MIXED>(tab, ser64, ser32, o, chi, g, dtfac, cnt, delta);
@@ -946,7 +948,7 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
     // With a generator factor f_g (Sec. VI) the photon of an event is created with
     // probability 1 / f_g and carries f_g times the lepton's weight; the recoil below
     // happens at every event.
-    wc.substeps += __popcll(wave_ballot(slot >= 0 && !redo));
+    wc.substeps += __popcll(act);
     bool child = emit;
     if (EXT && emit && a.fg_photon > 1.0)
       child = generator_runs(id, seed, step, (uint32_t)k, kGenPhoton, a.inv_fg_photon);
@@ -1022,7 +1024,7 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
     }
 
     // ---- lanes whose particle has done all its sub-steps write back and go idle ----
-    if (slot >= 0 && !redo && (++k, --left == 0)) {
+    if (slot >= 0 && (++k, --left == 0)) {
       LEPTON_COL(x, sp)[slot] = x.x;
       LEPTON_COL(y, sp)[slot] = x.y;
       LEPTON_COL(z, sp)[slot] = x.z;
@@ -1863,33 +1865,34 @@ __device__ __forceinline__ void gen_lepton_phase(const StepArgs& a, const GenArg
     if (wave_ballot(slot >= 0) == 0) break;
 
     // ---- one sub-step (taken again at half the length if its end state breaks Eq. (29)) ----
-    bool emit = false, redo = false;
+    bool emit = false;
     double f = 0.0;
     if (slot >= 0) {
-      V3 pn = p;
-      if (FMODE == kFieldE) {
-        pn = {p.x + 2.0 * qh2 * E.x, p.y + 2.0 * qh2 * E.y, p.z + 2.0 * qh2 * E.z};
-      } else {
-        boris(pn, qh2, E, B);
-      }
-      const double p2 = dot(pn, pn);
-      const double g = sqrt(1.0 + p2);
-      const double chi = chi_of(pn, g, E, FMODE == kFieldE ? V3{0.0, 0.0, 0.0} : B, a.eps_r);
-      if (refine && chi > 0.0)
-        redo = refine_substep(hs3, chi, p2, g, h, a.inv_lep_scale, k, left, bs);
-      if (redo) {
+      const V3 p0 = p;
+      double g, chi;
+      for (;;) {
+        if (FMODE == kFieldE) {
+          p = {p0.x + 2.0 * qh2 * E.x, p0.y + 2.0 * qh2 * E.y, p0.z + 2.0 * qh2 * E.z};
+        } else {
+          p = p0;
+          boris(p, qh2, E, B);
+        }
+        const double p2 = dot(p, p);
+        g = sqrt(1.0 + p2);
+        chi = chi_of(p, g, E, FMODE == kFieldE ? V3{0.0, 0.0, 0.0} : B, a.eps_r);
+        if (!(refine && chi > 0.0) ||
+            !refine_substep(hs3, chi, p2, g, h, a.inv_lep_scale, k, left, bs))
+          break;
         h *= 0.5;
         qh2 *= 0.5;
         dtfac *= 0.5;
         hs3 *= 0.125;
         left *= 2;
-      } else {
-        p = pn;
-        const double hg = h / g;
-        x = {x.x + hg * p.x, x.y + hg * p.y, x.z + hg * p.z};
-        ++cnt.subs;
       }
-      if (!redo && a.emission) {
+      const double hg = h / g;
+      x = {x.x + hg * p.x, x.y + hg * p.y, x.z + hg * p.z};
+      ++cnt.subs;
+      if (a.emission) {
         const uint4 o = draw_words(id, seed, step, (uint32_t)k, kDraw);
         double delta;
         emit = emission_decision<MIXED>(tab, ser64, ser32, o, chi, g, dtfac, cnt, delta);
@@ -1948,7 +1951,7 @@ __device__ __forceinline__ void gen_lepton_phase(const StepArgs& a, const GenArg
       // recoil: the lepton keeps p - k (momentum conservation, Sec. IV.F)
       p = {p.x - f * p.x, p.y - f * p.y, p.z - f * p.z};
     }
-    if (slot >= 0 && !redo && (++k, --left == 0)) {
+    if (slot >= 0 && (++k, --left == 0)) {
       LEPTON_COL(x, sp)[slot] = x.x;
       LEPTON_COL(y, sp)[slot] = x.y;
       LEPTON_COL(z, sp)[slot] = x.z;

@@ -189,6 +189,18 @@ class Engine:
         return [Q.qed_thin_record.from_buffer_copy(raw[i * n:(i + 1) * n]).as_dict()
                 for i in range(self.n_inst)]
 
+    # ------------------------------------------------------------------ cell sort
+    def sort_cells(self, species: int, field: Q.qed_field, stream: Optional[int] = None):
+        """qed_sort_cells on one species of every instance (workspace allocated on first
+        use, large enough for any species)."""
+        torch = _torch()
+        need = max(Q.qed_sort_work_bytes(self.n_inst, int(self.cols[s]["x"].numel()))
+                   for s in range(3))
+        if getattr(self, "_sort_work", None) is None or self._sort_work.numel() < need:
+            self._sort_work = torch.zeros(need, dtype=torch.uint8, device=self.device)
+        Q.qed_sort_cells(self.stores, species, field, self._sort_work.data_ptr(),
+                         self._sort_work.numel(), self.stream if stream is None else stream)
+
     # ------------------------------------------------------------------ Schwinger pairs
     def schwinger(self, field: Q.qed_field, dt: float, eps_r: float, weight: float = 1.0,
                   stream: Optional[int] = None):

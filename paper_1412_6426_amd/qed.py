@@ -112,7 +112,8 @@ class qed_schwinger_record(C.Structure):
 #: every symbol include/qed.h declares
 EXPORTS = ("qed_table_bytes", "qed_build_tables", "qed_work_bytes", "qed_step",
            "qed_step_noalloc",
-           "qed_thin_work_bytes", "qed_thin", "qed_schwinger", "qed_generator_work_bytes",
+           "qed_thin_work_bytes", "qed_thin", "qed_sort_work_bytes", "qed_sort_cells",
+           "qed_schwinger", "qed_generator_work_bytes",
            "qed_generator_trials", "qed_standard_w_table",
            "qed_append_stats", "qed_photon_spectrum", "qed_fill_standing_wave",
            "qed_status_string", "qed_version")
@@ -153,6 +154,11 @@ def lib():
                                C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
         L.qed_append_stats.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
                                        C.c_void_p]
+        L.qed_sort_work_bytes.restype = C.c_size_t
+        L.qed_sort_work_bytes.argtypes = [C.c_int, C.c_int64]
+        L.qed_sort_cells.restype = C.c_int
+        L.qed_sort_cells.argtypes = [C.POINTER(qed_stores), C.c_int, C.POINTER(qed_field),
+                                     C.c_void_p, C.c_size_t, C.c_void_p]
         L.qed_schwinger.restype = C.c_int
         L.qed_schwinger.argtypes = [C.POINTER(qed_stores), C.POINTER(qed_field), C.c_double,
                                     C.c_double, C.c_double, C.c_void_p, C.c_void_p,
@@ -222,6 +228,16 @@ def qed_thin(stores: qed_stores, species: int, trigger: int, target: int, d_step
              d_records: int, d_work: int, work_bytes: int, stream: int) -> None:
     _check(lib().qed_thin(C.byref(stores), species, trigger, target, d_step, d_records, d_work,
                           work_bytes, stream), "qed_thin")
+
+
+def qed_sort_work_bytes(n_instances: int, species_slots: int) -> int:
+    return int(lib().qed_sort_work_bytes(n_instances, species_slots))
+
+
+def qed_sort_cells(stores: qed_stores, species: int, field: qed_field, d_work: int,
+                   work_bytes: int, stream: int) -> None:
+    _check(lib().qed_sort_cells(C.byref(stores), species, C.byref(field), d_work, work_bytes,
+                                stream), "qed_sort_cells")
 
 
 def qed_schwinger(stores: qed_stores, field: qed_field, dt: float, eps_r: float,
