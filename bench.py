@@ -27,9 +27,9 @@ the FP64 job, the batched ensemble (64 rotating-field cascades, a0 log-spaced ov
 500-3000, 10^3-10^5 seeds each, 2 periods, 2*10^8 slots split evenly) as full jobs in mixed
 precision and in FP64 with the same comparison, the standing-wave cascade on a 256^3 Yee
 grid (field fill timed apart), the rotating-field cascade carried past its capacity by
-thinning, the Sec. VII shower and avalanche, config 1, Schwinger pairs, the three emission
-generators, and the FP64 CPU oracle's rate on a bounded sample of the rotating-field
-workload on this host.  Each leg's full record goes to stderr as a `bench-detail <leg>
+thinning, the Sec. VII shower and avalanche, 10^4 electrons in a uniform B, Schwinger
+pairs, the three emission generators, and the FP64 CPU oracle's rate on a bounded sample
+of the rotating-field workload on this host.  Each leg's full record goes to stderr as a `bench-detail <leg>
 <json>` line.
 
 HBM traffic of the dominant kernel comes from the rocprofv3 counter summary committed
@@ -302,14 +302,15 @@ def gpu_run(args, precision, kind="rotating", thin=None, fg=None, sample=None):
     return out
 
 
-def gpu_run_yee(args, precision, sort_every=None):
+def gpu_run_yee(args, precision, sort_every=None, sort_species=None):
     """Standing-wave cascade on a 256^3 Yee grid (two counter-propagating CP waves, a0 =
     2000 each, cells of lambda/32, 10^6 seeds Gaussian sigma = 0.1 lambda about the node,
     dt = T/100, 2*10^8 photon slots).  The grid is refilled with the analytic wave before
     every step (a stand-in for the field solver, timed separately); steps run eagerly with
     HIP events around the fill, the whole step, and the lepton and photon kernels.  Every
-    `sort_every` steps (0: never) the three stores are sorted by cell (qed_sort_cells) before
-    the step; that time counts as part of the step and is also reported apart."""
+    `sort_every` steps (0: never) the stores `sort_species` are sorted by cell
+    (qed_sort_cells) before the step; that time counts as part of the step and is also
+    reported apart."""
     import torch
     from paper_1412_6426_amd import qed as Q
     from paper_1412_6426_amd import runner as R
@@ -323,6 +324,8 @@ def gpu_run_yee(args, precision, sort_every=None):
     params = R.params_of(w, freeze_on_drop=1, tile=args.tile, grid_blocks=args.grid_blocks)
     K = w.n_steps
     S = args.sort_every if sort_every is None else sort_every
+    if sort_species is None:
+        sort_species = [int(v) for v in args.sort_species.split(",") if v.strip()]
     stream = torch.cuda.Stream()
     sp = stream.cuda_stream
     log = torch.zeros(K * e.stats_buf.numel(), dtype=torch.uint8, device=e.device)
@@ -340,7 +343,7 @@ def gpu_run_yee(args, precision, sort_every=None):
             grid.fill(w.t0 + n * w.dt, sp)
             hip.lib.hipEventRecord(C.c_void_p(ev[1]), C.c_void_p(sp))
             if S and n % S == 0:
-                for s_ in range(3):
+                for s_ in sort_species:
                     e.sort_cells(s_, field, stream=sp)
             hip.lib.hipEventRecord(C.c_void_p(ev[7]), C.c_void_p(sp))
             for j in range(4):
@@ -366,7 +369,7 @@ def gpu_run_yee(args, precision, sort_every=None):
         first_drop_step=next((r.step for r in recs if r.dropped > 0), None),
         particle_steps=int(sum(adv)), advanced=[int(a) for a in adv], emitted=int(emitted),
         pairs=int(sum(r.pairs for r in recs)), step_ms=step_ms, fill_ms=fill_ms,
-        sort_every=S, sort_ms=sort_ms, lep_ms=lep_ms, pho_ms=pho_ms,
+        sort_every=S, sort_species=list(sort_species) if S else [], sort_ms=sort_ms, lep_ms=lep_ms, pho_ms=pho_ms,
         value=sum(adv) / (step_ms / 1e3),
         substeps=int(sum(r.substeps for r in recs)),
         nsub_max=max((k for r in recs for k in range(len(r.nsub_hist)) if r.nsub_hist[k]),
@@ -917,7 +920,7 @@ def main():
     ap.add_argument("--schwinger-only", action="store_true",
                     help="run only the Schwinger leg and print its record (profiling)")
     ap.add_argument("--no-uniform-b", action="store_true",
-                    help="skip config 1 (10^4 electrons in a uniform B)")
+                    help="skip the 10^4 electrons in a uniform B")
     ap.add_argument("--only", choices=("uniform-b", "yee", "batched"), default=None,
                     help="run only this leg and print its record (profiling)")
     ap.add_argument("--no-generators", action="store_true",
@@ -927,8 +930,11 @@ def main():
     ap.add_argument("--tune-cache", default=None,
                     help="JSON file of tuned shapes per (arch, precision, workload): read "
                          "before tuning (known size classes are not tried again), written after")
-    ap.add_argument("--sort-every", type=int, default=0,
-                    help="grid cascade: sort the stores by cell every this many steps (0: never)")
+    ap.add_argument("--sort-every", type=int, default=3,
+                    help="grid cascade: sort stores by cell every this many steps (0: never)")
+    ap.add_argument("--sort-species", default="0,1",
+                    help="grid cascade: the stores --sort-every sorts (0 e-, 1 e+, 2 photons; "
+                         "photons are born in their parents' order)")
     ap.add_argument("--no-tune", action="store_true",
                     help="use --tile / --grid-blocks for every step instead of tuning")
     args = ap.parse_args()
@@ -1091,7 +1097,7 @@ def main():
             lepton_frac=y["lepton_roofline_gbs"] / HBM_PEAK_GBS,
             photon_frac=y["photon_roofline_gbs"] / HBM_PEAK_GBS, saturated=y["saturated"])
     if not args.no_uniform_b:
-        print("bench: config 1, uniform B", file=sys.stderr, flush=True)
+        print("bench: uniform B, 10^4 electrons", file=sys.stderr, flush=True)
         u = gpu_uniform_b(args)
         detail("uniform_b", u)
         legs["uniform_b"] = dict(us_per_step_graph=u["us_per_step_graph"],

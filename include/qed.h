@@ -336,12 +336,16 @@ size_t qed_sort_work_bytes(int n_instances, int64_t species_slots);
  * the grid cell that holds each particle, for position-dependent fields gathered from a
  * grid (Appendix A: the field of a particle comes from the eight nodes around it; Sec. IV.H:
  * this interpolation is usually the costliest part of the update).  Particles of one cell
- * then sit in neighbouring slots and a wavefront's gathers share cache lines.  The key is
- * the block of 2^s x 2^s x 2^s cells of `field` (kind QED_FIELD_YEE: n, dx, origin; cell
- * (i, j, k) = floor((x - origin) / dx) per axis, periodic) that holds the particle, blocks
- * numbered x fastest, with s the smallest shift that leaves at most 65534 blocks (s = 0 up
- * to 40^3 cells; 3 for 256^3).  Removed photons go to the end of their segment.  The sort
- * is stable (particles of one block keep their order), so the result is deterministic;
+ * then sit in neighbouring slots and a wavefront's gathers share cache lines; children are
+ * appended in their parents' order, so sorting the lepton stores also orders the photons
+ * they emit.  The key is the block of 2^s x 2^s x 2^s cells of `field` (kind QED_FIELD_YEE:
+ * n, dx, origin; cell (i, j, k) = floor((x - origin) / dx) per axis, periodic) that holds
+ * the particle, blocks numbered x fastest, with s the smallest shift that leaves at most
+ * 2^24 - 2 blocks (s = 0 up to 16,777,214 cells; 1 for 256^3), in keys of the fewest 8-bit
+ * digits that leave room for two more values: removed photons take the largest and go to
+ * the end of their segment, non-finite positions the one below it.  The sort is stable
+ * (particles of one block keep their order), so the result is deterministic; frozen
+ * instances (which qed_step skips) are left as they are;
  * counts, contents and every particle's state are unchanged, only the slots move.  d_work:
  * qed_sort_work_bytes(n_instances, slots of the species) bytes, 256-byte aligned.
  * Asynchronous on `stream`, graph-capturable.  QED_ERR_ARG for a field that is not a Yee

@@ -224,10 +224,16 @@ struct ThinLayout {
   }
 };
 
-// Cell sort (qed_sort_cells): tiles of kSortTile slots, 16-bit keys (cell blocks; removed
-// photons kSortDeadKey), and the workspace layout.
+// Cell sort (qed_sort_cells): tiles of kSortTile slots, keys of 8, 16 or 24 bits (cell
+// blocks; removed photons get the largest key), and the workspace layout.
 constexpr int kSortTile = 4096;
-constexpr unsigned kSortDeadKey = 65535u;
+constexpr int kSortMaxPasses = 3;
+struct SortGeometry {
+  int shift;      // blocks of 2^shift cells per axis
+  int passes;     // 8-bit digit passes: keys of 8 * passes bits
+  unsigned dead;  // key of a removed photon: 2^(8 passes) - 1; non-finite positions dead - 1
+  long long nb[3];
+};
 struct alignas(64) SortHdr {
   long long n;      // live slots of the species, all instances
   long long tiles;  // tiles of the instance-ordered tile list
@@ -334,8 +340,10 @@ hipError_t launch_schwinger(const qed_stores& st, const float* const grid[3], co
 hipError_t launch_sort_cells(const qed_soa& s, int species, qed_instance* inst, int n_inst,
                              long long slots, const int n[3], const double dx[3],
                              const double origin[3], void* work, hipStream_t st);
-// Smallest shift such that blocks of 2^shift cells per axis number at most kSortDeadKey - 1.
-int sort_block_shift(const int n[3]);
+// The key geometry of an n[0] x n[1] x n[2] grid: the smallest shift that leaves at most
+// 2^24 - 2 blocks, and the fewest 8-bit passes whose keys hold every block and the two
+// reserved keys.
+SortGeometry sort_geometry(const int n[3]);
 // Emission generators as trials (qed_generators.hip).
 long long standard_panels(double chi, double delta_min, double* u0, double* k0);
 size_t generator_work_bytes(long long panels);

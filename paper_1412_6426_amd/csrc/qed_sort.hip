@@ -6,23 +6,29 @@
 // by cell for it).  The stores here grow by appends in work order, so neighbouring slots
 // soon hold particles far apart, and every lane of a wavefront gathers from its own lines.
 // Sorting a store by cell puts the particles of one cell in neighbouring slots, so a
-// wavefront's gathers share cache lines; children appended by a sorted parent store come out
-// in runs from the same cells, so the order decays slowly and a sort every few steps keeps
-// most of the gain.
+// wavefront's gathers share cache lines.  Children are appended in the order of their
+// parents, so a sorted lepton store also hands its photons out in runs from the same cells.
 //
 // The key of a particle is the block of 2^shift x 2^shift x 2^shift cells that holds it
-// (periodic wrap), numbered x fastest; shift is the smallest that leaves at most 65535
-// blocks, so that the keys have 16 bits and the sort two 8-bit passes.  Removed photons get
-// key 65535 and go to the end of their segment.  The sort is a stable LSD radix sort over
-// each instance's live slots (ties keep their order), so the result is deterministic.
+// (periodic wrap), numbered x fastest; shift is the smallest that leaves at most 2^24 - 2
+// blocks (0 up to 16 million cells, 1 for 256^3), and the keys take the fewest 8-bit digits
+// that hold every block plus two reserved keys: removed photons get the largest (they go to
+// the end of their segment), particles with a non-finite position the one below it.  The
+// sort is a stable LSD radix sort over each instance's live slots (ties keep their order),
+// so the result is deterministic.
+//
+// Every kernel but the scans works tile by tile (kSortTile slots of one instance, one
+// workgroup each), so a tile's instance and slot base are found once; each thread loads
+// all of its items of a round before it stores any, which keeps many loads in flight.
 //
 // Launches (all on the caller's stream, sizes fixed by the store's slot count so that a
 // sequence can be captured):
-//   sort_prep     one workgroup: live counts, slot prefix and tile prefix per instance;
+//   sort_prep     one workgroup: live counts (none for a frozen instance), slot prefix and
+//                 tile prefix per instance;
 //   sort_key      keys and the identity permutation;
-//   per pass:  sort_hist (one workgroup per tile of kSortTile slots: digit counts),
-//              scan_chunks, scan_sums, scan_apply (exclusive scan of the counts, ordered
-//              instance, digit, tile), sort_scatter (stable ranks within the tile);
+//   per pass:  sort_hist (digit counts per tile), scan_chunks, scan_sums, scan_apply
+//              (exclusive scan of the counts, ordered instance, digit, tile), sort_scatter
+//              (stable ranks within the tile);
 //   sort_gather   the columns, in sorted order, into the workspace;
 //   sort_store    the workspace back into the segments.
 #include "qed_internal.h"
@@ -35,8 +41,9 @@ struct SortArgs {
   qed_soa s;
   qed_instance* inst;
   int n_inst, species;
-  int n[3], shift;
-  int nb[3];  // blocks per axis
+  int n[3], shift, passes;
+  unsigned dead;
+  long long nb[3];  // blocks per axis
   double inv_dx[3], origin[3];
   SortHdr* hdr;
   long long* gpref;  // [n_inst + 1] live-slot prefix
@@ -49,6 +56,10 @@ struct SortArgs {
   long long cap;     // slots (row length of the column copy)
 };
 
+constexpr int kSortThreads = 256;
+constexpr int kPerThread = kSortTile / kSortThreads;  // items of one thread in a tile
+constexpr int kBatch = 4;                             // items a thread loads before storing
+
 __device__ __forceinline__ int find_instance(const long long* pref, int n, long long g) {
   int lo = 0, hi = n;  // pref[lo] <= g < pref[hi]
   while (hi - lo > 1) {
@@ -59,7 +70,7 @@ __device__ __forceinline__ int find_instance(const long long* pref, int n, long 
   return lo;
 }
 
-__global__ void __launch_bounds__(256) sort_prep_kernel(SortArgs a) {
+__global__ void __launch_bounds__(64) sort_prep_kernel(SortArgs a) {
   if (threadIdx.x != 0) return;
   long long g = 0, t = 0;
   a.gpref[0] = 0;
@@ -68,6 +79,7 @@ __global__ void __launch_bounds__(256) sort_prep_kernel(SortArgs a) {
     long long c = a.inst[i].count[a.species];
     const long long cap = a.inst[i].capacity[a.species];
     c = c < 0 ? 0 : (c > cap ? cap : c);
+    if (a.inst[i].frozen) c = 0;  // a frozen instance no longer steps: left as it is
     g += c;
     t += (c + kSortTile - 1) / kSortTile;
     a.gpref[i + 1] = g;
@@ -77,71 +89,115 @@ __global__ void __launch_bounds__(256) sort_prep_kernel(SortArgs a) {
   a.hdr->tiles = t;
 }
 
-__device__ __forceinline__ long long slot_of(const SortArgs& a, long long g) {
-  const int i = find_instance(a.gpref, a.n_inst, g);
-  return a.inst[i].base[a.species] + (g - a.gpref[i]);
+// Tile t of the instance-ordered tile list: its instance, items [g0, g1) of the live-slot
+// index space, the instance's tile count, and sbase such that item g sits in slot sbase + g.
+struct Tile {
+  int inst;
+  long long g0, g1, nt, sbase;
+};
+__device__ __forceinline__ bool tile_of(const SortArgs& a, long long t, Tile& T) {
+  if (t >= a.hdr->tiles) return false;
+  T.inst = find_instance(a.tpref, a.n_inst, t);
+  T.g0 = a.gpref[T.inst] + (t - a.tpref[T.inst]) * kSortTile;
+  T.g1 = T.g0 + kSortTile < a.gpref[T.inst + 1] ? T.g0 + kSortTile : a.gpref[T.inst + 1];
+  T.nt = a.tpref[T.inst + 1] - a.tpref[T.inst];
+  T.sbase = a.inst[T.inst].base[a.species] - a.gpref[T.inst];
+  return true;
 }
 
-__device__ __forceinline__ int axis_cell(double x, double org, double inv, int n) {
+__device__ __forceinline__ long long axis_block(double x, double org, double inv, int n,
+                                                int shift) {
   if (!isfinite(x)) return -1;
   const CicAxis c = cic_axis((x - org) * inv, n);
-  return c.i0;
+  return (long long)(c.i0 >> shift);
 }
 
-__global__ void __launch_bounds__(256) sort_key_kernel(SortArgs a) {
-  const long long N = a.hdr->n;
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < N; g += stride) {
-    const long long s = slot_of(a, g);
-    unsigned key = kSortDeadKey;
-    if (a.species != QED_PHOTON || a.s.id[s] != QED_ID_DEAD) {
-      const int ix = axis_cell(a.s.x[s], a.origin[0], a.inv_dx[0], a.n[0]);
-      const int iy = axis_cell(a.s.y[s], a.origin[1], a.inv_dx[1], a.n[1]);
-      const int iz = axis_cell(a.s.z[s], a.origin[2], a.inv_dx[2], a.n[2]);
-      if (ix < 0 || iy < 0 || iz < 0) {
-        key = kSortDeadKey - 1;  // non-finite position: last of the live particles
-      } else {
-        key = (unsigned)((((long long)(iz >> a.shift) * a.nb[1]) + (iy >> a.shift)) * a.nb[0] +
-                         (ix >> a.shift));
+__global__ void __launch_bounds__(kSortThreads) sort_key_kernel(SortArgs a) {
+  Tile T;
+  if (!tile_of(a, blockIdx.x, T)) return;
+  const bool photons = a.species == QED_PHOTON;
+  for (long long r0 = T.g0 + threadIdx.x; r0 < T.g1; r0 += kBatch * kSortThreads) {
+    double x[kBatch], y[kBatch], z[kBatch];
+    uint64_t id[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const long long g = r0 + (long long)u * kSortThreads;
+      if (g < T.g1) {
+        const long long s = T.sbase + g;
+        id[u] = photons ? a.s.id[s] : 0ull;
+        x[u] = a.s.x[s];
+        y[u] = a.s.y[s];
+        z[u] = a.s.z[s];
       }
     }
-    a.key[0][g] = key;
-    a.val[0][g] = (unsigned)g;
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const long long g = r0 + (long long)u * kSortThreads;
+      if (g >= T.g1) break;
+      unsigned key = a.dead;
+      if (!photons || id[u] != QED_ID_DEAD) {
+        const long long bx = axis_block(x[u], a.origin[0], a.inv_dx[0], a.n[0], a.shift);
+        const long long by = axis_block(y[u], a.origin[1], a.inv_dx[1], a.n[1], a.shift);
+        const long long bz = axis_block(z[u], a.origin[2], a.inv_dx[2], a.n[2], a.shift);
+        if (bx < 0 || by < 0 || bz < 0) key = a.dead - 1u;  // last of the live particles
+        else key = (unsigned)((bz * a.nb[1] + by) * a.nb[0] + bx);
+      }
+      a.key[0][g] = key;
+      a.val[0][g] = (unsigned)g;
+    }
   }
-}
-
-// Tile t of the instance-ordered tile list: its instance and slots [g0, g1).
-__device__ __forceinline__ bool tile_range(const SortArgs& a, long long t, int& inst,
-                                           long long& g0, long long& g1, long long& nt) {
-  if (t >= a.hdr->tiles) return false;
-  inst = find_instance(a.tpref, a.n_inst, t);
-  g0 = a.gpref[inst] + (t - a.tpref[inst]) * kSortTile;
-  g1 = g0 + kSortTile < a.gpref[inst + 1] ? g0 + kSortTile : a.gpref[inst + 1];
-  nt = a.tpref[inst + 1] - a.tpref[inst];
-  return true;
 }
 
 // Position of (instance, digit, tile) in the scanned count array: instance-major, then
 // digit, then the instance's tiles, so that the exclusive scan gives each element's slot.
-__device__ __forceinline__ long long cnt_index(const SortArgs& a, int inst, int d, long long t,
-                                               long long nt) {
-  return a.tpref[inst] * 256 + (long long)d * nt + (t - a.tpref[inst]);
+__device__ __forceinline__ long long cnt_index(const SortArgs& a, const Tile& T, int d,
+                                               long long t) {
+  return a.tpref[T.inst] * 256 + (long long)d * T.nt + (t - a.tpref[T.inst]);
 }
 
-__global__ void __launch_bounds__(256) sort_hist_kernel(SortArgs a, int pass) {
+// Lanes of this wavefront holding the same digit as this lane (eight ballots, one per bit).
+__device__ __forceinline__ uint64_t same_digit(unsigned d, bool has) {
+  uint64_t same = wave_ballot(has);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const uint64_t m = wave_ballot(((d >> b) & 1u) != 0u);
+    same &= ((d >> b) & 1u) ? m : ~m;
+  }
+  return has ? same : 0ull;
+}
+
+// A thread's items of its tile: item i is tile item i * 256 + thread (so that the order of
+// (i, thread) is the tile's order).
+__device__ __forceinline__ void load_tile_words(const unsigned* src, const Tile& T,
+                                                unsigned (&k)[kPerThread]) {
+#pragma unroll
+  for (int i = 0; i < kPerThread; ++i) {
+    const long long g = T.g0 + (long long)i * kSortThreads + threadIdx.x;
+    k[i] = g < T.g1 ? src[g] : 0u;
+  }
+}
+
+__global__ void __launch_bounds__(kSortThreads) sort_hist_kernel(SortArgs a, int pass) {
   __shared__ unsigned h[256];
-  int inst;
-  long long g0, g1, nt;
+  Tile T;
   const long long t = blockIdx.x;
-  if (!tile_range(a, t, inst, g0, g1, nt)) return;
+  if (!tile_of(a, t, T)) return;
   h[threadIdx.x] = 0u;
+  unsigned k[kPerThread];
+  load_tile_words(a.key[pass & 1], T, k);
   __syncthreads();
-  const unsigned* key = a.key[pass & 1];
   const int sh = 8 * pass;
-  for (long long g = g0 + threadIdx.x; g < g1; g += blockDim.x)
-    atomicAdd(&h[(key[g] >> sh) & 255u], 1u);
+  const uint64_t below = lanes_below();
+  // one LDS add per digit group of a wavefront (sorted keys give few groups)
+#pragma unroll
+  for (int i = 0; i < kPerThread; ++i) {
+    const bool has = T.g0 + (long long)i * kSortThreads + threadIdx.x < T.g1;
+    const unsigned d = (k[i] >> sh) & 255u;
+    const uint64_t same = same_digit(d, has);
+    if (has && (same & below) == 0ull) atomicAdd(&h[d], (unsigned)__popcll(same));
+  }
   __syncthreads();
-  a.cnt[cnt_index(a, inst, (int)threadIdx.x, t, nt)] = h[threadIdx.x];
+  a.cnt[cnt_index(a, T, (int)threadIdx.x, t)] = h[threadIdx.x];
 }
 
 // Exclusive scan of the count array in chunks of kScanChunk: per-chunk totals, a scan of the
@@ -166,7 +222,7 @@ __device__ unsigned block_exclusive_scan(unsigned v, unsigned* sw, unsigned& tot
   return base + x - v;
 }
 
-__global__ void __launch_bounds__(256) scan_chunks_kernel(SortArgs a) {
+__global__ void __launch_bounds__(kSortThreads) scan_chunks_kernel(SortArgs a) {
   __shared__ unsigned sw[4];
   const long long M = a.hdr->tiles * 256;
   const long long c0 = (long long)blockIdx.x * kScanChunk;
@@ -179,7 +235,7 @@ __global__ void __launch_bounds__(256) scan_chunks_kernel(SortArgs a) {
   if (threadIdx.x == 0) a.sums[blockIdx.x] = total;
 }
 
-__global__ void __launch_bounds__(256) scan_sums_kernel(SortArgs a) {
+__global__ void __launch_bounds__(kSortThreads) scan_sums_kernel(SortArgs a) {
   __shared__ unsigned sw[4];
   const long long M = a.hdr->tiles * 256;
   const long long chunks = (M + kScanChunk - 1) / kScanChunk;
@@ -194,13 +250,13 @@ __global__ void __launch_bounds__(256) scan_sums_kernel(SortArgs a) {
   }
 }
 
-__global__ void __launch_bounds__(256) scan_apply_kernel(SortArgs a) {
+__global__ void __launch_bounds__(kSortThreads) scan_apply_kernel(SortArgs a) {
   __shared__ unsigned sw[4];
   const long long M = a.hdr->tiles * 256;
   const long long c0 = (long long)blockIdx.x * kScanChunk;
   if (c0 >= M) return;
   // each thread scans 16 consecutive entries; the threads' totals are scanned together
-  constexpr int per = kScanChunk / 256;
+  constexpr int per = kScanChunk / kSortThreads;
   const long long i0 = c0 + (long long)threadIdx.x * per;
   unsigned v[per];
   unsigned s = 0;
@@ -218,41 +274,32 @@ __global__ void __launch_bounds__(256) scan_apply_kernel(SortArgs a) {
   }
 }
 
-// Stable scatter of one tile: items are taken in 16 rounds of 256 (round r holds tile items
-// r*256 .. r*256+255, in thread order), so the order of (round, thread) is the tile's order.
-// An item's rank among the tile's items of its digit is the count so far of that digit, plus
-// the items of that digit in the round's earlier wavefronts, plus those on lower lanes of its
-// own wavefront (found with eight ballots, one per digit bit).
-__global__ void __launch_bounds__(256) sort_scatter_kernel(SortArgs a, int pass) {
+// Stable scatter of one tile: the thread's 16 items (keys and indices) are loaded first;
+// round i holds tile items i*256 .. i*256+255 in thread order.  An item's rank among the
+// tile's items of its digit is the count so far of that digit, plus the items of that digit
+// in the round's earlier wavefronts, plus those on lower lanes of its own wavefront.
+__global__ void __launch_bounds__(kSortThreads) sort_scatter_kernel(SortArgs a, int pass) {
   __shared__ unsigned base[256];   // where the tile's next item of each digit goes
   __shared__ unsigned wcnt[4][256];
-  int inst;
-  long long g0, g1, nt;
+  Tile T;
   const long long t = blockIdx.x;
-  if (!tile_range(a, t, inst, g0, g1, nt)) return;
-  const int tid = (int)threadIdx.x, w = tid >> 6, lane = lane_id();
-  base[tid] = a.cnt[cnt_index(a, inst, tid, t, nt)];
+  if (!tile_of(a, t, T)) return;
+  const int tid = (int)threadIdx.x, w = tid >> 6;
+  unsigned k[kPerThread], v[kPerThread];
+  load_tile_words(a.key[pass & 1], T, k);
+  load_tile_words(a.val[pass & 1], T, v);
+  base[tid] = a.cnt[cnt_index(a, T, tid, t)];
   for (int q = 0; q < 4; ++q) wcnt[q][tid] = 0u;
   __syncthreads();
-  const unsigned* kin = a.key[pass & 1];
-  const unsigned* vin = a.val[pass & 1];
   unsigned* kout = a.key[(pass + 1) & 1];
   unsigned* vout = a.val[(pass + 1) & 1];
   const int sh = 8 * pass;
   const uint64_t below = lanes_below();
-  for (long long r0 = g0; r0 < g1; r0 += blockDim.x) {
-    const long long g = r0 + tid;
-    const bool has = g < g1;
-    const unsigned k = has ? kin[g] : 0u;
-    const unsigned v = has ? vin[g] : 0u;
-    const unsigned d = (k >> sh) & 255u;
-    uint64_t same = wave_ballot(has);
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const uint64_t m = wave_ballot(((d >> b) & 1u) != 0u);
-      same &= ((d >> b) & 1u) ? m : ~m;
-    }
-    if (!has) same = 0;
+  for (int i = 0; i < kPerThread; ++i) {
+    const bool has = T.g0 + (long long)i * kSortThreads + tid < T.g1;
+    const unsigned d = (k[i] >> sh) & 255u;
+    const uint64_t same = same_digit(d, has);
     const unsigned in_wave = (unsigned)__popcll(same & below);
     // the lowest lane of each digit group records the group's size
     if (has && in_wave == 0u) wcnt[w][d] = (unsigned)__popcll(same);
@@ -261,8 +308,8 @@ __global__ void __launch_bounds__(256) sort_scatter_kernel(SortArgs a, int pass)
       unsigned before = 0;
       for (int q = 0; q < w; ++q) before += wcnt[q][d];
       const unsigned pos = base[d] + before + in_wave;
-      kout[pos] = k;
-      vout[pos] = v;
+      kout[pos] = k[i];
+      vout[pos] = v[i];
     }
     __syncthreads();
     // advance the digit bases by the round's counts and clear them for the next round
@@ -301,72 +348,131 @@ __device__ __forceinline__ ColView col_view(const SortArgs& a) {
   return c;
 }
 
-__global__ void __launch_bounds__(256) sort_gather_kernel(SortArgs a, int last) {
-  const long long N = a.hdr->n;
+// One particle's columns.
+struct Item {
+  double d[7];
+  unsigned long long id, parent;
+  unsigned birth, nev;
+};
+
+// Items of the tile in sorted order (through the permutation, which stays inside the
+// instance) into the workspace rows of the same index.
+__global__ void __launch_bounds__(kSortThreads) sort_gather_kernel(SortArgs a, int last) {
+  Tile T;
+  if (!tile_of(a, blockIdx.x, T)) return;
   const ColView c = col_view(a);
   const unsigned* perm = a.val[last];
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < N; g += stride) {
-    const long long s = slot_of(a, (long long)perm[g]);
-    c.d[0][g] = a.s.x[s];
-    c.d[1][g] = a.s.y[s];
-    c.d[2][g] = a.s.z[s];
-    c.d[3][g] = a.s.px[s];
-    c.d[4][g] = a.s.py[s];
-    c.d[5][g] = a.s.pz[s];
-    c.d[6][g] = a.s.w[s];
-    c.id[g] = a.s.id[s];
-    c.parent[g] = a.s.parent[s];
-    c.birth[g] = a.s.birth[s];
-    if (a.s.n_events) c.nev[g] = a.s.n_events[s];
+  const qed_soa& s = a.s;
+  const bool nev = s.n_events != nullptr;
+  for (long long r0 = T.g0 + threadIdx.x; r0 < T.g1; r0 += kBatch * kSortThreads) {
+    Item it[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const long long g = r0 + (long long)u * kSortThreads;
+      if (g < T.g1) {
+        const long long i = T.sbase + (long long)perm[g];
+        it[u].d[0] = s.x[i];
+        it[u].d[1] = s.y[i];
+        it[u].d[2] = s.z[i];
+        it[u].d[3] = s.px[i];
+        it[u].d[4] = s.py[i];
+        it[u].d[5] = s.pz[i];
+        it[u].d[6] = s.w[i];
+        it[u].id = s.id[i];
+        it[u].parent = s.parent[i];
+        it[u].birth = s.birth[i];
+        it[u].nev = nev ? s.n_events[i] : 0u;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const long long g = r0 + (long long)u * kSortThreads;
+      if (g >= T.g1) break;
+      for (int k = 0; k < 7; ++k) c.d[k][g] = it[u].d[k];
+      c.id[g] = it[u].id;
+      c.parent[g] = it[u].parent;
+      c.birth[g] = it[u].birth;
+      c.nev[g] = it[u].nev;
+    }
   }
 }
 
-__global__ void __launch_bounds__(256) sort_store_kernel(SortArgs a) {
-  const long long N = a.hdr->n;
+__global__ void __launch_bounds__(kSortThreads) sort_store_kernel(SortArgs a) {
+  Tile T;
+  if (!tile_of(a, blockIdx.x, T)) return;
   const ColView c = col_view(a);
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < N; g += stride) {
-    const long long s = slot_of(a, g);
-    a.s.x[s] = c.d[0][g];
-    a.s.y[s] = c.d[1][g];
-    a.s.z[s] = c.d[2][g];
-    a.s.px[s] = c.d[3][g];
-    a.s.py[s] = c.d[4][g];
-    a.s.pz[s] = c.d[5][g];
-    a.s.w[s] = c.d[6][g];
-    a.s.id[s] = c.id[g];
-    a.s.parent[s] = c.parent[g];
-    a.s.birth[s] = c.birth[g];
-    if (a.s.n_events) a.s.n_events[s] = c.nev[g];
+  const qed_soa& s = a.s;
+  const bool nev = s.n_events != nullptr;
+  for (long long r0 = T.g0 + threadIdx.x; r0 < T.g1; r0 += kBatch * kSortThreads) {
+    Item it[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const long long g = r0 + (long long)u * kSortThreads;
+      if (g < T.g1) {
+        for (int k = 0; k < 7; ++k) it[u].d[k] = c.d[k][g];
+        it[u].id = c.id[g];
+        it[u].parent = c.parent[g];
+        it[u].birth = c.birth[g];
+        it[u].nev = c.nev[g];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const long long g = r0 + (long long)u * kSortThreads;
+      if (g >= T.g1) break;
+      const long long i = T.sbase + g;
+      s.x[i] = it[u].d[0];
+      s.y[i] = it[u].d[1];
+      s.z[i] = it[u].d[2];
+      s.px[i] = it[u].d[3];
+      s.py[i] = it[u].d[4];
+      s.pz[i] = it[u].d[5];
+      s.w[i] = it[u].d[6];
+      s.id[i] = it[u].id;
+      s.parent[i] = it[u].parent;
+      s.birth[i] = it[u].birth;
+      if (nev) s.n_events[i] = it[u].nev;
+    }
   }
 }
 
 }  // namespace
 
-int sort_block_shift(const int n[3]) {
-  for (int s = 0; s < 31; ++s) {
+SortGeometry sort_geometry(const int n[3]) {
+  SortGeometry g{};
+  for (g.shift = 0; g.shift < 31; ++g.shift) {
     long long b = 1;
-    for (int d = 0; d < 3; ++d) b *= ((long long)n[d] + (1ll << s) - 1) >> s;
-    if (b <= (long long)kSortDeadKey - 1) return s;
+    for (int d = 0; d < 3; ++d) b *= ((long long)n[d] + (1ll << g.shift) - 1) >> g.shift;
+    if (b <= (1ll << 24) - 2) break;
   }
-  return 31;
+  long long blocks = 1;
+  for (int d = 0; d < 3; ++d) {
+    g.nb[d] = ((long long)n[d] + (1ll << g.shift) - 1) >> g.shift;
+    blocks *= g.nb[d];
+  }
+  g.passes = 1;
+  while (g.passes < kSortMaxPasses && blocks > (1ll << (8 * g.passes)) - 2) ++g.passes;
+  g.dead = (unsigned)((1ull << (8 * g.passes)) - 1);
+  return g;
 }
 
 hipError_t launch_sort_cells(const qed_soa& s, int species, qed_instance* inst, int n_inst,
                              long long slots, const int n[3], const double dx[3],
                              const double origin[3], void* work, hipStream_t st) {
   const SortLayout L = SortLayout::make(n_inst, slots);
+  const SortGeometry geo = sort_geometry(n);
   unsigned char* w = static_cast<unsigned char*>(work);
   SortArgs a{};
   a.s = s;
   a.inst = inst;
   a.n_inst = n_inst;
   a.species = species;
-  a.shift = sort_block_shift(n);
+  a.shift = geo.shift;
+  a.passes = geo.passes;
+  a.dead = geo.dead;
   for (int d = 0; d < 3; ++d) {
     a.n[d] = n[d];
-    a.nb[d] = (int)(((long long)n[d] + (1ll << a.shift) - 1) >> a.shift);
+    a.nb[d] = geo.nb[d];
     a.inv_dx[d] = 1.0 / dx[d];
     a.origin[d] = origin[d];
   }
@@ -381,21 +487,20 @@ hipError_t launch_sort_cells(const qed_soa& s, int species, qed_instance* inst, 
   a.sums = reinterpret_cast<unsigned*>(w + L.sums);
   a.cols = w + L.cols;
   a.cap = L.cap;
-  const long long grid = L.tiles_max;  // one workgroup per possible tile
-  const long long chunks = (L.tiles_max * 256 + kScanChunk - 1) / kScanChunk;
-  const long long stream_blocks = (slots + 255) / 256 < 8192 ? (slots + 255) / 256 : 8192;
-  const unsigned sb = (unsigned)(stream_blocks > 0 ? stream_blocks : 1);
+  const unsigned grid = (unsigned)L.tiles_max;  // one workgroup per possible tile
+  const unsigned chunks = (unsigned)((L.tiles_max * 256 + kScanChunk - 1) / kScanChunk);
+  const dim3 blk(kSortThreads);
   hipLaunchKernelGGL(sort_prep_kernel, dim3(1), dim3(64), 0, st, a);
-  hipLaunchKernelGGL(sort_key_kernel, dim3(sb), dim3(256), 0, st, a);
-  for (int pass = 0; pass < 2; ++pass) {
-    hipLaunchKernelGGL(sort_hist_kernel, dim3((unsigned)grid), dim3(256), 0, st, a, pass);
-    hipLaunchKernelGGL(scan_chunks_kernel, dim3((unsigned)chunks), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)chunks), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(sort_scatter_kernel, dim3((unsigned)grid), dim3(256), 0, st, a, pass);
+  hipLaunchKernelGGL(sort_key_kernel, dim3(grid), blk, 0, st, a);
+  for (int pass = 0; pass < geo.passes; ++pass) {
+    hipLaunchKernelGGL(sort_hist_kernel, dim3(grid), blk, 0, st, a, pass);
+    hipLaunchKernelGGL(scan_chunks_kernel, dim3(chunks), blk, 0, st, a);
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), blk, 0, st, a);
+    hipLaunchKernelGGL(scan_apply_kernel, dim3(chunks), blk, 0, st, a);
+    hipLaunchKernelGGL(sort_scatter_kernel, dim3(grid), blk, 0, st, a, pass);
   }
-  hipLaunchKernelGGL(sort_gather_kernel, dim3(sb), dim3(256), 0, st, a, 0);
-  hipLaunchKernelGGL(sort_store_kernel, dim3(sb), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(sort_gather_kernel, dim3(grid), blk, 0, st, a, geo.passes & 1);
+  hipLaunchKernelGGL(sort_store_kernel, dim3(grid), blk, 0, st, a);
   return hipGetLastError();
 }
 

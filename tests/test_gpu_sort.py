@@ -1,8 +1,8 @@
 """qed_sort_cells through the C ABI: the order of every instance's segment after the sort
 equals a stable sort, on the host, of the cell-block keys computed with the same arithmetic
 (cell = floor((x - origin) / dx) per axis, periodic; blocks of 2^s cells per axis, s the
-smallest that leaves at most 65534 blocks; removed photons last, non-finite positions just
-before them), column for column; and a grid cascade whose stores are sorted every other step
+smallest that leaves at most 2^24 - 2 blocks; removed photons last, non-finite positions
+just before them), column for column; and a grid cascade whose stores are sorted every other step
 still equals the oracle in every store and every step's record (the sort moves slots only)."""
 import math
 
@@ -33,9 +33,12 @@ def _note(msg):
 
 def host_keys(cols, n, dx, origin, dead):
     s = 0
-    while math.prod((v + (1 << s) - 1) >> s for v in n) > 65534:
+    while math.prod((v + (1 << s) - 1) >> s for v in n) > (1 << 24) - 2:
         s += 1
     nb = [(v + (1 << s) - 1) >> s for v in n]
+    # keys of 8, 16 or 24 bits: the fewest that hold every block and the two reserved keys
+    passes = next(p for p in (1, 2, 3) if math.prod(nb) <= (1 << (8 * p)) - 2 or p == 3)
+    top = (1 << (8 * passes)) - 1
     cell = []
     for d, c in enumerate(("x", "y", "z")):
         v = (cols[c] - origin[d]) * (1.0 / dx[d])
@@ -47,17 +50,18 @@ def host_keys(cols, n, dx, origin, dead):
         cell.append((i, ok))
     (ix, okx), (iy, oky), (iz, okz) = cell
     key = ((iz >> s) * nb[1] + (iy >> s)) * nb[0] + (ix >> s)
-    key = np.where(okx & oky & okz, key, 65534)
-    return np.where(dead, 65535, key)
+    key = np.where(okx & oky & okz, key, top - 1)
+    return np.where(dead, top, key)
 
 
-@pytest.mark.parametrize("n", [(7, 5, 4), (256, 256, 256), (300, 2, 9)])
+@pytest.mark.parametrize("n", [(7, 5, 4), (256, 256, 256), (300, 2, 9), (40, 40, 40),
+                               (300, 300, 300)])
 def test_sort_order_matches_a_stable_host_sort(n):
     rng = np.random.default_rng(sum(n))
     dx, origin = (0.7, 1.1, 0.45), (-2.0, 3.0, 0.5)
-    caps = [(9000, 700, 30000), (10, 10, 10), (5000, 900, 12000)]
-    counts = [(8000, 650, 25000), (0, 0, 0), (4096, 1, 4097)]
-    e = Engine(caps, [1, 2, 3])
+    caps = [(9000, 700, 30000), (10, 10, 10), (5000, 900, 12000), (300, 300, 300)]
+    counts = [(8000, 650, 25000), (0, 0, 0), (4096, 1, 4097), (290, 280, 270)]
+    e = Engine(caps, [1, 2, 3, 4])
     for i, cnt in enumerate(counts):
         for sp in range(3):
             m = cnt[sp]
@@ -73,6 +77,7 @@ def test_sort_order_matches_a_stable_host_sort(n):
                 cols["x"][: m // 50] = np.nan
             cols["n_events"] = rng.integers(0, 9, m, dtype=np.uint32)
             e.load(i, sp, cols)
+    e.set_frozen(3)  # a frozen instance is not sorted
     before = [[e.read(i, sp) for sp in range(3)] for i in range(len(caps))]
     f = Engine.make_field(Q.QED_FIELD_YEE, grid=[torch.zeros(1, device="cuda")] * 6, n=n,
                           dx=dx, origin=origin)
@@ -85,6 +90,8 @@ def test_sort_order_matches_a_stable_host_sort(n):
             b = before[i][sp]
             dead = (b["id"] == DEAD) if sp == 2 else np.zeros(len(b["id"]), bool)
             order = np.argsort(host_keys(b, n, dx, origin, dead), kind="stable")
+            if i == 3:
+                order = np.arange(len(order))
             got = e.read(i, sp)
             for c, v in b.items():
                 assert np.array_equal(got[c], v[order], equal_nan=True), (n, i, sp, c)
