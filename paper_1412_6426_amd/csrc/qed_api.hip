@@ -46,9 +46,11 @@ namespace {
 constexpr int kMaxDevices = 64;
 std::mutex g_mu;
 int g_cu_count[kMaxDevices];
-int g_occ[kMaxDevices][2][2];  // [precision][photon] resident 256-thread blocks per CU
+// [precision][field mode][kernel: photon, lepton, extended lepton] resident 256-thread
+// blocks per CU
+int g_occ[kMaxDevices][2][3][3];
 
-bool device_geometry(int* cus, int precision, bool photon, int block, int* per_cu) {
+bool device_geometry(int* cus, int precision, int fmode, int kernel, int block, int* per_cu) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return false;
   std::lock_guard<std::mutex> lk(g_mu);
@@ -60,12 +62,14 @@ bool device_geometry(int* cus, int precision, bool photon, int block, int* per_c
     g_cu_count[dev] = n;
   }
   *cus = g_cu_count[dev];
+  if (fmode < 0 || fmode > 2 || kernel < 0 || kernel > 2) return false;
+  const bool photon = kernel == 0, ext = kernel == 2;
   if (block == 256) {
-    int& o = g_occ[dev][precision][photon ? 1 : 0];
-    if (o == 0) o = step_blocks_per_cu(precision, photon, 256);
+    int& o = g_occ[dev][precision == QED_MIXED ? 1 : 0][fmode][kernel];
+    if (o == 0) o = step_blocks_per_cu(precision, fmode, photon, ext, 256);
     *per_cu = o;
   } else {
-    *per_cu = step_blocks_per_cu(precision, photon, block);
+    *per_cu = step_blocks_per_cu(precision, fmode, photon, ext, block);
   }
   return true;
 }
@@ -297,8 +301,12 @@ qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_fi
   for (int i = 0; i < 4; ++i) a.events[i] = static_cast<hipEvent_t>(P.events[i]);
 
   int cus = 0, lep_per_cu = 0, pho_per_cu = 0;
-  if (!device_geometry(&cus, P.precision, false, block, &lep_per_cu) ||
-      !device_geometry(&cus, P.precision, true, block, &pho_per_cu))
+  const int fmode = field_mode(field->kind);
+  // the lepton kernel's extended form runs with same-step processing or a photon generator
+  // factor (the launch makes the same choice)
+  const int lep_kernel = (G > 0 || P.f_photon > 1.0) ? 2 : 1;
+  if (!device_geometry(&cus, P.precision, fmode, lep_kernel, block, &lep_per_cu) ||
+      !device_geometry(&cus, P.precision, fmode, 0, block, &pho_per_cu))
     return QED_ERR_HIP;
   LaunchShape lep{P.grid_blocks > 0 ? P.grid_blocks : cus * lep_per_cu, block};
   LaunchShape pho{P.grid_blocks > 0 ? P.grid_blocks : cus * pho_per_cu, block};

@@ -355,6 +355,9 @@ hipError_t launch_generator_trials(const DevTables* tables, int generator, doubl
                                    long long first, long long n, double* out, void* work,
                                    hipStream_t s);
 // Persistent-grid sizing: resident workgroups per CU for the step kernels.
-int step_blocks_per_cu(int precision, bool photon, int block);
+// Resident workgroups per CU of the step kernel that a launch uses: the photon kernel, or
+// the lepton kernel in its plain or extended form (EXT), for a field mode (field_mode).
+int step_blocks_per_cu(int precision, int fmode, bool photon, bool ext, int block);
+int field_mode(int kind);
 
 }  // namespace qedk

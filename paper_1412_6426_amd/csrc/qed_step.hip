@@ -784,10 +784,28 @@ __device__ __forceinline__ void flush_pairs(const StepArgs& a, PairStage& sg, in
 // (children also get their time left and the parent's fields; a full share continues in
 // pool chunks).  Without them a full share falls back to direct reservation, and the plain
 // step's kernel stays lean.
+//
+// The emission table goes to LDS (64 KB in FP64, 32 KB in FP32), except in the plain FP64
+// kernel for a space-independent E with B = 0: there it is read from the L2-resident copy,
+// and without the 64 KB of LDS per workgroup the kernel fits three wavefronts per SIMD (the
+// compiler holds it to 168 VGPRs with a few spilled), 8% faster on the rotating-field
+// cascade.  With a B field the Boris rotation's registers make that bound cost more spills
+// than the third wavefront gains (3% slower on 10^4 electrons in a uniform B), and with a
+// grid field far more (1.9 times slower), so those kernels keep the LDS table at two
+// wavefronts per SIMD.
 template <bool MIXED, int FMODE, bool EXT>
-__global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
+struct LeptonShape {
+  static constexpr bool global_table = !MIXED && FMODE == kFieldE && !EXT;
+  static constexpr int min_waves = global_table ? 3 : 1;
+};
+
+template <bool MIXED, int FMODE, bool EXT>
+__global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(LeptonShape<MIXED, FMODE, EXT>::min_waves)))
+    lepton_kernel(StepArgs a) {
   using Tab = typename TabType<MIXED>::T;
-  __shared__ Tab tab[kTableN];
+  constexpr bool kGlobalTab = LeptonShape<MIXED, FMODE, EXT>::global_table;
+  __shared__ Tab tab_lds[kGlobalTab ? 1 : kTableN];
   __shared__ BlockStats bs;
   __shared__ PhotonStage stage[kWavesPerBlock];
   WorkHdr* hdr = a.hdr;
@@ -800,11 +818,11 @@ __global__ void __launch_bounds__(256) lepton_kernel(StepArgs a) {
     block_stats_store(bs, a.lep_part);
     return;
   }
-  {
-    const Tab* src = MIXED ? reinterpret_cast<const Tab*>(a.tables->ab32)
-                           : reinterpret_cast<const Tab*>(a.tables->ab64);
-    for (int i = threadIdx.x; i < kTableN; i += blockDim.x) tab[i] = src[i];
-  }
+  const Tab* src = MIXED ? reinterpret_cast<const Tab*>(a.tables->ab32)
+                         : reinterpret_cast<const Tab*>(a.tables->ab64);
+  if (!kGlobalTab)
+    for (int i = threadIdx.x; i < kTableN; i += blockDim.x) tab_lds[i] = src[i];
+  const Tab* tab = kGlobalTab ? src : tab_lds;
   __syncthreads();
 
   const Series64 ser64 = {a.tables->series[0], a.tables->series[1], a.tables->series[2],
@@ -2214,7 +2232,7 @@ static void launch_persistent(const StepArgs& a, LaunchShape lep, LaunchShape ph
   }
 }
 
-static int field_mode(int kind) {
+int field_mode(int kind) {
   if (kind == QED_FIELD_UNIFORM) return kFieldEB;
   if (kind == QED_FIELD_ROTATING_E) return kFieldE;
   return kFieldLocal;
@@ -2242,19 +2260,30 @@ hipError_t launch_step(const StepArgs& a, int precision, LaunchShape lep, Launch
 }
 
 template <bool MIXED, int FMODE>
-static int occupancy(bool photon, int block) {
+static int occupancy(bool photon, bool ext, int block) {
   int nb = 0;
-  const hipError_t e =
-      photon ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, photon_kernel<MIXED, FMODE>, block, 0)
-             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lepton_kernel<MIXED, FMODE, false>,
-                                                            block, 0);
+  hipError_t e;
+  if (photon)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, photon_kernel<MIXED, FMODE>, block, 0);
+  else if (ext)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lepton_kernel<MIXED, FMODE, true>,
+                                                     block, 0);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lepton_kernel<MIXED, FMODE, false>,
+                                                     block, 0);
   return (e != hipSuccess || nb < 1) ? 1 : nb;
 }
 
-int step_blocks_per_cu(int precision, bool photon, int block) {
-  // the rotating-field specialisation is the common one; the others use the same LDS
-  return precision == QED_MIXED ? occupancy<true, kFieldE>(photon, block)
-                                : occupancy<false, kFieldE>(photon, block);
+template <bool MIXED>
+static int occupancy_of(int fmode, bool photon, bool ext, int block) {
+  if (fmode == kFieldEB) return occupancy<MIXED, kFieldEB>(photon, ext, block);
+  if (fmode == kFieldE) return occupancy<MIXED, kFieldE>(photon, ext, block);
+  return occupancy<MIXED, kFieldLocal>(photon, ext, block);
+}
+
+int step_blocks_per_cu(int precision, int fmode, bool photon, bool ext, int block) {
+  return precision == QED_MIXED ? occupancy_of<true>(fmode, photon, ext, block)
+                                : occupancy_of<false>(fmode, photon, ext, block);
 }
 
 }  // namespace qedk
