@@ -8,7 +8,8 @@
 // totals; and that the largest index each kernel can form stays inside its region: the
 // photon wavefronts' candidate lists for every wavefront count a launch can have, and the
 // child arenas' shares, pool chunks, count matrices and chunk chains for every producer
-// (the lepton kernel's grids, the exact pair kernel's, the generation kernel's).
+// (the lepton kernel's grids, the exact pair kernel's, the generation kernel's).  The same
+// for the cell sort's workspace (SortLayout) and its key geometry.
 #include <stdio.h>
 #include <stdlib.h>
 
@@ -149,6 +150,59 @@ static void check_thin(int n_inst, long long slots, const char* what) {
   CHECK(slots < (1ll << 32), "%s: 32-bit hole list", what);
 }
 
+// qed_sort_cells: regions of SortLayout, the public size, and the indices the sort kernels
+// form for `slots` slots over n_inst instances (every tile list, count matrix and scan
+// chunk the prep kernel can produce), plus the key geometry of a grid.
+static void check_sort(int n_inst, long long slots, const char* what) {
+  const SortLayout L = SortLayout::make(n_inst, slots);
+  CHECK(qed_sort_work_bytes(n_inst, slots) == L.total, "%s: qed_sort_work_bytes", what);
+  const size_t cap = (size_t)L.cap;
+  const size_t col8 = (cap * 8 + 255) & ~(size_t)255, col4 = (cap * 4 + 255) & ~(size_t)255;
+  const size_t chunks = ((size_t)L.tiles_max * 256 + 4095) / 4096;
+  std::vector<Region> r = {{L.hdr, sizeof(SortHdr), "hdr"},
+                           {L.gpref, 8 * ((size_t)n_inst + 1), "gpref"},
+                           {L.tpref, 8 * ((size_t)n_inst + 1), "tpref"},
+                           {L.key[0], 4 * cap, "key0"},
+                           {L.key[1], 4 * cap, "key1"},
+                           {L.val[0], 4 * cap, "val0"},
+                           {L.val[1], 4 * cap, "val1"},
+                           {L.cnt, 4 * 256 * (size_t)L.tiles_max, "cnt"},
+                           {L.sums, 4 * chunks, "sums"},
+                           {L.cols, 9 * col8 + 2 * col4, "cols"}};
+  check_regions(r, 0, L.total, what);
+  // the most tiles: every instance's last tile partial (live counts summing to the slots)
+  const long long s = slots > 0 ? slots : 0;
+  const long long worst = (n_inst <= s ? (s - n_inst) / kSortTile + n_inst : s);
+  CHECK(worst <= L.tiles_max, "%s: %lld tiles > %lld", what, worst, L.tiles_max);
+  CHECK(L.tiles_max < (1ll << 31), "%s: tile grid of %lld workgroups", what, L.tiles_max);
+  CHECK(chunks < (1ull << 31), "%s: scan grid", what);
+  CHECK(s < (1ll << 32), "%s: 32-bit item indices", what);
+}
+
+static void check_sort_geometry(int nx, int ny, int nz) {
+  const int n[3] = {nx, ny, nz};
+  const SortGeometry g = sort_geometry(n);
+  long long blocks = 1;
+  for (int d = 0; d < 3; ++d) {
+    CHECK(g.nb[d] == (((long long)n[d] + (1ll << g.shift) - 1) >> g.shift), "nb %d", d);
+    CHECK(((long long)(n[d] - 1) >> g.shift) < g.nb[d], "last cell's block %d", d);
+    blocks *= g.nb[d];
+  }
+  CHECK(g.passes >= 1 && g.passes <= kSortMaxPasses, "%d passes", g.passes);
+  CHECK(g.dead == (unsigned)((1ull << (8 * g.passes)) - 1), "dead key %u", g.dead);
+  // block keys 0 .. blocks - 1 stay below the non-finite key dead - 1
+  CHECK(blocks <= (long long)g.dead - 1, "%dx%dx%d: %lld blocks for dead key %u", nx, ny, nz,
+        blocks, g.dead);
+  if (g.shift > 0) {  // the smallest shift: one less would not fit
+    long long b = 1;
+    for (int d = 0; d < 3; ++d) b *= ((long long)n[d] + (1ll << (g.shift - 1)) - 1) >> (g.shift - 1);
+    CHECK(b > (1ll << 24) - 2, "%dx%dx%d: shift %d is not the smallest", nx, ny, nz, g.shift);
+  }
+  if (g.passes > 1)  // the fewest passes
+    CHECK(blocks > (1ll << (8 * (g.passes - 1))) - 2, "%dx%dx%d: %d passes", nx, ny, nz,
+          g.passes);
+}
+
 int main() {
   const long long M = 1000000;
   struct W {
@@ -177,6 +231,17 @@ int main() {
   check_thin(1, 1, "thin, one slot");
   check_thin(5, 0, "thin, no slots");
   check_thin(1, (1ll << 32) - 1, "thin, largest store");
+  check_sort(1, 200 * M, "sort, 2*10^8 photon slots");
+  check_sort(1, 25 * M, "sort, 2.5*10^7 lepton slots");
+  check_sort(64, 200 * M, "sort, 64 instances");
+  check_sort(1024, 1 * M, "sort, 1024 instances");
+  check_sort(5, 0, "sort, no slots");
+  check_sort(3, 2, "sort, fewer slots than instances");
+  check_sort(1, (1ll << 32) - 1, "sort, largest store");
+  const int grids[][3] = {{1, 1, 1}, {7, 5, 4}, {40, 40, 40}, {254, 1, 1}, {255, 1, 1},
+                          {256, 256, 256}, {300, 300, 300}, {300, 2, 9}, {65534, 1, 1},
+                          {65535, 1, 1}, {1 << 20, 1 << 5, 1 << 5}, {2147483647, 1, 1}};
+  for (const auto& g : grids) check_sort_geometry(g[0], g[1], g[2]);
   printf("%s: %d failure(s)\n", failures ? "FAIL" : "ok", failures);
   return failures ? 1 : 0;
 }

@@ -127,3 +127,50 @@ def test_sorted_grid_cascade_matches_oracle(orc):
     assert e.stats()["n_start"][2] > 100
     compare_stats(st, ost, label="sorted yee")
     compare_all(e, os_, label="sorted yee")
+
+
+def test_full_size_lepton_store_sort_properties():
+    """The grid cascade's electron store at its full size (2.5*10^7 slots, all live), sorted
+    once on the 256^3 grid as the bench sorts it: checked by properties that hold at any
+    size.  The host recomputes every key from the sorted columns: the keys do not decrease;
+    the ids are a permutation of the input's; every row carries the columns of the input row
+    with its id; and among equal keys the input order is kept (stability)."""
+    n = 25_000_000
+    rng = np.random.default_rng(7)
+    cells, dxv = 256, 2.0 * np.pi / 32.0
+    dx, origin = (dxv, dxv, dxv), (-128 * dxv, -128 * dxv, -128 * dxv)
+    # most particles in a Gaussian cloud about the focus, the rest anywhere in and around
+    # the box (periodic wrap), a few non-finite
+    pos = []
+    for d in range(3):
+        v = rng.normal(0.0, 3.0 * dxv, n)
+        far = rng.random(n) < 0.2
+        v[far] = origin[d] + rng.uniform(-0.5, 1.5, int(far.sum())) * cells * dxv
+        pos.append(v)
+    pos[1][rng.random(n) < 1e-5] = np.inf
+    cols = W._seed_columns(*pos, rng.normal(size=n), rng.normal(size=n), rng.normal(size=n),
+                           first_id=1)
+    cols["w"] = rng.random(n)
+    cols["n_events"] = rng.integers(0, 50, n, dtype=np.uint32)
+    _note("full-size sort: loading 2.5e7 electrons")
+    e = Engine([(n, 10, 10)], [5])
+    e.load(0, 0, cols)
+    f = Engine.make_field(Q.QED_FIELD_YEE, grid=[torch.zeros(1, device="cuda")] * 6,
+                          n=(cells, cells, cells), dx=dx, origin=origin)
+    _note("full-size sort: sorting")
+    e.sort_cells(0, f)
+    torch.cuda.synchronize()
+    got = e.read(0, 0)
+    del e
+    torch.cuda.empty_cache()
+    assert int(len(got["id"])) == n
+    keys = host_keys(got, (cells, cells, cells), dx, origin, np.zeros(n, bool))
+    assert np.all(np.diff(keys) >= 0), "keys decrease"
+    src = (got["id"] - np.uint64(1)).astype(np.int64)  # the input row of each output row
+    assert np.array_equal(np.sort(src), np.arange(n)), "ids are not a permutation"
+    for c in ("x", "y", "z", "px", "py", "pz", "w", "parent", "birth", "n_events"):
+        assert np.array_equal(got[c], cols[c][src], equal_nan=True), c
+    same = np.diff(keys) == 0
+    assert np.all(np.diff(src)[same] > 0), "equal keys lost their order"
+    # the sort did move rows (a trivial identity would pass the checks above)
+    assert np.count_nonzero(src != np.arange(n)) > n // 2
