@@ -1,9 +1,11 @@
 """Host-side bounds of the workspace arithmetic: tests/layout_check.cpp, built with
 AddressSanitizer and UndefinedBehaviorSanitizer on its host code (hipcc, gfx950) and linked
 against the library, checks for the benchmark's workspace shapes and edge cases that every
-region of the qed_step and qed_thin workspaces is aligned, inside and disjoint, that the
-public size functions agree with the layouts, and that the largest candidate-list and
-arena index each kernel can form stays inside its region.  It launches nothing (no GPU)."""
+region of the qed_step, qed_thin and qed_sort_cells workspaces is aligned, inside and
+disjoint, that the public size functions agree with the layouts, that the largest
+candidate-list, arena and sort-tile index each kernel can form stays inside its region, and
+that the sort's key geometry keeps every block key below the reserved keys.  It launches
+nothing (no GPU)."""
 import os
 import shutil
 import subprocess
