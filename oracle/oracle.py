@@ -53,6 +53,12 @@ class OrThinRecord(C.Structure):
                 ("weight_after", C.c_double), ("factor", C.c_double)]
 
 
+class OrThinCellsRecord(C.Structure):
+    _fields_ = [("live_before", C.c_int64), ("kept", C.c_int64), ("groups", C.c_int64),
+                ("groups_thinned", C.c_int64), ("weight_before", C.c_double),
+                ("weight_after", C.c_double)]
+
+
 class OrField(C.Structure):
     _fields_ = [("kind", C.c_int), ("e0", C.c_double * 3), ("b0", C.c_double * 3),
                 ("amp", C.c_double), ("omega", C.c_double), ("phase", C.c_double),
@@ -140,6 +146,10 @@ def lib():
         L.or_thin.argtypes = [C.POINTER(OrStore), C.c_int64, C.c_int64, C.c_uint64, C.c_int64,
                               C.POINTER(OrThinRecord)]
         L.or_thin.restype = C.c_int
+        L.or_thin_cells.argtypes = [C.POINTER(OrStore), C.c_int, C.c_int * 3, C.c_double * 3,
+                                    C.c_double * 3, C.c_int64, C.c_uint64, C.c_int64,
+                                    C.POINTER(OrThinCellsRecord)]
+        L.or_thin_cells.restype = C.c_int
         L.or_schwinger.argtypes = [C.POINTER(OrStore), C.POINTER(OrField), C.c_double,
                                    C.c_double, C.c_double, C.c_uint64, C.c_int64,
                                    C.POINTER(OrSchwingerRecord)]
@@ -467,6 +477,21 @@ def thin(store: "Store", trigger: int, target: int, seed: int, step: int) -> Dic
         raise RuntimeError("oracle thinning failed")
     store.count = int(cs.count)
     return {k: getattr(rec, k) for k, _ in OrThinRecord._fields_} | {"thinned": rc == 1}
+
+
+def thin_cells(store: "Store", is_photon: bool, n, dx, origin, max_per_cell: int, seed: int,
+               step: int) -> Dict:
+    """Thinning per block of grid cells (Sec. VI's redistribution within each cell block
+    holding more than max_per_cell particles), in place; the store ends in block order."""
+    cs = store._cstruct()
+    rec = OrThinCellsRecord()
+    rc = lib().or_thin_cells(C.byref(cs), 1 if is_photon else 0, (C.c_int * 3)(*n),
+                             (C.c_double * 3)(*dx), (C.c_double * 3)(*origin),
+                             int(max_per_cell), int(seed), int(step), C.byref(rec))
+    if rc < 0:
+        raise RuntimeError("oracle thinning per cell failed")
+    store.count = int(cs.count)
+    return {k: getattr(rec, k) for k, _ in OrThinCellsRecord._fields_} | {"thinned": rc == 1}
 
 
 def run(stores: Sequence[Store], fld: Field, params: Params, n_steps: int,

@@ -909,6 +909,152 @@ int or_thin(or_store *s, int64_t trigger, int64_t target, uint64_t seed, int64_t
 }
 
 /* ------------------------------------------------------------------------------------
+ * Thinning per cell: Sec. VI's global even redistribution applied within each block of
+ * cells, to the groups holding more than max_per_cell particles.
+ * ------------------------------------------------------------------------------------ */
+typedef struct {
+  int64_t key, slot;
+} or_keyed;
+
+static int or_keyed_cmp(const void *a, const void *b) {
+  const or_keyed *u = (const or_keyed *)a, *v = (const or_keyed *)b;
+  if (u->key != v->key) return u->key < v->key ? -1 : 1;
+  return u->slot < v->slot ? -1 : (u->slot > v->slot ? 1 : 0);
+}
+
+/* The block of a position, or -1 for a non-finite coordinate. */
+static int64_t or_block_of(const double x[3], const int n[3], const double dx[3],
+                           const double origin[3], int shift, const int64_t nb[3]) {
+  int64_t b[3];
+  for (int d = 0; d < 3; ++d) {
+    if (!isfinite(x[d])) return -1;
+    const double fl = floor((x[d] - origin[d]) / dx[d]);
+    double c = fmod(fl, (double)n[d]); /* exact for integers below 2^53 */
+    if (c < 0.0) c += (double)n[d];
+    b[d] = (int64_t)c >> shift;
+  }
+  return (b[2] * nb[1] + b[1]) * nb[0] + b[0];
+}
+
+int or_thin_cells(or_store *s, int is_photon, const int n[3], const double dx[3],
+                  const double origin[3], int64_t max_per_cell, uint64_t seed, int64_t step,
+                  or_thin_cells_record *rec) {
+  memset(rec, 0, sizeof(*rec));
+  /* the coarsest grouping that still numbers every block below 2^24 - 2 */
+  int shift = 0;
+  int64_t nb[3];
+  for (;; ++shift) {
+    int64_t blocks = 1;
+    for (int d = 0; d < 3; ++d) {
+      nb[d] = ((int64_t)n[d] + ((int64_t)1 << shift) - 1) >> shift;
+      blocks *= nb[d];
+    }
+    if (blocks <= ((int64_t)1 << 24) - 2) break;
+  }
+  const int64_t nonfinite = nb[0] * nb[1] * nb[2]; /* after every block */
+  or_keyed *order = (or_keyed *)malloc(sizeof(or_keyed) * (size_t)(s->count > 0 ? s->count : 1));
+  double *u = (double *)malloc(sizeof(double) * (size_t)(s->count > 0 ? s->count : 1));
+  unsigned char *keep = (unsigned char *)malloc((size_t)(s->count > 0 ? s->count : 1));
+  double *factor = (double *)malloc(sizeof(double) * (size_t)(s->count > 0 ? s->count : 1));
+  if (!order || !u || !keep || !factor) {
+    free(order), free(u), free(keep), free(factor);
+    return -1;
+  }
+  int64_t live = 0;
+  for (int64_t i = 0; i < s->count; ++i) {
+    if (is_photon && s->id[i] == OR_ID_DEAD) continue;
+    const double x[3] = {s->x[i], s->y[i], s->z[i]};
+    const int64_t b = or_block_of(x, n, dx, origin, shift, nb);
+    order[live].key = b < 0 ? nonfinite : b;
+    order[live].slot = i;
+    ++live;
+  }
+  qsort(order, (size_t)live, sizeof(or_keyed), or_keyed_cmp);
+  rec->live_before = live;
+  for (int64_t a = 0; a < live;) {
+    int64_t e = a;
+    while (e < live && order[e].key == order[a].key) ++e;
+    const int64_t m = e - a;
+    double W = 0.0;
+    for (int64_t j = a; j < e; ++j) W += s->w[order[j].slot];
+    rec->groups += 1;
+    rec->weight_before += W;
+    if (m <= max_per_cell) {
+      for (int64_t j = a; j < e; ++j) {
+        keep[j] = 1;
+        factor[j] = 1.0;
+      }
+      rec->weight_after += W;
+    } else {
+      rec->groups_thinned += 1;
+      const double q = (double)max_per_cell / (double)m;
+      double K = 0.0;
+      int64_t kept = 0, first_min = a;
+      for (int64_t j = a; j < e; ++j) {
+        const uint64_t id = s->id[order[j].slot];
+        uint32_t ctr[4] = {(uint32_t)step, 11u << 16, (uint32_t)seed, (uint32_t)(seed >> 32)};
+        uint32_t key[2] = {(uint32_t)id, (uint32_t)(id >> 32)};
+        uint32_t o[4];
+        or_philox4x32_10(ctr, key, o);
+        u[j] = or_uniform(o[0], o[1]);
+        keep[j] = u[j] < q;
+        if (keep[j]) {
+          ++kept;
+          K += s->w[order[j].slot];
+        }
+        if (u[j] < u[first_min]) first_min = j;
+      }
+      if (kept == 0) { /* the group keeps its weight in its smallest draw */
+        keep[first_min] = 1;
+        K = s->w[order[first_min].slot];
+      }
+      const double f = W / K;
+      double Wa = 0.0;
+      for (int64_t j = a; j < e; ++j) {
+        factor[j] = f;
+        if (keep[j]) Wa += s->w[order[j].slot] * f;
+      }
+      rec->weight_after += Wa;
+    }
+    a = e;
+  }
+  /* survivors in group order; the columns are copied out first, since the order moves
+   * particles both ways */
+  or_store t = *s;
+  const size_t nn = (size_t)(s->count > 0 ? s->count : 1);
+  double *cp = (double *)malloc(sizeof(double) * nn * 7);
+  uint64_t *cu = (uint64_t *)malloc(sizeof(uint64_t) * nn * 2);
+  uint32_t *cb = (uint32_t *)malloc(sizeof(uint32_t) * nn * 2);
+  if (!cp || !cu || !cb) {
+    free(order), free(u), free(keep), free(factor), free(cp), free(cu), free(cb);
+    return -1;
+  }
+  for (int64_t i = 0; i < s->count; ++i) {
+    cp[7 * i + 0] = t.x[i], cp[7 * i + 1] = t.y[i], cp[7 * i + 2] = t.z[i];
+    cp[7 * i + 3] = t.px[i], cp[7 * i + 4] = t.py[i], cp[7 * i + 5] = t.pz[i];
+    cp[7 * i + 6] = t.w[i];
+    cu[2 * i] = t.id[i], cu[2 * i + 1] = t.parent[i];
+    cb[2 * i] = t.birth[i], cb[2 * i + 1] = t.n_events ? t.n_events[i] : 0u;
+  }
+  int64_t k = 0;
+  for (int64_t j = 0; j < live; ++j) {
+    if (!keep[j]) continue;
+    const int64_t i = order[j].slot;
+    s->x[k] = cp[7 * i + 0], s->y[k] = cp[7 * i + 1], s->z[k] = cp[7 * i + 2];
+    s->px[k] = cp[7 * i + 3], s->py[k] = cp[7 * i + 4], s->pz[k] = cp[7 * i + 5];
+    s->w[k] = cp[7 * i + 6] * factor[j];
+    s->id[k] = cu[2 * i], s->parent[k] = cu[2 * i + 1];
+    s->birth[k] = cb[2 * i];
+    if (s->n_events) s->n_events[k] = cb[2 * i + 1];
+    ++k;
+  }
+  s->count = k;
+  rec->kept = k;
+  free(order), free(u), free(keep), free(factor), free(cp), free(cu), free(cb);
+  return rec->groups_thinned > 0 ? 1 : 0;
+}
+
+/* ------------------------------------------------------------------------------------
  * Non-perturbative pair production (Sec. V.B): per grid cell and step, a pair with
  * probability R_S V c dt from the cell's field.
  * ------------------------------------------------------------------------------------ */

@@ -162,6 +162,31 @@ typedef struct {
 int or_thin(or_store *s, int64_t trigger, int64_t target, uint64_t seed, int64_t step,
             or_thin_record *rec);
 
+/* Thinning per cell (Sec. VI's redistribution applied within a cell; Sec. VII's thinning
+ * that caps the particles a cell may hold).  The live particles of the store are grouped
+ * by the block of cells that holds them: cell (i, j, k) = floor((x - origin) / dx) per axis,
+ * periodic (wrapped into [0, n)); block = cell >> s per axis, s the smallest shift that
+ * leaves at most 2^24 - 2 blocks on the n[0] x n[1] x n[2] grid; blocks numbered x fastest;
+ * particles with a non-finite coordinate form one more group after every block.  Groups
+ * are taken in block order, and the particles of a group in store order.  A group of at
+ * most `max_per_cell` particles is kept as it is.  In a larger group of n particles each
+ * survives with probability q = max_per_cell / n, decided by the Philox draw keyed by its
+ * id with counter (step, 11 << 16, seed lo, seed hi) (first two words as the uniform u;
+ * kept iff u < q); if none survives, the one with the smallest u does; the survivors'
+ * weights are multiplied by W / K, the group's weight over its survivors' weight (sums in
+ * group order), so each group keeps its weight.  The store is rewritten with the survivors
+ * in group order (removed photons, is_photon with dead ids, go) and its count set to their
+ * number.  rec: live particles before and after, groups (non-empty, removed photons not
+ * counted), groups thinned, and the live weight before and after (each the sum over groups
+ * in order of the group's sum in order). */
+typedef struct {
+  int64_t live_before, kept, groups, groups_thinned;
+  double weight_before, weight_after;
+} or_thin_cells_record;
+int or_thin_cells(or_store *s, int is_photon, const int n[3], const double dx[3],
+                  const double origin[3], int64_t max_per_cell, uint64_t seed, int64_t step,
+                  or_thin_cells_record *rec);
+
 /* Non-perturbative (Schwinger) pairs of Sec. V.B on a periodic Yee grid (f->kind ==
  * OR_FIELD_YEE), one global step n = step of length dt.  The field of cell (i, j, k), the
  * box [i, i+1) x [j, j+1) x [k, k+1) in units of dx from the origin, is taken as constant:

@@ -108,6 +108,19 @@ MUTANTS = [
     ("largest pair probability taken over every decision",
      "if (r2 < P && P > s->max_p_pair)", "if (P > s->max_p_pair)",
      ["tests/test_oracle_stats.py::test_largest_pair_probability_is_that_of_a_pair_made"]),
+    ("cell thinning that scales survivors by the group's count ratio, not its weight ratio",
+     "      const double f = W / K;", "      const double f = (double)m / (double)kept;",
+     ["tests/test_oracle_thin_cells.py"]),
+    ("cell thinning that groups by x alone",
+     "  return (b[2] * nb[1] + b[1]) * nb[0] + b[0];", "  return b[0];",
+     ["tests/test_oracle_thin_cells.py"]),
+    ("cell thinning that lets an empty group lose its weight",
+     "      if (kept == 0) { /* the group keeps its weight in its smallest draw */",
+     "      if (kept < 0) { /* the group keeps its weight in its smallest draw */",
+     ["tests/test_oracle_thin_cells.py"]),
+    ("cell thinning with the global thinning's draw purpose",
+     "uint32_t ctr[4] = {(uint32_t)step, 11u << 16,", "uint32_t ctr[4] = {(uint32_t)step, 4u << 16,",
+     ["tests/test_oracle_thin_cells.py"]),
 ]
 
 
