@@ -354,6 +354,44 @@ size_t qed_sort_work_bytes(int n_instances, int64_t species_slots);
 qed_status qed_sort_cells(const qed_stores *stores, int species, const qed_field *field,
                           void *d_work, size_t work_bytes, void *stream);
 
+/* Result of qed_thin_cells for one instance (device memory, one record per instance; all
+ * zero for a frozen instance). */
+typedef struct {
+  int64_t live_before;     /* live particles before (removed photons excluded) */
+  int64_t kept;            /* live particles after */
+  int64_t groups;          /* non-empty cell blocks (and the non-finite group, if any) */
+  int64_t groups_thinned;  /* groups that held more than max_per_cell particles */
+  double weight_before;    /* sum of w over the live particles before */
+  double weight_after;     /* after (equal up to rounding: every group keeps its weight) */
+} qed_thin_cells_record;
+
+/* Workspace size of qed_thin_cells: qed_sort_work_bytes plus 32 bytes per slot of the
+ * species store (per-group starts, factors, weights and survivor counts) and two 8-byte
+ * prefixes per instance.  0 for invalid arguments. */
+size_t qed_thin_cells_work_bytes(int n_instances, int64_t species_slots);
+
+/* Thinning per cell (Sec. VI's thinning with global even redistribution applied within
+ * each cell block; Sec. VII's thinning that limits how many particles a cell holds), for
+ * one species of every instance that is not frozen.  The store is first sorted as
+ * qed_sort_cells sorts it (the same blocks of 2^s cells, with the cell of a coordinate
+ * computed as floor((x - origin) / dx), periodic); a group is then a run of particles with
+ * one key: one block, or the particles with a non-finite coordinate.  A group of at most
+ * max_per_cell particles is kept as it is.  In a group of n > max_per_cell particles each
+ * survives with probability q = max_per_cell / n, decided by the Philox draw keyed by its
+ * id with counter (*d_step, 11 << 16, instance seed lo, hi), survival iff the first two
+ * words as a uniform in (0, 1) are below q; if none survives, the particle with the
+ * smallest draw does (the first, in store order, on a tie); the survivors' weights are
+ * multiplied by the group's weight over its survivors' weight (both summed in store order),
+ * so every group keeps its weight.  The survivors are written back in sorted order
+ * (removed photons go) and the count set to their number.  d_records[n_instances]
+ * receives one record per instance.  Graph-capturable; no host synchronisation.
+ * QED_ERR_ARG for a field that is not a Yee grid, max_per_cell < 1, bad sizes or pointers;
+ * QED_ERR_UNSUPPORTED for 2^32 or more slots. */
+qed_status qed_thin_cells(const qed_stores *stores, int species, const qed_field *field,
+                          int64_t max_per_cell, const int64_t *d_step,
+                          qed_thin_cells_record *d_records, void *d_work, size_t work_bytes,
+                          void *stream);
+
 /* Counters of one qed_schwinger call (device memory; overwritten by each call). */
 typedef struct {
   int64_t cells;      /* (cell, instance) pairs visited */

@@ -352,8 +352,14 @@ size_t qed_sort_work_bytes(int n_instances, int64_t species_slots) {
   return SortLayout::make(n_instances, species_slots).total;
 }
 
-qed_status qed_sort_cells(const qed_stores* stores, int species, const qed_field* field,
-                          void* d_work, size_t work_bytes, void* stream) {
+size_t qed_thin_cells_work_bytes(int n_instances, int64_t species_slots) {
+  if (n_instances < 1 || species_slots < 0) return 0;
+  return ThinCellsLayout::make(n_instances, species_slots).total;
+}
+
+// Shared argument checks of qed_sort_cells and qed_thin_cells.
+static qed_status check_cell_args(const qed_stores* stores, int species,
+                                  const qed_field* field, void* d_work) {
   if (!stores || !field || !d_work || !stores->d_instances) return QED_ERR_ARG;
   if (species < 0 || species >= QED_NSPECIES || stores->n_instances < 1) return QED_ERR_ARG;
   if (field->kind != QED_FIELD_YEE) return QED_ERR_ARG;
@@ -363,11 +369,35 @@ qed_status qed_sort_cells(const qed_stores* stores, int species, const qed_field
   for (int d = 0; d < 3; ++d)
     if (field->n[d] < 1 || !finite_pos(field->dx[d]) || !isfinite(field->origin[d]))
       return QED_ERR_ARG;
+  if (!soa_ok(stores->species[species], false)) return QED_ERR_ARG;
+  if (reinterpret_cast<uintptr_t>(d_work) & 255u) return QED_ERR_ARG;
+  return QED_OK;
+}
+
+qed_status qed_thin_cells(const qed_stores* stores, int species, const qed_field* field,
+                          int64_t max_per_cell, const int64_t* d_step,
+                          qed_thin_cells_record* d_records, void* d_work, size_t work_bytes,
+                          void* stream) {
+  const qed_status c = check_cell_args(stores, species, field, d_work);
+  if (c != QED_OK) return c;
+  if (max_per_cell < 1 || !d_step || !d_records) return QED_ERR_ARG;
+  const long long slots = stores->slots[species];
+  if (work_bytes < qed_thin_cells_work_bytes(stores->n_instances, slots)) return QED_ERR_ARG;
+  const hipError_t e = launch_thin_cells(
+      stores->species[species], species, stores->d_instances, stores->n_instances, slots,
+      field->n, field->dx, field->origin, (long long)max_per_cell,
+      reinterpret_cast<const long long*>(d_step), d_records, d_work,
+      static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? QED_OK : QED_ERR_HIP;
+}
+
+qed_status qed_sort_cells(const qed_stores* stores, int species, const qed_field* field,
+                          void* d_work, size_t work_bytes, void* stream) {
+  const qed_status c = check_cell_args(stores, species, field, d_work);
+  if (c != QED_OK) return c;
+  const long long slots = stores->slots[species];
   const qed_soa& s = stores->species[species];
-  if (!soa_ok(s, false)) return QED_ERR_ARG;
-  if (work_bytes < qed_sort_work_bytes(stores->n_instances, slots) ||
-      (reinterpret_cast<uintptr_t>(d_work) & 255u))
-    return QED_ERR_ARG;
+  if (work_bytes < qed_sort_work_bytes(stores->n_instances, slots)) return QED_ERR_ARG;
   const hipError_t e = launch_sort_cells(s, species, stores->d_instances, stores->n_instances,
                                          slots, field->n, field->dx, field->origin, d_work,
                                          static_cast<hipStream_t>(stream));

@@ -75,7 +75,8 @@ __device__ __forceinline__ float uniform32(uint32_t hi) {
 enum Purpose : uint32_t {
   kDraw = 0, kPhotonChild = 1, kElectronChild = 2, kPositronChild = 3, kThin = 4,
   kGenPhoton = 5, kGenPair = 6,  // generator-factor draws (Sec. VI)
-  kSchwinger = 7, kSchwingerPos = 8, kSchwingerElectron = 9, kSchwingerPositron = 10
+  kSchwinger = 7, kSchwingerPos = 8, kSchwingerElectron = 9, kSchwingerPositron = 10,
+  kThinCell = 11  // thinning per cell block
 };
 
 __device__ __forceinline__ uint4 draw_words(uint64_t id, uint64_t seed, uint32_t step, uint32_t sub,

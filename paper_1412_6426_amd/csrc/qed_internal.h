@@ -235,9 +235,11 @@ struct SortGeometry {
   long long nb[3];
 };
 struct alignas(64) SortHdr {
-  long long n;      // live slots of the species, all instances
-  long long tiles;  // tiles of the instance-ordered tile list
-  long long reserved[6];
+  long long n;       // live slots of the species, all instances
+  long long tiles;   // tiles of the instance-ordered tile list
+  long long groups;  // qed_thin_cells: groups (runs of one key), removed photons' included
+  long long kept;    // qed_thin_cells: survivors, all instances
+  long long reserved[4];
 };
 struct SortLayout {
   size_t hdr, gpref, tpref, key[2], val[2], cnt, sums, cols, total;
@@ -265,6 +267,36 @@ struct SortLayout {
     L.sums = take(sizeof(unsigned) * (((size_t)L.tiles_max * 256 + 4095) / 4096));
     const size_t col8 = (cap * 8 + 255) & ~(size_t)255, col4 = (cap * 4 + 255) & ~(size_t)255;
     L.cols = take(col8 * 9 + col4 * 2);  // x..w, id, parent; birth, n_events
+    L.total = off;
+    return L;
+  }
+};
+
+// qed_thin_cells: the sort's workspace, then per group (at most one per live slot) its first
+// item, weight factor, weight before and after, and survivors; per instance the group and
+// survivor prefixes.  The sort's second key and index arrays hold each item's group and its
+// survivor rank within its tile, its first index array the survival flags, and the count
+// array's first and second tiles_max words the per-tile group and survivor counts.
+struct ThinCellsLayout {
+  SortLayout sort;
+  size_t gstart, gfac, gw, gwa, gkept, gpfx, kpref, total;
+  static ThinCellsLayout make(int n_inst, long long slots) {
+    ThinCellsLayout L{};
+    L.sort = SortLayout::make(n_inst, slots);
+    size_t off = L.sort.total;
+    auto take = [&off](size_t bytes) {
+      size_t o = off;
+      off += (bytes + 255) & ~(size_t)255;
+      return o;
+    };
+    const size_t cap = (size_t)L.sort.cap;
+    L.gstart = take(sizeof(unsigned) * (cap + 1));
+    L.gfac = take(sizeof(double) * cap);
+    L.gw = take(sizeof(double) * cap);
+    L.gwa = take(sizeof(double) * cap);
+    L.gkept = take(sizeof(unsigned) * cap);
+    L.gpfx = take(sizeof(long long) * ((size_t)n_inst + 1));
+    L.kpref = take(sizeof(long long) * ((size_t)n_inst + 1));
     L.total = off;
     return L;
   }
@@ -344,6 +376,11 @@ hipError_t launch_sort_cells(const qed_soa& s, int species, qed_instance* inst, 
 // 2^24 - 2 blocks, and the fewest 8-bit passes whose keys hold every block and the two
 // reserved keys.
 SortGeometry sort_geometry(const int n[3]);
+hipError_t launch_thin_cells(const qed_soa& s, int species, qed_instance* inst, int n_inst,
+                             long long slots, const int n[3], const double dx[3],
+                             const double origin[3], long long max_per_cell,
+                             const long long* d_step, qed_thin_cells_record* rec, void* work,
+                             hipStream_t st);
 // Emission generators as trials (qed_generators.hip).
 long long standard_panels(double chi, double delta_min, double* u0, double* k0);
 size_t generator_work_bytes(long long panels);

@@ -44,7 +44,7 @@ struct SortArgs {
   int n[3], shift, passes;
   unsigned dead;
   long long nb[3];  // blocks per axis
-  double inv_dx[3], origin[3];
+  double dx[3], origin[3];
   SortHdr* hdr;
   long long* gpref;  // [n_inst + 1] live-slot prefix
   long long* tpref;  // [n_inst + 1] tile prefix
@@ -105,10 +105,13 @@ __device__ __forceinline__ bool tile_of(const SortArgs& a, long long t, Tile& T)
   return true;
 }
 
-__device__ __forceinline__ long long axis_block(double x, double org, double inv, int n,
+// The block of one coordinate: cell floor((x - origin) / dx), wrapped into [0, n), >> shift
+// (a division, not a product with 1/dx, so that a particle on a cell face falls in the cell
+// the definition gives).
+__device__ __forceinline__ long long axis_block(double x, double org, double dx, int n,
                                                 int shift) {
   if (!isfinite(x)) return -1;
-  const CicAxis c = cic_axis((x - org) * inv, n);
+  const CicAxis c = cic_axis((x - org) / dx, n);
   return (long long)(c.i0 >> shift);
 }
 
@@ -136,9 +139,9 @@ __global__ void __launch_bounds__(kSortThreads) sort_key_kernel(SortArgs a) {
       if (g >= T.g1) break;
       unsigned key = a.dead;
       if (!photons || id[u] != QED_ID_DEAD) {
-        const long long bx = axis_block(x[u], a.origin[0], a.inv_dx[0], a.n[0], a.shift);
-        const long long by = axis_block(y[u], a.origin[1], a.inv_dx[1], a.n[1], a.shift);
-        const long long bz = axis_block(z[u], a.origin[2], a.inv_dx[2], a.n[2], a.shift);
+        const long long bx = axis_block(x[u], a.origin[0], a.dx[0], a.n[0], a.shift);
+        const long long by = axis_block(y[u], a.origin[1], a.dx[1], a.n[1], a.shift);
+        const long long bz = axis_block(z[u], a.origin[2], a.dx[2], a.n[2], a.shift);
         if (bx < 0 || by < 0 || bz < 0) key = a.dead - 1u;  // last of the live particles
         else key = (unsigned)((bz * a.nb[1] + by) * a.nb[0] + bx);
       }
@@ -436,6 +439,307 @@ __global__ void __launch_bounds__(kSortThreads) sort_store_kernel(SortArgs a) {
   }
 }
 
+// ------------------------------------------------------------------------------------
+// Thinning per cell (qed_thin_cells), on the store the sort above has just ordered: a
+// group is a run of one key within an instance.  Heads (first items of groups) are counted
+// per tile and scanned, which numbers the groups; one thread per group then sums its weight,
+// draws its survivors and fixes its factor, in store order, as a sequential loop does; the
+// survivors are ranked per tile, scanned, gathered with their new weights into the column
+// copy and written back to the segments, whose counts and records the last launch sets.
+// ------------------------------------------------------------------------------------
+struct ThinArgs {
+  const unsigned* key;  // sorted keys
+  unsigned* gid;        // group of each item
+  unsigned* keep;       // survival flag of each item
+  unsigned* kpre;       // survivor rank of each item within its tile
+  unsigned* hcnt;       // per tile: heads, then (scanned) heads before the tile
+  unsigned* kcnt;       // per tile: survivors, then (scanned) survivors before the tile
+  unsigned* gstart;     // [groups + 1] first item of each group
+  double *gfac, *gw, *gwa;
+  unsigned* gkept;
+  long long* gpfx;      // [n_inst + 1] groups before each instance
+  long long* kpref;     // [n_inst + 1] survivors before each instance
+  long long max_per_cell;
+  const long long* d_step;
+  qed_thin_cells_record* rec;
+};
+
+__device__ __forceinline__ bool is_head(const SortArgs& a, const ThinArgs& t, const Tile& T,
+                                        long long g) {
+  return g == a.gpref[T.inst] || t.key[g] != t.key[g - 1];
+}
+
+// Exclusive scan, in tile order, of the thread's kPerThread flags (item i*256 + thread);
+// every thread of the workgroup calls it.  Returns the tile's total.
+__device__ unsigned tile_exclusive_scan(const unsigned (&f)[kPerThread],
+                                        unsigned (&pre)[kPerThread], unsigned* sw) {
+  unsigned carry = 0;
+#pragma unroll
+  for (int i = 0; i < kPerThread; ++i) {
+    unsigned total;
+    const unsigned ex = block_exclusive_scan(f[i], sw, total);
+    pre[i] = carry + ex;
+    carry += total;
+  }
+  return carry;
+}
+
+__global__ void __launch_bounds__(kSortThreads) thin_heads_kernel(SortArgs a, ThinArgs t) {
+  __shared__ unsigned sw[4];
+  Tile T;
+  if (!tile_of(a, blockIdx.x, T)) return;
+  unsigned f[kPerThread], pre[kPerThread];
+#pragma unroll
+  for (int i = 0; i < kPerThread; ++i) {
+    const long long g = T.g0 + (long long)i * kSortThreads + threadIdx.x;
+    f[i] = (g < T.g1 && is_head(a, t, T, g)) ? 1u : 0u;
+  }
+  const unsigned total = tile_exclusive_scan(f, pre, sw);
+  if (threadIdx.x == 0) t.hcnt[blockIdx.x] = total;
+}
+
+// One workgroup: exclusive scan of the per-tile counts (which = 0: heads, 1: survivors),
+// their total, and the per-instance prefix at each instance's first tile.
+__global__ void __launch_bounds__(kSortThreads) thin_scan_kernel(SortArgs a, ThinArgs t,
+                                                                 int which) {
+  __shared__ unsigned sw[4];
+  unsigned* cnt = which == 0 ? t.hcnt : t.kcnt;
+  long long* pfx = which == 0 ? t.gpfx : t.kpref;
+  const long long tiles = a.hdr->tiles;
+  unsigned long long carry = 0;
+  for (long long b = 0; b < tiles; b += blockDim.x) {
+    const long long i = b + threadIdx.x;
+    const unsigned v = i < tiles ? cnt[i] : 0u;
+    unsigned total;
+    const unsigned ex = block_exclusive_scan(v, sw, total);
+    if (i < tiles) cnt[i] = (unsigned)(carry + ex);
+    carry += total;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= a.n_inst; i += blockDim.x) {
+    const long long tp = a.tpref[i];
+    pfx[i] = tp < tiles ? (long long)cnt[tp] : (long long)carry;
+  }
+  if (threadIdx.x == 0) {
+    if (which == 0) {
+      a.hdr->groups = (long long)carry;
+      t.gstart[carry] = (unsigned)a.hdr->n;
+    } else {
+      a.hdr->kept = (long long)carry;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kSortThreads) thin_groups_kernel(SortArgs a, ThinArgs t) {
+  __shared__ unsigned sw[4];
+  Tile T;
+  if (!tile_of(a, blockIdx.x, T)) return;
+  unsigned f[kPerThread], pre[kPerThread];
+#pragma unroll
+  for (int i = 0; i < kPerThread; ++i) {
+    const long long g = T.g0 + (long long)i * kSortThreads + threadIdx.x;
+    f[i] = (g < T.g1 && is_head(a, t, T, g)) ? 1u : 0u;
+  }
+  tile_exclusive_scan(f, pre, sw);
+  const long long base = (long long)t.hcnt[blockIdx.x];
+#pragma unroll
+  for (int i = 0; i < kPerThread; ++i) {
+    const long long g = T.g0 + (long long)i * kSortThreads + threadIdx.x;
+    if (g >= T.g1) continue;
+    const long long gid = base + (long long)pre[i] + (long long)f[i] - 1;  // heads so far - 1
+    t.gid[g] = (unsigned)gid;
+    if (f[i]) t.gstart[gid] = (unsigned)g;
+  }
+}
+
+// One thread per group, in store order within the group: its weight, its survivors and its
+// factor (a group of removed photons: none, factor 0).
+__global__ void __launch_bounds__(kSortThreads) thin_decide_kernel(SortArgs a, ThinArgs t) {
+  const long long groups = a.hdr->groups;
+  const long long M = t.max_per_cell;
+  const uint32_t step = (uint32_t)*t.d_step;
+  const qed_soa& S = a.s;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < groups; q += stride) {
+    const long long g0 = t.gstart[q], g1 = t.gstart[q + 1];
+    const int inst = find_instance(a.gpref, a.n_inst, g0);
+    const long long sb = a.inst[inst].base[a.species] - a.gpref[inst];
+    if (t.key[g0] == a.dead) {  // removed photons
+      for (long long g = g0; g < g1; ++g) t.keep[g] = 0u;
+      t.gfac[q] = 0.0;
+      t.gw[q] = 0.0;
+      t.gwa[q] = 0.0;
+      t.gkept[q] = 0u;
+      continue;
+    }
+    const long long m = g1 - g0;
+    double W = 0.0;
+    for (long long g = g0; g < g1; ++g) W += S.w[sb + g];
+    t.gw[q] = W;
+    if (m <= M) {
+      for (long long g = g0; g < g1; ++g) t.keep[g] = 1u;
+      t.gfac[q] = 1.0;
+      t.gwa[q] = W;
+      t.gkept[q] = (unsigned)m;
+      continue;
+    }
+    const double qs = (double)M / (double)m;
+    const uint64_t seed = a.inst[inst].seed;
+    double K = 0.0, umin = 2.0;
+    long long kept = 0, gmin = g0;
+    for (long long g = g0; g < g1; ++g) {
+      const uint4 o = draw_words(S.id[sb + g], seed, step, 0u, kThinCell);
+      const double u = uniform64(o.x, o.y);
+      const bool k = u < qs;
+      t.keep[g] = k ? 1u : 0u;
+      if (k) {
+        ++kept;
+        K += S.w[sb + g];
+      }
+      if (u < umin) {
+        umin = u;
+        gmin = g;
+      }
+    }
+    if (kept == 0) {  // the group keeps its weight in its smallest draw
+      t.keep[gmin] = 1u;
+      K = S.w[sb + gmin];
+      kept = 1;
+    }
+    const double fac = W / K;
+    double Wa = 0.0;
+    for (long long g = g0; g < g1; ++g)
+      if (t.keep[g]) Wa += S.w[sb + g] * fac;
+    t.gfac[q] = fac;
+    t.gwa[q] = Wa;
+    t.gkept[q] = (unsigned)kept;
+  }
+}
+
+__global__ void __launch_bounds__(kSortThreads) thin_keep_kernel(SortArgs a, ThinArgs t) {
+  __shared__ unsigned sw[4];
+  Tile T;
+  if (!tile_of(a, blockIdx.x, T)) return;
+  unsigned f[kPerThread], pre[kPerThread];
+#pragma unroll
+  for (int i = 0; i < kPerThread; ++i) {
+    const long long g = T.g0 + (long long)i * kSortThreads + threadIdx.x;
+    f[i] = g < T.g1 ? t.keep[g] : 0u;
+  }
+  const unsigned total = tile_exclusive_scan(f, pre, sw);
+#pragma unroll
+  for (int i = 0; i < kPerThread; ++i) {
+    const long long g = T.g0 + (long long)i * kSortThreads + threadIdx.x;
+    if (g < T.g1) t.kpre[g] = pre[i];
+  }
+  if (threadIdx.x == 0) t.kcnt[blockIdx.x] = total;
+}
+
+// Survivors of the tile into the column copy at their rank among all survivors, with the
+// group's factor on the weight.
+__global__ void __launch_bounds__(kSortThreads) thin_gather_kernel(SortArgs a, ThinArgs t) {
+  Tile T;
+  if (!tile_of(a, blockIdx.x, T)) return;
+  const ColView c = col_view(a);
+  const qed_soa& s = a.s;
+  const bool nev = s.n_events != nullptr;
+  const long long base = (long long)t.kcnt[blockIdx.x];
+  for (long long g = T.g0 + threadIdx.x; g < T.g1; g += kSortThreads) {
+    if (!t.keep[g]) continue;
+    const long long i = T.sbase + g;
+    const long long d = base + (long long)t.kpre[g];
+    c.d[0][d] = s.x[i];
+    c.d[1][d] = s.y[i];
+    c.d[2][d] = s.z[i];
+    c.d[3][d] = s.px[i];
+    c.d[4][d] = s.py[i];
+    c.d[5][d] = s.pz[i];
+    c.d[6][d] = s.w[i] * t.gfac[t.gid[g]];
+    c.id[d] = s.id[i];
+    c.parent[d] = s.parent[i];
+    c.birth[d] = s.birth[i];
+    c.nev[d] = nev ? s.n_events[i] : 0u;
+  }
+}
+
+// The column copy back into the segments: survivor j of instance i goes to slot
+// base_i + (j - survivors before instance i).
+__global__ void __launch_bounds__(kSortThreads) thin_store_kernel(SortArgs a, ThinArgs t) {
+  const long long kept = a.hdr->kept;
+  const ColView c = col_view(a);
+  const qed_soa& s = a.s;
+  const bool nev = s.n_events != nullptr;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x; j < kept; j += stride) {
+    const int inst = find_instance(t.kpref, a.n_inst, j);
+    const long long i = a.inst[inst].base[a.species] + (j - t.kpref[inst]);
+    const double x = c.d[0][j], y = c.d[1][j], z = c.d[2][j];
+    const double px = c.d[3][j], py = c.d[4][j], pz = c.d[5][j], w = c.d[6][j];
+    const unsigned long long id = c.id[j], parent = c.parent[j];
+    const unsigned birth = c.birth[j], ne = c.nev[j];
+    s.x[i] = x;
+    s.y[i] = y;
+    s.z[i] = z;
+    s.px[i] = px;
+    s.py[i] = py;
+    s.pz[i] = pz;
+    s.w[i] = w;
+    s.id[i] = id;
+    s.parent[i] = parent;
+    s.birth[i] = birth;
+    if (nev) s.n_events[i] = ne;
+  }
+}
+
+// One workgroup per instance: the new count and the record (fixed-order reductions over
+// the instance's groups).
+__global__ void __launch_bounds__(kSortThreads) thin_finish_kernel(SortArgs a, ThinArgs t) {
+  __shared__ double sd[2][kSortThreads];
+  __shared__ long long sl[3][kSortThreads];
+  const int i = blockIdx.x;
+  qed_instance& I = a.inst[i];
+  qed_thin_cells_record* r = t.rec + i;
+  if (I.frozen) {
+    if (threadIdx.x == 0) *r = qed_thin_cells_record{};
+    return;
+  }
+  double wb = 0.0, wa = 0.0;
+  long long live = 0, groups = 0, thinned = 0;
+  for (long long q = t.gpfx[i] + threadIdx.x; q < t.gpfx[i + 1]; q += blockDim.x) {
+    const long long g0 = t.gstart[q], m = (long long)t.gstart[q + 1] - g0;
+    if (t.key[g0] == a.dead) continue;
+    live += m;
+    groups += 1;
+    thinned += m > t.max_per_cell ? 1 : 0;
+    wb += t.gw[q];
+    wa += t.gwa[q];
+  }
+  sd[0][threadIdx.x] = wb;
+  sd[1][threadIdx.x] = wa;
+  sl[0][threadIdx.x] = live;
+  sl[1][threadIdx.x] = groups;
+  sl[2][threadIdx.x] = thinned;
+  __syncthreads();
+  for (int h = kSortThreads / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      sd[0][threadIdx.x] += sd[0][threadIdx.x + h];
+      sd[1][threadIdx.x] += sd[1][threadIdx.x + h];
+      for (int k = 0; k < 3; ++k) sl[k][threadIdx.x] += sl[k][threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const long long kept = t.kpref[i + 1] - t.kpref[i];
+    I.count[a.species] = kept;
+    r->live_before = sl[0][0];
+    r->kept = kept;
+    r->groups = sl[1][0];
+    r->groups_thinned = sl[2][0];
+    r->weight_before = sd[0][0];
+    r->weight_after = sd[1][0];
+  }
+}
+
 }  // namespace
 
 SortGeometry sort_geometry(const int n[3]) {
@@ -456,12 +760,11 @@ SortGeometry sort_geometry(const int n[3]) {
   return g;
 }
 
-hipError_t launch_sort_cells(const qed_soa& s, int species, qed_instance* inst, int n_inst,
-                             long long slots, const int n[3], const double dx[3],
-                             const double origin[3], void* work, hipStream_t st) {
-  const SortLayout L = SortLayout::make(n_inst, slots);
-  const SortGeometry geo = sort_geometry(n);
-  unsigned char* w = static_cast<unsigned char*>(work);
+namespace {
+
+SortArgs sort_args(const qed_soa& s, int species, qed_instance* inst, int n_inst,
+                   const SortLayout& L, const SortGeometry& geo, const int n[3],
+                   const double dx[3], const double origin[3], unsigned char* w) {
   SortArgs a{};
   a.s = s;
   a.inst = inst;
@@ -473,7 +776,7 @@ hipError_t launch_sort_cells(const qed_soa& s, int species, qed_instance* inst, 
   for (int d = 0; d < 3; ++d) {
     a.n[d] = n[d];
     a.nb[d] = geo.nb[d];
-    a.inv_dx[d] = 1.0 / dx[d];
+    a.dx[d] = dx[d];
     a.origin[d] = origin[d];
   }
   a.hdr = reinterpret_cast<SortHdr*>(w + L.hdr);
@@ -487,6 +790,11 @@ hipError_t launch_sort_cells(const qed_soa& s, int species, qed_instance* inst, 
   a.sums = reinterpret_cast<unsigned*>(w + L.sums);
   a.cols = w + L.cols;
   a.cap = L.cap;
+  return a;
+}
+
+void enqueue_sort(const SortArgs& a, const SortLayout& L, const SortGeometry& geo,
+                  hipStream_t st) {
   const unsigned grid = (unsigned)L.tiles_max;  // one workgroup per possible tile
   const unsigned chunks = (unsigned)((L.tiles_max * 256 + kScanChunk - 1) / kScanChunk);
   const dim3 blk(kSortThreads);
@@ -501,6 +809,61 @@ hipError_t launch_sort_cells(const qed_soa& s, int species, qed_instance* inst, 
   }
   hipLaunchKernelGGL(sort_gather_kernel, dim3(grid), blk, 0, st, a, geo.passes & 1);
   hipLaunchKernelGGL(sort_store_kernel, dim3(grid), blk, 0, st, a);
+}
+
+}  // namespace
+
+hipError_t launch_sort_cells(const qed_soa& s, int species, qed_instance* inst, int n_inst,
+                             long long slots, const int n[3], const double dx[3],
+                             const double origin[3], void* work, hipStream_t st) {
+  const SortLayout L = SortLayout::make(n_inst, slots);
+  const SortGeometry geo = sort_geometry(n);
+  const SortArgs a = sort_args(s, species, inst, n_inst, L, geo, n, dx, origin,
+                               static_cast<unsigned char*>(work));
+  enqueue_sort(a, L, geo, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_thin_cells(const qed_soa& s, int species, qed_instance* inst, int n_inst,
+                             long long slots, const int n[3], const double dx[3],
+                             const double origin[3], long long max_per_cell,
+                             const long long* d_step, qed_thin_cells_record* rec, void* work,
+                             hipStream_t st) {
+  const ThinCellsLayout L = ThinCellsLayout::make(n_inst, slots);
+  const SortGeometry geo = sort_geometry(n);
+  unsigned char* w = static_cast<unsigned char*>(work);
+  const SortArgs a = sort_args(s, species, inst, n_inst, L.sort, geo, n, dx, origin, w);
+  enqueue_sort(a, L.sort, geo, st);
+  ThinArgs t{};
+  t.key = a.key[geo.passes & 1];
+  t.gid = a.key[(geo.passes + 1) & 1];
+  t.keep = a.val[geo.passes & 1];
+  t.kpre = a.val[(geo.passes + 1) & 1];
+  t.hcnt = a.cnt;
+  t.kcnt = a.cnt + L.sort.tiles_max;
+  t.gstart = reinterpret_cast<unsigned*>(w + L.gstart);
+  t.gfac = reinterpret_cast<double*>(w + L.gfac);
+  t.gw = reinterpret_cast<double*>(w + L.gw);
+  t.gwa = reinterpret_cast<double*>(w + L.gwa);
+  t.gkept = reinterpret_cast<unsigned*>(w + L.gkept);
+  t.gpfx = reinterpret_cast<long long*>(w + L.gpfx);
+  t.kpref = reinterpret_cast<long long*>(w + L.kpref);
+  t.max_per_cell = max_per_cell;
+  t.d_step = d_step;
+  t.rec = rec;
+  const unsigned grid = (unsigned)L.sort.tiles_max;
+  const long long gb = (L.sort.cap + 255) / 256;
+  const unsigned group_blocks = (unsigned)(gb < 4096 ? gb : 4096);
+  const dim3 blk(kSortThreads);
+  hipLaunchKernelGGL(thin_heads_kernel, dim3(grid), blk, 0, st, a, t);
+  hipLaunchKernelGGL(thin_scan_kernel, dim3(1), blk, 0, st, a, t, 0);
+  hipLaunchKernelGGL(thin_groups_kernel, dim3(grid), blk, 0, st, a, t);
+  hipLaunchKernelGGL(thin_decide_kernel, dim3(group_blocks), blk, 0, st, a, t);
+  hipLaunchKernelGGL(thin_keep_kernel, dim3(grid), blk, 0, st, a, t);
+  hipLaunchKernelGGL(thin_scan_kernel, dim3(1), blk, 0, st, a, t, 1);
+  hipLaunchKernelGGL(thin_gather_kernel, dim3(grid), blk, 0, st, a, t);
+  hipLaunchKernelGGL(thin_store_kernel, dim3(group_blocks), blk, 0, st, a, t);
+  hipLaunchKernelGGL(thin_finish_kernel, dim3((unsigned)n_inst), blk, 0, st, a, t);
   return hipGetLastError();
 }
 

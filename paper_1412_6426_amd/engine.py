@@ -189,6 +189,27 @@ class Engine:
         return [Q.qed_thin_record.from_buffer_copy(raw[i * n:(i + 1) * n]).as_dict()
                 for i in range(self.n_inst)]
 
+    def thin_cells(self, species: int, field: Q.qed_field, max_per_cell: int,
+                   stream: Optional[int] = None):
+        """qed_thin_cells on one species of every instance (workspace allocated on first
+        use); records stay on the device until thin_cells_records() reads them."""
+        torch = _torch()
+        need = Q.qed_thin_cells_work_bytes(self.n_inst, int(self.cols[species]["x"].numel()))
+        if getattr(self, "_tc_work", None) is None or self._tc_work.numel() < need:
+            self._tc_work = torch.zeros(need, dtype=torch.uint8, device=self.device)
+            self._tc_rec = torch.zeros(self.n_inst * C.sizeof(Q.qed_thin_cells_record),
+                                       dtype=torch.uint8, device=self.device)
+        Q.qed_thin_cells(self.stores, species, field, int(max_per_cell),
+                         self.step_ctr.data_ptr(), self._tc_rec.data_ptr(),
+                         self._tc_work.data_ptr(), self._tc_work.numel(),
+                         self.stream if stream is None else stream)
+
+    def thin_cells_records(self) -> List[Dict]:
+        raw = self._tc_rec.cpu().numpy().tobytes()
+        n = C.sizeof(Q.qed_thin_cells_record)
+        return [Q.qed_thin_cells_record.from_buffer_copy(raw[i * n:(i + 1) * n]).as_dict()
+                for i in range(self.n_inst)]
+
     # ------------------------------------------------------------------ cell sort
     def sort_cells(self, species: int, field: Q.qed_field, stream: Optional[int] = None):
         """qed_sort_cells on one species of every instance (workspace allocated on first

@@ -179,6 +179,37 @@ static void check_sort(int n_inst, long long slots, const char* what) {
   CHECK(s < (1ll << 32), "%s: 32-bit item indices", what);
 }
 
+// qed_thin_cells: the sort's regions, then its own; the per-tile group and survivor counts
+// share the sort's count array (2 x tiles_max of its 256 x tiles_max words).
+static void check_thin_cells(int n_inst, long long slots, const char* what) {
+  const ThinCellsLayout L = ThinCellsLayout::make(n_inst, slots);
+  CHECK(qed_thin_cells_work_bytes(n_inst, slots) == L.total, "%s: qed_thin_cells_work_bytes",
+        what);
+  const SortLayout& S = L.sort;
+  const size_t cap = (size_t)S.cap;
+  std::vector<Region> r = {{S.hdr, sizeof(SortHdr), "hdr"},
+                           {S.gpref, 8 * ((size_t)n_inst + 1), "gpref"},
+                           {S.tpref, 8 * ((size_t)n_inst + 1), "tpref"},
+                           {S.key[0], 4 * cap, "key0"},
+                           {S.key[1], 4 * cap, "key1"},
+                           {S.val[0], 4 * cap, "val0"},
+                           {S.val[1], 4 * cap, "val1"},
+                           {S.cnt, 4 * 256 * (size_t)S.tiles_max, "cnt"},
+                           {S.sums, 4 * (((size_t)S.tiles_max * 256 + 4095) / 4096), "sums"},
+                           {S.cols, 9 * ((cap * 8 + 255) & ~(size_t)255) +
+                                        2 * ((cap * 4 + 255) & ~(size_t)255), "cols"},
+                           {L.gstart, 4 * (cap + 1), "gstart"},
+                           {L.gfac, 8 * cap, "gfac"},
+                           {L.gw, 8 * cap, "gw"},
+                           {L.gwa, 8 * cap, "gwa"},
+                           {L.gkept, 4 * cap, "gkept"},
+                           {L.gpfx, 8 * ((size_t)n_inst + 1), "gpfx"},
+                           {L.kpref, 8 * ((size_t)n_inst + 1), "kpref"}};
+  check_regions(r, 0, L.total, what);
+  CHECK(L.gstart >= S.total, "%s: thinning regions overlap the sort's", what);
+  CHECK(2 * (size_t)S.tiles_max <= 256 * (size_t)S.tiles_max, "%s: tile counts", what);
+}
+
 static void check_sort_geometry(int nx, int ny, int nz) {
   const int n[3] = {nx, ny, nz};
   const SortGeometry g = sort_geometry(n);
@@ -238,6 +269,10 @@ int main() {
   check_sort(5, 0, "sort, no slots");
   check_sort(3, 2, "sort, fewer slots than instances");
   check_sort(1, (1ll << 32) - 1, "sort, largest store");
+  check_thin_cells(1, 200 * M, "thin cells, 2*10^8 photon slots");
+  check_thin_cells(64, 200 * M, "thin cells, 64 instances");
+  check_thin_cells(5, 0, "thin cells, no slots");
+  check_thin_cells(1, (1ll << 32) - 1, "thin cells, largest store");
   const int grids[][3] = {{1, 1, 1}, {7, 5, 4}, {40, 40, 40}, {254, 1, 1}, {255, 1, 1},
                           {256, 256, 256}, {300, 300, 300}, {300, 2, 9}, {65534, 1, 1},
                           {65535, 1, 1}, {1 << 20, 1 << 5, 1 << 5}, {2147483647, 1, 1}};

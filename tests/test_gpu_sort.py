@@ -41,7 +41,7 @@ def host_keys(cols, n, dx, origin, dead):
     top = (1 << (8 * passes)) - 1
     cell = []
     for d, c in enumerate(("x", "y", "z")):
-        v = (cols[c] - origin[d]) * (1.0 / dx[d])
+        v = (cols[c] - origin[d]) / dx[d]
         with np.errstate(invalid="ignore"):
             fl = np.floor(v)
         ok = np.isfinite(fl)

@@ -1,0 +1,151 @@
+"""qed_thin_cells through the C ABI against the oracle's thinning per cell block: the stores
+after the call equal the oracle's row for row (same order, ids, positions, momenta and
+bit-identical weights: from the same input order both sides sum each group in store order
+and scale by W / K), the
+counts and the records match (weights to 1e-12: the per-instance totals are reduced in
+another order), frozen instances are left alone; and a 32^3 grid cascade whose photon store
+is thinned per cell every few steps equals the oracle run with the same thinning."""
+import numpy as np
+import pytest
+
+from tests.conftest import gpu_available
+from tests.parity_util import compare_all, compare_stats, oracle_field, oracle_params, oracle_stores
+
+pytestmark = pytest.mark.gpu
+
+if not gpu_available():
+    pytest.skip("needs a HIP device", allow_module_level=True)
+
+import torch  # noqa: E402
+
+from paper_1412_6426_amd import qed as Q  # noqa: E402
+from paper_1412_6426_amd import runner as R  # noqa: E402
+from paper_1412_6426_amd import workloads as W  # noqa: E402
+from paper_1412_6426_amd.engine import Engine  # noqa: E402
+
+DEAD = np.uint64(0xFFFFFFFFFFFFFFFF)
+COLS = ("x", "y", "z", "px", "py", "pz", "w", "id", "parent", "birth")
+
+
+def _note(msg):
+    print(msg, flush=True)
+
+
+def _columns(rng, m, n, dx, origin, photon, first_id, spread):
+    span = np.array(n) * np.array(dx)
+    pos = []
+    for d in range(3):
+        v = origin[d] + spread * span[d] * rng.beta(1.0, 4.0, m)  # crowded near a corner
+        v[rng.random(m) < 0.05] += span[d] * rng.integers(-2, 3)  # periodic images
+        pos.append(v)
+    cols = W._seed_columns(*pos, rng.normal(size=m), rng.normal(size=m), rng.normal(size=m),
+                           first_id=first_id)
+    cols["w"] = rng.uniform(0.5, 2.0, m)
+    cols["parent"] = rng.integers(0, 2 ** 63, m, dtype=np.uint64)
+    cols["birth"] = rng.integers(0, 2 ** 31, m, dtype=np.uint32)
+    cols["n_events"] = rng.integers(0, 9, m, dtype=np.uint32)
+    if photon and m:
+        cols["id"][rng.random(m) < 0.08] = DEAD
+        cols["x"][: m // 97] = np.nan
+    return cols
+
+
+@pytest.mark.parametrize("grid", [((7, 5, 4), (0.7, 1.1, 0.45), (-2.0, 3.0, 0.5), 1.0),
+                                  ((300, 300, 300), (0.01, 0.01, 0.01), (0.0, 0.0, 0.0), 0.02)])
+def test_thin_cells_matches_oracle(orc, grid):
+    """A 7x5x4 grid (one cell per block) and a 300^3 grid (blocks of 2^3 cells, 24-bit
+    keys), four instances (one empty, one frozen), every species; caps 25, 3 and 40."""
+    n, dx, origin, spread = grid
+    rng = np.random.default_rng(sum(n))
+    caps = [(20000, 900, 40000), (10, 10, 10), (6000, 700, 9000), (300, 300, 300)]
+    counts = [(18000, 650, 33000), (0, 0, 0), (4097, 1, 8191), (290, 280, 270)]
+    seeds = [11, 12, 13, 14]
+    e = Engine(caps, seeds)
+    init = []
+    for i, cnt in enumerate(counts):
+        per = []
+        for sp in range(3):
+            cols = _columns(rng, cnt[sp], n, dx, origin, sp == 2, 1_000_000 * (i + 1), spread)
+            e.load(i, sp, cols)
+            per.append(cols)
+        init.append(per)
+    e.set_frozen(3)
+    step = 17
+    e.set_step(step)
+    f = Engine.make_field(Q.QED_FIELD_YEE, grid=[torch.zeros(1, device="cuda")] * 6, n=n,
+                          dx=dx, origin=origin)
+    for sp, cap in ((0, 25), (1, 3), (2, 40)):
+        _note(f"thin cells: grid {n}, species {sp}, cap {cap}")
+        before3 = e.read(3, sp)
+        e.thin_cells(sp, f, cap)
+        torch.cuda.synchronize()
+        recs = e.thin_cells_records()
+        for i in range(len(caps)):
+            got = e.read(i, sp)
+            if i == 3:  # frozen: untouched, zero record
+                for c in COLS:
+                    assert np.array_equal(got[c], before3[c], equal_nan=True), c
+                assert all(v == 0 for v in recs[i].values())
+                continue
+            st = orc.Store(caps[i][sp], with_events=sp != 2)
+            st.load({k: v for k, v in init[i][sp].items() if sp != 2 or k != "n_events"})
+            orec = orc.thin_cells(st, sp == 2, n, dx, origin, cap, seeds[i], step)
+            want = st.view()
+            assert e.counts()[i, sp] == st.count == len(got["id"]), (i, sp)
+            for c in COLS:
+                assert np.array_equal(got[c], want[c], equal_nan=True), (n, i, sp, c)
+            if sp != 2:
+                assert np.array_equal(got["n_events"], want["n_events"])
+            for k in ("live_before", "kept", "groups", "groups_thinned"):
+                assert recs[i][k] == orec[k], (i, sp, k)
+            for k in ("weight_before", "weight_after"):
+                assert recs[i][k] == pytest.approx(orec[k], rel=1e-12, abs=0.0), (i, sp, k)
+            if cnt_live := orec["live_before"]:
+                assert orec["groups"] >= 1 and cnt_live >= orec["kept"]
+        assert any(r["groups_thinned"] > 0 for r in recs), sp
+
+
+def test_grid_cascade_thinned_per_cell_matches_oracle(orc):
+    """The 32^3 standing-wave cascade with its photon store thinned to at most 6 photons per
+    cell block after every fourth step, on both sides: every store and record equals the
+    oracle's, which thins with the same rule.  The decisions are keyed by the particles, but
+    a group's weight sums follow its store order, and the children a step appends come in
+    another order on the GPU (by producing wavefront) than in the oracle (by parent), so
+    after the first step with children the factors agree to rounding: weights are held to
+    1e-12 relative, every other column as in the other parity tests."""
+    w = W.standing_wave_grid(n=300, cells=32, capacity=200_000, lepton_capacity=20_000,
+                             steps=40, a0=2000.0)
+    init = W.standing_wave_initial(300, seed=3)
+    _note(f"thinned yee grid: {w.description}")
+    e = R.engine_single(w, init)
+    grid = R.YeeGrid(w)
+    f = R.field_of(w, grid=grid.g)
+    p = R.params_of(w)
+    os_ = oracle_stores(orc, init, w.capacity)
+    op = oracle_params(orc, w)
+    fw = w.field
+    e.set_step(0)
+    st, ost, trec, otrec = [], [], [], []
+    for n in range(w.n_steps):
+        vals = W.standing_wave_grid_values(w.field, w.t0 + n * w.dt)
+        grid.load_numpy(vals)
+        e.step(f, p)
+        op.step = n
+        ost.append(orc.step(os_, oracle_field(orc, w, grids=vals), op))
+        torch.cuda.synchronize()
+        st.append(e.stats())
+        if n % 4 == 3:
+            # the step counter now reads n + 1
+            e.thin_cells(Q.QED_PHOTON, f, 6)
+            torch.cuda.synchronize()
+            trec.append(e.thin_cells_records()[0])
+            otrec.append(orc.thin_cells(os_[2], True, fw.grid_n, fw.grid_dx, fw.grid_origin, 6,
+                                        w.seed, n + 1))
+    assert sum(r["groups_thinned"] for r in otrec) > 0
+    assert e.stats()["n_start"][2] > 100
+    for g, o in zip(trec, otrec):
+        for k in ("live_before", "kept", "groups", "groups_thinned"):
+            assert g[k] == o[k], k
+        assert g["weight_after"] == pytest.approx(o["weight_after"], rel=1e-12)
+    compare_stats(st, ost, label="thinned yee")
+    compare_all(e, os_, label="thinned yee", wtol=1e-12)
