@@ -365,9 +365,9 @@ typedef struct {
   double weight_after;     /* after (equal up to rounding: every group keeps its weight) */
 } qed_thin_cells_record;
 
-/* Workspace size of qed_thin_cells: qed_sort_work_bytes plus 32 bytes per slot of the
- * species store (per-group starts, factors, weights and survivor counts) and two 8-byte
- * prefixes per instance.  0 for invalid arguments. */
+/* Workspace size of qed_thin_cells: qed_sort_work_bytes plus 36 bytes per slot of the
+ * species store (per-group starts, factors, weights and survivor counts, and a list of the
+ * large groups) and two 8-byte prefixes per instance.  0 for invalid arguments. */
 size_t qed_thin_cells_work_bytes(int n_instances, int64_t species_slots);
 
 /* Thinning per cell (Sec. VI's thinning with global even redistribution applied within
@@ -381,8 +381,9 @@ size_t qed_thin_cells_work_bytes(int n_instances, int64_t species_slots);
  * id with counter (*d_step, 11 << 16, instance seed lo, hi), survival iff the first two
  * words as a uniform in (0, 1) are below q; if none survives, the particle with the
  * smallest draw does (the first, in store order, on a tie); the survivors' weights are
- * multiplied by the group's weight over its survivors' weight (both summed in store order),
- * so every group keeps its weight.  The survivors are written back in sorted order
+ * multiplied by the group's weight over its survivors' weight, so every group keeps its
+ * weight (a group of up to 1024 particles is summed in store order; a larger one in a fixed
+ * order of its own, equal to rounding).  The survivors are written back in sorted order
  * (removed photons go) and the count set to their number.  d_records[n_instances]
  * receives one record per instance.  Graph-capturable; no host synchronisation.
  * QED_ERR_ARG for a field that is not a Yee grid, max_per_cell < 1, bad sizes or pointers;

@@ -239,7 +239,8 @@ struct alignas(64) SortHdr {
   long long tiles;   // tiles of the instance-ordered tile list
   long long groups;  // qed_thin_cells: groups (runs of one key), removed photons' included
   long long kept;    // qed_thin_cells: survivors, all instances
-  long long reserved[4];
+  long long nbig;    // qed_thin_cells: groups handed to the workgroup-per-group pass
+  long long reserved[3];
 };
 struct SortLayout {
   size_t hdr, gpref, tpref, key[2], val[2], cnt, sums, cols, total;
@@ -273,13 +274,13 @@ struct SortLayout {
 };
 
 // qed_thin_cells: the sort's workspace, then per group (at most one per live slot) its first
-// item, weight factor, weight before and after, and survivors; per instance the group and
-// survivor prefixes.  The sort's second key and index arrays hold each item's group and its
+// item, weight factor, weight before and after, and survivors, and the list of large groups;
+// per instance the group and survivor prefixes.  The sort's second key and index arrays hold each item's group and its
 // survivor rank within its tile, its first index array the survival flags, and the count
 // array's first and second tiles_max words the per-tile group and survivor counts.
 struct ThinCellsLayout {
   SortLayout sort;
-  size_t gstart, gfac, gw, gwa, gkept, gpfx, kpref, total;
+  size_t gstart, gfac, gw, gwa, gkept, big, gpfx, kpref, total;
   static ThinCellsLayout make(int n_inst, long long slots) {
     ThinCellsLayout L{};
     L.sort = SortLayout::make(n_inst, slots);
@@ -295,6 +296,7 @@ struct ThinCellsLayout {
     L.gw = take(sizeof(double) * cap);
     L.gwa = take(sizeof(double) * cap);
     L.gkept = take(sizeof(unsigned) * cap);
+    L.big = take(sizeof(unsigned) * cap);
     L.gpfx = take(sizeof(long long) * ((size_t)n_inst + 1));
     L.kpref = take(sizeof(long long) * ((size_t)n_inst + 1));
     L.total = off;

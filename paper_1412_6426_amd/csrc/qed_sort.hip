@@ -457,6 +457,7 @@ struct ThinArgs {
   unsigned* gstart;     // [groups + 1] first item of each group
   double *gfac, *gw, *gwa;
   unsigned* gkept;
+  unsigned* big;        // groups of more than kBigGroup particles, for thin_big_kernel
   long long* gpfx;      // [n_inst + 1] groups before each instance
   long long* kpref;     // [n_inst + 1] survivors before each instance
   long long max_per_cell;
@@ -523,6 +524,7 @@ __global__ void __launch_bounds__(kSortThreads) thin_scan_kernel(SortArgs a, Thi
   if (threadIdx.x == 0) {
     if (which == 0) {
       a.hdr->groups = (long long)carry;
+      a.hdr->nbig = 0;
       t.gstart[carry] = (unsigned)a.hdr->n;
     } else {
       a.hdr->kept = (long long)carry;
@@ -552,8 +554,19 @@ __global__ void __launch_bounds__(kSortThreads) thin_groups_kernel(SortArgs a, T
   }
 }
 
+// Groups of more particles than this go to thin_big_kernel (a workgroup each); smaller ones
+// are walked by one thread, in store order.
+constexpr long long kBigGroup = 1024;
+
+// The survival draw of one particle.
+__device__ __forceinline__ double thin_draw(uint64_t id, uint64_t seed, uint32_t step) {
+  const uint4 o = draw_words(id, seed, step, 0u, kThinCell);
+  return uniform64(o.x, o.y);
+}
+
 // One thread per group, in store order within the group: its weight, its survivors and its
-// factor (a group of removed photons: none, factor 0).
+// factor (a group of removed photons: none, factor 0).  Groups of more than kBigGroup
+// particles are listed for thin_big_kernel.
 __global__ void __launch_bounds__(kSortThreads) thin_decide_kernel(SortArgs a, ThinArgs t) {
   const long long groups = a.hdr->groups;
   const long long M = t.max_per_cell;
@@ -564,6 +577,12 @@ __global__ void __launch_bounds__(kSortThreads) thin_decide_kernel(SortArgs a, T
     const long long g0 = t.gstart[q], g1 = t.gstart[q + 1];
     const int inst = find_instance(a.gpref, a.n_inst, g0);
     const long long sb = a.inst[inst].base[a.species] - a.gpref[inst];
+    const long long m = g1 - g0;
+    if (m > kBigGroup) {  // removed photons too: all their flags are cleared there
+      const unsigned long long at = atomicAdd(reinterpret_cast<unsigned long long*>(&a.hdr->nbig), 1ull);
+      t.big[at] = (unsigned)q;
+      continue;
+    }
     if (t.key[g0] == a.dead) {  // removed photons
       for (long long g = g0; g < g1; ++g) t.keep[g] = 0u;
       t.gfac[q] = 0.0;
@@ -572,7 +591,6 @@ __global__ void __launch_bounds__(kSortThreads) thin_decide_kernel(SortArgs a, T
       t.gkept[q] = 0u;
       continue;
     }
-    const long long m = g1 - g0;
     double W = 0.0;
     for (long long g = g0; g < g1; ++g) W += S.w[sb + g];
     t.gw[q] = W;
@@ -588,8 +606,7 @@ __global__ void __launch_bounds__(kSortThreads) thin_decide_kernel(SortArgs a, T
     double K = 0.0, umin = 2.0;
     long long kept = 0, gmin = g0;
     for (long long g = g0; g < g1; ++g) {
-      const uint4 o = draw_words(S.id[sb + g], seed, step, 0u, kThinCell);
-      const double u = uniform64(o.x, o.y);
+      const double u = thin_draw(S.id[sb + g], seed, step);
       const bool k = u < qs;
       t.keep[g] = k ? 1u : 0u;
       if (k) {
@@ -613,6 +630,123 @@ __global__ void __launch_bounds__(kSortThreads) thin_decide_kernel(SortArgs a, T
     t.gfac[q] = fac;
     t.gwa[q] = Wa;
     t.gkept[q] = (unsigned)kept;
+  }
+}
+
+// Sums over a workgroup in a fixed order: each thread's partial, then a fixed tree.
+__device__ double block_sum(double v, double* sd) {
+  sd[threadIdx.x] = v;
+  __syncthreads();
+  for (int h = kSortThreads / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) sd[threadIdx.x] += sd[threadIdx.x + h];
+    __syncthreads();
+  }
+  const double r = sd[0];
+  __syncthreads();
+  return r;
+}
+
+// One workgroup per listed group (more than kBigGroup particles, removed photons' too): the
+// same decisions as thin_decide_kernel, with the sums taken per thread over a strided share
+// and then over the workgroup in a fixed order (the weights agree with a sequential walk to
+// rounding).
+__global__ void __launch_bounds__(kSortThreads) thin_big_kernel(SortArgs a, ThinArgs t) {
+  __shared__ double sd[kSortThreads];
+  __shared__ unsigned long long sk[kSortThreads];
+  __shared__ double su[kSortThreads];
+  __shared__ long long sg[kSortThreads];
+  const long long nbig = a.hdr->nbig;
+  const long long M = t.max_per_cell;
+  const uint32_t step = (uint32_t)*t.d_step;
+  const qed_soa& S = a.s;
+  const int tid = (int)threadIdx.x;
+  for (long long b = blockIdx.x; b < nbig; b += gridDim.x) {
+    const long long q = t.big[b];
+    const long long g0 = t.gstart[q], g1 = t.gstart[q + 1];
+    const int inst = find_instance(a.gpref, a.n_inst, g0);
+    const long long sb = a.inst[inst].base[a.species] - a.gpref[inst];
+    const long long m = g1 - g0;
+    if (t.key[g0] == a.dead) {  // removed photons
+      for (long long g = g0 + tid; g < g1; g += kSortThreads) t.keep[g] = 0u;
+      if (tid == 0) {
+        t.gfac[q] = 0.0;
+        t.gw[q] = 0.0;
+        t.gwa[q] = 0.0;
+        t.gkept[q] = 0u;
+      }
+      continue;
+    }
+    double w_part = 0.0;
+    for (long long g = g0 + tid; g < g1; g += kSortThreads) w_part += S.w[sb + g];
+    const double W = block_sum(w_part, sd);
+    if (m <= M) {  // not reached while kBigGroup >= the cap, kept for any cap
+      for (long long g = g0 + tid; g < g1; g += kSortThreads) t.keep[g] = 1u;
+      if (tid == 0) {
+        t.gw[q] = W;
+        t.gfac[q] = 1.0;
+        t.gwa[q] = W;
+        t.gkept[q] = (unsigned)m;
+      }
+      continue;
+    }
+    const double qs = (double)M / (double)m;
+    const uint64_t seed = a.inst[inst].seed;
+    double k_part = 0.0, umin = 2.0;
+    unsigned long long kept = 0;
+    long long gmin = g1;
+    for (long long g = g0 + tid; g < g1; g += kSortThreads) {
+      const double u = thin_draw(S.id[sb + g], seed, step);
+      const bool k = u < qs;
+      t.keep[g] = k ? 1u : 0u;
+      if (k) {
+        ++kept;
+        k_part += S.w[sb + g];
+      }
+      if (u < umin) {  // strided order: the first smallest of this thread's share
+        umin = u;
+        gmin = g;
+      }
+    }
+    double K = block_sum(k_part, sd);
+    // kept count and the smallest draw (the first in store order on a tie)
+    sk[tid] = kept;
+    su[tid] = umin;
+    sg[tid] = gmin;
+    __syncthreads();
+    for (int h = kSortThreads / 2; h > 0; h >>= 1) {
+      if (tid < h) {
+        sk[tid] += sk[tid + h];
+        if (su[tid + h] < su[tid] || (su[tid + h] == su[tid] && sg[tid + h] < sg[tid])) {
+          su[tid] = su[tid + h];
+          sg[tid] = sg[tid + h];
+        }
+      }
+      __syncthreads();
+    }
+    unsigned long long nkept = sk[0];
+    const long long gm = sg[0];
+    __syncthreads();
+    long long gforce = -1;  // the survivor a group without one gets (its flag is set below)
+    if (nkept == 0) {  // the group keeps its weight in its smallest draw
+      gforce = gm;
+      if (tid == 0) t.keep[gm] = 1u;
+      K = S.w[sb + gm];
+      nkept = 1;
+    }
+    const double fac = W / K;
+    double wa_part = 0.0;
+    for (long long g = g0 + tid; g < g1; g += kSortThreads) {
+      // a thread reads only the flags it wrote itself
+      const bool kept_g = gforce >= 0 ? g == gforce : t.keep[g] != 0u;
+      if (kept_g) wa_part += S.w[sb + g] * fac;
+    }
+    const double Wa = block_sum(wa_part, sd);
+    if (tid == 0) {
+      t.gw[q] = W;
+      t.gfac[q] = fac;
+      t.gwa[q] = Wa;
+      t.gkept[q] = (unsigned)nkept;
+    }
   }
 }
 
@@ -846,6 +980,7 @@ hipError_t launch_thin_cells(const qed_soa& s, int species, qed_instance* inst, 
   t.gw = reinterpret_cast<double*>(w + L.gw);
   t.gwa = reinterpret_cast<double*>(w + L.gwa);
   t.gkept = reinterpret_cast<unsigned*>(w + L.gkept);
+  t.big = reinterpret_cast<unsigned*>(w + L.big);
   t.gpfx = reinterpret_cast<long long*>(w + L.gpfx);
   t.kpref = reinterpret_cast<long long*>(w + L.kpref);
   t.max_per_cell = max_per_cell;
@@ -859,6 +994,7 @@ hipError_t launch_thin_cells(const qed_soa& s, int species, qed_instance* inst, 
   hipLaunchKernelGGL(thin_scan_kernel, dim3(1), blk, 0, st, a, t, 0);
   hipLaunchKernelGGL(thin_groups_kernel, dim3(grid), blk, 0, st, a, t);
   hipLaunchKernelGGL(thin_decide_kernel, dim3(group_blocks), blk, 0, st, a, t);
+  hipLaunchKernelGGL(thin_big_kernel, dim3(1024), blk, 0, st, a, t);
   hipLaunchKernelGGL(thin_keep_kernel, dim3(grid), blk, 0, st, a, t);
   hipLaunchKernelGGL(thin_scan_kernel, dim3(1), blk, 0, st, a, t, 1);
   hipLaunchKernelGGL(thin_gather_kernel, dim3(grid), blk, 0, st, a, t);

@@ -203,6 +203,7 @@ static void check_thin_cells(int n_inst, long long slots, const char* what) {
                            {L.gw, 8 * cap, "gw"},
                            {L.gwa, 8 * cap, "gwa"},
                            {L.gkept, 4 * cap, "gkept"},
+                           {L.big, 4 * cap, "big"},
                            {L.gpfx, 8 * ((size_t)n_inst + 1), "gpfx"},
                            {L.kpref, 8 * ((size_t)n_inst + 1), "kpref"}};
   check_regions(r, 0, L.total, what);

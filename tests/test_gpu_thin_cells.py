@@ -1,7 +1,8 @@
 """qed_thin_cells through the C ABI against the oracle's thinning per cell block: the stores
-after the call equal the oracle's row for row (same order, ids, positions, momenta and
-bit-identical weights: from the same input order both sides sum each group in store order
-and scale by W / K), the
+after the call equal the oracle's row for row (same order, ids, positions and momenta; the
+weights bit-identical in groups of up to 1024 particles, which one thread walks in store
+order as the oracle does, and within 1e-12 in larger ones, which a workgroup sums in
+another fixed order), the
 counts and the records match (weights to 1e-12: the per-instance totals are reduced in
 another order), frozen instances are left alone; and a 32^3 grid cascade whose photon store
 is thinned per cell every few steps equals the oracle run with the same thinning."""
@@ -50,6 +51,18 @@ def _columns(rng, m, n, dx, origin, photon, first_id, spread):
     return cols
 
 
+def _small_group_rows(before, after, n, dx, origin, limit, photon):
+    """Rows of `after` whose group held at most `limit` live particles in `before` (groups
+    recomputed on the host from the keys qed_sort_cells uses)."""
+    from tests.test_gpu_sort import host_keys
+    dead_b = (before["id"] == DEAD) if photon else np.zeros(len(before["id"]), bool)
+    kb = host_keys(before, n, dx, origin, dead_b)[~dead_b]
+    uk, cnt = np.unique(kb, return_counts=True)
+    size = dict(zip(uk.tolist(), cnt.tolist()))
+    ka = host_keys(after, n, dx, origin, np.zeros(len(after["id"]), bool))
+    return np.array([size[k] <= limit for k in ka.tolist()], bool)
+
+
 @pytest.mark.parametrize("grid", [((7, 5, 4), (0.7, 1.1, 0.45), (-2.0, 3.0, 0.5), 1.0),
                                   ((300, 300, 300), (0.01, 0.01, 0.01), (0.0, 0.0, 0.0), 0.02)])
 def test_thin_cells_matches_oracle(orc, grid):
@@ -74,6 +87,7 @@ def test_thin_cells_matches_oracle(orc, grid):
     e.set_step(step)
     f = Engine.make_field(Q.QED_FIELD_YEE, grid=[torch.zeros(1, device="cuda")] * 6, n=n,
                           dx=dx, origin=origin)
+    seen_big = seen_small = 0
     for sp, cap in ((0, 25), (1, 3), (2, 40)):
         _note(f"thin cells: grid {n}, species {sp}, cap {cap}")
         before3 = e.read(3, sp)
@@ -93,7 +107,15 @@ def test_thin_cells_matches_oracle(orc, grid):
             want = st.view()
             assert e.counts()[i, sp] == st.count == len(got["id"]), (i, sp)
             for c in COLS:
+                if c == "w":
+                    np.testing.assert_allclose(got[c], want[c], rtol=1e-12, atol=0)
+                    continue
                 assert np.array_equal(got[c], want[c], equal_nan=True), (n, i, sp, c)
+            # groups of at most 1024 particles are summed in store order: bit-identical
+            small = _small_group_rows(init[i][sp], want, n, dx, origin, 1024, sp == 2)
+            assert np.array_equal(got["w"][small], want["w"][small]), (n, i, sp)
+            seen_big += np.count_nonzero(~small)
+            seen_small += np.count_nonzero(small)
             if sp != 2:
                 assert np.array_equal(got["n_events"], want["n_events"])
             for k in ("live_before", "kept", "groups", "groups_thinned"):
@@ -103,6 +125,7 @@ def test_thin_cells_matches_oracle(orc, grid):
             if cnt_live := orec["live_before"]:
                 assert orec["groups"] >= 1 and cnt_live >= orec["kept"]
         assert any(r["groups_thinned"] > 0 for r in recs), sp
+    assert seen_big > 0 and seen_small > 0  # both the thread and the workgroup paths ran
 
 
 def test_grid_cascade_thinned_per_cell_matches_oracle(orc):
