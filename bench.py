@@ -302,7 +302,24 @@ def gpu_run(args, precision, kind="rotating", thin=None, fg=None, sample=None):
     return out
 
 
-def gpu_run_yee(args, precision, sort_every=None, sort_species=None):
+def _rounded(v, digits=6):
+    """Floats to `digits` significant digits (the leg summaries of the one-line record; the
+    full values are in the bench-detail lines)."""
+    if isinstance(v, float):
+        return float(f"{v:.{digits}g}")
+    if isinstance(v, dict):
+        return {k: _rounded(x, digits) for k, x in v.items()}
+    if isinstance(v, (list, tuple)):
+        return [_rounded(x, digits) for x in v]
+    return v
+
+
+def thin_cells_arg(args):
+    frac, cap = args.thin_cells.split(":")
+    return float(frac), int(cap)
+
+
+def gpu_run_yee(args, precision, sort_every=None, sort_species=None, thin=None):
     """Standing-wave cascade on a 256^3 Yee grid (two counter-propagating CP waves, a0 =
     2000 each, cells of lambda/32, 10^6 seeds Gaussian sigma = 0.1 lambda about the node,
     dt = T/100, 2*10^8 photon slots).  The grid is refilled with the analytic wave before
@@ -310,7 +327,10 @@ def gpu_run_yee(args, precision, sort_every=None, sort_species=None):
     HIP events around the fill, the whole step, and the lepton and photon kernels.  Every
     `sort_every` steps (0: never) the stores `sort_species` are sorted by cell
     (qed_sort_cells) before the step; that time counts as part of the step and is also
-    reported apart."""
+    reported apart.  thin = (fraction, cap): after each step, every store holding more slots
+    than that fraction of its capacity is thinned per cell block to at most `cap` particles
+    (qed_thin_cells; the counts are read on the host each step), so the job runs all its
+    steps without dropping children; the thinning is timed and counts in `value`."""
     import torch
     from paper_1412_6426_amd import qed as Q
     from paper_1412_6426_amd import runner as R
@@ -321,7 +341,8 @@ def gpu_run_yee(args, precision, sort_every=None, sort_species=None):
     e = R.engine_single(w, init)
     grid = R.YeeGrid(w)
     field = R.field_of(w, grid=grid.g)
-    params = R.params_of(w, freeze_on_drop=1, tile=args.tile, grid_blocks=args.grid_blocks)
+    params = R.params_of(w, freeze_on_drop=0 if thin else 1, tile=args.tile,
+                         grid_blocks=args.grid_blocks)
     K = w.n_steps
     S = args.sort_every if sort_every is None else sort_every
     if sort_species is None:
@@ -332,8 +353,13 @@ def gpu_run_yee(args, precision, sort_every=None, sort_species=None):
     cnt = torch.zeros(1, dtype=torch.int64, device=e.device)
     hip = HipEvents()
     evs = hip.create(8 * K)
+    tev = hip.create(2 * K) if thin else []
+    thin_calls = 0
     if S:
         e.sort_cells(0, field, stream=sp)  # allocates the sort workspace outside the timing
+    if thin:
+        for s_ in range(3):  # the thinning workspace and records, outside the timing
+            e.thin_cells(s_, field, 1 << 62, stream=sp)
     torch.cuda.synchronize()
     e.set_step(0)
     with torch.cuda.stream(stream):
@@ -351,9 +377,20 @@ def gpu_run_yee(args, precision, sort_every=None, sort_species=None):
             e.step(field, params, stream=sp)
             hip.lib.hipEventRecord(C.c_void_p(ev[6]), C.c_void_p(sp))
             Q.qed_append_stats(e.stats_buf.data_ptr(), log.data_ptr(), K, cnt.data_ptr(), sp)
+            if thin:
+                hip.lib.hipEventRecord(C.c_void_p(tev[2 * n]), C.c_void_p(sp))
+                stream.synchronize()
+                counts = e.counts()[0]
+                for s_ in range(3):
+                    if counts[s_] > thin[0] * w.capacity[s_]:
+                        e.thin_cells(s_, field, thin[1], stream=sp)
+                        thin_calls += 1
+                hip.lib.hipEventRecord(C.c_void_p(tev[2 * n + 1]), C.c_void_p(sp))
     torch.cuda.synchronize()
     for j in range(4):
         params.events[j] = None
+    thin_ms = sum(hip.elapsed_ms(tev[2 * n], tev[2 * n + 1]) for n in range(K)) if thin else 0.0
+    hip.destroy(tev)
     fill_ms = sum(hip.elapsed_ms(evs[8 * n], evs[8 * n + 1]) for n in range(K))
     step_ms = sum(hip.elapsed_ms(evs[8 * n + 1], evs[8 * n + 6]) for n in range(K))
     sort_ms = sum(hip.elapsed_ms(evs[8 * n + 1], evs[8 * n + 7]) for n in range(K))
@@ -370,7 +407,9 @@ def gpu_run_yee(args, precision, sort_every=None, sort_species=None):
         particle_steps=int(sum(adv)), advanced=[int(a) for a in adv], emitted=int(emitted),
         pairs=int(sum(r.pairs for r in recs)), step_ms=step_ms, fill_ms=fill_ms,
         sort_every=S, sort_species=list(sort_species) if S else [], sort_ms=sort_ms, lep_ms=lep_ms, pho_ms=pho_ms,
-        value=sum(adv) / (step_ms / 1e3),
+        value=sum(adv) / ((step_ms + thin_ms) / 1e3),
+        thin=list(thin) if thin else None, thin_ms=thin_ms, thin_calls=thin_calls,
+        dropped=int(sum(r.dropped for r in recs)), final_counts=e.counts()[0].tolist(),
         substeps=int(sum(r.substeps for r in recs)),
         nsub_max=max((k for r in recs for k in range(len(r.nsub_hist)) if r.nsub_hist[k]),
                      default=0),
@@ -921,7 +960,11 @@ def main():
                     help="run only the Schwinger leg and print its record (profiling)")
     ap.add_argument("--no-uniform-b", action="store_true",
                     help="skip the 10^4 electrons in a uniform B")
-    ap.add_argument("--only", choices=("uniform-b", "yee", "batched"), default=None,
+    ap.add_argument("--thin-cells", default="0.5:1024",
+                    help="grid cascade past its capacity: FRACTION:CAP, thin a store per cell "
+                         "block to CAP particles once it holds FRACTION of its slots")
+    ap.add_argument("--only", choices=("uniform-b", "yee", "yee-thinned", "batched"),
+                    default=None,
                     help="run only this leg and print its record (profiling)")
     ap.add_argument("--no-generators", action="store_true",
                     help="skip the comparison of the three emission generators")
@@ -961,6 +1004,10 @@ def main():
         return
     if args.only == "yee":
         print(json.dumps({"standing_wave_grid": gpu_run_yee(args, args.precision)}), flush=True)
+        return
+    if args.only == "yee-thinned":
+        print(json.dumps({"standing_wave_grid_thinned": gpu_run_yee(
+            args, args.precision, thin=thin_cells_arg(args))}), flush=True)
         return
     if args.only == "batched":
         out = {}
@@ -1037,8 +1084,7 @@ def main():
         legs["mixed_vs_f64"] = dict(
             value_f64=r64["value_job"], value_mixed=rmx["value_job"],
             speedup=rmx["value_job"] / r64["value_job"],
-            spectrum_l1=cmp_["spectrum_l1_vs_f64"], pair_yield_rel=cmp_["pair_yield_rel_diff"],
-            steps_compared=cmp_["steps_compared"])
+            spectrum_l1=cmp_["spectrum_l1_vs_f64"], pair_yield_rel=cmp_["pair_yield_rel_diff"])
     if not args.no_batched:
         # batched ensemble: 64 independent cascades in one step, mixed and FP64, full jobs
         b = {}
@@ -1096,6 +1142,12 @@ def main():
             sort_ms=round(y["sort_ms"], 2),
             lepton_frac=y["lepton_roofline_gbs"] / HBM_PEAK_GBS,
             photon_frac=y["photon_roofline_gbs"] / HBM_PEAK_GBS, saturated=y["saturated"])
+        print("bench: the same cascade thinned per cell past its capacity", file=sys.stderr,
+              flush=True)
+        yt = gpu_run_yee(args, args.precision, thin=thin_cells_arg(args))
+        detail("standing_wave_grid_thinned", yt)
+        legs["grid_thinned"] = dict(value=yt["value"], thin_ms=round(yt["thin_ms"], 1),
+                                    dropped=yt["dropped"])
     if not args.no_uniform_b:
         print("bench: uniform B, 10^4 electrons", file=sys.stderr, flush=True)
         u = gpu_uniform_b(args)
@@ -1114,7 +1166,7 @@ def main():
         detail("generator_comparison", gc)
         legs["generator_comparison"] = {k: round(v["ms_per_launch"], 4)
                                         for k, v in gc["generators"].items()}
-    line["legs"] = legs
+    line["legs"] = _rounded(legs)
     if not args.no_cpu_baseline:
         print("bench: oracle sample on the host", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(args)

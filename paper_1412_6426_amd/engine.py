@@ -173,9 +173,10 @@ class Engine:
         """qed_thin on one species of every instance; records stay on the device until
         thin_records() reads them."""
         torch = _torch()
-        slots = int(self.cols[species]["x"].numel())
-        need = Q.qed_thin_work_bytes(self.n_inst, slots)
+        need = max(Q.qed_thin_work_bytes(self.n_inst, int(self.cols[s]["x"].numel()))
+                   for s in range(3))
         if getattr(self, "_thin_work", None) is None or self._thin_work.numel() < need:
+            torch.cuda.synchronize()  # no call may still use a buffer being replaced
             self._thin_work = torch.zeros(need, dtype=torch.uint8, device=self.device)
             self._thin_rec = torch.zeros(self.n_inst * C.sizeof(Q.qed_thin_record),
                                          dtype=torch.uint8, device=self.device)
@@ -194,8 +195,12 @@ class Engine:
         """qed_thin_cells on one species of every instance (workspace allocated on first
         use); records stay on the device until thin_cells_records() reads them."""
         torch = _torch()
-        need = Q.qed_thin_cells_work_bytes(self.n_inst, int(self.cols[species]["x"].numel()))
+        # sized once for the largest store: a buffer replaced while a call on another
+        # stream still used it would be reused by the allocator under that call
+        need = max(Q.qed_thin_cells_work_bytes(self.n_inst, int(self.cols[s]["x"].numel()))
+                   for s in range(3))
         if getattr(self, "_tc_work", None) is None or self._tc_work.numel() < need:
+            torch.cuda.synchronize()
             self._tc_work = torch.zeros(need, dtype=torch.uint8, device=self.device)
             self._tc_rec = torch.zeros(self.n_inst * C.sizeof(Q.qed_thin_cells_record),
                                        dtype=torch.uint8, device=self.device)
@@ -218,6 +223,7 @@ class Engine:
         need = max(Q.qed_sort_work_bytes(self.n_inst, int(self.cols[s]["x"].numel()))
                    for s in range(3))
         if getattr(self, "_sort_work", None) is None or self._sort_work.numel() < need:
+            torch.cuda.synchronize()  # no call may still use a buffer being replaced
             self._sort_work = torch.zeros(need, dtype=torch.uint8, device=self.device)
         Q.qed_sort_cells(self.stores, species, field, self._sort_work.data_ptr(),
                          self._sort_work.numel(), self.stream if stream is None else stream)
