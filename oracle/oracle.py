@@ -72,7 +72,8 @@ class OrParams(C.Structure):
                 ("emission", C.c_int), ("pairs", C.c_int), ("push_photons", C.c_int),
                 ("backend", C.c_int), ("seed", C.c_uint64), ("step", C.c_int64),
                 ("f_photon", C.c_double), ("f_pair", C.c_double),
-                ("same_step_generations", C.c_int)]
+                ("same_step_generations", C.c_int), ("f_every", C.c_int),
+                ("runs_photon", C.c_int), ("runs_pair", C.c_int)]
 
 
 class OrSchwingerRecord(C.Structure):
@@ -421,12 +422,15 @@ class Params:
     f_photon: float = 1.0  # generator factors of Sec. VI (<= 1: off)
     f_pair: float = 1.0
     same_step_generations: int = 0  # children advanced in their birth step, generations
+    f_every: int = 0  # deterministic form of the generator factors (every f_g-th event)
+    runs_photon: int = 1  # reverse mode of Sec. VI: N_g runs per occasion (<= 1: off)
+    runs_pair: int = 1
 
     def cstruct(self) -> OrParams:
         p = OrParams()
         for k in ("dt", "eps_r", "kappa", "t0", "adaptive", "forced_substeps", "emission",
                   "pairs", "push_photons", "backend", "seed", "step", "f_photon", "f_pair",
-                  "same_step_generations"):
+                  "same_step_generations", "f_every", "runs_photon", "runs_pair"):
             setattr(p, k, getattr(self, k))
         return p
 

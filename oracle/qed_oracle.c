@@ -390,10 +390,12 @@ uint64_t or_child_id(uint64_t parent, uint64_t seed, int64_t step, int substep, 
   return id;
 }
 
-static void or_draw(uint64_t id, uint64_t seed, int64_t step, int substep, double *r1,
-                    double *r2) {
-  uint32_t ctr[4] = {(uint32_t)step, (uint32_t)substep & 0xFFFFu, (uint32_t)seed,
-                     (uint32_t)(seed >> 32)};
+/* The decision draw (r1, r2) of a sub-step, counter (step, substep, seed lo, seed hi); run
+ * r > 0 of the reverse mode (Sec. VI) puts r in the top byte of the second word. */
+static void or_draw_run(uint64_t id, uint64_t seed, int64_t step, int substep, int run,
+                        double *r1, double *r2) {
+  uint32_t ctr[4] = {(uint32_t)step, ((uint32_t)substep & 0xFFFFu) | ((uint32_t)run << 24),
+                     (uint32_t)seed, (uint32_t)(seed >> 32)};
   uint32_t key[2] = {(uint32_t)id, (uint32_t)(id >> 32)};
   uint32_t o[4];
   or_philox4x32_10(ctr, key, o);
@@ -416,6 +418,26 @@ static int or_generator_runs(uint64_t parent, uint64_t seed, int64_t step, int s
 
 /* The weight factor of children created by a generator with factor fg. */
 static double or_generator_weight(double fg) { return fg > 1.0 ? fg : 1.0; }
+
+/* Sec. VI, the deterministic form: the generator runs once every F occasions.  The parent's
+ * phase phi in [0, F) comes from its own draw (purpose 12, step word 0, so it is the same at
+ * every step); its event number e makes children iff (e + phi) mod F == 0. */
+static int or_generator_every(uint64_t parent, uint64_t seed, uint32_t e, int F) {
+  uint32_t ctr[4] = {0u, 12u << 16, (uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t key[2] = {(uint32_t)parent, (uint32_t)(parent >> 32)};
+  uint32_t o[4];
+  or_philox4x32_10(ctr, key, o);
+  uint64_t phi = ((uint64_t)o[0] * (uint64_t)F) >> 32;
+  return ((uint64_t)e + phi) % (uint64_t)F == 0;
+}
+
+/* Are the children of this event created (every rule of Sec. VI that thins them)? */
+static int or_children_made(const or_params *p, double fg, uint64_t parent, int64_t step,
+                            int substep, int purpose, uint32_t e) {
+  if (!(fg > 1.0)) return 1;
+  if (p->f_every) return or_generator_every(parent, p->seed, e, (int)fg);
+  return or_generator_runs(parent, p->seed, step, substep, purpose, fg);
+}
 
 /* ------------------------------------------------------------------------------------
  * The step.
@@ -562,11 +584,18 @@ static void or_lepton_advance(const or_tables *t, or_store *st, int species, int
     --left;
     if (!p->emission) continue;
     double dtfac = h * OR_ALPHA / p->eps_r;
-    double r1, r2;
-    or_draw(id, p->seed, p->step, kk, &r1, &r2);
-    double Pm = or_rate_modified(t, p->backend, r1, chi, gamma, dtfac);
-    or_note_decision(s, Pm, r2, 0);
-    if (r2 < Pm) {
+    /* the generator runs R times (R > 1 in the reverse mode of Sec. VI), each run with its
+     * own draw, from the momentum the lepton has before the sub-step's events */
+    const int R = p->runs_photon > 1 ? p->runs_photon : 1;
+    const double wrun = st->w[j] / (double)R;
+    double rec[3] = {0.0, 0.0, 0.0};
+    int fired = 0;
+    for (int r = 0; r < R; ++r) {
+      double r1, r2;
+      or_draw_run(id, p->seed, p->step, kk, r, &r1, &r2);
+      double Pm = or_rate_modified(t, p->backend, r1, chi, gamma, dtfac);
+      or_note_decision(s, Pm, r2, 0);
+      if (!(r2 < Pm)) continue;
       double delta = r1 * r1 * r1;
       double eps = delta * gamma; /* photon energy, units m c^2 */
       double pabs = sqrt(mom[0] * mom[0] + mom[1] * mom[1] + mom[2] * mom[2]);
@@ -580,14 +609,19 @@ static void or_lepton_advance(const or_tables *t, or_store *st, int species, int
         c.x[d] = x[d];
       }
       /* the lepton recoils at every event, whether or not the photon is created */
-      for (int d = 0; d < 3; ++d) mom[d] = mom[d] - c.p[d];
-      nev++;
-      s->photon_energy += st->w[j] * eps;
+      if (R == 1) {
+        for (int d = 0; d < 3; ++d) mom[d] = mom[d] - c.p[d];
+      } else {
+        for (int d = 0; d < 3; ++d) rec[d] = rec[d] + c.p[d];
+        fired = 1;
+      }
+      const uint32_t e = nev++;
+      s->photon_energy += wrun * eps;
       double bin = floor(10.0 * (log10(eps) + 8.0));
       if (bin >= 0.0 && bin < (double)OR_SPECTRUM_BINS) s->photon_hist[(int)bin]++;
-      if (or_generator_runs(id, p->seed, p->step, kk, 5, p->f_photon)) {
-        c.w = st->w[j] * or_generator_weight(p->f_photon);
-        c.id = or_child_id(id, p->seed, p->step, kk, 1);
+      if (or_children_made(p, p->f_photon, id, p->step, kk, 5, e)) {
+        c.w = R > 1 ? wrun : st->w[j] * or_generator_weight(p->f_photon);
+        c.id = or_child_id(id, p->seed, p->step, kk, 1 | (r << 8));
         c.parent = id;
         c.birth = (uint32_t)(((uint64_t)(p->step + 1) << 14) | (uint32_t)kk);
         c.species = 2;
@@ -600,6 +634,9 @@ static void or_lepton_advance(const or_tables *t, or_store *st, int species, int
         s->emitted++;
       }
     }
+    /* reverse mode: the mean recoil of the R runs */
+    if (fired)
+      for (int d = 0; d < 3; ++d) mom[d] = mom[d] - rec[d] / (double)R;
   }
   st->x[j] = x[0];
   st->y[j] = x[1];
@@ -646,20 +683,28 @@ static void or_photon_advance(const or_tables *t, or_store *st, int64_t j, const
   double h = span->T / (double)nsub;
   double dtfac = h * OR_ALPHA / p->eps_r;
   int dead = 0;
+  /* reverse mode (Sec. VI): the photon stands for R copies of weight w / R */
+  const int R = p->runs_pair > 1 ? p->runs_pair : 1;
+  double wcur = st->w[j];
   for (int kk = 0; kk < nsub; ++kk) {
     if (p->push_photons)
       for (int d = 0; d < 3; ++d) x[d] += h * (k[d] / kabs); /* photons move at c along k */
     chi_g = or_chi_photon(k, E, B, p->eps_r);
     s->substeps++;
     if (!p->pairs) continue;
-    double r1, r2;
-    or_draw(id, p->seed, p->step, kk, &r1, &r2);
-    double Pp = or_rate_pair(t, p->backend, r1, chi_g, kabs, dtfac);
-    or_note_decision(s, Pp, r2, 1);
-    if (r2 < Pp) {
+    /* R runs of the pair generator (R = 1 but in the reverse mode of Sec. VI), each with
+     * its own draw; every run that fires makes a pair of weight wcur / R */
+    const double wc = R > 1 ? wcur / (double)R : wcur;
+    int m = 0;
+    for (int r = 0; r < R; ++r) {
+      double r1, r2;
+      or_draw_run(id, p->seed, p->step, kk, r, &r1, &r2);
+      double Pp = or_rate_pair(t, p->backend, r1, chi_g, kabs, dtfac);
+      or_note_decision(s, Pp, r2, 1);
+      if (!(r2 < Pp)) continue;
+      ++m;
       /* the photon decays at every event, whether or not the pair is created */
-      dead = 1;
-      if (!or_generator_runs(id, p->seed, p->step, kk, 6, p->f_pair)) break;
+      if (R == 1 && !or_children_made(p, p->f_pair, id, p->step, kk, 6, 0u)) continue;
       or_child e, pos;
       for (int d = 0; d < 3; ++d) {
         e.x[d] = x[d];
@@ -667,11 +712,11 @@ static void or_photon_advance(const or_tables *t, or_store *st, int64_t j, const
         e.p[d] = r1 * k[d];
         pos.p[d] = (1.0 - r1) * k[d];
       }
-      e.w = pos.w = st->w[j] * or_generator_weight(p->f_pair);
+      e.w = pos.w = R > 1 ? wc : wc * or_generator_weight(p->f_pair);
       e.parent = pos.parent = id;
       e.birth = pos.birth = (uint32_t)(((uint64_t)(p->step + 1) << 14) | (uint32_t)kk);
-      e.id = or_child_id(id, p->seed, p->step, kk, 2);
-      pos.id = or_child_id(id, p->seed, p->step, kk, 3);
+      e.id = or_child_id(id, p->seed, p->step, kk, 2 | (r << 8));
+      pos.id = or_child_id(id, p->seed, p->step, kk, 3 | (r << 8));
       e.species = 0;
       pos.species = 1;
       e.tau = pos.tau = (double)(nsub - kk - 1) * h;
@@ -682,13 +727,18 @@ static void or_photon_advance(const or_tables *t, or_store *st, int64_t j, const
       or_push_child(cb, &e);
       or_push_child(cb, &pos);
       s->pairs++;
+    }
+    if (m == R) { /* every copy decayed */
+      dead = 1;
       break;
     }
+    if (m > 0) wcur = wc * (double)(R - m);
   }
   st->x[j] = x[0];
   st->y[j] = x[1];
   st->z[j] = x[2];
   if (dead) st->id[j] = OR_ID_DEAD;
+  else if (wcur != st->w[j]) st->w[j] = wcur;
 }
 
 /* Appends a child to its store; returns its slot, or -1 when the store is full. */
@@ -762,6 +812,16 @@ static int or_append_all(or_store *st, or_childbuf *bufs, int nthreads, or_stats
 int or_step(const or_tables *t, or_store *st, const or_field *f, const or_params *p,
             or_stats *s) {
   memset(s, 0, sizeof(*s));
+  /* the forms of Sec. VI that do not combine: a factor and the reverse mode on one
+   * generator, a deterministic factor that is no integer, more than 64 runs */
+  if ((p->f_photon > 1.0 && p->runs_photon > 1) || (p->f_pair > 1.0 && p->runs_pair > 1) ||
+      p->runs_photon > 64 || p->runs_pair > 64)
+    return -2;
+  if (p->f_every && ((p->f_photon > 1.0 && (p->f_photon != floor(p->f_photon) ||
+                                            p->f_photon > 2147483647.0)) ||
+                     (p->f_pair > 1.0 && (p->f_pair != floor(p->f_pair) ||
+                                          p->f_pair > 2147483647.0))))
+    return -2;
   const int64_t n0[3] = {st[0].count, st[1].count, st[2].count};
   for (int i = 0; i < 3; ++i) s->n_start[i] = n0[i];
   const double tn = p->t0 + (double)p->step * p->dt;

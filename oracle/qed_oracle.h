@@ -87,6 +87,26 @@ typedef struct {
    * E, B, its own n_sub over tau, and its own events; children of children likewise, up to G
    * generations.  Children of generation G + 1 wait for the next step. */
   int same_step_generations;
+  /* The deterministic form of f_g (Sec. VI, the generator run once every f_g occasions).
+   * With f_every set, a factor f_g > 1 must be an integer F, and the children of a parent's
+   * event number e (its event count before the event: the n_events column of a lepton, 0
+   * for a photon, which has one event) are created iff (e + phi) mod F == 0.  The phase phi
+   * in [0, F) is fixed for the parent's life: phi = (o0 F) >> 32 for the first word o0 of
+   * the Philox draw keyed by its id with counter (0, 12 << 16, seed lo, seed hi).  Over the
+   * phase every event is sampled with probability 1/F, as in the random form, and a parent
+   * with n events makes floor(n/F) or ceil(n/F) children. */
+  int f_every;
+  /* The reverse mode of Sec. VI: the generator runs N_g times at every occasion (a value
+   * of at most 1 means off, at most 64; not together with a factor f_g > 1 for the same
+   * generator).  Run r draws from counter (step, substep | r << 24, seed lo, seed hi) (run
+   * 0 is the ordinary draw) and its children get ids with purpose p | r << 8.  Emission: every
+   * run that fires makes a photon of weight w / N_g, with the momentum the lepton had before
+   * the sub-step's events; the lepton recoils by the sum of those photon momenta divided by
+   * N_g, so that the weighted momentum is conserved event by event.  Pairs: the photon
+   * stands for N_g copies of weight w / N_g; every run that fires makes a pair of that
+   * weight, the photon keeps (w / N_g) (N_g - m) after m firings in a sub-step and goes on,
+   * and is removed when all N_g fire. */
+  int runs_photon, runs_pair;
 } or_params;
 
 typedef struct {

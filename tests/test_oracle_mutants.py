@@ -118,6 +118,21 @@ MUTANTS = [
      "      if (kept == 0) { /* the group keeps its weight in its smallest draw */",
      "      if (kept < 0) { /* the group keeps its weight in its smallest draw */",
      ["tests/test_oracle_thin_cells.py"]),
+    ("reverse-mode recoil by the sum of the runs' photons, not their mean",
+     "mom[d] = mom[d] - rec[d] / (double)R;", "mom[d] = mom[d] - rec[d];",
+     ["tests/test_oracle_generator_forms.py::test_reverse_emission_conserves_the_weighted_momentum"]),
+    ("reverse-mode runs that share one draw",
+     "((uint32_t)substep & 0xFFFFu) | ((uint32_t)run << 24),", "((uint32_t)substep & 0xFFFFu),",
+     ["tests/test_oracle_generator_forms.py::test_reverse_emission_runs_are_independent_and_unbiased"]),
+    ("reverse-mode photon that keeps its whole weight after a partial decay",
+     "if (m > 0) wcur = wc * (double)(R - m);", "if (m > 0) wcur = wcur;",
+     ["tests/test_oracle_generator_forms.py::test_reverse_pairs_conserve_the_photon_weight"]),
+    ("deterministic factor without a phase (the first event always makes a child)",
+     "return ((uint64_t)e + phi) % (uint64_t)F == 0;", "return (uint64_t)e % (uint64_t)F == 0;",
+     ["tests/test_oracle_generator_forms.py::test_deterministic_factor_is_unbiased"]),
+    ("deterministic factor whose phase changes along the parent's life",
+     "uint32_t ctr[4] = {0u, 12u << 16,", "uint32_t ctr[4] = {e / 3u, 12u << 16,",
+     ["tests/test_oracle_generator_forms.py::test_deterministic_every_fourth_event_with_one_phase"]),
     ("cell thinning with the global thinning's draw purpose",
      "uint32_t ctr[4] = {(uint32_t)step, 11u << 16,", "uint32_t ctr[4] = {(uint32_t)step, 4u << 16,",
      ["tests/test_oracle_thin_cells.py"]),
