@@ -196,6 +196,28 @@ typedef struct {
                            to G generations (generation G + 1 waits for step n+1).  Needs
                            child arenas (at most 1024 instances, arena space in the
                            workspace, sized with same_step set in qed_work_bytes). */
+  int f_every;          /* the deterministic form of f_g (Sec. VI: the generator run once
+                           every f_g occasions).  Nonzero: a factor f_g > 1 must be an
+                           integer F <= 2^31 - 1, and the children of a parent's event number
+                           e are created iff (e + phi) mod F == 0.  e is the parent's event
+                           count before the event (a lepton's n_events, or 0 at the step start
+                           if its store has no n_events column; 0 for a photon, whose one
+                           event is its decay); phi = (o0 F) >> 32 for the first word o0 of
+                           the Philox draw keyed by the parent id with counter
+                           (0, 12 << 16, seed), so the phase is the parent's for life. */
+  int runs_photon;      /* the reverse mode N_g of Sec. VI for emission and for pair          */
+  int runs_pair;        /* creation: the generator runs N_g times at every sub-step, run r
+                           drawing with counter (step, sub-step | r << 24, seed) (run 0 is the
+                           ordinary draw) and naming its children with purpose p | r << 8.
+                           Emission: each run that fires makes a photon of weight w / N_g
+                           from the lepton's momentum before the sub-step's events, and the
+                           lepton then loses the sum of those photon momenta divided by N_g.
+                           Pairs: the photon stands for N_g copies of weight w / N_g; each
+                           run that fires makes a pair of that weight; after m firings in a
+                           sub-step the photon keeps weight (w / N_g) (N_g - m) and goes on,
+                           and it is removed when all N_g fire.  A value <= 1 means off; at
+                           most 64; not with a factor f_g > 1 on the same generator
+                           (QED_ERR_ARG). */
 } qed_params;
 
 /* Per-step record written by qed_step (device memory). */

@@ -46,9 +46,9 @@ namespace {
 constexpr int kMaxDevices = 64;
 std::mutex g_mu;
 int g_cu_count[kMaxDevices];
-// [precision][field mode][kernel: photon, lepton, extended lepton] resident 256-thread
-// blocks per CU
-int g_occ[kMaxDevices][2][3][3];
+// [precision][field mode][kernel: photon, lepton, extended lepton, reverse-mode lepton]
+// resident 256-thread blocks per CU
+int g_occ[kMaxDevices][2][3][4];
 
 bool device_geometry(int* cus, int precision, int fmode, int kernel, int block, int* per_cu) {
   int dev = 0;
@@ -62,14 +62,13 @@ bool device_geometry(int* cus, int precision, int fmode, int kernel, int block, 
     g_cu_count[dev] = n;
   }
   *cus = g_cu_count[dev];
-  if (fmode < 0 || fmode > 2 || kernel < 0 || kernel > 2) return false;
-  const bool photon = kernel == 0, ext = kernel == 2;
+  if (fmode < 0 || fmode > 2 || kernel < 0 || kernel > 3) return false;
   if (block == 256) {
     int& o = g_occ[dev][precision == QED_MIXED ? 1 : 0][fmode][kernel];
-    if (o == 0) o = step_blocks_per_cu(precision, fmode, photon, ext, 256);
+    if (o == 0) o = step_blocks_per_cu(precision, fmode, kernel, 256);
     *per_cu = o;
   } else {
-    *per_cu = step_blocks_per_cu(precision, fmode, photon, ext, block);
+    *per_cu = step_blocks_per_cu(precision, fmode, kernel, block);
   }
   return true;
 }
@@ -197,6 +196,15 @@ qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_fi
   if ((P.emission || run_photons) && !soa_ok(stores->species[QED_PHOTON], false))
     return QED_ERR_ARG;
   if (!isfinite(P.f_photon) || !isfinite(P.f_pair)) return QED_ERR_ARG;
+  // the forms of Sec. VI that do not combine, and the limits of the run index and phase
+  if ((P.f_photon > 1.0 && P.runs_photon > 1) || (P.f_pair > 1.0 && P.runs_pair > 1) ||
+      P.runs_photon > kMaxRuns || P.runs_pair > kMaxRuns)
+    return QED_ERR_ARG;
+  if (P.f_every && ((P.f_photon > 1.0 && (P.f_photon != floor(P.f_photon) ||
+                                          P.f_photon > 2147483647.0)) ||
+                    (P.f_pair > 1.0 && (P.f_pair != floor(P.f_pair) ||
+                                        P.f_pair > 2147483647.0))))
+    return QED_ERR_ARG;
   if (!finite_pos(P.dt) || !finite_pos(P.eps_r) || !finite_pos(P.kappa) || !isfinite(P.t0))
     return QED_ERR_ARG;
   if (P.precision != QED_FP64 && P.precision != QED_MIXED) return QED_ERR_ARG;
@@ -256,6 +264,10 @@ qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_fi
   a.inv_fg_photon = 1.0 / a.fg_photon;
   a.fg_pair = P.f_pair > 1.0 ? P.f_pair : 1.0;
   a.inv_fg_pair = 1.0 / a.fg_pair;
+  a.every_photon = (P.f_every && P.f_photon > 1.0) ? (unsigned)P.f_photon : 0u;
+  a.every_pair = (P.f_every && P.f_pair > 1.0) ? (unsigned)P.f_pair : 0u;
+  a.runs_photon = P.runs_photon > 1 ? P.runs_photon : 1;
+  a.runs_pair = P.runs_pair > 1 ? P.runs_pair : 1;
   a.adaptive = P.adaptive;
   a.forced = P.forced_substeps;
   a.emission = P.emission;
@@ -302,9 +314,10 @@ qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_fi
 
   int cus = 0, lep_per_cu = 0, pho_per_cu = 0;
   const int fmode = field_mode(field->kind);
-  // the lepton kernel's extended form runs with same-step processing or a photon generator
-  // factor (the launch makes the same choice)
-  const int lep_kernel = (G > 0 || P.f_photon > 1.0) ? 2 : 1;
+  // the lepton kernel's extended form runs with same-step processing, a photon generator
+  // factor or its reverse mode (the launch makes the same choice)
+  const bool lep_ext = G > 0 || P.f_photon > 1.0 || P.runs_photon > 1;
+  const int lep_kernel = P.runs_photon > 1 ? 3 : lep_ext ? 2 : 1;
   if (!device_geometry(&cus, P.precision, fmode, lep_kernel, block, &lep_per_cu) ||
       !device_geometry(&cus, P.precision, fmode, 0, block, &pho_per_cu))
     return QED_ERR_HIP;
@@ -322,8 +335,9 @@ qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_fi
   if (arena > 0) {
     const bool on = G > 0;
     // the lepton kernel continues in the pool only in its extended form (same-step
-    // processing or a generator factor); the pair and generation producers always do
-    const bool lep_pool = on || P.f_photon > 1.0;
+    // processing, a generator factor or its reverse mode); the pair and generation
+    // producers always do
+    const bool lep_pool = lep_ext;
     a.pa = arena_at(w, L.ph_cols[0], L.ph_cnt[0], L.ph_nrec[0], L.ph_base[0], L.ph_chain[0],
                     L.ph_cap, false, lep_waves, L.same_step, on, lep_pool);
     if (a.ex_grid > 0)

@@ -71,17 +71,24 @@ __device__ __forceinline__ float uniform32(uint32_t hi) {
 }
 
 // Counter layout shared by the event draw and the child ids:
-//   key = particle id, counter = (step, sub-step | purpose << 16, seed lo, seed hi).
+//   key = particle id, counter = (step, sub-step | purpose << 16 | run << 24, seed lo, seed hi),
+// run = the run of the reverse mode of Sec. VI (0 for the ordinary generator).  A sub-step
+// code carries the run in its top byte (sub_code), so that records keep both in one word.
 enum Purpose : uint32_t {
   kDraw = 0, kPhotonChild = 1, kElectronChild = 2, kPositronChild = 3, kThin = 4,
   kGenPhoton = 5, kGenPair = 6,  // generator-factor draws (Sec. VI)
   kSchwinger = 7, kSchwingerPos = 8, kSchwingerElectron = 9, kSchwingerPositron = 10,
-  kThinCell = 11  // thinning per cell block
+  kThinCell = 11,  // thinning per cell block
+  kPhase = 12      // phase of the deterministic generator factor (Sec. VI)
 };
+
+__device__ __forceinline__ uint32_t sub_code(int k, int run) {
+  return (uint32_t)k | ((uint32_t)run << 24);
+}
 
 __device__ __forceinline__ uint4 draw_words(uint64_t id, uint64_t seed, uint32_t step, uint32_t sub,
                                             uint32_t purpose) {
-  return philox4x32_10(make_uint4(step, (sub & 0xFFFFu) | (purpose << 16), (uint32_t)seed,
+  return philox4x32_10(make_uint4(step, (sub & 0xFF00FFFFu) | (purpose << 16), (uint32_t)seed,
                                   (uint32_t)(seed >> 32)),
                        (uint32_t)id, (uint32_t)(id >> 32));
 }
@@ -94,7 +101,7 @@ __device__ __forceinline__ uint64_t child_id(uint64_t parent, uint64_t seed, uin
 }
 
 __device__ __forceinline__ uint32_t birth_code(uint32_t step, uint32_t sub) {
-  return ((step + 1u) << 14) | sub;
+  return ((step + 1u) << 14) | (sub & 0x3FFFu);
 }
 
 // Tunable generator factor (Sec. VI): does the generator that fired for `parent` at this
@@ -104,6 +111,16 @@ __device__ __forceinline__ bool generator_runs(uint64_t parent, uint64_t seed, u
                                                uint32_t sub, uint32_t purpose, double inv_fg) {
   const uint4 o = draw_words(parent, seed, step, sub, purpose);
   return uniform64(o.x, o.y) < inv_fg;
+}
+
+// Deterministic form (Sec. VI, once every F occasions): the children of the parent's event
+// number e are created iff (e + phi) mod F == 0, with the phase phi = (o.x F) >> 32 in
+// [0, F) from the parent's own draw at step word 0, the same over its life.
+__device__ __forceinline__ bool generator_every(uint64_t parent, uint64_t seed, uint32_t e,
+                                                uint32_t F) {
+  const uint4 o = draw_words(parent, seed, 0u, 0u, kPhase);
+  const uint32_t phi = (uint32_t)(((uint64_t)o.x * (uint64_t)F) >> 32);
+  return ((uint64_t)e + (uint64_t)phi) % (uint64_t)F == 0ull;
 }
 
 // ------------------------------------------------------------------------------------

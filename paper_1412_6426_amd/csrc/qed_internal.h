@@ -110,6 +110,7 @@ inline ArenaGeometry arena_geometry(long long cap, int waves, bool pool) {
 
 // Upper bound of generations advanced in their birth step (qed_params.same_step_generations).
 constexpr int kMaxGenerations = 64;
+constexpr int kMaxRuns = 64;  // runs of the reverse mode of Sec. VI (the run sits in one byte)
 
 struct WorkLayout {
   size_t n0;        // long long [n_inst * 3]: live slots at step start (0 when frozen)
@@ -317,6 +318,10 @@ struct StepArgs {
   double dtfac_per_h;    // alpha / eps_r
   // generator factors (Sec. VI): fg = f_g when f_g > 1, else 1 (off); inv_fg = 1 / f_g
   double fg_photon, inv_fg_photon, fg_pair, inv_fg_pair;
+  // deterministic form (Sec. VI): every_* = F when the factor is taken once every F events,
+  // else 0; runs_* = N_g of the reverse mode (1: off)
+  unsigned every_photon, every_pair;
+  int runs_photon, runs_pair;
   int adaptive, forced, emission, pairs, push_photons, freeze_on_drop;
   int generations;  // children advanced in their birth step: generations (0: none)
   long long tile;  // particles per work chunk (0: one chunk per wavefront)
@@ -396,7 +401,7 @@ hipError_t launch_generator_trials(const DevTables* tables, int generator, doubl
 // Persistent-grid sizing: resident workgroups per CU for the step kernels.
 // Resident workgroups per CU of the step kernel that a launch uses: the photon kernel, or
 // the lepton kernel in its plain or extended form (EXT), for a field mode (field_mode).
-int step_blocks_per_cu(int precision, int fmode, bool photon, bool ext, int block);
+int step_blocks_per_cu(int precision, int fmode, int kind, int block);
 int field_mode(int kind);
 
 }  // namespace qedk

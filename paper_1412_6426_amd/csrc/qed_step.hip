@@ -799,10 +799,9 @@ struct LeptonShape {
   static constexpr int min_waves = global_table ? 3 : 1;
 };
 
-template <bool MIXED, int FMODE, bool EXT>
-__global__ void __launch_bounds__(256)
-    __attribute__((amdgpu_waves_per_eu(LeptonShape<MIXED, FMODE, EXT>::min_waves)))
-    lepton_kernel(StepArgs a) {
+// RUNS: the reverse mode of Sec. VI (runs_photon > 1) is compiled in (with EXT).
+template <bool MIXED, int FMODE, bool EXT, bool RUNS>
+__device__ __forceinline__ void lepton_step(const StepArgs& a) {
   using Tab = typename TabType<MIXED>::T;
   constexpr bool kGlobalTab = LeptonShape<MIXED, FMODE, EXT>::global_table;
   __shared__ Tab tab_lds[kGlobalTab ? 1 : kTableN];
@@ -925,10 +924,12 @@ __global__ void __launch_bounds__(256)
     // A sub-step whose end state breaks Eq. (29) is taken again from its start at half the
     // length (rare: such lanes repeat the push while the others wait).
     bool emit = false;
-    double f = 0.0, g = 1.0;
+    double f = 0.0, g = 1.0, chi = 0.0;
+    // the weight of an event's photon before any factor: w, or w / N_g in the reverse mode
+    // of Sec. VI, whose runs beyond the first follow the first below
+    const double wrun = RUNS ? wgt / (double)a.runs_photon : wgt;
     if (slot >= 0) {
       const V3 p0 = p;
-      double chi;
       for (;;) {
         if (FMODE == kFieldE) {
           // B = 0: the Boris rotation is the identity and the push is p += q h E
@@ -956,7 +957,7 @@ __global__ void __launch_bounds__(256)
         double delta;
         emit = emission_decision<MIXED>(tab, ser64, ser32, o, chi, g, dtfac, cnt, delta);
         if (emit) {
-          emit = emission_photon(p, g, delta, wgt, bs, cnt, f);
+          emit = emission_photon(p, g, delta, wrun, bs, cnt, f);
           if (emit) ++nev;
         }
       }
@@ -964,13 +965,17 @@ __global__ void __launch_bounds__(256)
 
     // ---- emitted photons: into the wavefront's arena share, else staged and reserved ----
     // With a generator factor f_g (Sec. VI) the photon of an event is created with
-    // probability 1 / f_g and carries f_g times the lepton's weight; the recoil below
-    // happens at every event.
+    // probability 1 / f_g, or for every f_g-th event of the lepton in the deterministic
+    // form, and carries f_g times the lepton's weight; the recoil below happens at every
+    // event.
     wc.substeps += __popcll(act);
     bool child = emit;
-    if (EXT && emit && a.fg_photon > 1.0)
-      child = generator_runs(id, seed, step, (uint32_t)k, kGenPhoton, a.inv_fg_photon);
-    const double cw = EXT ? wgt * a.fg_photon : wgt;
+    if (EXT && emit) {
+      if (a.every_photon) child = generator_every(id, seed, nev - 1u, a.every_photon);
+      else if (a.fg_photon > 1.0)
+        child = generator_runs(id, seed, step, (uint32_t)k, kGenPhoton, a.inv_fg_photon);
+    }
+    const double cw = RUNS ? wrun : EXT ? wgt * a.fg_photon : wgt;
     const bool ss = EXT && a.generations > 0;
     const uint64_t em = wave_ballot(child);
     ArenaSpan span;
@@ -1035,6 +1040,75 @@ __global__ void __launch_bounds__(256)
         staged += n_new;
       }
     }
+    if constexpr (RUNS) {
+      // reverse mode: runs 1 .. N_g - 1 of the generator on the same state, each photon
+      // appended as above; the lepton then recoils by the mean of the runs' photons
+      V3 rec = {0.0, 0.0, 0.0};
+      if (emit) rec = {f * p.x, f * p.y, f * p.z};
+      bool fired = emit;
+      for (int run = 1; run < a.runs_photon; ++run) {
+        const uint32_t sc = sub_code(k, run);
+        bool e2 = false;
+        double f2 = 0.0;
+        if (slot >= 0 && a.emission) {
+          const uint4 o = draw_words(id, seed, step, sc, kDraw);
+          double delta;
+          e2 = emission_decision<MIXED>(tab, ser64, ser32, o, chi, g, dtfac, cnt, delta);
+          if (e2) {
+            e2 = emission_photon(p, g, delta, wrun, bs, cnt, f2);
+            if (e2) ++nev;
+          }
+        }
+        const uint64_t em2 = wave_ballot(e2);
+        if (em2) {
+          const int n_new = __popcll(em2);
+          wc.events += n_new;
+          ArenaSpan span2;
+          if (pa.waves > 0 && arena_reserve(pa, wid, acur, n_new, span2)) {
+            tally.add(pa, wid, em2, e2, inst);
+            if (e2) {
+              const long long r = span2.at(__popcll(em2 & below));
+              pa.x[r] = x.x;
+              pa.y[r] = x.y;
+              pa.z[r] = x.z;
+              pa.px[r] = f2 * p.x;
+              pa.py[r] = f2 * p.y;
+              pa.pz[r] = f2 * p.z;
+              pa.w[r] = wrun;
+              pa.parent[r] = id;
+              pa.sub[r] = sc;
+              pa.inst[r] = (unsigned)inst;
+              if (ss) record_same_step<FMODE>(pa, r, (double)(left - 1) * h, E, B);
+            }
+          } else {
+            // reserved directly in the stores: not advanced in this step
+            if (ss) wc.deferred += __popcll(wave_ballot(e2 && left > 1));
+            wave_append<QED_PHOTON>(a, e2, inst, cnt, [&](const qed_soa& o, long long s) {
+              o.x[s] = x.x;
+              o.y[s] = x.y;
+              o.z[s] = x.z;
+              o.px[s] = f2 * p.x;
+              o.py[s] = f2 * p.y;
+              o.pz[s] = f2 * p.z;
+              o.w[s] = wrun;
+              o.id[s] = child_id(id, seed, step, sc, kPhotonChild);
+              o.parent[s] = id;
+              o.birth[s] = birth_code(step, (uint32_t)k);
+              if (o.n_events) o.n_events[s] = 0u;
+            });
+          }
+        }
+        if (e2) {
+          rec = {rec.x + f2 * p.x, rec.y + f2 * p.y, rec.z + f2 * p.z};
+          fired = true;
+        }
+      }
+      if (fired) {
+        const double R = (double)a.runs_photon;
+        p = {p.x - rec.x / R, p.y - rec.y / R, p.z - rec.z / R};
+      }
+      emit = false;  // the recoil is done
+    }
     if (emit) {
       // recoil: the lepton keeps p - k (momentum conservation, Sec. IV.F)
       const V3 kq = {f * p.x, f * p.y, f * p.z};
@@ -1063,6 +1137,20 @@ __global__ void __launch_bounds__(256)
   wave_to_block(bs, cnt, wc);
   __syncthreads();
   block_stats_store(bs, a.lep_part);
+}
+
+template <bool MIXED, int FMODE, bool EXT>
+__global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(LeptonShape<MIXED, FMODE, EXT>::min_waves)))
+    lepton_kernel(StepArgs a) {
+  lepton_step<MIXED, FMODE, EXT, false>(a);
+}
+
+// The reverse mode of Sec. VI in a kernel of its own: its extra runs hold more registers,
+// which the other forms would pay for in occupancy.
+template <bool MIXED, int FMODE>
+__global__ void __launch_bounds__(256) lepton_runs_kernel(StepArgs a) {
+  lepton_step<MIXED, FMODE, true, true>(a);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1277,16 +1365,22 @@ __global__ void __launch_bounds__(256) photon_kernel(StepArgs a) {
           if (a.push_photons) x = {x.x + st.hk * kv.x, x.y + st.hk * kv.y, x.z + st.hk * kv.z};
           if (!a.pairs) continue;
           if (!bound_reachable<MIXED>(st.pbound)) {
-            ++cnt.early;
+            cnt.early += a.runs_pair;
             continue;
           }
-          const uint4 o = draw_words(id, seed, step, (uint32_t)k, kDraw);
-          if (below_bound<MIXED>(o, st.pbound)) {
+          // a candidate if the draw of any run (N_g of them in the reverse mode of Sec. VI)
+          // falls below the bound
+          bool hit = below_bound<MIXED>(draw_words(id, seed, step, (uint32_t)k, kDraw),
+                                        st.pbound);
+          for (int run = 1; run < a.runs_pair && !hit; ++run)
+            hit = below_bound<MIXED>(draw_words(id, seed, step, sub_code(k, run), kDraw),
+                                     st.pbound);
+          if (hit) {
             cand = true;
             kcand = k;
             break;
           }
-          ++cnt.early;
+          cnt.early += a.runs_pair;
         }
         if (!cand) {
           cnt.subs += st.nsub;
@@ -1339,78 +1433,17 @@ struct ExactCtx {
   const double* bound;  // per-octave pair-rate bounds (LDS)
 };
 
-// Exact pair decision for the candidates list[i0 + lane] (i0 + lane < n); all lanes call.
-template <bool MIXED, int FMODE>
-__device__ __forceinline__ void exact_batch(const StepArgs& a, ExactCtx& c, PairStage& ps,
-                                            LaneCounters& cnt, WaveCounters& wc,
-                                            const unsigned long long* list, long long i0,
-                                            long long n) {
+// The pair records of the lanes with `make` into the wavefront's arena share or pool chunks,
+// else staged and reserved in the stores (an electron and a positron each); all lanes call.
+// `sub` is the sub-step code (sub-step and run), `later` whether the pair has time left in
+// the step.
+template <int FMODE>
+__device__ __forceinline__ void exact_append(const StepArgs& a, ExactCtx& c, PairStage& ps,
+                                             LaneCounters& cnt, WaveCounters& wc, bool make,
+                                             const V3& x, const V3& kv, double r1, double wp,
+                                             uint64_t id, uint32_t sub, int inst, double tau,
+                                             const V3& Ef, const V3& Bf, bool later) {
   const uint64_t below = lanes_below();
-  const qed_soa& S = a.sp[QED_PHOTON];
-  const long long i = i0 + lane_id();
-  bool pair = false, make = false;
-  double r1 = 0.0, wp = 0.0, tau = 0.0;
-  int kpair = 0, inst = 0, nsub = 0;
-  long long s = 0;
-  V3 x{}, kv{}, Ef{}, Bf{};
-  uint64_t id = 0;
-  if (i < n) {
-    const unsigned long long e = list[i];
-    const long long g = (long long)(e >> 16);
-    const int kc = (int)(e & 0xFFFFull);
-    int lo = 0, hi = a.n_inst;  // pho_pref[lo] <= g < pho_pref[hi]
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (a.pho_pref[mid] <= g) lo = mid;
-      else hi = mid;
-    }
-    inst = lo;
-    s = a.inst[inst].base[QED_PHOTON] + (g - a.pho_pref[inst]);
-    id = S.id[s];
-    x = {S.x[s], S.y[s], S.z[s]};
-    kv = {S.px[s], S.py[s], S.pz[s]};
-    const double kabs = sqrt(dot(kv, kv));
-    const uint64_t seed = a.inst[inst].seed;
-    V3 E, B;
-    if (FMODE == kFieldLocal) field_at_position<true>(c.fld, a.inst[inst].amp, x, E, B);
-    else instance_fields<FMODE>(a, inst, E, B);
-    const PhotonSetup st = photon_setup<MIXED>(a, E, B, kv, kabs, c.bound, nullptr);
-    int done = st.nsub;
-    for (int k = 0; k < st.nsub; ++k) {
-      if (a.push_photons) x = {x.x + st.hk * kv.x, x.y + st.hk * kv.y, x.z + st.hk * kv.z};
-      if (k < kc) continue;  // settled by the bound in photon_kernel
-      const uint4 o = draw_words(id, seed, c.step, (uint32_t)k, kDraw);
-      if (k > kc && !below_bound<MIXED>(o, st.pbound)) {
-        ++cnt.early;
-        continue;
-      }
-      if (pair_decision<MIXED>(a, c.ser64, c.ser32, o, st.chi, st.pref, cnt, &r1)) {
-        pair = true;
-        kpair = k;
-        done = k + 1;
-        break;
-      }
-    }
-    cnt.subs += done - kc;
-    if (a.push_photons) {
-      S.x[s] = x.x;
-      S.y[s] = x.y;
-      S.z[s] = x.z;
-    }
-    if (pair) {
-      // the photon decays at every event; with a generator factor f_g (Sec. VI) the pair is
-      // created with probability 1 / f_g and carries f_g times the photon's weight
-      S.id[s] = QED_ID_DEAD;
-      make = a.fg_pair > 1.0
-                 ? generator_runs(id, seed, c.step, (uint32_t)kpair, kGenPair, a.inv_fg_pair)
-                 : true;
-      wp = S.w[s] * a.fg_pair;
-      nsub = st.nsub;
-      tau = (double)(st.nsub - kpair - 1) * st.h;
-      Ef = E;
-      Bf = B;
-    }
-  }
   const uint64_t pm = wave_ballot(make);
   if (!pm) return;
   const int n_new = __popcll(pm);
@@ -1431,14 +1464,14 @@ __device__ __forceinline__ void exact_batch(const StepArgs& a, ExactCtx& c, Pair
       qa.r1[r] = r1;
       qa.w[r] = wp;
       qa.parent[r] = id;
-      qa.sub[r] = (unsigned)kpair;
+      qa.sub[r] = sub;
       qa.inst[r] = (unsigned)inst;
       if (a.generations > 0) record_same_step<FMODE>(qa, r, tau, Ef, Bf);
     }
     return;
   }
   // reserved directly in the stores: not advanced in this step (an electron and a positron)
-  if (a.generations > 0) wc.deferred += 2 * __popcll(wave_ballot(make && kpair < nsub - 1));
+  if (a.generations > 0) wc.deferred += 2 * __popcll(wave_ballot(later));
   // ---- else stage them and reserve e-/e+ slots once per batch ----
   if (c.staged + n_new > kStageCap) {
     flush_pairs(a, ps, c.staged, c.step, cnt);
@@ -1455,14 +1488,180 @@ __device__ __forceinline__ void exact_batch(const StepArgs& a, ExactCtx& c, Pair
     ps.r1[r] = r1;
     ps.w[r] = wp;
     ps.parent[r] = id;
-    ps.sub[r] = (unsigned)kpair;
+    ps.sub[r] = sub;
     ps.inst[r] = inst;
   }
   c.staged += n_new;
 }
 
+// One candidate of the photon kernel's lists, re-derived from the stores: its slot, instance,
+// columns, fields and setup, and the sub-step kc its draw fell below the bound at.
+struct ExactCand {
+  long long s;
+  int inst, kc;
+  uint64_t id, seed;
+  V3 x, kv, E, B;
+  PhotonSetup st;
+};
+
 template <bool MIXED, int FMODE>
-__global__ void __launch_bounds__(256) photon_exact_kernel(StepArgs a) {
+__device__ __forceinline__ ExactCand load_candidate(const StepArgs& a, const ExactCtx& c,
+                                                    unsigned long long e) {
+  const qed_soa& S = a.sp[QED_PHOTON];
+  ExactCand q;
+  const long long g = (long long)(e >> 16);
+  q.kc = (int)(e & 0xFFFFull);
+  int lo = 0, hi = a.n_inst;  // pho_pref[lo] <= g < pho_pref[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (a.pho_pref[mid] <= g) lo = mid;
+    else hi = mid;
+  }
+  q.inst = lo;
+  q.s = a.inst[q.inst].base[QED_PHOTON] + (g - a.pho_pref[q.inst]);
+  q.id = S.id[q.s];
+  q.x = {S.x[q.s], S.y[q.s], S.z[q.s]};
+  q.kv = {S.px[q.s], S.py[q.s], S.pz[q.s]};
+  const double kabs = sqrt(dot(q.kv, q.kv));
+  q.seed = a.inst[q.inst].seed;
+  if (FMODE == kFieldLocal) field_at_position<true>(c.fld, a.inst[q.inst].amp, q.x, q.E, q.B);
+  else instance_fields<FMODE>(a, q.inst, q.E, q.B);
+  q.st = photon_setup<MIXED>(a, q.E, q.B, q.kv, kabs, c.bound, nullptr);
+  return q;
+}
+
+// Exact pair decision for the candidates list[i0 + lane] (i0 + lane < n); all lanes call.
+template <bool MIXED, int FMODE>
+__device__ __forceinline__ void exact_batch(const StepArgs& a, ExactCtx& c, PairStage& ps,
+                                            LaneCounters& cnt, WaveCounters& wc,
+                                            const unsigned long long* list, long long i0,
+                                            long long n) {
+  const qed_soa& S = a.sp[QED_PHOTON];
+  const long long i = i0 + lane_id();
+  bool pair = false, make = false;
+  double r1 = 0.0, wp = 0.0, tau = 0.0;
+  int kpair = 0, inst = 0, nsub = 0;
+  V3 x{}, kv{}, Ef{}, Bf{};
+  uint64_t id = 0;
+  if (i < n) {
+    const ExactCand q = load_candidate<MIXED, FMODE>(a, c, list[i]);
+    const PhotonSetup& st = q.st;
+    const long long s = q.s;
+    inst = q.inst;
+    id = q.id;
+    x = q.x;
+    kv = q.kv;
+    int done = st.nsub;
+    for (int k = 0; k < st.nsub; ++k) {
+      if (a.push_photons) x = {x.x + st.hk * kv.x, x.y + st.hk * kv.y, x.z + st.hk * kv.z};
+      if (k < q.kc) continue;  // settled by the bound in photon_kernel
+      const uint4 o = draw_words(id, q.seed, c.step, (uint32_t)k, kDraw);
+      if (k > q.kc && !below_bound<MIXED>(o, st.pbound)) {
+        ++cnt.early;
+        continue;
+      }
+      if (pair_decision<MIXED>(a, c.ser64, c.ser32, o, st.chi, st.pref, cnt, &r1)) {
+        pair = true;
+        kpair = k;
+        done = k + 1;
+        break;
+      }
+    }
+    cnt.subs += done - q.kc;
+    if (a.push_photons) {
+      S.x[s] = x.x;
+      S.y[s] = x.y;
+      S.z[s] = x.z;
+    }
+    if (pair) {
+      // the photon decays at every event; with a generator factor f_g (Sec. VI) the pair is
+      // created with probability 1 / f_g, or for one photon in f_g in the deterministic
+      // form, and carries f_g times the photon's weight
+      S.id[s] = QED_ID_DEAD;
+      make = a.every_pair     ? generator_every(id, q.seed, 0u, a.every_pair)
+             : a.fg_pair > 1.0 ? generator_runs(id, q.seed, c.step, (uint32_t)kpair, kGenPair,
+                                                a.inv_fg_pair)
+                               : true;
+      wp = S.w[s] * a.fg_pair;
+      nsub = st.nsub;
+      tau = (double)(st.nsub - kpair - 1) * st.h;
+      Ef = q.E;
+      Bf = q.B;
+    }
+  }
+  exact_append<FMODE>(a, c, ps, cnt, wc, make, x, kv, r1, wp, id, (uint32_t)kpair, inst, tau,
+                      Ef, Bf, make && kpair < nsub - 1);
+}
+
+// The same in the reverse mode of Sec. VI (N_g = runs_pair > 1): the photon stands for N_g
+// copies of weight w / N_g.  Lanes go through their sub-steps together from the candidate's
+// kc; at each, every run draws (the bound settles most), each run that fires makes a pair of
+// the copies' weight, the photon keeps the weight of the copies left and is removed when all
+// N_g fire.  Pairs are appended run by run, so a photon can make several.
+template <bool MIXED, int FMODE>
+__device__ __forceinline__ void exact_batch_runs(const StepArgs& a, ExactCtx& c, PairStage& ps,
+                                                 LaneCounters& cnt, WaveCounters& wc,
+                                                 const unsigned long long* list, long long i0,
+                                                 long long n) {
+  const qed_soa& S = a.sp[QED_PHOTON];
+  const long long i = i0 + lane_id();
+  const int R = a.runs_pair;
+  bool live = i < n;
+  ExactCand q{};
+  int k = 0;
+  double wcur = 0.0;
+  if (live) {
+    q = load_candidate<MIXED, FMODE>(a, c, list[i]);
+    // the sub-steps before kc were settled by the bound: only the push remains
+    if (a.push_photons)
+      for (; k < q.kc; ++k)
+        q.x = {q.x.x + q.st.hk * q.kv.x, q.x.y + q.st.hk * q.kv.y, q.x.z + q.st.hk * q.kv.z};
+    k = q.kc;
+    wcur = S.w[q.s];
+  }
+  while (wave_ballot(live)) {
+    double wc_run = 0.0;
+    if (live) {
+      if (a.push_photons)
+        q.x = {q.x.x + q.st.hk * q.kv.x, q.x.y + q.st.hk * q.kv.y, q.x.z + q.st.hk * q.kv.z};
+      wc_run = wcur / (double)R;
+    }
+    int m = 0;
+    const double tau = live ? (double)(q.st.nsub - k - 1) * q.st.h : 0.0;
+    for (int run = 0; run < R; ++run) {
+      bool make = false;
+      double r1 = 0.0;
+      const uint32_t sc = sub_code(k, run);
+      if (live) {
+        const uint4 o = draw_words(q.id, q.seed, c.step, sc, kDraw);
+        if (!below_bound<MIXED>(o, q.st.pbound)) ++cnt.early;
+        else make = pair_decision<MIXED>(a, c.ser64, c.ser32, o, q.st.chi, q.st.pref, cnt, &r1);
+        m += make;
+      }
+      exact_append<FMODE>(a, c, ps, cnt, wc, make, q.x, q.kv, r1, wc_run, q.id, sc, q.inst, tau,
+                          q.E, q.B, make && k < q.st.nsub - 1);
+    }
+    if (live) {
+      ++k;
+      ++cnt.subs;
+      const bool dead = m == R;
+      if (!dead && m > 0) wcur = wc_run * (double)(R - m);
+      if (dead || k == q.st.nsub) {
+        live = false;
+        if (a.push_photons) {
+          S.x[q.s] = q.x.x;
+          S.y[q.s] = q.x.y;
+          S.z[q.s] = q.x.z;
+        }
+        if (dead) S.id[q.s] = QED_ID_DEAD;
+        else if (wcur != S.w[q.s]) S.w[q.s] = wcur;
+      }
+    }
+  }
+}
+
+template <bool MIXED, int FMODE, bool RUNS>
+__device__ __forceinline__ void exact_pass(const StepArgs& a) {
   __shared__ BlockStats bs;
   __shared__ PairStage pstage[kWavesPerBlock];
   __shared__ double sbound[kBoundEntries];
@@ -1492,14 +1691,18 @@ __global__ void __launch_bounds__(256) photon_exact_kernel(StepArgs a) {
   for (int sw = c.wid; sw < a.pho_waves; sw += V) {
     const long long n = (long long)a.candn[sw];
     const unsigned long long* list = a.candw + (size_t)sw * a.cand_per_wave;
-    for (long long i0 = 0; i0 < n; i0 += 64)
-      exact_batch<MIXED, FMODE>(a, c, ps, cnt, wc, list, i0, n);
+    for (long long i0 = 0; i0 < n; i0 += 64) {
+      if constexpr (RUNS) exact_batch_runs<MIXED, FMODE>(a, c, ps, cnt, wc, list, i0, n);
+      else exact_batch<MIXED, FMODE>(a, c, ps, cnt, wc, list, i0, n);
+    }
   }
   // then the overflow list
   long long n = (long long)hdr->n_cand;
   if (n > a.cand_cap) n = a.cand_cap;
-  for (long long i0 = (long long)c.wid * 64; i0 < n; i0 += (long long)V * 64)
-    exact_batch<MIXED, FMODE>(a, c, ps, cnt, wc, a.cand, i0, n);
+  for (long long i0 = (long long)c.wid * 64; i0 < n; i0 += (long long)V * 64) {
+    if constexpr (RUNS) exact_batch_runs<MIXED, FMODE>(a, c, ps, cnt, wc, a.cand, i0, n);
+    else exact_batch<MIXED, FMODE>(a, c, ps, cnt, wc, a.cand, i0, n);
+  }
 
   if (c.staged > 0) flush_pairs(a, ps, c.staged, c.step, cnt);
   if (a.qa.waves > 0) {
@@ -1509,6 +1712,17 @@ __global__ void __launch_bounds__(256) photon_exact_kernel(StepArgs a) {
   wave_to_block(bs, cnt, wc);
   __syncthreads();
   block_stats_store(bs, a.ex_part);
+}
+
+template <bool MIXED, int FMODE>
+__global__ void __launch_bounds__(256) photon_exact_kernel(StepArgs a) {
+  exact_pass<MIXED, FMODE, false>(a);
+}
+
+// The reverse mode of Sec. VI (runs_pair > 1) in a kernel of its own, for the registers.
+template <bool MIXED, int FMODE>
+__global__ void __launch_bounds__(256) photon_exact_runs_kernel(StepArgs a) {
+  exact_pass<MIXED, FMODE, true>(a);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1809,7 +2023,7 @@ struct GenStream {
 
 // Electrons and positrons of the input pair records, each advanced through its tau; a lane
 // whose lepton has done all its sub-steps takes the next one from the wavefront's stream.
-template <bool MIXED, int FMODE>
+template <bool MIXED, int FMODE, bool RUNS>
 __device__ __forceinline__ void gen_lepton_phase(const StepArgs& a, const GenArgs& q,
                                                  GenWave& gw, int V,
                                                  const typename TabType<MIXED>::T* tab,
@@ -1883,11 +2097,9 @@ __device__ __forceinline__ void gen_lepton_phase(const StepArgs& a, const GenArg
     if (wave_ballot(slot >= 0) == 0) break;
 
     // ---- one sub-step (taken again at half the length if its end state breaks Eq. (29)) ----
-    bool emit = false;
-    double f = 0.0;
+    double g = 1.0, chi = 0.0;
     if (slot >= 0) {
       const V3 p0 = p;
-      double g, chi;
       for (;;) {
         if (FMODE == kFieldE) {
           p = {p0.x + 2.0 * qh2 * E.x, p0.y + 2.0 * qh2 * E.y, p0.z + 2.0 * qh2 * E.z};
@@ -1910,64 +2122,86 @@ __device__ __forceinline__ void gen_lepton_phase(const StepArgs& a, const GenArg
       const double hg = h / g;
       x = {x.x + hg * p.x, x.y + hg * p.y, x.z + hg * p.z};
       ++cnt.subs;
-      if (a.emission) {
-        const uint4 o = draw_words(id, seed, step, (uint32_t)k, kDraw);
+    }
+    // the emission generator, N_g times in the reverse mode of Sec. VI (as in lepton_kernel)
+    const int runs = RUNS ? a.runs_photon : 1;
+    const double wrun = wgt / (double)runs;
+    V3 rec = {0.0, 0.0, 0.0};
+    bool fired = false;
+    for (int run = 0; run < runs; ++run) {
+      const uint32_t sc = sub_code(k, run);
+      bool emit = false;
+      double f = 0.0;
+      if (slot >= 0 && a.emission) {
+        const uint4 o = draw_words(id, seed, step, sc, kDraw);
         double delta;
         emit = emission_decision<MIXED>(tab, ser64, ser32, o, chi, g, dtfac, cnt, delta);
         if (emit) {
-          emit = emission_photon(p, g, delta, wgt, bs, cnt, f);
+          emit = emission_photon(p, g, delta, wrun, bs, cnt, f);
           if (emit) ++nev;
         }
       }
-    }
-    bool child = emit;
-    if (emit && a.fg_photon > 1.0)
-      child = generator_runs(id, seed, step, (uint32_t)k, kGenPhoton, a.inv_fg_photon);
-    const uint64_t em = wave_ballot(child);
-    if (em) {
-      const int n_new = __popcll(em);
-      wc.events += n_new;
-      const double cw = wgt * a.fg_photon;
-      const bool later = child && left > 1;  // the photon has time left in the step
-      ArenaSpan span;
-      if (O.waves > 0 && arena_reserve(O, gw.wid, gw.cp, n_new, span)) {
-        gw.tp.add(O, gw.wid, em, child, inst);
-        if (child) {
-          const long long rr = span.at(__popcll(em & below));
-          O.x[rr] = x.x;
-          O.y[rr] = x.y;
-          O.z[rr] = x.z;
-          O.px[rr] = f * p.x;
-          O.py[rr] = f * p.y;
-          O.pz[rr] = f * p.z;
-          O.w[rr] = cw;
-          O.parent[rr] = id;
-          O.sub[rr] = (unsigned)k;
-          O.inst[rr] = (unsigned)inst;
-          record_same_step<FMODE>(O, rr, (double)(left - 1) * h, E, B);
+      bool child = emit;
+      if (emit) {
+        if (a.every_photon) child = generator_every(id, seed, nev - 1u, a.every_photon);
+        else if (a.fg_photon > 1.0)
+          child = generator_runs(id, seed, step, (uint32_t)k, kGenPhoton, a.inv_fg_photon);
+      }
+      const uint64_t em = wave_ballot(child);
+      if (em) {
+        const int n_new = __popcll(em);
+        wc.events += n_new;
+        const double cw = runs > 1 ? wrun : wgt * a.fg_photon;
+        const bool later = child && left > 1;  // the photon has time left in the step
+        ArenaSpan span;
+        if (O.waves > 0 && arena_reserve(O, gw.wid, gw.cp, n_new, span)) {
+          gw.tp.add(O, gw.wid, em, child, inst);
+          if (child) {
+            const long long rr = span.at(__popcll(em & below));
+            O.x[rr] = x.x;
+            O.y[rr] = x.y;
+            O.z[rr] = x.z;
+            O.px[rr] = f * p.x;
+            O.py[rr] = f * p.y;
+            O.pz[rr] = f * p.z;
+            O.w[rr] = cw;
+            O.parent[rr] = id;
+            O.sub[rr] = sc;
+            O.inst[rr] = (unsigned)inst;
+            record_same_step<FMODE>(O, rr, (double)(left - 1) * h, E, B);
+          }
+          if (q.last) wc.deferred += __popcll(wave_ballot(later));
+        } else {
+          // the arena is full: reserved directly, not advanced in this step
+          wave_append<QED_PHOTON>(a, child, inst, cnt, [&](const qed_soa& o, long long s2) {
+            o.x[s2] = x.x;
+            o.y[s2] = x.y;
+            o.z[s2] = x.z;
+            o.px[s2] = f * p.x;
+            o.py[s2] = f * p.y;
+            o.pz[s2] = f * p.z;
+            o.w[s2] = cw;
+            o.id[s2] = child_id(id, seed, step, sc, kPhotonChild);
+            o.parent[s2] = id;
+            o.birth[s2] = birth_code(step, (uint32_t)k);
+            if (o.n_events) o.n_events[s2] = 0u;
+          });
+          wc.deferred += __popcll(wave_ballot(later));
         }
-        if (q.last) wc.deferred += __popcll(wave_ballot(later));
-      } else {
-        // the arena is full: reserved directly, not advanced in this step
-        wave_append<QED_PHOTON>(a, child, inst, cnt, [&](const qed_soa& o, long long s2) {
-          o.x[s2] = x.x;
-          o.y[s2] = x.y;
-          o.z[s2] = x.z;
-          o.px[s2] = f * p.x;
-          o.py[s2] = f * p.y;
-          o.pz[s2] = f * p.z;
-          o.w[s2] = cw;
-          o.id[s2] = child_id(id, seed, step, (uint32_t)k, kPhotonChild);
-          o.parent[s2] = id;
-          o.birth[s2] = birth_code(step, (uint32_t)k);
-          if (o.n_events) o.n_events[s2] = 0u;
-        });
-        wc.deferred += __popcll(wave_ballot(later));
+      }
+      if (emit) {
+        // recoil: the lepton keeps p - k (momentum conservation, Sec. IV.F)
+        if (runs == 1) {
+          p = {p.x - f * p.x, p.y - f * p.y, p.z - f * p.z};
+        } else {
+          rec = {rec.x + f * p.x, rec.y + f * p.y, rec.z + f * p.z};
+          fired = true;
+        }
       }
     }
-    if (emit) {
-      // recoil: the lepton keeps p - k (momentum conservation, Sec. IV.F)
-      p = {p.x - f * p.x, p.y - f * p.y, p.z - f * p.z};
+    if (fired) {
+      const double R = (double)runs;
+      p = {p.x - rec.x / R, p.y - rec.y / R, p.z - rec.z / R};
     }
     if (slot >= 0 && (++k, --left == 0)) {
       LEPTON_COL(x, sp)[slot] = x.x;
@@ -1985,7 +2219,7 @@ __device__ __forceinline__ void gen_lepton_phase(const StepArgs& a, const GenArg
 
 // Photons of the input photon records, each advanced through its tau (lane refill as for
 // the leptons).
-template <bool MIXED, int FMODE>
+template <bool MIXED, int FMODE, bool RUNS>
 __device__ __forceinline__ void gen_photon_phase(const StepArgs& a, const GenArgs& q,
                                                  GenWave& gw, int V, const Series64& ser64,
                                                  const Series32& ser32, BlockStats& bs,
@@ -2003,7 +2237,7 @@ __device__ __forceinline__ void gen_photon_phase(const StepArgs& a, const GenArg
   int inst = 0, nsub = 0, k = 0;
   uint64_t id = 0, seed = 0;
   V3 x{}, kv{}, E{}, B{};
-  double chi = 0.0, h = 0.0, hk = 0.0, pref = 0.0;
+  double chi = 0.0, h = 0.0, hk = 0.0, pref = 0.0, wcur = 0.0;
   while (true) {
     // ---- refill idle lanes ----
     uint64_t freem = wave_ballot(slot < 0);
@@ -2045,6 +2279,7 @@ __device__ __forceinline__ void gen_photon_phase(const StepArgs& a, const GenArg
             h = nsub == 1 ? tau : tau / (double)nsub;
             hk = h * inv_k;
             pref = h * (a.dtfac_per_h * kInvSqrt3Pi) * inv_k;
+            wcur = S.w[sl];
             k = 0;
             slot = sl;
           }
@@ -2055,26 +2290,35 @@ __device__ __forceinline__ void gen_photon_phase(const StepArgs& a, const GenArg
     }
     if (wave_ballot(slot >= 0) == 0) break;
 
-    // ---- one sub-step ----
-    bool pair = false, make = false;
-    double r1 = 0.0, wp = 0.0;
+    // ---- one sub-step: the pair generator once, or N_g times in the reverse mode of
+    // Sec. VI (as in the exact pass) ----
+    const int R = RUNS ? a.runs_pair : 1;
+    int m = 0;
     if (slot >= 0) {
       if (a.push_photons) x = {x.x + hk * kv.x, x.y + hk * kv.y, x.z + hk * kv.z};
       ++cnt.subs;
-      if (a.pairs) {
-        const uint4 o = draw_words(id, seed, step, (uint32_t)k, kDraw);
-        pair = pair_decision<MIXED>(a, ser64, ser32, o, chi, pref, pcnt, &r1);
-      }
-      if (pair) {
-        // the photon decays; its pair is created with probability 1 / f_g (Sec. VI)
-        make = a.fg_pair > 1.0
-                   ? generator_runs(id, seed, step, (uint32_t)k, kGenPair, a.inv_fg_pair)
-                   : true;
-        wp = S.w[slot] * a.fg_pair;
-      }
     }
-    const uint64_t pm = wave_ballot(make);
-    if (pm) {
+    const double wc_run = R > 1 ? wcur / (double)R : wcur;
+    for (int run = 0; run < R; ++run) {
+      const uint32_t sc = sub_code(k, run);
+      bool make = false;
+      double r1 = 0.0, wp = 0.0;
+      if (slot >= 0 && a.pairs) {
+        const uint4 o = draw_words(id, seed, step, sc, kDraw);
+        if (pair_decision<MIXED>(a, ser64, ser32, o, chi, pref, pcnt, &r1)) {
+          ++m;
+          // the photon decays; its pair is created with probability 1 / f_g, or for one
+          // photon in f_g in the deterministic form (Sec. VI)
+          make = R > 1           ? true
+                 : a.every_pair  ? generator_every(id, seed, 0u, a.every_pair)
+                 : a.fg_pair > 1.0 ? generator_runs(id, seed, step, (uint32_t)k, kGenPair,
+                                                    a.inv_fg_pair)
+                                   : true;
+          wp = R > 1 ? wc_run : wcur * a.fg_pair;
+        }
+      }
+      const uint64_t pm = wave_ballot(make);
+      if (!pm) continue;
       const int n_new = __popcll(pm);
       wc.pairs += n_new;
       const bool later = make && k < nsub - 1;
@@ -2092,7 +2336,7 @@ __device__ __forceinline__ void gen_photon_phase(const StepArgs& a, const GenArg
           O.r1[rr] = r1;
           O.w[rr] = wp;
           O.parent[rr] = id;
-          O.sub[rr] = (unsigned)k;
+          O.sub[rr] = sc;
           O.inst[rr] = (unsigned)inst;
           record_same_step<FMODE>(O, rr, (double)(nsub - k - 1) * h, E, B);
         }
@@ -2108,7 +2352,7 @@ __device__ __forceinline__ void gen_photon_phase(const StepArgs& a, const GenArg
           o.py[s2] = r1 * kv.y;
           o.pz[s2] = r1 * kv.z;
           o.w[s2] = wp;
-          o.id[s2] = child_id(id, seed, step, (uint32_t)k, kElectronChild);
+          o.id[s2] = child_id(id, seed, step, sc, kElectronChild);
           o.parent[s2] = id;
           o.birth[s2] = birth_code(step, (uint32_t)k);
           if (o.n_events) o.n_events[s2] = 0u;
@@ -2121,7 +2365,7 @@ __device__ __forceinline__ void gen_photon_phase(const StepArgs& a, const GenArg
           o.py[s2] = r1c * kv.y;
           o.pz[s2] = r1c * kv.z;
           o.w[s2] = wp;
-          o.id[s2] = child_id(id, seed, step, (uint32_t)k, kPositronChild);
+          o.id[s2] = child_id(id, seed, step, sc, kPositronChild);
           o.parent[s2] = id;
           o.birth[s2] = birth_code(step, (uint32_t)k);
           if (o.n_events) o.n_events[s2] = 0u;
@@ -2129,20 +2373,25 @@ __device__ __forceinline__ void gen_photon_phase(const StepArgs& a, const GenArg
         wc.deferred += 2 * __popcll(wave_ballot(later));
       }
     }
-    if (slot >= 0 && (pair || ++k == nsub)) {
-      if (a.push_photons) {
-        S.x[slot] = x.x;
-        S.y[slot] = x.y;
-        S.z[slot] = x.z;
+    if (slot >= 0) {
+      const bool dead = m == R;  // every copy decayed
+      if (!dead && m > 0) wcur = wc_run * (double)(R - m);
+      if (dead || ++k == nsub) {
+        if (a.push_photons) {
+          S.x[slot] = x.x;
+          S.y[slot] = x.y;
+          S.z[slot] = x.z;
+        }
+        if (dead) S.id[slot] = QED_ID_DEAD;
+        else if (wcur != S.w[slot]) S.w[slot] = wcur;
+        slot = -1;
       }
-      if (pair) S.id[slot] = QED_ID_DEAD;
-      slot = -1;
     }
   }
 }
 
-template <bool MIXED, int FMODE>
-__global__ void __launch_bounds__(256) gen_kernel(StepArgs a, GenArgs q) {
+template <bool MIXED, int FMODE, bool RUNS>
+__device__ __forceinline__ void gen_pass(const StepArgs& a, const GenArgs& q) {
   using Tab = typename TabType<MIXED>::T;
   __shared__ BlockStats bs;
   __shared__ Tab tab[kTableN];  // the emission table, as in the lepton kernel
@@ -2166,8 +2415,8 @@ __global__ void __launch_bounds__(256) gen_kernel(StepArgs a, GenArgs q) {
   pcnt.bs = &bs;
   WaveCounters wc;
   // photons of the previous generation, then its electrons and positrons
-  gen_photon_phase<MIXED, FMODE>(a, q, gw, V, ser64, ser32, bs, cnt, pcnt, wc);
-  gen_lepton_phase<MIXED, FMODE>(a, q, gw, V, tab, ser64, ser32, bs, cnt, wc);
+  gen_photon_phase<MIXED, FMODE, RUNS>(a, q, gw, V, ser64, ser32, bs, cnt, pcnt, wc);
+  gen_lepton_phase<MIXED, FMODE, RUNS>(a, q, gw, V, tab, ser64, ser32, bs, cnt, wc);
   if (q.opa.waves > 0) {
     gw.tp.flush(q.opa, gw.wid);
     if (lane == 0) q.opa.nrec[gw.wid] = (unsigned)gw.cp.n;
@@ -2181,6 +2430,17 @@ __global__ void __launch_bounds__(256) gen_kernel(StepArgs a, GenArgs q) {
   block_stats_accumulate(bs, a.gen_part, q.pass == 1);
 }
 
+template <bool MIXED, int FMODE>
+__global__ void __launch_bounds__(256) gen_kernel(StepArgs a, GenArgs q) {
+  gen_pass<MIXED, FMODE, false>(a, q);
+}
+
+// The reverse mode of Sec. VI (runs_photon or runs_pair > 1) in a kernel of its own.
+template <bool MIXED, int FMODE>
+__global__ void __launch_bounds__(256) gen_runs_kernel(StepArgs a, GenArgs q) {
+  gen_pass<MIXED, FMODE, true>(a, q);
+}
+
 #undef LEPTON_COL
 
 // ------------------------------------------------------------------------------------
@@ -2188,7 +2448,10 @@ template <bool MIXED, int FMODE>
 static void launch_persistent(const StepArgs& a, LaunchShape lep, LaunchShape pho,
                               bool run_photons, hipStream_t s) {
   if (a.events[0]) (void)hipEventRecord(a.events[0], s);
-  if (a.generations > 0 || a.fg_photon > 1.0)
+  if (a.runs_photon > 1)
+    hipLaunchKernelGGL((lepton_runs_kernel<MIXED, FMODE>), dim3(lep.grid), dim3(lep.block), 0,
+                       s, a);
+  else if (a.generations > 0 || a.fg_photon > 1.0)
     hipLaunchKernelGGL((lepton_kernel<MIXED, FMODE, true>), dim3(lep.grid), dim3(lep.block), 0,
                        s, a);
   else
@@ -2199,7 +2462,10 @@ static void launch_persistent(const StepArgs& a, LaunchShape lep, LaunchShape ph
     if (a.events[2]) (void)hipEventRecord(a.events[2], s);
     hipLaunchKernelGGL((photon_kernel<MIXED, FMODE>), dim3(pho.grid), dim3(pho.block), 0, s, a);
     if (a.events[3]) (void)hipEventRecord(a.events[3], s);
-    if (a.ex_grid > 0)
+    if (a.ex_grid > 0 && a.runs_pair > 1)
+      hipLaunchKernelGGL((photon_exact_runs_kernel<MIXED, FMODE>), dim3(a.ex_grid), dim3(256), 0,
+                         s, a);
+    else if (a.ex_grid > 0)
       hipLaunchKernelGGL((photon_exact_kernel<MIXED, FMODE>), dim3(a.ex_grid), dim3(256), 0, s, a);
   }
   const int src = a.pa.waves + a.qa.waves;
@@ -2222,7 +2488,10 @@ static void launch_persistent(const StepArgs& a, LaunchShape lep, LaunchShape ph
     q.oqa = a.gqa[g % 2];
     q.pass = g;
     q.last = g == a.generations ? 1 : 0;
-    hipLaunchKernelGGL((gen_kernel<MIXED, FMODE>), dim3(a.gen_grid), dim3(256), 0, s, a, q);
+    if (a.runs_photon > 1 || a.runs_pair > 1)
+      hipLaunchKernelGGL((gen_runs_kernel<MIXED, FMODE>), dim3(a.gen_grid), dim3(256), 0, s, a, q);
+    else
+      hipLaunchKernelGGL((gen_kernel<MIXED, FMODE>), dim3(a.gen_grid), dim3(256), 0, s, a, q);
     const int gsrc = q.opa.waves + q.oqa.waves;
     const bool more = g < a.generations;
     hipLaunchKernelGGL(arena_scan_kernel, dim3(a.n_inst), dim3(1024), 0, s, a, q.opa, q.oqa);
@@ -2259,13 +2528,18 @@ hipError_t launch_step(const StepArgs& a, int precision, LaunchShape lep, Launch
   return hipGetLastError();
 }
 
+// Resident workgroups per CU of a step kernel: kind 0 the photon kernel, 1 the lepton
+// kernel, 2 its extended form, 3 its reverse-mode form.
 template <bool MIXED, int FMODE>
-static int occupancy(bool photon, bool ext, int block) {
+static int occupancy(int kind, int block) {
   int nb = 0;
   hipError_t e;
-  if (photon)
+  if (kind == 0)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, photon_kernel<MIXED, FMODE>, block, 0);
-  else if (ext)
+  else if (kind == 3)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lepton_runs_kernel<MIXED, FMODE>,
+                                                     block, 0);
+  else if (kind == 2)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lepton_kernel<MIXED, FMODE, true>,
                                                      block, 0);
   else
@@ -2275,15 +2549,15 @@ static int occupancy(bool photon, bool ext, int block) {
 }
 
 template <bool MIXED>
-static int occupancy_of(int fmode, bool photon, bool ext, int block) {
-  if (fmode == kFieldEB) return occupancy<MIXED, kFieldEB>(photon, ext, block);
-  if (fmode == kFieldE) return occupancy<MIXED, kFieldE>(photon, ext, block);
-  return occupancy<MIXED, kFieldLocal>(photon, ext, block);
+static int occupancy_of(int fmode, int kind, int block) {
+  if (fmode == kFieldEB) return occupancy<MIXED, kFieldEB>(kind, block);
+  if (fmode == kFieldE) return occupancy<MIXED, kFieldE>(kind, block);
+  return occupancy<MIXED, kFieldLocal>(kind, block);
 }
 
-int step_blocks_per_cu(int precision, int fmode, bool photon, bool ext, int block) {
-  return precision == QED_MIXED ? occupancy_of<true>(fmode, photon, ext, block)
-                                : occupancy_of<false>(fmode, photon, ext, block);
+int step_blocks_per_cu(int precision, int fmode, int kind, int block) {
+  return precision == QED_MIXED ? occupancy_of<true>(fmode, kind, block)
+                                : occupancy_of<false>(fmode, kind, block);
 }
 
 }  // namespace qedk

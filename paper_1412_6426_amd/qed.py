@@ -67,7 +67,8 @@ class qed_params(C.Structure):
                 ("precision", C.c_int), ("freeze_on_drop", C.c_int), ("tile", C.c_int),
                 ("block", C.c_int), ("grid_blocks", C.c_int), ("events", C.c_void_p * 4),
                 ("f_photon", C.c_double), ("f_pair", C.c_double),
-                ("same_step_generations", C.c_int)]
+                ("same_step_generations", C.c_int), ("f_every", C.c_int),
+                ("runs_photon", C.c_int), ("runs_pair", C.c_int)]
 
 
 class qed_stats(C.Structure):
