@@ -1,9 +1,9 @@
 """The oracle built with AddressSanitizer and UndefinedBehaviorSanitizer, every report fatal,
 passes its pins: no out-of-bounds access, use after free, signed overflow, misaligned or
 null dereference on the paths the pins exercise (the step with and without same-step
-children, thinning, Schwinger pairs, the generators, the kinematics).  The sanitized copy is
-built from the oracle's own source into a temporary directory and loaded in a child
-process; the oracle itself is untouched.  CPU only."""
+children, thinning, Schwinger pairs, the generators and their factors, the kinematics).
+The sanitized copy is built from the oracle's own source into a temporary directory and
+loaded in a child process; the oracle itself is untouched.  CPU only."""
 import os
 import subprocess
 import sys
@@ -14,7 +14,7 @@ PINS = ["tests/test_oracle_step.py", "tests/test_oracle_stats.py",
         "tests/test_oracle_same_step.py", "tests/test_oracle_thinning.py",
         "tests/test_oracle_thin_cells.py",
         "tests/test_oracle_schwinger.py", "tests/test_oracle_kinematics.py",
-        "tests/test_oracle_generator_factor.py"]
+        "tests/test_oracle_generator_factor.py", "tests/test_oracle_generator_forms.py"]
 
 
 def _runtime(name):
