@@ -76,6 +76,12 @@ class OrParams(C.Structure):
                 ("runs_photon", C.c_int), ("runs_pair", C.c_int)]
 
 
+class OrThinChildrenRecord(C.Structure):
+    _fields_ = [("children", C.c_int64), ("groups", C.c_int64), ("groups_thinned", C.c_int64),
+                ("kept", C.c_int64), ("weight_before", C.c_double),
+                ("weight_after", C.c_double)]
+
+
 class OrSchwingerRecord(C.Structure):
     _fields_ = [("cells", C.c_int64), ("pairs", C.c_int64), ("dropped", C.c_int64),
                 ("saturated", C.c_int64), ("expected", C.c_double)]
@@ -151,6 +157,9 @@ def lib():
                                     C.c_double * 3, C.c_int64, C.c_uint64, C.c_int64,
                                     C.POINTER(OrThinCellsRecord)]
         L.or_thin_cells.restype = C.c_int
+        L.or_thin_children.argtypes = [C.POINTER(OrStore), C.c_int, C.c_int64, C.c_uint64,
+                                       C.c_int64, C.POINTER(OrThinChildrenRecord)]
+        L.or_thin_children.restype = C.c_int
         L.or_schwinger.argtypes = [C.POINTER(OrStore), C.POINTER(OrField), C.c_double,
                                    C.c_double, C.c_double, C.c_uint64, C.c_int64,
                                    C.POINTER(OrSchwingerRecord)]
@@ -481,6 +490,20 @@ def thin(store: "Store", trigger: int, target: int, seed: int, step: int) -> Dic
         raise RuntimeError("oracle thinning failed")
     store.count = int(cs.count)
     return {k: getattr(rec, k) for k, _ in OrThinRecord._fields_} | {"thinned": rc == 1}
+
+
+def thin_children(store: "Store", is_photon: bool, max_per_parent: int, seed: int,
+                  step: int) -> Dict:
+    """The cap on the children one parent made in the last step (Sec. VII), in place;
+    `step` is the step counter after that step."""
+    cs = store._cstruct()
+    rec = OrThinChildrenRecord()
+    rc = lib().or_thin_children(C.byref(cs), 1 if is_photon else 0, int(max_per_parent),
+                                int(seed), int(step), C.byref(rec))
+    if rc < 0:
+        raise RuntimeError("oracle thinning per parent failed")
+    store.count = int(cs.count)
+    return {k: getattr(rec, k) for k, _ in OrThinChildrenRecord._fields_} | {"thinned": rc == 1}
 
 
 def thin_cells(store: "Store", is_photon: bool, n, dx, origin, max_per_cell: int, seed: int,

@@ -1115,6 +1115,104 @@ int or_thin_cells(or_store *s, int is_photon, const int n[3], const double dx[3]
 }
 
 /* ------------------------------------------------------------------------------------
+ * The cap on the children of one parent in one iteration (Sec. VII).
+ * ------------------------------------------------------------------------------------ */
+typedef struct {
+  uint64_t parent;
+  int64_t slot;
+} or_by_parent;
+
+static int or_by_parent_cmp(const void *a, const void *b) {
+  const or_by_parent *u = (const or_by_parent *)a, *v = (const or_by_parent *)b;
+  if (u->parent != v->parent) return u->parent < v->parent ? -1 : 1;
+  return u->slot < v->slot ? -1 : (u->slot > v->slot ? 1 : 0);
+}
+
+int or_thin_children(or_store *s, int is_photon, int64_t max_per_parent, uint64_t seed,
+                     int64_t step, or_thin_children_record *rec) {
+  memset(rec, 0, sizeof(*rec));
+  const size_t nn = (size_t)(s->count > 0 ? s->count : 1);
+  or_by_parent *kids = (or_by_parent *)malloc(sizeof(or_by_parent) * nn);
+  unsigned char *keep = (unsigned char *)malloc(nn);
+  double *u = (double *)malloc(sizeof(double) * nn);
+  if (!kids || !keep || !u) {
+    free(kids), free(keep), free(u);
+    return -1;
+  }
+  int64_t nk = 0;
+  for (int64_t i = 0; i < s->count; ++i) {
+    keep[i] = 1;
+    if (is_photon && s->id[i] == OR_ID_DEAD) continue;
+    if ((int64_t)(s->birth[i] >> 14) != step) continue;
+    kids[nk].parent = s->parent[i];
+    kids[nk].slot = i;
+    ++nk;
+    rec->weight_before += s->w[i];
+  }
+  rec->children = nk;
+  qsort(kids, (size_t)nk, sizeof(or_by_parent), or_by_parent_cmp);
+  for (int64_t a = 0; a < nk;) {
+    int64_t e = a;
+    while (e < nk && kids[e].parent == kids[a].parent) ++e;
+    const int64_t n = e - a;
+    rec->groups += 1;
+    if (n > max_per_parent) {
+      rec->groups_thinned += 1;
+      const double q = (double)max_per_parent / (double)n;
+      int64_t K = 0;
+      double umin = 2.0;
+      for (int64_t j = a; j < e; ++j) {
+        const int64_t i = kids[j].slot;
+        const uint64_t id = s->id[i];
+        uint32_t ctr[4] = {(uint32_t)step, 13u << 16, (uint32_t)seed, (uint32_t)(seed >> 32)};
+        uint32_t key[2] = {(uint32_t)id, (uint32_t)(id >> 32)};
+        uint32_t o[4];
+        or_philox4x32_10(ctr, key, o);
+        u[i] = or_uniform(o[0], o[1]);
+        keep[i] = u[i] < q;
+        K += keep[i];
+        if (u[i] < umin) umin = u[i];
+      }
+      if (K == 0) /* the group keeps its weight in its smallest draw */
+        for (int64_t j = a; j < e; ++j) {
+          const int64_t i = kids[j].slot;
+          if (u[i] == umin) {
+            keep[i] = 1;
+            ++K;
+          }
+        }
+      const double f = (double)n / (double)K;
+      for (int64_t j = a; j < e; ++j)
+        if (keep[kids[j].slot]) s->w[kids[j].slot] *= f;
+    }
+    a = e;
+  }
+  /* the survivors and every other particle in store order */
+  int64_t k = 0;
+  for (int64_t i = 0; i < s->count; ++i) {
+    if (!keep[i]) continue;
+    if (is_photon && s->id[i] == OR_ID_DEAD) {
+      /* removed photons stay where they are among the others */
+    } else if ((int64_t)(s->birth[i] >> 14) == step) {
+      rec->kept += 1;
+      rec->weight_after += s->w[i];
+    }
+    if (k != i) {
+      s->x[k] = s->x[i], s->y[k] = s->y[i], s->z[k] = s->z[i];
+      s->px[k] = s->px[i], s->py[k] = s->py[i], s->pz[k] = s->pz[i];
+      s->w[k] = s->w[i];
+      s->id[k] = s->id[i], s->parent[k] = s->parent[i];
+      s->birth[k] = s->birth[i];
+      if (s->n_events) s->n_events[k] = s->n_events[i];
+    }
+    ++k;
+  }
+  s->count = k;
+  free(kids), free(keep), free(u);
+  return rec->groups_thinned > 0 ? 1 : 0;
+}
+
+/* ------------------------------------------------------------------------------------
  * Non-perturbative pair production (Sec. V.B): per grid cell and step, a pair with
  * probability R_S V c dt from the cell's field.
  * ------------------------------------------------------------------------------------ */

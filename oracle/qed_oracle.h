@@ -207,6 +207,28 @@ int or_thin_cells(or_store *s, int is_photon, const int n[3], const double dx[3]
                   const double origin[3], int64_t max_per_cell, uint64_t seed, int64_t step,
                   or_thin_cells_record *rec);
 
+/* The cap on the children one particle generates in one iteration (Sec. VII).  The
+ * children born in the last step are the live particles whose birth code (step + 1) << 14 |
+ * sub-step names it: birth >> 14 == step, `step` being the step counter after that step.
+ * They are grouped by their parent id.  A group of at most `max_per_parent` children is
+ * kept as it is.  In a larger group of n children each survives with probability
+ * q = max_per_parent / n, decided by the Philox draw keyed by its id with counter
+ * (step, 13 << 16, seed lo, seed hi) (first two words as the uniform u; kept iff u < q); if
+ * none survives, those with the smallest u do; the survivors' weights are multiplied by
+ * n / K, the group's count over its survivors'.  The children of one parent in one step
+ * share its weight (times the generator's factor), so that is the group's weight over its
+ * survivors' and each group keeps its weight; only the pairs of one photon in the reverse
+ * mode of Sec. VI differ in weight, and keep it in expectation.  Every other particle, and
+ * the survivors, keep their store order; the count becomes the number left.  rec: the
+ * children, their parents (groups), the groups thinned, the children kept, and the
+ * children's weight before and after (sums in store order). */
+typedef struct {
+  int64_t children, groups, groups_thinned, kept;
+  double weight_before, weight_after;
+} or_thin_children_record;
+int or_thin_children(or_store *s, int is_photon, int64_t max_per_parent, uint64_t seed,
+                     int64_t step, or_thin_children_record *rec);
+
 /* Non-perturbative (Schwinger) pairs of Sec. V.B on a periodic Yee grid (f->kind ==
  * OR_FIELD_YEE), one global step n = step of length dt.  The field of cell (i, j, k), the
  * box [i, i+1) x [j, j+1) x [k, k+1) in units of dx from the origin, is taken as constant:

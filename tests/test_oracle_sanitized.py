@@ -12,7 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 ORACLE = os.path.join(ROOT, "oracle")
 PINS = ["tests/test_oracle_step.py", "tests/test_oracle_stats.py",
         "tests/test_oracle_same_step.py", "tests/test_oracle_thinning.py",
-        "tests/test_oracle_thin_cells.py",
+        "tests/test_oracle_thin_cells.py", "tests/test_oracle_thin_children.py",
         "tests/test_oracle_schwinger.py", "tests/test_oracle_kinematics.py",
         "tests/test_oracle_generator_factor.py", "tests/test_oracle_generator_forms.py"]
 
