@@ -1144,6 +1144,7 @@ int or_thin_children(or_store *s, int is_photon, int64_t max_per_parent, uint64_
     keep[i] = 1;
     if (is_photon && s->id[i] == OR_ID_DEAD) continue;
     if ((int64_t)(s->birth[i] >> 14) != step) continue;
+    if (s->parent[i] == OR_NO_PARENT) continue; /* Schwinger pairs: no particle made them */
     kids[nk].parent = s->parent[i];
     kids[nk].slot = i;
     ++nk;
@@ -1193,7 +1194,7 @@ int or_thin_children(or_store *s, int is_photon, int64_t max_per_parent, uint64_
     if (!keep[i]) continue;
     if (is_photon && s->id[i] == OR_ID_DEAD) {
       /* removed photons stay where they are among the others */
-    } else if ((int64_t)(s->birth[i] >> 14) == step) {
+    } else if ((int64_t)(s->birth[i] >> 14) == step && s->parent[i] != OR_NO_PARENT) {
       rec->kept += 1;
       rec->weight_after += s->w[i];
     }

@@ -209,8 +209,9 @@ int or_thin_cells(or_store *s, int is_photon, const int n[3], const double dx[3]
 
 /* The cap on the children one particle generates in one iteration (Sec. VII).  The
  * children born in the last step are the live particles whose birth code (step + 1) << 14 |
- * sub-step names it: birth >> 14 == step, `step` being the step counter after that step.
- * They are grouped by their parent id.  A group of at most `max_per_parent` children is
+ * sub-step names it: birth >> 14 == step, `step` being the step counter after that step,
+ * and that have a parent (Schwinger pairs, whose parent is OR_NO_PARENT, are no particle's
+ * children).  They are grouped by their parent id.  A group of at most `max_per_parent` children is
  * kept as it is.  In a larger group of n children each survives with probability
  * q = max_per_parent / n, decided by the Philox draw keyed by its id with counter
  * (step, 13 << 16, seed lo, seed hi) (first two words as the uniform u; kept iff u < q); if

@@ -173,6 +173,22 @@ def test_removed_photons_stay_and_other_steps_are_not_children(orc):
     assert rec2["children"] == 0 and st2.count == len(cols["id"])
 
 
+def test_pairs_without_a_parent_are_no_group(orc):
+    """Schwinger pairs of the last step carry no parent: however many, they stay."""
+    rng = np.random.default_rng(10)
+    st, cols = _store(orc, rng, [60, 5], old=100)
+    orphans = np.flatnonzero((cols["parent"] == 1000) & ((cols["birth"] >> 14) == STEP))
+    assert len(orphans) == 60  # the children of the first parent lose it
+    cols["parent"][orphans] = np.uint64(0xFFFFFFFFFFFFFFFF)
+    st = orc.Store(len(cols["id"]))
+    st.load(cols)
+    rec = _thin(orc, st, 4)
+    assert rec["children"] == 5 and rec["groups"] == 1 and rec["groups_thinned"] == 1
+    v = st.view()
+    none = np.uint64(0xFFFFFFFFFFFFFFFF)
+    assert np.array_equal(v["id"][v["parent"] == none], cols["id"][cols["parent"] == none])
+
+
 def test_unequal_weights_are_kept_in_expectation(orc):
     """Children of one parent with different weights (the pairs of one photon in the reverse
     mode): the survivors take n / K of their own weight, so the group keeps its weight on
