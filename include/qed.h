@@ -415,6 +415,44 @@ qed_status qed_thin_cells(const qed_stores *stores, int species, const qed_field
                           qed_thin_cells_record *d_records, void *d_work, size_t work_bytes,
                           void *stream);
 
+/* Result of qed_thin_children for one instance (device memory, one record per instance;
+ * all zero for a frozen instance). */
+typedef struct {
+  int64_t children;        /* children of the last step (live, with a parent) before */
+  int64_t groups;          /* their parents */
+  int64_t groups_thinned;  /* parents with more than max_per_parent of them */
+  int64_t kept;            /* children of the last step after */
+  double weight_before;    /* their weight before */
+  double weight_after;     /* after (equal up to rounding where a parent's children share
+                              one weight, which they do but for the pairs of one photon in
+                              the reverse mode) */
+} qed_thin_children_record;
+
+/* Workspace size of qed_thin_children: 141 bytes per slot of the species store (a hash
+ * table of 2 entries per slot, an entry index, a keep flag and a copy of the columns), 72
+ * bytes per instance and range (ranges of about 8192 slots of the mean segment, at most
+ * 2048 per instance) and 64 per instance.  0 for invalid arguments. */
+size_t qed_thin_children_work_bytes(int n_instances, int64_t species_slots);
+
+/* The cap on the children one particle generates in one iteration (Sec. VII), for one
+ * species of every instance that is not frozen, after the step whose counter *d_step now
+ * holds (the counter after it).  The children of that step are the live particles with
+ * birth >> 14 == *d_step (birth codes (step + 1) << 14 | sub-step) and a parent other than
+ * QED_NO_PARENT (Schwinger pairs have none), grouped by parent id.  A group of at most
+ * max_per_parent children is kept as it is.  In a group of n > max_per_parent children
+ * each survives with probability q = max_per_parent / n, decided by the Philox draw keyed by
+ * its id with counter (*d_step, 13 << 16, instance seed lo, hi), survival iff the first two
+ * words as a uniform in (0, 1) are below q; if none survives, those with the smallest draw
+ * do; the survivors' weights are multiplied by n / K for K survivors.  Every other particle
+ * (removed photons included) and the survivors keep their store order; the count becomes
+ * the number left.  d_records[n_instances] receives one record per instance.
+ * Graph-capturable; no host synchronisation.  QED_ERR_ARG for max_per_parent < 1, bad
+ * sizes or pointers; QED_ERR_UNSUPPORTED for 2^31 or more slots or more than 65535
+ * instances. */
+qed_status qed_thin_children(const qed_stores *stores, int species, int64_t max_per_parent,
+                             const int64_t *d_step, qed_thin_children_record *d_records,
+                             void *d_work, size_t work_bytes, void *stream);
+
 /* Counters of one qed_schwinger call (device memory; overwritten by each call). */
 typedef struct {
   int64_t cells;      /* (cell, instance) pairs visited */

@@ -405,6 +405,32 @@ qed_status qed_thin_cells(const qed_stores* stores, int species, const qed_field
   return e == hipSuccess ? QED_OK : QED_ERR_HIP;
 }
 
+size_t qed_thin_children_work_bytes(int n_instances, int64_t species_slots) {
+  if (n_instances < 1 || species_slots < 0) return 0;
+  return ThinChildrenLayout::make(n_instances, species_slots).total;
+}
+
+qed_status qed_thin_children(const qed_stores* stores, int species, int64_t max_per_parent,
+                             const int64_t* d_step, qed_thin_children_record* d_records,
+                             void* d_work, size_t work_bytes, void* stream) {
+  if (!stores || !d_work || !stores->d_instances || !d_step || !d_records) return QED_ERR_ARG;
+  if (species < 0 || species >= QED_NSPECIES || stores->n_instances < 1) return QED_ERR_ARG;
+  if (max_per_parent < 1) return QED_ERR_ARG;
+  const long long slots = stores->slots[species];
+  if (slots < 0) return QED_ERR_ARG;
+  // hash-table entries are 32-bit indices of tables of twice the capacity; instances are
+  // the y dimension of the grids
+  if (slots >= (1ll << 31) || stores->n_instances > 65535) return QED_ERR_UNSUPPORTED;
+  if (!soa_ok(stores->species[species], false)) return QED_ERR_ARG;
+  if (reinterpret_cast<uintptr_t>(d_work) & 255u) return QED_ERR_ARG;
+  if (work_bytes < qed_thin_children_work_bytes(stores->n_instances, slots)) return QED_ERR_ARG;
+  const hipError_t e = launch_thin_children(
+      stores->species[species], species, stores->d_instances, stores->n_instances, slots,
+      (long long)max_per_parent, reinterpret_cast<const long long*>(d_step), d_records, d_work,
+      static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? QED_OK : QED_ERR_HIP;
+}
+
 qed_status qed_sort_cells(const qed_stores* stores, int species, const qed_field* field,
                           void* d_work, size_t work_bytes, void* stream) {
   const qed_status c = check_cell_args(stores, species, field, d_work);

@@ -78,8 +78,9 @@ enum Purpose : uint32_t {
   kDraw = 0, kPhotonChild = 1, kElectronChild = 2, kPositronChild = 3, kThin = 4,
   kGenPhoton = 5, kGenPair = 6,  // generator-factor draws (Sec. VI)
   kSchwinger = 7, kSchwingerPos = 8, kSchwingerElectron = 9, kSchwingerPositron = 10,
-  kThinCell = 11,  // thinning per cell block
-  kPhase = 12      // phase of the deterministic generator factor (Sec. VI)
+  kThinCell = 11,   // thinning per cell block
+  kPhase = 12,      // phase of the deterministic generator factor (Sec. VI)
+  kThinParent = 13  // the cap on the children of one parent in one step (Sec. VII)
 };
 
 __device__ __forceinline__ uint32_t sub_code(int k, int run) {

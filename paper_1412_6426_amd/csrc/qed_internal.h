@@ -383,6 +383,17 @@ hipError_t launch_sort_cells(const qed_soa& s, int species, qed_instance* inst, 
 // 2^24 - 2 blocks, and the fewest 8-bit passes whose keys hold every block and the two
 // reserved keys.
 SortGeometry sort_geometry(const int n[3]);
+// The cap on the children of one parent in one step (qed_thin_children): per-instance hash
+// tables of 2 x capacity entries, range partials and a column copy.
+struct ThinChildrenLayout {
+  int nb;
+  size_t hdr, part, off, tkey, tn, tk, tk2, tmin, ent, keep, cd, cu, cb, total;
+  static ThinChildrenLayout make(int n_inst, long long slots);
+};
+hipError_t launch_thin_children(const qed_soa& s, int species, qed_instance* inst, int n_inst,
+                                long long slots, long long max_per_parent,
+                                const long long* d_step, qed_thin_children_record* rec,
+                                void* work, hipStream_t st);
 hipError_t launch_thin_cells(const qed_soa& s, int species, qed_instance* inst, int n_inst,
                              long long slots, const int n[3], const double dx[3],
                              const double origin[3], long long max_per_cell,

@@ -215,6 +215,28 @@ class Engine:
         return [Q.qed_thin_cells_record.from_buffer_copy(raw[i * n:(i + 1) * n]).as_dict()
                 for i in range(self.n_inst)]
 
+    def thin_children(self, species: int, max_per_parent: int, stream: Optional[int] = None):
+        """qed_thin_children on one species of every instance, after the step the step
+        counter has just passed (workspace allocated on first use, for the largest store);
+        records stay on the device until thin_children_records() reads them."""
+        torch = _torch()
+        need = max(Q.qed_thin_children_work_bytes(self.n_inst, int(self.cols[s]["x"].numel()))
+                   for s in range(3))
+        if getattr(self, "_tp_work", None) is None or self._tp_work.numel() < need:
+            torch.cuda.synchronize()  # no call may still use a buffer being replaced
+            self._tp_work = torch.zeros(need, dtype=torch.uint8, device=self.device)
+            self._tp_rec = torch.zeros(self.n_inst * C.sizeof(Q.qed_thin_children_record),
+                                       dtype=torch.uint8, device=self.device)
+        Q.qed_thin_children(self.stores, species, int(max_per_parent), self.step_ctr.data_ptr(),
+                            self._tp_rec.data_ptr(), self._tp_work.data_ptr(),
+                            self._tp_work.numel(), self.stream if stream is None else stream)
+
+    def thin_children_records(self) -> List[Dict]:
+        raw = self._tp_rec.cpu().numpy().tobytes()
+        n = C.sizeof(Q.qed_thin_children_record)
+        return [Q.qed_thin_children_record.from_buffer_copy(raw[i * n:(i + 1) * n]).as_dict()
+                for i in range(self.n_inst)]
+
     # ------------------------------------------------------------------ cell sort
     def sort_cells(self, species: int, field: Q.qed_field, stream: Optional[int] = None):
         """qed_sort_cells on one species of every instance (workspace allocated on first

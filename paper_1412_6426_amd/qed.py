@@ -111,6 +111,14 @@ class qed_thin_cells_record(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class qed_thin_children_record(C.Structure):
+    _fields_ = [("children", C.c_int64), ("groups", C.c_int64), ("groups_thinned", C.c_int64),
+                ("kept", C.c_int64), ("weight_before", C.c_double), ("weight_after", C.c_double)]
+
+    def as_dict(self) -> Dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class qed_schwinger_record(C.Structure):
     _fields_ = [("cells", C.c_int64), ("pairs", C.c_int64), ("dropped", C.c_int64),
                 ("saturated", C.c_int64), ("expected", C.c_double), ("reserved", C.c_int64)]
@@ -124,6 +132,7 @@ EXPORTS = ("qed_table_bytes", "qed_build_tables", "qed_work_bytes", "qed_step",
            "qed_step_noalloc",
            "qed_thin_work_bytes", "qed_thin", "qed_sort_work_bytes", "qed_sort_cells",
            "qed_thin_cells_work_bytes", "qed_thin_cells",
+           "qed_thin_children_work_bytes", "qed_thin_children",
            "qed_schwinger", "qed_generator_work_bytes",
            "qed_generator_trials", "qed_standard_w_table",
            "qed_append_stats", "qed_photon_spectrum", "qed_fill_standing_wave",
@@ -176,6 +185,11 @@ def lib():
         L.qed_thin_cells.argtypes = [C.POINTER(qed_stores), C.c_int, C.POINTER(qed_field),
                                      C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.c_size_t, C.c_void_p]
+        L.qed_thin_children_work_bytes.restype = C.c_size_t
+        L.qed_thin_children_work_bytes.argtypes = [C.c_int, C.c_int64]
+        L.qed_thin_children.restype = C.c_int
+        L.qed_thin_children.argtypes = [C.POINTER(qed_stores), C.c_int, C.c_int64, C.c_void_p,
+                                        C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
         L.qed_schwinger.restype = C.c_int
         L.qed_schwinger.argtypes = [C.POINTER(qed_stores), C.POINTER(qed_field), C.c_double,
                                     C.c_double, C.c_double, C.c_void_p, C.c_void_p,
@@ -267,6 +281,17 @@ def qed_thin_cells(stores: qed_stores, species: int, field: qed_field, max_per_c
     _check(lib().qed_thin_cells(C.byref(stores), species, C.byref(field), int(max_per_cell),
                                 d_step, d_records, d_work, work_bytes, stream),
            "qed_thin_cells")
+
+
+def qed_thin_children_work_bytes(n_instances: int, species_slots: int) -> int:
+    return int(lib().qed_thin_children_work_bytes(n_instances, species_slots))
+
+
+def qed_thin_children(stores: qed_stores, species: int, max_per_parent: int, d_step: int,
+                      d_records: int, d_work: int, work_bytes: int, stream: int) -> None:
+    _check(lib().qed_thin_children(C.byref(stores), species, int(max_per_parent), d_step,
+                                   d_records, d_work, work_bytes, stream),
+           "qed_thin_children")
 
 
 def qed_schwinger(stores: qed_stores, field: qed_field, dt: float, eps_r: float,

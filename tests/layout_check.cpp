@@ -9,7 +9,8 @@
 // photon wavefronts' candidate lists for every wavefront count a launch can have, and the
 // child arenas' shares, pool chunks, count matrices and chunk chains for every producer
 // (the lepton kernel's grids, the exact pair kernel's, the generation kernel's).  The same
-// for the cell sort's workspace (SortLayout) and its key geometry.
+// for the cell sort's workspace (SortLayout) and its key geometry, and for the workspaces of
+// the thinning per cell and the cap per parent.
 #include <stdio.h>
 #include <stdlib.h>
 
@@ -211,6 +212,33 @@ static void check_thin_cells(int n_inst, long long slots, const char* what) {
   CHECK(2 * (size_t)S.tiles_max <= 256 * (size_t)S.tiles_max, "%s: tile counts", what);
 }
 
+// qed_thin_children: the hash tables (2 entries per slot), entry indices, keep flags, the
+// column copy, and per (instance, range) partials and offsets; a table entry is a 32-bit
+// index below 2 x capacity, so stores of fewer than 2^31 slots.
+static void check_thin_children(int n_inst, long long slots, const char* what) {
+  const ThinChildrenLayout L = ThinChildrenLayout::make(n_inst, slots);
+  CHECK(qed_thin_children_work_bytes(n_inst, slots) == L.total,
+        "%s: qed_thin_children_work_bytes", what);
+  const size_t n = (size_t)(slots > 0 ? slots : 1);
+  const size_t nb = (size_t)n_inst * L.nb;
+  std::vector<Region> r = {{L.hdr, 64 * (size_t)n_inst, "hdr"}, {L.part, 64 * nb, "part"},
+                           {L.off, 8 * nb, "off"},          {L.tkey, 16 * n, "tkey"},
+                           {L.tn, 8 * n, "tn"},             {L.tk, 8 * n, "tk"},
+                           {L.tk2, 8 * n, "tk2"},           {L.tmin, 16 * n, "tmin"},
+                           {L.ent, 4 * n, "ent"},           {L.keep, n, "keep"},
+                           {L.cd, 56 * n, "cd"},            {L.cu, 16 * n, "cu"},
+                           {L.cb, 8 * n, "cb"}};
+  check_regions(r, 0, L.total, what);
+  CHECK(L.nb >= 1 && L.nb <= kThinBlocks, "%s: %d ranges", what, L.nb);
+  if (slots < (1ll << 31))
+    CHECK((unsigned long long)(2 * n - 1) <= 0xFFFFFFFEull, "%s: entry indices overflow", what);
+  // the documented size: 141 bytes per slot, 72 per instance and range, 64 per instance,
+  // plus the alignment of 13 regions
+  const size_t doc = 141 * n + 72 * nb + 64 * (size_t)n_inst;
+  CHECK(L.total >= doc && L.total <= doc + 13 * 256, "%s: %zu bytes against %zu documented",
+        what, L.total, doc);
+}
+
 static void check_sort_geometry(int nx, int ny, int nz) {
   const int n[3] = {nx, ny, nz};
   const SortGeometry g = sort_geometry(n);
@@ -274,6 +302,11 @@ int main() {
   check_thin_cells(64, 200 * M, "thin cells, 64 instances");
   check_thin_cells(5, 0, "thin cells, no slots");
   check_thin_cells(1, (1ll << 32) - 1, "thin cells, largest store");
+  check_thin_children(1, 200 * M, "thin children, 2*10^8 photon slots");
+  check_thin_children(64, 200 * M, "thin children, 64 instances");
+  check_thin_children(5, 0, "thin children, no slots");
+  check_thin_children(3, 2, "thin children, fewer slots than instances");
+  check_thin_children(1, (1ll << 31) - 1, "thin children, largest store");
   const int grids[][3] = {{1, 1, 1}, {7, 5, 4}, {40, 40, 40}, {254, 1, 1}, {255, 1, 1},
                           {256, 256, 256}, {300, 300, 300}, {300, 2, 9}, {65534, 1, 1},
                           {65535, 1, 1}, {1 << 20, 1 << 5, 1 << 5}, {2147483647, 1, 1}};

@@ -44,7 +44,8 @@ def test_ctypes_layout_matches_header(Q, tmp_path):
     """Compile a probe against include/qed.h with gcc and compare every struct's size and
     every field's offset with the ctypes mirror."""
     structs = [Q.qed_soa, Q.qed_instance, Q.qed_stores, Q.qed_field, Q.qed_params, Q.qed_stats,
-               Q.qed_thin_record, Q.qed_thin_cells_record, Q.qed_schwinger_record]
+               Q.qed_thin_record, Q.qed_thin_cells_record, Q.qed_thin_children_record,
+               Q.qed_schwinger_record]
     lines = ['#include "qed.h"', "#include <stdio.h>", "#include <stddef.h>", "int main(void){"]
     expect = []
     for S in structs:
