@@ -40,8 +40,9 @@ struct ChildHdr {
   long long tab;        // first entry of the instance's table
   long long size;       // its entries (2 x capacity; 0 when frozen)
   unsigned long long groups, thinned;
+  long long before;     // slots before (the count, at most the capacity)
   long long count;      // slots after
-  long long pad[3];
+  long long pad[2];
 };
 static_assert(sizeof(ChildHdr) == 64, "instance headers are 64 bytes");
 
@@ -118,7 +119,10 @@ __global__ void __launch_bounds__(kTcThreads) tc_prep_kernel(TcArgs a) {
     ChildHdr h{};
     h.tab = t;
     h.size = I.frozen ? 0 : 2 * I.capacity[a.species];
-    h.count = I.count[a.species];
+    // a count beyond the segment (left by an append that dropped) covers only its capacity
+    const long long n = I.count[a.species];
+    h.before = n < 0 ? 0 : (n > I.capacity[a.species] ? I.capacity[a.species] : n);
+    h.count = h.before;
     t += h.size;
     a.hdr[i] = h;
   }
@@ -141,7 +145,7 @@ __global__ void __launch_bounds__(kTcThreads) tc_insert_kernel(TcArgs a) {
   const qed_instance& I = a.inst[i];
   const ChildHdr& h = a.hdr[i];
   long long lo, hi;
-  range_of(h.count, a.nb, blockIdx.x, lo, hi);
+  range_of(h.before, a.nb, blockIdx.x, lo, hi);
   const uint32_t step = (uint32_t)*a.d_step;
   const long long base = I.base[a.species];
   for (long long j = lo + threadIdx.x; j < hi; j += blockDim.x) {
@@ -176,7 +180,7 @@ __global__ void __launch_bounds__(kTcThreads) tc_draw_kernel(TcArgs a, int tie) 
   const qed_instance& I = a.inst[i];
   const ChildHdr& h = a.hdr[i];
   long long lo, hi;
-  range_of(h.count, a.nb, blockIdx.x, lo, hi);
+  range_of(h.before, a.nb, blockIdx.x, lo, hi);
   const uint32_t step = (uint32_t)*a.d_step;
   const long long base = I.base[a.species];
   for (long long j = lo + threadIdx.x; j < hi; j += blockDim.x) {
@@ -233,7 +237,7 @@ __global__ void __launch_bounds__(kTcThreads) tc_keep_kernel(TcArgs a) {
   const qed_instance& I = a.inst[i];
   const ChildHdr& h = a.hdr[i];
   long long lo, hi;
-  range_of(h.count, a.nb, blockIdx.x, lo, hi);
+  range_of(h.before, a.nb, blockIdx.x, lo, hi);
   const uint32_t step = (uint32_t)*a.d_step;
   const long long base = I.base[a.species];
   long long kept = 0, children = 0, kept_children = 0;
@@ -303,7 +307,7 @@ __global__ void __launch_bounds__(kTcThreads) tc_scatter_kernel(TcArgs a) {
   const ChildHdr& h = a.hdr[i];
   long long lo, hi;
   // the range over the count before thinning (the plan kernel has set the count after it)
-  range_of(I.count[a.species], a.nb, blockIdx.x, lo, hi);
+  range_of(h.before, a.nb, blockIdx.x, lo, hi);
   const uint32_t step = (uint32_t)*a.d_step;
   const long long base = I.base[a.species];
   long long run = a.off[(size_t)i * a.nb + blockIdx.x];

@@ -144,3 +144,41 @@ def test_forms_that_do_not_combine_are_refused():
     for c in before:
         assert np.array_equal(before[c], after[c]), c
     assert int(e.step_ctr.item()) == 0
+
+
+@pytest.mark.parametrize("form", list(FORMS))
+def test_mixed_precision_follows_fp64_oracle(orc, form):
+    """Both forms in mixed precision (the FP32 lepton, exact and generation kernels of each)
+    against the FP64 oracle on the rotating-E cascade from 10^3 seeds: both draw the same
+    numbers, so only decisions within FP32 rounding of a threshold differ; the weighted
+    photon spectrum within L1 1e-3 and the pairs within 1% (plus three)."""
+    import math
+    over = FORMS[form]
+    kw = dict(n=1000, periods=PERIODS[form], capacity=4_000_000, lepton_capacity=400_000)
+    w = W.rotating_e(**kw)
+    init = W.rotating_e_initial(1000, seed=21)
+    os_ = oracle_stores(orc, init, w.capacity)
+    ost = orc.run(os_, oracle_field(orc, w), oracle_params(orc, w, **over), w.n_steps)
+    assert sum(s["dropped"] for s in ost) == 0
+
+    def spectrum(cols):
+        live = cols["id"] != DEAD
+        e = np.sqrt(cols["px"][live] ** 2 + cols["py"][live] ** 2 + cols["pz"][live] ** 2)
+        lo, hi, bins = W.SPECTRUM_LO, W.SPECTRUM_HI, W.SPECTRUM_BINS
+        u = (np.log10(e) - math.log10(lo)) * bins / (math.log10(hi) - math.log10(lo))
+        ok = (u >= 0) & (u < bins)
+        return np.bincount(u[ok].astype(np.int64), weights=cols["w"][live][ok], minlength=bins)
+
+    h_or = spectrum(os_[2].view())
+    p_or = sum(s["pairs"] for s in ost)
+    assert p_or > 100
+    wm = W.rotating_e(**kw, precision="mixed")
+    _note(f"mixed, {over}: {wm.description}")
+    e = R.engine_single(wm, init)
+    st = R.run(e, R.field_of(wm), R.params_of(wm, **over), wm.n_steps)
+    h = spectrum(e.read(0, 2))
+    l1 = float(np.abs(h - h_or).sum() / h_or.sum())
+    pairs = sum(s["pairs"] for s in st)
+    _note(f"mixed {form}: L1 {l1:.3e}, pairs {pairs} vs {p_or}")
+    assert l1 <= 1e-3
+    assert abs(pairs - p_or) <= 0.01 * p_or + 3
