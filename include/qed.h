@@ -218,6 +218,12 @@ typedef struct {
                            and it is removed when all N_g fire.  A value <= 1 means off; at
                            most 64; not with a factor f_g > 1 on the same generator
                            (QED_ERR_ARG). */
+  int refill_min;       /* work queue of the lepton kernel: a wavefront takes new particles
+                           into its idle lanes once at least refill_min of its 64 lanes are
+                           idle (or all of them); 1 refills every idle lane at once.  0: 40 on
+                           a Yee grid or a rotating field when no generator factor, reverse
+                           mode or same-step processing is on, else 1.  0..64; results do not
+                           depend on it (only the order of the children in the stores). */
 } qed_params;
 
 /* Per-step record written by qed_step (device memory). */

@@ -200,6 +200,7 @@ qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_fi
   if ((P.f_photon > 1.0 && P.runs_photon > 1) || (P.f_pair > 1.0 && P.runs_pair > 1) ||
       P.runs_photon > kMaxRuns || P.runs_pair > kMaxRuns)
     return QED_ERR_ARG;
+  if (P.refill_min < 0 || P.refill_min > 64) return QED_ERR_ARG;
   if (P.f_every && ((P.f_photon > 1.0 && (P.f_photon != floor(P.f_photon) ||
                                           P.f_photon > 2147483647.0)) ||
                     (P.f_pair > 1.0 && (P.f_pair != floor(P.f_pair) ||
@@ -318,6 +319,11 @@ qed_status qed_step(const void* d_tables, const qed_stores* stores, const qed_fi
   // factor or its reverse mode (the launch makes the same choice)
   const bool lep_ext = G > 0 || P.f_photon > 1.0 || P.runs_photon > 1;
   const int lep_kernel = P.runs_photon > 1 ? 3 : lep_ext ? 2 : 1;
+  if (P.refill_min > 0)
+    a.refill_min = P.refill_min;
+  else
+    a.refill_min = !lep_ext && (field->kind == QED_FIELD_YEE ||
+                                field->kind == QED_FIELD_ROTATING_E) ? kRefillMin : 1;
   if (!device_geometry(&cus, P.precision, fmode, lep_kernel, block, &lep_per_cu) ||
       !device_geometry(&cus, P.precision, fmode, 0, block, &pho_per_cu))
     return QED_ERR_HIP;

@@ -112,6 +112,18 @@ inline ArenaGeometry arena_geometry(long long cap, int waves, bool pool) {
 constexpr int kMaxGenerations = 64;
 constexpr int kMaxRuns = 64;  // runs of the reverse mode of Sec. VI (the run sits in one byte)
 
+// The lepton kernel's default refill threshold (qed_params.refill_min = 0).  Each refill is a
+// round of dependent loads (the columns, and on a grid the 24 CIC gathers) that the
+// wavefront waits for; taking them in batches of at least kRefillMin idle lanes costs some
+// idle lanes in the sub-steps in between and saves most of those rounds where particles take
+// few sub-steps a step.  On the 256^3 grid cascade the lepton kernel took 197 ms with a
+// refill for every idle lane and 155-160 ms with thresholds of 24 to 56 (157 ms at 40); on
+// the rotating-field cascade 274.8 ms per job against 270.4 at 40.  Where particles take
+// hundreds of sub-steps a step (the large-step shower and avalanche, same-step children)
+// idle lanes wait long and the threshold costs 4-22%, so the default is 1 there: the plain
+// kernel on a Yee grid or a rotating field gets kRefillMin, every other case 1.
+constexpr int kRefillMin = 40;
+
 struct WorkLayout {
   size_t n0;        // long long [n_inst * 3]: live slots at step start (0 when frozen)
   size_t lep_pref;  // long long [2 n_inst + 1]: particle prefix over (instance, e-/e+)
@@ -322,6 +334,7 @@ struct StepArgs {
   // else 0; runs_* = N_g of the reverse mode (1: off)
   unsigned every_photon, every_pair;
   int runs_photon, runs_pair;
+  int refill_min;  // a lepton wavefront refills idle lanes once this many are idle (or all)
   int adaptive, forced, emission, pairs, push_photons, freeze_on_drop;
   int generations;  // children advanced in their birth step: generations (0: none)
   long long tile;  // particles per work chunk (0: one chunk per wavefront)

@@ -859,8 +859,9 @@ __device__ __forceinline__ void lepton_step(const StepArgs& a) {
   const bool refine = a.forced <= 0 && a.adaptive;
 
   while (true) {
-    // ---- refill idle lanes from the wavefront's share ----
+    // ---- refill idle lanes from the wavefront's share, once enough of them are idle ----
     uint64_t freem = wave_ballot(slot < 0);
+    if (__popcll(freem) < a.refill_min && ~freem != 0ull) freem = 0ull;
     while (freem != 0 && open) {
       if (tc.cur >= tc.end) {
         open = wr.next(a, a.lep_pref, nseg, true, tc);

@@ -296,11 +296,12 @@ class Engine:
                     pairs=1, push_photons=1, precision=Q.QED_FP64, freeze_on_drop=0, tile=0,
                     block=0, grid_blocks=0, f_photon=1.0, f_pair=1.0,
                     same_step_generations=0, f_every=0, runs_photon=1,
-                    runs_pair=1) -> Q.qed_params:
+                    runs_pair=1, refill_min=0) -> Q.qed_params:
         p = Q.qed_params()
         p.f_photon, p.f_pair = float(f_photon), float(f_pair)
         p.same_step_generations = int(same_step_generations)
         p.f_every, p.runs_photon, p.runs_pair = int(f_every), int(runs_photon), int(runs_pair)
+        p.refill_min = int(refill_min)
         p.dt, p.eps_r, p.kappa, p.t0 = float(dt), float(eps_r), float(kappa), float(t0)
         p.adaptive, p.forced_substeps = int(adaptive), int(forced_substeps)
         p.emission, p.pairs, p.push_photons = int(emission), int(pairs), int(push_photons)

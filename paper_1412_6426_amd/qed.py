@@ -68,7 +68,7 @@ class qed_params(C.Structure):
                 ("block", C.c_int), ("grid_blocks", C.c_int), ("events", C.c_void_p * 4),
                 ("f_photon", C.c_double), ("f_pair", C.c_double),
                 ("same_step_generations", C.c_int), ("f_every", C.c_int),
-                ("runs_photon", C.c_int), ("runs_pair", C.c_int)]
+                ("runs_photon", C.c_int), ("runs_pair", C.c_int), ("refill_min", C.c_int)]
 
 
 class qed_stats(C.Structure):

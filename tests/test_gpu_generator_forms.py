@@ -128,14 +128,16 @@ def test_yee_grid(orc, form):
 
 def test_forms_that_do_not_combine_are_refused():
     """A factor and the reverse mode on one generator, a deterministic factor that is no
-    integer, more than 64 runs: QED_ERR_ARG before any launch, the stores untouched."""
+    integer, more than 64 runs, a refill threshold outside 0..64: QED_ERR_ARG before any
+    launch, the stores untouched."""
     from paper_1412_6426_amd import qed as Q
     w = W.rotating_e(n=50, periods=0.05, capacity=10_000, lepton_capacity=1000)
     e = R.engine_single(w, W.rotating_e_initial(50, seed=1))
     before = e.read(0, 0)
     for over in (dict(f_photon=2.0, runs_photon=2), dict(f_pair=3.0, runs_pair=3),
                  dict(f_every=1, f_photon=2.5), dict(f_every=1, f_pair=1.5),
-                 dict(runs_photon=65), dict(runs_pair=65)):
+                 dict(runs_photon=65), dict(runs_pair=65), dict(refill_min=65),
+                 dict(refill_min=-1)):
         _note(f"refused: {over}")
         with pytest.raises(Q.QedError, match="argument"):
             e.step(R.field_of(w), R.params_of(w, **over))

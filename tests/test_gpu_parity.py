@@ -674,3 +674,41 @@ def test_batched_mixed_graph_replay_equals_eager(orc):
             a, b = e.read(i, sp), ref.read(i, sp)
             for c, v in a.items():
                 assert np.array_equal(v, b[c], equal_nan=True), (i, sp, c)
+
+
+@pytest.mark.parametrize("refill", [1, 17, 64])
+def test_refill_threshold_leaves_results_unchanged(orc, refill):
+    """The lepton kernel's work-queue threshold (qed_params.refill_min) changes when idle
+    lanes take new particles, not what happens to any particle: the rotating cascade and the
+    32^3 Yee-grid cascade equal the oracle at thresholds 1, 17 and 64."""
+    w = W.rotating_e(n=300, periods=1.0, capacity=400_000, lepton_capacity=40_000)
+    init = W.rotating_e_initial(300, seed=3)
+    _note(f"rotating cascade, refill_min {refill}")
+    e = R.engine_single(w, init)
+    st = R.run(e, R.field_of(w), R.params_of(w, refill_min=refill), w.n_steps)
+    os_ = oracle_stores(orc, init, w.capacity)
+    ost = orc.run(os_, oracle_field(orc, w), oracle_params(orc, w), w.n_steps)
+    compare_stats(st, ost, label=f"rotating refill {refill}")
+    compare_all(e, os_, label=f"rotating refill {refill}")
+    w = W.standing_wave_grid(n=300, cells=32, capacity=200_000, lepton_capacity=20_000,
+                             steps=30, a0=2000.0)
+    init = W.standing_wave_initial(300, seed=2)
+    _note(f"yee grid, refill_min {refill}")
+    e = R.engine_single(w, init)
+    grid = R.YeeGrid(w)
+    f = R.field_of(w, grid=grid.g)
+    p = R.params_of(w, refill_min=refill)
+    os_ = oracle_stores(orc, init, w.capacity)
+    op = oracle_params(orc, w)
+    e.set_step(0)
+    st, ost = [], []
+    for n in range(w.n_steps):
+        vals = W.standing_wave_grid_values(w.field, w.t0 + n * w.dt)
+        grid.load_numpy(vals)
+        e.step(f, p)
+        torch.cuda.synchronize()
+        st.append(e.stats())
+        op.step = n
+        ost.append(orc.step(os_, oracle_field(orc, w, grids=vals), op))
+    compare_stats(st, ost, label=f"yee refill {refill}")
+    compare_all(e, os_, label=f"yee refill {refill}")
