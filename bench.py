@@ -173,7 +173,7 @@ def gpu_run(args, precision, kind="rotating", thin=None, fg=None, sample=None):
             thin_now()
     # ---- tuning run: launch shape per size class ----
     if args.no_tune:
-        sched = AT.Schedule(steps=[0], shapes=[(args.tile, args.grid_blocks, 0)])
+        sched = AT.Schedule(steps=[0], shapes=[(args.tile, args.grid_blocks, 0, 0)])
     else:
         restart()
         props = torch.cuda.get_device_properties(0)
@@ -280,8 +280,8 @@ def gpu_run(args, precision, kind="rotating", thin=None, fg=None, sample=None):
         launches=K, lep_bytes=lep_bytes,
         pho_bytes=pho_bytes, final_counts=[int(sum(c[s] for c in counts)) for s in range(3)],
         eager_matches_graph=bool(same),
-        schedule=[dict(from_step=k, tile=t, grid_blocks=g, arena_div=a)
-                  for k, (t, g, a) in zip(sched.steps, sched.shapes)],
+        schedule=[dict(from_step=k, tile=t, grid_blocks=g, arena_div=a, refill_min=r)
+                  for k, (t, g, a, r) in zip(sched.steps, sched.shapes)],
         substeps=int(sum(r.substeps for r in recs)),
         nsub_refined=int(sum(r.nsub_refined for r in recs)),
         low_occupancy_iters=int(sum(r.low_occupancy_iters for r in recs)),

@@ -1,4 +1,5 @@
-"""Launch tuner for qed_step: work-chunk size (`tile`), persistent grid and child-arena size.
+"""Launch tuner for qed_step: work-chunk size (`tile`), persistent grid, child-arena size and
+the lepton work queue's refill threshold.
 
 What a step decides does not depend on these (every draw and child id is keyed by the
 particle), only how fast it runs does, and that depends mostly on how many particles are
@@ -10,8 +11,11 @@ alive.  The tuner therefore works inside a run of the real job:
   per-wavefront work queue's chunk size and the persistent grid) with the engine's own
   arena; then, with the best of those, the child-arena sizes (records = photon slots /
   divisor: the per-wavefront shares and pool the lepton and pair producers write their
-  children into before the ordered copy).  The lowest time per particle-step wins;
-* the result is a schedule: (first step, shape) pairs, shape = (tile, grid, arena divisor).
+  children into before the ordered copy); then, with the best of those, the refill
+  thresholds of the lepton kernel's work queue (idle lanes taken in batches of at least
+  that many).  The lowest time per particle-step wins;
+* the result is a schedule: (first step, shape) pairs, shape = (tile, grid, arena divisor,
+  refill threshold).
 
 A cascade is deterministic, so a second run of the same job from the same seeds reaches the
 same counts at the same steps and can replay the schedule without synchronising, for
@@ -30,19 +34,24 @@ from typing import Callable, Dict, List, Optional, Sequence, Tuple
 
 from . import qed as Q
 
-# (tile, grid_blocks, arena divisor); 0 = the library's or the engine's default
-Shape = Tuple[int, int, int]
+# (tile, grid_blocks, arena divisor, refill threshold); 0 = the library's or the engine's
+# default
+Shape = Tuple[int, int, int, int]
+DEFAULT_SHAPE: Shape = (0, 0, 0, 0)
 
 
 def default_candidates(cu_count: int) -> List[Shape]:
     """Chunks of 64..512 particles on the library's resident grid, and 128-particle chunks
     on smaller and larger grids."""
-    return [(64, 0, 0), (128, 0, 0), (256, 0, 0), (512, 0, 0), (128, 2 * cu_count, 0),
-            (128, 8 * cu_count, 0)]
+    return [(64, 0, 0, 0), (128, 0, 0, 0), (256, 0, 0, 0), (512, 0, 0, 0),
+            (128, 2 * cu_count, 0, 0), (128, 8 * cu_count, 0, 0)]
 
 
 # Child-arena sizes tried with the best launch shape: photon slots / divisor records.
 DEFAULT_ARENA_DIVISORS = (32, 8, 2)
+# Refill thresholds tried last (1: every idle lane at once; 0, the library's default, is
+# the shape they are compared with).
+DEFAULT_REFILLS = (1, 16, 40)
 
 
 class HipTimer:
@@ -83,7 +92,7 @@ class Schedule:
     choices: Dict[int, Shape] = field(default_factory=dict)  # size class -> shape
 
     def shape_at(self, n: int) -> Shape:
-        s = self.shapes[0] if self.shapes else (0, 0, 0)
+        s = self.shapes[0] if self.shapes else DEFAULT_SHAPE
         for k, sh in zip(self.steps, self.shapes):
             if n >= k:
                 s = sh
@@ -94,7 +103,7 @@ class Schedule:
         for s in self.shapes:
             if s not in out:
                 out.append(s)
-        return out or [(0, 0, 0)]
+        return out or [DEFAULT_SHAPE]
 
 
 class TuneCache:
@@ -112,7 +121,9 @@ class TuneCache:
         return f"{arch}|{precision}|{workload}"
 
     def get(self, key: str) -> Dict[int, Shape]:
-        return {int(c): tuple(s) for c, s in self.data.get(key, {}).items()}
+        # entries written before the refill threshold was tuned have three fields
+        return {int(c): tuple(list(s) + [0] * (4 - len(s)))
+                for c, s in self.data.get(key, {}).items()}
 
     def put(self, key: str, choices: Dict[int, Shape]):
         self.data[key] = {str(c): list(s) for c, s in sorted(choices.items())}
@@ -123,13 +134,16 @@ class TuneCache:
 
 
 def apply_shape(e, params: Q.qed_params, shape: Shape):
-    """Set the launch shape in the step parameters and the arena size on the engine."""
+    """Set the launch shape and refill threshold in the step parameters and the arena size
+    on the engine."""
     params.tile, params.grid_blocks = int(shape[0]), int(shape[1])
+    params.refill_min = int(shape[3])
     e.set_arena(int(shape[2]))
 
 
 def tune_run(e, field, params: Q.qed_params, n_steps: int, candidates: Sequence[Shape],
-             arena_divisors: Sequence[int] = DEFAULT_ARENA_DIVISORS, rounds: int = 2,
+             arena_divisors: Sequence[int] = DEFAULT_ARENA_DIVISORS,
+             refills: Sequence[int] = DEFAULT_REFILLS, rounds: int = 2,
              class_factor: float = 4.0, min_live: int = 1 << 16, stop_on_drop: bool = False,
              after_step: Optional[Callable[[], None]] = None, timer=None,
              known: Optional[Dict[int, Shape]] = None,
@@ -152,7 +166,7 @@ def tune_run(e, field, params: Q.qed_params, n_steps: int, candidates: Sequence[
     best: Dict[int, Shape] = dict(known or {})
     pending: List[Shape] = []
     timings: Dict[Shape, List[float]] = {}
-    phase = 0  # 0: launch shapes, 1: arena sizes
+    phase = 0  # 0: launch shapes, 1: arena sizes, 2: refill thresholds
     cls_of_step: List[int] = []
     tuning: Optional[int] = None  # class whose trials are running
 
@@ -165,10 +179,12 @@ def tune_run(e, field, params: Q.qed_params, n_steps: int, candidates: Sequence[
         phase = ph
         if ph == 0:
             cands = list(candidates)
+        elif ph == 1:
+            cands = [(base[0], base[1], d, base[3]) for d in arena_divisors]
         else:
-            cands = [(base[0], base[1], d) for d in arena_divisors]
-            if base not in cands:
-                cands.append(base)
+            cands = [(base[0], base[1], base[2], r) for r in refills]
+        if ph > 0 and base not in cands:
+            cands.append(base)
         pending = [s for _ in range(rounds) for s in cands]
         timings = {s: [] for s in cands}
 
@@ -190,7 +206,7 @@ def tune_run(e, field, params: Q.qed_params, n_steps: int, candidates: Sequence[
             tuning = cls
             start_phase(0, None)
         if cls < 0:
-            shape = (0, 0, 0)
+            shape = DEFAULT_SHAPE
         elif cls in best:
             shape = best[cls]
         else:
@@ -208,16 +224,17 @@ def tune_run(e, field, params: Q.qed_params, n_steps: int, candidates: Sequence[
             if done > 0:
                 timings[shape].append(ms / done)
             trials.append(dict(step=n, cls=cls, tile=shape[0], grid=shape[1],
-                               arena_div=shape[2], ms=ms, particle_steps=done))
+                               arena_div=shape[2], refill=shape[3], ms=ms,
+                               particle_steps=done))
             if not pending:
-                if phase == 0:
-                    b = fastest()
-                    if b is None or not arena_divisors:
-                        settle(cls)
-                    else:
-                        start_phase(1, b)
-                else:
+                b = fastest()
+                nxt = phase + 1
+                if nxt == 1 and not arena_divisors:
+                    nxt = 2
+                if b is None or nxt > 2 or (nxt == 2 and not refills):
                     settle(cls)
+                else:
+                    start_phase(nxt, b)
         if stop_on_drop and st["dropped"] > 0:
             break
     settle(tuning)
@@ -226,7 +243,7 @@ def tune_run(e, field, params: Q.qed_params, n_steps: int, candidates: Sequence[
         ev.close()
     sched = Schedule(trials=trials, choices=dict(best))
     for n, cls in enumerate(cls_of_step):
-        shape = best.get(cls, (0, 0, 0)) if cls >= 0 else (0, 0, 0)
+        shape = best.get(cls, DEFAULT_SHAPE) if cls >= 0 else DEFAULT_SHAPE
         if not sched.shapes or sched.shapes[-1] != shape:
             sched.steps.append(n)
             sched.shapes.append(shape)

@@ -1,7 +1,8 @@
 """The launch tuner (autotune.tune_run, Schedule, TuneCache) on a stand-in engine whose step
 times are scripted: per size class it must pick the fastest launch shape, then the fastest
 child-arena size with that shape, give every step its class's choice, skip the classes a
-cache already knows, and keep the best so far for a class the run leaves early.  No GPU."""
+cache already knows, and keep the best so far for a class the run leaves early; then the
+refill threshold with that shape.  No GPU."""
 import math
 from types import SimpleNamespace
 
@@ -31,7 +32,7 @@ class FakeEngine:
         self.arena = divisor
 
     def step(self, field, params):
-        shape = (params.tile, params.grid_blocks, self.arena)
+        shape = (params.tile, params.grid_blocks, self.arena, params.refill_min)
         self.shapes.append(shape)
         self.done = self.live
         self.last_ms = self.live * self.cost(shape, self.live)
@@ -62,43 +63,49 @@ def cls_of(live):
 
 def scripted_cost(shape, live):
     """Small classes like 64-particle chunks, large ones 512; arena divisor 8 is best at
-    every size; the default grid beats the smaller and larger ones."""
-    tile, grid, arena = shape
+    every size; the default grid beats the smaller and larger ones; small classes refill
+    every idle lane, large ones in batches of 40."""
+    tile, grid, arena, refill = shape
     want_tile = 64 if cls_of(live) < 2 else 512
     c = 1.0 + 0.1 * abs(math.log2(max(tile, 1) / want_tile))
     c += 0.05 if grid else 0.0
     c += {0: 0.02, 2: 0.03, 8: 0.0, 32: 0.04}[arena]
+    want_refill = 1 if cls_of(live) < 2 else 40
+    c += 0.0 if refill == want_refill else 0.01
     return c
 
 
 def _tune(e, steps, **kw):
-    params = SimpleNamespace(tile=0, grid_blocks=0)
+    params = SimpleNamespace(tile=0, grid_blocks=0, refill_min=0)
     return AT.tune_run(e, None, params, steps, CANDS, min_live=MIN_LIVE, timer=FakeTimer(e),
                        sync=lambda: None, **kw)
 
 
 def test_each_class_gets_its_fastest_launch_shape_then_arena():
-    e = FakeEngine(scripted_cost, growth=1.08)
-    sched = _tune(e, 160)
+    # 1.04 a step: a class (a factor 4) lasts 35 steps, more than its 28 trial steps
+    e = FakeEngine(scripted_cost, growth=1.04)
+    sched = _tune(e, 240)
     lives = [100]
-    for _ in range(159):
-        lives.append(int(math.ceil(lives[-1] * 1.08)))
+    for _ in range(239):
+        lives.append(int(math.ceil(lives[-1] * 1.04)))
     classes = sorted({cls_of(v) for v in lives if cls_of(v) >= 0})
     assert len(classes) >= 3
     for c in classes[:-1]:  # the last class may be cut short by the end of the run
         want_tile = 64 if c < 2 else 512
-        assert sched.choices[c] == (want_tile, 0, 8), c
+        assert sched.choices[c] == (want_tile, 0, 8, 1 if c < 2 else 40), c
     # every step follows its class's choice (trial steps included), the default below
     # min_live, and the trials tried both phases
     for n, live in enumerate(lives):
         c = cls_of(live)
-        assert sched.shape_at(n) == (sched.choices.get(c, (0, 0, 0)) if c >= 0 else (0, 0, 0))
-    tried = {(t["tile"], t["grid"], t["arena_div"]) for t in sched.trials}
-    assert set(CANDS) <= tried and {(64, 0, 2), (64, 0, 32)} <= tried
-    assert sched.distinct()[0] == (0, 0, 0)
+        assert sched.shape_at(n) == (sched.choices.get(c, AT.DEFAULT_SHAPE) if c >= 0
+                                     else AT.DEFAULT_SHAPE)
+    tried = {(t["tile"], t["grid"], t["arena_div"], t["refill"]) for t in sched.trials}
+    assert set(CANDS) <= tried and {(64, 0, 2, 0), (64, 0, 32, 0)} <= tried
+    assert {(64, 0, 8, 1), (64, 0, 8, 16), (64, 0, 8, 40)} <= tried
+    assert sched.distinct()[0] == AT.DEFAULT_SHAPE
     # the engine really ran the trial shapes, and each class's choice afterwards
-    assert e.shapes[0] == (0, 0, 0)
-    assert (512, 0, 8) in e.shapes
+    assert e.shapes[0] == AT.DEFAULT_SHAPE
+    assert (512, 0, 8, 40) in e.shapes
 
 
 def test_known_classes_skip_their_trials(tmp_path):
@@ -126,12 +133,19 @@ def test_a_class_left_early_keeps_its_best_so_far():
         timed = [t for t in sched.trials if t["cls"] == c]
         assert timed, c
         best = min(timed, key=lambda t: t["ms"] / t["particle_steps"])
-        assert shape == (best["tile"], best["grid"], best["arena_div"])
+        assert shape == (best["tile"], best["grid"], best["arena_div"], best["refill"])
 
 
 def test_schedule_lookup():
-    s = AT.Schedule(steps=[0, 5, 9], shapes=[(0, 0, 0), (64, 0, 8), (512, 0, 2)])
-    assert [s.shape_at(n) for n in (0, 4, 5, 8, 9, 100)] == \
-        [(0, 0, 0), (0, 0, 0), (64, 0, 8), (64, 0, 8), (512, 0, 2), (512, 0, 2)]
-    assert s.distinct() == [(0, 0, 0), (64, 0, 8), (512, 0, 2)]
-    assert AT.Schedule().distinct() == [(0, 0, 0)]
+    a, b, c = (0, 0, 0, 0), (64, 0, 8, 40), (512, 0, 2, 1)
+    s = AT.Schedule(steps=[0, 5, 9], shapes=[a, b, c])
+    assert [s.shape_at(n) for n in (0, 4, 5, 8, 9, 100)] == [a, a, b, b, c, c]
+    assert s.distinct() == [a, b, c]
+    assert AT.Schedule().distinct() == [AT.DEFAULT_SHAPE]
+
+
+def test_cache_entries_without_a_refill_threshold_read_as_the_default(tmp_path):
+    import json
+    path = tmp_path / "old.json"
+    path.write_text(json.dumps({"k": {"0": [64, 0, 8], "2": [512, 0, 2]}}))
+    assert AT.TuneCache(str(path)).get("k") == {0: (64, 0, 8, 0), 2: (512, 0, 2, 0)}
