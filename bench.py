@@ -128,7 +128,8 @@ def sampled_steps(n_steps, k):
     return sorted({int((i + 0.5) * n_steps / k) for i in range(k)})
 
 
-def gpu_run(args, precision, kind="rotating", thin=None, fg=None, sample=None):
+def gpu_run(args, precision, kind="rotating", thin=None, fg=None, sample=None, over=None,
+            per_parent=None):
     """One job (every step of it) three times from the same seeds: a tuning run that picks
     the launch shape per size class (untimed); the timed run, one captured graph per chosen
     shape replayed step by step, with HIP events around the whole job and around each step
@@ -136,7 +137,9 @@ def gpu_run(args, precision, kind="rotating", thin=None, fg=None, sample=None):
     HIP events around the lepton and photon kernels of every step (per-kernel durations for
     the roofline).  The three runs compute the same thing.  thin = (trigger, target):
     qed_thin on the photon store after every step (timed with the step).  fg = (f_photon,
-    f_pair): the generator factors of Sec. VI."""
+    f_pair): the generator factors of Sec. VI; `over`: other step parameters (the
+    deterministic factor, the reverse mode); per_parent: qed_thin_children on the photon
+    store after every step with that cap (timed with the step, as thinning)."""
     import numpy as np
     import torch
     from paper_1412_6426_amd import autotune as AT
@@ -149,6 +152,9 @@ def gpu_run(args, precision, kind="rotating", thin=None, fg=None, sample=None):
     params = R.params_of(w, freeze_on_drop=1, tile=args.tile, grid_blocks=args.grid_blocks)
     if fg is not None:
         params.f_photon, params.f_pair = fg
+    for k, v in (over or {}).items():
+        setattr(params, k, v)
+    thinning = thin is not None or per_parent is not None
     K = w.n_steps
     timed = sampled_steps(K, sample)
     stream = torch.cuda.Stream()
@@ -163,6 +169,8 @@ def gpu_run(args, precision, kind="rotating", thin=None, fg=None, sample=None):
         torch.cuda.synchronize()
 
     def thin_now():
+        if per_parent is not None:
+            e.thin_children(Q.QED_PHOTON, per_parent, stream=sp)
         if thin is not None:
             e.thin(Q.QED_PHOTON, thin[0], thin[1], stream=sp)
 
@@ -235,14 +243,14 @@ def gpu_run(args, precision, kind="rotating", thin=None, fg=None, sample=None):
     # ---- per-kernel durations: the same K steps eagerly, HIP events on our stream ----
     restart()
     evs = hip.create(4 * K)
-    tev = hip.create(2 * K) if thin is not None else []
+    tev = hip.create(2 * K) if thinning else []
     with torch.cuda.stream(stream):
         for n in range(K):
             AT.apply_shape(e, params, shape_of[n])
             for j in range(4):
                 params.events[j] = evs[4 * n + j]
             e.step(field, params, stream=sp)
-            if thin is not None:
+            if thinning:
                 hip.lib.hipEventRecord(C.c_void_p(tev[2 * n]), C.c_void_p(sp))
                 thin_now()
                 hip.lib.hipEventRecord(C.c_void_p(tev[2 * n + 1]), C.c_void_p(sp))
@@ -252,7 +260,7 @@ def gpu_run(args, precision, kind="rotating", thin=None, fg=None, sample=None):
         params.events[j] = None
     lep_t = [hip.elapsed_ms(evs[4 * n], evs[4 * n + 1]) for n in range(K)]
     pho_t = [hip.elapsed_ms(evs[4 * n + 2], evs[4 * n + 3]) for n in range(K)]
-    thin_t = [hip.elapsed_ms(tev[2 * n], tev[2 * n + 1]) for n in range(K)] if thin else []
+    thin_t = [hip.elapsed_ms(tev[2 * n], tev[2 * n + 1]) for n in range(K)] if thinning else []
     hip.destroy(evs)
     hip.destroy(tev)
     recs2 = _stats_records(log.cpu().numpy().tobytes(), K)
@@ -1119,6 +1127,21 @@ def main():
         detail("generator_factor_cascade",
                {k: v for k, v in rf.items() if not k.startswith("step_")})
         legs["generator_factor_cascade"] = dict(value=rf["value_job"], dropped=rf["dropped"])
+        # the other forms of Sec. VI and VII on the same job: the factor taken once every
+        # f_g events, the reverse mode (two emission runs per sub-step at half the weight),
+        # and at most one photon per lepton and step kept (the cap per parent), each with
+        # the same global thinning past the capacity
+        forms = {}
+        for name, kw in (("every", dict(fg=(4.0, 1.0), over=dict(f_every=1))),
+                         ("reverse", dict(over=dict(runs_photon=2))),
+                         ("capped", dict(per_parent=1))):
+            print(f"bench: rotating-E cascade, {name}", file=sys.stderr, flush=True)
+            rr = gpu_run(args, args.precision, thin=(int(0.8 * cap), int(0.4 * cap)), **kw)
+            detail(f"generator_forms_{name}",
+                   {k: v for k, v in rr.items() if not k.startswith("step_")})
+            forms[name] = rr["value_job"]
+            forms[name + "_drop"] = rr["dropped"]
+        legs["generator_forms"] = forms
     if not args.no_shower:
         sh = gpu_shower(args)
         detail("shower_time_step_invariance", sh)

@@ -1148,9 +1148,11 @@ __global__ void __launch_bounds__(256)
 }
 
 // The reverse mode of Sec. VI in a kernel of its own: its extra runs hold more registers,
-// which the other forms would pay for in occupancy.
+// which the other forms would pay for in occupancy.  Held to two wavefronts per SIMD (a few
+// spilled registers) rather than one.
 template <bool MIXED, int FMODE>
-__global__ void __launch_bounds__(256) lepton_runs_kernel(StepArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+    lepton_runs_kernel(StepArgs a) {
   lepton_step<MIXED, FMODE, true, true>(a);
 }
 
@@ -1720,9 +1722,11 @@ __global__ void __launch_bounds__(256) photon_exact_kernel(StepArgs a) {
   exact_pass<MIXED, FMODE, false>(a);
 }
 
-// The reverse mode of Sec. VI (runs_pair > 1) in a kernel of its own, for the registers.
+// The reverse mode of Sec. VI (runs_pair > 1) in a kernel of its own, for the registers,
+// held to two wavefronts per SIMD.
 template <bool MIXED, int FMODE>
-__global__ void __launch_bounds__(256) photon_exact_runs_kernel(StepArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+    photon_exact_runs_kernel(StepArgs a) {
   exact_pass<MIXED, FMODE, true>(a);
 }
 

@@ -8,24 +8,31 @@
 // child's id), at least the one with the smallest draw, and its survivors take n / K of their
 // weight (K survivors).  Everything else keeps its place; the store is compacted stably.
 //
-// Groups are found with an open-addressing hash table per instance (2 x capacity entries,
+// Groups are found with an open-addressing hash table per instance (twice its children,
 // linear probing, keys claimed by compare-and-swap), whose counts are sums of integers and
 // so do not depend on the order of the threads.  Weight totals for the records are summed
 // per range in a fixed tree order and then range by range.
 //
+// Only the tail of a segment from its first child on is touched after the first pass: the
+// children of a step are appended to the stores, so the tail is about the last step's
+// children, and the rest of the store keeps its place without being read or written.
+//
 // Launches on the caller's stream (grids fixed by the slot count, so the sequence can be
 // captured):
-//   prep     one workgroup: table bases, counters cleared;
+//   prep     one workgroup: counts, counters cleared;
+//   count    the children of each instance and its first one (birth codes first, the parent
+//            and id only where the birth code names the step);
+//   bases    one thread per instance: table bases and sizes, the tail;
 //   clear    the tables;
-//   insert   each child into its instance's table: entry per slot, group sizes, groups,
-//            groups above the cap;
+//   insert   each child of the tail into its instance's table: entry per slot, group sizes,
+//            groups, groups above the cap;
 //   draw     in groups above the cap: survivors counted, smallest draw per group;
 //   tie      in groups without survivors: the children with the smallest draw;
-//   keep     keep flags, and per range the kept slots, children, their weight before and
-//            after;
+//   keep     keep flags, and per range of the tail the kept slots, children, their weight
+//            before and after;
 //   plan     one thread per instance: offsets of the ranges, the new count, the records;
-//   scatter  kept rows, in order, into a column copy (survivors scaled);
-//   back     the copy into the segments;
+//   scatter  kept rows of the tail, in order, into a column copy (survivors scaled);
+//   back     the copy into the tail;
 //   finish   the counts.
 #include "qed_internal.h"
 
@@ -38,11 +45,12 @@ constexpr unsigned kNoEntry = 0xFFFFFFFFu;
 
 struct ChildHdr {
   long long tab;        // first entry of the instance's table
-  long long size;       // its entries (2 x capacity; 0 when frozen)
+  long long size;       // its entries (2 x its children; 0 when frozen)
   unsigned long long groups, thinned;
   long long before;     // slots before (the count, at most the capacity)
   long long count;      // slots after
-  long long pad[2];
+  unsigned long long children;  // children of the last step
+  unsigned long long first;     // the slot of the first one (the tail starts there)
 };
 static_assert(sizeof(ChildHdr) == 64, "instance headers are 64 bytes");
 
@@ -88,10 +96,12 @@ __device__ __forceinline__ void range_of(long long n, int nb, int b, long long& 
   if (lo > n) lo = n;
 }
 
-// A child of the last step: live, born in it (birth >> 14 == the step counter), with a parent.
+// A child of the last step: born in it (birth >> 14 == the step counter), live, with a
+// parent (the birth code first: most slots stop there).
 __device__ __forceinline__ bool is_child(const TcArgs& a, long long s, uint32_t step) {
+  if ((a.s.birth[s] >> 14) != step) return false;
   if (a.species == QED_PHOTON && a.s.id[s] == QED_ID_DEAD) return false;
-  return (a.s.birth[s] >> 14) == step && a.s.parent[s] != QED_NO_PARENT;
+  return a.s.parent[s] != QED_NO_PARENT;
 }
 
 __device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
@@ -112,26 +122,71 @@ __device__ __forceinline__ double bits_uniform(unsigned long long m) {
 }
 
 __global__ void __launch_bounds__(kTcThreads) tc_prep_kernel(TcArgs a) {
-  if (threadIdx.x != 0) return;
-  long long t = 0;
-  for (int i = 0; i < a.n_inst; ++i) {
+  for (int i = threadIdx.x; i < a.n_inst; i += blockDim.x) {
     const qed_instance& I = a.inst[i];
     ChildHdr h{};
-    h.tab = t;
-    h.size = I.frozen ? 0 : 2 * I.capacity[a.species];
     // a count beyond the segment (left by an append that dropped) covers only its capacity
     const long long n = I.count[a.species];
     h.before = n < 0 ? 0 : (n > I.capacity[a.species] ? I.capacity[a.species] : n);
     h.count = h.before;
-    t += h.size;
+    h.first = (unsigned long long)h.before;
     a.hdr[i] = h;
   }
 }
 
+__global__ void __launch_bounds__(kTcThreads) tc_count_kernel(TcArgs a) {
+  const int i = blockIdx.y;
+  const qed_instance& I = a.inst[i];
+  if (I.frozen) return;
+  long long lo, hi;
+  range_of(a.hdr[i].before, a.nb, blockIdx.x, lo, hi);
+  const uint32_t step = (uint32_t)*a.d_step;
+  const long long base = I.base[a.species];
+  unsigned long long n = 0, first = ~0ull;
+  for (long long j = lo + threadIdx.x; j < hi; j += blockDim.x) {
+    if (!is_child(a, base + j, step)) continue;
+    ++n;
+    if ((unsigned long long)j < first) first = (unsigned long long)j;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    n += __shfl_xor(n, o, 64);
+    const unsigned long long f = __shfl_xor(first, o, 64);
+    first = f < first ? f : first;
+  }
+  if (lane_id() == 0 && n) {
+    atomicAdd(&a.hdr[i].children, n);
+    atomicMin(&a.hdr[i].first, first);
+  }
+}
+
+// Table bases: twice each instance's children (so an empty entry is always found), in
+// instance order; one thread does the prefix.
+__global__ void __launch_bounds__(kTcThreads) tc_bases_kernel(TcArgs a) {
+  if (threadIdx.x != 0) return;
+  long long t = 0;
+  for (int i = 0; i < a.n_inst; ++i) {
+    ChildHdr& h = a.hdr[i];
+    h.tab = t;
+    h.size = 2 * (long long)h.children;
+    t += h.size;
+  }
+}
+
+// The tail of instance i: from its first child to its count.
+__device__ __forceinline__ void tail_range(const ChildHdr& h, int nb, int b, long long& lo,
+                                           long long& hi) {
+  const long long t0 = (long long)h.first;
+  range_of(h.before - t0, nb, b, lo, hi);
+  lo += t0;
+  hi += t0;
+}
+
 __global__ void __launch_bounds__(kTcThreads) tc_clear_kernel(TcArgs a) {
-  const long long n = 2 * a.slots;
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
-       e += (long long)gridDim.x * blockDim.x) {
+  const ChildHdr& h = a.hdr[blockIdx.y];
+  long long lo, hi;
+  range_of(h.size, a.nb, blockIdx.x, lo, hi);
+  for (long long e = h.tab + lo + threadIdx.x; e < h.tab + hi; e += blockDim.x) {
     a.tkey[e] = QED_NO_PARENT;
     a.tn[e] = 0u;
     a.tk[e] = 0u;
@@ -145,9 +200,10 @@ __global__ void __launch_bounds__(kTcThreads) tc_insert_kernel(TcArgs a) {
   const qed_instance& I = a.inst[i];
   const ChildHdr& h = a.hdr[i];
   long long lo, hi;
-  range_of(h.before, a.nb, blockIdx.x, lo, hi);
+  tail_range(h, a.nb, blockIdx.x, lo, hi);
   const uint32_t step = (uint32_t)*a.d_step;
   const long long base = I.base[a.species];
+  unsigned long long groups = 0, thinned = 0;
   for (long long j = lo + threadIdx.x; j < hi; j += blockDim.x) {
     const long long s = base + j;
     if (h.size == 0 || !is_child(a, s, step)) {
@@ -155,7 +211,7 @@ __global__ void __launch_bounds__(kTcThreads) tc_insert_kernel(TcArgs a) {
       continue;
     }
     const unsigned long long parent = a.s.parent[s];
-    // the table holds twice the capacity: an empty entry is always found
+    // the table holds twice the children: an empty entry is always found
     unsigned long long e = mix64(parent) % (unsigned long long)h.size;
     unsigned long long old;
     for (;;) {
@@ -165,8 +221,18 @@ __global__ void __launch_bounds__(kTcThreads) tc_insert_kernel(TcArgs a) {
     }
     a.ent[s] = (unsigned)e;
     const unsigned before = atomicAdd(&a.tn[h.tab + e], 1u);
-    if (old == QED_NO_PARENT) atomicAdd(&a.hdr[i].groups, 1ull);
-    if ((long long)before == a.cap) atomicAdd(&a.hdr[i].thinned, 1ull);
+    groups += old == QED_NO_PARENT;
+    thinned += (long long)before == a.cap;
+  }
+  // one add per wavefront to the instance's counters
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    groups += __shfl_xor(groups, o, 64);
+    thinned += __shfl_xor(thinned, o, 64);
+  }
+  if (lane_id() == 0) {
+    if (groups) atomicAdd(&a.hdr[i].groups, groups);
+    if (thinned) atomicAdd(&a.hdr[i].thinned, thinned);
   }
 }
 
@@ -180,7 +246,7 @@ __global__ void __launch_bounds__(kTcThreads) tc_draw_kernel(TcArgs a, int tie) 
   const qed_instance& I = a.inst[i];
   const ChildHdr& h = a.hdr[i];
   long long lo, hi;
-  range_of(h.before, a.nb, blockIdx.x, lo, hi);
+  tail_range(h, a.nb, blockIdx.x, lo, hi);
   const uint32_t step = (uint32_t)*a.d_step;
   const long long base = I.base[a.species];
   for (long long j = lo + threadIdx.x; j < hi; j += blockDim.x) {
@@ -237,7 +303,7 @@ __global__ void __launch_bounds__(kTcThreads) tc_keep_kernel(TcArgs a) {
   const qed_instance& I = a.inst[i];
   const ChildHdr& h = a.hdr[i];
   long long lo, hi;
-  range_of(h.before, a.nb, blockIdx.x, lo, hi);
+  tail_range(h, a.nb, blockIdx.x, lo, hi);
   const uint32_t step = (uint32_t)*a.d_step;
   const long long base = I.base[a.species];
   long long kept = 0, children = 0, kept_children = 0;
@@ -274,28 +340,59 @@ __global__ void __launch_bounds__(kTcThreads) tc_keep_kernel(TcArgs a) {
   }
 }
 
+// One workgroup per instance: thread t takes ranges [t k, t k + k) (k = nb / threads, rounded
+// up), sums them in order, the workgroup scans the thread totals, and the ranges' offsets
+// follow; the record's sums go thread by thread in order.
 __global__ void __launch_bounds__(kTcThreads) tc_plan_kernel(TcArgs a) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.n_inst) return;
+  __shared__ long long skept[kTcThreads];
+  __shared__ long long sch[kTcThreads], skc[kTcThreads];
+  __shared__ double swb[kTcThreads], swa[kTcThreads];
+  const int i = blockIdx.x;
   const ChildHdr& h = a.hdr[i];
-  qed_thin_children_record r{};
-  long long o = 0;
-  for (int b = 0; b < a.nb; ++b) {
+  const int per = (a.nb + (int)blockDim.x - 1) / (int)blockDim.x;
+  const int b0 = (int)threadIdx.x * per;
+  const int b1 = b0 + per < a.nb ? b0 + per : a.nb;
+  long long kept = 0, ch = 0, kc = 0;
+  double wb = 0.0, wa = 0.0;
+  for (int b = b0; b < b1; ++b) {
     const ChildPart& p = a.part[(size_t)i * a.nb + b];
-    a.off[(size_t)i * a.nb + b] = o;
-    o += p.kept;
-    r.children += p.children;
-    r.kept += p.kept_children;
-    r.weight_before += p.w_before;
-    r.weight_after += p.w_after;
+    kept += p.kept;
+    ch += p.children;
+    kc += p.kept_children;
+    wb += p.w_before;
+    wa += p.w_after;
   }
+  skept[threadIdx.x] = kept;
+  sch[threadIdx.x] = ch;
+  skc[threadIdx.x] = kc;
+  swb[threadIdx.x] = wb;
+  swa[threadIdx.x] = wa;
+  __syncthreads();
+  // exclusive prefix of the kept slots over the threads before this one
+  long long o = 0;
+  for (int u = 0; u < (int)threadIdx.x; ++u) o += skept[u];
+  for (int b = b0; b < b1; ++b) {
+    a.off[(size_t)i * a.nb + b] = o;
+    o += a.part[(size_t)i * a.nb + b].kept;
+  }
+  if (threadIdx.x != 0) return;
+  qed_thin_children_record r{};
+  long long total = 0;
+  for (int u = 0; u < (int)blockDim.x; ++u) {
+    total += skept[u];
+    r.children += sch[u];
+    r.kept += skc[u];
+    r.weight_before += swb[u];
+    r.weight_after += swa[u];
+  }
+  total += (long long)h.first;
   if (a.inst[i].frozen) {
     r = qed_thin_children_record{};
-    o = h.count;
+    total = h.count;
   }
   r.groups = (long long)h.groups;
   r.groups_thinned = (long long)h.thinned;
-  a.hdr[i].count = o;  // read by back and finish only, after this kernel
+  a.hdr[i].count = total;  // read by back and finish only, after this kernel
   a.rec[i] = r;
 }
 
@@ -306,11 +403,11 @@ __global__ void __launch_bounds__(kTcThreads) tc_scatter_kernel(TcArgs a) {
   if (I.frozen) return;
   const ChildHdr& h = a.hdr[i];
   long long lo, hi;
-  // the range over the count before thinning (the plan kernel has set the count after it)
-  range_of(h.before, a.nb, blockIdx.x, lo, hi);
+  // the tail before thinning (the plan kernel has set the count after it)
+  tail_range(h, a.nb, blockIdx.x, lo, hi);
   const uint32_t step = (uint32_t)*a.d_step;
   const long long base = I.base[a.species];
-  long long run = a.off[(size_t)i * a.nb + blockIdx.x];
+  long long run = (long long)h.first + a.off[(size_t)i * a.nb + blockIdx.x];
   const uint64_t below = lanes_below();
   const int wv = (int)(threadIdx.x >> 6);
   const long long cap = a.slots;
@@ -353,8 +450,12 @@ __global__ void __launch_bounds__(kTcThreads) tc_back_kernel(TcArgs a) {
   const int i = blockIdx.y;
   const qed_instance& I = a.inst[i];
   if (I.frozen) return;
+  const ChildHdr& h = a.hdr[i];
+  const long long t0 = (long long)h.first;
   long long lo, hi;
-  range_of(a.hdr[i].count, a.nb, blockIdx.x, lo, hi);
+  range_of(h.count - t0, a.nb, blockIdx.x, lo, hi);
+  lo += t0;
+  hi += t0;
   const long long base = I.base[a.species];
   const long long cap = a.slots;
   for (long long j = lo + threadIdx.x; j < hi; j += blockDim.x) {
@@ -440,16 +541,15 @@ hipError_t launch_thin_children(const qed_soa& s, int species, qed_instance* ins
   a.rec = rec;
   const dim3 ranges(L.nb, n_inst);
   const int per_inst = (n_inst + kTcThreads - 1) / kTcThreads;
-  const long long entries = 2 * a.slots;
-  long long cg = (entries + kTcThreads - 1) / kTcThreads;
-  if (cg > 65536) cg = 65536;
   hipLaunchKernelGGL(tc_prep_kernel, dim3(1), dim3(kTcThreads), 0, st, a);
-  hipLaunchKernelGGL(tc_clear_kernel, dim3((unsigned)cg), dim3(kTcThreads), 0, st, a);
+  hipLaunchKernelGGL(tc_count_kernel, ranges, dim3(kTcThreads), 0, st, a);
+  hipLaunchKernelGGL(tc_bases_kernel, dim3(1), dim3(kTcThreads), 0, st, a);
+  hipLaunchKernelGGL(tc_clear_kernel, ranges, dim3(kTcThreads), 0, st, a);
   hipLaunchKernelGGL(tc_insert_kernel, ranges, dim3(kTcThreads), 0, st, a);
   hipLaunchKernelGGL(tc_draw_kernel, ranges, dim3(kTcThreads), 0, st, a, 0);
   hipLaunchKernelGGL(tc_draw_kernel, ranges, dim3(kTcThreads), 0, st, a, 1);
   hipLaunchKernelGGL(tc_keep_kernel, ranges, dim3(kTcThreads), 0, st, a);
-  hipLaunchKernelGGL(tc_plan_kernel, dim3(per_inst), dim3(kTcThreads), 0, st, a);
+  hipLaunchKernelGGL(tc_plan_kernel, dim3(n_inst), dim3(kTcThreads), 0, st, a);
   hipLaunchKernelGGL(tc_scatter_kernel, ranges, dim3(kTcThreads), 0, st, a);
   hipLaunchKernelGGL(tc_back_kernel, ranges, dim3(kTcThreads), 0, st, a);
   hipLaunchKernelGGL(tc_finish_kernel, dim3(per_inst), dim3(kTcThreads), 0, st, a);
