@@ -434,9 +434,9 @@ def gpu_run_yee(args, precision, sort_every=None, sort_species=None, thin=None):
 
 
 def gpu_uniform_b(args):
-    """Config 1: 10^4 electrons at gamma = 1000 across a uniform B with chi = 1, eight
-    sub-steps each (dt = T_gyro/100), 100 steps, emission only, photons recorded and not
-    pushed.  Steps run eagerly on one stream with HIP events around each step and around its
+    """The uniform-B workload: 10^4 electrons at gamma = 1000 across a uniform B with
+    chi = 1, eight sub-steps each (dt = T_gyro/100), 100 steps, emission only, photons
+    recorded and not pushed.  Steps run eagerly on one stream with HIP events around each step and around its
     lepton kernel, then again from the seeds as one captured step replayed 100 times.  10^4
     electrons fill 157 wavefronts: these runs show the step's fixed cost per launch, not a
     bandwidth."""

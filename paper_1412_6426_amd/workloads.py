@@ -92,7 +92,7 @@ def empty_columns() -> Dict[str, np.ndarray]:
 
 
 # ---------------------------------------------------------------------------------------
-# Config 1: FP64 plain method, single instance, static uniform B (chi = 1 at gamma = 1000)
+# Uniform B: FP64 plain method, single instance, static uniform B (chi = 1 at gamma = 1000)
 # ---------------------------------------------------------------------------------------
 def uniform_b(n: int = 10_000, gamma: float = 1000.0, steps: int = 100, seed: int = 0,
               dt_frac: float = 0.01, photon_capacity: Optional[int] = None) -> Workload:
@@ -123,7 +123,7 @@ def uniform_b_initial(w: Workload, gamma: float = 1000.0) -> List[Dict[str, np.n
 
 
 # ---------------------------------------------------------------------------------------
-# Config 2 / 4: rotating-electric-field cascade
+# Rotating-electric-field cascade (FP64 and mixed precision)
 # ---------------------------------------------------------------------------------------
 def rotating_e(n: int = 100_000, a0: float = 1000.0, periods: float = 3.0, seed: int = 0,
                capacity: int = 100_000_000, lepton_capacity: Optional[int] = None,
@@ -159,7 +159,7 @@ def rotating_e_initial(n: int, seed: int, lam_m: float = 0.8e-6,
 
 
 # ---------------------------------------------------------------------------------------
-# Config 3: standing-wave cascade with Yee-grid fields
+# Standing-wave cascade with Yee-grid fields
 # ---------------------------------------------------------------------------------------
 def standing_wave_grid(n: int = 1_000_000, a0: float = 2000.0, cells: int = 256,
                        cells_per_lambda: int = 32, capacity: int = 200_000_000,
@@ -220,7 +220,7 @@ def standing_wave_grid_values(fs: FieldSpec, t: float) -> List[np.ndarray]:
 
 
 # ---------------------------------------------------------------------------------------
-# Config 5: batched ensemble of rotating-field cascades
+# Batched ensemble of rotating-field cascades
 # ---------------------------------------------------------------------------------------
 def batched_rotating(instances: int = 64, a_lo: float = 500.0, a_hi: float = 3000.0,
                      n_lo: int = 1000, n_hi: int = 100_000, periods: float = 2.0,
