@@ -1342,7 +1342,12 @@ __global__ void __launch_bounds__(256) photon_kernel(StepArgs a) {
     for (long long base = cur; base < end; base += 64) {
       const PhotonIn in = nxt;
       if (base + 64 < end) {
+        // the next batch's loads go out at a raised wave priority, ahead of the other
+        // wavefronts' arithmetic on the SIMD (265 against 267 us per launch on the
+        // rotating-field cascade)
+        __builtin_amdgcn_s_setprio(1);
         nxt = load_photons(S, base + 64, end, lane);
+        __builtin_amdgcn_s_setprio(0);
       } else {
         has_next = wr.next(a, a.pho_pref, a.n_inst, false, tn);
         if (has_next) nxt = load_photons(S, wave_uniform(tn.cur), wave_uniform(tn.end), lane);
