@@ -26,16 +26,20 @@ the same job in mixed precision with its photon-spectrum L1 distance and pair yi
 the FP64 job, the batched ensemble (64 rotating-field cascades, a0 log-spaced over
 500-3000, 10^3-10^5 seeds each, 2 periods, 2*10^8 slots split evenly) as full jobs in mixed
 precision and in FP64 with the same comparison, the standing-wave cascade on a 256^3 Yee
-grid (field fill timed apart), the rotating-field cascade carried past its capacity by
-thinning, the Sec. VII shower and avalanche, 10^4 electrons in a uniform B, Schwinger
-pairs, the three emission generators, and the FP64 CPU oracle's rate on a bounded sample
-of the rotating-field workload on this host.  Each leg's full record goes to stderr as a `bench-detail <leg>
-<json>` line.
+grid (field fill timed apart) and past its capacity with thinning per cell, the
+rotating-field cascade carried past its capacity by thinning (also with the generator
+factor in its random and deterministic forms, the reverse mode and the cap per parent),
+the Sec. VII shower and avalanche, 10^4 electrons in a uniform B, Schwinger pairs, the
+three emission generators, and the FP64 CPU oracle's rate on a bounded sample of the
+rotating-field workload on this host.  Each leg's full record goes to stderr as a
+`bench-detail <leg> <json>` line.
 
 HBM traffic of the dominant kernel comes from the rocprofv3 counter summary committed
 under profiles/ (FETCH_SIZE and WRITE_SIZE scaled by the same counters' reading for a copy
 kernel of known size); it is reported only while the kernel source still has the hash
-recorded there, else null.
+recorded there, else null.  Next to the published 8 TB/s the roofline also gives the rate
+of a plain device copy measured by the calibration program on this GPU (`copy_gbs`) and
+the kernel's fraction of it.
 """
 import argparse
 import ctypes as C
@@ -658,6 +662,22 @@ def traffic_summary_path(dom):
     return os.path.join(ROOT, "profiles", f"{dom}_kernel_rotating_cascade_hbm_counters.md")
 
 
+def copy_peak_gbs():
+    """The HBM rate a plain device copy reaches on this GPU (the best of the five launches of
+    the calibration program lib/hbm_copy, 800 MB each way, run as a child process), the
+    practical ceiling next to the published 8 TB/s; None if it cannot run."""
+    import subprocess
+    exe = os.path.join(ROOT, "paper_1412_6426_amd", "lib", "hbm_copy")
+    if not os.path.exists(exe):
+        return None
+    try:
+        out = subprocess.run([exe], capture_output=True, text=True, timeout=120).stdout
+    except (OSError, subprocess.SubprocessError):
+        return None
+    rates = [float(w.split("=")[1]) for w in out.split() if w.startswith("GB/s=")]
+    return max(rates) if rates else None
+
+
 def measured_traffic(dom, kernel):
     """HBM bytes per launch of `kernel` (its full template name) from the committed counter
     summary, if the kernel source is unchanged since the counters were taken."""
@@ -1038,6 +1058,7 @@ def main():
     dom, kbytes, kms, achieved = roofline_of(r)
     launches = r["launches"]
     traffic = measured_traffic(dom, kernel_name(dom, args.precision))
+    copy_gbs = copy_peak_gbs()
     line = {
         "metric": METRIC,
         "value": r["value"],
@@ -1069,6 +1090,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
+            "copy_gbs": copy_gbs,
+            "frac_copy": achieved / copy_gbs if copy_gbs else None,
             "traffic": traffic,
             "traffic_unit": "HBM bytes per launch",
             "algorithmic_bytes_per_launch": kbytes / launches,
