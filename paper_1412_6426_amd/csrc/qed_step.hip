@@ -137,11 +137,10 @@ __device__ __forceinline__ void stats_add(int64_t* p, unsigned long long v) {
 // counters below kPfNsub (their histogram fields stay zero).  Sums go into the zeroed stats
 // record with atomics.
 constexpr int kReduceJobs = 2 * kPfCount + 2 * kPfNsub;
+constexpr int kReduceBlocks = (kReduceJobs + 3) / 4;  // workgroups of 4 wavefronts
 
-__global__ void __launch_bounds__(256) reduce_kernel(StepArgs a) {
-  const int job = (int)blockIdx.x * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6);
+__device__ __forceinline__ void reduce_job(const StepArgs& a, int job, int lane) {
   if (job >= kReduceJobs) return;
-  const int lane = (int)(threadIdx.x & 63u);
   int kind, f;  // kind 0 leptons, 1 photons, 2 exact pairs, 3 generations
   if (job < kPfCount) {
     kind = 0;
@@ -211,6 +210,11 @@ __global__ void __launch_bounds__(256) reduce_kernel(StepArgs a) {
       else if (f >= kPfHist)
         stats_add(&st->photon_hist[f - kPfHist], v);
   }
+}
+
+__global__ void __launch_bounds__(256) reduce_kernel(StepArgs a) {
+  const int job = (int)blockIdx.x * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6);
+  reduce_job(a, job, (int)(threadIdx.x & 63u));
 }
 
 __global__ void __launch_bounds__(256) finalize_kernel(StepArgs a) {
@@ -1753,26 +1757,32 @@ __global__ void __launch_bounds__(1024) arena_scan_kernel(StepArgs a, ChildArena
     const ChildArena& A = kind == 0 ? pa : qa;
     if (A.waves <= 0) continue;
     unsigned int* row = A.cnt + (size_t)i * A.waves;
-    unsigned long long carry = 0;
-    for (int b0 = 0; b0 < A.waves; b0 += (int)blockDim.x) {
-      const int j = b0 + (int)threadIdx.x;
-      const unsigned long long v = j < A.waves ? row[j] : 0ull;
-      unsigned long long x = v;
+    // thread t takes the run [t k, t k + k) of the row: its sum, one scan of the thread
+    // sums over the workgroup, then the run's offsets
+    const int k = (A.waves + (int)blockDim.x - 1) / (int)blockDim.x;
+    const int j0 = (int)threadIdx.x * k;
+    const int j1 = j0 + k < A.waves ? j0 + k : A.waves;
+    unsigned long long v = 0ull;
+    for (int j = j0; j < j1; ++j) v += row[j];
+    unsigned long long x = v;
 #pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const unsigned long long y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-      }
-      if (lane == 63) wsum[wv] = x;
-      __syncthreads();
-      unsigned long long before = carry;
-      for (int q = 0; q < wv; ++q) before += wsum[q];
-      unsigned long long chunk = 0;
-      for (int q = 0; q < nw; ++q) chunk += wsum[q];
-      if (j < A.waves) row[j] = (unsigned)(before + x - v);
-      carry += chunk;
-      __syncthreads();
+    for (int o = 1; o < 64; o <<= 1) {
+      const unsigned long long y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
     }
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    unsigned long long run = x - v, carry = 0;
+    for (int q = 0; q < nw; ++q) {
+      if (q < wv) run += wsum[q];
+      carry += wsum[q];
+    }
+    for (int j = j0; j < j1; ++j) {
+      const unsigned c = row[j];
+      row[j] = (unsigned)run;
+      run += c;
+    }
+    __syncthreads();  // wsum is taken again for the next arena
     if (threadIdx.x == 0) {
       qed_instance& I = a.inst[i];
       if (kind == 0) {
@@ -1809,21 +1819,28 @@ __device__ __forceinline__ void count_drops(const StepArgs& a, int inst, bool lo
 // next store slot of its instance after the offsets of the scan (a per-instance running
 // count in LDS), then writes the child (photon) or both children (pair record), and, for
 // same-step processing, the slots into the record.  The launch also clears the count
-// matrices of the arenas zpa, zqa (the next generation's, whose readers are done).
+// matrices of the arenas zpa, zqa (the next generation's, whose readers are done).  When
+// the step has no later producer, its first reduce_blocks workgroups take the partial-stats
+// reduction instead (the reduce kernel's jobs, so the step saves that launch).
 __global__ void __launch_bounds__(256) arena_copy_kernel(StepArgs a, ChildArena pa,
                                                          ChildArena qa, ChildArena zpa,
-                                                         ChildArena zqa) {
+                                                         ChildArena zqa, int reduce_blocks) {
   __shared__ unsigned int lcnt[kWavesPerBlock][kArenaMaxInstances];
+  if ((int)blockIdx.x < reduce_blocks) {
+    reduce_job(a, (int)blockIdx.x * kWavesPerBlock + (int)(threadIdx.x >> 6), lane_id());
+    return;
+  }
+  const int blk = (int)blockIdx.x - reduce_blocks;  // the copy's own workgroups
+  const int nblk = (int)gridDim.x - reduce_blocks;
   {
     const long long n1 = zpa.waves > 0 ? (long long)a.n_inst * zpa.waves : 0;
     const long long n2 = zqa.waves > 0 ? (long long)a.n_inst * zqa.waves : 0;
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n1 + n2;
-         i += stride) {
+    const long long stride = (long long)nblk * blockDim.x;
+    for (long long i = (long long)blk * blockDim.x + threadIdx.x; i < n1 + n2; i += stride) {
       if (i < n1) zpa.cnt[i] = 0u;
       else zqa.cnt[i - n1] = 0u;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (blk == 0 && threadIdx.x == 0) {
       if (zpa.waves > 0) *zpa.used = 0u;
       if (zqa.waves > 0) *zqa.used = 0u;
     }
@@ -1834,8 +1851,9 @@ __global__ void __launch_bounds__(256) arena_copy_kernel(StepArgs a, ChildArena 
   const uint32_t step = (uint32_t)a.hdr->step;
   const int npa = pa.waves;
   const int nqa = qa.waves;
-  const int V = (int)gridDim.x * (int)(blockDim.x >> 6);
-  for (int t = wave_index(); t < npa + nqa; t += V) {
+  const int V = nblk * (int)(blockDim.x >> 6);
+  const int wid = blk * (int)(blockDim.x >> 6) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  for (int t = wid; t < npa + nqa; t += V) {
     const bool pair = t >= npa;
     const ChildArena& A = pair ? qa : pa;
     const int sw = pair ? t - npa : t;
@@ -1965,7 +1983,7 @@ struct GenArgs {
 };
 // kernel arguments stay within the 4 KB the launch passes
 static_assert(sizeof(StepArgs) + sizeof(GenArgs) <= 4096, "generation kernel arguments");
-static_assert(sizeof(StepArgs) + 4 * sizeof(ChildArena) <= 4096, "copy kernel arguments");
+static_assert(sizeof(StepArgs) + 4 * sizeof(ChildArena) + 8 <= 4096, "copy kernel arguments");
 
 // Fields a child inherited from its parent (record r of A).
 template <int FMODE>
@@ -2454,8 +2472,9 @@ __global__ void __launch_bounds__(256) gen_runs_kernel(StepArgs a, GenArgs q) {
 #undef LEPTON_COL
 
 // ------------------------------------------------------------------------------------
+// Returns whether the arena copy took the partial-stats reduction (no producer after it).
 template <bool MIXED, int FMODE>
-static void launch_persistent(const StepArgs& a, LaunchShape lep, LaunchShape pho,
+static bool launch_persistent(const StepArgs& a, LaunchShape lep, LaunchShape pho,
                               bool run_photons, hipStream_t s) {
   if (a.events[0]) (void)hipEventRecord(a.events[0], s);
   if (a.runs_photon > 1)
@@ -2480,13 +2499,14 @@ static void launch_persistent(const StepArgs& a, LaunchShape lep, LaunchShape ph
   }
   const int src = a.pa.waves + a.qa.waves;
   const ChildArena none{};
+  const bool gen = a.generations > 0;
+  const int rb = gen ? 0 : kReduceBlocks;
   if (src > 0) {
     hipLaunchKernelGGL(arena_scan_kernel, dim3(a.n_inst), dim3(1024), 0, s, a, a.pa, a.qa);
     // with same-step processing the copy also clears generation 1's count matrices
-    const bool gen = a.generations > 0;
-    hipLaunchKernelGGL(arena_copy_kernel, dim3((src + kWavesPerBlock - 1) / kWavesPerBlock),
-                       dim3(256), 0, s, a, a.pa, a.qa, gen ? a.gpa[1] : none,
-                       gen ? a.gqa[1] : none);
+    hipLaunchKernelGGL(arena_copy_kernel,
+                       dim3(rb + (src + kWavesPerBlock - 1) / kWavesPerBlock), dim3(256), 0, s,
+                       a, a.pa, a.qa, gen ? a.gpa[1] : none, gen ? a.gqa[1] : none, rb);
   }
   // children through the rest of the step: generation g reads set (g - 1) % 2 (set 0 as the
   // particle kernels wrote it for g = 1) and writes set g % 2
@@ -2507,8 +2527,9 @@ static void launch_persistent(const StepArgs& a, LaunchShape lep, LaunchShape ph
     hipLaunchKernelGGL(arena_scan_kernel, dim3(a.n_inst), dim3(1024), 0, s, a, q.opa, q.oqa);
     hipLaunchKernelGGL(arena_copy_kernel, dim3((gsrc + kWavesPerBlock - 1) / kWavesPerBlock),
                        dim3(256), 0, s, a, q.opa, q.oqa, more ? a.gpa[(g + 1) % 2] : none,
-                       more ? a.gqa[(g + 1) % 2] : none);
+                       more ? a.gqa[(g + 1) % 2] : none, 0);
   }
+  return src > 0 && !gen;
 }
 
 int field_mode(int kind) {
@@ -2524,16 +2545,17 @@ hipError_t launch_step(const StepArgs& a, int precision, LaunchShape lep, Launch
   if (zb > 1024) zb = 1024;
   hipLaunchKernelGGL(prep_kernel, dim3(1 + (int)zb), dim3(256), 0, s, a, run_photons ? 1 : 0);
   const int fm = field_mode(a.field.kind);
+  bool reduced;
   if (precision == QED_MIXED) {
-    if (fm == kFieldEB) launch_persistent<true, kFieldEB>(a, lep, pho, run_photons, s);
-    else if (fm == kFieldE) launch_persistent<true, kFieldE>(a, lep, pho, run_photons, s);
-    else launch_persistent<true, kFieldLocal>(a, lep, pho, run_photons, s);
+    if (fm == kFieldEB) reduced = launch_persistent<true, kFieldEB>(a, lep, pho, run_photons, s);
+    else if (fm == kFieldE) reduced = launch_persistent<true, kFieldE>(a, lep, pho, run_photons, s);
+    else reduced = launch_persistent<true, kFieldLocal>(a, lep, pho, run_photons, s);
   } else {
-    if (fm == kFieldEB) launch_persistent<false, kFieldEB>(a, lep, pho, run_photons, s);
-    else if (fm == kFieldE) launch_persistent<false, kFieldE>(a, lep, pho, run_photons, s);
-    else launch_persistent<false, kFieldLocal>(a, lep, pho, run_photons, s);
+    if (fm == kFieldEB) reduced = launch_persistent<false, kFieldEB>(a, lep, pho, run_photons, s);
+    else if (fm == kFieldE) reduced = launch_persistent<false, kFieldE>(a, lep, pho, run_photons, s);
+    else reduced = launch_persistent<false, kFieldLocal>(a, lep, pho, run_photons, s);
   }
-  hipLaunchKernelGGL(reduce_kernel, dim3((kReduceJobs + 3) / 4), dim3(256), 0, s, a);
+  if (!reduced) hipLaunchKernelGGL(reduce_kernel, dim3(kReduceBlocks), dim3(256), 0, s, a);
   hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, a);
   return hipGetLastError();
 }
