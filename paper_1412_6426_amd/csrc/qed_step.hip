@@ -1,7 +1,8 @@
 // qed_step.hip -- the per-step kernels of the QED step (Sec. IV.H adaptive event generator
 // of Gonoskov et al., arXiv:1412.6426, with the Sec. V.A pair generator).
 //
-// One step is up to eight launches on the caller's stream:
+// One step is up to eight launches on the caller's stream (plus three per same-step
+// generation):
 //   prep     (1 + k wgs)    snapshot live counts, particle prefix sums over the
 //                           (instance, species) segments, space-independent fields at t_n,
 //                           zero the stats record and the arenas' count matrices;
@@ -10,10 +11,14 @@
 //   photons  (persistent)   photons: push, chi_gamma, pair-rate bound; draws below the
 //                           bound go to the wavefront's candidate list for
 //   exact    (grid-stride)  the exact pair decision; pair records go to the pair arena;
-//   scan     (1 wg/instance) arena counts -> store offsets, instance counts raised;
+//   scan     (1 wg/instance) arena counts -> store offsets, instance counts raised and
+//                           clamped to the capacities;
 //   copy     (1 wave/source wave) arena records -> photon, electron, positron stores;
-//   reduce   (1 wave/field) per-workgroup partial stats -> the stats record;
-//   finalize (1 workgroup)  clamp counts, status bits, step index + 1.
+//   reduce   (1 wave/field) per-workgroup partial stats -> the stats record (status bits
+//                           set with the counters they report);
+//   finalize (1 workgroup)  clamp counts, step index + 1.
+// Where the copy is the step's last producer (arenas on, no same-step children), its launch
+// also takes the reduce jobs and the step index, and the step is six launches.
 // Children land after the step-start counts, so they are first processed at step n+1.
 //
 // Work distribution: the particles alive at the step start form one index space per kernel
@@ -189,12 +194,24 @@ __device__ __forceinline__ void reduce_job(const StepArgs& a, int job, int lane)
   switch (f) {
     case kPfSubsteps: stats_add(&st->substeps, v); break;
     case kPfEvents: stats_add(pho ? &st->pairs : &st->emitted, v); break;
-    case kPfSaturated: stats_add(&st->saturated, v); break;
+    case kPfSaturated:
+      stats_add(&st->saturated, v);
+      atomicOr(&st->status, QED_STATUS_SATURATED);
+      break;
     case kPfNear: stats_add(&st->near_threshold, v); break;
-    case kPfNonfinite: stats_add(&st->nonfinite, v); break;
+    case kPfNonfinite:
+      stats_add(&st->nonfinite, v);
+      atomicOr(&st->status, QED_STATUS_NONFINITE);
+      break;
     case kPfNearInt: stats_add(&st->nsub_near_int, v); break;
-    case kPfClamped: stats_add(&st->nsub_clamped, v); break;
-    case kPfDropped: stats_add(&st->dropped, v); break;
+    case kPfClamped:
+      stats_add(&st->nsub_clamped, v);
+      atomicOr(&st->status, QED_STATUS_NSUB_CLAMPED);
+      break;
+    case kPfDropped:
+      stats_add(&st->dropped, v);
+      atomicOr(&st->status, QED_STATUS_DROPPED);
+      break;
     case kPfEarly: stats_add(&st->early_out, v); break;
     case kPfAdv0: stats_add(&st->advanced[pho ? QED_PHOTON : QED_ELECTRON], v); break;
     case kPfAdv1: stats_add(&st->advanced[QED_POSITRON], v); break;
@@ -217,22 +234,15 @@ __global__ void __launch_bounds__(256) reduce_kernel(StepArgs a) {
   reduce_job(a, job, (int)(threadIdx.x & 63u));
 }
 
+// The end of a step whose last launch is not the arena copy: counts clamped to the
+// capacities, step + 1.  (The status bits are set where their counters are raised.)
 __global__ void __launch_bounds__(256) finalize_kernel(StepArgs a) {
   for (int i = threadIdx.x; i < a.n_inst; i += blockDim.x) {
     qed_instance& I = a.inst[i];
     for (int s = 0; s < 3; ++s)
       if (I.count[s] > I.capacity[s]) I.count[s] = I.capacity[s];
   }
-  if (threadIdx.x == 0) {
-    qed_stats* st = a.stats;
-    uint32_t status = st->status;
-    if (st->dropped > 0) status |= QED_STATUS_DROPPED;
-    if (st->nonfinite > 0) status |= QED_STATUS_NONFINITE;
-    if (st->saturated > 0) status |= QED_STATUS_SATURATED;
-    if (st->nsub_clamped > 0) status |= QED_STATUS_NSUB_CLAMPED;
-    st->status = status;
-    *a.d_step = a.hdr->step + 1;
-  }
+  if (threadIdx.x == 0) *a.d_step = a.hdr->step + 1;
 }
 
 // ------------------------------------------------------------------------------------
@@ -1744,8 +1754,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 // ------------------------------------------------------------------------------------
 // One workgroup per instance: exclusive prefix over the wavefronts of each arena's counts
 // (in place), the store count before the append into base[], and the counts raised by the
-// totals.  Counts above the capacity are clamped by the finalize kernel; the copy kernel
-// drops and counts the children that land beyond it.
+// totals, clamped to the capacities; the copy kernel drops and counts the children that land
+// beyond them.
 __global__ void __launch_bounds__(1024) arena_scan_kernel(StepArgs a, ChildArena pa,
                                                           ChildArena qa) {
   __shared__ unsigned long long wsum[16];
@@ -1796,6 +1806,12 @@ __global__ void __launch_bounds__(1024) arena_scan_kernel(StepArgs a, ChildArena
       }
     }
   }
+  // counts above the capacity (the copy drops and counts what lands beyond it) clamped
+  if (threadIdx.x == 0) {
+    qed_instance& I = a.inst[i];
+    for (int s = 0; s < 3; ++s)
+      if (I.count[s] > I.capacity[s]) I.count[s] = I.capacity[s];
+  }
 }
 
 // Count n children dropped for lack of capacity (rare: only at a full store).
@@ -1810,6 +1826,7 @@ __device__ __forceinline__ void count_drops(const StepArgs& a, int inst, bool lo
                 (unsigned long long)__popcll(same));
       atomicAdd(reinterpret_cast<unsigned long long*>(&a.stats->dropped),
                 (unsigned long long)__popcll(same));
+      atomicOr(&a.stats->status, QED_STATUS_DROPPED);
     }
     m &= ~same;
   }
@@ -1821,12 +1838,15 @@ __device__ __forceinline__ void count_drops(const StepArgs& a, int inst, bool lo
 // same-step processing, the slots into the record.  The launch also clears the count
 // matrices of the arenas zpa, zqa (the next generation's, whose readers are done).  When
 // the step has no later producer, its first reduce_blocks workgroups take the partial-stats
-// reduction instead (the reduce kernel's jobs, so the step saves that launch).
+// reduction instead (the reduce kernel's jobs), and the launch ends the step: the scan has
+// clamped the counts and the status bits are set where their counters are raised, so only
+// the step counter is left to advance (no kernel of this launch reads it).
 __global__ void __launch_bounds__(256) arena_copy_kernel(StepArgs a, ChildArena pa,
                                                          ChildArena qa, ChildArena zpa,
                                                          ChildArena zqa, int reduce_blocks) {
   __shared__ unsigned int lcnt[kWavesPerBlock][kArenaMaxInstances];
   if ((int)blockIdx.x < reduce_blocks) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.d_step = a.hdr->step + 1;
     reduce_job(a, (int)blockIdx.x * kWavesPerBlock + (int)(threadIdx.x >> 6), lane_id());
     return;
   }
@@ -2472,7 +2492,8 @@ __global__ void __launch_bounds__(256) gen_runs_kernel(StepArgs a, GenArgs q) {
 #undef LEPTON_COL
 
 // ------------------------------------------------------------------------------------
-// Returns whether the arena copy took the partial-stats reduction (no producer after it).
+// Returns whether the arena copy took the partial-stats reduction and ended the step (no
+// producer after it).
 template <bool MIXED, int FMODE>
 static bool launch_persistent(const StepArgs& a, LaunchShape lep, LaunchShape pho,
                               bool run_photons, hipStream_t s) {
@@ -2555,8 +2576,10 @@ hipError_t launch_step(const StepArgs& a, int precision, LaunchShape lep, Launch
     else if (fm == kFieldE) reduced = launch_persistent<false, kFieldE>(a, lep, pho, run_photons, s);
     else reduced = launch_persistent<false, kFieldLocal>(a, lep, pho, run_photons, s);
   }
-  if (!reduced) hipLaunchKernelGGL(reduce_kernel, dim3(kReduceBlocks), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, a);
+  if (!reduced) {
+    hipLaunchKernelGGL(reduce_kernel, dim3(kReduceBlocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, a);
+  }
   return hipGetLastError();
 }
 
