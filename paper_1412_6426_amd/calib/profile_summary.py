@@ -108,9 +108,12 @@ def cmd_trace(a):
     lines += ["", f"Sum of kernel time: {total / 1e6:.3f} ms."]
     for spec in a.window or []:
         name, lo, hi = spec.rsplit(":", 2)
-        v = durs.get(name, [])[int(lo):int(hi)]
+        allv = durs.get(name, [])
+        v = allv[int(lo):int(hi)]
         if v:
-            lines += ["", f"- window: {name} dispatches {lo}..{int(hi) - 1} "
+            # a negative start counts from the last dispatch
+            first = int(lo) if int(lo) >= 0 else len(allv) + int(lo)
+            lines += ["", f"- window: {name} dispatches {first}..{first + len(v) - 1} "
                           f"({len(v)}): total {sum(v) / 1e6:.3f} ms, "
                           f"avg {statistics.mean(v) / 1e3:.2f} us"]
     if a.note:
