@@ -11,7 +11,11 @@ alive.  The tuner therefore works inside a run of the real job:
   per-wavefront work queue's chunk size and the persistent grid) with the engine's own
   arena; then, with the best of those, the child-arena sizes (records = photon slots /
   divisor: the per-wavefront shares and pool the lepton and pair producers write their
-  children into before the ordered copy); then, with the best of those, the refill
+  children into before the ordered copy), only those with room for the children of the
+  class's last steps (a full arena sends children to slower direct reservations, which the
+  first steps of a class may not show, and a class chosen by live count can come back with
+  another mix of species, after a thinning: a choice whose arena some step of its class
+  outgrew falls back to the engine's whole arena); then, with the best of those, the refill
   thresholds of the lepton kernel's work queue (idle lanes taken in batches of at least
   that many).  The lowest time per particle-step wins;
 * the result is a schedule: (first step, shape) pairs, shape = (tile, grid, arena divisor,
@@ -52,6 +56,17 @@ DEFAULT_ARENA_DIVISORS = (32, 8, 2)
 # Refill thresholds tried last (1: every idle lane at once; 0, the library's default, is
 # the shape they are compared with).
 DEFAULT_REFILLS = (1, 16, 40)
+# An arena is tried only if it holds ARENA_ROOM times the children of the class's busiest
+# trial step, scaled by the class factor (the class ends with that many times the
+# particles): half of an arena is the wavefronts' equal shares, which the busiest
+# wavefronts outgrow first.
+ARENA_ROOM = 2.0
+
+
+def step_children(st) -> int:
+    """Arena records a step's children take: a photon record per emission, and pair
+    records, whose arena is a quarter of the photon arena's size, counted four times."""
+    return int(st.get("emitted", 0)) + 4 * int(st.get("pairs", 0))
 
 
 class HipTimer:
@@ -167,6 +182,9 @@ def tune_run(e, field, params: Q.qed_params, n_steps: int, candidates: Sequence[
     pending: List[Shape] = []
     timings: Dict[Shape, List[float]] = {}
     phase = 0  # 0: launch shapes, 1: arena sizes, 2: refill thresholds
+    peak_children = 0  # the busiest trial step of the class being tuned
+    records_for = getattr(e, "arena_records_for", None)
+    class_children: Dict[int, int] = {}  # the busiest step of each class over the run
     cls_of_step: List[int] = []
     tuning: Optional[int] = None  # class whose trials are running
 
@@ -180,7 +198,9 @@ def tune_run(e, field, params: Q.qed_params, n_steps: int, candidates: Sequence[
         if ph == 0:
             cands = list(candidates)
         elif ph == 1:
-            cands = [(base[0], base[1], d, base[3]) for d in arena_divisors]
+            need = ARENA_ROOM * class_factor * peak_children
+            cands = [(base[0], base[1], d, base[3]) for d in arena_divisors
+                     if records_for is None or records_for(d) >= need]
         else:
             cands = [(base[0], base[1], base[2], r) for r in refills]
         if ph > 0 and base not in cands:
@@ -204,6 +224,7 @@ def tune_run(e, field, params: Q.qed_params, n_steps: int, candidates: Sequence[
         if cls >= 0 and cls not in best and cls != tuning:
             settle(tuning)  # a class left before its trials ended keeps its best so far
             tuning = cls
+            peak_children = 0
             start_phase(0, None)
         if cls < 0:
             shape = DEFAULT_SHAPE
@@ -220,7 +241,10 @@ def tune_run(e, field, params: Q.qed_params, n_steps: int, candidates: Sequence[
         st = e.stats()
         done = sum(st["advanced"])
         live = int(e.counts().sum())
+        if cls >= 0:
+            class_children[cls] = max(class_children.get(cls, 0), step_children(st))
         if cls >= 0 and cls not in best:
+            peak_children = max(peak_children, step_children(st))
             if done > 0:
                 timings[shape].append(ms / done)
             trials.append(dict(step=n, cls=cls, tile=shape[0], grid=shape[1],
@@ -238,6 +262,10 @@ def tune_run(e, field, params: Q.qed_params, n_steps: int, candidates: Sequence[
         if stop_on_drop and st["dropped"] > 0:
             break
     settle(tuning)
+    if records_for is not None:
+        for c, s in list(best.items()):
+            if s[2] > 0 and records_for(s[2]) < ARENA_ROOM * class_children.get(c, 0):
+                best[c] = (s[0], s[1], 0, s[3])
     sync()
     if timer is None:
         ev.close()

@@ -1407,9 +1407,11 @@ __global__ void __launch_bounds__(256) photon_kernel(StepArgs a) {
         if (!cand) {
           cnt.subs += st.nsub;
           if (a.push_photons) {
-            X[lane] = x.x;
-            Y[lane] = x.y;
-            Z[lane] = x.z;
+            // streaming stores: the positions are not read again in this step (1% faster
+            // than plain stores; non-temporal loads as well were slower)
+            __builtin_nontemporal_store(x.x, &X[lane]);
+            __builtin_nontemporal_store(x.y, &Y[lane]);
+            __builtin_nontemporal_store(x.z, &Z[lane]);
           }
         } else {
           cnt.subs += kcand;  // the exact kernel counts the rest

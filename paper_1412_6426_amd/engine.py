@@ -309,6 +309,13 @@ class Engine:
         p.tile, p.block, p.grid_blocks = int(tile), int(block), int(grid_blocks)
         return p
 
+    def arena_records_for(self, divisor: int = 0) -> int:
+        """Records of the photon arena that set_arena(divisor) gives (bounded by the
+        workspace allocated at construction)."""
+        if divisor <= 0:
+            return self.arena_records
+        return min(max(self._pslots // int(divisor), 1024), self.arena_records)
+
     def set_arena(self, divisor: int = 0):
         """Child arenas of photon slots / divisor records for the following steps (within
         the workspace allocated at construction; qed_step uses the largest arena that fits

@@ -149,3 +149,87 @@ def test_cache_entries_without_a_refill_threshold_read_as_the_default(tmp_path):
     path = tmp_path / "old.json"
     path.write_text(json.dumps({"k": {"0": [64, 0, 8], "2": [512, 0, 2]}}))
     assert AT.TuneCache(str(path)).get("k") == {0: (64, 0, 8, 0), 2: (512, 0, 2, 0)}
+
+
+class ChildEngine(FakeEngine):
+    """One child per live particle a step, and arenas of 10^6 / divisor records."""
+
+    RECORDS = 10 ** 6
+
+    def arena_records_for(self, divisor):
+        return self.RECORDS if divisor <= 0 else self.RECORDS // divisor
+
+    def stats(self):
+        return {"advanced": [self.done, 0, 0], "dropped": 0, "emitted": self.done,
+                "pairs": 0}
+
+
+def test_arenas_without_room_for_the_class_are_not_tried():
+    """Divisor 32 is the fastest in the scripted costs below, but an arena that the
+    children of a class's last steps would overflow sends them to direct reservations: a
+    class whose busiest trial step has n children tries only arenas of at least
+    2 x 4 x n records."""
+    def cost(shape, live):
+        tile, grid, arena, refill = shape
+        return 1.0 + {0: 0.02, 2: 0.03, 8: 0.01, 32: 0.0}[arena] + (0.05 if tile != 128 else 0)
+
+    e = ChildEngine(cost, growth=1.04)
+    sched = _tune(e, 300)
+    seen_small = seen_large = False
+    for c, shape in sched.choices.items():
+        div = shape[2]
+        tried = {t["arena_div"] for t in sched.trials if t["cls"] == c}
+        # the busiest step (one child per particle) before the class's arena trials began
+        first_arena = min((t["step"] for t in sched.trials
+                           if t["cls"] == c and t["arena_div"] > 0), default=None)
+        peak = max((t["particle_steps"] for t in sched.trials
+                    if t["cls"] == c and (first_arena is None or t["step"] < first_arena)),
+                   default=0)
+        need = AT.ARENA_ROOM * 4.0 * peak
+        for d in tried - {0}:
+            assert e.arena_records_for(d) >= need, (c, d, need)
+        assert div == 0 or e.arena_records_for(div) >= need
+        if 32 in tried:
+            seen_small = True
+        if need > e.arena_records_for(32):
+            seen_large = True
+            assert 32 not in tried
+    assert seen_small and seen_large
+
+
+def test_a_class_whose_arena_a_later_step_outgrows_falls_back_to_the_whole_arena():
+    """Thinning can bring the live count back into a class with many more children per
+    particle than when the class was tuned: its arena choice must then give way to the
+    engine's whole arena (divisor 0) in the schedule."""
+    def cost(shape, live):
+        tile, grid, arena, refill = shape
+        return 1.0 + {0: 0.02, 2: 0.03, 8: 0.01, 32: 0.0}[arena]
+
+    class Mix(ChildEngine):
+        RECORDS = 10 ** 7
+
+        def __init__(self, *a, **kw):
+            super().__init__(*a, **kw)
+            self.n = 0
+
+        def step(self, field, params):
+            super().step(field, params)
+            self.n += 1
+            if self.n == 150:  # a thinning: back to a small class, now rich in children
+                self.live = 2000
+                self.growth = 1.0
+                self.per = 200
+
+        def stats(self):
+            st = super().stats()
+            st["emitted"] = self.done * getattr(self, "per", 1)
+            return st
+
+    e = Mix(cost, growth=1.04)
+    sched = _tune(e, 200)
+    c = cls_of(2000)
+    assert c in sched.choices
+    assert any(t["cls"] == c and t["arena_div"] == 32 for t in sched.trials)
+    # 2000 particles x 200 children outgrow 10^7 / 32 records (x 2 room): the whole arena
+    assert sched.choices[c][2] == 0
+    assert sched.shape_at(199)[2] == 0
