@@ -1412,7 +1412,7 @@ __global__ void __launch_bounds__(256) photon_kernel(StepArgs a) {
           cnt.subs += st.nsub;
           if (a.push_photons) {
             // streaming stores: the positions are not read again in this step (1% faster
-            // than plain stores; non-temporal loads as well were slower)
+            // than plain stores; reading the positions non-temporally as well was slower)
             __builtin_nontemporal_store(x.x, &X[lane]);
             __builtin_nontemporal_store(x.y, &Y[lane]);
             __builtin_nontemporal_store(x.z, &Z[lane]);
